@@ -1,0 +1,152 @@
+"""Seeded synthetic graph inputs (CSR) for the MIS solver and its oracle.
+
+This module is the only code that the CPU oracle and the GPU library share: it
+makes inputs and holds none of the solver's arithmetic.  All generation runs in
+``graphgen.c`` (host C, compiled to ``libgraphgen.so`` next to this file).
+
+The workloads stand in for the paper's SuiteSparse evaluation graphs (Table 1:
+mesh/road graphs, power-law web and social graphs, a Graph500 Kronecker graph),
+which are not available here; no item of that collection is reproduced.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "graphgen.c")
+_LIB = os.path.join(_HERE, "libgraphgen.so")
+_lib = None
+
+
+def build_lib() -> str:
+    """Compile graphgen.c with gcc into libgraphgen.so (always recompiles)."""
+    tmp = _LIB + ".tmp"
+    subprocess.check_call(["gcc", "-O3", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
+                           "-o", tmp, _SRC])
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build_lib()
+    lib = ctypes.CDLL(_LIB)
+    i64, u64, i32 = ctypes.c_int64, ctypes.c_uint64, ctypes.c_int
+    p = ctypes.c_void_p
+    lib.gg_er.argtypes = [i64, i64, u64, p, p]
+    lib.gg_er.restype = i64
+    lib.gg_rmat.argtypes = [i64, i64, u64, u64, u64, i32, u64, p, p]
+    lib.gg_rmat.restype = i64
+    lib.gg_grid.argtypes = [i64, i64, i64, i64, u64, p, p]
+    lib.gg_grid.restype = i64
+    lib.gg_grid_edges.argtypes = [i64, i64, i64]
+    lib.gg_grid_edges.restype = i64
+    lib.gg_splitmix64.argtypes = [u64, i64, p]
+    lib.gg_splitmix64.restype = None
+    _lib = lib
+    return lib
+
+
+@dataclass
+class Graph:
+    """Undirected simple graph in CSR form; every edge appears in both rows."""
+    n: int
+    row_ptr: np.ndarray  # int64[n+1]
+    col_idx: np.ndarray  # int32[nnz], each row sorted ascending
+    name: str = ""
+
+    @property
+    def nnz(self) -> int:
+        return int(self.row_ptr[-1])
+
+    @property
+    def m(self) -> int:
+        """Undirected edges, each counted once."""
+        return self.nnz // 2
+
+    def degrees(self) -> np.ndarray:
+        return np.diff(self.row_ptr)
+
+
+def _alloc(n: int, m: int):
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    col_idx = np.zeros(max(2 * m, 1), dtype=np.int32)
+    return row_ptr, col_idx
+
+
+def _check(rc: int, what: str) -> int:
+    if rc < 0:
+        raise RuntimeError(f"{what}: generator error {rc}")
+    return rc
+
+
+def splitmix64(seed: int, count: int) -> np.ndarray:
+    out = np.zeros(count, dtype=np.uint64)
+    _load().gg_splitmix64(seed & (2**64 - 1), count, out.ctypes.data)
+    return out
+
+
+def er(n: int, m: int, seed: int = 1) -> Graph:
+    """Erdos-Renyi G(n, m): m distinct uniform pairs u != v (redraw duplicates)."""
+    row_ptr, col_idx = _alloc(n, m)
+    _check(_load().gg_er(n, m, seed, row_ptr.ctypes.data, col_idx.ctypes.data), "er")
+    return Graph(n, row_ptr, col_idx[: 2 * m], f"er_n{n}_m{m}_s{seed}")
+
+
+RMAT_ABC = (0.57, 0.19, 0.19)
+
+
+def rmat(n: int, m: int, seed: int = 1, abc=RMAT_ABC, permute: bool = True) -> Graph:
+    """R-MAT with quadrant probabilities abc (d = rest), m distinct non-loop edges."""
+    a32, b32, c32 = (int(math.floor(x * 2**32)) for x in abc)
+    row_ptr, col_idx = _alloc(n, m)
+    _check(_load().gg_rmat(n, m, a32, b32, c32, int(permute), seed,
+                           row_ptr.ctypes.data, col_idx.ctypes.data), "rmat")
+    return Graph(n, row_ptr, col_idx[: 2 * m], f"rmat_n{n}_m{m}_s{seed}")
+
+
+def grid_edges(sx: int, sy: int, sz: int) -> int:
+    return int(_load().gg_grid_edges(sx, sy, sz))
+
+
+def grid(sx: int, sy: int, sz: int, long_frac: float = 0.01, seed: int = 1) -> Graph:
+    """3D 7-point mesh plus round-down(long_frac * grid edges) random long-range pairs."""
+    mg = grid_edges(sx, sy, sz)
+    n_long = int(math.floor(long_frac * mg))
+    n = sx * sy * sz
+    row_ptr, col_idx = _alloc(n, mg + n_long)
+    m = _check(_load().gg_grid(sx, sy, sz, n_long, seed, row_ptr.ctypes.data,
+                               col_idx.ctypes.data), "grid")
+    return Graph(n, row_ptr, col_idx[: 2 * m], f"grid_{sx}x{sy}x{sz}_l{n_long}_s{seed}")
+
+
+# ---- named workloads (the five synthetic configurations) ----
+
+def workload(name: str, seed: int = 1) -> Graph:
+    """Named synthetic workloads.
+
+    er10k   : G(n=10,000, m=40,000), average degree exactly 8.
+    rmat22  : R-MAT scale 22 (n=4,194,304), m=8n distinct edges (avg degree 16),
+              a,b,c,d = .57,.19,.19,.05, random vertex relabelling.
+    grid256 : 256^3 7-point mesh (50,135,040 edges) + 1% = 501,350 long-range pairs.
+    Smaller variants for tests: rmat<k> (scale k, avg degree 16), grid<s> (s^3 mesh).
+    """
+    if name == "er10k":
+        return er(10_000, 40_000, seed)
+    if name.startswith("rmat"):
+        scale = int(name[4:])
+        n = 1 << scale
+        return rmat(n, 8 * n, seed)
+    if name.startswith("grid"):
+        s = int(name[4:])
+        return grid(s, s, s, 0.01, seed)
+    raise KeyError(name)

@@ -1,0 +1,299 @@
+"""Pins of the CPU oracle against facts fixed outside it.
+
+- published SplitMix64 test vector (hash half of the priority key);
+- the paper's worked example (Section 3.1, Phase 1 and Phase 3 walk-through);
+- a hand-derived multi-round trace;
+- sequential greedy in key order (a different algorithm with the same unique answer);
+- independence + maximality verifier and the lexicographically-first certificate;
+- brute-force enumeration of all MIS on graphs of <= 20 vertices, itself pinned by
+  Padovan / Perrin / Moon-Moser counts;
+- closed-form special cases (edgeless graph, K_n, stars, matchings, paths with
+  increasing keys, disjoint unions).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute
+from conftest import csr_from_edges, distinct_keys, golden, random_graph
+from paper_2605_29604_amd import gen
+
+
+# ---------------------------------------------------------------- the key rule
+
+def test_oracle_splitmix_vector():
+    want = [int(x) for x in golden("splitmix64_seed1234567.txt")]
+    assert [int(x) for x in oracle.splitmix64(1234567, 5)] == want
+
+
+def test_q_table():
+    # floor(255 / (1 + deg)): lower degree -> higher priority (Eq. 1 favours low degree)
+    table = {0: 255, 1: 127, 2: 85, 3: 63, 4: 51, 5: 42, 6: 36, 7: 31, 8: 28, 254: 1, 255: 0, 10**6: 0}
+    for d, want in table.items():
+        assert oracle.q(d) == want
+    qs = [oracle.q(d) for d in range(400)]
+    assert all(a >= b for a, b in zip(qs, qs[1:]))
+
+
+def test_key_fields_against_vector():
+    vec = [int(x) for x in golden("splitmix64_seed1234567.txt")]
+    for v in range(5):
+        for deg in (0, 3, 17, 300):
+            k = oracle.key(1234567, v, deg)
+            assert k >> 56 == oracle.q(deg)
+            assert (k >> 24) & 0xFFFFFFFF == vec[v] >> 32
+            assert k & 0xFFFFFF == v
+
+
+def test_keys_distinct_and_degree_ordered():
+    g = gen.er(5000, 20000, 3)
+    k = oracle.keys(g.row_ptr, 9)
+    assert np.unique(k).size == g.n
+    d = g.degrees()
+    lo, hi = np.argmin(d), np.argmax(d)
+    assert k[lo] > k[hi]
+    with pytest.raises(ValueError):
+        oracle.keys(np.zeros((1 << 24) + 2, dtype=np.int64), 1)
+
+
+# ------------------------------------------------------------ paper example
+
+def test_worked_example_section_3_1():
+    fx = golden("worked_example_sec3_1.json")
+    rp, ci = csr_from_edges(fx["n"], fx["edges"])
+    k = np.array(fx["keys"], dtype=np.uint64)
+    nb1 = ci[rp[1]:rp[2]]
+    assert max(k[u] for u in nb1) == fx["round1"]["max_np_1"]
+    st, r, tr = oracle.roundsync(rp, ci, k, max_rounds=1)
+    assert st[1] == oracle.IN and st[5] == oracle.OUT
+    assert list(tr[0]) == fx["round1"]["trace"]
+    # exactly the stated candidates joined the set in round 1
+    assert sorted(np.nonzero(st == oracle.IN)[0].tolist()) == fx["round1"]["candidates"]
+
+
+def test_strict_comparison():
+    # Phase 1 uses a strict ">" (Algorithm 1 and 2): a vertex needs to beat every alive
+    # neighbour. Two vertices, keys 5 and 7: only the 7 is a candidate in round 1.
+    rp, ci = csr_from_edges(2, [(0, 1)])
+    st, r, tr = oracle.roundsync(rp, ci, np.array([5, 7], dtype=np.uint64))
+    assert list(st) == [oracle.OUT, oracle.IN] and r == 1
+
+
+def test_hand_trace():
+    fx = golden("hand_trace_tree5.json")
+    rp, ci = csr_from_edges(fx["n"], fx["edges"])
+    st, r, tr = oracle.roundsync(rp, ci, np.array(fx["keys"], dtype=np.uint64))
+    assert r == fx["rounds"]
+    assert tr.tolist() == fx["trace"]
+    assert (st == oracle.IN).astype(int).tolist() == fx["in_set"]
+
+
+# ----------------------------------------------------------- brute force pins
+
+def path_edges(n):
+    return [(i, i + 1) for i in range(n - 1)]
+
+
+def cycle_edges(n):
+    return [(i, (i + 1) % n) for i in range(n)]
+
+
+def test_brute_force_counts():
+    fx = golden("mis_counts.json")
+    for n, c in fx["path"].items():
+        assert brute.all_mis(int(n), path_edges(int(n))).size == c
+    for n, c in fx["cycle"].items():
+        assert brute.all_mis(int(n), cycle_edges(int(n))).size == c
+    for k, c in fx["triangles"].items():
+        k = int(k)
+        edges = [e for t in range(k) for e in [(3 * t, 3 * t + 1), (3 * t + 1, 3 * t + 2), (3 * t, 3 * t + 2)]]
+        assert brute.all_mis(3 * k, edges).size == c
+    assert brute.all_mis(6, [(u, v) for u in range(6) for v in range(u + 1, 6)]).size == 6
+    assert brute.all_mis(7, []).size == 1
+    # Moon-Moser bound attained with a K4 (n=19) and a K2 (n=20)
+    tri = [e for t in range(5) for e in [(3 * t, 3 * t + 1), (3 * t + 1, 3 * t + 2), (3 * t, 3 * t + 2)]]
+    k4 = [(15 + a, 15 + b) for a in range(4) for b in range(a + 1, 4)]
+    assert brute.all_mis(19, tri + k4).size == 243 * 4
+    tri6 = [e for t in range(6) for e in [(3 * t, 3 * t + 1), (3 * t + 1, 3 * t + 2), (3 * t, 3 * t + 2)]]
+    assert brute.all_mis(20, tri6 + [(18, 19)]).size == 729 * 2
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_oracle_vs_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 15))
+    edges = random_graph(n, float(rng.uniform(0.1, 0.7)), rng)
+    rp, ci = csr_from_edges(n, edges)
+    k = distinct_keys(n, rng)
+    ins = oracle.mis(rp, ci, k)
+    masks = brute.all_mis(n, edges)
+    mine = int(sum(int(b) << v for v, b in enumerate(ins)))
+    assert mine in set(int(m) for m in masks)
+    assert mine == brute.lex_greatest_in_key_order(masks, k)
+    # the certificate singles out exactly one MIS
+    certified = [int(m) for m in masks
+                 if oracle.lfmis_cert(rp, ci, k, brute.to_indicator(int(m), n)) == 0]
+    assert certified == [mine]
+
+
+def test_oracle_vs_brute_force_20():
+    rng = np.random.default_rng(99)
+    n = 20
+    edges = random_graph(n, 0.2, rng)
+    rp, ci = csr_from_edges(n, edges)
+    k = oracle.keys(rp, 5)
+    ins = oracle.mis(rp, ci, k)
+    masks = brute.all_mis(n, edges)
+    mine = int(sum(int(b) << v for v, b in enumerate(ins)))
+    assert mine == brute.lex_greatest_in_key_order(masks, k)
+
+
+# ------------------------------------------------------- greedy and verifiers
+
+@pytest.mark.parametrize("name", ["er10k", "rmat12", "grid12"])
+def test_oracle_equals_greedy(name):
+    g = gen.workload(name, seed=2)
+    k = oracle.keys(g.row_ptr, 4)
+    st, r, tr = oracle.roundsync(g.row_ptr, g.col_idx, k)
+    ins = (st == oracle.IN).astype(np.uint8)
+    assert np.all(st != oracle.UNDECIDED)
+    assert np.array_equal(ins, oracle.greedy(g.row_ptr, g.col_idx, k))
+    assert oracle.verify(g.row_ptr, g.col_idx, ins) == 0
+    assert oracle.lfmis_cert(g.row_ptr, g.col_idx, k, ins) == 0
+    # per-round invariants: each round decides >= 1 vertex, counts add up
+    assert np.all(tr[:, 0] >= 1)
+    assert tr[:, 0].sum() == ins.sum()
+    assert tr[:, 0].sum() + tr[:, 1].sum() == g.n
+    assert np.all(np.diff(tr[:, 2]) < 0) or r == 1
+    assert tr[-1, 2] == 0
+
+
+def test_verifier_catches_planted_mistakes():
+    g = gen.er(3000, 12000, 5)
+    k = oracle.keys(g.row_ptr, 1)
+    ins = oracle.mis(g.row_ptr, g.col_idx, k)
+    # add a vertex adjacent to a member -> not independent
+    v_out = int(np.nonzero(ins == 0)[0][0])
+    bad = ins.copy(); bad[v_out] = 1
+    assert oracle.verify(g.row_ptr, g.col_idx, bad) == 1
+    assert oracle.lfmis_cert(g.row_ptr, g.col_idx, k, bad) != 0
+    # drop a member -> some vertex is left uncovered (the dropped one at least)
+    v_in = int(np.nonzero(ins == 1)[0][0])
+    bad = ins.copy(); bad[v_in] = 0
+    assert oracle.verify(g.row_ptr, g.col_idx, bad) == 2
+    assert oracle.lfmis_cert(g.row_ptr, g.col_idx, k, bad) != 0
+
+
+def test_min_degree_greedy_is_mis():
+    g = gen.workload("rmat12", seed=3)
+    md = oracle.mindeg_greedy(g.row_ptr, g.col_idx)
+    assert oracle.verify(g.row_ptr, g.col_idx, md) == 0
+    # on a star the min-degree rule takes all leaves
+    rp, ci = csr_from_edges(6, [(0, i) for i in range(1, 6)])
+    assert oracle.mindeg_greedy(rp, ci).tolist() == [0, 1, 1, 1, 1, 1]
+
+
+# --------------------------------------------------------------- special cases
+
+def test_edgeless_graph():
+    n = 17
+    rp = np.zeros(n + 1, dtype=np.int64)
+    ci = np.zeros(0, dtype=np.int32)
+    k = oracle.keys(rp, 1)
+    st, r, tr = oracle.roundsync(rp, ci, k)
+    assert np.all(st == oracle.IN) and r == 1 and tr.tolist() == [[n, 0, 0]]
+
+
+def test_empty_graph():
+    rp = np.zeros(1, dtype=np.int64)
+    st, r, tr = oracle.roundsync(rp, np.zeros(0, np.int32), np.zeros(0, np.uint64))
+    assert st.size == 0 and r == 0
+
+
+def test_complete_graph():
+    n = 9
+    rp, ci = csr_from_edges(n, [(u, v) for u in range(n) for v in range(u + 1, n)])
+    k = oracle.keys(rp, 3)
+    st, r, tr = oracle.roundsync(rp, ci, k)
+    assert r == 1 and np.nonzero(st == oracle.IN)[0].tolist() == [int(np.argmax(k))]
+
+
+@pytest.mark.parametrize("s", [2, 3, 10])
+def test_star(s):
+    rp, ci = csr_from_edges(s + 1, [(0, i) for i in range(1, s + 1)])
+    st, r, tr = oracle.roundsync(rp, ci, oracle.keys(rp, 1))
+    # q(1) = 127 > q(s) for s >= 2: every leaf out-ranks the centre
+    assert r == 1 and st[0] == oracle.OUT and np.all(st[1:] == oracle.IN)
+
+
+def test_matching():
+    n = 40
+    rp, ci = csr_from_edges(n, [(2 * i, 2 * i + 1) for i in range(n // 2)])
+    k = oracle.keys(rp, 8)
+    st, r, tr = oracle.roundsync(rp, ci, k)
+    assert r == 1
+    for i in range(n // 2):
+        hi = 2 * i if k[2 * i] > k[2 * i + 1] else 2 * i + 1
+        assert st[hi] == oracle.IN and st[hi ^ 1] == oracle.OUT
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 8, 31])
+def test_path_increasing_keys(n):
+    # keys increase along the path: only the top end is a candidate each round,
+    # so the solve takes exactly ceil(n/2) rounds, deciding 2 vertices per round
+    rp, ci = csr_from_edges(n, path_edges(n))
+    k = np.arange(1, n + 1, dtype=np.uint64)
+    st, r, tr = oracle.roundsync(rp, ci, k)
+    assert r == (n + 1) // 2
+    assert np.nonzero(st == oracle.IN)[0].tolist() == list(range(n - 1, -1, -2))[::-1]
+    for i in range(r):
+        left = n - 2 * (i + 1)
+        assert tr[i].tolist() == ([1, 1, left] if left >= 0 else [1, 0, 0])
+
+
+def test_disjoint_union():
+    g1 = gen.er(700, 2500, 1)
+    g2 = gen.rmat(1 << 10, 8 << 10, 2)
+    k1, k2 = oracle.keys(g1.row_ptr, 1), oracle.keys(g2.row_ptr, 1)
+    rp = np.concatenate([g1.row_ptr, g2.row_ptr[1:] + g1.nnz])
+    ci = np.concatenate([g1.col_idx, g2.col_idx + g1.n])
+    k = np.concatenate([k1, k2])        # graph-local keys: equal keys never meet on an edge
+    s, r, _ = oracle.roundsync(rp, ci, k)
+    s1, r1, _ = oracle.roundsync(g1.row_ptr, g1.col_idx, k1)
+    s2, r2, _ = oracle.roundsync(g2.row_ptr, g2.col_idx, k2)
+    assert np.array_equal(s, np.concatenate([s1, s2])) and r == max(r1, r2)
+
+
+def test_round_limit_resume_consistency():
+    g = gen.workload("grid12", seed=1)
+    k = oracle.keys(g.row_ptr, 2)
+    full, r, tr = oracle.roundsync(g.row_ptr, g.col_idx, k)
+    for j in range(1, r + 1):
+        part, rj, trj = oracle.roundsync(g.row_ptr, g.col_idx, k, max_rounds=j)
+        assert rj == j and np.array_equal(trj, tr[:j])
+        decided = part != oracle.UNDECIDED
+        assert np.array_equal(part[decided], full[decided])
+        assert decided.sum() == g.n - tr[j - 1, 2]
+
+
+# ----------------------------------------------------------------- validation
+
+def test_validate():
+    rp, ci = csr_from_edges(4, [(0, 1), (1, 2)])
+    assert oracle.validate(rp, ci) == 0
+    assert oracle.validate(np.array([0, 1, 1]), np.array([0])) == -3          # self-loop
+    assert oracle.validate(np.array([0, 2, 4]), np.array([1, 1, 0, 0])) == -4  # duplicate
+    assert oracle.validate(np.array([0, 1, 1]), np.array([1])) == -2          # asymmetric
+    assert oracle.validate(np.array([0, 1, 2]), np.array([1, 5])) == -5       # range
+
+
+@pytest.mark.parametrize("n", [2, 9, 30])
+def test_path_decreasing_keys(n):
+    # keys decrease along the vertex ids: the same ceil(n/2)-round staircase from the
+    # other end; an implementation that updated states in place while scanning ids
+    # upwards would finish in one round and fail here
+    rp, ci = csr_from_edges(n, path_edges(n))
+    k = np.arange(n, 0, -1).astype(np.uint64)
+    st, r, tr = oracle.roundsync(rp, ci, k)
+    assert r == (n + 1) // 2
+    assert np.nonzero(st == oracle.IN)[0].tolist() == list(range(0, n, 2))
