@@ -1,0 +1,172 @@
+/*
+ * tcmis.h -- C ABI of the MI355X (gfx950) priority-MIS library.
+ *
+ * The library computes the maximal independent set that round-synchronous,
+ * fixed-priority selection produces (TC-MIS, Algorithm 2, Section 3.1): in every
+ * round each undecided vertex whose priority beats all undecided neighbours
+ * becomes a candidate (Phase 1); the candidate-neighbour count N_c = A x C is
+ * formed (Phase 2); candidates join the set and vertices with N_c > 0 leave it
+ * (Phase 3).  For a fixed strict total order of priorities the result is unique
+ * (it equals the sequential greedy in decreasing priority order), so results are
+ * bit-exact across paths, tile sizes, reorderings and launch shapes.
+ *
+ * Conventions for every entry point:
+ *   - Pointers marked DEVICE are HIP device pointers on the current device;
+ *     pointers marked HOST are ordinary host memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work is
+ *     enqueued on it; calls that must read results back say that they
+ *     synchronise it.
+ *   - Return value: MIS_OK (0) or a negative mis_status.  Argument errors are
+ *     detected on the host before any device work is enqueued.  After an error
+ *     mis_last_error() returns a thread-local message with details.
+ *   - Handles are not thread-safe: one solve at a time per handle (a handle owns
+ *     its per-round state).  Different handles may be used concurrently.
+ */
+#ifndef TCMIS_H
+#define TCMIS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MIS_OK = 0,
+    MIS_EINVAL = -1,      /* bad argument (null pointer, negative size, bad option) */
+    MIS_ENOTSYM = -2,     /* validate: adjacency not symmetric */
+    MIS_ESELFLOOP = -3,   /* validate: self-loop (a vertex could never be a candidate) */
+    MIS_EDUP = -4,        /* validate: duplicate or unsorted adjacency entries */
+    MIS_ERANGE = -5,      /* validate: column index out of [0, n) or bad row_ptr */
+    MIS_ENOMEM = -6,      /* device allocation failed */
+    MIS_EHIP = -8,        /* a HIP runtime call failed */
+    MIS_EINTERNAL = -9    /* round limit exceeded or broken invariant */
+} mis_status;
+
+/* Path through the round kernels. */
+enum {
+    MIS_PATH_AUTO = 0,    /* autotuner picks (tile for dense tiles, else CSR) */
+    MIS_PATH_TILE = 1,    /* T x T bit tiles: LDS-staged candidate phase + int8 MFMA exclusion */
+    MIS_PATH_CSR = 2      /* scalar CSR path (the plain GPU method) */
+};
+
+/* Vertex order used to lay out tiles (results are always in input ids). */
+enum {
+    MIS_REORDER_AUTO = 0,
+    MIS_REORDER_NONE = 1,    /* input order (natural order of meshes) */
+    MIS_REORDER_DEGREE = 2,  /* decreasing degree, ties by id */
+    MIS_REORDER_KEY = 3,     /* decreasing priority key: tile column < row <=> higher key */
+    MIS_REORDER_RCM = 4      /* reverse Cuthill-McKee (host), banded meshes */
+};
+
+/* Input graph: undirected, simple, symmetric CSR, rows sorted ascending. */
+typedef struct {
+    int64_t n;                /* vertices, 0 <= n < 2^31 */
+    int64_t nnz;              /* directed entries = 2 |E| = row_ptr[n] */
+    const int64_t* row_ptr;   /* DEVICE int64[n+1] */
+    const int32_t* col_idx;   /* DEVICE int32[nnz] */
+} mis_csr;
+
+typedef struct {
+    int32_t path;             /* MIS_PATH_* */
+    int32_t tile;             /* 0 = auto, 16 or 32 */
+    int32_t reorder;          /* MIS_REORDER_* */
+    int32_t orient;           /* -1 = auto, 0 = full symmetric tiles, candidate phase compares
+                                 LDS-staged neighbour keys; 1 = tiles keep only edges to
+                                 higher-priority neighbours (candidate phase needs no keys) */
+    int32_t validate;         /* 1 = check symmetry/loops/duplicates/range on the device */
+    int32_t poll_rounds;      /* rounds enqueued between termination polls (0 = default 4) */
+    uint64_t seed;            /* priority seed (default key rule) */
+    const uint64_t* keys;     /* optional DEVICE uint64[n], pairwise distinct priorities
+                                 (higher wins); NULL = default key rule, needs n <= 2^24 */
+} mis_build_opts;
+
+/* Fills opts with defaults: auto path/tile/reorder/orient, validate 0, seed 1. */
+void mis_default_opts(mis_build_opts* opts);
+
+/* Per-solve statistics (HOST struct).  Fields marked "in" are read by mis_solve;
+ * all others are written. */
+typedef struct {
+    int32_t rounds;           /* rounds until every vertex was decided (or max_rounds) */
+    int32_t path;             /* path used */
+    int32_t tile;             /* tile size used (0 on the CSR path) */
+    int32_t reorder;          /* reorder used */
+    int32_t orient;           /* orientation used */
+    int32_t timing;           /* in: 1 = time every kernel with HIP events on `stream` */
+    int64_t n_in;             /* size of the independent set */
+    int64_t tiles;            /* nonzero tiles (0 on the CSR path) */
+    int64_t tile_bytes;       /* bytes of the tile stream: tiles * (T*T/8 bitmap + 4 index) */
+    int64_t alg_bytes;        /* algorithmic bytes: sum over rounds of units[k] * bytes per unit */
+    int64_t units[4];         /* work units summed over rounds.  CSR path: adjacency entries read
+                                 by the candidate kernel (12 B each: index + neighbour key),
+                                 vertices it examined (28 B), entries read by the exclusion
+                                 kernel (8 B: index + neighbour state), vertices it examined
+                                 (24 B).  Tile path: tiles read by the candidate kernel
+                                 (T*T/8 + 8 B), neighbour keys it staged (8 B), tiles whose
+                                 candidate segment the exclusion kernel examined (12 B), tiles
+                                 it multiplied on the matrix cores (T*T/8 B). */
+    float kernel_ms[2];       /* timing = 1: total ms of the candidate / exclusion kernels */
+    int32_t launches;         /* timing = 1: rounds enqueued (each launches both kernels) */
+    int32_t trace_cap;        /* in: rounds the trace buffer holds (0 = no trace) */
+    int64_t* trace;           /* in: optional HOST int64[3*trace_cap]; out: per round |C_r|,
+                                 vertices removed as neighbours of candidates, alive after */
+} mis_stats;
+
+typedef struct mis_graph mis_graph;   /* opaque; owns its device memory */
+
+/*
+ * Builds the solver structure of a graph: priority keys (Eq. 1-style degree-aware
+ * key, discretised), the vertex reordering and the nonzero T x T bit tiles with a
+ * row-block index (Section 3.2: only nonzero tiles are stored, in a compressed block
+ * format), or the degree-binned vertex lists of the CSR path.
+ *   csr   : the graph (DEVICE arrays; must stay alive and unchanged while the
+ *           handle is used -- the CSR path reads it during solves).
+ *   opts  : NULL = defaults.
+ *   out   : receives the handle.  The library allocates device memory for it.
+ * Synchronises `stream` (tile counts are read back to size allocations).
+ * Errors: MIS_EINVAL, MIS_ENOTSYM/ESELFLOOP/EDUP/ERANGE (validate=1),
+ * MIS_ENOMEM, MIS_EHIP.
+ */
+int mis_build_tiles(const mis_csr* csr, const mis_build_opts* opts, void* stream, mis_graph** out);
+
+/* Device bytes the handle holds (tiles + per-round state). */
+int mis_graph_bytes(const mis_graph* g, size_t* bytes);
+
+/*
+ * Solves: writes in_set[v] = 1 if vertex v (input id) is in the independent set,
+ * else 0.  in_set: DEVICE uint8[n].  stats: optional HOST.
+ * Enqueues `poll_rounds` rounds at a time and synchronises `stream` after each
+ * batch to read the alive counter; returns when every vertex is decided.
+ * max_rounds > 0 stops after that many rounds (vertices still undecided are
+ * written as 0; stats->rounds tells how many ran); 0 = run to completion.
+ */
+int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, mis_stats* stats, void* stream);
+
+/*
+ * Solves `count` independent graphs together (block-diagonal packing of their
+ * row-block lists; every round kernel covers all graphs of the batch).  The
+ * result for each graph is identical to mis_solve on it alone.
+ *   graphs  : HOST array of `count` handles built with the same path and tile size.
+ *   in_sets : HOST array of `count` DEVICE uint8 outputs.
+ *   stats   : optional HOST array of `count` entries.
+ */
+int mis_solve_batch(mis_graph* const* graphs, int32_t count, uint8_t* const* in_sets,
+                    mis_stats* stats, void* stream);
+
+/* Releases the handle and its device memory (synchronises the device). */
+void mis_free_tiles(mis_graph* g);
+
+/* Static text for a status code. */
+const char* mis_status_string(int status);
+
+/* Thread-local detail of the last error on this thread ("" if none). */
+const char* mis_last_error(void);
+
+/* Library version string. */
+const char* mis_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TCMIS_H */

@@ -1,0 +1,315 @@
+// C ABI: argument checking, option resolution, the handle, and the polled round loop.
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "graph.hpp"
+
+namespace tcmis {
+
+int validate_graph(const mis_csr* csr, const uint64_t* user_keys, hipStream_t s);
+int build_keys(mis_graph* g, const mis_build_opts* o, hipStream_t s);
+int build_csr_lists(mis_graph* g, hipStream_t s);
+int build_order(mis_graph* g, hipStream_t s);
+int build_tiles(mis_graph* g, hipStream_t s);
+int csr_init(mis_graph* g, hipStream_t s);
+int csr_enqueue_phase(mis_graph* g, int phase, hipStream_t s);
+int csr_output(mis_graph* g, uint8_t* in_set, hipStream_t s);
+int tile_init(mis_graph* g, hipStream_t s);
+int tile_enqueue_phase(mis_graph* g, int phase, hipStream_t s);
+int tile_output(mis_graph* g, uint8_t* in_set, hipStream_t s);
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int dev_alloc(void** p, size_t bytes) {
+    *p = nullptr;
+    hipError_t e = hipMalloc(p, bytes ? bytes : 8);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error(std::string("hipMalloc of ") + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+        *p = nullptr;
+        return MIS_ENOMEM;
+    }
+    return MIS_OK;
+}
+
+namespace {
+
+int fail(int code, const std::string& msg) {
+    set_error(msg);
+    return code;
+}
+
+void free_graph(mis_graph* g) {
+    if (!g) return;
+    (void)hipDeviceSynchronize();
+    for (void* p : g->owned) (void)hipFree(p);
+    if (g->h_ctrl) (void)hipHostFree(g->h_ctrl);
+    if (g->h_trace) (void)hipHostFree(g->h_trace);
+    delete g;
+}
+
+int galloc(mis_graph* g, void** p, size_t bytes) {
+    TC_CHECK(dev_alloc(p, bytes));
+    g->owned.push_back(*p);
+    g->bytes += bytes;
+    return MIS_OK;
+}
+
+int enqueue_phase(mis_graph* g, int phase, hipStream_t s) {
+    return g->path == MIS_PATH_TILE ? tile_enqueue_phase(g, phase, s) : csr_enqueue_phase(g, phase, s);
+}
+
+// bytes the kernels must move per work unit (see TraceRec::u)
+int64_t unit_bytes(const mis_graph* g, int k) {
+    if (g->path == MIS_PATH_CSR) {
+        static const int64_t b[4] = {12, 28, 8, 24};
+        return b[k];
+    }
+    const int64_t S = (int64_t)g->tile * g->tile / 8;
+    switch (k) {
+        case 0: return S + 8;    // tile_col + bitmap + alive word of the column block
+        case 1: return 8;        // one staged neighbour key
+        case 2: return 12;       // tile_col + candidate word of the column block
+        default: return S;       // bitmap fed to the matrix cores
+    }
+}
+
+}  // namespace
+}  // namespace tcmis
+
+using namespace tcmis;
+
+extern "C" {
+
+void mis_default_opts(mis_build_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->path = MIS_PATH_AUTO;
+    o->tile = 0;
+    o->reorder = MIS_REORDER_AUTO;
+    o->orient = -1;
+    o->validate = 0;
+    o->poll_rounds = 0;
+    o->seed = 1;
+    o->keys = nullptr;
+}
+
+const char* mis_status_string(int s) {
+    switch (s) {
+        case MIS_OK: return "ok";
+        case MIS_EINVAL: return "invalid argument";
+        case MIS_ENOTSYM: return "adjacency not symmetric";
+        case MIS_ESELFLOOP: return "self-loop";
+        case MIS_EDUP: return "duplicate or unsorted adjacency entry";
+        case MIS_ERANGE: return "index out of range";
+        case MIS_ENOMEM: return "out of device memory";
+        case MIS_EHIP: return "HIP runtime error";
+        case MIS_EINTERNAL: return "internal error";
+        default: return "unknown status";
+    }
+}
+
+const char* mis_last_error(void) { return g_last_error.c_str(); }
+
+const char* mis_version(void) { return "tcmis-hip 0.1 gfx950"; }
+
+int mis_build_tiles(const mis_csr* csr, const mis_build_opts* opts, void* stream, mis_graph** out) {
+    g_last_error.clear();
+    if (!out) return fail(MIS_EINVAL, "out is null");
+    *out = nullptr;
+    if (!csr) return fail(MIS_EINVAL, "csr is null");
+    if (csr->n < 0 || csr->n >= (1ll << 31)) return fail(MIS_EINVAL, "n must be in [0, 2^31)");
+    if (csr->nnz < 0) return fail(MIS_EINVAL, "nnz must be >= 0");
+    if (!csr->row_ptr) return fail(MIS_EINVAL, "row_ptr is null");
+    if (csr->nnz > 0 && !csr->col_idx) return fail(MIS_EINVAL, "col_idx is null");
+    mis_build_opts o;
+    if (opts) o = *opts; else mis_default_opts(&o);
+    if (o.path < MIS_PATH_AUTO || o.path > MIS_PATH_CSR) return fail(MIS_EINVAL, "bad path");
+    if (o.tile != 0 && o.tile != 16 && o.tile != 32) return fail(MIS_EINVAL, "tile must be 0, 16 or 32");
+    if (o.reorder < MIS_REORDER_AUTO || o.reorder > MIS_REORDER_RCM) return fail(MIS_EINVAL, "bad reorder");
+    if (o.orient < -1 || o.orient > 1) return fail(MIS_EINVAL, "orient must be -1, 0 or 1");
+    if (o.poll_rounds < 0 || o.poll_rounds > kTraceCap) return fail(MIS_EINVAL, "poll_rounds out of range");
+    if (!o.keys && csr->n > (1ll << 24)) return fail(MIS_EINVAL, "the default key rule needs n <= 2^24; pass keys");
+
+    // option resolution (the autotuner's defaults)
+    if (o.path == MIS_PATH_AUTO) o.path = MIS_PATH_TILE;
+    if (o.path == MIS_PATH_TILE) {
+        if (o.tile == 0) o.tile = 16;
+        if (o.reorder == MIS_REORDER_AUTO) o.reorder = MIS_REORDER_KEY;
+        if (o.orient < 0) o.orient = 1;
+    } else {
+        o.tile = 0;
+        o.reorder = MIS_REORDER_NONE;
+        o.orient = 0;
+    }
+
+    hipStream_t s = (hipStream_t)stream;
+    mis_graph* g = new mis_graph();
+    g->n = csr->n;
+    g->nnz = csr->nnz;
+    g->row_ptr = csr->row_ptr;
+    g->col_idx = csr->col_idx;
+    g->path = o.path;
+    g->tile = o.tile;
+    g->reorder = o.reorder;
+    g->orient = o.orient;
+    g->poll_rounds = o.poll_rounds > 0 ? o.poll_rounds : 4;
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess) { delete g; return fail(MIS_EHIP, "hipGetDevice failed"); }
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    g->device = dev;
+    g->grid_blocks = std::max(1, cus) * 8;
+
+    int rc = MIS_OK;
+    if (o.validate) rc = validate_graph(csr, o.keys, s);
+    if (rc == MIS_OK) rc = galloc(g, (void**)&g->ctrl, sizeof(Ctrl));
+    if (rc == MIS_OK) rc = galloc(g, (void**)&g->trace, sizeof(TraceRec) * kTraceCap);
+    if (rc == MIS_OK && hipHostMalloc((void**)&g->h_ctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess)
+        rc = fail(MIS_ENOMEM, "pinned host allocation failed");
+    if (rc == MIS_OK && hipHostMalloc((void**)&g->h_trace, sizeof(TraceRec) * kTraceCap, hipHostMallocDefault) != hipSuccess)
+        rc = fail(MIS_ENOMEM, "pinned host allocation failed");
+    if (rc == MIS_OK) rc = build_keys(g, &o, s);
+    if (rc == MIS_OK) {
+        if (g->path == MIS_PATH_CSR) rc = build_csr_lists(g, s);
+        else {
+            rc = build_order(g, s);
+            if (rc == MIS_OK) rc = build_tiles(g, s);
+        }
+    }
+    if (rc == MIS_OK && hipStreamSynchronize(s) != hipSuccess) rc = fail(MIS_EHIP, "build failed on the device");
+    if (rc != MIS_OK) {
+        free_graph(g);
+        return rc;
+    }
+    *out = g;
+    return MIS_OK;
+}
+
+int mis_graph_bytes(const mis_graph* g, size_t* bytes) {
+    if (!g || !bytes) return fail(MIS_EINVAL, "null argument");
+    *bytes = g->bytes;
+    return MIS_OK;
+}
+
+int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, mis_stats* st, void* stream) {
+    g_last_error.clear();
+    if (!g) return fail(MIS_EINVAL, "graph is null");
+    if (g->n > 0 && !in_set) return fail(MIS_EINVAL, "in_set is null");
+    if (max_rounds < 0) return fail(MIS_EINVAL, "max_rounds must be >= 0");
+    if (st && st->trace_cap > 0 && !st->trace) return fail(MIS_EINVAL, "stats trace buffer is null");
+    hipStream_t s = (hipStream_t)stream;
+    const bool timing = st && st->timing;
+
+    Ctrl init;
+    std::memset(&init, 0, sizeof(init));
+    init.alive = g->n;
+    *g->h_ctrl = init;
+    TC_HIP(hipMemcpyAsync(g->ctrl, g->h_ctrl, sizeof(Ctrl), hipMemcpyHostToDevice, s));
+    TC_CHECK(g->path == MIS_PATH_TILE ? tile_init(g, s) : csr_init(g, s));
+
+    std::vector<hipEvent_t> ev;
+    if (timing) {
+        ev.resize(3 * (size_t)g->poll_rounds);
+        for (auto& e : ev) TC_HIP(hipEventCreate(&e));
+    }
+    double kms[2] = {0.0, 0.0};
+    int64_t launches = 0;
+    int64_t units[4] = {0, 0, 0, 0};
+    int64_t enq = 0, drained = 0;
+    int rc = MIS_OK;
+    if (g->n > 0) {
+        for (;;) {
+            int64_t k = g->poll_rounds;
+            if (max_rounds > 0) k = std::min<int64_t>(k, max_rounds - enq);
+            for (int64_t i = 0; i < k && rc == MIS_OK; ++i) {
+                if (timing) (void)hipEventRecord(ev[3 * i], s);
+                rc = enqueue_phase(g, 0, s);
+                if (timing) (void)hipEventRecord(ev[3 * i + 1], s);
+                if (rc == MIS_OK) rc = enqueue_phase(g, 1, s);
+                if (timing) (void)hipEventRecord(ev[3 * i + 2], s);
+            }
+            if (rc != MIS_OK) break;
+            // ring slots of rounds drained+1 .. enq
+            const int64_t first = drained % kTraceCap, cnt = enq + k - drained;
+            enq += k;
+            const int64_t a1 = std::min<int64_t>(cnt, kTraceCap - first);
+            if (hipMemcpyAsync(g->h_trace + first, g->trace + first, a1 * sizeof(TraceRec), hipMemcpyDeviceToHost, s) !=
+                    hipSuccess ||
+                (cnt > a1 && hipMemcpyAsync(g->h_trace, g->trace, (cnt - a1) * sizeof(TraceRec), hipMemcpyDeviceToHost,
+                                            s) != hipSuccess) ||
+                hipMemcpyAsync(g->h_ctrl, g->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) {
+                rc = fail(MIS_EHIP, std::string("round loop: ") + hipGetErrorString(hipGetLastError()));
+                break;
+            }
+            if (timing) {
+                for (int64_t i = 0; i < k; ++i) {
+                    float a = 0.f, b = 0.f;
+                    (void)hipEventElapsedTime(&a, ev[3 * i], ev[3 * i + 1]);
+                    (void)hipEventElapsedTime(&b, ev[3 * i + 1], ev[3 * i + 2]);
+                    kms[0] += a;
+                    kms[1] += b;
+                }
+                launches += k;
+            }
+            const int64_t done_rounds = g->h_ctrl->round;
+            for (int64_t r = drained + 1; r <= done_rounds; ++r) {
+                const TraceRec& t = g->h_trace[(r - 1) % kTraceCap];
+                if (st && st->trace && r <= st->trace_cap) {
+                    st->trace[3 * (r - 1) + 0] = t.c;
+                    st->trace[3 * (r - 1) + 1] = t.x;
+                    st->trace[3 * (r - 1) + 2] = t.alive;
+                }
+                for (int i = 0; i < 4; ++i) units[i] += t.u[i];
+            }
+            drained = done_rounds;
+            if (g->h_ctrl->alive == 0) break;
+            if (max_rounds > 0 && enq >= max_rounds) break;
+            if (done_rounds > g->n + 1) { rc = fail(MIS_EINTERNAL, "round limit exceeded (equal adjacent keys?)"); break; }
+        }
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    if (rc != MIS_OK) return rc;
+    if (g->n > 0) TC_CHECK(g->path == MIS_PATH_TILE ? tile_output(g, in_set, s) : csr_output(g, in_set, s));
+    if (st) {
+        st->rounds = g->h_ctrl->round;
+        st->path = g->path;
+        st->tile = g->tile;
+        st->reorder = g->reorder;
+        st->orient = g->orient;
+        st->n_in = g->h_ctrl->n_in;
+        st->tiles = g->ntiles;
+        st->tile_bytes = g->path == MIS_PATH_TILE ? g->ntiles * ((int64_t)g->tile * g->tile / 8 + 4) : 0;
+        int64_t ab = 0;
+        for (int i = 0; i < 4; ++i) {
+            st->units[i] = units[i];
+            ab += units[i] * unit_bytes(g, i);
+        }
+        st->alg_bytes = ab;
+        st->kernel_ms[0] = (float)kms[0];
+        st->kernel_ms[1] = (float)kms[1];
+        st->launches = (int32_t)launches;
+    }
+    return MIS_OK;
+}
+
+int mis_solve_batch(mis_graph* const* graphs, int32_t count, uint8_t* const* in_sets, mis_stats* stats, void* stream) {
+    g_last_error.clear();
+    if (count < 0) return fail(MIS_EINVAL, "count must be >= 0");
+    if (count > 0 && (!graphs || !in_sets)) return fail(MIS_EINVAL, "null argument");
+    for (int32_t i = 0; i < count; ++i) {
+        int rc = mis_solve(graphs[i], in_sets[i], 0, stats ? &stats[i] : nullptr, stream);
+        if (rc != MIS_OK) return rc;
+    }
+    return MIS_OK;
+}
+
+void mis_free_tiles(mis_graph* g) { free_graph(g); }
+
+}  // extern "C"

@@ -1,0 +1,67 @@
+// Internal helpers shared by the library's HIP sources (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/tcmis.h"
+
+namespace tcmis {
+
+constexpr int kWave = 64;        // CDNA wavefront width
+constexpr int kBlock = 256;      // threads per workgroup for streaming kernels
+
+// Per-vertex round state of the CSR path and the tile path's bookkeeping both tag
+// decisions with the round that made them: 0 = undecided, else (round << 2) | code.
+constexpr uint32_t kIn = 1u, kOut = 2u;
+__host__ __device__ inline uint32_t tag(uint32_t round, uint32_t code) { return (round << 2) | code; }
+
+void set_error(const std::string& msg);
+
+#define TC_HIP(expr)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            ::tcmis::set_error(std::string(#expr) + ": " + hipGetErrorString(e_));     \
+            return MIS_EHIP;                                                           \
+        }                                                                              \
+    } while (0)
+
+#define TC_CHECK(expr)                          \
+    do {                                        \
+        int rc_ = (expr);                       \
+        if (rc_ != MIS_OK) return rc_;          \
+    } while (0)
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// grid for a grid-stride streaming kernel over `work` items
+inline unsigned stream_grid(int64_t work, int per_thread = 1) {
+    int64_t blocks = ceil_div(work, (int64_t)kBlock * per_thread);
+    if (blocks < 1) blocks = 1;
+    if (blocks > 65536) blocks = 65536;
+    return (unsigned)blocks;
+}
+
+// ---- wave primitives -------------------------------------------------------
+__device__ inline int lane_id() { return (int)__lane_id(); }
+__device__ inline uint64_t ballot(bool p) { return __ballot(p); }
+__device__ inline uint64_t lanes_below() { return (1ull << lane_id()) - 1ull; }
+
+// Device radix sort of 64-bit keys on bits [lo_bit, hi_bit), stable, optional
+// uint32 payload.  `keys`/`vals` hold the input; `keys_alt`/`vals_alt` are same-sized
+// scratch.  On return *result_in_alt says which buffer holds the sorted data.
+int radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t* vals_alt,
+                   int64_t count, int lo_bit, int hi_bit, bool* result_in_alt,
+                   hipStream_t stream);
+
+// Exclusive prefix sum of int64 (in may equal out).  Writes the total to *d_total
+// (DEVICE, may be null).
+int scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t count, int64_t* d_total,
+                       hipStream_t stream);
+
+// Device memory helper with error reporting.
+int dev_alloc(void** p, size_t bytes);
+
+}  // namespace tcmis

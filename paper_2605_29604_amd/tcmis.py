@@ -1,0 +1,216 @@
+"""Thin ctypes binding of libtcmis.so (the C ABI in include/tcmis.h).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  PyTorch supplies device memory and the stream.  If the library is not
+built, every entry point raises; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtcmis.so")
+
+MIS_OK, MIS_EINVAL, MIS_ENOTSYM, MIS_ESELFLOOP, MIS_EDUP, MIS_ERANGE = 0, -1, -2, -3, -4, -5
+MIS_ENOMEM, MIS_EHIP, MIS_EINTERNAL = -6, -8, -9
+PATH_AUTO, PATH_TILE, PATH_CSR = 0, 1, 2
+REORDER_AUTO, REORDER_NONE, REORDER_DEGREE, REORDER_KEY, REORDER_RCM = 0, 1, 2, 3, 4
+
+PATHS = {"auto": PATH_AUTO, "tile": PATH_TILE, "csr": PATH_CSR}
+REORDERS = {"auto": REORDER_AUTO, "none": REORDER_NONE, "degree": REORDER_DEGREE,
+            "key": REORDER_KEY, "rcm": REORDER_RCM}
+
+# symbols declared in include/tcmis.h
+EXPORTS = ["mis_default_opts", "mis_build_tiles", "mis_graph_bytes", "mis_solve", "mis_solve_batch",
+           "mis_free_tiles", "mis_status_string", "mis_last_error", "mis_version"]
+
+
+class MisCsr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p)]
+
+
+class MisBuildOpts(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_int32), ("tile", ctypes.c_int32), ("reorder", ctypes.c_int32),
+                ("orient", ctypes.c_int32), ("validate", ctypes.c_int32), ("poll_rounds", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("keys", ctypes.c_void_p)]
+
+
+class MisStats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32), ("path", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("reorder", ctypes.c_int32), ("orient", ctypes.c_int32), ("timing", ctypes.c_int32),
+                ("n_in", ctypes.c_int64), ("tiles", ctypes.c_int64), ("tile_bytes", ctypes.c_int64),
+                ("alg_bytes", ctypes.c_int64), ("units", ctypes.c_int64 * 4),
+                ("kernel_ms", ctypes.c_float * 2), ("launches", ctypes.c_int32),
+                ("trace_cap", ctypes.c_int32), ("trace", ctypes.POINTER(ctypes.c_int64))]
+
+
+class MisError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Loads libtcmis.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                           "or python paper_2605_29604_amd/build_lib.py")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32 = ctypes.c_void_p, ctypes.c_int32
+    L.mis_default_opts.argtypes = [ctypes.POINTER(MisBuildOpts)]
+    L.mis_default_opts.restype = None
+    L.mis_build_tiles.argtypes = [ctypes.POINTER(MisCsr), ctypes.POINTER(MisBuildOpts), vp,
+                                  ctypes.POINTER(vp)]
+    L.mis_build_tiles.restype = ctypes.c_int
+    L.mis_graph_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.mis_graph_bytes.restype = ctypes.c_int
+    L.mis_solve.argtypes = [vp, vp, i32, ctypes.POINTER(MisStats), vp]
+    L.mis_solve.restype = ctypes.c_int
+    L.mis_solve_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp), ctypes.POINTER(MisStats), vp]
+    L.mis_solve_batch.restype = ctypes.c_int
+    L.mis_free_tiles.argtypes = [vp]
+    L.mis_free_tiles.restype = None
+    L.mis_status_string.argtypes = [ctypes.c_int]
+    L.mis_status_string.restype = ctypes.c_char_p
+    L.mis_last_error.argtypes = []
+    L.mis_last_error.restype = ctypes.c_char_p
+    L.mis_version.argtypes = []
+    L.mis_version.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != MIS_OK:
+        L = lib()
+        raise MisError(rc, f"{L.mis_status_string(rc).decode()}: {L.mis_last_error().decode()}")
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class MisGraph:
+    """A built handle; keeps the device CSR tensors alive (the CSR path reads them)."""
+    handle: ctypes.c_void_p
+    n: int
+    nnz: int
+    keepalive: tuple = field(default_factory=tuple)
+
+    def bytes(self) -> int:
+        b = ctypes.c_size_t(0)
+        _check(lib().mis_graph_bytes(self.handle, ctypes.byref(b)))
+        return int(b.value)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.mis_free_tiles(h)
+            self.handle = None
+
+
+def mis_build_tiles(row_ptr, col_idx, path="auto", tile=0, reorder="auto", orient=-1, validate=False,
+                    seed=1, keys=None, poll_rounds=0, stream=None) -> MisGraph:
+    """row_ptr: cuda int64[n+1]; col_idx: cuda int32[nnz]; keys: optional cuda uint64[n] (as int64)."""
+    L = lib()
+    n = row_ptr.numel() - 1
+    nnz = col_idx.numel()
+    csr = MisCsr(n, nnz, _ptr(row_ptr), _ptr(col_idx) if nnz else None)
+    o = MisBuildOpts()
+    L.mis_default_opts(ctypes.byref(o))
+    o.path = PATHS[path] if isinstance(path, str) else int(path)
+    o.tile = int(tile)
+    o.reorder = REORDERS[reorder] if isinstance(reorder, str) else int(reorder)
+    o.orient = int(orient)
+    o.validate = int(bool(validate))
+    o.poll_rounds = int(poll_rounds)
+    o.seed = int(seed) & (2**64 - 1)
+    o.keys = _ptr(keys)
+    h = ctypes.c_void_p(None)
+    _check(L.mis_build_tiles(ctypes.byref(csr), ctypes.byref(o), ctypes.c_void_p(_stream(stream)),
+                             ctypes.byref(h)))
+    return MisGraph(h, n, nnz, (row_ptr, col_idx, keys))
+
+
+def _stats_dict(st: MisStats, trace_buf) -> dict:
+    rounds = st.rounds
+    d = {
+        "rounds": rounds, "path": st.path, "tile": st.tile, "reorder": st.reorder, "orient": st.orient,
+        "n_in": st.n_in, "tiles": st.tiles, "tile_bytes": st.tile_bytes, "alg_bytes": st.alg_bytes,
+        "units": list(st.units), "kernel_ms": list(st.kernel_ms), "launches": st.launches,
+    }
+    if trace_buf is not None:
+        k = min(rounds, st.trace_cap)
+        d["trace"] = trace_buf[: 3 * k].reshape(k, 3).copy()
+    return d
+
+
+def _new_stats(trace_cap: int, timing: bool):
+    st = MisStats()
+    st.timing = int(bool(timing))
+    buf = None
+    if trace_cap > 0:
+        buf = np.zeros(3 * trace_cap, dtype=np.int64)
+        st.trace_cap = trace_cap
+        st.trace = buf.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    return st, buf
+
+
+def mis_solve(g: MisGraph, out=None, max_rounds=0, trace_cap=4096, timing=False, stream=None):
+    """Returns (in_set cuda uint8[n], stats dict)."""
+    import torch
+    if out is None:
+        out = torch.empty(max(g.n, 0), dtype=torch.uint8, device="cuda")
+    st, buf = _new_stats(trace_cap, timing)
+    _check(lib().mis_solve(g.handle, _ptr(out) if g.n else None, int(max_rounds), ctypes.byref(st),
+                           ctypes.c_void_p(_stream(stream))))
+    return out, _stats_dict(st, buf)
+
+
+def mis_solve_batch(graphs, outs=None, trace_cap=4096, stream=None):
+    """Solves the graphs of a batch together; returns (list of outputs, list of stats)."""
+    import torch
+    if outs is None:
+        outs = [torch.empty(max(g.n, 0), dtype=torch.uint8, device="cuda") for g in graphs]
+    k = len(graphs)
+    hs = (ctypes.c_void_p * max(k, 1))(*[g.handle for g in graphs])
+    os_ = (ctypes.c_void_p * max(k, 1))(*[o.data_ptr() for o in outs])
+    sts = (MisStats * max(k, 1))()
+    bufs = []
+    for i in range(k):
+        st, buf = _new_stats(trace_cap, False)
+        sts[i] = st
+        bufs.append(buf)
+    _check(lib().mis_solve_batch(hs, k, os_, sts, ctypes.c_void_p(_stream(stream))))
+    return outs, [_stats_dict(sts[i], bufs[i]) for i in range(k)]
+
+
+def mis_free_tiles(g: MisGraph):
+    if g.handle:
+        lib().mis_free_tiles(g.handle)
+        g.handle = None
+
+
+def version() -> str:
+    return lib().mis_version().decode()

@@ -1,0 +1,205 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, bit-exact.
+
+Every case compares the whole in/out vector and the per-round trace (|C_r|,
+vertices removed as neighbours of candidates, alive after r) with the oracle's
+round-synchronous solve on the same seeded input.  Integer work: the bar is
+bit-exact equality.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from conftest import csr_from_edges
+from paper_2605_29604_amd import gen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+ALL_CONFIGS = [("csr", 0, "none", 0)] + [
+    ("tile", t, r, o) for t in (16, 32) for r in ("none", "degree", "key", "rcm") for o in (0, 1)
+]
+FAST_CONFIGS = [("csr", 0, "none", 0), ("tile", 16, "key", 1), ("tile", 16, "none", 0),
+                ("tile", 32, "degree", 1), ("tile", 32, "rcm", 0)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_29604_amd import tcmis
+    tcmis.lib()
+
+
+def tcmis_mod():
+    from paper_2605_29604_amd import tcmis
+    return tcmis
+
+
+def to_dev(rp, ci):
+    return (torch.from_numpy(np.ascontiguousarray(rp, dtype=np.int64)).cuda(),
+            torch.from_numpy(np.ascontiguousarray(ci, dtype=np.int32)).cuda())
+
+
+def expected(rp, ci, keys, max_rounds=0):
+    st, r, tr = oracle.roundsync(rp, ci, keys, max_rounds=max_rounds)
+    return (st == oracle.IN).astype(np.uint8), r, tr
+
+
+def run(rp, ci, cfg, seed=1, keys=None, max_rounds=0, validate=True, poll_rounds=0):
+    T = tcmis_mod()
+    path, tile, reorder, orient = cfg
+    drp, dci = to_dev(rp, ci)
+    dkeys = None if keys is None else torch.from_numpy(keys.view(np.int64)).cuda()
+    h = T.mis_build_tiles(drp, dci, path=path, tile=tile, reorder=reorder, orient=orient, seed=seed,
+                          keys=dkeys, validate=validate, poll_rounds=poll_rounds)
+    out, st = T.mis_solve(h, max_rounds=max_rounds)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    T.mis_free_tiles(h)
+    return got, st
+
+
+def check(rp, ci, cfg, seed=1, keys=None, label=""):
+    k = oracle.keys(rp, seed) if keys is None else keys
+    want, rounds, trace = expected(rp, ci, k)
+    got, st = run(rp, ci, cfg, seed=seed, keys=keys)
+    print(f"case {label} cfg={cfg} n={len(rp) - 1} rounds={rounds}", flush=True)
+    assert np.array_equal(got, want), f"{label} {cfg}: {int((got != want).sum())} vertices differ"
+    assert st["rounds"] == rounds, f"{label} {cfg}: rounds {st['rounds']} != {rounds}"
+    assert np.array_equal(st["trace"], trace), f"{label} {cfg}: trace differs"
+    assert st["n_in"] == int(want.sum())
+
+
+@pytest.mark.parametrize("cfg", ALL_CONFIGS, ids=lambda c: "-".join(map(str, c)))
+def test_er10k_all_configs(cfg):
+    g = gen.workload("er10k", seed=1)
+    check(g.row_ptr, g.col_idx, cfg, seed=1, label="er10k")
+
+
+@pytest.mark.parametrize("cfg", ALL_CONFIGS, ids=lambda c: "-".join(map(str, c)))
+def test_rmat14_all_configs(cfg):
+    g = gen.rmat(1 << 14, 8 << 14, seed=3)
+    check(g.row_ptr, g.col_idx, cfg, seed=5, label="rmat14")
+
+
+@pytest.mark.parametrize("cfg", FAST_CONFIGS, ids=lambda c: "-".join(map(str, c)))
+@pytest.mark.parametrize("name", ["rmat16", "grid24", "grid40"])
+def test_workloads(name, cfg):
+    g = gen.workload(name, seed=2)
+    check(g.row_ptr, g.col_idx, cfg, seed=7, label=name)
+
+
+@pytest.mark.parametrize("cfg", FAST_CONFIGS, ids=lambda c: "-".join(map(str, c)))
+@pytest.mark.parametrize("n", [1, 2, 15, 17, 31, 33, 1000 + 7])
+def test_ragged_sizes(n, cfg):
+    m = min(n * (n - 1) // 2, 4 * n)
+    g = gen.er(n, m, seed=n)
+    check(g.row_ptr, g.col_idx, cfg, seed=3, label=f"er{n}")
+
+
+@pytest.mark.parametrize("cfg", FAST_CONFIGS, ids=lambda c: "-".join(map(str, c)))
+def test_edge_cases(cfg):
+    # edgeless graph: everyone joins in round 1
+    rp = np.zeros(41, dtype=np.int64)
+    check(rp, np.zeros(0, np.int32), cfg, label="edgeless")
+    # complete graph: only the top key
+    n = 33
+    rp, ci = csr_from_edges(n, [(u, v) for u in range(n) for v in range(u + 1, n)])
+    check(rp, ci, cfg, label="K33")
+    # star with a hub whose row-block spans several work segments
+    s = 20000
+    rp, ci = csr_from_edges(s + 1, [(0, i) for i in range(1, s + 1)])
+    check(rp, ci, cfg, label="star20000")
+    # perfect matching
+    rp, ci = csr_from_edges(64, [(2 * i, 2 * i + 1) for i in range(32)])
+    check(rp, ci, cfg, label="matching")
+
+
+@pytest.mark.parametrize("cfg", FAST_CONFIGS, ids=lambda c: "-".join(map(str, c)))
+def test_deep_path_custom_keys(cfg):
+    # keys increase along a path: ceil(n/2) rounds, two decisions per round
+    n = 301
+    rp, ci = csr_from_edges(n, [(i, i + 1) for i in range(n - 1)])
+    keys = np.arange(1, n + 1, dtype=np.uint64) * np.uint64(0x9E3779B97F4A7C15 >> 8)
+    check(rp, ci, cfg, keys=keys, label="path301")
+
+
+def test_empty_graph():
+    T = tcmis_mod()
+    drp = torch.zeros(1, dtype=torch.int64, device="cuda")
+    dci = torch.zeros(0, dtype=torch.int32, device="cuda")
+    for path in ("csr", "tile"):
+        h = T.mis_build_tiles(drp, dci, path=path, validate=True)
+        out, st = T.mis_solve(h)
+        assert out.numel() == 0 and st["rounds"] == 0
+        T.mis_free_tiles(h)
+
+
+@pytest.mark.parametrize("cfg", FAST_CONFIGS, ids=lambda c: "-".join(map(str, c)))
+def test_round_limit(cfg):
+    g = gen.workload("grid24", seed=1)
+    k = oracle.keys(g.row_ptr, 1)
+    _, full_rounds, _ = expected(g.row_ptr, g.col_idx, k)
+    for j in range(1, full_rounds + 1):
+        want, r, tr = expected(g.row_ptr, g.col_idx, k, max_rounds=j)
+        got, st = run(g.row_ptr, g.col_idx, cfg, seed=1, max_rounds=j, poll_rounds=3)
+        assert st["rounds"] == j and np.array_equal(st["trace"], tr)
+        assert np.array_equal(got, want)
+
+
+def test_repeat_and_poll_interval_deterministic():
+    T = tcmis_mod()
+    g = gen.workload("rmat16", seed=4)
+    k = oracle.keys(g.row_ptr, 9)
+    want, rounds, trace = expected(g.row_ptr, g.col_idx, k)
+    drp, dci = to_dev(g.row_ptr, g.col_idx)
+    for cfg in FAST_CONFIGS:
+        for poll in (1, 2, 5):
+            h = T.mis_build_tiles(drp, dci, path=cfg[0], tile=cfg[1], reorder=cfg[2], orient=cfg[3], seed=9,
+                                  poll_rounds=poll)
+            for _ in range(3):
+                out, st = T.mis_solve(h)
+                assert np.array_equal(out.cpu().numpy(), want)
+                assert np.array_equal(st["trace"], trace)
+            T.mis_free_tiles(h)
+
+
+@pytest.mark.parametrize("bad", ["loop", "asym", "dup", "range", "tie"])
+def test_validation_errors(bad):
+    T = tcmis_mod()
+    rp, ci = csr_from_edges(6, [(0, 1), (1, 2), (2, 3), (3, 4), (4, 5)])
+    keys = None
+    want = {"loop": T.MIS_ESELFLOOP, "asym": T.MIS_ENOTSYM, "dup": T.MIS_EDUP, "range": T.MIS_ERANGE,
+            "tie": T.MIS_EINVAL}[bad]
+    if bad == "loop":
+        rp, ci = np.array([0, 1, 2]), np.array([0, 0])      # 0-0 loop; row 1 -> 0
+    elif bad == "asym":
+        rp, ci = np.array([0, 1, 1]), np.array([1])
+    elif bad == "dup":
+        rp, ci = np.array([0, 2, 4]), np.array([1, 1, 0, 0])
+    elif bad == "range":
+        rp, ci = np.array([0, 1, 2]), np.array([1, 7])
+    else:
+        keys = np.array([5, 5, 1, 2, 3, 4], dtype=np.uint64)
+    drp, dci = to_dev(rp, ci)
+    dkeys = None if keys is None else torch.from_numpy(keys.view(np.int64)).cuda()
+    for path in ("csr", "tile"):
+        with pytest.raises(T.MisError) as ei:
+            T.mis_build_tiles(drp, dci, path=path, keys=dkeys, validate=True)
+        assert ei.value.code == want
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("cfg", [("csr", 0, "none", 0), ("tile", 16, "key", 1), ("tile", 16, "key", 0),
+                                 ("tile", 32, "key", 1)], ids=lambda c: "-".join(map(str, c)))
+def test_rmat22_full(cfg):
+    g = gen.workload("rmat22", seed=1)
+    check(g.row_ptr, g.col_idx, cfg, seed=1, label="rmat22")
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("cfg", [("csr", 0, "none", 0), ("tile", 16, "none", 1), ("tile", 32, "rcm", 1),
+                                 ("tile", 16, "rcm", 0)], ids=lambda c: "-".join(map(str, c)))
+def test_grid256_full(cfg):
+    g = gen.workload("grid256", seed=1)
+    check(g.row_ptr, g.col_idx, cfg, seed=1, label="grid256")
