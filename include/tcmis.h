@@ -39,7 +39,7 @@ typedef enum {
     MIS_ESELFLOOP = -3,   /* validate: self-loop (a vertex could never be a candidate) */
     MIS_EDUP = -4,        /* validate: duplicate or unsorted adjacency entries */
     MIS_ERANGE = -5,      /* validate: column index out of [0, n) or bad row_ptr */
-    MIS_ENOMEM = -6,      /* device allocation failed */
+    MIS_ENOMEM = -6,      /* host allocation failed */
     MIS_EHIP = -8,        /* a HIP runtime call failed */
     MIS_EINTERNAL = -9    /* round limit exceeded or broken invariant */
 } mis_status;
@@ -116,21 +116,37 @@ typedef struct {
 typedef struct mis_graph mis_graph;   /* opaque; owns its device memory */
 
 /*
- * Builds the solver structure of a graph: priority keys (Eq. 1-style degree-aware
- * key, discretised), the vertex reordering and the nonzero T x T bit tiles with a
- * row-block index (Section 3.2: only nonzero tiles are stored, in a compressed block
- * format), or the degree-binned vertex lists of the CSR path.
- *   csr   : the graph (DEVICE arrays; must stay alive and unchanged while the
- *           handle is used -- the CSR path reads it during solves).
- *   opts  : NULL = defaults.
- *   out   : receives the handle.  The library allocates device memory for it.
- * Synchronises `stream` (tile counts are read back to size allocations).
- * Errors: MIS_EINVAL, MIS_ENOTSYM/ESELFLOOP/EDUP/ERANGE (validate=1),
- * MIS_ENOMEM, MIS_EHIP.
+ * Device workspace bytes that mis_build_tiles needs for this graph and these
+ * options (host-only arithmetic on n, nnz and the options; no device access).
+ * The figure is an upper bound (tile counts are bounded by the entry count), and
+ * it is the handle's whole device footprint: tiles, keys, per-round state,
+ * build temporaries.
  */
-int mis_build_tiles(const mis_csr* csr, const mis_build_opts* opts, void* stream, mis_graph** out);
+int mis_build_bytes(const mis_csr* csr, const mis_build_opts* opts, size_t* bytes);
 
-/* Device bytes the handle holds (tiles + per-round state). */
+/*
+ * Builds the solver structure of a graph inside a caller-provided workspace:
+ * priority keys (the degree-aware priority of Eq. 1, discretised), the vertex
+ * reordering and the nonzero T x T bit tiles with a row-block index (Section 3.2:
+ * only nonzero tiles are stored, in a compressed block format), or the
+ * degree-binned vertex lists of the CSR path.
+ *   csr       : the graph (DEVICE arrays; must stay alive and unchanged while the
+ *               handle is used -- the CSR path reads it during solves).
+ *   opts      : NULL = defaults.
+ *   workspace : DEVICE memory of at least mis_build_bytes bytes, 256-byte aligned,
+ *               owned by the caller; it must outlive the handle and must not be
+ *               touched while work of the handle is in flight.
+ *   out       : receives the handle (host memory owned by the library).
+ * All device work is enqueued on `stream`; nothing is allocated on the device and
+ * the stream is not synchronised, except with validate = 1 (the error flags are
+ * read back) or reorder = MIS_REORDER_RCM (the order is computed on the host).
+ * Errors: MIS_EINVAL (also: workspace too small or misaligned),
+ * MIS_ENOTSYM/ESELFLOOP/EDUP/ERANGE (validate = 1), MIS_EHIP.
+ */
+int mis_build_tiles(const mis_csr* csr, const mis_build_opts* opts, void* workspace, size_t workspace_bytes,
+                    void* stream, mis_graph** out);
+
+/* Workspace bytes the handle uses (as mis_build_bytes reported for it). */
 int mis_graph_bytes(const mis_graph* g, size_t* bytes);
 
 /*
@@ -154,7 +170,7 @@ int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, mis_stats* stat
 int mis_solve_batch(mis_graph* const* graphs, int32_t count, uint8_t* const* in_sets,
                     mis_stats* stats, void* stream);
 
-/* Releases the handle and its device memory (synchronises the device). */
+/* Releases the handle (host memory only; the workspace stays the caller's). */
 void mis_free_tiles(mis_graph* g);
 
 /* Static text for a status code. */

@@ -1,23 +1,24 @@
 // C ABI: argument checking, option resolution, the handle, and the polled round loop.
 #include <algorithm>
+#include <new>
 #include <cstring>
 #include <string>
 #include <vector>
 
-#include "graph.hpp"
+#include "round.hpp"
 
 namespace tcmis {
 
-int validate_graph(const mis_csr* csr, const uint64_t* user_keys, hipStream_t s);
+int validate_graph(const mis_csr* csr, const uint64_t* user_keys, uint32_t* d_err, hipStream_t s);
 int build_keys(mis_graph* g, const mis_build_opts* o, hipStream_t s);
 int build_csr_lists(mis_graph* g, hipStream_t s);
 int build_order(mis_graph* g, hipStream_t s);
 int build_tiles(mis_graph* g, hipStream_t s);
 int csr_init(mis_graph* g, hipStream_t s);
-int csr_enqueue_phase(mis_graph* g, int phase, hipStream_t s);
+int csr_enqueue_phase(mis_graph* g, int phase, int r, hipStream_t s);
 int csr_output(mis_graph* g, uint8_t* in_set, hipStream_t s);
 int tile_init(mis_graph* g, hipStream_t s);
-int tile_enqueue_phase(mis_graph* g, int phase, hipStream_t s);
+int tile_enqueue_phase(mis_graph* g, int phase, int r, hipStream_t s);
 int tile_output(mis_graph* g, uint8_t* in_set, hipStream_t s);
 
 namespace {
@@ -26,18 +27,6 @@ thread_local std::string g_last_error;
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
-int dev_alloc(void** p, size_t bytes) {
-    *p = nullptr;
-    hipError_t e = hipMalloc(p, bytes ? bytes : 8);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        set_error(std::string("hipMalloc of ") + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
-        *p = nullptr;
-        return MIS_ENOMEM;
-    }
-    return MIS_OK;
-}
-
 namespace {
 
 int fail(int code, const std::string& msg) {
@@ -45,24 +34,86 @@ int fail(int code, const std::string& msg) {
     return code;
 }
 
-void free_graph(mis_graph* g) {
-    if (!g) return;
-    (void)hipDeviceSynchronize();
-    for (void* p : g->owned) (void)hipFree(p);
-    if (g->h_ctrl) (void)hipHostFree(g->h_ctrl);
-    if (g->h_trace) (void)hipHostFree(g->h_trace);
-    delete g;
-}
+// Pinned host staging for the round-loop polls, one per host thread.
+struct Staging {
+    Ctrl* ctrl = nullptr;
+    Meta* meta = nullptr;
+    TraceRec* trace = nullptr;
+    ~Staging() {
+        if (ctrl) (void)hipHostFree(ctrl);
+        if (meta) (void)hipHostFree(meta);
+        if (trace) (void)hipHostFree(trace);
+    }
+};
+thread_local Staging t_stage;
 
-int galloc(mis_graph* g, void** p, size_t bytes) {
-    TC_CHECK(dev_alloc(p, bytes));
-    g->owned.push_back(*p);
-    g->bytes += bytes;
+int staging(Staging** out) {
+    Staging& st = t_stage;
+    if (!st.ctrl) {
+        if (hipHostMalloc((void**)&st.ctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void**)&st.meta, sizeof(Meta), hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void**)&st.trace, sizeof(TraceRec) * kTraceCap, hipHostMallocDefault) != hipSuccess)
+            return fail(MIS_ENOMEM, "pinned host allocation failed");
+    }
+    *out = &st;
     return MIS_OK;
 }
 
-int enqueue_phase(mis_graph* g, int phase, hipStream_t s) {
-    return g->path == MIS_PATH_TILE ? tile_enqueue_phase(g, phase, s) : csr_enqueue_phase(g, phase, s);
+__global__ void k_ctrl_init(Ctrl* ctrl, int64_t n) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        Ctrl c;
+        memset(&c, 0, sizeof(c));
+        c.alive = n;
+        *ctrl = c;
+    }
+}
+
+// Checks arguments and resolves automatic options (host-only).
+int resolve(const mis_csr* csr, const mis_build_opts* opts, mis_build_opts* o) {
+    if (!csr) return fail(MIS_EINVAL, "csr is null");
+    if (csr->n < 0 || csr->n >= (1ll << 31)) return fail(MIS_EINVAL, "n must be in [0, 2^31)");
+    if (csr->nnz < 0 || csr->nnz >= (1ll << 31)) return fail(MIS_EINVAL, "nnz must be in [0, 2^31)");
+    if (!csr->row_ptr) return fail(MIS_EINVAL, "row_ptr is null");
+    if (csr->nnz > 0 && !csr->col_idx) return fail(MIS_EINVAL, "col_idx is null");
+    if (opts) *o = *opts; else mis_default_opts(o);
+    if (o->path < MIS_PATH_AUTO || o->path > MIS_PATH_CSR) return fail(MIS_EINVAL, "bad path");
+    if (o->tile != 0 && o->tile != 16 && o->tile != 32) return fail(MIS_EINVAL, "tile must be 0, 16 or 32");
+    if (o->reorder < MIS_REORDER_AUTO || o->reorder > MIS_REORDER_RCM) return fail(MIS_EINVAL, "bad reorder");
+    if (o->orient < -1 || o->orient > 1) return fail(MIS_EINVAL, "orient must be -1, 0 or 1");
+    if (o->poll_rounds < 0 || o->poll_rounds > kTraceCap) return fail(MIS_EINVAL, "poll_rounds out of range");
+    if (!o->keys && csr->n > (1ll << 24)) return fail(MIS_EINVAL, "the default key rule needs n <= 2^24; pass keys");
+    if (o->path == MIS_PATH_AUTO) o->path = MIS_PATH_TILE;
+    if (o->path == MIS_PATH_TILE) {
+        if (o->tile == 0) o->tile = 16;
+        if (o->reorder == MIS_REORDER_AUTO) o->reorder = MIS_REORDER_KEY;
+        if (o->orient < 0) o->orient = 1;
+    } else {
+        o->tile = 0;
+        o->reorder = MIS_REORDER_NONE;
+        o->orient = 0;
+    }
+    if (o->poll_rounds == 0) o->poll_rounds = 4;
+    return MIS_OK;
+}
+
+void configure(mis_graph* g, const mis_csr* csr, const mis_build_opts& o) {
+    g->n = csr->n;
+    g->nnz = csr->nnz;
+    g->row_ptr = csr->row_ptr;
+    g->col_idx = csr->col_idx;
+    g->path = o.path;
+    g->tile = o.tile;
+    g->reorder = o.reorder;
+    g->orient = o.orient;
+    g->poll_rounds = o.poll_rounds;
+}
+
+int enqueue_phase(mis_graph* g, int phase, int r, hipStream_t s) {
+    return g->path == MIS_PATH_TILE ? tile_enqueue_phase(g, phase, r, s) : csr_enqueue_phase(g, phase, r, s);
+}
+
+__global__ void k_close(Ctrl* ctrl, TraceRec* trace, int r) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) close_round(ctrl, trace, r);
 }
 
 // bytes the kernels must move per work unit (see TraceRec::u)
@@ -119,61 +170,44 @@ const char* mis_last_error(void) { return g_last_error.c_str(); }
 
 const char* mis_version(void) { return "tcmis-hip 0.1 gfx950"; }
 
-int mis_build_tiles(const mis_csr* csr, const mis_build_opts* opts, void* stream, mis_graph** out) {
+int mis_build_bytes(const mis_csr* csr, const mis_build_opts* opts, size_t* bytes) {
+    g_last_error.clear();
+    if (!bytes) return fail(MIS_EINVAL, "bytes is null");
+    mis_build_opts o;
+    TC_CHECK(resolve(csr, opts, &o));
+    mis_graph g;
+    configure(&g, csr, o);
+    *bytes = layout(&g, nullptr);
+    return MIS_OK;
+}
+
+int mis_build_tiles(const mis_csr* csr, const mis_build_opts* opts, void* workspace, size_t workspace_bytes,
+                    void* stream, mis_graph** out) {
     g_last_error.clear();
     if (!out) return fail(MIS_EINVAL, "out is null");
     *out = nullptr;
-    if (!csr) return fail(MIS_EINVAL, "csr is null");
-    if (csr->n < 0 || csr->n >= (1ll << 31)) return fail(MIS_EINVAL, "n must be in [0, 2^31)");
-    if (csr->nnz < 0) return fail(MIS_EINVAL, "nnz must be >= 0");
-    if (!csr->row_ptr) return fail(MIS_EINVAL, "row_ptr is null");
-    if (csr->nnz > 0 && !csr->col_idx) return fail(MIS_EINVAL, "col_idx is null");
     mis_build_opts o;
-    if (opts) o = *opts; else mis_default_opts(&o);
-    if (o.path < MIS_PATH_AUTO || o.path > MIS_PATH_CSR) return fail(MIS_EINVAL, "bad path");
-    if (o.tile != 0 && o.tile != 16 && o.tile != 32) return fail(MIS_EINVAL, "tile must be 0, 16 or 32");
-    if (o.reorder < MIS_REORDER_AUTO || o.reorder > MIS_REORDER_RCM) return fail(MIS_EINVAL, "bad reorder");
-    if (o.orient < -1 || o.orient > 1) return fail(MIS_EINVAL, "orient must be -1, 0 or 1");
-    if (o.poll_rounds < 0 || o.poll_rounds > kTraceCap) return fail(MIS_EINVAL, "poll_rounds out of range");
-    if (!o.keys && csr->n > (1ll << 24)) return fail(MIS_EINVAL, "the default key rule needs n <= 2^24; pass keys");
-
-    // option resolution (the autotuner's defaults)
-    if (o.path == MIS_PATH_AUTO) o.path = MIS_PATH_TILE;
-    if (o.path == MIS_PATH_TILE) {
-        if (o.tile == 0) o.tile = 16;
-        if (o.reorder == MIS_REORDER_AUTO) o.reorder = MIS_REORDER_KEY;
-        if (o.orient < 0) o.orient = 1;
-    } else {
-        o.tile = 0;
-        o.reorder = MIS_REORDER_NONE;
-        o.orient = 0;
+    TC_CHECK(resolve(csr, opts, &o));
+    mis_graph* g = new (std::nothrow) mis_graph();
+    if (!g) return fail(MIS_ENOMEM, "host allocation failed");
+    configure(g, csr, o);
+    const size_t need = layout(g, nullptr);
+    if (!workspace || workspace_bytes < need || ((uintptr_t)workspace & 255)) {
+        delete g;
+        return fail(MIS_EINVAL, "workspace must be 256-byte aligned device memory of at least " +
+                                    std::to_string(need) + " bytes (mis_build_bytes)");
     }
-
-    hipStream_t s = (hipStream_t)stream;
-    mis_graph* g = new mis_graph();
-    g->n = csr->n;
-    g->nnz = csr->nnz;
-    g->row_ptr = csr->row_ptr;
-    g->col_idx = csr->col_idx;
-    g->path = o.path;
-    g->tile = o.tile;
-    g->reorder = o.reorder;
-    g->orient = o.orient;
-    g->poll_rounds = o.poll_rounds > 0 ? o.poll_rounds : 4;
+    g->ws = (char*)workspace;
+    g->ws_bytes = need;
+    layout(g, g->ws);
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) != hipSuccess) { delete g; return fail(MIS_EHIP, "hipGetDevice failed"); }
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    g->device = dev;
     g->grid_blocks = std::max(1, cus) * 8;
 
+    hipStream_t s = (hipStream_t)stream;
     int rc = MIS_OK;
-    if (o.validate) rc = validate_graph(csr, o.keys, s);
-    if (rc == MIS_OK) rc = galloc(g, (void**)&g->ctrl, sizeof(Ctrl));
-    if (rc == MIS_OK) rc = galloc(g, (void**)&g->trace, sizeof(TraceRec) * kTraceCap);
-    if (rc == MIS_OK && hipHostMalloc((void**)&g->h_ctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess)
-        rc = fail(MIS_ENOMEM, "pinned host allocation failed");
-    if (rc == MIS_OK && hipHostMalloc((void**)&g->h_trace, sizeof(TraceRec) * kTraceCap, hipHostMallocDefault) != hipSuccess)
-        rc = fail(MIS_ENOMEM, "pinned host allocation failed");
+    if (o.validate) rc = validate_graph(csr, o.keys, &g->ctrl->error, s);
     if (rc == MIS_OK) rc = build_keys(g, &o, s);
     if (rc == MIS_OK) {
         if (g->path == MIS_PATH_CSR) rc = build_csr_lists(g, s);
@@ -182,9 +216,8 @@ int mis_build_tiles(const mis_csr* csr, const mis_build_opts* opts, void* stream
             if (rc == MIS_OK) rc = build_tiles(g, s);
         }
     }
-    if (rc == MIS_OK && hipStreamSynchronize(s) != hipSuccess) rc = fail(MIS_EHIP, "build failed on the device");
     if (rc != MIS_OK) {
-        free_graph(g);
+        delete g;
         return rc;
     }
     *out = g;
@@ -193,7 +226,7 @@ int mis_build_tiles(const mis_csr* csr, const mis_build_opts* opts, void* stream
 
 int mis_graph_bytes(const mis_graph* g, size_t* bytes) {
     if (!g || !bytes) return fail(MIS_EINVAL, "null argument");
-    *bytes = g->bytes;
+    *bytes = g->ws_bytes;
     return MIS_OK;
 }
 
@@ -206,11 +239,10 @@ int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, mis_stats* st, 
     hipStream_t s = (hipStream_t)stream;
     const bool timing = st && st->timing;
 
-    Ctrl init;
-    std::memset(&init, 0, sizeof(init));
-    init.alive = g->n;
-    *g->h_ctrl = init;
-    TC_HIP(hipMemcpyAsync(g->ctrl, g->h_ctrl, sizeof(Ctrl), hipMemcpyHostToDevice, s));
+    Staging* sg = nullptr;
+    TC_CHECK(staging(&sg));
+    hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, s, g->ctrl, g->n);
+    TC_HIP(hipGetLastError());
     TC_CHECK(g->path == MIS_PATH_TILE ? tile_init(g, s) : csr_init(g, s));
 
     std::vector<hipEvent_t> ev;
@@ -228,22 +260,25 @@ int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, mis_stats* st, 
             int64_t k = g->poll_rounds;
             if (max_rounds > 0) k = std::min<int64_t>(k, max_rounds - enq);
             for (int64_t i = 0; i < k && rc == MIS_OK; ++i) {
+                const int r = (int)(enq + i + 1);
                 if (timing) (void)hipEventRecord(ev[3 * i], s);
-                rc = enqueue_phase(g, 0, s);
+                rc = enqueue_phase(g, 0, r, s);
                 if (timing) (void)hipEventRecord(ev[3 * i + 1], s);
-                if (rc == MIS_OK) rc = enqueue_phase(g, 1, s);
+                if (rc == MIS_OK) rc = enqueue_phase(g, 1, r, s);
                 if (timing) (void)hipEventRecord(ev[3 * i + 2], s);
             }
             if (rc != MIS_OK) break;
+            hipLaunchKernelGGL(k_close, dim3(1), dim3(64), 0, s, g->ctrl, g->trace, (int)(enq + k));
             // ring slots of rounds drained+1 .. enq
             const int64_t first = drained % kTraceCap, cnt = enq + k - drained;
             enq += k;
             const int64_t a1 = std::min<int64_t>(cnt, kTraceCap - first);
-            if (hipMemcpyAsync(g->h_trace + first, g->trace + first, a1 * sizeof(TraceRec), hipMemcpyDeviceToHost, s) !=
+            if (hipMemcpyAsync(sg->trace + first, g->trace + first, a1 * sizeof(TraceRec), hipMemcpyDeviceToHost, s) !=
                     hipSuccess ||
-                (cnt > a1 && hipMemcpyAsync(g->h_trace, g->trace, (cnt - a1) * sizeof(TraceRec), hipMemcpyDeviceToHost,
+                (cnt > a1 && hipMemcpyAsync(sg->trace, g->trace, (cnt - a1) * sizeof(TraceRec), hipMemcpyDeviceToHost,
                                             s) != hipSuccess) ||
-                hipMemcpyAsync(g->h_ctrl, g->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipMemcpyAsync(sg->ctrl, g->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipMemcpyAsync(sg->meta, g->meta, sizeof(Meta), hipMemcpyDeviceToHost, s) != hipSuccess ||
                 hipStreamSynchronize(s) != hipSuccess) {
                 rc = fail(MIS_EHIP, std::string("round loop: ") + hipGetErrorString(hipGetLastError()));
                 break;
@@ -258,9 +293,9 @@ int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, mis_stats* st, 
                 }
                 launches += k;
             }
-            const int64_t done_rounds = g->h_ctrl->round;
+            const int64_t done_rounds = sg->ctrl->round;
             for (int64_t r = drained + 1; r <= done_rounds; ++r) {
-                const TraceRec& t = g->h_trace[(r - 1) % kTraceCap];
+                const TraceRec& t = sg->trace[(r - 1) % kTraceCap];
                 if (st && st->trace && r <= st->trace_cap) {
                     st->trace[3 * (r - 1) + 0] = t.c;
                     st->trace[3 * (r - 1) + 1] = t.x;
@@ -269,7 +304,7 @@ int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, mis_stats* st, 
                 for (int i = 0; i < 4; ++i) units[i] += t.u[i];
             }
             drained = done_rounds;
-            if (g->h_ctrl->alive == 0) break;
+            if (sg->ctrl->alive == 0) break;
             if (max_rounds > 0 && enq >= max_rounds) break;
             if (done_rounds > g->n + 1) { rc = fail(MIS_EINTERNAL, "round limit exceeded (equal adjacent keys?)"); break; }
         }
@@ -277,15 +312,21 @@ int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, mis_stats* st, 
     for (auto& e : ev) (void)hipEventDestroy(e);
     if (rc != MIS_OK) return rc;
     if (g->n > 0) TC_CHECK(g->path == MIS_PATH_TILE ? tile_output(g, in_set, s) : csr_output(g, in_set, s));
+    if (g->n == 0) {   // nothing ran: no staging contents of this graph
+        sg->ctrl->round = 0;
+        sg->ctrl->n_in = 0;
+        sg->meta->ntiles = 0;
+    }
     if (st) {
-        st->rounds = g->h_ctrl->round;
+        st->rounds = sg->ctrl->round;
         st->path = g->path;
         st->tile = g->tile;
         st->reorder = g->reorder;
         st->orient = g->orient;
-        st->n_in = g->h_ctrl->n_in;
-        st->tiles = g->ntiles;
-        st->tile_bytes = g->path == MIS_PATH_TILE ? g->ntiles * ((int64_t)g->tile * g->tile / 8 + 4) : 0;
+        st->n_in = sg->ctrl->n_in;
+        const int64_t nt = g->path == MIS_PATH_TILE ? sg->meta->ntiles : 0;
+        st->tiles = nt;
+        st->tile_bytes = nt * ((int64_t)g->tile * g->tile / 8 + 4);
         int64_t ab = 0;
         for (int i = 0; i < 4; ++i) {
             st->units[i] = units[i];
@@ -310,6 +351,6 @@ int mis_solve_batch(mis_graph* const* graphs, int32_t count, uint8_t* const* in_
     return MIS_OK;
 }
 
-void mis_free_tiles(mis_graph* g) { free_graph(g); }
+void mis_free_tiles(mis_graph* g) { delete g; }
 
 }  // extern "C"

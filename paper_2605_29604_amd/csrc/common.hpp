@@ -49,19 +49,19 @@ __device__ inline int lane_id() { return (int)__lane_id(); }
 __device__ inline uint64_t ballot(bool p) { return __ballot(p); }
 __device__ inline uint64_t lanes_below() { return (1ull << lane_id()) - 1ull; }
 
-// Device radix sort of 64-bit keys on bits [lo_bit, hi_bit), stable, optional
-// uint32 payload.  `keys`/`vals` hold the input; `keys_alt`/`vals_alt` are same-sized
-// scratch.  On return *result_in_alt says which buffer holds the sorted data.
-int radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t* vals_alt,
-                   int64_t count, int lo_bit, int hi_bit, bool* result_in_alt,
-                   hipStream_t stream);
+// Prefix scans (no allocation; `scratch` holds scan_scratch_elems(count) elements
+// of the scanned type; d_total, if given, receives the grand total on the device).
+int64_t scan_scratch_elems(int64_t count);
+int scan_excl_i32(const int32_t* in, int32_t* out, int64_t count, int32_t* d_total, int32_t* scratch, hipStream_t s);
+int scan_excl_i64(const int64_t* in, int64_t* out, int64_t count, int64_t* d_total, int64_t* scratch, hipStream_t s);
+int scan_incl_max_i32(const int32_t* in, int32_t* out, int64_t count, int32_t* scratch, hipStream_t s);
 
-// Exclusive prefix sum of int64 (in may equal out).  Writes the total to *d_total
-// (DEVICE, may be null).
-int scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t count, int64_t* d_total,
-                       hipStream_t stream);
-
-// Device memory helper with error reporting.
-int dev_alloc(void** p, size_t bytes);
+// Stable LSD radix sort of 64-bit keys on bits [lo_bit, hi_bit), optional uint32
+// payload; `keys_alt`/`vals_alt` are same-sized scratch and `scratch` holds
+// sort_scratch_bytes(count) bytes.  *result_in_alt tells which buffer holds the
+// sorted data.  count < 2^31.
+size_t sort_scratch_bytes(int64_t count);
+int radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, int64_t count,
+                   int lo_bit, int hi_bit, void* scratch, bool* result_in_alt, hipStream_t s);
 
 }  // namespace tcmis

@@ -1,5 +1,7 @@
-// The opaque handle behind mis_graph and the device-side round control block.
+// The opaque handle behind mis_graph, its device workspace layout and the
+// device-side round control block.
 #pragma once
+#include <type_traits>
 #include <vector>
 
 #include "common.hpp"
@@ -10,21 +12,19 @@ constexpr int kLightDeg = 32;       // CSR path: thread per vertex up to this de
 constexpr int kTraceCap = 4096;     // device trace ring (rounds); the host drains it at every poll
 constexpr int kSegTiles = 512;      // tile path: at most this many tiles per work segment
 
-// Device control block of the round loop.  Every round kernel reads `round` and
-// `alive` at entry; only the last workgroup of the round's final kernel writes them
-// (after every other workgroup has finished), so the round loop can be enqueued or
-// captured without host involvement.
+// Device control block of the round loop.  Round r's kernels take r as an
+// argument and count into cnt[r & 1]; round r is closed (counters moved to the
+// trace ring, `alive` and `round` advanced) by the first thread of round r+1's
+// candidate kernel, or by the one-thread close kernel the host enqueues before it
+// reads the block.  No workgroup ever waits for another, and no fence is needed:
+// every cross-workgroup hand-over crosses a kernel boundary.
 struct Ctrl {
-    int32_t round;          // rounds completed
-    int32_t pad0;
-    int64_t alive;          // undecided vertices after `round` rounds
-    int64_t cnt_c;          // candidates of the round in progress
-    int64_t cnt_x;          // removed neighbours of candidates in the round in progress
-    int64_t n_act[2][2];    // active work items per list buffer (CSR: [light, heavy]; tile: [segments, -])
-    uint32_t blocks_done;   // last-workgroup detection
+    int32_t round;          // rounds closed
     uint32_t error;         // invariant violation flags
+    int64_t alive;          // undecided vertices after `round` rounds
     int64_t n_in;           // vertices in the set so far
-    int64_t u[4];           // work units of the round in progress (see TraceRec)
+    int64_t n_act[2][2];    // active work items per list buffer (CSR: [light, heavy]; tile: [segments, -])
+    int64_t cnt[2][6];      // per round parity: |C|, removed neighbours, work units u0..u3
 };
 
 // Per-round trace record in the device ring.
@@ -39,6 +39,15 @@ struct TraceRec {
     int64_t u[4];
 };
 
+// Sizes the build produces on the device (never read back during the build).
+struct Meta {
+    int32_t ntiles;         // nonzero tiles
+    int32_t nvalid;         // adjacency entries kept in tiles
+    int64_t nseg;           // work segments
+    int32_t n_light;        // CSR path: vertices with degree <= kLightDeg
+    int32_t pad;
+};
+
 }  // namespace tcmis
 
 struct mis_graph {
@@ -46,53 +55,70 @@ struct mis_graph {
     int64_t n = 0, nnz = 0;
     const int64_t* row_ptr = nullptr;
     const int32_t* col_idx = nullptr;
-    int device = 0;
 
     // chosen configuration
     int path = MIS_PATH_CSR, tile = 0, reorder = MIS_REORDER_NONE, orient = 0;
     int poll_rounds = 4;
     int grid_blocks = 2048;           // persistent grid of the round kernels
 
-    // priorities (input ids)
-    uint64_t* key = nullptr;
+    // workspace (caller-owned device memory)
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+
+    tcmis::Ctrl* ctrl = nullptr;
+    tcmis::Meta* meta = nullptr;
+    tcmis::TraceRec* trace = nullptr;
+    char* scan_tmp = nullptr;         // scan scratch (int64 elements)
+    char* sort_tmp = nullptr;         // radix sort scratch
+
+    uint64_t* key = nullptr;          // priorities, input ids
 
     // ---- CSR path
-    int64_t n_light = 0, n_heavy = 0;
     int32_t* light = nullptr;         // vertices with degree <= kLightDeg (initial active list)
     int32_t* heavy = nullptr;
     int32_t* act[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     uint32_t* st = nullptr;           // per-vertex decision word: 0 or (round << 2 | code)
     uint64_t* ak = nullptr;           // alive ? key : 0
+    int32_t* flag32 = nullptr;        // [n] build temporary
 
     // ---- tile path (new vertex order)
     int64_t nI = 0;                   // row-blocks of `tile` rows
+    int64_t tile_cap = 0;             // capacity in tiles (upper bound)
+    int64_t seg_cap = 0;              // capacity in segments
     int32_t* new_id = nullptr;        // input id -> new id
-    int64_t ntiles = 0;
+    int32_t* order = nullptr;         // new id -> input id
+    uint64_t* sk = nullptr;           // [n] x2 order sort keys
+    uint64_t* sk2 = nullptr;
+    uint32_t* pl = nullptr;           // [n] x2 order sort payload
+    uint32_t* pl2 = nullptr;
+    int32_t* ndeg = nullptr;          // [n+1] degrees in new order -> new row pointer
+    int64_t* rbase = nullptr;         // [n] old entry offset of each new row minus its new offset
+    int32_t* rowof = nullptr;         // [nnz] new row of each new-order entry
+    uint64_t* ent = nullptr;          // [nnz] x2 tile entries
+    uint64_t* ent2 = nullptr;
+    int32_t* tflag = nullptr;         // [nnz] tile-start flags -> tile index
     int64_t* rb_ptr = nullptr;        // [nI+1] tile range of each row-block
-    int32_t* tile_col = nullptr;      // [ntiles] column block J
-    uint32_t* tile_bits = nullptr;    // [ntiles * tile*tile/32] row masks (T=16: two rows per word)
+    int32_t* tile_col = nullptr;      // [tile_cap] column block J
+    int32_t* tile_row = nullptr;      // [tile_cap] row block I
+    int32_t* tile_start = nullptr;    // [tile_cap] first sorted entry of each tile
+    uint32_t* tile_bits = nullptr;    // [tile_cap * tile*tile/32] row masks (T=16: two rows per word)
     uint64_t* key_p = nullptr;        // [nI*tile] keys in new order, padding 0 (orient = 0)
-    int64_t nseg = 0;
-    int32_t* seg_rb = nullptr;        // [nseg] row-block of a segment
-    int64_t* seg_t0 = nullptr;        // [nseg] first tile
-    int64_t* seg_t1 = nullptr;        // [nseg] one past the last tile
+    int64_t* segc = nullptr;          // [nI] segments per row-block -> first segment
+    int32_t* seg_rb = nullptr;        // [seg_cap] row-block of a segment
+    int64_t* seg_t0 = nullptr;        // [seg_cap] first tile
+    int64_t* seg_t1 = nullptr;        // [seg_cap] one past the last tile
     int32_t* rb_seg0 = nullptr;       // [nI] first segment of a row-block
     int32_t* rb_nseg = nullptr;       // [nI]
+    int32_t* seg_all = nullptr;       // [seg_cap] 0, 1, 2, ... (round-1 active list)
+    int32_t* seglist[2] = {nullptr, nullptr};
     uint32_t* alive0 = nullptr;       // [nI] rows that exist (initial alive mask)
     uint32_t* alive = nullptr;        // [nI] undecided rows
     uint64_t* cand = nullptr;         // [nI] (round << 32) | candidate mask
     uint32_t* inmask = nullptr;       // [nI] rows in the set
-    uint32_t* acc = nullptr;          // [2*nI] partial masks of multi-segment row-blocks
-    uint32_t* done = nullptr;         // [2*nI] finished segments of multi-segment row-blocks
-    int32_t* seglist[2] = {nullptr, nullptr};
-    int32_t* seg_all = nullptr;       // [nseg] 0..nseg-1 (initial active list)
-
-    // ---- round control
-    tcmis::Ctrl* ctrl = nullptr;      // device
-    tcmis::Ctrl* h_ctrl = nullptr;    // pinned host mirror
-    tcmis::TraceRec* trace = nullptr; // device ring [kTraceCap]
-    tcmis::TraceRec* h_trace = nullptr;  // pinned host copy
-
-    size_t bytes = 0;                 // device bytes owned
-    std::vector<void*> owned;         // device allocations to free
+    uint64_t* part = nullptr;         // [2*nI] (segments done << 32 | partial mask) of multi-segment row-blocks
 };
+
+namespace tcmis {
+// Assigns every workspace array of g (base == nullptr: only computes the size).
+size_t layout(mis_graph* g, char* base);
+}  // namespace tcmis

@@ -1,88 +1,136 @@
-// Device prefix scan and LSD radix sort used by the tile builder.
+// Device prefix scans and the LSD radix sort used by the build stage.
 //
-// Radix sort: 8-bit digits, three kernels per pass (per-block digit histogram,
-// exclusive scan of the digit-major histogram, stable scatter).  The scatter ranks
-// equal digits inside a wavefront with eight ballots (one per digit bit), and
-// across the block's wavefronts and iterations through LDS counters, which keeps
-// the pass stable.
+// No allocation and no host synchronisation: callers pass scratch sized by
+// scan_scratch_elems / sort_scratch_bytes, and results stay on the device.
+//
+// Scans: reduce-then-scan over tiles of 2048 items (256 threads x 8), recursive on
+// the tile totals.  Radix sort: 8-bit digits, three kernels per pass (per-block
+// digit histogram, exclusive scan of the digit-major histogram, stable scatter);
+// the scatter ranks equal digits inside a wavefront with eight ballots and across
+// the block's wavefronts and iterations through LDS counters, which keeps every
+// pass stable.
 #include "common.hpp"
 
 namespace tcmis {
 
 namespace {
 
-constexpr int kScanItems = 8;                       // items per thread in the scan
-constexpr int kScanTile = kBlock * kScanItems;      // 2048
-constexpr int kSortIters = 16;                      // iterations per sort block
-constexpr int kSortTile = kBlock * kSortIters;      // 4096 keys per block
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;   // 2048
+constexpr int kSortIters = 16;
+constexpr int kSortTile = kBlock * kSortIters;   // 4096 keys per block
 constexpr int kDigits = 256;
-constexpr int kWavesPerBlock = kBlock / kWave;      // 4
+constexpr int kWavesPerBlock = kBlock / kWave;
 
-// inclusive scan of one value per thread across the block; returns the block total
-__device__ int64_t block_inclusive_scan(int64_t x, int64_t* lds_wave /*[kWavesPerBlock]*/, int64_t& total) {
+struct OpAdd {
+    template <typename T> __device__ static T apply(T a, T b) { return a + b; }
+    template <typename T> __device__ static T identity() { return T(0); }
+};
+struct OpMax {
+    template <typename T> __device__ static T apply(T a, T b) { return a > b ? a : b; }
+    template <typename T> __device__ static T identity() { return T(-1); }
+};
+
+// inclusive scan of one value per thread over the block; *total = block aggregate
+template <typename T, typename Op>
+__device__ T block_scan(T x, T* lds_wave, T* total) {
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     for (int off = 1; off < kWave; off <<= 1) {
-        int64_t y = __shfl_up(x, off, kWave);
-        if (lane >= off) x += y;
+        T y = __shfl_up(x, off, kWave);
+        if (lane >= off) x = Op::apply(x, y);
     }
     if (lane == kWave - 1) lds_wave[wid] = x;
     __syncthreads();
-    int64_t before = 0;
-    total = 0;
+    T before = Op::template identity<T>(), all = Op::template identity<T>();
     for (int w = 0; w < kWavesPerBlock; ++w) {
-        int64_t s = lds_wave[w];
-        if (w < wid) before += s;
-        total += s;
+        T s = lds_wave[w];
+        if (w < wid) before = Op::apply(before, s);
+        all = Op::apply(all, s);
     }
     __syncthreads();
-    return x + before;
+    *total = all;
+    return Op::apply(before, x);
 }
 
-__global__ void __launch_bounds__(kBlock) k_scan_reduce(const int64_t* in, int64_t count, int64_t* sums) {
-    __shared__ int64_t lds[kWavesPerBlock];
+template <typename T, typename Op>
+__global__ void __launch_bounds__(kBlock) k_scan_reduce(const T* in, int64_t count, T* sums) {
+    __shared__ T lds[kWavesPerBlock];
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    int64_t s = 0;
+    T s = Op::template identity<T>();
     for (int i = 0; i < kScanItems; ++i) {
-        int64_t idx = base + i;
-        if (idx < count) s += in[idx];
+        const int64_t idx = base + i;
+        if (idx < count) s = Op::apply(s, in[idx]);
     }
-    int64_t total;
-    block_inclusive_scan(s, lds, total);
+    T total;
+    block_scan<T, Op>(s, lds, &total);
     if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
 
-__global__ void __launch_bounds__(kBlock) k_scan_apply(const int64_t* in, int64_t* out, int64_t count,
-                                                       const int64_t* block_offsets, int64_t* d_total,
-                                                       int64_t grand_total_index) {
-    __shared__ int64_t lds[kWavesPerBlock];
+// exclusive (kIncl = false) or inclusive scan of each tile, seeded with the
+// exclusive scan of the tile totals
+template <typename T, typename Op, bool kIncl>
+__global__ void __launch_bounds__(kBlock) k_scan_apply(const T* in, T* out, int64_t count, const T* tile_prefix,
+                                                       T* d_total) {
+    __shared__ T lds[kWavesPerBlock];
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    int64_t v[kScanItems];
-    int64_t s = 0;
+    T v[kScanItems];
+    T s = Op::template identity<T>();
     for (int i = 0; i < kScanItems; ++i) {
-        int64_t idx = base + i;
-        v[i] = idx < count ? in[idx] : 0;
-        s += v[i];
+        const int64_t idx = base + i;
+        v[i] = idx < count ? in[idx] : Op::template identity<T>();
+        s = Op::apply(s, v[i]);
     }
-    int64_t total;
-    int64_t incl = block_inclusive_scan(s, lds, total);
-    int64_t run = incl - s + (block_offsets ? block_offsets[blockIdx.x] : 0);
+    T total;
+    const T incl = block_scan<T, Op>(s, lds, &total);
+    // exclusive prefix of this thread's first item = inclusive result of the previous thread
+    __shared__ T lds_incl[kBlock];
+    lds_incl[threadIdx.x] = incl;
+    __syncthreads();
+    T run = threadIdx.x == 0 ? Op::template identity<T>() : lds_incl[threadIdx.x - 1];
+    if (tile_prefix) run = Op::apply(tile_prefix[blockIdx.x], run);
     for (int i = 0; i < kScanItems; ++i) {
-        int64_t idx = base + i;
-        if (idx < count) out[idx] = run;
-        run += v[i];
+        const int64_t idx = base + i;
+        if (kIncl) {
+            run = Op::apply(run, v[i]);
+            if (idx < count) out[idx] = run;
+        } else {
+            if (idx < count) out[idx] = run;
+            run = Op::apply(run, v[i]);
+        }
     }
-    if (d_total && (int64_t)blockIdx.x == grand_total_index && threadIdx.x == kBlock - 1) *d_total = run;
+    if (d_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == kBlock - 1) *d_total = run;
+}
+
+template <typename T, typename Op, bool kIncl>
+int scan_impl(const T* in, T* out, int64_t count, T* d_total, T* scratch, hipStream_t s) {
+    if (count <= 0) return MIS_OK;
+    const int64_t nb = ceil_div(count, kScanTile);
+    if (nb == 1) {
+        hipLaunchKernelGGL((k_scan_apply<T, Op, kIncl>), dim3(1), dim3(kBlock), 0, s, in, out, count, (const T*)nullptr,
+                           d_total);
+        TC_HIP(hipGetLastError());
+        return MIS_OK;
+    }
+    T* sums = scratch;
+    T* rest = scratch + nb;
+    hipLaunchKernelGGL((k_scan_reduce<T, Op>), dim3((unsigned)nb), dim3(kBlock), 0, s, in, count, sums);
+    TC_HIP(hipGetLastError());
+    TC_CHECK((scan_impl<T, Op, false>(sums, sums, nb, (T*)nullptr, rest, s)));
+    hipLaunchKernelGGL((k_scan_apply<T, Op, kIncl>), dim3((unsigned)nb), dim3(kBlock), 0, s, in, out, count,
+                       (const T*)sums, d_total);
+    TC_HIP(hipGetLastError());
+    return MIS_OK;
 }
 
 // ---- radix sort kernels ----
 __global__ void __launch_bounds__(kBlock) k_radix_hist(const uint64_t* keys, int64_t count, int shift,
-                                                       int64_t nblocks, int64_t* hist) {
+                                                       int64_t nblocks, int32_t* hist) {
     __shared__ int cnt[kDigits];
     cnt[threadIdx.x] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     for (int it = 0; it < kSortIters; ++it) {
-        int64_t idx = base + (int64_t)it * kBlock + threadIdx.x;
+        const int64_t idx = base + (int64_t)it * kBlock + threadIdx.x;
         if (idx < count) atomicAdd(&cnt[(keys[idx] >> shift) & 0xff], 1);
     }
     __syncthreads();
@@ -91,11 +139,10 @@ __global__ void __launch_bounds__(kBlock) k_radix_hist(const uint64_t* keys, int
 
 template <bool kVals>
 __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint64_t* keys, uint64_t* keys_out,
-                                                          const uint32_t* vals, uint32_t* vals_out,
-                                                          int64_t count, int shift, int64_t nblocks,
-                                                          const int64_t* offsets) {
-    __shared__ int64_t base_of[kDigits];
-    __shared__ int wave_cnt[kWavesPerBlock][kDigits];
+                                                          const uint32_t* vals, uint32_t* vals_out, int64_t count,
+                                                          int shift, int64_t nblocks, const int32_t* offsets) {
+    __shared__ int32_t base_of[kDigits];
+    __shared__ int32_t wave_cnt[kWavesPerBlock][kDigits];
     const int t = threadIdx.x, lane = lane_id(), wid = t / kWave;
     base_of[t] = offsets[(int64_t)t * nblocks + blockIdx.x];
     for (int w = 0; w < kWavesPerBlock; ++w) wave_cnt[w][t] = 0;
@@ -104,8 +151,8 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint64_t* keys, 
     for (int it = 0; it < kSortIters; ++it) {
         const int64_t idx = base + (int64_t)it * kBlock + t;
         const bool valid = idx < count;
-        uint64_t k = valid ? keys[idx] : 0;
-        uint32_t val = (kVals && valid) ? vals[idx] : 0;
+        const uint64_t k = valid ? keys[idx] : 0;
+        const uint32_t val = (kVals && valid) ? vals[idx] : 0;
         const int d = (int)((k >> shift) & 0xff);
         uint64_t match = ballot(valid);
         #pragma unroll
@@ -115,18 +162,21 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint64_t* keys, 
             match &= bit ? bb : ~bb;
         }
         const int rank = __popcll(match & lanes_below());
-        const int leader = match ? __ffsll((unsigned long long)match) - 1 : 0;
+        const int leader = match ? __builtin_ctzll(match) : 0;
         if (valid && lane == leader) wave_cnt[wid][d] = __popcll(match);
         __syncthreads();
         if (valid) {
-            int64_t dst = base_of[d] + rank;
+            int64_t dst = (int64_t)base_of[d] + rank;
             for (int w = 0; w < wid; ++w) dst += wave_cnt[w][d];
             keys_out[dst] = k;
             if (kVals) vals_out[dst] = val;
         }
         __syncthreads();
         int add = 0;
-        for (int w = 0; w < kWavesPerBlock; ++w) { add += wave_cnt[w][t]; wave_cnt[w][t] = 0; }
+        for (int w = 0; w < kWavesPerBlock; ++w) {
+            add += wave_cnt[w][t];
+            wave_cnt[w][t] = 0;
+        }
         base_of[t] += add;
         __syncthreads();
     }
@@ -134,66 +184,60 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint64_t* keys, 
 
 }  // namespace
 
-int scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t count, int64_t* d_total,
-                       hipStream_t stream) {
-    if (count <= 0) {
-        if (d_total) TC_HIP(hipMemsetAsync(d_total, 0, sizeof(int64_t), stream));
-        return MIS_OK;
+int64_t scan_scratch_elems(int64_t count) {
+    int64_t total = 0;
+    while (count > kScanTile) {
+        count = ceil_div(count, kScanTile);
+        total += count;
     }
-    const int64_t nb = ceil_div(count, kScanTile);
-    if (nb == 1) {
-        hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(kBlock), 0, stream, in, out, count,
-                           (const int64_t*)nullptr, d_total, (int64_t)0);
-        TC_HIP(hipGetLastError());
-        return MIS_OK;
-    }
-    int64_t* sums = nullptr;
-    TC_CHECK(dev_alloc((void**)&sums, (size_t)nb * sizeof(int64_t)));
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kBlock), 0, stream, in, count, sums);
-    int rc = hipGetLastError() == hipSuccess ? MIS_OK : MIS_EHIP;
-    if (rc == MIS_OK) rc = scan_exclusive_i64(sums, sums, nb, nullptr, stream);
-    if (rc == MIS_OK) {
-        hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kBlock), 0, stream, in, out, count,
-                           (const int64_t*)sums, d_total, nb - 1);
-        if (hipGetLastError() != hipSuccess) rc = MIS_EHIP;
-    }
-    (void)hipStreamSynchronize(stream);
-    (void)hipFree(sums);
-    if (rc != MIS_OK) set_error("scan_exclusive_i64 launch failed");
-    return rc;
+    return total + 1;
 }
 
-int radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t* vals_alt,
-                   int64_t count, int lo_bit, int hi_bit, bool* result_in_alt, hipStream_t stream) {
+int scan_excl_i32(const int32_t* in, int32_t* out, int64_t count, int32_t* d_total, int32_t* scratch, hipStream_t s) {
+    return scan_impl<int32_t, OpAdd, false>(in, out, count, d_total, scratch, s);
+}
+int scan_excl_i64(const int64_t* in, int64_t* out, int64_t count, int64_t* d_total, int64_t* scratch, hipStream_t s) {
+    return scan_impl<int64_t, OpAdd, false>(in, out, count, d_total, scratch, s);
+}
+int scan_incl_max_i32(const int32_t* in, int32_t* out, int64_t count, int32_t* scratch, hipStream_t s) {
+    return scan_impl<int32_t, OpMax, true>(in, out, count, (int32_t*)nullptr, scratch, s);
+}
+
+size_t sort_scratch_bytes(int64_t count) {
+    const int64_t nb = ceil_div(count > 0 ? count : 1, kSortTile);
+    const int64_t h = nb * kDigits;
+    return (size_t)(h + scan_scratch_elems(h)) * sizeof(int32_t);
+}
+
+int radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, int64_t count,
+                   int lo_bit, int hi_bit, void* scratch, bool* result_in_alt, hipStream_t s) {
     *result_in_alt = false;
     if (count <= 1 || hi_bit <= lo_bit) return MIS_OK;
+    if (count >= (1ll << 31)) {
+        set_error("radix sort is limited to 2^31 keys");
+        return MIS_EINVAL;
+    }
     const int64_t nb = ceil_div(count, kSortTile);
-    int64_t* hist = nullptr;
-    TC_CHECK(dev_alloc((void**)&hist, (size_t)nb * kDigits * sizeof(int64_t)));
+    int32_t* hist = (int32_t*)scratch;
+    int32_t* scan_tmp = hist + nb * kDigits;
     uint64_t *src = keys, *dst = keys_alt;
     uint32_t *vsrc = vals, *vdst = vals_alt;
-    int rc = MIS_OK;
-    for (int shift = lo_bit; shift < hi_bit && rc == MIS_OK; shift += 8) {
-        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kBlock), 0, stream, src, count, shift, nb, hist);
-        if (hipGetLastError() != hipSuccess) { rc = MIS_EHIP; break; }
-        rc = scan_exclusive_i64(hist, hist, nb * kDigits, nullptr, stream);
-        if (rc != MIS_OK) break;
-        if (vals) {
-            hipLaunchKernelGGL(k_radix_scatter<true>, dim3((unsigned)nb), dim3(kBlock), 0, stream, src, dst,
-                               vsrc, vdst, count, shift, nb, hist);
-        } else {
-            hipLaunchKernelGGL(k_radix_scatter<false>, dim3((unsigned)nb), dim3(kBlock), 0, stream, src, dst,
+    for (int shift = lo_bit; shift < hi_bit; shift += 8) {
+        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kBlock), 0, s, src, count, shift, nb, hist);
+        TC_HIP(hipGetLastError());
+        TC_CHECK(scan_excl_i32(hist, hist, nb * kDigits, nullptr, scan_tmp, s));
+        if (vals)
+            hipLaunchKernelGGL(k_radix_scatter<true>, dim3((unsigned)nb), dim3(kBlock), 0, s, src, dst, vsrc, vdst, count,
+                               shift, nb, hist);
+        else
+            hipLaunchKernelGGL(k_radix_scatter<false>, dim3((unsigned)nb), dim3(kBlock), 0, s, src, dst,
                                (const uint32_t*)nullptr, (uint32_t*)nullptr, count, shift, nb, hist);
-        }
-        if (hipGetLastError() != hipSuccess) { rc = MIS_EHIP; break; }
+        TC_HIP(hipGetLastError());
         uint64_t* t = src; src = dst; dst = t;
         uint32_t* tv = vsrc; vsrc = vdst; vdst = tv;
         *result_in_alt = !*result_in_alt;
     }
-    (void)hipStreamSynchronize(stream);
-    (void)hipFree(hist);
-    if (rc != MIS_OK) set_error("radix_sort_u64 failed");
-    return rc;
+    return MIS_OK;
 }
 
 }  // namespace tcmis

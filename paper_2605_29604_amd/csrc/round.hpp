@@ -39,33 +39,37 @@ __device__ inline void lbuf_push(int32_t* lbuf, int& pend, int32_t* list, int64_
     pend += k;
 }
 
-// Called by every workgroup at the end of a round's last kernel.  The workgroup
-// that finishes last closes the round: it moves the counters into the trace ring
-// and advances the round state, after every other workgroup has exited.
-__device__ inline void finish_round(Ctrl* ctrl, TraceRec* trace, int r) {
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    __threadfence();
-    const uint32_t prev = atomicAdd(&ctrl->blocks_done, 1u);
-    if (prev != gridDim.x - 1) return;
-    __threadfence();
-    const int64_t c = (int64_t)atomicAdd((unsigned long long*)&ctrl->cnt_c, 0ull);
-    const int64_t x = (int64_t)atomicAdd((unsigned long long*)&ctrl->cnt_x, 0ull);
-    const int64_t alive = ctrl->alive - c - x;
+__device__ inline int64_t atomic_read(int64_t* p) {
+    return (int64_t)__hip_atomic_load((unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Closes round r (one thread): moves its counters into the trace ring and advances
+// `round` and `alive`.  A round that is already closed, or that ran after every
+// vertex was decided, is left alone.
+__device__ inline void close_round(Ctrl* ctrl, TraceRec* trace, int r) {
+    if (r < 1 || ctrl->round != r - 1 || ctrl->alive == 0) return;
+    int64_t* c = ctrl->cnt[r & 1];
     TraceRec rec;
-    rec.c = c;
-    rec.x = x;
-    rec.alive = alive;
+    rec.c = atomic_read(&c[0]);
+    rec.x = atomic_read(&c[1]);
+    rec.alive = ctrl->alive - rec.c - rec.x;
     rec.round = r;
-    for (int i = 0; i < 4; ++i) rec.u[i] = (int64_t)atomicExch((unsigned long long*)&ctrl->u[i], 0ull);
+    for (int i = 0; i < 4; ++i) rec.u[i] = atomic_read(&c[2 + i]);
     trace[(r - 1) % kTraceCap] = rec;
-    ctrl->n_in += c;
-    ctrl->alive = alive;
-    atomicExch((unsigned long long*)&ctrl->cnt_c, 0ull);
-    atomicExch((unsigned long long*)&ctrl->cnt_x, 0ull);
+    for (int i = 0; i < 6; ++i) c[i] = 0;
+    ctrl->n_in += rec.c;
+    ctrl->alive = rec.alive;
     ctrl->round = r;
-    atomicExch(&ctrl->blocks_done, 0u);
-    __threadfence();
+}
+
+// Round prologue run by the first thread of round r's candidate kernel: closes
+// round r-1 and empties the list that round r's exclusion kernel fills.
+__device__ inline void open_round(Ctrl* ctrl, TraceRec* trace, int r) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        close_round(ctrl, trace, r - 1);
+        ctrl->n_act[r & 1][0] = 0;
+        ctrl->n_act[r & 1][1] = 0;
+    }
 }
 
 }  // namespace tcmis

@@ -28,15 +28,16 @@ struct CsrArgs {
     Ctrl* ctrl;
     TraceRec* trace;
     const int32_t* master[2];   // initial light / heavy lists (round 1)
-    int64_t n_master[2];
+    const Meta* meta;           // meta->n_light: length of the light list
+    int64_t n;
     int32_t* act[2][2];         // [buffer][light, heavy]
 };
 
 __device__ inline void round_lists(const CsrArgs& a, int r, const int32_t** in_l, int64_t* n_l,
                                    const int32_t** in_h, int64_t* n_h) {
     if (r == 1) {
-        *in_l = a.master[0]; *n_l = a.n_master[0];
-        *in_h = a.master[1]; *n_h = a.n_master[1];
+        *in_l = a.master[0]; *n_l = a.meta->n_light;
+        *in_h = a.master[1]; *n_h = a.n - a.meta->n_light;
     } else {
         const int b = (r - 1) & 1;
         *in_l = a.act[b][0]; *n_l = a.ctrl->n_act[b][0];
@@ -44,16 +45,12 @@ __device__ inline void round_lists(const CsrArgs& a, int r, const int32_t** in_l
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_csr_cand(CsrArgs a) {
-    if (a.ctrl->alive == 0) return;
-    const int r = a.ctrl->round + 1;
+__global__ void __launch_bounds__(kBlock) k_csr_cand(CsrArgs a, int r) {
+    open_round(a.ctrl, a.trace, r);
     const int32_t *L, *H;
     int64_t nl, nh;
     round_lists(a, r, &L, &nl, &H, &nh);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        a.ctrl->n_act[r & 1][0] = 0;
-        a.ctrl->n_act[r & 1][1] = 0;
-    }
+    if (nl + nh == 0) return;
     const int lane = lane_id();
     const int64_t nthreads = (int64_t)gridDim.x * kBlock;
     const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -91,19 +88,19 @@ __global__ void __launch_bounds__(kBlock) k_csr_cand(CsrArgs a) {
             if (!blocked) { a.st[v] = tag(r, kIn); ++n_cand; }
         }
     }
-    wave_add(&a.ctrl->cnt_c, n_cand);
-    wave_add(&a.ctrl->u[0], edges);
-    wave_add(&a.ctrl->u[1], verts);
+    int64_t* cnt = a.ctrl->cnt[r & 1];
+    wave_add(&cnt[0], n_cand);
+    wave_add(&cnt[2], edges);
+    wave_add(&cnt[3], verts);
 }
 
-__global__ void __launch_bounds__(kBlock) k_csr_excl(CsrArgs a) {
+__global__ void __launch_bounds__(kBlock) k_csr_excl(CsrArgs a, int r) {
     __shared__ int32_t lbuf[kBlock / kWave][2][kWave];
-    if (a.ctrl->alive == 0) return;
-    const int r = a.ctrl->round + 1;
     const uint32_t in_r = tag(r, kIn), out_r = tag(r, kOut);
     const int32_t *L, *H;
     int64_t nl, nh;
     round_lists(a, r, &L, &nl, &H, &nh);
+    if (nl + nh == 0) return;
     int32_t* nextL = a.act[r & 1][0];
     int32_t* nextH = a.act[r & 1][1];
     int64_t* cntL = &a.ctrl->n_act[r & 1][0];
@@ -164,10 +161,10 @@ __global__ void __launch_bounds__(kBlock) k_csr_excl(CsrArgs a) {
         lbuf_push(bufH, pendH, nextH, cntH, lane == 0 && !hit, v);
     }
     lbuf_flush(bufH, pendH, nextH, cntH);
-    wave_add(&a.ctrl->cnt_x, n_out);
-    wave_add(&a.ctrl->u[2], edges);
-    wave_add(&a.ctrl->u[3], verts);
-    finish_round(a.ctrl, a.trace, r);
+    int64_t* cnt = a.ctrl->cnt[r & 1];
+    wave_add(&cnt[1], n_out);
+    wave_add(&cnt[4], edges);
+    wave_add(&cnt[5], verts);
 }
 
 __global__ void k_csr_init(const uint64_t* key, uint64_t* ak, uint32_t* st, int64_t n) {
@@ -187,7 +184,7 @@ CsrArgs make_args(mis_graph* g) {
     a.rp = g->row_ptr; a.ci = g->col_idx; a.key = g->key; a.ak = g->ak; a.st = g->st;
     a.ctrl = g->ctrl; a.trace = g->trace;
     a.master[0] = g->light; a.master[1] = g->heavy;
-    a.n_master[0] = g->n_light; a.n_master[1] = g->n_heavy;
+    a.meta = g->meta; a.n = g->n;
     for (int b = 0; b < 2; ++b)
         for (int k = 0; k < 2; ++k) a.act[b][k] = g->act[b][k];
     return a;
@@ -203,10 +200,10 @@ int csr_init(mis_graph* g, hipStream_t s) {
 }
 
 // phase 0 = candidate kernel, 1 = exclusion kernel (which closes the round)
-int csr_enqueue_phase(mis_graph* g, int phase, hipStream_t s) {
+int csr_enqueue_phase(mis_graph* g, int phase, int r, hipStream_t s) {
     CsrArgs a = make_args(g);
-    if (phase == 0) hipLaunchKernelGGL(k_csr_cand, dim3(g->grid_blocks), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL(k_csr_excl, dim3(g->grid_blocks), dim3(kBlock), 0, s, a);
+    if (phase == 0) hipLaunchKernelGGL(k_csr_cand, dim3(g->grid_blocks), dim3(kBlock), 0, s, a, r);
+    else hipLaunchKernelGGL(k_csr_excl, dim3(g->grid_blocks), dim3(kBlock), 0, s, a, r);
     TC_HIP(hipGetLastError());
     return MIS_OK;
 }

@@ -10,25 +10,32 @@
 // row-block with several segments combines their partial masks with one atomic OR
 // each, and the segment that finishes last completes the row-block.
 //
-// Candidate kernel (Phase 1, Section 3.1; Phase 1 of the paper runs on the vector
-// units): for each tile of an active row-block the wave loads the row masks, ANDs
-// them with the alive mask of the tile's column block and
-//   orient = 0: stages the keys of the alive columns in LDS and compares each row's
-//               key against the keys of its set, alive columns;
-//   orient = 1: the tiles hold only edges to higher-priority neighbours, so any set,
-//               alive bit blocks the row (no keys are read).
-// Rows blocked anywhere are combined with a ballot; candidates = alive & ~blocked.
+// A wave takes one segment at a time and streams its tiles 64 lanes wide: each
+// lane owns one tile (T=16) or a quarter tile (T=32: rows 8k..8k+7) and loads 32
+// contiguous bytes of bitmap, so a wave keeps 64 tiles of independent loads in
+// flight.  Bitmaps are only read for tiles whose column block can matter (alive
+// rows for Phase 1, candidate rows for Phase 2).
+//
+// Candidate kernel (Phase 1, Section 3.1): a row is blocked when it has a set bit
+// in a column that is alive and
+//   orient = 1: unconditionally (the tiles hold only edges to higher-priority
+//               neighbours, so no keys are read);
+//   orient = 0: whose key beats the row's key (the row keys of the segment's
+//               row-block are staged in LDS once per segment, neighbour keys are
+//               gathered per set alive bit).
+// Blocked rows are OR-reduced across the wave; candidates = alive & ~blocked.
 //
 // Exclusion kernel (Phases 2 and 3, Section 3.2): N_c = A x C on the matrix cores
-// as an int8 x int8 -> int32 product (exact: every count is <= the degree).  Bit
-// tiles are expanded to 0/1 bytes in registers.  T=16: v_mfma_i32_16x16x64_i8
-// takes four tiles of a row-block at once along K (A: lane = row, k-group = tile;
-// B: the same four candidate segments, identical in all 16 columns).  T=32:
-// v_mfma_i32_32x32x32_i8 takes one tile.  Tiles whose candidate segment is empty
-// are skipped (the paper's early exit), and a row-block stops as soon as every
-// alive non-candidate row has a candidate neighbour.  Phase 3 is fused: the wave
-// that completes a row-block writes its new alive mask, its members and, if rows
-// remain, its segments to the next round's active list.
+// as an int8 x int8 -> int32 product (exact: every count is <= the degree).  The
+// tiles of an iteration whose candidate segment is non-empty (the paper's early
+// exit skips the rest) are compacted into LDS, then fed to
+// v_mfma_i32_16x16x64_i8 four tiles at a time (A: lane = row, k-group = tile; B:
+// the four candidate segments, equal in all 16 columns) or to
+// v_mfma_i32_32x32x32_i8 one 32x32 tile at a time.  Bits are expanded to 0/1
+// bytes in registers.  A row-block stops as soon as every alive non-candidate row
+// has a candidate neighbour.  Phase 3 is fused: the wave that completes a
+// row-block writes its new alive mask, its members and, if rows remain, its
+// segments to the next round's active list.
 #include "round.hpp"
 
 namespace tcmis {
@@ -37,6 +44,8 @@ namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
+
+constexpr int kWpb = kBlock / kWave;   // waves per block
 
 struct TileArgs {
     const int32_t* seg_rb;
@@ -50,33 +59,64 @@ struct TileArgs {
     uint32_t* alive;
     uint64_t* cand;
     uint32_t* inmask;
-    uint32_t* acc;      // [2*nI]: candidate-phase and exclusion-phase partial masks
-    uint32_t* done;     // [2*nI]
+    uint64_t* part;     // [2*nI]: candidate-phase and exclusion-phase (count << 32 | mask) words
     const int32_t* seg_all;
     int32_t* seglist[2];
-    int64_t nseg;
+    const Meta* meta;
     int64_t nI;
     Ctrl* ctrl;
     TraceRec* trace;
 };
 
 template <int T>
-__device__ inline uint32_t row_mask(const uint32_t* bits, int64_t t, int row) {
-    if (T == 16) return (bits[t * 8 + (row >> 1)] >> ((row & 1) << 4)) & 0xFFFFu;
-    return bits[t * 32 + row];
+struct Geo {
+    static constexpr int kLpt = T == 16 ? 1 : 4;      // lanes per tile
+    static constexpr int kTpi = kWave / kLpt;          // tiles per wave iteration
+    static constexpr int kWpt = T * T / 32;            // bitmap words per tile
+};
+
+// the 8 bitmap words a lane owns: tile t, quarter k
+template <int T>
+__device__ inline void load8(const uint32_t* bits, int64_t t, int k, uint32_t w[8]) {
+    const uint4* p = reinterpret_cast<const uint4*>(bits + t * Geo<T>::kWpt + 8 * k);
+    const uint4 a = p[0], b = p[1];
+    w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w;
+    w[4] = b.x; w[5] = b.y; w[6] = b.z; w[7] = b.w;
 }
 
-// rows (bit r) with any lane of that row set, from a 64-lane ballot laid out as
-// lane = g*T + r
+// rows (bit r of the row-block) among the lane's words with a set bit in colmask
 template <int T>
-__device__ inline uint32_t fold_rows(uint64_t b) {
-    if (T == 16) return (uint32_t)((b | (b >> 16) | (b >> 32) | (b >> 48)) & 0xFFFFull);
-    return (uint32_t)((b | (b >> 32)) & 0xFFFFFFFFull);
+__device__ inline uint32_t rows_hit(const uint32_t w[8], uint32_t colmask, int k) {
+    uint32_t r = 0;
+    if (T == 16) {
+        const uint32_t cm = colmask | (colmask << 16);
+        #pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const uint32_t x = w[j] & cm;
+            r |= (uint32_t)((x & 0xFFFFu) != 0) << (2 * j);
+            r |= (uint32_t)((x >> 16) != 0) << (2 * j + 1);
+        }
+    } else {
+        #pragma unroll
+        for (int j = 0; j < 8; ++j) r |= (uint32_t)((w[j] & colmask) != 0) << j;
+        r <<= 8 * k;
+    }
+    return r;
+}
+
+__device__ inline uint32_t wave_or(uint32_t x) {
+    for (int off = kWave / 2; off > 0; off >>= 1) x |= (uint32_t)__shfl_xor((int)x, off, kWave);
+    return x;
 }
 
 __device__ inline void active_list(const TileArgs& a, int r, const int32_t** list, int64_t* n) {
-    if (r == 1) { *list = a.seg_all; *n = a.nseg; }
+    if (r == 1) { *list = a.seg_all; *n = a.meta->nseg; }
     else { *list = a.seglist[(r - 1) & 1]; *n = a.ctrl->n_act[(r - 1) & 1][0]; }
+}
+
+__device__ inline uint32_t cand_of(const uint64_t* cand, int64_t J, int r) {
+    const uint64_t w = cand[J];
+    return (uint32_t)(w >> 32) == (uint32_t)r ? (uint32_t)w : 0u;
 }
 
 // 16 bits -> 16 bytes of 0/1 (byte i = bit i)
@@ -90,87 +130,92 @@ __device__ inline v4i expand16(uint32_t x) {
 }
 
 // Completes a row-block's mask: single-segment row-blocks use the wave's own mask;
-// otherwise the last of the row-block's segments gets the OR of all partials.
-// Returns true (in lane 0) when the caller must finalise the row-block with *total.
-__device__ inline bool combine(uint32_t* acc, uint32_t* done, int64_t I, int nseg, uint32_t part, uint32_t* total) {
-    if (nseg == 1) { *total = part; return true; }
-    if (part) atomicOr(&acc[I], part);
-    __threadfence();
-    const uint32_t prev = atomicAdd(&done[I], 1u);
-    if (prev != (uint32_t)nseg - 1) return false;
-    __threadfence();
-    *total = atomicExch(&acc[I], 0u);
-    atomicExch(&done[I], 0u);
+// otherwise each segment folds its partial mask and a completion count into one
+// 64-bit word (count << 32 | mask) with compare-and-swap, and the segment that
+// brings the count to nseg receives the OR of all partials and resets the word.
+// One atomic word carries both, so no fence is needed between them.
+__device__ inline bool combine(uint64_t* part, int64_t I, int nseg, uint32_t mine, uint32_t* total) {
+    if (nseg == 1) { *total = mine; return true; }
+    unsigned long long* w = (unsigned long long*)&part[I];
+    unsigned long long old = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), seen;
+    do {
+        seen = old;
+        const unsigned long long nw = ((seen >> 32) + 1) << 32 | ((uint32_t)seen | mine);
+        old = atomicCAS(w, seen, nw);
+    } while (old != seen);
+    if ((int64_t)(seen >> 32) + 1 != nseg) return false;
+    *total = (uint32_t)seen | mine;
+    atomicExch(w, 0ull);
     return true;
 }
 
 template <int T, int ORIENT>
-__global__ void __launch_bounds__(kBlock) k_tile_cand(TileArgs a) {
-    constexpr int G = kWave / T;   // tiles per pass
-    __shared__ uint64_t kst[kBlock / kWave][kWave];
-    if (a.ctrl->alive == 0) return;
-    const int r = a.ctrl->round + 1;
+__global__ void __launch_bounds__(kBlock) k_tile_cand(TileArgs a, int r) {
+    using G = Geo<T>;
+    __shared__ uint64_t rkeys[kWpb][32];
+    open_round(a.ctrl, a.trace, r);
     const int32_t* list;
     int64_t nact;
     active_list(a, r, &list, &nact);
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.ctrl->n_act[r & 1][0] = 0;
     const int lane = lane_id(), wid = threadIdx.x / kWave;
-    const int g = lane / T, row = lane % T;
-    uint64_t* kw = kst[wid];
-    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / kWave);
+    const int sub = lane / G::kLpt, k = lane % G::kLpt;
+    uint64_t* rk = rkeys[wid];
+    const int64_t nwaves = (int64_t)gridDim.x * kWpb;
     int64_t n_cand = 0, tiles = 0, keys = 0;
-    for (int64_t w = (int64_t)blockIdx.x * (kBlock / kWave) + wid; w < nact; w += nwaves) {
+    for (int64_t w = (int64_t)blockIdx.x * kWpb + wid; w < nact; w += nwaves) {
         const int s = list[w];
         const int64_t I = a.seg_rb[s];
         const int64_t t0 = a.seg_t0[s], t1 = a.seg_t1[s];
         const uint32_t al = a.alive[I];
-        const uint64_t kr = ORIENT ? 0 : a.key_p[I * T + row];
-        bool blk = false;
+        if (!ORIENT) {
+            wave_sync_lds();
+            if (lane < T) rk[lane] = a.key_p[I * T + lane];
+            wave_sync_lds();
+        }
         uint32_t blocked = 0;
-        for (int64_t tb = t0; tb < t1; tb += G) {
-            const int64_t t = tb + g;
+        for (int64_t tb = t0; tb < t1; tb += G::kTpi) {
+            const int64_t t = tb + sub;
             const bool valid = t < t1;
             const int64_t J = valid ? a.tile_col[t] : 0;
             const uint32_t aJ = valid ? a.alive[J] : 0u;
-            uint32_t m = valid ? (row_mask<T>(a.bits, t, row) & aJ) : 0u;
-            if (ORIENT) {
-                blk |= m != 0;
-            } else {
-                // stage the keys of the alive columns of this lane's tile
-                const bool need = (aJ >> row) & 1u;
-                kw[lane] = need ? a.key_p[J * T + row] : 0ull;
-                keys += need;
-                wave_sync_lds();
-                while (m && !blk) {
-                    const int c = __builtin_ctz(m);
-                    m &= m - 1;
-                    blk = kw[g * T + c] > kr;
+            tiles += valid && k == 0;
+            if (aJ) {
+                uint32_t wd[8];
+                load8<T>(a.bits, t, k, wd);
+                if (ORIENT) {
+                    blocked |= rows_hit<T>(wd, aJ, k);
+                } else {
+                    #pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        uint32_t x = wd[j] & (T == 16 ? (aJ | (aJ << 16)) : aJ);
+                        while (x) {
+                            const int b = __builtin_ctz(x);
+                            x &= x - 1;
+                            const int row = T == 16 ? 2 * j + (b >> 4) : 8 * k + j;
+                            const int col = T == 16 ? (b & 15) : b;
+                            if ((blocked >> row) & 1u) continue;
+                            ++keys;
+                            if (a.key_p[J * T + col] > rk[row]) blocked |= 1u << row;
+                        }
+                    }
                 }
-                wave_sync_lds();
             }
-            tiles += valid && row == 0;
-            blocked = fold_rows<T>(ballot(blk));
-            if ((blocked & al) == al) break;
+            if ((wave_or(blocked) & al) == al) break;
         }
-        blocked = fold_rows<T>(ballot(blk));
+        blocked = wave_or(blocked);
         if (lane == 0) {
             uint32_t total;
-            if (combine(a.acc, a.done, I, a.rb_nseg[I], blocked, &total)) {
+            if (combine(a.part, I, a.rb_nseg[I], blocked, &total)) {
                 const uint32_t c = al & ~total;
                 a.cand[I] = ((uint64_t)(uint32_t)r << 32) | c;
                 n_cand += __popc(c);
             }
         }
     }
-    wave_add(&a.ctrl->cnt_c, n_cand);
-    wave_add(&a.ctrl->u[0], tiles);
-    wave_add(&a.ctrl->u[1], keys);
-}
-
-template <int T>
-__device__ inline uint32_t cand_of(const uint64_t* cand, int64_t J, int r) {
-    const uint64_t w = cand[J];
-    return (uint32_t)(w >> 32) == (uint32_t)r ? (uint32_t)w : 0u;
+    int64_t* cnt = a.ctrl->cnt[r & 1];
+    wave_add(&cnt[0], n_cand);
+    wave_add(&cnt[2], tiles);
+    wave_add(&cnt[3], keys);
 }
 
 // rows with N_c > 0 from the accumulator (all B columns are equal, so any column works)
@@ -201,71 +246,85 @@ __device__ inline uint32_t hits32(const v16i& acc) {
     return h;
 }
 
+template <int T>
+struct Acc;
+template <>
+struct Acc<16> { typedef v4i type; };
+template <>
+struct Acc<32> { typedef v16i type; };
+
 template <int T, int ORIENT>
-__global__ void __launch_bounds__(kBlock) k_tile_excl(TileArgs a) {
-    __shared__ int32_t lbuf[kBlock / kWave][kWave];
-    if (a.ctrl->alive == 0) return;
-    const int r = a.ctrl->round + 1;
+__global__ void __launch_bounds__(kBlock) k_tile_excl(TileArgs a, int r) {
+    using G = Geo<T>;
+    __shared__ uint32_t sbits[kWpb][G::kTpi * G::kWpt];
+    __shared__ uint32_t scand[kWpb][G::kTpi];
+    __shared__ int32_t lbuf[kWpb][kWave];
     const int32_t* list;
     int64_t nact;
     active_list(a, r, &list, &nact);
     int32_t* next = a.seglist[r & 1];
     int64_t* next_cnt = &a.ctrl->n_act[r & 1][0];
     const int lane = lane_id(), wid = threadIdx.x / kWave;
+    const int sub = lane / G::kLpt, k = lane % G::kLpt;
+    uint32_t* sb = sbits[wid];
+    uint32_t* sc = scand[wid];
     int32_t* buf = lbuf[wid];
     int pend = 0;
-    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / kWave);
+    const int64_t nwaves = (int64_t)gridDim.x * kWpb;
     int64_t n_out = 0, scanned = 0, mult = 0;
-    for (int64_t w = (int64_t)blockIdx.x * (kBlock / kWave) + wid; w < nact; w += nwaves) {
+    for (int64_t w = (int64_t)blockIdx.x * kWpb + wid; w < nact; w += nwaves) {
         const int s = list[w];
         const int64_t I = a.seg_rb[s];
         const int64_t t0 = a.seg_t0[s], t1 = a.seg_t1[s];
         const uint32_t al = a.alive[I];
-        const uint32_t cI = cand_of<T>(a.cand, I, r);
+        const uint32_t cI = cand_of(a.cand, I, r);
         const uint32_t rest = al & ~cI;     // undecided non-candidates
         uint32_t hit = 0;
         if (rest) {
-            if (T == 16) {
-                const int g = lane >> 4, row = lane & 15;
-                v4i acc = {0, 0, 0, 0};
-                int since = 0;
-                for (int64_t tb = t0; tb < t1; tb += 4) {
-                    const int64_t t = tb + g;
-                    const bool valid = t < t1;
-                    const int64_t J = valid ? a.tile_col[t] : 0;
-                    const uint32_t cJ = valid ? cand_of<T>(a.cand, J, r) : 0u;
-                    scanned += valid && row == 0;
-                    if (!ballot(cJ != 0)) continue;      // no candidate in any of the 4 segments
-                    const uint32_t m = cJ ? row_mask<16>(a.bits, t, row) : 0u;
-                    mult += cJ != 0 && row == 0;
-                    acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(expand16(m), expand16(cJ), acc, 0, 0, 0);
-                    if (++since == 4) {
-                        since = 0;
-                        hit = hits16(acc);
-                        if ((hit & rest) == rest) break;
-                    }
+            typename Acc<T>::type acc = {};
+            for (int64_t tb = t0; tb < t1; tb += G::kTpi) {
+                const int64_t t = tb + sub;
+                const bool valid = t < t1;
+                const int64_t J = valid ? a.tile_col[t] : 0;
+                const uint32_t cJ = valid ? cand_of(a.cand, J, r) : 0u;
+                scanned += valid && k == 0;
+                const uint64_t heads = ballot(cJ != 0 && k == 0);
+                if (!heads) continue;
+                // compact the tiles with candidates into LDS
+                wave_sync_lds();
+                if (cJ) {
+                    const int slot = __popcll(heads & ((1ull << (lane - k)) - 1ull));
+                    uint32_t wd[8];
+                    load8<T>(a.bits, t, k, wd);
+                    uint4* dst = reinterpret_cast<uint4*>(sb + slot * G::kWpt + 8 * k);
+                    dst[0] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+                    dst[1] = make_uint4(wd[4], wd[5], wd[6], wd[7]);
+                    if (k == 0) sc[slot] = cJ;
                 }
-                hit = hits16(acc);
-            } else {
-                const int h = lane >> 5, row = lane & 31;
-                v16i acc = {};
-                int since = 0;
-                for (int64_t t = t0; t < t1; ++t) {
-                    const int64_t J = a.tile_col[t];
-                    const uint32_t cJ = cand_of<T>(a.cand, J, r);
-                    scanned += lane == 0;
-                    if (!cJ) continue;
-                    const uint32_t m = row_mask<32>(a.bits, t, row);
-                    mult += lane == 0;
-                    acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(expand16(m >> (16 * h)), expand16(cJ >> (16 * h)), acc,
-                                                               0, 0, 0);
-                    if (++since == 4) {
-                        since = 0;
-                        hit = hits32(acc);
-                        if ((hit & rest) == rest) break;
+                wave_sync_lds();
+                const int ntc = __popcll(heads);
+                mult += lane == 0 ? ntc : 0;
+                if constexpr (T == 16) {
+                    const int g = lane >> 4, row = lane & 15;
+                    for (int base = 0; base < ntc; base += 4) {
+                        const int sl = base + g;
+                        const bool v = sl < ntc;
+                        const uint32_t m = v ? (sb[sl * 8 + (row >> 1)] >> ((row & 1) << 4)) & 0xFFFFu : 0u;
+                        const uint32_t c = v ? sc[sl] : 0u;
+                        acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(expand16(m), expand16(c), acc, 0, 0, 0);
                     }
+                    hit = hits16(acc);
+                } else {
+                    const int h = lane >> 5, row = lane & 31;
+                    for (int sl = 0; sl < ntc; ++sl) {
+                        const uint32_t m = sb[sl * 32 + row];
+                        const uint32_t c = sc[sl];
+                        acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(expand16(m >> (16 * h)), expand16(c >> (16 * h)),
+                                                                   acc, 0, 0, 0);
+                    }
+                    hit = hits32(acc);
                 }
-                hit = hits32(acc);
+                if ((hit & rest) == rest) break;
             }
         }
         bool keep_rb = false;
@@ -273,7 +332,7 @@ __global__ void __launch_bounds__(kBlock) k_tile_excl(TileArgs a) {
         if (lane == 0) {
             uint32_t total;
             nseg_I = a.rb_nseg[I];
-            if (combine(a.acc + a.nI, a.done + a.nI, I, nseg_I, hit & rest, &total)) {
+            if (combine(a.part + a.nI, I, nseg_I, hit & rest, &total)) {
                 const uint32_t out = rest & total;
                 const uint32_t na = rest & ~total;
                 a.alive[I] = na;
@@ -290,17 +349,17 @@ __global__ void __launch_bounds__(kBlock) k_tile_excl(TileArgs a) {
             if (lane == 0) {
                 const unsigned long long p = atomicAdd((unsigned long long*)next_cnt, (unsigned long long)nseg_I);
                 const int s0 = a.rb_seg0[I];
-                for (int k = 0; k < nseg_I; ++k) next[p + k] = s0 + k;
+                for (int q = 0; q < nseg_I; ++q) next[p + q] = s0 + q;
             }
         } else {
             lbuf_push(buf, pend, next, next_cnt, keep_rb && lane == 0, s);
         }
     }
     lbuf_flush(buf, pend, next, next_cnt);
-    wave_add(&a.ctrl->cnt_x, n_out);
-    wave_add(&a.ctrl->u[2], scanned);
-    wave_add(&a.ctrl->u[3], mult);
-    finish_round(a.ctrl, a.trace, r);
+    int64_t* cnt = a.ctrl->cnt[r & 1];
+    wave_add(&cnt[1], n_out);
+    wave_add(&cnt[4], scanned);
+    wave_add(&cnt[5], mult);
 }
 
 __global__ void k_tile_output(const int32_t* new_id, const uint32_t* inmask, int64_t n, int tshift, uint8_t* in_set) {
@@ -310,43 +369,52 @@ __global__ void k_tile_output(const int32_t* new_id, const uint32_t* inmask, int
     }
 }
 
+__global__ void k_tile_init(const uint32_t* alive0, uint32_t* alive, uint64_t* cand, uint32_t* inmask, uint64_t* part,
+                            int64_t nI) {
+    for (int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; I < nI; I += (int64_t)gridDim.x * blockDim.x) {
+        alive[I] = alive0[I];
+        cand[I] = 0;
+        inmask[I] = 0;
+        part[I] = 0;
+        part[nI + I] = 0;
+    }
+}
+
 TileArgs make_args(mis_graph* g) {
     TileArgs a;
     a.seg_rb = g->seg_rb; a.seg_t0 = g->seg_t0; a.seg_t1 = g->seg_t1;
     a.rb_seg0 = g->rb_seg0; a.rb_nseg = g->rb_nseg;
     a.tile_col = g->tile_col; a.bits = g->tile_bits; a.key_p = g->key_p;
-    a.alive = g->alive; a.cand = g->cand; a.inmask = g->inmask; a.acc = g->acc; a.done = g->done;
+    a.alive = g->alive; a.cand = g->cand; a.inmask = g->inmask; a.part = g->part;
     a.seg_all = g->seg_all; a.seglist[0] = g->seglist[0]; a.seglist[1] = g->seglist[1];
-    a.nseg = g->nseg; a.nI = g->nI;
+    a.meta = g->meta; a.nI = g->nI;
     a.ctrl = g->ctrl; a.trace = g->trace;
     return a;
 }
 
 template <int T, int ORIENT>
-void launch_phase(mis_graph* g, int phase, hipStream_t s) {
+void launch_phase(mis_graph* g, int phase, int r, hipStream_t s) {
     TileArgs a = make_args(g);
-    if (phase == 0) hipLaunchKernelGGL((k_tile_cand<T, ORIENT>), dim3(g->grid_blocks), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((k_tile_excl<T, ORIENT>), dim3(g->grid_blocks), dim3(kBlock), 0, s, a);
+    if (phase == 0) hipLaunchKernelGGL((k_tile_cand<T, ORIENT>), dim3(g->grid_blocks), dim3(kBlock), 0, s, a, r);
+    else hipLaunchKernelGGL((k_tile_excl<T, ORIENT>), dim3(g->grid_blocks), dim3(kBlock), 0, s, a, r);
 }
 
 }  // namespace
 
 int tile_init(mis_graph* g, hipStream_t s) {
-    const size_t nI = (size_t)g->nI;
-    TC_HIP(hipMemcpyAsync(g->alive, g->alive0, nI * 4, hipMemcpyDeviceToDevice, s));
-    TC_HIP(hipMemsetAsync(g->cand, 0, nI * 8, s));
-    TC_HIP(hipMemsetAsync(g->inmask, 0, nI * 4, s));
-    TC_HIP(hipMemsetAsync(g->acc, 0, nI * 2 * 4, s));
-    TC_HIP(hipMemsetAsync(g->done, 0, nI * 2 * 4, s));
+    if (g->nI > 0)
+        hipLaunchKernelGGL(k_tile_init, dim3(stream_grid(g->nI)), dim3(kBlock), 0, s, g->alive0, g->alive, g->cand,
+                           g->inmask, g->part, g->nI);
+    TC_HIP(hipGetLastError());
     return MIS_OK;
 }
 
 // phase 0 = candidate kernel, 1 = exclusion kernel (which closes the round)
-int tile_enqueue_phase(mis_graph* g, int phase, hipStream_t s) {
+int tile_enqueue_phase(mis_graph* g, int phase, int r, hipStream_t s) {
     if (g->tile == 16) {
-        if (g->orient) launch_phase<16, 1>(g, phase, s); else launch_phase<16, 0>(g, phase, s);
+        if (g->orient) launch_phase<16, 1>(g, phase, r, s); else launch_phase<16, 0>(g, phase, r, s);
     } else {
-        if (g->orient) launch_phase<32, 1>(g, phase, s); else launch_phase<32, 0>(g, phase, s);
+        if (g->orient) launch_phase<32, 1>(g, phase, r, s); else launch_phase<32, 0>(g, phase, r, s);
     }
     TC_HIP(hipGetLastError());
     return MIS_OK;

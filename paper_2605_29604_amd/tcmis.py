@@ -25,7 +25,7 @@ REORDERS = {"auto": REORDER_AUTO, "none": REORDER_NONE, "degree": REORDER_DEGREE
             "key": REORDER_KEY, "rcm": REORDER_RCM}
 
 # symbols declared in include/tcmis.h
-EXPORTS = ["mis_default_opts", "mis_build_tiles", "mis_graph_bytes", "mis_solve", "mis_solve_batch",
+EXPORTS = ["mis_default_opts", "mis_build_bytes", "mis_build_tiles", "mis_graph_bytes", "mis_solve", "mis_solve_batch",
            "mis_free_tiles", "mis_status_string", "mis_last_error", "mis_version"]
 
 
@@ -70,8 +70,11 @@ def lib():
     vp, i32 = ctypes.c_void_p, ctypes.c_int32
     L.mis_default_opts.argtypes = [ctypes.POINTER(MisBuildOpts)]
     L.mis_default_opts.restype = None
-    L.mis_build_tiles.argtypes = [ctypes.POINTER(MisCsr), ctypes.POINTER(MisBuildOpts), vp,
-                                  ctypes.POINTER(vp)]
+    L.mis_build_bytes.argtypes = [ctypes.POINTER(MisCsr), ctypes.POINTER(MisBuildOpts),
+                                  ctypes.POINTER(ctypes.c_size_t)]
+    L.mis_build_bytes.restype = ctypes.c_int
+    L.mis_build_tiles.argtypes = [ctypes.POINTER(MisCsr), ctypes.POINTER(MisBuildOpts), vp, ctypes.c_size_t,
+                                  vp, ctypes.POINTER(vp)]
     L.mis_build_tiles.restype = ctypes.c_int
     L.mis_graph_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
     L.mis_graph_bytes.restype = ctypes.c_int
@@ -130,15 +133,9 @@ class MisGraph:
             self.handle = None
 
 
-def mis_build_tiles(row_ptr, col_idx, path="auto", tile=0, reorder="auto", orient=-1, validate=False,
-                    seed=1, keys=None, poll_rounds=0, stream=None) -> MisGraph:
-    """row_ptr: cuda int64[n+1]; col_idx: cuda int32[nnz]; keys: optional cuda uint64[n] (as int64)."""
-    L = lib()
-    n = row_ptr.numel() - 1
-    nnz = col_idx.numel()
-    csr = MisCsr(n, nnz, _ptr(row_ptr), _ptr(col_idx) if nnz else None)
+def _opts(path="auto", tile=0, reorder="auto", orient=-1, validate=False, seed=1, keys=None, poll_rounds=0):
     o = MisBuildOpts()
-    L.mis_default_opts(ctypes.byref(o))
+    lib().mis_default_opts(ctypes.byref(o))
     o.path = PATHS[path] if isinstance(path, str) else int(path)
     o.tile = int(tile)
     o.reorder = REORDERS[reorder] if isinstance(reorder, str) else int(reorder)
@@ -147,10 +144,39 @@ def mis_build_tiles(row_ptr, col_idx, path="auto", tile=0, reorder="auto", orien
     o.poll_rounds = int(poll_rounds)
     o.seed = int(seed) & (2**64 - 1)
     o.keys = _ptr(keys)
+    return o
+
+
+def mis_build_bytes(n: int, nnz: int, **opts) -> int:
+    """Workspace bytes mis_build_tiles needs (host-only arithmetic)."""
+    csr = MisCsr(n, nnz, ctypes.c_void_p(256), ctypes.c_void_p(256) if nnz else None)
+    o = _opts(**opts)
+    b = ctypes.c_size_t(0)
+    _check(lib().mis_build_bytes(ctypes.byref(csr), ctypes.byref(o), ctypes.byref(b)))
+    return int(b.value)
+
+
+def mis_build_tiles(row_ptr, col_idx, path="auto", tile=0, reorder="auto", orient=-1, validate=False,
+                    seed=1, keys=None, poll_rounds=0, workspace=None, stream=None) -> MisGraph:
+    """row_ptr: cuda int64[n+1]; col_idx: cuda int32[nnz]; keys: optional cuda uint64[n] (as int64).
+
+    The device workspace comes from torch's allocator unless one is passed (a cuda
+    uint8 tensor of at least mis_build_bytes bytes); the handle keeps it alive.
+    """
+    import torch
+    L = lib()
+    n = row_ptr.numel() - 1
+    nnz = col_idx.numel()
+    csr = MisCsr(n, nnz, _ptr(row_ptr), _ptr(col_idx) if nnz else None)
+    o = _opts(path, tile, reorder, orient, validate, seed, keys, poll_rounds)
+    need = ctypes.c_size_t(0)
+    _check(L.mis_build_bytes(ctypes.byref(csr), ctypes.byref(o), ctypes.byref(need)))
+    if workspace is None:
+        workspace = torch.empty(int(need.value), dtype=torch.uint8, device=row_ptr.device)
     h = ctypes.c_void_p(None)
-    _check(L.mis_build_tiles(ctypes.byref(csr), ctypes.byref(o), ctypes.c_void_p(_stream(stream)),
-                             ctypes.byref(h)))
-    return MisGraph(h, n, nnz, (row_ptr, col_idx, keys))
+    _check(L.mis_build_tiles(ctypes.byref(csr), ctypes.byref(o), _ptr(workspace), workspace.numel(),
+                             ctypes.c_void_p(_stream(stream)), ctypes.byref(h)))
+    return MisGraph(h, n, nnz, (row_ptr, col_idx, keys, workspace))
 
 
 def _stats_dict(st: MisStats, trace_buf) -> dict:

@@ -46,29 +46,51 @@ def test_default_opts(L):
     assert (o.path, o.tile, o.reorder, o.orient, o.validate, o.seed) == (0, 0, 0, -1, 0, 1)
 
 
+def build(L, csr, opts, ws, ws_bytes, h):
+    return L.mis_build_tiles(ctypes.byref(csr) if csr is not None else None,
+                             ctypes.byref(opts) if opts is not None else None, ws, ws_bytes, None, h)
+
+
 def test_host_argument_errors(L):
     h = ctypes.c_void_p(None)
-    csr = tcmis.MisCsr(10, 0, ctypes.c_void_p(8), None)
-    assert L.mis_build_tiles(ctypes.byref(csr), None, None, None) == tcmis.MIS_EINVAL
-    assert L.mis_build_tiles(None, None, None, ctypes.byref(h)) == tcmis.MIS_EINVAL
-    bad = tcmis.MisCsr(-1, 0, ctypes.c_void_p(8), None)
-    assert L.mis_build_tiles(ctypes.byref(bad), None, None, ctypes.byref(h)) == tcmis.MIS_EINVAL
-    nul = tcmis.MisCsr(10, 5, None, None)
-    assert L.mis_build_tiles(ctypes.byref(nul), None, None, ctypes.byref(h)) == tcmis.MIS_EINVAL
-    nocol = tcmis.MisCsr(10, 5, ctypes.c_void_p(8), None)
-    assert L.mis_build_tiles(ctypes.byref(nocol), None, None, ctypes.byref(h)) == tcmis.MIS_EINVAL
+    hp = ctypes.byref(h)
+    ws = ctypes.c_void_p(1 << 20)   # never dereferenced: every call below fails on the host
+    csr = tcmis.MisCsr(10, 0, ctypes.c_void_p(256), None)
+    assert build(L, csr, None, ws, 1 << 40, None) == tcmis.MIS_EINVAL
+    assert build(L, None, None, ws, 1 << 40, hp) == tcmis.MIS_EINVAL
+    for bad in (tcmis.MisCsr(-1, 0, ctypes.c_void_p(256), None), tcmis.MisCsr(10, 5, None, None),
+                tcmis.MisCsr(10, 5, ctypes.c_void_p(256), None), tcmis.MisCsr(10, 1 << 31, ctypes.c_void_p(256),
+                                                                               ctypes.c_void_p(256))):
+        assert build(L, bad, None, ws, 1 << 40, hp) == tcmis.MIS_EINVAL
     for field, value in (("tile", 8), ("path", 7), ("reorder", 9), ("orient", 2), ("poll_rounds", -1)):
         o = tcmis.MisBuildOpts()
         L.mis_default_opts(ctypes.byref(o))
         setattr(o, field, value)
-        assert L.mis_build_tiles(ctypes.byref(csr), ctypes.byref(o), None, ctypes.byref(h)) == tcmis.MIS_EINVAL
+        assert build(L, csr, o, ws, 1 << 40, hp) == tcmis.MIS_EINVAL
         assert field.split("_")[0] in L.mis_last_error().decode()
-    big = tcmis.MisCsr((1 << 24) + 1, 0, ctypes.c_void_p(8), None)
-    assert L.mis_build_tiles(ctypes.byref(big), None, None, ctypes.byref(h)) == tcmis.MIS_EINVAL
+    big = tcmis.MisCsr((1 << 24) + 1, 0, ctypes.c_void_p(256), None)
+    assert build(L, big, None, ws, 1 << 40, hp) == tcmis.MIS_EINVAL
     assert "2^24" in L.mis_last_error().decode()
+    # workspace checks: size from mis_build_bytes, alignment
+    need = ctypes.c_size_t(0)
+    assert L.mis_build_bytes(ctypes.byref(csr), None, ctypes.byref(need)) == 0 and need.value > 0
+    assert build(L, csr, None, ws, need.value - 1, hp) == tcmis.MIS_EINVAL
+    assert "workspace" in L.mis_last_error().decode()
+    assert build(L, csr, None, ctypes.c_void_p((1 << 20) + 64), need.value, hp) == tcmis.MIS_EINVAL
+    assert build(L, csr, None, None, need.value, hp) == tcmis.MIS_EINVAL
     assert not h.value
     assert L.mis_solve(None, None, 0, None, None) == tcmis.MIS_EINVAL
     assert L.mis_solve_batch(None, -1, None, None, None) == tcmis.MIS_EINVAL
     assert L.mis_solve_batch(None, 2, None, None, None) == tcmis.MIS_EINVAL
     assert L.mis_graph_bytes(None, None) == tcmis.MIS_EINVAL
     L.mis_free_tiles(None)
+
+
+def test_build_bytes_scaling(L):
+    # footprint grows with the graph and is larger for tiles than for the CSR path
+    small = tcmis.mis_build_bytes(1000, 8000, path="csr")
+    big = tcmis.mis_build_bytes(100000, 800000, path="csr")
+    big2 = tcmis.mis_build_bytes(200000, 1600000, path="csr")
+    assert 1.8 < (big2 - small) / (big - small) < 2.2     # linear in the graph size
+    assert tcmis.mis_build_bytes(100000, 800000, path="tile", tile=32, orient=0) > \
+        tcmis.mis_build_bytes(100000, 800000, path="tile", tile=16, orient=1) > big
