@@ -55,7 +55,7 @@ enum {
 enum {
     MIS_REORDER_AUTO = 0,
     MIS_REORDER_NONE = 1,    /* input order (natural order of meshes) */
-    MIS_REORDER_DEGREE = 2,  /* decreasing degree, ties by id */
+    MIS_REORDER_DEGREE = 2,  /* decreasing degree class floor(255 / (1 + deg)), ties by id */
     MIS_REORDER_KEY = 3,     /* decreasing priority key: tile column < row <=> higher key */
     MIS_REORDER_RCM = 4      /* reverse Cuthill-McKee (host), banded meshes */
 };

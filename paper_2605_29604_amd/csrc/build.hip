@@ -97,18 +97,24 @@ __global__ void k_invert(const int32_t* new_id, int32_t* order, int64_t n) {
     GRID_STRIDE(v, n) order[new_id[v]] = (int32_t)v;
 }
 
-// sort keys of the degree and priority orders (ascending sort)
+// Sort keys of the degree-class and priority orders (ascending, stable sort).
+//   degree class: 255 - floor(255 / (1 + deg)) (the discretised priority of the key
+//                 rule, highest first), one 8-bit pass; ties keep increasing id.
+//   priority:     ~key, input laid out by decreasing id.  With the default key rule
+//                 the low 24 key bits are the id, so sorting bits 24..63 stably
+//                 already yields decreasing key order; user keys sort all 64 bits.
 __global__ void k_order_keys(const int64_t* rp, const uint64_t* key, int64_t n, int mode, uint64_t* sk,
                              uint32_t* payload) {
-    GRID_STRIDE(v, n) {
+    GRID_STRIDE(i, n) {
         if (mode == MIS_REORDER_DEGREE) {
-            const int64_t deg = rp[v + 1] - rp[v];
-            const uint64_t inv = 0xFFFFFFFFull - (uint64_t)(deg > 0xFFFFFFFFll ? 0xFFFFFFFFll : deg);
-            sk[v] = (inv << 32) | (uint64_t)v;   // decreasing degree, then id
+            const int64_t deg = rp[i + 1] - rp[i];
+            sk[i] = (uint64_t)(255 - 255 / (1 + deg));
+            payload[i] = (uint32_t)i;
         } else {
-            sk[v] = ~key[v];                      // decreasing priority
+            const int64_t v = n - 1 - i;
+            sk[i] = ~key[v];
+            payload[i] = (uint32_t)v;
         }
-        payload[v] = (uint32_t)v;
     }
 }
 
@@ -127,66 +133,156 @@ __global__ void k_new_degrees(const int64_t* rp, const int32_t* order, int64_t n
     }
 }
 
-// after the scan ndeg holds the new row pointer; mark row starts and the offset
-// between old and new entry positions of every row
-__global__ void k_mark_rows(const int64_t* rp, const int32_t* order, const int32_t* nrp, int64_t n, int32_t* rowof,
-                            int64_t* rbase) {
-    GRID_STRIDE(p, n) {
-        const int32_t v = order[p];
-        const int64_t start = nrp[p];
-        rbase[p] = rp[v] - start;
-        if (rp[v + 1] > rp[v]) rowof[start] = (int32_t)p;
-    }
-}
-
 template <int kTshift, int kMode>   // kMode: 0 all entries, 1 lower-key by id (priority order), 2 lower-key by key
-__global__ void k_entries(const int32_t* ci, const int32_t* rowof, const int64_t* rbase, const int32_t* order,
-                          const int32_t* new_id, const uint64_t* key, int64_t nnz, uint64_t* ent) {
-    GRID_STRIDE(e, nnz) {
-        const int32_t p = rowof[e];
-        const int32_t u = ci[rbase[p] + e];
-        const int32_t q = new_id[u];
-        bool keep = true;
-        if (kMode == 1) keep = q > p;
-        if (kMode == 2) keep = key[u] < key[order[p]];
-        ent[e] = keep ? (((uint64_t)(q >> kTshift) << 36) | ((uint64_t)p << 5) | (uint64_t)(q & ((1 << kTshift) - 1)))
-                      : ~0ull;
+__device__ inline bool make_entry(int32_t p, int32_t u, uint64_t kv, const int32_t* new_id, const uint64_t* key,
+                                  uint64_t* out) {
+    const int32_t q = new_id[u];
+    bool keep = true;
+    if (kMode == 1) keep = q > p;
+    if (kMode == 2) keep = key[u] < kv;
+    *out = ((uint64_t)(q >> kTshift) << 36) | ((uint64_t)p << 5) | (uint64_t)(q & ((1 << kTshift) - 1));
+    return keep;
+}
+
+constexpr int kEntIters = 16;
+constexpr int kEntBlock = kBlock * kEntIters;   // new-order entries per workgroup (= one sort block)
+constexpr int kEntWindow = 4096;                // new rows a workgroup keeps in LDS
+
+// largest row p in [lo, hi] with nrp[p] <= e (the row that holds new-order entry e)
+__device__ inline int32_t find_row(const int32_t* nrp, int64_t lo, int64_t hi, int64_t e) {
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (nrp[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    return (int32_t)lo;
+}
+
+// first row of every workgroup's entry range
+__global__ void k_block_rows(const int32_t* nrp, int64_t n, int64_t nnz, int64_t nblocks, int32_t* brow) {
+    GRID_STRIDE(b, nblocks + 1) {
+        const int64_t e = b < nblocks ? b * kEntBlock : nnz - 1;
+        brow[b] = find_row(nrp, 0, n - 1, e);
     }
 }
 
-constexpr uint64_t kSentinelTop = ~0ull >> 36;
+// One candidate entry per adjacency entry in new-row order, coalesced over entries;
+// the rows of the workgroup's range are looked up in an LDS copy of the new row
+// pointer.  Kept entries are compacted to the front of the workgroup's 4096-slot
+// range (order preserved) and their number goes to cnt[block].
+template <int kTshift, int kMode>
+__global__ void __launch_bounds__(kBlock) k_entries(const int64_t* rp, const int32_t* ci, const int32_t* order,
+                                                    const int32_t* nrp, const int32_t* brow, const int32_t* new_id,
+                                                    const uint64_t* key, int64_t nnz, uint64_t* ent, int32_t* cnt) {
+    __shared__ int32_t win[kEntWindow];
+    __shared__ int32_t wcnt[kBlock / kWave];
+    const int lane = lane_id(), wid = threadIdx.x / kWave;
+    const int64_t base = (int64_t)blockIdx.x * kEntBlock;
+    const int64_t p0 = brow[blockIdx.x], p1 = brow[blockIdx.x + 1];
+    const int64_t w = p1 - p0 + 1;
+    const bool in_lds = w <= kEntWindow;
+    if (in_lds)
+        for (int64_t i = threadIdx.x; i < w; i += kBlock) win[i] = nrp[p0 + i];
+    __syncthreads();
+    int written = 0;   // kept entries of earlier iterations (block-uniform)
+    for (int it = 0; it < kEntIters; ++it) {
+        const int64_t e = base + (int64_t)it * kBlock + threadIdx.x;
+        bool keep = false;
+        uint64_t x = 0;
+        if (e < nnz) {
+            int32_t p;
+            if (in_lds) {
+                int lo = 0, hi = (int)w - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (win[mid] <= e) lo = mid; else hi = mid - 1;
+                }
+                p = (int32_t)(p0 + lo);
+            } else {
+                p = find_row(nrp, p0, p1, e);
+            }
+            const int32_t v = order[p];
+            const int64_t off = e - (in_lds ? win[p - p0] : nrp[p]);
+            const uint64_t kv = kMode == 2 ? key[v] : 0;
+            keep = make_entry<kTshift, kMode>(p, ci[rp[v] + off], kv, new_id, key, &x);
+        }
+        const uint64_t b = ballot(keep);
+        if (lane == 0) wcnt[wid] = __popcll(b);
+        __syncthreads();
+        int before = written, total = written;
+        for (int q = 0; q < kBlock / kWave; ++q) {
+            if (q < wid) before += wcnt[q];
+            total += wcnt[q];
+        }
+        if (keep) ent[base + before + __popcll(b & lanes_below())] = x;
+        written = total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) cnt[blockIdx.x] = written;
+}
+
+constexpr int kHeadIters = 8;
+constexpr int kHeadChunk = kBlock * kHeadIters;   // sorted entries per workgroup
 
 template <int kTshift>
 __device__ inline uint64_t tile_key(uint64_t x) {
     return ((x >> 36) << 32) | ((uint32_t)((x >> 5) & 0x7FFFFFFFull) >> kTshift);
 }
 
+// does sorted entry e start a tile (its (row block, column block) differs from e-1's)?
 template <int kTshift>
-__global__ void k_tile_flags(const uint64_t* ent, int64_t nnz, int32_t* flag, Meta* meta) {
-    GRID_STRIDE(e, nnz) {
-        const uint64_t x = ent[e];
-        const bool valid = (x >> 36) != kSentinelTop;
-        bool head = false;
-        if (valid) {
-            head = e == 0 || tile_key<kTshift>(x) != tile_key<kTshift>(ent[e - 1]);
-            if (e + 1 == nnz || (ent[e + 1] >> 36) == kSentinelTop) meta->nvalid = (int32_t)(e + 1);
-        }
-        flag[e] = head ? 1 : 0;
+__device__ inline bool is_head(const uint64_t* ent, int64_t e, int64_t nvalid, uint64_t* x) {
+    if (e >= nvalid) return false;
+    *x = ent[e];
+    return e == 0 || tile_key<kTshift>(*x) != tile_key<kTshift>(ent[e - 1]);
+}
+
+template <int kTshift>
+__global__ void __launch_bounds__(kBlock) k_head_count(const uint64_t* ent, const Meta* meta, int32_t* sums) {
+    __shared__ int32_t wsum[kBlock / kWave];
+    const int64_t nvalid = meta->nvalid;
+    const int64_t base = (int64_t)blockIdx.x * kHeadChunk;
+    int c = 0;
+    for (int it = 0; it < kHeadIters; ++it) {
+        uint64_t x;
+        c += __popcll(ballot(is_head<kTshift>(ent, base + (int64_t)it * kBlock + threadIdx.x, nvalid, &x)));
+    }
+    if (lane_id() == 0) wsum[threadIdx.x / kWave] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int q = 0; q < kBlock / kWave; ++q) t += wsum[q];
+        sums[blockIdx.x] = t;
     }
 }
 
 template <int kTshift>
-__global__ void k_tile_heads(const uint64_t* ent, int64_t nnz, const int32_t* excl, int32_t* tile_start,
-                             int32_t* tile_col, int32_t* tile_row) {
-    GRID_STRIDE(e, nnz) {
-        const uint64_t x = ent[e];
-        if ((x >> 36) == kSentinelTop) continue;
-        if (e == 0 || tile_key<kTshift>(x) != tile_key<kTshift>(ent[e - 1])) {
-            const int32_t t = excl[e];
+__global__ void __launch_bounds__(kBlock) k_head_write(const uint64_t* ent, const Meta* meta, const int32_t* chunk_off,
+                                                       int32_t* tile_start, int32_t* tile_col, int32_t* tile_row) {
+    __shared__ int32_t wcnt[kBlock / kWave];
+    const int64_t nvalid = meta->nvalid;
+    const int lane = lane_id(), wid = threadIdx.x / kWave;
+    const int64_t base = (int64_t)blockIdx.x * kHeadChunk;
+    int run = chunk_off[blockIdx.x];
+    for (int it = 0; it < kHeadIters; ++it) {
+        const int64_t e = base + (int64_t)it * kBlock + threadIdx.x;
+        uint64_t x = 0;
+        const bool h = is_head<kTshift>(ent, e, nvalid, &x);
+        const uint64_t b = ballot(h);
+        if (lane == 0) wcnt[wid] = __popcll(b);
+        __syncthreads();
+        int before = run, total = run;
+        for (int q = 0; q < kBlock / kWave; ++q) {
+            if (q < wid) before += wcnt[q];
+            total += wcnt[q];
+        }
+        if (h) {
+            const int t = before + __popcll(b & lanes_below());
             tile_start[t] = (int32_t)e;
             tile_col[t] = (int32_t)(((x >> 5) & 0x7FFFFFFFull) >> kTshift);
             tile_row[t] = (int32_t)(x >> 36);
         }
+        run = total;
+        __syncthreads();
     }
 }
 
@@ -331,11 +427,11 @@ size_t layout(mis_graph* g, char* base) {
     take(&g->pl2, (size_t)n * 4);
     take(&g->sort_tmp, sort_scratch_bytes(std::max(n, nnz)));
     take(&g->ndeg, (size_t)(n + 1) * 4);
-    take(&g->rbase, (size_t)n * 8);
-    take(&g->rowof, (size_t)nnz * 4);
+    take(&g->brow, (size_t)(ceil_div(nnz, kEntBlock) + 2) * 4);
     take(&g->ent, (size_t)nnz * 8);
     take(&g->ent2, (size_t)nnz * 8);
-    take(&g->tflag, (size_t)nnz * 4);
+    take(&g->hsums, (size_t)(ceil_div(nnz, 2048) + 2) * 4);
+    take(&g->ecnt, (size_t)(ceil_div(nnz, kEntBlock) + 1) * 4);
     take(&g->rb_ptr, (size_t)(nI + 1) * 8);
     take(&g->tile_col, (size_t)cap * 4);
     take(&g->tile_row, (size_t)cap * 4);
@@ -426,7 +522,9 @@ int build_order(mis_graph* g, hipStream_t s) {
     }
     LAUNCH(k_order_keys, n, g->row_ptr, g->key, n, g->reorder, g->sk, g->pl);
     bool alt = false;
-    TC_CHECK(radix_sort_u64(g->sk, g->sk2, g->pl, g->pl2, n, 0, 64, g->sort_tmp, &alt, s));
+    const int lo = g->reorder == MIS_REORDER_DEGREE ? 0 : (g->user_keys ? 0 : 24);
+    const int hi = g->reorder == MIS_REORDER_DEGREE ? 8 : 64;
+    TC_CHECK(radix_sort_u64(g->sk, g->sk2, g->pl, g->pl2, n, nullptr, lo, hi, g->sort_tmp, &alt, s));
     LAUNCH(k_scatter_order, n, alt ? g->pl2 : g->pl, n, g->order, g->new_id);
     return MIS_OK;
 }
@@ -436,25 +534,45 @@ int build_tiles_t(mis_graph* g, hipStream_t s) {
     constexpr int kTshift = T == 16 ? 4 : 5;
     const int64_t n = g->n, nnz = g->nnz, nI = g->nI;
     TC_HIP(hipMemsetAsync(g->meta, 0, sizeof(Meta), s));
-    // 1. new row pointer and the new row of every new-order entry
+    // 1. new row pointer
     LAUNCH(k_new_degrees, n, g->row_ptr, g->order, n, g->ndeg);
     TC_CHECK(scan_excl_i32(g->ndeg, g->ndeg, n, g->ndeg + n, (int32_t*)g->scan_tmp, s));
-    if (nnz > 0) TC_HIP(hipMemsetAsync(g->rowof, 0xFF, (size_t)nnz * 4, s));
-    LAUNCH(k_mark_rows, n, g->row_ptr, g->order, g->ndeg, n, g->rowof, g->rbase);
-    TC_CHECK(scan_incl_max_i32(g->rowof, g->rowof, nnz, (int32_t*)g->scan_tmp, s));
-    // 2. entries in new-row order
+    // 2. entries in new-row order, one lane per entry
     const int mode = !g->orient ? 0 : (g->reorder == MIS_REORDER_KEY ? 1 : 2);
-    if (mode == 0) LAUNCH((k_entries<kTshift, 0>), nnz, g->col_idx, g->rowof, g->rbase, g->order, g->new_id, g->key, nnz, g->ent);
-    if (mode == 1) LAUNCH((k_entries<kTshift, 1>), nnz, g->col_idx, g->rowof, g->rbase, g->order, g->new_id, g->key, nnz, g->ent);
-    if (mode == 2) LAUNCH((k_entries<kTshift, 2>), nnz, g->col_idx, g->rowof, g->rbase, g->order, g->new_id, g->key, nnz, g->ent);
-    // 3. stable sort on the row-block of the transposed entry
+    const int64_t eblocks = ceil_div(nnz, kEntBlock);
+    if (nnz > 0) {
+        LAUNCH(k_block_rows, eblocks + 1, g->ndeg, n, nnz, eblocks, g->brow);
+        const dim3 grid((unsigned)eblocks), blk(kBlock);
+        if (mode == 0)
+            hipLaunchKernelGGL((k_entries<kTshift, 0>), grid, blk, 0, s, g->row_ptr, g->col_idx, g->order, g->ndeg,
+                               g->brow, g->new_id, g->key, nnz, g->ent, g->ecnt);
+        if (mode == 1)
+            hipLaunchKernelGGL((k_entries<kTshift, 1>), grid, blk, 0, s, g->row_ptr, g->col_idx, g->order, g->ndeg,
+                               g->brow, g->new_id, g->key, nnz, g->ent, g->ecnt);
+        if (mode == 2)
+            hipLaunchKernelGGL((k_entries<kTshift, 2>), grid, blk, 0, s, g->row_ptr, g->col_idx, g->order, g->ndeg,
+                               g->brow, g->new_id, g->key, nnz, g->ent, g->ecnt);
+        TC_HIP(hipGetLastError());
+        // number of kept entries
+        TC_CHECK(scan_excl_i32(g->ecnt, g->hsums, eblocks, &g->meta->nvalid, (int32_t*)g->scan_tmp, s));
+    }
+    // 3. stable sort of the kept entries on the row-block of the transposed entry
     bool alt = false;
-    TC_CHECK(radix_sort_u64(g->ent, g->ent2, nullptr, nullptr, nnz, 36, 36 + bits_for(nI), g->sort_tmp, &alt, s));
+    if (nnz > 0)
+        TC_CHECK(radix_sort_u64(g->ent, g->ent2, nullptr, nullptr, nnz, g->ecnt, 36, 36 + bits_for(std::max<int64_t>(nI - 1, 1)),
+                                g->sort_tmp, &alt, s));
     const uint64_t* sorted = alt ? g->ent2 : g->ent;
-    // 4. tiles
-    LAUNCH((k_tile_flags<kTshift>), nnz, sorted, nnz, g->tflag, g->meta);
-    TC_CHECK(scan_excl_i32(g->tflag, g->tflag, nnz, &g->meta->ntiles, (int32_t*)g->scan_tmp, s));
-    LAUNCH((k_tile_heads<kTshift>), nnz, sorted, nnz, g->tflag, g->tile_start, g->tile_col, g->tile_row);
+    // 4. tiles: count heads per chunk, scan, write tile heads; then the bitmaps
+    const int64_t nchunks = ceil_div(nnz, kHeadChunk);
+    if (nchunks > 0) {
+        hipLaunchKernelGGL((k_head_count<kTshift>), dim3((unsigned)nchunks), dim3(kBlock), 0, s, sorted, g->meta,
+                           g->hsums);
+        TC_HIP(hipGetLastError());
+        TC_CHECK(scan_excl_i32(g->hsums, g->hsums, nchunks, &g->meta->ntiles, (int32_t*)g->scan_tmp, s));
+        hipLaunchKernelGGL((k_head_write<kTshift>), dim3((unsigned)nchunks), dim3(kBlock), 0, s, sorted, g->meta,
+                           g->hsums, g->tile_start, g->tile_col, g->tile_row);
+        TC_HIP(hipGetLastError());
+    }
     constexpr int L = T == 16 ? 1 : 4;
     LAUNCH((k_tile_bits<T>), g->tile_cap * L, sorted, g->tile_start, g->meta, g->tile_cap, g->tile_bits);
     LAUNCH(k_rb_ptr, nI + 1, g->tile_row, g->meta, nI, g->rb_ptr);

@@ -106,6 +106,7 @@ void configure(mis_graph* g, const mis_csr* csr, const mis_build_opts& o) {
     g->reorder = o.reorder;
     g->orient = o.orient;
     g->poll_rounds = o.poll_rounds;
+    g->user_keys = o.keys != nullptr;
 }
 
 int enqueue_phase(mis_graph* g, int phase, int r, hipStream_t s) {

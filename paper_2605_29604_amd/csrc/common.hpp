@@ -58,10 +58,13 @@ int scan_incl_max_i32(const int32_t* in, int32_t* out, int64_t count, int32_t* s
 
 // Stable LSD radix sort of 64-bit keys on bits [lo_bit, hi_bit), optional uint32
 // payload; `keys_alt`/`vals_alt` are same-sized scratch and `scratch` holds
-// sort_scratch_bytes(count) bytes.  *result_in_alt tells which buffer holds the
+// sort_scratch_bytes(count) bytes.  With `counts` (DEVICE, one per 4096-key block)
+// block b of the input holds only its first counts[b] keys and the output is the
+// dense sorted sequence of those keys.  *result_in_alt tells which buffer holds the
 // sorted data.  count < 2^31.
+constexpr int kSortTileKeys = 4096;
 size_t sort_scratch_bytes(int64_t count);
 int radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, int64_t count,
-                   int lo_bit, int hi_bit, void* scratch, bool* result_in_alt, hipStream_t s);
+                   const int32_t* counts, int lo_bit, int hi_bit, void* scratch, bool* result_in_alt, hipStream_t s);
 
 }  // namespace tcmis

@@ -59,6 +59,7 @@ struct mis_graph {
     // chosen configuration
     int path = MIS_PATH_CSR, tile = 0, reorder = MIS_REORDER_NONE, orient = 0;
     int poll_rounds = 4;
+    bool user_keys = false;           // priorities supplied by the caller
     int grid_blocks = 2048;           // persistent grid of the round kernels
 
     // workspace (caller-owned device memory)
@@ -92,11 +93,11 @@ struct mis_graph {
     uint32_t* pl = nullptr;           // [n] x2 order sort payload
     uint32_t* pl2 = nullptr;
     int32_t* ndeg = nullptr;          // [n+1] degrees in new order -> new row pointer
-    int64_t* rbase = nullptr;         // [n] old entry offset of each new row minus its new offset
-    int32_t* rowof = nullptr;         // [nnz] new row of each new-order entry
+    int32_t* brow = nullptr;          // [nnz/2048+2] first new row of each entry workgroup
     uint64_t* ent = nullptr;          // [nnz] x2 tile entries
     uint64_t* ent2 = nullptr;
-    int32_t* tflag = nullptr;         // [nnz] tile-start flags -> tile index
+    int32_t* hsums = nullptr;         // [nnz/2048+2] tile heads per chunk -> first tile of the chunk
+    int32_t* ecnt = nullptr;          // [nnz/4096+1] kept entries per entry workgroup
     int64_t* rb_ptr = nullptr;        // [nI+1] tile range of each row-block
     int32_t* tile_col = nullptr;      // [tile_cap] column block J
     int32_t* tile_row = nullptr;      // [tile_cap] row block I

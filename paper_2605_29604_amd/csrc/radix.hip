@@ -9,6 +9,8 @@
 // the scatter ranks equal digits inside a wavefront with eight ballots and across
 // the block's wavefronts and iterations through LDS counters, which keeps every
 // pass stable.
+#include <utility>
+
 #include "common.hpp"
 
 namespace tcmis {
@@ -19,7 +21,6 @@ constexpr int kScanItems = 8;
 constexpr int kScanTile = kBlock * kScanItems;   // 2048
 constexpr int kSortIters = 16;
 constexpr int kSortTile = kBlock * kSortIters;   // 4096 keys per block
-constexpr int kDigits = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 
 struct OpAdd {
@@ -123,40 +124,69 @@ int scan_impl(const T* in, T* out, int64_t count, T* d_total, T* scratch, hipStr
 }
 
 // ---- radix sort kernels ----
-__global__ void __launch_bounds__(kBlock) k_radix_hist(const uint64_t* keys, int64_t count, int shift,
-                                                       int64_t nblocks, int32_t* hist) {
-    __shared__ int cnt[kDigits];
-    cnt[threadIdx.x] = 0;
-    __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
-    for (int it = 0; it < kSortIters; ++it) {
-        const int64_t idx = base + (int64_t)it * kBlock + threadIdx.x;
-        if (idx < count) atomicAdd(&cnt[(keys[idx] >> shift) & 0xff], 1);
-    }
-    __syncthreads();
-    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+// Keys are processed in blocks of kSortTile; block b holds keys
+// [b*kSortTile, b*kSortTile + len_b) with len_b = counts[b] when per-block counts are
+// given (compacted producer output), else kSortTile (the last block: the rest).
+// (with `dense_total`, a pass after a compacted first pass: the keys are dense and
+// their number is on the device)
+__device__ inline int block_len(const int32_t* counts, const int32_t* dense_total, int64_t count, int64_t b) {
+    if (counts) return counts[b];
+    const int64_t c = dense_total ? (int64_t)*dense_total : count;
+    const int64_t rest = c - b * kSortTile;
+    return (int)(rest < 0 ? 0 : (rest < kSortTile ? rest : kSortTile));
 }
 
-template <bool kVals>
-__global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint64_t* keys, uint64_t* keys_out,
-                                                          const uint32_t* vals, uint32_t* vals_out, int64_t count,
-                                                          int shift, int64_t nblocks, const int32_t* offsets) {
-    __shared__ int32_t base_of[kDigits];
-    __shared__ int32_t wave_cnt[kWavesPerBlock][kDigits];
-    const int t = threadIdx.x, lane = lane_id(), wid = t / kWave;
-    base_of[t] = offsets[(int64_t)t * nblocks + blockIdx.x];
-    for (int w = 0; w < kWavesPerBlock; ++w) wave_cnt[w][t] = 0;
+// Digit histogram of one block; per-wave LDS counters.
+template <int DB>
+__global__ void __launch_bounds__(kBlock) k_radix_hist(const uint64_t* keys, int64_t count, const int32_t* counts,
+                                                       const int32_t* dense_total, int shift, int64_t nblocks,
+                                                       int32_t* hist) {
+    constexpr int D = 1 << DB;
+    __shared__ int cnt[kWavesPerBlock][D];
+    const int wid = threadIdx.x / kWave;
+    for (int i = threadIdx.x; i < kWavesPerBlock * D; i += kBlock) (&cnt[0][0])[i] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
-    for (int it = 0; it < kSortIters; ++it) {
-        const int64_t idx = base + (int64_t)it * kBlock + t;
-        const bool valid = idx < count;
-        const uint64_t k = valid ? keys[idx] : 0;
-        const uint32_t val = (kVals && valid) ? vals[idx] : 0;
-        const int d = (int)((k >> shift) & 0xff);
+    const int len = block_len(counts, dense_total, count, blockIdx.x);
+    for (int i = threadIdx.x; i < len; i += kBlock)
+        atomicAdd(&cnt[wid][(keys[base + i] >> shift) & (D - 1)], 1);
+    __syncthreads();
+    for (int d = threadIdx.x; d < D; d += kBlock) {
+        int tot = 0;
+        for (int w = 0; w < kWavesPerBlock; ++w) tot += cnt[w][d];
+        hist[(int64_t)d * nblocks + blockIdx.x] = tot;
+    }
+}
+
+// Stable scatter of one block: every key gets its rank among equal digits of the
+// block (DB ballots inside a wavefront, LDS counters across wavefronts and
+// iterations) and is written straight to its global position.
+template <int DB, bool kVals>
+__global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint64_t* keys, uint64_t* keys_out,
+                                                          const uint32_t* vals, uint32_t* vals_out, int64_t count,
+                                                          const int32_t* counts, const int32_t* dense_total, int shift,
+                                                          int64_t nblocks, const int32_t* offsets) {
+    constexpr int D = 1 << DB;
+    __shared__ int32_t base_of[D];
+    __shared__ int32_t wave_cnt[kWavesPerBlock][D];
+    const int t = threadIdx.x, lane = lane_id(), wid = t / kWave;
+    for (int d = t; d < D; d += kBlock) {
+        base_of[d] = offsets[(int64_t)d * nblocks + blockIdx.x];
+        for (int w = 0; w < kWavesPerBlock; ++w) wave_cnt[w][d] = 0;
+    }
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    const int len = block_len(counts, dense_total, count, blockIdx.x);
+    const int iters = (len + kBlock - 1) / kBlock;
+    for (int it = 0; it < iters; ++it) {
+        const int i = it * kBlock + t;
+        const bool valid = i < len;
+        const uint64_t k = valid ? keys[base + i] : 0;
+        const uint32_t val = (kVals && valid) ? vals[base + i] : 0;
+        const int d = (int)((k >> shift) & (D - 1));
         uint64_t match = ballot(valid);
         #pragma unroll
-        for (int b = 0; b < 8; ++b) {
+        for (int b = 0; b < DB; ++b) {
             const bool bit = (d >> b) & 1;
             const uint64_t bb = ballot(bit);
             match &= bit ? bb : ~bb;
@@ -172,14 +202,43 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint64_t* keys, 
             if (kVals) vals_out[dst] = val;
         }
         __syncthreads();
-        int add = 0;
-        for (int w = 0; w < kWavesPerBlock; ++w) {
-            add += wave_cnt[w][t];
-            wave_cnt[w][t] = 0;
+        for (int dd = t; dd < D; dd += kBlock) {
+            int add = 0;
+            for (int w = 0; w < kWavesPerBlock; ++w) {
+                add += wave_cnt[w][dd];
+                wave_cnt[w][dd] = 0;
+            }
+            base_of[dd] += add;
         }
-        base_of[t] += add;
         __syncthreads();
     }
+}
+
+template <int DB>
+int sort_passes(uint64_t** src, uint64_t** dst, uint32_t** vsrc, uint32_t** vdst, int64_t count,
+                const int32_t* counts, int lo_bit, int hi_bit, int32_t* hist, int32_t* total, int32_t* scan_tmp,
+                bool* alt, hipStream_t s) {
+    const int64_t nb = ceil_div(count, kSortTile);
+    const int32_t* dense = nullptr;
+    for (int shift = lo_bit; shift < hi_bit; shift += DB) {
+        hipLaunchKernelGGL((k_radix_hist<DB>), dim3((unsigned)nb), dim3(kBlock), 0, s, *src, count, counts, dense, shift,
+                           nb, hist);
+        TC_HIP(hipGetLastError());
+        TC_CHECK(scan_excl_i32(hist, hist, nb * (1 << DB), counts ? total : nullptr, scan_tmp, s));
+        if (*vsrc)
+            hipLaunchKernelGGL((k_radix_scatter<DB, true>), dim3((unsigned)nb), dim3(kBlock), 0, s, *src, *dst, *vsrc,
+                               *vdst, count, counts, dense, shift, nb, hist);
+        else
+            hipLaunchKernelGGL((k_radix_scatter<DB, false>), dim3((unsigned)nb), dim3(kBlock), 0, s, *src, *dst,
+                               (const uint32_t*)nullptr, (uint32_t*)nullptr, count, counts, dense, shift, nb, hist);
+        TC_HIP(hipGetLastError());
+        std::swap(*src, *dst);
+        std::swap(*vsrc, *vdst);
+        *alt = !*alt;
+        if (counts) dense = total;   // after a compacted first pass the keys are dense
+        counts = nullptr;
+    }
+    return MIS_OK;
 }
 
 }  // namespace
@@ -205,39 +264,36 @@ int scan_incl_max_i32(const int32_t* in, int32_t* out, int64_t count, int32_t* s
 
 size_t sort_scratch_bytes(int64_t count) {
     const int64_t nb = ceil_div(count > 0 ? count : 1, kSortTile);
-    const int64_t h = nb * kDigits;
-    return (size_t)(h + scan_scratch_elems(h)) * sizeof(int32_t);
+    const int64_t h = nb * 1024;   // up to 10-bit digits
+    return (size_t)(h + 64 + scan_scratch_elems(h)) * sizeof(int32_t);
 }
 
 int radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, int64_t count,
-                   int lo_bit, int hi_bit, void* scratch, bool* result_in_alt, hipStream_t s) {
+                   const int32_t* counts, int lo_bit, int hi_bit, void* scratch, bool* result_in_alt, hipStream_t s) {
     *result_in_alt = false;
-    if (count <= 1 || hi_bit <= lo_bit) return MIS_OK;
+    if (count <= 1 && !counts) return MIS_OK;
+    if (hi_bit <= lo_bit) return MIS_OK;
     if (count >= (1ll << 31)) {
         set_error("radix sort is limited to 2^31 keys");
         return MIS_EINVAL;
     }
     const int64_t nb = ceil_div(count, kSortTile);
     int32_t* hist = (int32_t*)scratch;
-    int32_t* scan_tmp = hist + nb * kDigits;
+    int32_t* total = hist + nb * 1024;
+    int32_t* scan_tmp = total + 64;
     uint64_t *src = keys, *dst = keys_alt;
     uint32_t *vsrc = vals, *vdst = vals_alt;
-    for (int shift = lo_bit; shift < hi_bit; shift += 8) {
-        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kBlock), 0, s, src, count, shift, nb, hist);
-        TC_HIP(hipGetLastError());
-        TC_CHECK(scan_excl_i32(hist, hist, nb * kDigits, nullptr, scan_tmp, s));
-        if (vals)
-            hipLaunchKernelGGL(k_radix_scatter<true>, dim3((unsigned)nb), dim3(kBlock), 0, s, src, dst, vsrc, vdst, count,
-                               shift, nb, hist);
-        else
-            hipLaunchKernelGGL(k_radix_scatter<false>, dim3((unsigned)nb), dim3(kBlock), 0, s, src, dst,
-                               (const uint32_t*)nullptr, (uint32_t*)nullptr, count, shift, nb, hist);
-        TC_HIP(hipGetLastError());
-        uint64_t* t = src; src = dst; dst = t;
-        uint32_t* tv = vsrc; vsrc = vdst; vdst = tv;
-        *result_in_alt = !*result_in_alt;
+    // 8-bit digits, or 9/10-bit digits when that saves a pass
+    const int bits = hi_bit - lo_bit;
+    if (bits > 8 && ceil_div(bits, 10) < ceil_div(bits, 8)) {
+        if (ceil_div(bits, 9) == ceil_div(bits, 10))
+            return sort_passes<9>(&src, &dst, &vsrc, &vdst, count, counts, lo_bit, hi_bit, hist, total,
+                                  scan_tmp, result_in_alt, s);
+        return sort_passes<10>(&src, &dst, &vsrc, &vdst, count, counts, lo_bit, hi_bit, hist, total, scan_tmp,
+                               result_in_alt, s);
     }
-    return MIS_OK;
+    return sort_passes<8>(&src, &dst, &vsrc, &vdst, count, counts, lo_bit, hi_bit, hist, total, scan_tmp,
+                          result_in_alt, s);
 }
 
 }  // namespace tcmis
