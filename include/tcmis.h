@@ -46,7 +46,7 @@ typedef enum {
 
 /* Path through the round kernels. */
 enum {
-    MIS_PATH_AUTO = 0,    /* autotuner picks (tile for dense tiles, else CSR) */
+    MIS_PATH_AUTO = 0,    /* tile path, T = 16, key order (mis_autotune picks per graph) */
     MIS_PATH_TILE = 1,    /* T x T bit tiles: LDS-staged candidate phase + int8 MFMA exclusion */
     MIS_PATH_CSR = 2      /* scalar CSR path (the plain GPU method) */
 };
@@ -58,6 +58,13 @@ enum {
     MIS_REORDER_DEGREE = 2,  /* decreasing degree class floor(255 / (1 + deg)), ties by id */
     MIS_REORDER_KEY = 3,     /* decreasing priority key: tile column < row <=> higher key */
     MIS_REORDER_RCM = 4      /* reverse Cuthill-McKee (host), banded meshes */
+};
+
+/* How the rounds are launched (results are identical). */
+enum {
+    MIS_LAUNCH_AUTO = 0,      /* hipGraph when capture works, else direct */
+    MIS_LAUNCH_DIRECT = 1,    /* two kernel launches per round, enqueued back to back */
+    MIS_LAUNCH_GRAPH = 2      /* poll_rounds rounds captured once as a hipGraph and replayed */
 };
 
 /* Input graph: undirected, simple, symmetric CSR, rows sorted ascending. */
@@ -77,6 +84,9 @@ typedef struct {
                                  higher-priority neighbours (candidate phase needs no keys) */
     int32_t validate;         /* 1 = check symmetry/loops/duplicates/range on the device */
     int32_t poll_rounds;      /* rounds enqueued between termination polls (0 = default 4) */
+    int32_t launch;           /* MIS_LAUNCH_* */
+    int32_t blocks_per_cu;    /* workgroups per compute unit of the persistent round kernels
+                                 (0 = default 8, at most 32) */
     uint64_t seed;            /* priority seed (default key rule) */
     const uint64_t* keys;     /* optional DEVICE uint64[n], pairwise distinct priorities
                                  (higher wins); NULL = default key rule, needs n <= 2^24 */
@@ -109,11 +119,13 @@ typedef struct {
     float kernel_ms[2];       /* timing = 1: total ms of the candidate / exclusion kernels */
     int32_t launches;         /* timing = 1: rounds enqueued (each launches both kernels) */
     int32_t trace_cap;        /* in: rounds the trace buffer holds (0 = no trace) */
+    int32_t graph;            /* 1 if full batches of rounds ran as a replayed hipGraph */
+    int32_t pad3_;
     int64_t* trace;           /* in: optional HOST int64[3*trace_cap]; out: per round |C_r|,
                                  vertices removed as neighbours of candidates, alive after */
 } mis_stats;
 
-typedef struct mis_graph mis_graph;   /* opaque; owns its device memory */
+typedef struct mis_graph mis_graph;   /* opaque host handle; device memory is the caller's workspace */
 
 /*
  * Device workspace bytes that mis_build_tiles needs for this graph and these
@@ -160,15 +172,53 @@ int mis_graph_bytes(const mis_graph* g, size_t* bytes);
 int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, mis_stats* stats, void* stream);
 
 /*
- * Solves `count` independent graphs together (block-diagonal packing of their
- * row-block lists; every round kernel covers all graphs of the batch).  The
- * result for each graph is identical to mis_solve on it alone.
- *   graphs  : HOST array of `count` handles built with the same path and tile size.
- *   in_sets : HOST array of `count` DEVICE uint8 outputs.
- *   stats   : optional HOST array of `count` entries.
+ * Batches: `count` independent graphs solved together as one block-diagonal graph.
+ *   csr     : the disjoint union of the graphs (DEVICE arrays): graph g owns vertices
+ *             offsets[g] .. offsets[g+1]-1 and has no edge to another graph.
+ *   offsets : HOST int64[count+1], offsets[0] = 0, offsets[count] = csr->n.
+ * Priorities use graph-local ids (vertex v of graph g gets the key of vertex
+ * v - offsets[g] in g alone), so graph g's result is identical to solving it alone,
+ * and so is its number of rounds.  Every round kernel covers all graphs of the batch
+ * in one launch.  With validate = 1 an edge between two graphs is rejected
+ * (MIS_EINVAL).  Workspace, streams and errors as for mis_build_tiles.
  */
-int mis_solve_batch(mis_graph* const* graphs, int32_t count, uint8_t* const* in_sets,
-                    mis_stats* stats, void* stream);
+int mis_build_batch_bytes(const mis_csr* csr, int32_t count, const int64_t* offsets, const mis_build_opts* opts,
+                          size_t* bytes);
+int mis_build_batch(const mis_csr* csr, int32_t count, const int64_t* offsets, const mis_build_opts* opts,
+                    void* workspace, size_t workspace_bytes, void* stream, mis_graph** out);
+
+/*
+ * Solves a batch built with mis_build_batch.  in_set: DEVICE uint8[csr->n] (graph g's
+ * answer is in_set[offsets[g] .. offsets[g+1]-1]).  stats: optional HOST, for the
+ * whole batch (rounds = the largest per-graph round count).  graph_rounds (HOST
+ * int32[count]) and graph_in (HOST int64[count]), optional: each graph's own number
+ * of rounds and set size.  Synchronises `stream`.
+ */
+int mis_solve_batch(mis_graph* batch, uint8_t* in_set, mis_stats* stats, int32_t* graph_rounds, int64_t* graph_in,
+                    void* stream);
+
+/*
+ * Autotuning of implementation choices that leave the result unchanged (tile size,
+ * vertex order, CSR-vs-tile path, grid size of the round kernels).  Measures the
+ * degree profile of the graph (or batch: count/offsets as for mis_build_batch,
+ * count = 0 for one graph) on the device, rounds it to a bucket, and on the first
+ * graph of a bucket builds and solves every candidate -- path CSR or tiles, tile 16
+ * or 32, key-sorted or input order, 4/8/16 workgroups per CU -- twice in the
+ * workspace, timing the second run of build + solve with HIP events.  The fastest
+ * candidate is cached per bucket (process-wide, thread-safe) and written to *out as
+ * complete build options (base's seed, keys, validate, poll_rounds and launch are
+ * kept).  A nonzero path, tile or blocks_per_cu in `base` fixes that choice.
+ *   workspace : DEVICE, 256-byte aligned, at least mis_autotune_bytes bytes; its
+ *               contents are scratch.  from_cache (HOST, optional): 1 if no trial ran.
+ * Synchronises `stream`.  Every candidate computes the same set; only time differs.
+ * Errors: MIS_EINVAL, MIS_EHIP, MIS_EINTERNAL (no candidate could run).
+ */
+int mis_autotune_bytes(const mis_csr* csr, int32_t count, const int64_t* offsets, const mis_build_opts* base,
+                       size_t* bytes);
+int mis_autotune(const mis_csr* csr, int32_t count, const int64_t* offsets, const mis_build_opts* base,
+                 void* workspace, size_t workspace_bytes, void* stream, mis_build_opts* out, int32_t* from_cache);
+/* Forgets every tuned bucket. */
+void mis_autotune_clear(void);
 
 /* Releases the handle (host memory only; the workspace stays the caller's). */
 void mis_free_tiles(mis_graph* g);

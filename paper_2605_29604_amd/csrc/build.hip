@@ -26,7 +26,7 @@ namespace tcmis {
 
 namespace {
 
-enum : uint32_t { kErrRange = 1, kErrLoop = 2, kErrDup = 4, kErrAsym = 8, kErrTie = 16 };
+enum : uint32_t { kErrRange = 1, kErrLoop = 2, kErrDup = 4, kErrAsym = 8, kErrTie = 16, kErrCross = 32 };
 
 #define GRID_STRIDE(i, count) \
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (count); i += (int64_t)gridDim.x * blockDim.x)
@@ -48,6 +48,16 @@ __device__ inline int64_t row_of(const int64_t* rp, int64_t n, int64_t e) {
     return lo;
 }
 
+// graph of input vertex v in a batch: largest g with goff[g] <= v
+__device__ inline int64_t graph_of(const int64_t* goff, int64_t count, int64_t v) {
+    int64_t lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (goff[mid] <= v) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 __global__ void k_validate_rows(const int64_t* rp, int64_t n, int64_t nnz, uint32_t* err) {
     GRID_STRIDE(v, n) {
         const int64_t a = rp[v], b = rp[v + 1];
@@ -56,7 +66,7 @@ __global__ void k_validate_rows(const int64_t* rp, int64_t n, int64_t nnz, uint3
 }
 
 __global__ void k_validate_edges(const int64_t* rp, const int32_t* ci, int64_t n, int64_t nnz, const uint64_t* key,
-                                 uint32_t* err) {
+                                 const int64_t* goff, int64_t count, uint32_t* err) {
     GRID_STRIDE(e, nnz) {
         const int64_t v = row_of(rp, n, e);
         const int64_t u = ci[e];
@@ -70,18 +80,21 @@ __global__ void k_validate_edges(const int64_t* rp, const int32_t* ci, int64_t n
         }
         if (lo >= rp[u + 1] || (int64_t)ci[lo] != v) atomicOr(err, kErrAsym);
         if (key && key[u] == key[v]) atomicOr(err, kErrTie);
+        if (goff && graph_of(goff, count, u) != graph_of(goff, count, v)) atomicOr(err, kErrCross);
     }
 }
 
 // Default priority key (Eq. 1, discretised): q(deg) << 56 | hash << 24 | v with
 // q(d) = floor(255 / (1 + d)) (lower degree wins) and hash = top 32 bits of output
 // v+1 of the SplitMix64 stream seeded with `seed` (the random perturbation).
-__global__ void k_keys(const int64_t* rp, int64_t n, uint64_t seed, uint64_t* key) {
+// In a batch the id in the key is graph-local (v - goff[g]).
+__global__ void k_keys(const int64_t* rp, int64_t n, uint64_t seed, const int64_t* goff, int64_t count, uint64_t* key) {
     GRID_STRIDE(v, n) {
         const int64_t deg = rp[v + 1] - rp[v];
         const uint64_t q = (uint64_t)(255 / (1 + deg));
-        const uint64_t h = splitmix_at(seed, (uint64_t)v + 1) >> 32;
-        key[v] = (q << 56) | (h << 24) | (uint64_t)v;
+        const int64_t lv = goff ? v - goff[graph_of(goff, count, v)] : v;
+        const uint64_t h = splitmix_at(seed, (uint64_t)lv + 1) >> 32;
+        key[v] = (q << 56) | (h << 24) | (uint64_t)lv;
     }
 }
 
@@ -402,6 +415,11 @@ size_t layout(mis_graph* g, char* base) {
     take(&g->meta, sizeof(Meta));
     take(&g->trace, sizeof(TraceRec) * kTraceCap);
     take(&g->key, (size_t)n * 8);
+    if (g->count > 0) {
+        take(&g->goff, (size_t)(g->count + 1) * 8);
+        take(&g->g_rounds, (size_t)g->count * 4);
+        take(&g->g_in, (size_t)g->count * 8);
+    }
     take(&g->scan_tmp, (size_t)scan_scratch_elems(std::max(n, nnz) + 1) * 8);
     if (g->path == MIS_PATH_CSR) {
         take(&g->light, (size_t)n * 4);
@@ -450,12 +468,14 @@ size_t layout(mis_graph* g, char* base) {
     take(&g->alive0, (size_t)nI * 4);
     take(&g->alive, (size_t)nI * 4);
     take(&g->inmask, (size_t)nI * 4);
+    take(&g->dround, (size_t)nI * T * 4);
     take(&g->cand, (size_t)nI * 8);
     take(&g->part, (size_t)nI * 2 * 8);
     return off;
 }
 
-int validate_graph(const mis_csr* csr, const uint64_t* user_keys, uint32_t* d_err, hipStream_t s) {
+int validate_graph(const mis_csr* csr, const uint64_t* user_keys, const int64_t* goff, int64_t count, uint32_t* d_err,
+                   hipStream_t s) {
     TC_HIP(hipMemsetAsync(d_err, 0, 4, s));
     int64_t ends[2] = {0, 0};
     TC_HIP(hipMemcpyAsync(&ends[0], csr->row_ptr, 8, hipMemcpyDeviceToHost, s));
@@ -470,7 +490,7 @@ int validate_graph(const mis_csr* csr, const uint64_t* user_keys, uint32_t* d_er
     TC_HIP(hipMemcpyAsync(&h, d_err, 4, hipMemcpyDeviceToHost, s));
     TC_HIP(hipStreamSynchronize(s));
     if (h) { set_error("row_ptr is not monotone within [0, nnz]"); return MIS_ERANGE; }
-    LAUNCH(k_validate_edges, csr->nnz, csr->row_ptr, csr->col_idx, csr->n, csr->nnz, user_keys, d_err);
+    LAUNCH(k_validate_edges, csr->nnz, csr->row_ptr, csr->col_idx, csr->n, csr->nnz, user_keys, goff, count, d_err);
     TC_HIP(hipMemcpyAsync(&h, d_err, 4, hipMemcpyDeviceToHost, s));
     TC_HIP(hipStreamSynchronize(s));
     if (h & kErrRange) { set_error("column index out of range"); return MIS_ERANGE; }
@@ -478,6 +498,7 @@ int validate_graph(const mis_csr* csr, const uint64_t* user_keys, uint32_t* d_er
     if (h & kErrDup) { set_error("duplicate or unsorted adjacency entries"); return MIS_EDUP; }
     if (h & kErrAsym) { set_error("adjacency is not symmetric"); return MIS_ENOTSYM; }
     if (h & kErrTie) { set_error("two adjacent vertices have equal keys"); return MIS_EINVAL; }
+    if (h & kErrCross) { set_error("an edge joins two graphs of the batch"); return MIS_EINVAL; }
     return MIS_OK;
 }
 
@@ -486,7 +507,7 @@ int build_keys(mis_graph* g, const mis_build_opts* o, hipStream_t s) {
     if (o->keys) {
         TC_HIP(hipMemcpyAsync(g->key, o->keys, (size_t)g->n * 8, hipMemcpyDeviceToDevice, s));
     } else {
-        LAUNCH(k_keys, g->n, g->row_ptr, g->n, o->seed, g->key);
+        LAUNCH(k_keys, g->n, g->row_ptr, g->n, o->seed, g->goff, (int64_t)g->count, g->key);
     }
     return MIS_OK;
 }

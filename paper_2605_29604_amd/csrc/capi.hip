@@ -9,7 +9,8 @@
 
 namespace tcmis {
 
-int validate_graph(const mis_csr* csr, const uint64_t* user_keys, uint32_t* d_err, hipStream_t s);
+int validate_graph(const mis_csr* csr, const uint64_t* user_keys, const int64_t* goff, int64_t count,
+                   uint32_t* d_err, hipStream_t s);
 int build_keys(mis_graph* g, const mis_build_opts* o, hipStream_t s);
 int build_csr_lists(mis_graph* g, hipStream_t s);
 int build_order(mis_graph* g, hipStream_t s);
@@ -69,7 +70,8 @@ __global__ void k_ctrl_init(Ctrl* ctrl, int64_t n) {
 }
 
 // Checks arguments and resolves automatic options (host-only).
-int resolve(const mis_csr* csr, const mis_build_opts* opts, mis_build_opts* o) {
+int resolve(const mis_csr* csr, const mis_build_opts* opts, mis_build_opts* o, int32_t count = 0,
+            const int64_t* offsets = nullptr) {
     if (!csr) return fail(MIS_EINVAL, "csr is null");
     if (csr->n < 0 || csr->n >= (1ll << 31)) return fail(MIS_EINVAL, "n must be in [0, 2^31)");
     if (csr->nnz < 0 || csr->nnz >= (1ll << 31)) return fail(MIS_EINVAL, "nnz must be in [0, 2^31)");
@@ -81,7 +83,20 @@ int resolve(const mis_csr* csr, const mis_build_opts* opts, mis_build_opts* o) {
     if (o->reorder < MIS_REORDER_AUTO || o->reorder > MIS_REORDER_RCM) return fail(MIS_EINVAL, "bad reorder");
     if (o->orient < -1 || o->orient > 1) return fail(MIS_EINVAL, "orient must be -1, 0 or 1");
     if (o->poll_rounds < 0 || o->poll_rounds > kTraceCap) return fail(MIS_EINVAL, "poll_rounds out of range");
-    if (!o->keys && csr->n > (1ll << 24)) return fail(MIS_EINVAL, "the default key rule needs n <= 2^24; pass keys");
+    if (o->launch < MIS_LAUNCH_AUTO || o->launch > MIS_LAUNCH_GRAPH) return fail(MIS_EINVAL, "bad launch mode");
+    if (o->blocks_per_cu < 0 || o->blocks_per_cu > 32) return fail(MIS_EINVAL, "blocks_per_cu must be in [0, 32]");
+    if (count < 0) return fail(MIS_EINVAL, "count must be >= 0");
+    if (count > 0) {
+        if (!offsets) return fail(MIS_EINVAL, "offsets is null");
+        if (offsets[0] != 0 || offsets[count] != csr->n) return fail(MIS_EINVAL, "offsets must run from 0 to n");
+        for (int32_t i = 0; i < count; ++i) {
+            if (offsets[i + 1] < offsets[i]) return fail(MIS_EINVAL, "offsets must not decrease");
+            if (!o->keys && offsets[i + 1] - offsets[i] > (1ll << 24))
+                return fail(MIS_EINVAL, "the default key rule needs graphs of at most 2^24 vertices; pass keys");
+        }
+    } else if (!o->keys && csr->n > (1ll << 24)) {
+        return fail(MIS_EINVAL, "the default key rule needs n <= 2^24; pass keys");
+    }
     if (o->path == MIS_PATH_AUTO) o->path = MIS_PATH_TILE;
     if (o->path == MIS_PATH_TILE) {
         if (o->tile == 0) o->tile = 16;
@@ -106,6 +121,7 @@ void configure(mis_graph* g, const mis_csr* csr, const mis_build_opts& o) {
     g->reorder = o.reorder;
     g->orient = o.orient;
     g->poll_rounds = o.poll_rounds;
+    g->launch = o.launch;
     g->user_keys = o.keys != nullptr;
 }
 
@@ -113,8 +129,79 @@ int enqueue_phase(mis_graph* g, int phase, int r, hipStream_t s) {
     return g->path == MIS_PATH_TILE ? tile_enqueue_phase(g, phase, r, s) : csr_enqueue_phase(g, phase, r, s);
 }
 
-__global__ void k_close(Ctrl* ctrl, TraceRec* trace, int r) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) close_round(ctrl, trace, r);
+// per-graph rounds (largest decision round of its vertices) and set sizes; one
+// workgroup per graph of the batch
+__global__ void __launch_bounds__(kBlock) k_batch_stats(const int64_t* goff, const uint8_t* in_set,
+                                                        const int32_t* new_id, const int32_t* dround, const uint32_t* st,
+                                                        int32_t* g_rounds, int64_t* g_in) {
+    __shared__ int32_t smax[kBlock / kWave];
+    __shared__ int64_t ssum[kBlock / kWave];
+    const int64_t g = blockIdx.x;
+    int32_t mx = 0;
+    int64_t sum = 0;
+    for (int64_t v = goff[g] + threadIdx.x; v < goff[g + 1]; v += kBlock) {
+        const int32_t r = new_id ? dround[new_id[v]] : (int32_t)(st[v] >> 2);
+        mx = max(mx, r);
+        sum += in_set[v];
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        mx = max(mx, __shfl_xor(mx, off, kWave));
+        sum += __shfl_xor(sum, off, kWave);
+    }
+    if (lane_id() == 0) { smax[threadIdx.x / kWave] = mx; ssum[threadIdx.x / kWave] = sum; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / kWave; ++w) { mx = max(mx, smax[w]); sum += ssum[w]; }
+        g_rounds[g] = mx;
+        g_in[g] = sum;
+    }
+}
+
+// closes the last round of a batch of k rounds and moves the round base past it
+__global__ void k_close(Ctrl* ctrl, TraceRec* trace, int k) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        close_round(ctrl, trace, ctrl->rbase + k);
+        ctrl->rbase += k;
+    }
+}
+
+// enqueues a batch of k rounds (round indices 1..k after the device-side base) and
+// the close kernel
+int enqueue_batch(mis_graph* g, int64_t k, hipStream_t s, hipEvent_t* ev) {
+    for (int64_t i = 0; i < k; ++i) {
+        if (ev) (void)hipEventRecord(ev[3 * i], s);
+        TC_CHECK(enqueue_phase(g, 0, (int)(i + 1), s));
+        if (ev) (void)hipEventRecord(ev[3 * i + 1], s);
+        TC_CHECK(enqueue_phase(g, 1, (int)(i + 1), s));
+        if (ev) (void)hipEventRecord(ev[3 * i + 2], s);
+    }
+    hipLaunchKernelGGL(k_close, dim3(1), dim3(64), 0, s, g->ctrl, g->trace, (int)k);
+    TC_HIP(hipGetLastError());
+    return MIS_OK;
+}
+
+// captures a full batch (poll_rounds rounds) once, on a private stream
+bool ensure_graph(mis_graph* g) {
+    if (g->graph_exec) return true;
+    if (g->graph_failed) return false;
+    bool ok = hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking) == hipSuccess &&
+              hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+        const int rc = enqueue_batch(g, g->poll_rounds, g->cap_stream, nullptr);
+        hipGraph_t graph = nullptr;
+        ok = hipStreamEndCapture(g->cap_stream, &graph) == hipSuccess && rc == MIS_OK && graph;
+        if (ok) {
+            g->graph = graph;
+            ok = hipGraphInstantiate(&g->graph_exec, graph, nullptr, nullptr, 0) == hipSuccess;
+        } else if (graph) {
+            (void)hipGraphDestroy(graph);
+        }
+    }
+    if (!ok) {
+        (void)hipGetLastError();
+        g->graph_failed = true;
+    }
+    return ok;
 }
 
 // bytes the kernels must move per work unit (see TraceRec::u)
@@ -172,26 +259,38 @@ const char* mis_last_error(void) { return g_last_error.c_str(); }
 const char* mis_version(void) { return "tcmis-hip 0.1 gfx950"; }
 
 int mis_build_bytes(const mis_csr* csr, const mis_build_opts* opts, size_t* bytes) {
+    return mis_build_batch_bytes(csr, 0, nullptr, opts, bytes);
+}
+
+int mis_build_batch_bytes(const mis_csr* csr, int32_t count, const int64_t* offsets, const mis_build_opts* opts,
+                          size_t* bytes) {
     g_last_error.clear();
     if (!bytes) return fail(MIS_EINVAL, "bytes is null");
     mis_build_opts o;
-    TC_CHECK(resolve(csr, opts, &o));
+    TC_CHECK(resolve(csr, opts, &o, count, offsets));
     mis_graph g;
     configure(&g, csr, o);
+    g.count = count;
     *bytes = layout(&g, nullptr);
     return MIS_OK;
 }
 
 int mis_build_tiles(const mis_csr* csr, const mis_build_opts* opts, void* workspace, size_t workspace_bytes,
                     void* stream, mis_graph** out) {
+    return mis_build_batch(csr, 0, nullptr, opts, workspace, workspace_bytes, stream, out);
+}
+
+int mis_build_batch(const mis_csr* csr, int32_t count, const int64_t* offsets, const mis_build_opts* opts,
+                    void* workspace, size_t workspace_bytes, void* stream, mis_graph** out) {
     g_last_error.clear();
     if (!out) return fail(MIS_EINVAL, "out is null");
     *out = nullptr;
     mis_build_opts o;
-    TC_CHECK(resolve(csr, opts, &o));
+    TC_CHECK(resolve(csr, opts, &o, count, offsets));
     mis_graph* g = new (std::nothrow) mis_graph();
     if (!g) return fail(MIS_ENOMEM, "host allocation failed");
     configure(g, csr, o);
+    g->count = count;
     const size_t need = layout(g, nullptr);
     if (!workspace || workspace_bytes < need || ((uintptr_t)workspace & 255)) {
         delete g;
@@ -204,11 +303,13 @@ int mis_build_tiles(const mis_csr* csr, const mis_build_opts* opts, void* worksp
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) != hipSuccess) { delete g; return fail(MIS_EHIP, "hipGetDevice failed"); }
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    g->grid_blocks = std::max(1, cus) * 8;
+    g->grid_blocks = std::max(1, cus) * (o.blocks_per_cu ? o.blocks_per_cu : 8);
 
     hipStream_t s = (hipStream_t)stream;
     int rc = MIS_OK;
-    if (o.validate) rc = validate_graph(csr, o.keys, &g->ctrl->error, s);
+    if (count > 0 && hipMemcpyAsync(g->goff, offsets, (size_t)(count + 1) * 8, hipMemcpyHostToDevice, s) != hipSuccess)
+        rc = fail(MIS_EHIP, "copy of the batch offsets failed");
+    if (rc == MIS_OK && o.validate) rc = validate_graph(csr, o.keys, g->goff, count, &g->ctrl->error, s);
     if (rc == MIS_OK) rc = build_keys(g, &o, s);
     if (rc == MIS_OK) {
         if (g->path == MIS_PATH_CSR) rc = build_csr_lists(g, s);
@@ -260,16 +361,13 @@ int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, mis_stats* st, 
         for (;;) {
             int64_t k = g->poll_rounds;
             if (max_rounds > 0) k = std::min<int64_t>(k, max_rounds - enq);
-            for (int64_t i = 0; i < k && rc == MIS_OK; ++i) {
-                const int r = (int)(enq + i + 1);
-                if (timing) (void)hipEventRecord(ev[3 * i], s);
-                rc = enqueue_phase(g, 0, r, s);
-                if (timing) (void)hipEventRecord(ev[3 * i + 1], s);
-                if (rc == MIS_OK) rc = enqueue_phase(g, 1, r, s);
-                if (timing) (void)hipEventRecord(ev[3 * i + 2], s);
+            const bool use_graph = !timing && g->launch != MIS_LAUNCH_DIRECT && k == g->poll_rounds && ensure_graph(g);
+            if (use_graph) {
+                if (hipGraphLaunch(g->graph_exec, s) != hipSuccess) rc = fail(MIS_EHIP, "hipGraphLaunch failed");
+            } else {
+                rc = enqueue_batch(g, k, s, timing ? ev.data() : nullptr);
             }
             if (rc != MIS_OK) break;
-            hipLaunchKernelGGL(k_close, dim3(1), dim3(64), 0, s, g->ctrl, g->trace, (int)(enq + k));
             // ring slots of rounds drained+1 .. enq
             const int64_t first = drained % kTraceCap, cnt = enq + k - drained;
             enq += k;
@@ -337,18 +435,29 @@ int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, mis_stats* st, 
         st->kernel_ms[0] = (float)kms[0];
         st->kernel_ms[1] = (float)kms[1];
         st->launches = (int32_t)launches;
+        st->graph = g->graph_exec != nullptr && !timing && g->launch != MIS_LAUNCH_DIRECT;
     }
     return MIS_OK;
 }
 
-int mis_solve_batch(mis_graph* const* graphs, int32_t count, uint8_t* const* in_sets, mis_stats* stats, void* stream) {
+int mis_solve_batch(mis_graph* g, uint8_t* in_set, mis_stats* stats, int32_t* graph_rounds, int64_t* graph_in,
+                    void* stream) {
     g_last_error.clear();
-    if (count < 0) return fail(MIS_EINVAL, "count must be >= 0");
-    if (count > 0 && (!graphs || !in_sets)) return fail(MIS_EINVAL, "null argument");
-    for (int32_t i = 0; i < count; ++i) {
-        int rc = mis_solve(graphs[i], in_sets[i], 0, stats ? &stats[i] : nullptr, stream);
-        if (rc != MIS_OK) return rc;
+    if (!g) return fail(MIS_EINVAL, "batch is null");
+    if (g->count <= 0) return fail(MIS_EINVAL, "the handle was not built with mis_build_batch");
+    TC_CHECK(mis_solve(g, in_set, 0, stats, stream));
+    hipStream_t s = (hipStream_t)stream;
+    if (g->n > 0) {
+        hipLaunchKernelGGL(k_batch_stats, dim3((unsigned)g->count), dim3(kBlock), 0, s, g->goff, in_set,
+                           g->path == MIS_PATH_TILE ? g->new_id : nullptr, g->dround, g->st, g->g_rounds, g->g_in);
+        TC_HIP(hipGetLastError());
+    } else {
+        TC_HIP(hipMemsetAsync(g->g_rounds, 0, (size_t)g->count * 4, s));
+        TC_HIP(hipMemsetAsync(g->g_in, 0, (size_t)g->count * 8, s));
     }
+    if (graph_rounds) TC_HIP(hipMemcpyAsync(graph_rounds, g->g_rounds, (size_t)g->count * 4, hipMemcpyDeviceToHost, s));
+    if (graph_in) TC_HIP(hipMemcpyAsync(graph_in, g->g_in, (size_t)g->count * 8, hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
     return MIS_OK;
 }
 

@@ -20,7 +20,9 @@ constexpr int kSegTiles = 512;      // tile path: at most this many tiles per wo
 // every cross-workgroup hand-over crosses a kernel boundary.
 struct Ctrl {
     int32_t round;          // rounds closed
+    int32_t rbase;          // rounds enqueued before the current batch (round = rbase + index in batch)
     uint32_t error;         // invariant violation flags
+    int32_t pad0;
     int64_t alive;          // undecided vertices after `round` rounds
     int64_t n_in;           // vertices in the set so far
     int64_t n_act[2][2];    // active work items per list buffer (CSR: [light, heavy]; tile: [segments, -])
@@ -59,7 +61,20 @@ struct mis_graph {
     // chosen configuration
     int path = MIS_PATH_CSR, tile = 0, reorder = MIS_REORDER_NONE, orient = 0;
     int poll_rounds = 4;
+    int launch = MIS_LAUNCH_AUTO;
     bool user_keys = false;           // priorities supplied by the caller
+
+    // captured round loop (launch = graph): poll_rounds rounds and the close kernel
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    bool graph_failed = false;
+
+    ~mis_graph() {
+        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    }
     int grid_blocks = 2048;           // persistent grid of the round kernels
 
     // workspace (caller-owned device memory)
@@ -73,6 +88,12 @@ struct mis_graph {
     char* sort_tmp = nullptr;         // radix sort scratch
 
     uint64_t* key = nullptr;          // priorities, input ids
+
+    // batch (mis_build_batch): graph g owns input vertices goff[g] .. goff[g+1]-1
+    int32_t count = 0;
+    int64_t* goff = nullptr;          // [count+1] device copy of the offsets
+    int32_t* g_rounds = nullptr;      // [count] per-graph rounds (mis_solve_batch)
+    int64_t* g_in = nullptr;          // [count] per-graph set sizes
 
     // ---- CSR path
     int32_t* light = nullptr;         // vertices with degree <= kLightDeg (initial active list)
@@ -116,6 +137,7 @@ struct mis_graph {
     uint32_t* alive = nullptr;        // [nI] undecided rows
     uint64_t* cand = nullptr;         // [nI] (round << 32) | candidate mask
     uint32_t* inmask = nullptr;       // [nI] rows in the set
+    int32_t* dround = nullptr;        // [nI*tile] round in which each row was decided
     uint64_t* part = nullptr;         // [2*nI] (segments done << 32 | partial mask) of multi-segment row-blocks
 };
 

@@ -45,7 +45,8 @@ __device__ inline void round_lists(const CsrArgs& a, int r, const int32_t** in_l
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_csr_cand(CsrArgs a, int r) {
+__global__ void __launch_bounds__(kBlock) k_csr_cand(CsrArgs a, int ri) {
+    const int r = a.ctrl->rbase + ri;   // round number (the batch base is on the device)
     open_round(a.ctrl, a.trace, r);
     const int32_t *L, *H;
     int64_t nl, nh;
@@ -94,7 +95,8 @@ __global__ void __launch_bounds__(kBlock) k_csr_cand(CsrArgs a, int r) {
     wave_add(&cnt[3], verts);
 }
 
-__global__ void __launch_bounds__(kBlock) k_csr_excl(CsrArgs a, int r) {
+__global__ void __launch_bounds__(kBlock) k_csr_excl(CsrArgs a, int ri) {
+    const int r = a.ctrl->rbase + ri;   // round number (the batch base is on the device)
     __shared__ int32_t lbuf[kBlock / kWave][2][kWave];
     const uint32_t in_r = tag(r, kIn), out_r = tag(r, kOut);
     const int32_t *L, *H;

@@ -62,6 +62,7 @@ struct TileArgs {
     uint64_t* part;     // [2*nI]: candidate-phase and exclusion-phase (count << 32 | mask) words
     const int32_t* seg_all;
     int32_t* seglist[2];
+    int32_t* dround;
     const Meta* meta;
     int64_t nI;
     Ctrl* ctrl;
@@ -150,7 +151,8 @@ __device__ inline bool combine(uint64_t* part, int64_t I, int nseg, uint32_t min
 }
 
 template <int T, int ORIENT>
-__global__ void __launch_bounds__(kBlock) k_tile_cand(TileArgs a, int r) {
+__global__ void __launch_bounds__(kBlock) k_tile_cand(TileArgs a, int ri) {
+    const int r = a.ctrl->rbase + ri;   // round number (the batch base is on the device)
     using G = Geo<T>;
     __shared__ uint64_t rkeys[kWpb][32];
     open_round(a.ctrl, a.trace, r);
@@ -254,7 +256,8 @@ template <>
 struct Acc<32> { typedef v16i type; };
 
 template <int T, int ORIENT>
-__global__ void __launch_bounds__(kBlock) k_tile_excl(TileArgs a, int r) {
+__global__ void __launch_bounds__(kBlock) k_tile_excl(TileArgs a, int ri) {
+    const int r = a.ctrl->rbase + ri;   // round number (the batch base is on the device)
     using G = Geo<T>;
     __shared__ uint32_t sbits[kWpb][G::kTpi * G::kWpt];
     __shared__ uint32_t scand[kWpb][G::kTpi];
@@ -329,6 +332,7 @@ __global__ void __launch_bounds__(kBlock) k_tile_excl(TileArgs a, int r) {
         }
         bool keep_rb = false;
         int nseg_I = 0;
+        uint32_t decided = 0;
         if (lane == 0) {
             uint32_t total;
             nseg_I = a.rb_nseg[I];
@@ -339,12 +343,15 @@ __global__ void __launch_bounds__(kBlock) k_tile_excl(TileArgs a, int r) {
                 if (cI) a.inmask[I] |= cI;
                 n_out += __popc(out);
                 keep_rb = na != 0;
+                decided = cI | out;
             }
         }
-        // next round's active list: single-segment row-blocks through the wave
-        // buffer, longer ones directly
+        // rows decided this round record the round; the next round's active list
+        // takes single-segment row-blocks through the wave buffer, longer ones directly
         nseg_I = __shfl(nseg_I, 0, kWave);
         keep_rb = __shfl((int)keep_rb, 0, kWave) != 0;
+        decided = (uint32_t)__shfl((int)decided, 0, kWave);
+        if (lane < T && ((decided >> lane) & 1u)) a.dround[I * T + lane] = r;
         if (keep_rb && nseg_I > 1) {
             if (lane == 0) {
                 const unsigned long long p = atomicAdd((unsigned long long*)next_cnt, (unsigned long long)nseg_I);
@@ -387,6 +394,7 @@ TileArgs make_args(mis_graph* g) {
     a.tile_col = g->tile_col; a.bits = g->tile_bits; a.key_p = g->key_p;
     a.alive = g->alive; a.cand = g->cand; a.inmask = g->inmask; a.part = g->part;
     a.seg_all = g->seg_all; a.seglist[0] = g->seglist[0]; a.seglist[1] = g->seglist[1];
+    a.dround = g->dround;
     a.meta = g->meta; a.nI = g->nI;
     a.ctrl = g->ctrl; a.trace = g->trace;
     return a;

@@ -1,0 +1,202 @@
+// Autotuner: picks the path (CSR lists or bit tiles), the tile size, the vertex order
+// and the persistent grid size of the round kernels for a graph's degree profile.
+//
+// The profile (vertex count, average degree, maximum over average degree, share of
+// isolated vertices, graphs in the batch) is measured on the device and rounded to a
+// bucket.  On a cache miss every candidate configuration is built and solved inside
+// the caller's workspace and timed with HIP events over build + solve, the cost a
+// graph pays once; the fastest is remembered for the bucket, so later graphs with
+// the same profile reuse it without trials.  Every candidate returns the same set
+// (the result depends only on the priorities), so the choice is purely one of speed.
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "common.hpp"
+
+namespace tcmis {
+namespace {
+
+__global__ void k_degree_profile(const int64_t* rp, int64_t n, unsigned long long* max_deg,
+                                 unsigned long long* isolated) {
+    unsigned long long mx = 0, iso = 0;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned long long d = (unsigned long long)(rp[v + 1] - rp[v]);
+        mx = d > mx ? d : mx;
+        iso += d == 0;
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(mx, off, kWave);
+        mx = o > mx ? o : mx;
+        iso += __shfl_xor(iso, off, kWave);
+    }
+    if (lane_id() == 0) {
+        atomicMax(max_deg, mx);
+        atomicAdd(isolated, iso);
+    }
+}
+
+struct Candidate {
+    int path, tile, reorder, orient, blocks_per_cu;
+};
+
+// Trial configurations allowed by the caller's options: a fixed path, tile size or
+// grid size in `base` restricts the search to it.
+std::vector<Candidate> candidates(const mis_build_opts& base) {
+    std::vector<Candidate> c;
+    std::vector<int> grids = {4, 8, 16};
+    if (base.blocks_per_cu) grids = {base.blocks_per_cu};
+    std::vector<int> tiles = {16, 32};
+    if (base.tile) tiles = {base.tile};
+    for (int b : grids) {
+        if (base.path != MIS_PATH_TILE) c.push_back({MIS_PATH_CSR, 0, MIS_REORDER_NONE, 0, b});
+        if (base.path != MIS_PATH_CSR)
+            for (int t : tiles) {
+                c.push_back({MIS_PATH_TILE, t, MIS_REORDER_KEY, 1, b});
+                c.push_back({MIS_PATH_TILE, t, MIS_REORDER_NONE, 1, b});
+            }
+    }
+    return c;
+}
+
+mis_build_opts apply(const mis_build_opts& base, const Candidate& c) {
+    mis_build_opts o = base;
+    o.path = c.path;
+    o.tile = c.tile;
+    o.reorder = c.reorder;
+    o.orient = c.orient;
+    o.blocks_per_cu = c.blocks_per_cu;
+    return o;
+}
+
+size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+using Bucket = std::tuple<int, int, int, int, int, int, int, int>;
+std::mutex g_mu;
+std::map<Bucket, Candidate> g_cache;
+
+// largest build footprint over the candidates (or an error)
+int trial_bytes(const mis_csr* csr, int32_t count, const int64_t* offsets, const mis_build_opts& b, size_t* most) {
+    *most = 0;
+    for (const Candidate& c : candidates(b)) {
+        const mis_build_opts o = apply(b, c);
+        size_t need = 0;
+        TC_CHECK(mis_build_batch_bytes(csr, count, offsets, &o, &need));
+        *most = std::max(*most, need);
+    }
+    return MIS_OK;
+}
+
+}  // namespace
+}  // namespace tcmis
+
+using namespace tcmis;
+
+extern "C" {
+
+int mis_autotune_bytes(const mis_csr* csr, int32_t count, const int64_t* offsets, const mis_build_opts* base,
+                       size_t* bytes) {
+    if (!csr || !bytes) return MIS_EINVAL;
+    mis_build_opts b;
+    if (base) b = *base; else mis_default_opts(&b);
+    size_t most = 0;
+    TC_CHECK(trial_bytes(csr, count, offsets, b, &most));
+    *bytes = round256(most) + round256((size_t)std::max<int64_t>(csr->n, 16));
+    return MIS_OK;
+}
+
+int mis_autotune(const mis_csr* csr, int32_t count, const int64_t* offsets, const mis_build_opts* base,
+                 void* workspace, size_t workspace_bytes, void* stream, mis_build_opts* out, int32_t* from_cache) {
+    if (!csr || !out) return MIS_EINVAL;
+    mis_build_opts b;
+    if (base) b = *base; else mis_default_opts(&b);
+    size_t most = 0;
+    TC_CHECK(trial_bytes(csr, count, offsets, b, &most));
+    const size_t build_bytes = round256(most);
+    if (!workspace || ((uintptr_t)workspace & 255) ||
+        workspace_bytes < build_bytes + round256((size_t)std::max<int64_t>(csr->n, 16))) {
+        set_error("autotune workspace must be 256-byte aligned and hold mis_autotune_bytes bytes");
+        return MIS_EINVAL;
+    }
+    char* ws = (char*)workspace;
+    uint8_t* trial_out = (uint8_t*)(ws + build_bytes);
+    hipStream_t s = (hipStream_t)stream;
+
+    // degree profile: maximum degree and isolated vertices (16 bytes at the output area)
+    unsigned long long* prof = (unsigned long long*)trial_out;
+    unsigned long long h[2] = {0, 0};
+    if (csr->n > 0) {
+        TC_HIP(hipMemsetAsync(prof, 0, 16, s));
+        hipLaunchKernelGGL(k_degree_profile, dim3(stream_grid(csr->n)), dim3(kBlock), 0, s, csr->row_ptr, csr->n,
+                           prof, prof + 1);
+        TC_HIP(hipGetLastError());
+        TC_HIP(hipMemcpyAsync(h, prof, 16, hipMemcpyDeviceToHost, s));
+        TC_HIP(hipStreamSynchronize(s));
+    }
+    const double n = (double)std::max<int64_t>(csr->n, 1);
+    const double avg = (double)csr->nnz / n;
+    const double skew = avg > 0 ? (double)h[0] / avg : 1.0;
+    const int per_graph = count > 0 ? count : 1;
+    const Bucket key{(int)std::ceil(std::log2(n)), (int)std::lround(2.0 * std::log2(avg + 1.0)),
+                     (int)std::lround(std::log2(skew + 1.0)), (int)(8.0 * (double)h[1] / n),
+                     (int)std::ceil(std::log2((double)per_graph)), b.path, b.tile, b.blocks_per_cu};
+    Candidate best{};
+    bool cached = false, found = false;
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        auto it = g_cache.find(key);
+        if (it != g_cache.end()) { best = it->second; cached = found = true; }
+    }
+    if (!cached) {
+        hipEvent_t e0, e1;
+        TC_HIP(hipEventCreate(&e0));
+        if (hipEventCreate(&e1) != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            set_error("hipEventCreate failed");
+            return MIS_EHIP;
+        }
+        float best_ms = 0.f;
+        for (const Candidate& c : candidates(b)) {
+            mis_build_opts o = apply(b, c);
+            o.validate = 0;
+            float ms = 0.f;
+            bool ok = true;
+            // the first run warms code objects and caches; the second is timed
+            for (int rep = 0; rep < 2 && ok; ++rep) {
+                mis_graph* g = nullptr;
+                ok = hipEventRecord(e0, s) == hipSuccess;
+                if (ok) ok = mis_build_batch(csr, count, offsets, &o, ws, build_bytes, stream, &g) == MIS_OK;
+                if (ok) ok = mis_solve(g, trial_out, 0, nullptr, stream) == MIS_OK;
+                if (ok) ok = hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+                if (ok) ok = hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+                mis_free_tiles(g);
+            }
+            if (ok && (!found || ms < best_ms)) {
+                best_ms = ms;
+                best = c;
+                found = true;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (!found) {
+            set_error("no autotune candidate could be built and solved");
+            return MIS_EINTERNAL;
+        }
+        std::lock_guard<std::mutex> lock(g_mu);
+        g_cache[key] = best;
+    }
+    *out = apply(b, best);
+    if (from_cache) *from_cache = cached ? 1 : 0;
+    return MIS_OK;
+}
+
+void mis_autotune_clear(void) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_cache.clear();
+}
+
+}  // extern "C"

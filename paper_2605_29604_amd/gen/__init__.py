@@ -150,3 +150,47 @@ def workload(name: str, seed: int = 1) -> Graph:
         s = int(name[4:])
         return grid(s, s, s, 0.01, seed)
     raise KeyError(name)
+
+
+# ---- batches of independent graphs ----
+
+def batch_spec(count: int, seed: int = 1, n_min: int = 500, n_max: int = 200_000):
+    """Per-graph recipe of a batch: graph g draws from the SplitMix64 stream seeded with
+    seed_g = first output of the stream seeded with (seed XOR g).  Even g: Erdos-Renyi
+    with an integer average degree uniform in [4, 32]; odd g: R-MAT with an integer
+    average degree uniform in [8, 24]; n_g = round(exp(U[ln n_min, ln n_max]));
+    m_g = round(n_g * d_g / 2) (capped to what the graph can hold)."""
+    out = []
+    for g in range(count):
+        sg = int(splitmix64(seed ^ g, 1)[0])
+        d = splitmix64(sg, 3)
+        u1 = (int(d[0]) >> 11) / float(1 << 53)
+        n = int(round(math.exp(math.log(n_min) + u1 * (math.log(n_max) - math.log(n_min)))))
+        if g % 2 == 0:
+            kind, deg = "er", 4 + int(((int(d[1]) >> 32) * 29) >> 32)
+        else:
+            kind, deg = "rmat", 8 + int(((int(d[1]) >> 32) * 17) >> 32)
+        m = min(int(round(n * deg / 2)), n * (n - 1) // 4)
+        out.append((kind, n, m, sg))
+    return out
+
+
+def make(kind: str, n: int, m: int, seed: int) -> Graph:
+    return er(n, m, seed) if kind == "er" else rmat(n, m, seed)
+
+
+def union(graphs):
+    """Disjoint union of graphs: (row_ptr int64, col_idx int32, offsets int64[count+1])."""
+    offsets = np.zeros(len(graphs) + 1, dtype=np.int64)
+    for i, g in enumerate(graphs):
+        offsets[i + 1] = offsets[i] + g.n
+    nnz = sum(g.nnz for g in graphs)
+    row_ptr = np.zeros(int(offsets[-1]) + 1, dtype=np.int64)
+    col_idx = np.zeros(nnz, dtype=np.int32)
+    e = 0
+    for i, g in enumerate(graphs):
+        o = int(offsets[i])
+        row_ptr[o + 1: o + g.n + 1] = g.row_ptr[1:] + e
+        col_idx[e: e + g.nnz] = g.col_idx + o
+        e += g.nnz
+    return row_ptr, col_idx, offsets

@@ -21,12 +21,14 @@ PATH_AUTO, PATH_TILE, PATH_CSR = 0, 1, 2
 REORDER_AUTO, REORDER_NONE, REORDER_DEGREE, REORDER_KEY, REORDER_RCM = 0, 1, 2, 3, 4
 
 PATHS = {"auto": PATH_AUTO, "tile": PATH_TILE, "csr": PATH_CSR}
+LAUNCHES = {"auto": 0, "direct": 1, "graph": 2}
 REORDERS = {"auto": REORDER_AUTO, "none": REORDER_NONE, "degree": REORDER_DEGREE,
             "key": REORDER_KEY, "rcm": REORDER_RCM}
 
 # symbols declared in include/tcmis.h
-EXPORTS = ["mis_default_opts", "mis_build_bytes", "mis_build_tiles", "mis_graph_bytes", "mis_solve", "mis_solve_batch",
-           "mis_free_tiles", "mis_status_string", "mis_last_error", "mis_version"]
+EXPORTS = ["mis_default_opts", "mis_build_bytes", "mis_build_tiles", "mis_build_batch_bytes", "mis_build_batch",
+           "mis_graph_bytes", "mis_solve", "mis_solve_batch", "mis_free_tiles", "mis_status_string", "mis_last_error",
+           "mis_version", "mis_autotune_bytes", "mis_autotune", "mis_autotune_clear"]
 
 
 class MisCsr(ctypes.Structure):
@@ -37,6 +39,7 @@ class MisCsr(ctypes.Structure):
 class MisBuildOpts(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("tile", ctypes.c_int32), ("reorder", ctypes.c_int32),
                 ("orient", ctypes.c_int32), ("validate", ctypes.c_int32), ("poll_rounds", ctypes.c_int32),
+                ("launch", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("keys", ctypes.c_void_p)]
 
 
@@ -46,7 +49,8 @@ class MisStats(ctypes.Structure):
                 ("n_in", ctypes.c_int64), ("tiles", ctypes.c_int64), ("tile_bytes", ctypes.c_int64),
                 ("alg_bytes", ctypes.c_int64), ("units", ctypes.c_int64 * 4),
                 ("kernel_ms", ctypes.c_float * 2), ("launches", ctypes.c_int32),
-                ("trace_cap", ctypes.c_int32), ("trace", ctypes.POINTER(ctypes.c_int64))]
+                ("trace_cap", ctypes.c_int32), ("graph", ctypes.c_int32), ("pad3_", ctypes.c_int32),
+                ("trace", ctypes.POINTER(ctypes.c_int64))]
 
 
 class MisError(RuntimeError):
@@ -80,8 +84,24 @@ def lib():
     L.mis_graph_bytes.restype = ctypes.c_int
     L.mis_solve.argtypes = [vp, vp, i32, ctypes.POINTER(MisStats), vp]
     L.mis_solve.restype = ctypes.c_int
-    L.mis_solve_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp), ctypes.POINTER(MisStats), vp]
+    L.mis_build_batch_bytes.argtypes = [ctypes.POINTER(MisCsr), i32, ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(MisBuildOpts), ctypes.POINTER(ctypes.c_size_t)]
+    L.mis_build_batch_bytes.restype = ctypes.c_int
+    L.mis_build_batch.argtypes = [ctypes.POINTER(MisCsr), i32, ctypes.POINTER(ctypes.c_int64),
+                                  ctypes.POINTER(MisBuildOpts), vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.mis_build_batch.restype = ctypes.c_int
+    L.mis_solve_batch.argtypes = [vp, vp, ctypes.POINTER(MisStats), ctypes.POINTER(ctypes.c_int32),
+                                  ctypes.POINTER(ctypes.c_int64), vp]
     L.mis_solve_batch.restype = ctypes.c_int
+    L.mis_autotune_bytes.argtypes = [ctypes.POINTER(MisCsr), i32, ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(MisBuildOpts), ctypes.POINTER(ctypes.c_size_t)]
+    L.mis_autotune_bytes.restype = ctypes.c_int
+    L.mis_autotune.argtypes = [ctypes.POINTER(MisCsr), i32, ctypes.POINTER(ctypes.c_int64),
+                               ctypes.POINTER(MisBuildOpts), vp, ctypes.c_size_t, vp, ctypes.POINTER(MisBuildOpts),
+                               ctypes.POINTER(ctypes.c_int32)]
+    L.mis_autotune.restype = ctypes.c_int
+    L.mis_autotune_clear.argtypes = []
+    L.mis_autotune_clear.restype = None
     L.mis_free_tiles.argtypes = [vp]
     L.mis_free_tiles.restype = None
     L.mis_status_string.argtypes = [ctypes.c_int]
@@ -120,6 +140,7 @@ class MisGraph:
     n: int
     nnz: int
     keepalive: tuple = field(default_factory=tuple)
+    count: int = 0
 
     def bytes(self) -> int:
         b = ctypes.c_size_t(0)
@@ -133,7 +154,8 @@ class MisGraph:
             self.handle = None
 
 
-def _opts(path="auto", tile=0, reorder="auto", orient=-1, validate=False, seed=1, keys=None, poll_rounds=0):
+def _opts(path="auto", tile=0, reorder="auto", orient=-1, validate=False, seed=1, keys=None, poll_rounds=0,
+          launch="auto", blocks_per_cu=0):
     o = MisBuildOpts()
     lib().mis_default_opts(ctypes.byref(o))
     o.path = PATHS[path] if isinstance(path, str) else int(path)
@@ -142,6 +164,8 @@ def _opts(path="auto", tile=0, reorder="auto", orient=-1, validate=False, seed=1
     o.orient = int(orient)
     o.validate = int(bool(validate))
     o.poll_rounds = int(poll_rounds)
+    o.launch = LAUNCHES[launch] if isinstance(launch, str) else int(launch)
+    o.blocks_per_cu = int(blocks_per_cu)
     o.seed = int(seed) & (2**64 - 1)
     o.keys = _ptr(keys)
     return o
@@ -157,7 +181,8 @@ def mis_build_bytes(n: int, nnz: int, **opts) -> int:
 
 
 def mis_build_tiles(row_ptr, col_idx, path="auto", tile=0, reorder="auto", orient=-1, validate=False,
-                    seed=1, keys=None, poll_rounds=0, workspace=None, stream=None) -> MisGraph:
+                    seed=1, keys=None, poll_rounds=0, launch="auto", blocks_per_cu=0, workspace=None,
+                    stream=None) -> MisGraph:
     """row_ptr: cuda int64[n+1]; col_idx: cuda int32[nnz]; keys: optional cuda uint64[n] (as int64).
 
     The device workspace comes from torch's allocator unless one is passed (a cuda
@@ -168,7 +193,7 @@ def mis_build_tiles(row_ptr, col_idx, path="auto", tile=0, reorder="auto", orien
     n = row_ptr.numel() - 1
     nnz = col_idx.numel()
     csr = MisCsr(n, nnz, _ptr(row_ptr), _ptr(col_idx) if nnz else None)
-    o = _opts(path, tile, reorder, orient, validate, seed, keys, poll_rounds)
+    o = _opts(path, tile, reorder, orient, validate, seed, keys, poll_rounds, launch, blocks_per_cu)
     need = ctypes.c_size_t(0)
     _check(L.mis_build_bytes(ctypes.byref(csr), ctypes.byref(o), ctypes.byref(need)))
     if workspace is None:
@@ -184,7 +209,7 @@ def _stats_dict(st: MisStats, trace_buf) -> dict:
     d = {
         "rounds": rounds, "path": st.path, "tile": st.tile, "reorder": st.reorder, "orient": st.orient,
         "n_in": st.n_in, "tiles": st.tiles, "tile_bytes": st.tile_bytes, "alg_bytes": st.alg_bytes,
-        "units": list(st.units), "kernel_ms": list(st.kernel_ms), "launches": st.launches,
+        "units": list(st.units), "kernel_ms": list(st.kernel_ms), "launches": st.launches, "graph": st.graph,
     }
     if trace_buf is not None:
         k = min(rounds, st.trace_cap)
@@ -214,22 +239,95 @@ def mis_solve(g: MisGraph, out=None, max_rounds=0, trace_cap=4096, timing=False,
     return out, _stats_dict(st, buf)
 
 
-def mis_solve_batch(graphs, outs=None, trace_cap=4096, stream=None):
-    """Solves the graphs of a batch together; returns (list of outputs, list of stats)."""
+def _offsets(offsets):
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    return off, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+
+def mis_build_batch_bytes(n: int, nnz: int, offsets, **opts) -> int:
+    csr = MisCsr(n, nnz, ctypes.c_void_p(256), ctypes.c_void_p(256) if nnz else None)
+    off, offp = _offsets(offsets)
+    o = _opts(**opts)
+    b = ctypes.c_size_t(0)
+    _check(lib().mis_build_batch_bytes(ctypes.byref(csr), len(off) - 1, offp, ctypes.byref(o), ctypes.byref(b)))
+    return int(b.value)
+
+
+def mis_build_batch(row_ptr, col_idx, offsets, path="auto", tile=0, reorder="auto", orient=-1, validate=False,
+                    seed=1, keys=None, poll_rounds=0, launch="auto", blocks_per_cu=0, workspace=None,
+                    stream=None) -> MisGraph:
+    """A batch of independent graphs given as their disjoint union (cuda CSR) and host
+    vertex offsets (count+1).  Priorities use graph-local ids."""
     import torch
-    if outs is None:
-        outs = [torch.empty(max(g.n, 0), dtype=torch.uint8, device="cuda") for g in graphs]
-    k = len(graphs)
-    hs = (ctypes.c_void_p * max(k, 1))(*[g.handle for g in graphs])
-    os_ = (ctypes.c_void_p * max(k, 1))(*[o.data_ptr() for o in outs])
-    sts = (MisStats * max(k, 1))()
-    bufs = []
-    for i in range(k):
-        st, buf = _new_stats(trace_cap, False)
-        sts[i] = st
-        bufs.append(buf)
-    _check(lib().mis_solve_batch(hs, k, os_, sts, ctypes.c_void_p(_stream(stream))))
-    return outs, [_stats_dict(sts[i], bufs[i]) for i in range(k)]
+    L = lib()
+    n = row_ptr.numel() - 1
+    nnz = col_idx.numel()
+    csr = MisCsr(n, nnz, _ptr(row_ptr), _ptr(col_idx) if nnz else None)
+    off, offp = _offsets(offsets)
+    o = _opts(path, tile, reorder, orient, validate, seed, keys, poll_rounds, launch, blocks_per_cu)
+    need = ctypes.c_size_t(0)
+    _check(L.mis_build_batch_bytes(ctypes.byref(csr), len(off) - 1, offp, ctypes.byref(o), ctypes.byref(need)))
+    if workspace is None:
+        workspace = torch.empty(int(need.value), dtype=torch.uint8, device=row_ptr.device)
+    h = ctypes.c_void_p(None)
+    _check(L.mis_build_batch(ctypes.byref(csr), len(off) - 1, offp, ctypes.byref(o), _ptr(workspace),
+                             workspace.numel(), ctypes.c_void_p(_stream(stream)), ctypes.byref(h)))
+    g = MisGraph(h, n, nnz, (row_ptr, col_idx, keys, workspace))
+    g.count = len(off) - 1
+    return g
+
+
+def mis_solve_batch(g: MisGraph, out=None, trace_cap=4096, stream=None):
+    """Returns (in_set cuda uint8[n] of the union, batch stats, per-graph rounds int32[count],
+    per-graph set sizes int64[count])."""
+    import torch
+    if out is None:
+        out = torch.empty(max(g.n, 0), dtype=torch.uint8, device="cuda")
+    st, buf = _new_stats(trace_cap, False)
+    rounds = np.zeros(max(g.count, 1), dtype=np.int32)
+    sizes = np.zeros(max(g.count, 1), dtype=np.int64)
+    _check(lib().mis_solve_batch(g.handle, _ptr(out) if g.n else None, ctypes.byref(st),
+                                 rounds.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                 sizes.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                 ctypes.c_void_p(_stream(stream))))
+    return out, _stats_dict(st, buf), rounds[: g.count], sizes[: g.count]
+
+
+_PATH_NAMES = {v: k for k, v in PATHS.items()}
+_REORDER_NAMES = {v: k for k, v in REORDERS.items()}
+
+
+def mis_autotune(row_ptr, col_idx, offsets=None, path="auto", tile=0, blocks_per_cu=0, seed=1, keys=None,
+                 poll_rounds=0, launch="auto", workspace=None, stream=None):
+    """Tuned build options for this graph (or batch, with host offsets) as a dict of
+    mis_build_tiles / mis_build_batch keyword arguments, plus whether the profile
+    bucket was already cached: (opts, from_cache)."""
+    import torch
+    L = lib()
+    n = row_ptr.numel() - 1
+    nnz = col_idx.numel()
+    csr = MisCsr(n, nnz, _ptr(row_ptr), _ptr(col_idx) if nnz else None)
+    count, offp = 0, None
+    if offsets is not None:
+        off, offp = _offsets(offsets)
+        count = len(off) - 1
+    o = _opts(path, tile, "auto", -1, False, seed, keys, poll_rounds, launch, blocks_per_cu)
+    need = ctypes.c_size_t(0)
+    _check(L.mis_autotune_bytes(ctypes.byref(csr), count, offp, ctypes.byref(o), ctypes.byref(need)))
+    if workspace is None:
+        workspace = torch.empty(int(need.value), dtype=torch.uint8, device=row_ptr.device)
+    res = MisBuildOpts()
+    cached = ctypes.c_int32(0)
+    _check(L.mis_autotune(ctypes.byref(csr), count, offp, ctypes.byref(o), _ptr(workspace), workspace.numel(),
+                          ctypes.c_void_p(_stream(stream)), ctypes.byref(res), ctypes.byref(cached)))
+    opts = dict(path=_PATH_NAMES[res.path], tile=res.tile, reorder=_REORDER_NAMES[res.reorder],
+                orient=res.orient, blocks_per_cu=res.blocks_per_cu, seed=seed, keys=keys,
+                poll_rounds=poll_rounds, launch=launch)
+    return opts, bool(cached.value)
+
+
+def mis_autotune_clear():
+    lib().mis_autotune_clear()
 
 
 def mis_free_tiles(g: MisGraph):

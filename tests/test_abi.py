@@ -80,8 +80,6 @@ def test_host_argument_errors(L):
     assert build(L, csr, None, None, need.value, hp) == tcmis.MIS_EINVAL
     assert not h.value
     assert L.mis_solve(None, None, 0, None, None) == tcmis.MIS_EINVAL
-    assert L.mis_solve_batch(None, -1, None, None, None) == tcmis.MIS_EINVAL
-    assert L.mis_solve_batch(None, 2, None, None, None) == tcmis.MIS_EINVAL
     assert L.mis_graph_bytes(None, None) == tcmis.MIS_EINVAL
     L.mis_free_tiles(None)
 
@@ -94,3 +92,43 @@ def test_build_bytes_scaling(L):
     assert 1.8 < (big2 - small) / (big - small) < 2.2     # linear in the graph size
     assert tcmis.mis_build_bytes(100000, 800000, path="tile", tile=32, orient=0) > \
         tcmis.mis_build_bytes(100000, 800000, path="tile", tile=16, orient=1) > big
+
+
+def test_batch_argument_errors(L):
+    n = 10
+    ok = [0, 4, 10]
+    assert tcmis.mis_build_batch_bytes(n, 20, ok, path="tile") > tcmis.mis_build_bytes(n, 20, path="tile")
+    for bad in ([0, 4, 9], [1, 4, 10], [0, 6, 4, 10]):
+        with pytest.raises(tcmis.MisError) as ei:
+            tcmis.mis_build_batch_bytes(n, 20, bad)
+        assert ei.value.code == tcmis.MIS_EINVAL
+    with pytest.raises(tcmis.MisError):
+        tcmis.mis_build_batch_bytes((1 << 24) + 10, 0, [0, (1 << 24) + 10])   # one graph too large for the key rule
+    assert tcmis.mis_build_batch_bytes((1 << 24) + 10, 0, [0, 1 << 23, (1 << 24) + 10]) > 0
+    assert L.mis_solve_batch(None, None, None, None, None, None) == tcmis.MIS_EINVAL
+
+
+def test_autotune_argument_errors(L):
+    csr = tcmis.MisCsr(1000, 8000, ctypes.c_void_p(256), ctypes.c_void_p(256))
+    need = ctypes.c_size_t(0)
+    assert L.mis_autotune_bytes(ctypes.byref(csr), 0, None, None, ctypes.byref(need)) == 0
+    # room for the largest trial build plus the trial output
+    for path, tile in (("tile", 16), ("tile", 32), ("csr", 0)):
+        one = tcmis.mis_build_bytes(1000, 8000, path=path, tile=tile)
+        assert need.value >= one + 1000
+    out = tcmis.MisBuildOpts()
+    ws = ctypes.c_void_p(1 << 20)   # never dereferenced: every call below fails on the host
+    assert L.mis_autotune(None, 0, None, None, ws, need.value, None, ctypes.byref(out), None) == tcmis.MIS_EINVAL
+    assert L.mis_autotune(ctypes.byref(csr), 0, None, None, ws, need.value, None, None, None) == tcmis.MIS_EINVAL
+    assert L.mis_autotune(ctypes.byref(csr), 0, None, None, ws, need.value - 1, None, ctypes.byref(out),
+                          None) == tcmis.MIS_EINVAL
+    assert "workspace" in L.mis_last_error().decode()
+    assert L.mis_autotune(ctypes.byref(csr), 0, None, None, ctypes.c_void_p((1 << 20) + 8), need.value, None,
+                          ctypes.byref(out), None) == tcmis.MIS_EINVAL
+    o = tcmis.MisBuildOpts()
+    L.mis_default_opts(ctypes.byref(o))
+    o.blocks_per_cu = 33
+    assert L.mis_autotune(ctypes.byref(csr), 0, None, ctypes.byref(o), ws, 1 << 40, None, ctypes.byref(out),
+                          None) == tcmis.MIS_EINVAL
+    assert "blocks_per_cu" in L.mis_last_error().decode()
+    L.mis_autotune_clear()

@@ -96,3 +96,30 @@ def test_thread_count_independent():
         env = dict(os.environ, GG_THREADS=t)
         outs.add(subprocess.check_output([sys.executable, "-c", code], cwd=ROOT, env=env).strip())
     assert len(outs) == 1
+
+
+def test_batch_spec():
+    sp = gen.batch_spec(4096, 1)
+    assert sp == gen.batch_spec(4096, 1) and sp != gen.batch_spec(4096, 2)
+    ns = np.array([s[1] for s in sp])
+    assert ns.min() >= 500 and ns.max() <= 200_000
+    # log-uniform: the median is near the geometric mean of the range
+    assert 6_000 < np.median(ns) < 14_000
+    kinds = [s[0] for s in sp]
+    assert kinds[::2] == ["er"] * 2048 and kinds[1::2] == ["rmat"] * 2048
+    for kind, n, m, _ in sp[:200]:
+        d = 2 * m / n
+        assert (3.9 <= d <= 32.1) if kind == "er" else (7.9 <= d <= 24.1)
+
+
+def test_union():
+    gs = [gen.er(30, 60, 1), gen.er(0, 0, 1), gen.rmat(50, 120, 2), gen.er(1, 0, 3)]
+    rp, ci, off = gen.union(gs)
+    assert list(off) == [0, 30, 30, 80, 81]
+    u = gen.Graph(int(off[-1]), rp, ci)
+    check_simple(u)
+    for i, g in enumerate(gs):
+        o = int(off[i])
+        for v in range(g.n):
+            a = ci[rp[o + v]:rp[o + v + 1]] - o
+            assert np.array_equal(a, g.col_idx[g.row_ptr[v]:g.row_ptr[v + 1]])

@@ -203,3 +203,113 @@ def test_rmat22_full(cfg):
 def test_grid256_full(cfg):
     g = gen.workload("grid256", seed=1)
     check(g.row_ptr, g.col_idx, cfg, seed=1, label="grid256")
+
+
+@pytest.mark.parametrize("cfg", FAST_CONFIGS, ids=lambda c: "-".join(map(str, c)))
+def test_launch_modes_and_graph_replays(cfg):
+    # the captured round loop is replayed many times (several batches per solve and
+    # several solves per handle, with host work and synchronisation in between);
+    # every replay must give the direct-launch result, which must equal the oracle
+    T = tcmis_mod()
+    g = gen.workload("grid24", seed=3)
+    k = oracle.keys(g.row_ptr, 6)
+    want, rounds, trace = expected(g.row_ptr, g.col_idx, k)
+    drp, dci = to_dev(g.row_ptr, g.col_idx)
+    for launch in ("direct", "graph"):
+        h = T.mis_build_tiles(drp, dci, path=cfg[0], tile=cfg[1], reorder=cfg[2], orient=cfg[3], seed=6,
+                              poll_rounds=2, launch=launch)
+        for rep in range(4):
+            out, st = T.mis_solve(h)
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy(), want), f"{launch} replay {rep}"
+            assert np.array_equal(st["trace"], trace) and st["rounds"] == rounds
+            assert st["graph"] == (1 if launch == "graph" else 0)
+            _ = torch.ones(1000, device="cuda").sum().item()   # unrelated eager work between replays
+        T.mis_free_tiles(h)
+
+
+BATCH_CONFIGS = [("csr", 0, "none", 0), ("tile", 16, "key", 1), ("tile", 32, "degree", 0), ("tile", 16, "rcm", 1)]
+
+
+def solve_batch(graphs, cfg, seed):
+    T = tcmis_mod()
+    rp, ci, off = gen.union(graphs)
+    drp, dci = to_dev(rp, ci)
+    h = T.mis_build_batch(drp, dci, off, path=cfg[0], tile=cfg[1], reorder=cfg[2], orient=cfg[3], seed=seed,
+                          validate=True, poll_rounds=3)
+    out, st, rounds, sizes = T.mis_solve_batch(h)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    T.mis_free_tiles(h)
+    return got, st, rounds, sizes, off
+
+
+@pytest.mark.parametrize("cfg", BATCH_CONFIGS, ids=lambda c: "-".join(map(str, c)))
+def test_batch_equals_each_graph_alone(cfg):
+    # disjoint union with graph-local priorities: every graph's slice, round count
+    # and set size equal its own round-synchronous solve
+    spec = gen.batch_spec(40, seed=5, n_min=20, n_max=4000)
+    graphs = [gen.make(*s) for s in spec]
+    graphs.insert(7, gen.er(1, 0, 1))          # a one-vertex graph
+    graphs.insert(11, gen.er(0, 0, 1))         # an empty graph
+    got, st, rounds, sizes, off = solve_batch(graphs, cfg, seed=11)
+    worst = 0
+    for i, g in enumerate(graphs):
+        want, r, tr = expected(g.row_ptr, g.col_idx, oracle.keys(g.row_ptr, 11))
+        assert np.array_equal(got[off[i]:off[i + 1]], want), f"graph {i} {spec[i] if i < len(spec) else ''}"
+        assert rounds[i] == r and sizes[i] == int(want.sum()), f"graph {i}"
+        worst = max(worst, r)
+    assert st["rounds"] == worst and st["n_in"] == int(sizes.sum())
+
+
+def test_batch_rejects_cross_edges():
+    T = tcmis_mod()
+    rp, ci = csr_from_edges(6, [(0, 1), (2, 3), (3, 4)])
+    drp, dci = to_dev(rp, ci)
+    T.mis_build_batch(drp, dci, [0, 2, 6], validate=True)      # fine: no edge crosses
+    with pytest.raises(T.MisError) as ei:
+        T.mis_build_batch(drp, dci, [0, 3, 6], validate=True)  # edge 2-3 joins the graphs
+    assert ei.value.code == T.MIS_EINVAL
+
+
+def test_autotune_picks_a_valid_config_and_caches_it():
+    T = tcmis_mod()
+    T.mis_autotune_clear()
+    for name in ("er10k", "rmat14"):
+        g = gen.workload(name, seed=2)
+        drp, dci = to_dev(g.row_ptr, g.col_idx)
+        opts, cached = T.mis_autotune(drp, dci, seed=4)
+        print(f"case autotune {name} -> {opts['path']} T={opts['tile']} {opts['reorder']} "
+              f"bpc={opts['blocks_per_cu']} cached={cached}", flush=True)
+        assert not cached
+        assert opts["path"] in ("tile", "csr") and opts["blocks_per_cu"] in (4, 8, 16)
+        if opts["path"] == "tile":
+            assert opts["tile"] in (16, 32) and opts["reorder"] in ("key", "none")
+        again, cached = T.mis_autotune(drp, dci, seed=4)
+        assert cached and again == opts
+        h = T.mis_build_tiles(drp, dci, validate=True, **opts)
+        out, st = T.mis_solve(h)
+        torch.cuda.synchronize()
+        want, rounds, trace = expected(g.row_ptr, g.col_idx, oracle.keys(g.row_ptr, 4))
+        assert np.array_equal(out.cpu().numpy(), want) and st["rounds"] == rounds
+        assert np.array_equal(st["trace"], trace)
+        T.mis_free_tiles(h)
+    # a fixed path is kept
+    opts, _ = T.mis_autotune(drp, dci, path="csr", seed=4)
+    assert opts["path"] == "csr" and opts["tile"] == 0
+
+
+def test_autotune_batch():
+    T = tcmis_mod()
+    graphs = [gen.make(*s) for s in gen.batch_spec(24, seed=8, n_min=50, n_max=3000)]
+    rp, ci, off = gen.union(graphs)
+    drp, dci = to_dev(rp, ci)
+    opts, _ = T.mis_autotune(drp, dci, off, seed=3)
+    h = T.mis_build_batch(drp, dci, off, validate=True, **opts)
+    out, st, rounds, sizes = T.mis_solve_batch(h)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    T.mis_free_tiles(h)
+    for i, g in enumerate(graphs):
+        want, r, _ = expected(g.row_ptr, g.col_idx, oracle.keys(g.row_ptr, 3))
+        assert np.array_equal(got[off[i]:off[i + 1]], want) and rounds[i] == r, f"graph {i}"
