@@ -10,7 +10,19 @@ Also reported: solve-only throughput (structure built once), the scalar CSR path
 on the same graph, per-kernel HIP-event timings of the round kernels, the
 roofline of the dominant round kernel, and the CPU oracle timed on this host.
 
+"batch": 4,096 independent graphs (sizes log-uniform over 500..200,000 vertices,
+half Erdos-Renyi with average degree 4..32, half R-MAT with 8..24) solved as
+block-diagonal batches (mis_build_batch + mis_solve_batch) against one graph per
+build+solve; graphs/s, Medges/s and per-graph completion percentiles.
+
+"serving": a pool of requests (log-uniform 1e3..4e6 vertices, Erdos-Renyi / R-MAT /
+3D grid) in pinned host memory; Poisson arrivals at 0.5, 0.8, 1.0 and 1.2 times
+the measured one-at-a-time capacity; the continuous-batching session against the
+same session limited to one live request (FCFS, one graph per launch); graphs/s
+and p50/p99 latency from arrival to result in host memory (H2D, build, solve, D2H).
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rmat22]
+                       [--batch-graphs 4096] [--serve-requests 2000] [--no-batch] [--no-serve]
 """
 from __future__ import annotations
 
@@ -40,7 +52,199 @@ def parse():
     p.add_argument("--orient", type=int, default=1)
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU oracle sample")
     p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--no-batch", action="store_true")
+    p.add_argument("--no-serve", action="store_true")
+    p.add_argument("--batch-graphs", type=int, default=4096)
+    p.add_argument("--serve-requests", type=int, default=2000)
+    p.add_argument("--serve-pool", type=int, default=48)
+    p.add_argument("--serve-live", type=int, default=8)
     return p.parse_args()
+
+
+def log(msg):
+    print(f"# {msg}", file=sys.stderr, flush=True)
+
+
+def pct(x, q):
+    return round(float(np.percentile(np.asarray(x), q)), 3) if len(x) else None
+
+
+def bench_batch(a, torch, gen, tcmis):
+    """Block-diagonal batches vs one graph per build+solve on the 4,096-graph mix."""
+    t0 = time.perf_counter()
+    spec = gen.batch_spec(a.batch_graphs, seed=1)
+    rp_h, ci_h, off = gen.batch_union(spec)
+    log(f"batch: {len(spec)} graphs, n={off[-1]} nnz={ci_h.size} generated in {time.perf_counter() - t0:.1f}s")
+    cfg = dict(path="tile", tile=a.tile, reorder=a.reorder, orient=a.orient, seed=a.seed)
+    # handles index entries with 32-bit offsets: split into consecutive sub-batches of < 2^31 entries
+    limit = (1 << 31) - 1
+    groups, start = [], 0
+    for g in range(1, len(spec) + 1):
+        if rp_h[off[g]] - rp_h[off[start]] > limit:
+            groups.append((start, g - 1))
+            start = g - 1
+    groups.append((start, len(spec)))
+    subs = []
+    for (ga, gb) in groups:
+        va, vb = int(off[ga]), int(off[gb])
+        ea, eb = int(rp_h[va]), int(rp_h[vb])
+        rp = torch.from_numpy(rp_h[va:vb + 1] - ea).cuda()
+        ci = torch.from_numpy(ci_h[ea:eb]).cuda()
+        ci -= va
+        subs.append((rp, ci, off[ga:gb + 1] - va))
+    ws_bytes = max(tcmis.mis_build_batch_bytes(s[0].numel() - 1, s[1].numel(), s[2], **cfg) for s in subs)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    outs = [torch.empty(s[0].numel() - 1, dtype=torch.uint8, device="cuda") for s in subs]
+
+    def batched():
+        done_t, rounds = [], []
+        t = time.perf_counter()
+        for (rp, ci, o), out in zip(subs, outs):
+            h = tcmis.mis_build_batch(rp, ci, o, workspace=ws, **cfg)
+            _, st, r, _ = tcmis.mis_solve_batch(h, out=out, trace_cap=0)
+            tcmis.mis_free_tiles(h)
+            done_t += [time.perf_counter() - t] * (len(o) - 1)
+            rounds.append(int(st["rounds"]))
+        return time.perf_counter() - t, done_t, rounds
+
+    batched()
+    torch.cuda.synchronize()
+    reps = [batched() for _ in range(3)]
+    b_s = float(np.mean([r[0] for r in reps]))
+    b_done = reps[-1][1]
+    # one graph per build + solve, on per-graph device copies of the same CSR
+    singles, where = [], []
+    for si, (ga, gb) in enumerate(groups):
+        for g in range(ga, gb):
+            va, vb = int(off[g]), int(off[g + 1])
+            ea, eb = int(rp_h[va]), int(rp_h[vb])
+            base_v, base_e = int(off[ga]), int(rp_h[off[ga]])
+            rp_s, ci_s = subs[si][0], subs[si][1]
+            singles.append((rp_s[va - base_v:vb - base_v + 1] - (ea - base_e), ci_s[ea - base_e:eb - base_e] - (va - base_v)))
+            where.append((si, va - base_v, vb - base_v))
+    torch.cuda.synchronize()
+    one_ws = torch.empty(max(tcmis.mis_build_bytes(r.numel() - 1, c.numel(), **cfg) for r, c in singles),
+                         dtype=torch.uint8, device="cuda")
+    one_out = torch.empty(max(r.numel() - 1 for r, _ in singles), dtype=torch.uint8, device="cuda")
+
+    def one_by_one(k):
+        done_t = []
+        t = time.perf_counter()
+        for rp, ci in singles[:k]:
+            h = tcmis.mis_build_tiles(rp, ci, workspace=one_ws, **cfg)
+            tcmis.mis_solve(h, out=one_out[: rp.numel() - 1], trace_cap=0)
+            tcmis.mis_free_tiles(h)
+            done_t.append(time.perf_counter() - t)
+        return time.perf_counter() - t, done_t
+
+    one_by_one(64)
+    torch.cuda.synchronize()
+    o_s, o_done = one_by_one(len(singles))
+    # spot parity: graphs solved in the batch equal the same graphs solved alone
+    same = True
+    for gi in range(0, len(singles), max(1, len(singles) // 16)):
+        rp, ci = singles[gi]
+        h = tcmis.mis_build_tiles(rp, ci, workspace=one_ws, **cfg)
+        alone, _ = tcmis.mis_solve(h, out=one_out[: rp.numel() - 1], trace_cap=0)
+        tcmis.mis_free_tiles(h)
+        si, a0, a1 = where[gi]
+        same &= bool(torch.equal(alone, outs[si][a0:a1]))
+    edges = int(ci_h.size) // 2
+    res = {"graphs": len(spec), "vertices": int(off[-1]), "edges": edges, "launch_groups": len(subs),
+           "config": f"tile {a.tile}, reorder {a.reorder}, orient {a.orient}",
+           "batched": {"s": round(b_s, 4), "graphs_s": round(len(spec) / b_s, 1),
+                       "medges_s": round(edges / b_s / 1e6, 1), "rounds": reps[-1][2],
+                       "p50_ms": pct(np.array(b_done) * 1e3, 50), "p99_ms": pct(np.array(b_done) * 1e3, 99)},
+           "one_graph_per_launch": {"s": round(o_s, 4), "graphs_s": round(len(singles) / o_s, 1),
+                                    "medges_s": round(edges / o_s / 1e6, 1),
+                                    "p50_ms": pct(np.array(o_done) * 1e3, 50),
+                                    "p99_ms": pct(np.array(o_done) * 1e3, 99)},
+           "speedup": round(o_s / b_s, 2), "batch_equals_alone_sampled": same}
+    del subs, outs, ws, singles, one_ws, one_out
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_serve(a, torch, gen, tcmis):
+    """Continuous-batching session vs FCFS one-at-a-time on the same Poisson traces."""
+    t0 = time.perf_counter()
+    spec = gen.serve_spec(a.serve_pool, seed=1)
+    rp_h, ci_h, off = gen.batch_union(spec)
+    pool = []
+    for i in range(len(spec)):
+        va, vb = int(off[i]), int(off[i + 1])
+        ea, eb = int(rp_h[va]), int(rp_h[vb])
+        rp = torch.from_numpy(rp_h[va:vb + 1] - ea).pin_memory()
+        ci = torch.from_numpy(ci_h[ea:eb] - va).pin_memory()
+        pool.append((rp, ci, vb - va))
+    del rp_h, ci_h
+    log(f"serving pool: {len(pool)} graphs, mean n={np.mean([p[2] for p in pool]):.0f}, "
+        f"made in {time.perf_counter() - t0:.1f}s")
+    r = lambda x: (x + 255) // 256 * 256
+    foot = max(r(tcmis.mis_build_bytes(p[2], p[1].numel())) + r((p[2] + 1) * 8) + r(p[1].numel() * 4) + r(p[2])
+               for p in pool)
+    arena = torch.empty(max(2 * foot, min(foot * 2 * a.serve_live, 96 << 30)), dtype=torch.uint8, device="cuda")
+    nmax = max(p[2] for p in pool)
+    rng = np.random.default_rng(12345)
+    picks = rng.integers(0, len(pool), size=a.serve_requests)
+    ref = {}
+
+    def run(max_live, arrivals):
+        sess = tcmis.Session(arena=arena, max_live=max_live, rounds_per_step=4)
+        bufs = [torch.empty(nmax, dtype=torch.uint8).pin_memory() for _ in range(max_live)]
+        free = list(range(max_live))
+        owner, lat, mismatch = {}, [], 0
+        nxt, done_n = 0, 0
+        t = time.perf_counter()
+        while done_n < len(arrivals):
+            now = time.perf_counter() - t
+            while nxt < len(arrivals) and arrivals[nxt] <= now and free:
+                p = pool[picks[nxt]]
+                b = free[-1]
+                if not sess.admit(p[0], p[1], tag=nxt, host_out=bufs[b][: p[2]]):
+                    break
+                free.pop()
+                owner[nxt] = b
+                nxt += 1
+            for d in sess.progress(wait=False):
+                i = d["tag"]
+                lat.append(time.perf_counter() - t - arrivals[i])
+                b = owner.pop(i)
+                res = bufs[b][: pool[picks[i]][2]]
+                k = int(picks[i])
+                if k not in ref:
+                    ref[k] = res.clone()
+                elif not torch.equal(ref[k], res):
+                    mismatch += 1
+                free.append(b)
+                done_n += 1
+        span = time.perf_counter() - t
+        sess.close()
+        lat_ms = np.array(lat) * 1e3
+        return {"graphs_s": round(len(arrivals) / span, 1), "p50_ms": pct(lat_ms, 50), "p99_ms": pct(lat_ms, 99),
+                "mean_ms": round(float(lat_ms.mean()), 3)}, mismatch
+
+    # capacity of one request at a time (all requests queued at t = 0)
+    ncap = min(400, a.serve_requests)
+    run(1, np.zeros(min(32, ncap)))
+    cap_res, _ = run(1, np.zeros(ncap))
+    capacity = cap_res["graphs_s"]
+    log(f"serving: one-at-a-time capacity {capacity} graphs/s")
+    points, mism = [], 0
+    for rel in (0.5, 0.8, 1.0, 1.2):
+        rate = rel * capacity
+        arrivals = np.cumsum(np.random.default_rng(int(rel * 100)).exponential(1.0 / rate, a.serve_requests))
+        mix, m1 = run(a.serve_live, arrivals)
+        fcfs, m2 = run(1, arrivals)
+        mism += m1 + m2
+        points.append({"load": rel, "rate_per_s": round(rate, 1), "continuous": mix, "fcfs_one_at_a_time": fcfs})
+        log(f"serving load {rel}: continuous {mix} | fcfs {fcfs}")
+    del arena
+    torch.cuda.empty_cache()
+    return {"requests_per_point": a.serve_requests, "pool": len(pool),
+            "pool_mean_n": round(float(np.mean([p[2] for p in pool])), 1), "max_live": a.serve_live,
+            "capacity_one_at_a_time_graphs_s": capacity, "points": points,
+            "mix_equals_alone": mism == 0, "latency": "arrival to result in pinned host memory"}
 
 
 def main():
@@ -159,6 +363,11 @@ def main():
                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                        "avg_launch_us": round(avg_ms * 1e3, 3), "launches": launches,
                        "alg_bytes_per_launch": int(bytes_k / launches)}
+
+    if not a.no_batch:
+        res["batch"] = bench_batch(a, torch, gen, tcmis)
+    if not a.no_serve:
+        res["serving"] = bench_serve(a, torch, gen, tcmis)
 
     if not a.no_cpu:
         import oracle

@@ -40,6 +40,7 @@ typedef enum {
     MIS_EDUP = -4,        /* validate: duplicate or unsorted adjacency entries */
     MIS_ERANGE = -5,      /* validate: column index out of [0, n) or bad row_ptr */
     MIS_ENOMEM = -6,      /* host allocation failed */
+    MIS_EBUSY = -7,       /* session: no free slot or arena region right now (retry later) */
     MIS_EHIP = -8,        /* a HIP runtime call failed */
     MIS_EINTERNAL = -9    /* round limit exceeded or broken invariant */
 } mis_status;
@@ -219,6 +220,71 @@ int mis_autotune(const mis_csr* csr, int32_t count, const int64_t* offsets, cons
                  void* workspace, size_t workspace_bytes, void* stream, mis_build_opts* out, int32_t* from_cache);
 /* Forgets every tuned bucket. */
 void mis_autotune_clear(void);
+
+/*
+ * Serving session: continuous batching of independent MIS requests on one GPU.
+ * Requests are admitted while others run, as long as a slot and a region of the
+ * caller's device arena are free (admission by HBM footprint: the request's CSR copy,
+ * its solver structure from mis_build_bytes and its output).  Every live request
+ * has its own stream; mis_session_progress enqueues its rounds rounds_per_step at a
+ * time without waiting on any one request, so the rounds of all live requests
+ * overlap on the device, and a request admitted between two progress calls starts
+ * at once instead of waiting for the others to finish.  A request's result is
+ * identical to solving it alone (its kernels read only its own state).
+ * A session is driven by one host thread at a time.
+ */
+typedef struct mis_session mis_session;
+
+typedef struct {
+    void* arena;              /* DEVICE, 256-byte aligned, caller-owned; every per-request
+                                 device byte comes from here (no device allocation) */
+    size_t arena_bytes;
+    int32_t max_live;         /* requests on the device at once, 1..256 */
+    int32_t rounds_per_step;  /* rounds enqueued per request between polls (0 = 4) */
+    mis_build_opts opts;      /* build options of requests admitted without their own */
+} mis_session_config;
+
+typedef struct {
+    uint64_t tag;             /* the caller's tag from mis_session_admit */
+    int32_t status;           /* MIS_OK, or MIS_EINTERNAL if the round bound was exceeded */
+    int32_t rounds;           /* rounds the request took */
+    int64_t n;                /* vertices */
+    int64_t n_in;             /* size of its independent set */
+    double admit_s, done_s;   /* seconds since session creation: admission, retirement */
+} mis_done;
+
+/* Creates a session (streams, events, pinned host mirrors; no device memory). */
+int mis_session_create(const mis_session_config* cfg, mis_session** out);
+
+/*
+ * Admits one request: copies its CSR to the arena if csr_on_host (HOST arrays that
+ * must stay valid until the request retires; pinned memory keeps the copy
+ * asynchronous), builds its solver structure, and enqueues its first rounds.
+ *   opts  : NULL = the session's options (poll_rounds is the session's rounds_per_step)
+ *   d_out : DEVICE uint8[n] for the result, or NULL to place it in the arena
+ *   h_out : HOST uint8[n] that receives the result when the request retires, or NULL
+ *           (at least one of d_out / h_out).
+ * Returns MIS_EBUSY, with nothing enqueued, when no slot or no arena region of the
+ * request's footprint is free (retry after mis_session_progress retires requests),
+ * and MIS_EINVAL when the footprint exceeds the whole arena.  Validation options
+ * (validate = 1, reorder = MIS_REORDER_RCM) synchronise the request's stream.
+ */
+int mis_session_admit(mis_session* s, const mis_csr* csr, int32_t csr_on_host, const mis_build_opts* opts,
+                      uint8_t* d_out, uint8_t* h_out, uint64_t tag);
+
+/*
+ * Advances every live request whose last enqueued work has finished (next rounds,
+ * or output), and retires finished requests into done[0 .. *n_done-1] (HOST, at
+ * most cap), freeing their slot and arena region.  wait = 0 returns at once;
+ * wait = 1 returns once at least one request retired or none is live.
+ */
+int mis_session_progress(mis_session* s, int32_t wait, mis_done* done, int32_t cap, int32_t* n_done);
+
+/* Live requests, arena bytes in use and the largest free arena region (HOST, each optional). */
+int mis_session_query(const mis_session* s, int32_t* live, size_t* bytes_in_use, size_t* largest_free);
+
+/* Waits for the session's device work, then releases it (the arena stays the caller's). */
+void mis_session_destroy(mis_session* s);
 
 /* Releases the handle (host memory only; the workspace stays the caller's). */
 void mis_free_tiles(mis_graph* g);

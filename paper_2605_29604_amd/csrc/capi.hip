@@ -220,6 +220,25 @@ int64_t unit_bytes(const mis_graph* g, int k) {
 }
 
 }  // namespace
+
+int solve_begin(mis_graph* g, hipStream_t s) {
+    hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, s, g->ctrl, g->n);
+    TC_HIP(hipGetLastError());
+    return g->path == MIS_PATH_TILE ? tile_init(g, s) : csr_init(g, s);
+}
+
+int solve_rounds(mis_graph* g, int64_t k, bool allow_graph, hipStream_t s) {
+    if (allow_graph && g->launch != MIS_LAUNCH_DIRECT && k == g->poll_rounds && ensure_graph(g)) {
+        if (hipGraphLaunch(g->graph_exec, s) != hipSuccess) return fail(MIS_EHIP, "hipGraphLaunch failed");
+        return MIS_OK;
+    }
+    return enqueue_batch(g, k, s, nullptr);
+}
+
+int solve_output(mis_graph* g, uint8_t* in_set, hipStream_t s) {
+    return g->path == MIS_PATH_TILE ? tile_output(g, in_set, s) : csr_output(g, in_set, s);
+}
+
 }  // namespace tcmis
 
 using namespace tcmis;
@@ -248,6 +267,7 @@ const char* mis_status_string(int s) {
         case MIS_EDUP: return "duplicate or unsorted adjacency entry";
         case MIS_ERANGE: return "index out of range";
         case MIS_ENOMEM: return "out of device memory";
+        case MIS_EBUSY: return "busy: no free slot or arena region";
         case MIS_EHIP: return "HIP runtime error";
         case MIS_EINTERNAL: return "internal error";
         default: return "unknown status";
@@ -343,9 +363,7 @@ int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, mis_stats* st, 
 
     Staging* sg = nullptr;
     TC_CHECK(staging(&sg));
-    hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, s, g->ctrl, g->n);
-    TC_HIP(hipGetLastError());
-    TC_CHECK(g->path == MIS_PATH_TILE ? tile_init(g, s) : csr_init(g, s));
+    TC_CHECK(solve_begin(g, s));
 
     std::vector<hipEvent_t> ev;
     if (timing) {
@@ -361,12 +379,7 @@ int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, mis_stats* st, 
         for (;;) {
             int64_t k = g->poll_rounds;
             if (max_rounds > 0) k = std::min<int64_t>(k, max_rounds - enq);
-            const bool use_graph = !timing && g->launch != MIS_LAUNCH_DIRECT && k == g->poll_rounds && ensure_graph(g);
-            if (use_graph) {
-                if (hipGraphLaunch(g->graph_exec, s) != hipSuccess) rc = fail(MIS_EHIP, "hipGraphLaunch failed");
-            } else {
-                rc = enqueue_batch(g, k, s, timing ? ev.data() : nullptr);
-            }
+            rc = timing ? enqueue_batch(g, k, s, ev.data()) : solve_rounds(g, k, true, s);
             if (rc != MIS_OK) break;
             // ring slots of rounds drained+1 .. enq
             const int64_t first = drained % kTraceCap, cnt = enq + k - drained;
@@ -410,7 +423,7 @@ int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, mis_stats* st, 
     }
     for (auto& e : ev) (void)hipEventDestroy(e);
     if (rc != MIS_OK) return rc;
-    if (g->n > 0) TC_CHECK(g->path == MIS_PATH_TILE ? tile_output(g, in_set, s) : csr_output(g, in_set, s));
+    if (g->n > 0) TC_CHECK(solve_output(g, in_set, s));
     if (g->n == 0) {   // nothing ran: no staging contents of this graph
         sg->ctrl->round = 0;
         sg->ctrl->n_in = 0;

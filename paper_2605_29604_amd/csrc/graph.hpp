@@ -144,4 +144,12 @@ struct mis_graph {
 namespace tcmis {
 // Assigns every workspace array of g (base == nullptr: only computes the size).
 size_t layout(mis_graph* g, char* base);
+
+// Pieces of the round loop, enqueued on `s` without synchronising it:
+// solve_begin resets the round state, solve_rounds enqueues k more rounds (as the
+// captured hipGraph when k == poll_rounds and graph launch is allowed) and
+// solve_output writes the in/out vector in input ids.
+int solve_begin(mis_graph* g, hipStream_t s);
+int solve_rounds(mis_graph* g, int64_t k, bool allow_graph, hipStream_t s);
+int solve_output(mis_graph* g, uint8_t* in_set, hipStream_t s);
 }  // namespace tcmis

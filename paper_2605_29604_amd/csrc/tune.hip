@@ -15,6 +15,7 @@
 #include <tuple>
 #include <vector>
 
+#include "arena.hpp"
 #include "common.hpp"
 
 namespace tcmis {
@@ -71,8 +72,6 @@ mis_build_opts apply(const mis_build_opts& base, const Candidate& c) {
     o.blocks_per_cu = c.blocks_per_cu;
     return o;
 }
-
-size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 using Bucket = std::tuple<int, int, int, int, int, int, int, int>;
 std::mutex g_mu;

@@ -50,6 +50,8 @@ def _load():
     lib.gg_grid.restype = i64
     lib.gg_grid_edges.argtypes = [i64, i64, i64]
     lib.gg_grid_edges.restype = i64
+    lib.gg_union.argtypes = [i64, p, p, p, p, u64, u64, u64, p, p, i64, p, p]
+    lib.gg_union.restype = i64
     lib.gg_splitmix64.argtypes = [u64, i64, p]
     lib.gg_splitmix64.restype = None
     _lib = lib
@@ -175,8 +177,75 @@ def batch_spec(count: int, seed: int = 1, n_min: int = 500, n_max: int = 200_000
     return out
 
 
+def serve_spec(count: int, seed: int = 1, n_min: int = 1000, n_max: int = 4_000_000):
+    """Request mix of the serving workload: like batch_spec, but the kind is uniform
+    over Erdos-Renyi, R-MAT and 3D grid (draw 2 of the graph's stream, multiply-shift
+    to [0, 3)); a grid request has side round(n^(1/3)), n = side^3 and 1% long-range
+    pairs, so its tuple is ("grid", side^3, grid edges + long-range pairs, seed)."""
+    out = []
+    for g in range(count):
+        sg = int(splitmix64(seed ^ (g + 0x5E4E), 1)[0])
+        d = splitmix64(sg, 3)
+        u1 = (int(d[0]) >> 11) / float(1 << 53)
+        n = int(round(math.exp(math.log(n_min) + u1 * (math.log(n_max) - math.log(n_min)))))
+        kind = ("er", "rmat", "grid")[((int(d[2]) >> 32) * 3) >> 32]
+        if kind == "grid":
+            side = max(2, int(round(n ** (1.0 / 3.0))))
+            mg = grid_edges(side, side, side)
+            out.append(("grid", side ** 3, mg + int(math.floor(0.01 * mg)), sg))
+            continue
+        if kind == "er":
+            deg = 4 + int(((int(d[1]) >> 32) * 29) >> 32)
+        else:
+            deg = 8 + int(((int(d[1]) >> 32) * 17) >> 32)
+        out.append((kind, n, min(int(round(n * deg / 2)), n * (n - 1) // 4), sg))
+    return out
+
+
+def _cube_side(n: int) -> int:
+    side = int(round(n ** (1.0 / 3.0)))
+    while side ** 3 < n:
+        side += 1
+    while side ** 3 > n:
+        side -= 1
+    if side ** 3 != n:
+        raise ValueError(f"grid request size {n} is not a cube")
+    return side
+
+
 def make(kind: str, n: int, m: int, seed: int) -> Graph:
-    return er(n, m, seed) if kind == "er" else rmat(n, m, seed)
+    """One graph of a batch or serving spec tuple (kind, n, m, seed)."""
+    if kind == "er":
+        return er(n, m, seed)
+    if kind == "rmat":
+        return rmat(n, m, seed)
+    side = _cube_side(n)
+    row_ptr, col_idx = _alloc(n, m)
+    _check(_load().gg_grid(side, side, side, m - grid_edges(side, side, side), seed, row_ptr.ctypes.data,
+                           col_idx.ctypes.data), "grid")
+    return Graph(n, row_ptr, col_idx[: 2 * m], f"grid_{side}^3_m{m}_s{seed}")
+
+
+def batch_union(spec, big_edges: int = 1 << 22):
+    """Disjoint union of the graphs of a spec, generated in parallel across graphs;
+    identical to union([make(*s) for s in spec]).  Returns (row_ptr, col_idx, offsets)."""
+    count = len(spec)
+    kinds = np.array([{"er": 1, "rmat": 2, "grid": 3}[s[0]] for s in spec], dtype=np.int32)
+    a = np.array([s[1] if s[0] != "grid" else _cube_side(s[1]) for s in spec], dtype=np.int64)
+    b = np.array([s[2] if s[0] != "grid" else s[2] - grid_edges(*(3 * [_cube_side(s[1])])) for s in spec],
+                 dtype=np.int64)
+    seeds = np.array([s[3] for s in spec], dtype=np.uint64)
+    voff = np.zeros(count + 1, dtype=np.int64)
+    eoff = np.zeros(count + 1, dtype=np.int64)
+    voff[1:] = np.cumsum([s[1] for s in spec])
+    eoff[1:] = np.cumsum([2 * s[2] for s in spec])
+    row_ptr = np.zeros(int(voff[-1]) + 1, dtype=np.int64)
+    col_idx = np.zeros(max(int(eoff[-1]), 1), dtype=np.int32)
+    a32, b32, c32 = (int(math.floor(x * 2**32)) for x in RMAT_ABC)
+    _check(_load().gg_union(count, kinds.ctypes.data, a.ctypes.data, b.ctypes.data, seeds.ctypes.data,
+                            a32, b32, c32, voff.ctypes.data, eoff.ctypes.data, big_edges,
+                            row_ptr.ctypes.data, col_idx.ctypes.data), "batch")
+    return row_ptr, col_idx[: int(eoff[-1])], voff
 
 
 def union(graphs):

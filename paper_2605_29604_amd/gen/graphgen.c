@@ -81,7 +81,11 @@ static void* gg_worker(void* arg) {
     return NULL;
 }
 
+/* worker threads of a batch generate each of their graphs with one thread */
+static __thread int gg_single_thread = 0;
+
 static int gg_threads(void) {
+    if (gg_single_thread) return 1;
     const char* env = getenv("GG_THREADS");
     if (env && atoi(env) > 0) return atoi(env);
     cpu_set_t set;
@@ -203,24 +207,28 @@ typedef struct {
     const gg_family* f;
     uint64_t first;      /* candidate index of slot 0 */
     uint64_t* key;       /* [count] candidate keys */
+    uint8_t* pid;        /* [count] hash partition of the key, GG_NPART = rejected */
     uint8_t* fresh;      /* [count] 1 = first occurrence */
+    uint32_t* order;     /* [count] candidate indices grouped by partition, draw order inside */
+    int64_t start[GG_NPART + 1];
     gg_set* part;        /* [GG_NPART] */
     int err;
-} gg_batch;
+} gg_draws;
 
-static void gg_batch_gen(void* c, int64_t b, int64_t e) {
-    gg_batch* B = (gg_batch*)c;
-    for (int64_t i = b; i < e; ++i) B->key[i] = gg_candidate(B->f, B->first + (uint64_t)i);
+static void gg_draws_gen(void* c, int64_t b, int64_t e) {
+    gg_draws* B = (gg_draws*)c;
+    for (int64_t i = b; i < e; ++i) {
+        const uint64_t k = gg_candidate(B->f, B->first + (uint64_t)i);
+        B->key[i] = k;
+        B->pid[i] = (uint8_t)(k == GG_REJECT ? GG_NPART : gg_part(k));
+    }
 }
-typedef struct { gg_batch* B; int64_t count; } gg_dedup_ctx;
-static void gg_batch_dedup(void* c, int64_t b, int64_t e) {
-    gg_dedup_ctx* D = (gg_dedup_ctx*)c;
-    gg_batch* B = D->B;
+static void gg_draws_dedup(void* c, int64_t b, int64_t e) {
+    gg_draws* B = (gg_draws*)c;
     for (int64_t p = b; p < e; ++p) {
-        for (int64_t i = 0; i < D->count; ++i) {
-            uint64_t k = B->key[i];
-            if (k == GG_REJECT || gg_part(k) != p) continue;
-            int r = gg_set_insert(&B->part[p], k);
+        for (int64_t j = B->start[p]; j < B->start[p + 1]; ++j) {
+            const uint32_t i = B->order[j];
+            int r = gg_set_insert(&B->part[p], B->key[i]);
             if (r < 0) { B->err = -2; return; }
             B->fresh[i] = (uint8_t)r;
         }
@@ -235,14 +243,28 @@ static int gg_draw_edges(const gg_family* f, int64_t m, uint32_t* eu, uint32_t* 
     while (k < m) {
         int64_t want = m - k;
         int64_t count = want + want / 4 + 4096;
-        gg_batch B = { f, next, NULL, NULL, part, 0 };
+        gg_draws B;
+        memset(&B, 0, sizeof B);
+        B.f = f; B.first = next; B.part = part;
         B.key = (uint64_t*)malloc((size_t)count * 8);
+        B.pid = (uint8_t*)malloc((size_t)count);
         B.fresh = (uint8_t*)calloc((size_t)count, 1);
-        if (!B.key || !B.fresh) { free(B.key); free(B.fresh); return -2; }
-        gg_parallel(gg_batch_gen, &B, count, 1 << 16);
-        gg_dedup_ctx D = { &B, count };
-        gg_parallel(gg_batch_dedup, &D, GG_NPART, 1);
-        if (B.err) { free(B.key); free(B.fresh); return B.err; }
+        B.order = (uint32_t*)malloc((size_t)count * 4);
+        if (!B.key || !B.pid || !B.fresh || !B.order) {
+            free(B.key); free(B.pid); free(B.fresh); free(B.order);
+            return -2;
+        }
+        gg_parallel(gg_draws_gen, &B, count, 1 << 16);
+        /* group candidate indices by partition, keeping draw order inside each */
+        int64_t cnt[GG_NPART + 1] = {0};
+        for (int64_t i = 0; i < count; ++i) cnt[B.pid[i]]++;
+        int64_t fill[GG_NPART];
+        B.start[0] = 0;
+        for (int p = 0; p < GG_NPART; ++p) { fill[p] = B.start[p]; B.start[p + 1] = B.start[p] + cnt[p]; }
+        for (int64_t i = 0; i < count; ++i)
+            if (B.pid[i] < GG_NPART) B.order[fill[B.pid[i]]++] = (uint32_t)i;
+        gg_parallel(gg_draws_dedup, &B, GG_NPART, 1);
+        if (B.err) { free(B.key); free(B.pid); free(B.fresh); free(B.order); return B.err; }
         for (int64_t i = 0; i < count && k < m; ++i) {
             if (!B.fresh[i]) continue;
             eu[k] = (uint32_t)(B.key[i] >> 32);
@@ -250,7 +272,7 @@ static int gg_draw_edges(const gg_family* f, int64_t m, uint32_t* eu, uint32_t* 
             ++k;
         }
         next += (uint64_t)count;
-        free(B.key); free(B.fresh);
+        free(B.key); free(B.pid); free(B.fresh); free(B.order);
     }
     *k_out = k;
     return 0;
@@ -440,6 +462,78 @@ int64_t gg_grid(int64_t sx, int64_t sy, int64_t sz, int64_t n_long, uint64_t see
     if (!rc) rc = gg_csr(n, m, eu, ev, row_ptr, col_idx);
     free(eu); free(ev);
     return rc ? rc : m;
+}
+
+/* ------------------------------------------------ batches of graphs
+ * Disjoint union of `count` graphs, graph g of kind[g] (1 = Erdos-Renyi G(a, b),
+ * 2 = R-MAT with n = a, m = b, the given quadrant thresholds and relabelling,
+ * 3 = grid a x a x a with b long-range pairs) and seed[g].  voff (count+1) and eoff
+ * (count+1, directed entries) are the caller's prefix sums of the vertex counts
+ * and of 2 * edges; graph g fills row_ptr[voff[g] .. voff[g+1]-1] and
+ * col_idx[eoff[g] .. eoff[g+1]-1] with ids shifted by voff[g], exactly as if it
+ * were generated alone and appended.  Graphs with at least `big` edges are made
+ * one at a time with every thread; the rest in parallel, one thread each. */
+typedef struct {
+    const int32_t* kind; const int64_t* a; const int64_t* b; const uint64_t* seed;
+    const int64_t* voff; const int64_t* eoff; uint64_t t1, t2, t3;
+    int64_t* row_ptr; int32_t* col_idx; int64_t big; int small_pass; int rc;
+    pthread_mutex_t mu;
+} gg_batch_ctx;
+
+static int gg_batch_one(gg_batch_ctx* B, int64_t g) {
+    const int64_t n = B->voff[g + 1] - B->voff[g], e0 = B->eoff[g];
+    int64_t* rp = (int64_t*)malloc((size_t)(n + 1) * 8);
+    if (!rp) return -2;
+    int32_t* ci = B->col_idx + e0;
+    int64_t m;
+    switch (B->kind[g]) {
+        case 1: m = gg_er(B->a[g], B->b[g], B->seed[g], rp, ci); break;
+        case 2: m = gg_rmat(B->a[g], B->b[g], B->t1, B->t2 - B->t1, B->t3 - B->t2, 1, B->seed[g], rp, ci); break;
+        case 3: m = gg_grid(B->a[g], B->a[g], B->a[g], B->b[g], B->seed[g], rp, ci); break;
+        default: m = -1;
+    }
+    int rc = 0;
+    if (m < 0) rc = (int)m;
+    else if (2 * m != B->eoff[g + 1] - e0 || rp[n] != 2 * m) rc = -1;
+    else {
+        const int32_t o = (int32_t)B->voff[g];
+        for (int64_t k = 0; k < 2 * m; ++k) ci[k] += o;
+        for (int64_t v = 0; v < n; ++v) B->row_ptr[B->voff[g] + v] = e0 + rp[v];
+    }
+    free(rp);
+    return rc;
+}
+
+static void gg_batch_body(void* c, int64_t b, int64_t e) {
+    gg_batch_ctx* B = (gg_batch_ctx*)c;
+    gg_single_thread = 1;
+    for (int64_t g = b; g < e; ++g) {
+        if (B->eoff[g + 1] - B->eoff[g] >= 2 * B->big) continue;
+        int rc = gg_batch_one(B, g);
+        if (rc) { pthread_mutex_lock(&B->mu); B->rc = rc; pthread_mutex_unlock(&B->mu); }
+    }
+    gg_single_thread = 0;
+}
+
+int64_t gg_union(int64_t count, const int32_t* kind, const int64_t* a, const int64_t* b, const uint64_t* seed,
+                 uint64_t a32, uint64_t b32, uint64_t c32, const int64_t* voff, const int64_t* eoff,
+                 int64_t big, int64_t* row_ptr, int32_t* col_idx) {
+    if (count < 0 || !kind || !a || !b || !seed || !voff || !eoff || !row_ptr) return -1;
+    if (a32 + b32 + c32 > (1ull << 32) || voff[count] > 0x7fffffff) return -1;
+    if (eoff[count] > 0 && !col_idx) return -1;
+    gg_batch_ctx B;
+    memset(&B, 0, sizeof B);
+    B.kind = kind; B.a = a; B.b = b; B.seed = seed; B.voff = voff; B.eoff = eoff;
+    B.t1 = a32; B.t2 = a32 + b32; B.t3 = a32 + b32 + c32;
+    B.row_ptr = row_ptr; B.col_idx = col_idx; B.big = big;
+    pthread_mutex_init(&B.mu, NULL);
+    for (int64_t g = 0; g < count && !B.rc; ++g)
+        if (eoff[g + 1] - eoff[g] >= 2 * big) B.rc = gg_batch_one(&B, g);
+    if (!B.rc) gg_parallel(gg_batch_body, &B, count, 1);
+    pthread_mutex_destroy(&B.mu);
+    if (B.rc) return B.rc;
+    row_ptr[voff[count]] = eoff[count];
+    return eoff[count] / 2;
 }
 
 /* raw SplitMix64 stream: outputs 1..count of the stream seeded with seed */

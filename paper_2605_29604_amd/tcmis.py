@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtcmis.so")
 
 MIS_OK, MIS_EINVAL, MIS_ENOTSYM, MIS_ESELFLOOP, MIS_EDUP, MIS_ERANGE = 0, -1, -2, -3, -4, -5
-MIS_ENOMEM, MIS_EHIP, MIS_EINTERNAL = -6, -8, -9
+MIS_ENOMEM, MIS_EBUSY, MIS_EHIP, MIS_EINTERNAL = -6, -7, -8, -9
 PATH_AUTO, PATH_TILE, PATH_CSR = 0, 1, 2
 REORDER_AUTO, REORDER_NONE, REORDER_DEGREE, REORDER_KEY, REORDER_RCM = 0, 1, 2, 3, 4
 
@@ -28,7 +28,8 @@ REORDERS = {"auto": REORDER_AUTO, "none": REORDER_NONE, "degree": REORDER_DEGREE
 # symbols declared in include/tcmis.h
 EXPORTS = ["mis_default_opts", "mis_build_bytes", "mis_build_tiles", "mis_build_batch_bytes", "mis_build_batch",
            "mis_graph_bytes", "mis_solve", "mis_solve_batch", "mis_free_tiles", "mis_status_string", "mis_last_error",
-           "mis_version", "mis_autotune_bytes", "mis_autotune", "mis_autotune_clear"]
+           "mis_version", "mis_autotune_bytes", "mis_autotune", "mis_autotune_clear", "mis_session_create",
+           "mis_session_admit", "mis_session_progress", "mis_session_query", "mis_session_destroy"]
 
 
 class MisCsr(ctypes.Structure):
@@ -51,6 +52,17 @@ class MisStats(ctypes.Structure):
                 ("kernel_ms", ctypes.c_float * 2), ("launches", ctypes.c_int32),
                 ("trace_cap", ctypes.c_int32), ("graph", ctypes.c_int32), ("pad3_", ctypes.c_int32),
                 ("trace", ctypes.POINTER(ctypes.c_int64))]
+
+
+class MisSessionConfig(ctypes.Structure):
+    _fields_ = [("arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t), ("max_live", ctypes.c_int32),
+                ("rounds_per_step", ctypes.c_int32), ("opts", MisBuildOpts)]
+
+
+class MisDone(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32), ("rounds", ctypes.c_int32),
+                ("n", ctypes.c_int64), ("n_in", ctypes.c_int64), ("admit_s", ctypes.c_double),
+                ("done_s", ctypes.c_double)]
 
 
 class MisError(RuntimeError):
@@ -102,6 +114,18 @@ def lib():
     L.mis_autotune.restype = ctypes.c_int
     L.mis_autotune_clear.argtypes = []
     L.mis_autotune_clear.restype = None
+    L.mis_session_create.argtypes = [ctypes.POINTER(MisSessionConfig), ctypes.POINTER(vp)]
+    L.mis_session_create.restype = ctypes.c_int
+    L.mis_session_admit.argtypes = [vp, ctypes.POINTER(MisCsr), i32, ctypes.POINTER(MisBuildOpts), vp, vp,
+                                    ctypes.c_uint64]
+    L.mis_session_admit.restype = ctypes.c_int
+    L.mis_session_progress.argtypes = [vp, i32, ctypes.POINTER(MisDone), i32, ctypes.POINTER(ctypes.c_int32)]
+    L.mis_session_progress.restype = ctypes.c_int
+    L.mis_session_query.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_size_t),
+                                    ctypes.POINTER(ctypes.c_size_t)]
+    L.mis_session_query.restype = ctypes.c_int
+    L.mis_session_destroy.argtypes = [vp]
+    L.mis_session_destroy.restype = None
     L.mis_free_tiles.argtypes = [vp]
     L.mis_free_tiles.restype = None
     L.mis_status_string.argtypes = [ctypes.c_int]
@@ -334,6 +358,91 @@ def mis_free_tiles(g: MisGraph):
     if g.handle:
         lib().mis_free_tiles(g.handle)
         g.handle = None
+
+
+class Session:
+    """Serving session over a device arena (a torch uint8 tensor it allocates or is given).
+
+    admit() takes a request's CSR as HOST numpy / pinned torch arrays (copied to the
+    arena by the library) or cuda tensors, and returns False when the session is busy
+    (no slot or arena region free).  progress() returns the retired requests as dicts.
+    The session keeps every request's host/device arrays alive until it retires.
+    """
+
+    def __init__(self, arena_bytes=None, max_live=8, rounds_per_step=4, arena=None, path="auto", tile=0,
+                 reorder="auto", orient=-1, seed=1, launch="direct", blocks_per_cu=0):
+        import torch
+        if arena is None:
+            arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device="cuda")
+        self.arena = arena
+        cfg = MisSessionConfig()
+        cfg.arena = _ptr(arena)
+        cfg.arena_bytes = arena.numel()
+        cfg.max_live = int(max_live)
+        cfg.rounds_per_step = int(rounds_per_step)
+        cfg.opts = _opts(path, tile, reorder, orient, False, seed, None, 0, launch, blocks_per_cu)
+        h = ctypes.c_void_p(None)
+        _check(lib().mis_session_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h
+        self.cap = int(max_live)
+        self._keep = {}
+        self._buf = (MisDone * self.cap)()
+
+    def admit(self, row_ptr, col_idx, tag, out=None, host_out=None, opts=None) -> bool:
+        """row_ptr/col_idx: both host (numpy or torch cpu, pinned preferred) or both cuda.
+        out: cuda uint8[n] or None; host_out: host uint8[n] (numpy / torch cpu) or None."""
+        import torch
+        on_host = not (isinstance(row_ptr, torch.Tensor) and row_ptr.is_cuda)
+        n = (row_ptr.numel() if isinstance(row_ptr, torch.Tensor) else row_ptr.size) - 1
+        nnz = col_idx.numel() if isinstance(col_idx, torch.Tensor) else col_idx.size
+        csr = MisCsr(n, nnz, _host_or_dev_ptr(row_ptr), _host_or_dev_ptr(col_idx) if nnz else None)
+        o = None if opts is None else ctypes.byref(_opts(**opts))
+        rc = lib().mis_session_admit(self.handle, ctypes.byref(csr), int(on_host), o,
+                                     _host_or_dev_ptr(out) if out is not None else None,
+                                     _host_or_dev_ptr(host_out) if host_out is not None else None,
+                                     ctypes.c_uint64(int(tag)))
+        if rc == MIS_EBUSY:
+            return False
+        _check(rc)
+        self._keep[int(tag)] = (row_ptr, col_idx, out, host_out, opts)
+        return True
+
+    def progress(self, wait=False):
+        nd = ctypes.c_int32(0)
+        _check(lib().mis_session_progress(self.handle, int(bool(wait)), self._buf, self.cap, ctypes.byref(nd)))
+        res = []
+        for i in range(nd.value):
+            d = self._buf[i]
+            res.append(dict(tag=int(d.tag), status=d.status, rounds=d.rounds, n=d.n, n_in=d.n_in,
+                            admit_s=d.admit_s, done_s=d.done_s))
+            self._keep.pop(int(d.tag), None)
+        return res
+
+    def query(self):
+        live = ctypes.c_int32(0)
+        used = ctypes.c_size_t(0)
+        big = ctypes.c_size_t(0)
+        _check(lib().mis_session_query(self.handle, ctypes.byref(live), ctypes.byref(used), ctypes.byref(big)))
+        return live.value, used.value, big.value
+
+    def close(self):
+        if self.handle:
+            lib().mis_session_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _host_or_dev_ptr(a):
+    import torch
+    if isinstance(a, torch.Tensor):
+        return ctypes.c_void_p(a.data_ptr())
+    return ctypes.c_void_p(a.ctypes.data)
 
 
 def version() -> str:

@@ -123,3 +123,28 @@ def test_union():
         for v in range(g.n):
             a = ci[rp[o + v]:rp[o + v + 1]] - o
             assert np.array_equal(a, g.col_idx[g.row_ptr[v]:g.row_ptr[v + 1]])
+
+
+def test_serve_spec_and_grid_requests():
+    sp = gen.serve_spec(600, 1)
+    assert sp == gen.serve_spec(600, 1)
+    kinds = [s[0] for s in sp]
+    assert all(150 < kinds.count(k) < 250 for k in ("er", "rmat", "grid"))
+    for kind, n, m, sd in sp:
+        assert 900 <= n <= 4_100_000
+        if kind == "grid":
+            side = round(n ** (1 / 3))
+            assert side ** 3 == n and m == gen.grid_edges(side, side, side) * 101 // 100
+    g = gen.make("grid", 8 ** 3, gen.grid_edges(8, 8, 8) + 3, 5)
+    check_simple(g)
+    assert g.m == gen.grid_edges(8, 8, 8) + 3
+
+
+def test_batch_union_equals_union_of_makes():
+    spec = gen.batch_spec(40, seed=3, n_min=50, n_max=20000) + gen.serve_spec(12, seed=4, n_min=100, n_max=40000)
+    spec.insert(5, ("er", 0, 0, 9))
+    spec.insert(9, ("er", 1, 0, 9))
+    # small threshold: the large graphs go through the one-at-a-time multithreaded pass
+    rp, ci, off = gen.batch_union(spec, big_edges=20000)
+    rp2, ci2, off2 = gen.union([gen.make(*s) for s in spec])
+    assert np.array_equal(off, off2) and np.array_equal(rp, rp2) and np.array_equal(ci, ci2)
