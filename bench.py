@@ -250,8 +250,8 @@ def bench_serve(a, torch, gen, tcmis):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); multi-GPU sharding is a design "
-              "note, not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the solver does not shard a graph "
+              "or a batch across GPUs", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2605_29604_amd import gen, tcmis
@@ -348,15 +348,12 @@ def main():
         "tile_equals_csr": same,
     }
     # roofline of the dominant round kernel (HIP events on the solve stream)
-    names = ["tile_candidate", "tile_exclusion_mfma"]
+    names = ["tile_candidate", "tile_exclusion_mfma", "tile_finalize"]
     k = int(np.argmax(stt["kernel_ms"]))
     launches = max(1, stt["launches"])
-    units = stt["units"]
+    u = stt["units"]
     S = a.tile * a.tile // 8
-    if k == 0:
-        bytes_k = units[0] * (S + 8) + units[1] * 8
-    else:
-        bytes_k = units[2] * 12 + units[3] * S
+    bytes_k = [u[0] * 4 + u[1], u[2] * 4 + u[3] * S, u[4] * 24 + u[5] * 8][k]
     avg_ms = stt["kernel_ms"][k] / launches
     achieved = (bytes_k / launches) / (avg_ms * 1e-3) / 1e9
     res["roofline"] = {"kernel": names[k], "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,

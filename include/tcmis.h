@@ -109,16 +109,20 @@ typedef struct {
     int64_t tiles;            /* nonzero tiles (0 on the CSR path) */
     int64_t tile_bytes;       /* bytes of the tile stream: tiles * (T*T/8 bitmap + 4 index) */
     int64_t alg_bytes;        /* algorithmic bytes: sum over rounds of units[k] * bytes per unit */
-    int64_t units[4];         /* work units summed over rounds.  CSR path: adjacency entries read
+    int64_t units[6];         /* work units summed over rounds.  CSR path: adjacency entries read
                                  by the candidate kernel (12 B each: index + neighbour key),
                                  vertices it examined (28 B), entries read by the exclusion
                                  kernel (8 B: index + neighbour state), vertices it examined
-                                 (24 B).  Tile path: tiles read by the candidate kernel
-                                 (T*T/8 + 8 B), neighbour keys it staged (8 B), tiles whose
-                                 candidate segment the exclusion kernel examined (12 B), tiles
-                                 it multiplied on the matrix cores (T*T/8 B). */
-    float kernel_ms[2];       /* timing = 1: total ms of the candidate / exclusion kernels */
-    int32_t launches;         /* timing = 1: rounds enqueued (each launches both kernels) */
+                                 (24 B), units[4] = units[5] = 0.  Tile path: 4-byte index and
+                                 row-mask words the candidate kernel read (4 B), bytes of
+                                 bitmaps and neighbour keys it read (1 B), 4-byte words the
+                                 exclusion kernel read (4 B), tiles it multiplied on the matrix
+                                 cores (T*T/8 B), row-blocks the finalize kernel updated (24 B:
+                                 three row masks read and written), chunk list entries it
+                                 wrote (8 B). */
+    float kernel_ms[3];       /* timing = 1: total ms of the candidate / exclusion / finalize
+                                 kernels (the CSR path has no finalize kernel) */
+    int32_t launches;         /* timing = 1: rounds enqueued (each launches every kernel once) */
     int32_t trace_cap;        /* in: rounds the trace buffer holds (0 = no trace) */
     int32_t graph;            /* 1 if full batches of rounds ran as a replayed hipGraph */
     int32_t pad3_;

@@ -15,8 +15,8 @@
 //      symmetric, and the kept orientation is transposed on purpose), is exactly
 //      the tile order (row block, column block) with each tile's entries contiguous;
 //   4. tile heads by a scan of head flags; one lane per tile (four for T=32) ORs its
-//      entries into registers and stores the bitmap; row-block pointers by binary
-//      search; work segments of at most kSegTiles tiles per row-block.
+//      entries into registers, stores the bitmap and ORs the tile's nonempty rows
+//      into its row-block's mask; row-block pointers by binary search.
 #include <algorithm>
 #include <vector>
 
@@ -98,10 +98,6 @@ __global__ void k_keys(const int64_t* rp, int64_t n, uint64_t seed, const int64_
     }
 }
 
-__global__ void k_iota_i32(int32_t* out, int64_t n) {
-    GRID_STRIDE(i, n) out[i] = (int32_t)i;
-}
-
 __global__ void k_identity_order(int32_t* order, int32_t* new_id, int64_t n) {
     GRID_STRIDE(v, n) { order[v] = (int32_t)v; new_id[v] = (int32_t)v; }
 }
@@ -146,13 +142,16 @@ __global__ void k_new_degrees(const int64_t* rp, const int32_t* order, int64_t n
     }
 }
 
-template <int kTshift, int kMode>   // kMode: 0 all entries, 1 lower-key by id (priority order), 2 lower-key by key
-__device__ inline bool make_entry(int32_t p, int32_t u, uint64_t kv, const int32_t* new_id, const uint64_t* key,
-                                  uint64_t* out) {
-    const int32_t q = new_id[u];
+// kMode: 0 all entries, 1 entries whose column has a lower priority, by new id (the
+// priority order), 2 the same by key.  Entry = block(q) << 36 | p << 5 | q mod T for
+// new row p and new column q: read transposed (row q, column p) after a stable sort
+// on block(q), the kept entries are each lower-priority vertex's higher-priority
+// neighbours, in tile order.
+template <int kTshift, int kMode>
+__device__ inline bool make_entry(int32_t p, int32_t q, uint64_t kv, uint64_t ku, uint64_t* out) {
     bool keep = true;
     if (kMode == 1) keep = q > p;
-    if (kMode == 2) keep = key[u] < kv;
+    if (kMode == 2) keep = ku < kv;
     *out = ((uint64_t)(q >> kTshift) << 36) | ((uint64_t)p << 5) | (uint64_t)(q & ((1 << kTshift) - 1));
     return keep;
 }
@@ -180,14 +179,16 @@ __global__ void k_block_rows(const int32_t* nrp, int64_t n, int64_t nnz, int64_t
 
 // One candidate entry per adjacency entry in new-row order, coalesced over entries;
 // the rows of the workgroup's range are looked up in an LDS copy of the new row
-// pointer.  Kept entries are compacted to the front of the workgroup's 4096-slot
-// range (order preserved) and their number goes to cnt[block].
+// pointer.  Every thread first issues the column reads and the new-id (and key)
+// gathers of all its kEntIters entries, so they are in flight together; the kept
+// entries are then compacted to the front of the workgroup's range (order
+// preserved) and their number goes to cnt[block].
 template <int kTshift, int kMode>
 __global__ void __launch_bounds__(kBlock) k_entries(const int64_t* rp, const int32_t* ci, const int32_t* order,
                                                     const int32_t* nrp, const int32_t* brow, const int32_t* new_id,
                                                     const uint64_t* key, int64_t nnz, uint64_t* ent, int32_t* cnt) {
     __shared__ int32_t win[kEntWindow];
-    __shared__ int32_t wcnt[kBlock / kWave];
+    __shared__ int32_t wcnt[kEntIters][kBlock / kWave];
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     const int64_t base = (int64_t)blockIdx.x * kEntBlock;
     const int64_t p0 = brow[blockIdx.x], p1 = brow[blockIdx.x + 1];
@@ -196,11 +197,14 @@ __global__ void __launch_bounds__(kBlock) k_entries(const int64_t* rp, const int
     if (in_lds)
         for (int64_t i = threadIdx.x; i < w; i += kBlock) win[i] = nrp[p0 + i];
     __syncthreads();
-    int written = 0;   // kept entries of earlier iterations (block-uniform)
+    int32_t pr[kEntIters], qv[kEntIters];
+    uint64_t kv[kEntIters], ku[kEntIters];
+    #pragma unroll
     for (int it = 0; it < kEntIters; ++it) {
         const int64_t e = base + (int64_t)it * kBlock + threadIdx.x;
-        bool keep = false;
-        uint64_t x = 0;
+        pr[it] = -1;
+        qv[it] = 0;
+        kv[it] = ku[it] = 0;
         if (e < nnz) {
             int32_t p;
             if (in_lds) {
@@ -215,20 +219,39 @@ __global__ void __launch_bounds__(kBlock) k_entries(const int64_t* rp, const int
             }
             const int32_t v = order[p];
             const int64_t off = e - (in_lds ? win[p - p0] : nrp[p]);
-            const uint64_t kv = kMode == 2 ? key[v] : 0;
-            keep = make_entry<kTshift, kMode>(p, ci[rp[v] + off], kv, new_id, key, &x);
+            const int32_t u = ci[rp[v] + off];
+            pr[it] = p;
+            qv[it] = new_id[u];
+            if (kMode == 2) {
+                kv[it] = key[v];
+                ku[it] = key[u];
+            }
         }
-        const uint64_t b = ballot(keep);
-        if (lane == 0) wcnt[wid] = __popcll(b);
-        __syncthreads();
+    }
+    uint64_t kept = 0;   // bit it: entry it is kept
+    uint64_t x[kEntIters];
+    #pragma unroll
+    for (int it = 0; it < kEntIters; ++it) {
+        x[it] = 0;
+        if (pr[it] >= 0 && make_entry<kTshift, kMode>(pr[it], qv[it], kv[it], ku[it], &x[it])) kept |= 1ull << it;
+    }
+    #pragma unroll
+    for (int it = 0; it < kEntIters; ++it) {
+        const uint64_t b = ballot((kept >> it) & 1);
+        if (lane == 0) wcnt[it][wid] = __popcll(b);
+    }
+    __syncthreads();
+    int written = 0;
+    #pragma unroll
+    for (int it = 0; it < kEntIters; ++it) {
         int before = written, total = written;
         for (int q = 0; q < kBlock / kWave; ++q) {
-            if (q < wid) before += wcnt[q];
-            total += wcnt[q];
+            if (q < wid) before += wcnt[it][q];
+            total += wcnt[it][q];
         }
-        if (keep) ent[base + before + __popcll(b & lanes_below())] = x;
+        const uint64_t b = ballot((kept >> it) & 1);
+        if ((kept >> it) & 1) ent[base + before + __popcll(b & lanes_below())] = x[it];
         written = total;
-        __syncthreads();
     }
     if (threadIdx.x == 0) cnt[blockIdx.x] = written;
 }
@@ -300,36 +323,55 @@ __global__ void __launch_bounds__(kBlock) k_head_write(const uint64_t* ent, cons
 }
 
 // one lane per tile (T=16) or per quarter tile (T=32, rows 8k..8k+7): OR the
-// tile's entries into 8 registers and store them
+// tile's entries into 8 registers, store them, and OR the rows that have an entry
+// into hrows of the tile's row-block (lanes of one row-block combine first)
 template <int T>
-__global__ void k_tile_bits(const uint64_t* ent, const int32_t* tile_start, const Meta* meta, int64_t cap,
-                            uint32_t* bits) {
+__global__ void k_tile_bits(const uint64_t* ent, const int32_t* tile_start, const int32_t* tile_row, const Meta* meta,
+                            int64_t cap, uint32_t* bits, uint32_t* hrows) {
     constexpr int L = T == 16 ? 1 : 4;
     const int64_t nt = meta->ntiles;
-    GRID_STRIDE(gid, cap * L) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // wave-uniform trip count: every lane reaches the combine step of every pass
+    for (int64_t base = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~(kWave - 1)); base < cap * L;
+         base += stride) {
+        const int64_t gid = base + lane_id();
         const int64_t t = gid / L;
-        if (t >= nt) break;
         const int k = (int)(gid % L);
-        const int64_t e0 = tile_start[t];
-        const int64_t e1 = t + 1 < nt ? tile_start[t + 1] : meta->nvalid;
-        uint32_t w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        for (int64_t e = e0; e < e1; ++e) {
-            const uint64_t x = ent[e];
-            const uint32_t r = (uint32_t)(x & (T - 1));
-            const uint32_t c = (uint32_t)((x >> 5) & (T - 1));
-            if (T == 16) {
-                const uint32_t word = r >> 1, bit = 1u << (((r & 1) << 4) | c);
-                #pragma unroll
-                for (int j = 0; j < 8; ++j) w[j] |= word == (uint32_t)j ? bit : 0u;
-            } else {
-                if ((int)(r >> 3) != k) continue;
-                #pragma unroll
-                for (int j = 0; j < 8; ++j) w[j] |= (r & 7) == (uint32_t)j ? (1u << c) : 0u;
+        int32_t I = -1;
+        uint32_t rm = 0;
+        if (gid < cap * L && t < nt) {
+            const int64_t e0 = tile_start[t];
+            const int64_t e1 = t + 1 < nt ? tile_start[t + 1] : meta->nvalid;
+            uint32_t w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            for (int64_t e = e0; e < e1; ++e) {
+                const uint64_t x = ent[e];
+                const uint32_t r = (uint32_t)(x & (T - 1));
+                const uint32_t c = (uint32_t)((x >> 5) & (T - 1));
+                if (T == 16) {
+                    const uint32_t word = r >> 1, bit = 1u << (((r & 1) << 4) | c);
+                    #pragma unroll
+                    for (int j = 0; j < 8; ++j) w[j] |= word == (uint32_t)j ? bit : 0u;
+                } else {
+                    if ((int)(r >> 3) != k) continue;
+                    #pragma unroll
+                    for (int j = 0; j < 8; ++j) w[j] |= (r & 7) == (uint32_t)j ? (1u << c) : 0u;
+                }
             }
+            uint4* dst = (uint4*)(bits + t * (T * T / 32) + 8 * k);
+            dst[0] = make_uint4(w[0], w[1], w[2], w[3]);
+            dst[1] = make_uint4(w[4], w[5], w[6], w[7]);
+            #pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (T == 16) {
+                    rm |= (uint32_t)((w[j] & 0xFFFFu) != 0) << (2 * j);
+                    rm |= (uint32_t)((w[j] >> 16) != 0) << (2 * j + 1);
+                } else {
+                    rm |= (uint32_t)(w[j] != 0) << (8 * k + j);
+                }
+            }
+            I = tile_row[t];
         }
-        uint4* dst = (uint4*)(bits + t * (T * T / 32) + 8 * k);
-        dst[0] = make_uint4(w[0], w[1], w[2], w[3]);
-        dst[1] = make_uint4(w[4], w[5], w[6], w[7]);
+        run_or(I, rm, hrows);
     }
 }
 
@@ -345,32 +387,28 @@ __global__ void k_rb_ptr(const int32_t* tile_row, const Meta* meta, int64_t nI, 
     }
 }
 
-__global__ void k_seg_count(const int64_t* rb_ptr, int64_t nI, int64_t* cnt) {
-    GRID_STRIDE(I, nI) {
-        const int64_t t = rb_ptr[I + 1] - rb_ptr[I];
-        const int64_t s = (t + kSegTiles - 1) / kSegTiles;
-        cnt[I] = s < 1 ? 1 : s;
+// chunks of each row-block (at most tpi tiles each)
+__global__ void k_chunk_count(const int64_t* rb_ptr, int64_t nI, int tpi, int64_t* cnt) {
+    GRID_STRIDE(I, nI) cnt[I] = (rb_ptr[I + 1] - rb_ptr[I] + tpi - 1) / tpi;
+}
+
+// chunk q belongs to the last row-block whose first chunk is <= q
+__global__ void k_chunk_fill(const int64_t* first, const int64_t* rb_ptr, const Meta* meta, int64_t nI, int tpi,
+                             int64_t cap, uint64_t* out) {
+    const int64_t total = meta->nchunks;
+    GRID_STRIDE(q, cap) {
+        if (q >= total) break;
+        int64_t lo = 0, hi = nI - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (first[mid] <= q) lo = mid; else hi = mid - 1;
+        }
+        const int64_t t0 = rb_ptr[lo] + (q - first[lo]) * tpi;
+        out[q] = chunk_word(t0, min((int64_t)tpi, rb_ptr[lo + 1] - t0), lo);
     }
 }
 
-__global__ void k_seg_fill(const int64_t* rb_ptr, const int64_t* seg0, int64_t nI, int64_t n, int tile,
-                           int32_t* seg_rb, int64_t* seg_t0, int64_t* seg_t1, int32_t* rb_seg0, int32_t* rb_nseg,
-                           uint32_t* alive0) {
-    GRID_STRIDE(I, nI) {
-        const int64_t a = rb_ptr[I], b = rb_ptr[I + 1];
-        const int64_t s0 = seg0[I];
-        const int64_t ns = b - a > 0 ? (b - a + kSegTiles - 1) / kSegTiles : 1;
-        rb_seg0[I] = (int32_t)s0;
-        rb_nseg[I] = (int32_t)ns;
-        for (int64_t k = 0; k < ns; ++k) {
-            seg_rb[s0 + k] = (int32_t)I;
-            seg_t0[s0 + k] = a + k * kSegTiles;
-            seg_t1[s0 + k] = min(b, a + (k + 1) * kSegTiles);
-        }
-        const int64_t rows = min((int64_t)tile, n - I * tile);
-        alive0[I] = rows >= 32 ? 0xFFFFFFFFu : ((1u << rows) - 1u);
-    }
-}
+__global__ void k_rb_chunk_end(const Meta* meta, int64_t nI, int64_t* rb_chunk) { rb_chunk[nI] = meta->nchunks; }
 
 __global__ void k_permute_keys(const uint64_t* key, const int32_t* new_id, int64_t n, uint64_t* key_p) {
     GRID_STRIDE(v, n) key_p[new_id[v]] = key[v];
@@ -412,6 +450,7 @@ size_t layout(mis_graph* g, char* base) {
     };
     const int64_t n = g->n, nnz = g->nnz;
     take(&g->ctrl, sizeof(Ctrl));
+    take(&g->stripes, sizeof(int64_t) * 2 * kStripes * kStripeWords);
     take(&g->meta, sizeof(Meta));
     take(&g->trace, sizeof(TraceRec) * kTraceCap);
     take(&g->key, (size_t)n * 8);
@@ -435,8 +474,8 @@ size_t layout(mis_graph* g, char* base) {
     g->nI = ceil_div(n, T);
     const int64_t nI = g->nI;
     g->tile_cap = g->orient ? nnz / 2 + 1 : nnz + 1;
-    g->seg_cap = nI + g->tile_cap / kSegTiles + 1;
-    const int64_t cap = g->tile_cap, sc = g->seg_cap;
+    g->chunk_cap = g->tile_cap / (T == 16 ? 64 : 16) + nI + 1;
+    const int64_t cap = g->tile_cap;
     take(&g->new_id, (size_t)n * 4);
     take(&g->order, (size_t)n * 4);
     take(&g->sk, (size_t)n * 8);
@@ -451,26 +490,23 @@ size_t layout(mis_graph* g, char* base) {
     take(&g->hsums, (size_t)(ceil_div(nnz, 2048) + 2) * 4);
     take(&g->ecnt, (size_t)(ceil_div(nnz, kEntBlock) + 1) * 4);
     take(&g->rb_ptr, (size_t)(nI + 1) * 8);
+    take(&g->rb_chunk, (size_t)(nI + 1) * 8);
     take(&g->tile_col, (size_t)cap * 4);
     take(&g->tile_row, (size_t)cap * 4);
     take(&g->tile_start, (size_t)cap * 4);
     take(&g->tile_bits, (size_t)cap * (T * T / 32) * 4);
     if (!g->orient) take(&g->key_p, (size_t)nI * T * 8);
-    take(&g->segc, (size_t)nI * 8);
-    take(&g->seg_rb, (size_t)sc * 4);
-    take(&g->seg_t0, (size_t)sc * 8);
-    take(&g->seg_t1, (size_t)sc * 8);
-    take(&g->rb_seg0, (size_t)nI * 4);
-    take(&g->rb_nseg, (size_t)nI * 4);
-    take(&g->seg_all, (size_t)sc * 4);
-    take(&g->seglist[0], (size_t)sc * 4);
-    take(&g->seglist[1], (size_t)sc * 4);
-    take(&g->alive0, (size_t)nI * 4);
+    take(&g->hrows, (size_t)nI * 4);
+    take(&g->chunks_all, (size_t)g->chunk_cap * 8);
+    for (int b = 0; b < 2; ++b) {
+        take(&g->chunks[b], (size_t)g->chunk_cap * 8);
+        take(&g->rbl[b], (size_t)nI * 4);
+    }
     take(&g->alive, (size_t)nI * 4);
+    take(&g->blocked, (size_t)nI * 4);
+    take(&g->hit, (size_t)nI * 4);
     take(&g->inmask, (size_t)nI * 4);
     take(&g->dround, (size_t)nI * T * 4);
-    take(&g->cand, (size_t)nI * 8);
-    take(&g->part, (size_t)nI * 2 * 8);
     return off;
 }
 
@@ -580,29 +616,34 @@ int build_tiles_t(mis_graph* g, hipStream_t s) {
     // 3. stable sort of the kept entries on the row-block of the transposed entry
     bool alt = false;
     if (nnz > 0)
-        TC_CHECK(radix_sort_u64(g->ent, g->ent2, nullptr, nullptr, nnz, g->ecnt, 36, 36 + bits_for(std::max<int64_t>(nI - 1, 1)),
-                                g->sort_tmp, &alt, s));
+        TC_CHECK(radix_sort_u64(g->ent, g->ent2, nullptr, nullptr, nnz, g->ecnt, 36,
+                                36 + bits_for(std::max<int64_t>(nI - 1, 1)), g->sort_tmp, &alt, s));
     const uint64_t* sorted = alt ? g->ent2 : g->ent;
-    // 4. tiles: count heads per chunk, scan, write tile heads; then the bitmaps
-    const int64_t nchunks = ceil_div(nnz, kHeadChunk);
-    if (nchunks > 0) {
-        hipLaunchKernelGGL((k_head_count<kTshift>), dim3((unsigned)nchunks), dim3(kBlock), 0, s, sorted, g->meta,
+    // 4. tiles: count heads per chunk, scan, write tile heads; then the bitmaps and
+    //    the rows with entries; row-block tile ranges
+    const int64_t nheads = ceil_div(nnz, kHeadChunk);
+    if (nheads > 0) {
+        hipLaunchKernelGGL((k_head_count<kTshift>), dim3((unsigned)nheads), dim3(kBlock), 0, s, sorted, g->meta,
                            g->hsums);
         TC_HIP(hipGetLastError());
-        TC_CHECK(scan_excl_i32(g->hsums, g->hsums, nchunks, &g->meta->ntiles, (int32_t*)g->scan_tmp, s));
-        hipLaunchKernelGGL((k_head_write<kTshift>), dim3((unsigned)nchunks), dim3(kBlock), 0, s, sorted, g->meta,
+        TC_CHECK(scan_excl_i32(g->hsums, g->hsums, nheads, &g->meta->ntiles, (int32_t*)g->scan_tmp, s));
+        hipLaunchKernelGGL((k_head_write<kTshift>), dim3((unsigned)nheads), dim3(kBlock), 0, s, sorted, g->meta,
                            g->hsums, g->tile_start, g->tile_col, g->tile_row);
         TC_HIP(hipGetLastError());
     }
     constexpr int L = T == 16 ? 1 : 4;
-    LAUNCH((k_tile_bits<T>), g->tile_cap * L, sorted, g->tile_start, g->meta, g->tile_cap, g->tile_bits);
+    TC_HIP(hipMemsetAsync(g->hrows, 0, (size_t)nI * 4, s));
+    LAUNCH((k_tile_bits<T>), g->tile_cap * L, sorted, g->tile_start, g->tile_row, g->meta, g->tile_cap, g->tile_bits,
+           g->hrows);
     LAUNCH(k_rb_ptr, nI + 1, g->tile_row, g->meta, nI, g->rb_ptr);
-    // 5. work segments
-    LAUNCH(k_seg_count, nI, g->rb_ptr, nI, g->segc);
-    TC_CHECK(scan_excl_i64(g->segc, g->segc, nI, &g->meta->nseg, (int64_t*)g->scan_tmp, s));
-    LAUNCH(k_seg_fill, nI, g->rb_ptr, g->segc, nI, n, T, g->seg_rb, g->seg_t0, g->seg_t1, g->rb_seg0, g->rb_nseg,
-           g->alive0);
-    LAUNCH(k_iota_i32, g->seg_cap, g->seg_all, g->seg_cap);
+    // 5. the round-1 chunk list: every row-block's tiles in chunks of kTpi; rb_chunk
+    //    holds each row-block's first chunk
+    constexpr int kTpi = T == 16 ? 64 : 16;
+    LAUNCH(k_chunk_count, nI, g->rb_ptr, nI, kTpi, g->rb_chunk);
+    TC_CHECK(scan_excl_i64(g->rb_chunk, g->rb_chunk, nI, &g->meta->nchunks, (int64_t*)g->scan_tmp, s));
+    LAUNCH(k_chunk_fill, g->chunk_cap, g->rb_chunk, g->rb_ptr, g->meta, nI, kTpi, g->chunk_cap, g->chunks_all);
+    hipLaunchKernelGGL(k_rb_chunk_end, dim3(1), dim3(1), 0, s, g->meta, nI, g->rb_chunk);
+    TC_HIP(hipGetLastError());
     if (!g->orient) {
         TC_HIP(hipMemsetAsync(g->key_p, 0, (size_t)nI * T * 8, s));
         LAUNCH(k_permute_keys, n, g->key, g->new_id, n, g->key_p);

@@ -60,13 +60,14 @@ int staging(Staging** out) {
     return MIS_OK;
 }
 
-__global__ void k_ctrl_init(Ctrl* ctrl, int64_t n) {
+__global__ void k_ctrl_init(Ctrl* ctrl, int64_t* stripes, int64_t n) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         Ctrl c;
         memset(&c, 0, sizeof(c));
         c.alive = n;
         *ctrl = c;
     }
+    for (int i = threadIdx.x; i < 2 * kStripes * kStripeWords; i += blockDim.x) stripes[i] = 0;
 }
 
 // Checks arguments and resolves automatic options (host-only).
@@ -125,6 +126,9 @@ void configure(mis_graph* g, const mis_csr* csr, const mis_build_opts& o) {
     g->user_keys = o.keys != nullptr;
 }
 
+// kernels per round: tile path candidate / exclusion / finalize, CSR path candidate / exclusion
+int phases(const mis_graph* g) { return g->path == MIS_PATH_TILE ? 3 : 2; }
+
 int enqueue_phase(mis_graph* g, int phase, int r, hipStream_t s) {
     return g->path == MIS_PATH_TILE ? tile_enqueue_phase(g, phase, r, s) : csr_enqueue_phase(g, phase, r, s);
 }
@@ -158,24 +162,25 @@ __global__ void __launch_bounds__(kBlock) k_batch_stats(const int64_t* goff, con
 }
 
 // closes the last round of a batch of k rounds and moves the round base past it
-__global__ void k_close(Ctrl* ctrl, TraceRec* trace, int k) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        close_round(ctrl, trace, ctrl->rbase + k);
-        ctrl->rbase += k;
-    }
+// (one wave)
+__global__ void k_close(Ctrl* ctrl, int64_t* stripes, TraceRec* trace, int k) {
+    const int rb = ctrl->rbase;
+    close_round(ctrl, stripes, trace, rb + k);
+    if (threadIdx.x == 0) ctrl->rbase = rb + k;
 }
 
 // enqueues a batch of k rounds (round indices 1..k after the device-side base) and
 // the close kernel
 int enqueue_batch(mis_graph* g, int64_t k, hipStream_t s, hipEvent_t* ev) {
     for (int64_t i = 0; i < k; ++i) {
-        if (ev) (void)hipEventRecord(ev[3 * i], s);
-        TC_CHECK(enqueue_phase(g, 0, (int)(i + 1), s));
-        if (ev) (void)hipEventRecord(ev[3 * i + 1], s);
-        TC_CHECK(enqueue_phase(g, 1, (int)(i + 1), s));
-        if (ev) (void)hipEventRecord(ev[3 * i + 2], s);
+        const int P = phases(g);
+        for (int ph = 0; ph < P; ++ph) {
+            if (ev) (void)hipEventRecord(ev[(P + 1) * i + ph], s);
+            TC_CHECK(enqueue_phase(g, ph, (int)(i + 1), s));
+        }
+        if (ev) (void)hipEventRecord(ev[(P + 1) * i + P], s);
     }
-    hipLaunchKernelGGL(k_close, dim3(1), dim3(64), 0, s, g->ctrl, g->trace, (int)k);
+    hipLaunchKernelGGL(k_close, dim3(1), dim3(kWave), 0, s, g->ctrl, g->stripes, g->trace, (int)k);
     TC_HIP(hipGetLastError());
     return MIS_OK;
 }
@@ -207,22 +212,20 @@ bool ensure_graph(mis_graph* g) {
 // bytes the kernels must move per work unit (see TraceRec::u)
 int64_t unit_bytes(const mis_graph* g, int k) {
     if (g->path == MIS_PATH_CSR) {
-        static const int64_t b[4] = {12, 28, 8, 24};
+        static const int64_t b[kUnits] = {12, 28, 8, 24, 0, 0};
         return b[k];
     }
+    // tile path: 4-byte words, bytes, 4-byte words, bitmaps multiplied, row-blocks
+    // finalized (alive, blocked, hit read and written), chunk entries written
     const int64_t S = (int64_t)g->tile * g->tile / 8;
-    switch (k) {
-        case 0: return S + 8;    // tile_col + bitmap + alive word of the column block
-        case 1: return 8;        // one staged neighbour key
-        case 2: return 12;       // tile_col + candidate word of the column block
-        default: return S;       // bitmap fed to the matrix cores
-    }
+    static const int64_t b[kUnits] = {4, 1, 4, 0, 24, 8};
+    return k == 3 ? S : b[k];
 }
 
 }  // namespace
 
 int solve_begin(mis_graph* g, hipStream_t s) {
-    hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, s, g->ctrl, g->n);
+    hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(256), 0, s, g->ctrl, g->stripes, g->n);
     TC_HIP(hipGetLastError());
     return g->path == MIS_PATH_TILE ? tile_init(g, s) : csr_init(g, s);
 }
@@ -365,14 +368,15 @@ int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, mis_stats* st, 
     TC_CHECK(staging(&sg));
     TC_CHECK(solve_begin(g, s));
 
+    const int P = phases(g);
     std::vector<hipEvent_t> ev;
     if (timing) {
-        ev.resize(3 * (size_t)g->poll_rounds);
+        ev.resize((size_t)(P + 1) * g->poll_rounds);
         for (auto& e : ev) TC_HIP(hipEventCreate(&e));
     }
-    double kms[2] = {0.0, 0.0};
+    double kms[3] = {0.0, 0.0, 0.0};
     int64_t launches = 0;
-    int64_t units[4] = {0, 0, 0, 0};
+    int64_t units[kUnits] = {0, 0, 0, 0, 0, 0};
     int64_t enq = 0, drained = 0;
     int rc = MIS_OK;
     if (g->n > 0) {
@@ -397,11 +401,11 @@ int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, mis_stats* st, 
             }
             if (timing) {
                 for (int64_t i = 0; i < k; ++i) {
-                    float a = 0.f, b = 0.f;
-                    (void)hipEventElapsedTime(&a, ev[3 * i], ev[3 * i + 1]);
-                    (void)hipEventElapsedTime(&b, ev[3 * i + 1], ev[3 * i + 2]);
-                    kms[0] += a;
-                    kms[1] += b;
+                    for (int ph = 0; ph < P; ++ph) {
+                        float ms = 0.f;
+                        (void)hipEventElapsedTime(&ms, ev[(P + 1) * i + ph], ev[(P + 1) * i + ph + 1]);
+                        kms[ph] += ms;
+                    }
                 }
                 launches += k;
             }
@@ -413,7 +417,7 @@ int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, mis_stats* st, 
                     st->trace[3 * (r - 1) + 1] = t.x;
                     st->trace[3 * (r - 1) + 2] = t.alive;
                 }
-                for (int i = 0; i < 4; ++i) units[i] += t.u[i];
+                for (int i = 0; i < kUnits; ++i) units[i] += t.u[i];
             }
             drained = done_rounds;
             if (sg->ctrl->alive == 0) break;
@@ -440,13 +444,12 @@ int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, mis_stats* st, 
         st->tiles = nt;
         st->tile_bytes = nt * ((int64_t)g->tile * g->tile / 8 + 4);
         int64_t ab = 0;
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < kUnits; ++i) {
             st->units[i] = units[i];
             ab += units[i] * unit_bytes(g, i);
         }
         st->alg_bytes = ab;
-        st->kernel_ms[0] = (float)kms[0];
-        st->kernel_ms[1] = (float)kms[1];
+        for (int ph = 0; ph < 3; ++ph) st->kernel_ms[ph] = (float)kms[ph];
         st->launches = (int32_t)launches;
         st->graph = g->graph_exec != nullptr && !timing && g->launch != MIS_LAUNCH_DIRECT;
     }

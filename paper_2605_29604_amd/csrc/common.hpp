@@ -49,6 +49,21 @@ __device__ inline int lane_id() { return (int)__lane_id(); }
 __device__ inline uint64_t ballot(bool p) { return __ballot(p); }
 __device__ inline uint64_t lanes_below() { return (1ull << lane_id()) - 1ull; }
 
+// Lanes that share a key I are adjacent (I < 0: none).  ORs each run's masks in
+// registers (segmented suffix scan) and lets the run's first lane apply the result
+// to dst[I] with one atomic OR.  Every lane of the wave must call it.
+__device__ inline void run_or(int32_t I, uint32_t m, uint32_t* dst) {
+    const int lane = lane_id();
+    #pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t mo = (uint32_t)__shfl_down((int)m, off, kWave);
+        const int32_t Io = __shfl_down(I, off, kWave);
+        if (lane + off < kWave && Io == I) m |= mo;
+    }
+    const int32_t Ip = __shfl_up(I, 1, kWave);
+    if ((lane == 0 || Ip != I) && I >= 0 && m) atomicOr(&dst[I], m);
+}
+
 // Prefix scans (no allocation; `scratch` holds scan_scratch_elems(count) elements
 // of the scanned type; d_total, if given, receives the grand total on the device).
 int64_t scan_scratch_elems(int64_t count);

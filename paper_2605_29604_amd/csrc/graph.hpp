@@ -10,14 +10,18 @@ namespace tcmis {
 
 constexpr int kLightDeg = 32;       // CSR path: thread per vertex up to this degree, wave above
 constexpr int kTraceCap = 4096;     // device trace ring (rounds); the host drains it at every poll
-constexpr int kSegTiles = 512;      // tile path: at most this many tiles per work segment
+constexpr int kUnits = 6;           // work-unit counters per round (TraceRec::u)
+constexpr int kStripes = 32;        // round counters are spread over this many cache lines
+constexpr int kStripeWords = 16;    // int64 words per stripe (one 128-byte line)
 
 // Device control block of the round loop.  Round r's kernels take r as an
-// argument and count into cnt[r & 1]; round r is closed (counters moved to the
-// trace ring, `alive` and `round` advanced) by the first thread of round r+1's
-// candidate kernel, or by the one-thread close kernel the host enqueues before it
-// reads the block.  No workgroup ever waits for another, and no fence is needed:
-// every cross-workgroup hand-over crosses a kernel boundary.
+// argument and count into the round-parity half of the counter stripes (each
+// workgroup adds into stripe blockIdx % kStripes, so no single line takes every
+// atomic); round r is closed (stripes summed into the trace ring and cleared,
+// `alive` and `round` advanced) by the first wave of round r+1's first kernel, or
+// by the one-wave close kernel the host enqueues before it reads the block.  No
+// workgroup ever waits for another, and no fence is needed: every
+// cross-workgroup hand-over crosses a kernel boundary.
 struct Ctrl {
     int32_t round;          // rounds closed
     int32_t rbase;          // rounds enqueued before the current batch (round = rbase + index in batch)
@@ -25,27 +29,35 @@ struct Ctrl {
     int32_t pad0;
     int64_t alive;          // undecided vertices after `round` rounds
     int64_t n_in;           // vertices in the set so far
-    int64_t n_act[2][2];    // active work items per list buffer (CSR: [light, heavy]; tile: [segments, -])
-    int64_t cnt[2][6];      // per round parity: |C|, removed neighbours, work units u0..u3
+    int64_t n_act[2][2];    // active work items per list buffer (CSR: [light, heavy]; tile: [chunks, row-blocks])
 };
+// Counter words of a stripe: |C|, removed neighbours, work units u0..u5.
+
+// A tile chunk: at most 64 consecutive tiles of one row-block, packed as
+// t0 (bits 33..63) | len - 1 (bits 27..32) | row-block (bits 0..26).
+__host__ __device__ inline uint64_t chunk_word(int64_t t0, int64_t len, int64_t I) {
+    return ((uint64_t)t0 << 33) | ((uint64_t)(len - 1) << 27) | (uint64_t)I;
+}
 
 // Per-round trace record in the device ring.
 //   c, x, alive : |C_r|, vertices removed as neighbours of candidates, undecided after r
-//   u[0..3]     : work units.  CSR path: adjacency entries read by the candidate
+//   u[0..5]     : work units.  CSR path: adjacency entries read by the candidate
 //                 kernel, vertices it examined, entries read by the exclusion kernel,
-//                 vertices it examined.  Tile path: tiles read by the candidate kernel,
-//                 neighbour keys it staged, tiles whose candidate segment the exclusion
-//                 kernel examined, tiles it multiplied on the matrix cores.
+//                 vertices it examined (u4 = u5 = 0).  Tile path: 4-byte index and
+//                 mask words the candidate kernel read, bytes of bitmaps and keys it
+//                 read, 4-byte words the exclusion kernel read, tiles it multiplied on
+//                 the matrix cores, row-blocks the finalize kernel updated, chunk list
+//                 entries it wrote.
 struct TraceRec {
     int64_t c, x, alive, round;
-    int64_t u[4];
+    int64_t u[kUnits];
 };
 
 // Sizes the build produces on the device (never read back during the build).
 struct Meta {
     int32_t ntiles;         // nonzero tiles
     int32_t nvalid;         // adjacency entries kept in tiles
-    int64_t nseg;           // work segments
+    int64_t nchunks;        // tile path: chunks of the round-1 list
     int32_t n_light;        // CSR path: vertices with degree <= kLightDeg
     int32_t pad;
 };
@@ -82,6 +94,7 @@ struct mis_graph {
     size_t ws_bytes = 0;
 
     tcmis::Ctrl* ctrl = nullptr;
+    int64_t* stripes = nullptr;       // [2][kStripes][kStripeWords] round counters
     tcmis::Meta* meta = nullptr;
     tcmis::TraceRec* trace = nullptr;
     char* scan_tmp = nullptr;         // scan scratch (int64 elements)
@@ -106,7 +119,7 @@ struct mis_graph {
     // ---- tile path (new vertex order)
     int64_t nI = 0;                   // row-blocks of `tile` rows
     int64_t tile_cap = 0;             // capacity in tiles (upper bound)
-    int64_t seg_cap = 0;              // capacity in segments
+    int64_t chunk_cap = 0;            // capacity of a chunk list
     int32_t* new_id = nullptr;        // input id -> new id
     int32_t* order = nullptr;         // new id -> input id
     uint64_t* sk = nullptr;           // [n] x2 order sort keys
@@ -120,25 +133,21 @@ struct mis_graph {
     int32_t* hsums = nullptr;         // [nnz/2048+2] tile heads per chunk -> first tile of the chunk
     int32_t* ecnt = nullptr;          // [nnz/4096+1] kept entries per entry workgroup
     int64_t* rb_ptr = nullptr;        // [nI+1] tile range of each row-block
+    int64_t* rb_chunk = nullptr;      // [nI+1] first round-1 chunk of each row-block
     int32_t* tile_col = nullptr;      // [tile_cap] column block J
     int32_t* tile_row = nullptr;      // [tile_cap] row block I
     int32_t* tile_start = nullptr;    // [tile_cap] first sorted entry of each tile
     uint32_t* tile_bits = nullptr;    // [tile_cap * tile*tile/32] row masks (T=16: two rows per word)
     uint64_t* key_p = nullptr;        // [nI*tile] keys in new order, padding 0 (orient = 0)
-    int64_t* segc = nullptr;          // [nI] segments per row-block -> first segment
-    int32_t* seg_rb = nullptr;        // [seg_cap] row-block of a segment
-    int64_t* seg_t0 = nullptr;        // [seg_cap] first tile
-    int64_t* seg_t1 = nullptr;        // [seg_cap] one past the last tile
-    int32_t* rb_seg0 = nullptr;       // [nI] first segment of a row-block
-    int32_t* rb_nseg = nullptr;       // [nI]
-    int32_t* seg_all = nullptr;       // [seg_cap] 0, 1, 2, ... (round-1 active list)
-    int32_t* seglist[2] = {nullptr, nullptr};
-    uint32_t* alive0 = nullptr;       // [nI] rows that exist (initial alive mask)
+    uint32_t* hrows = nullptr;        // [nI] rows with at least one tile entry
+    uint64_t* chunks_all = nullptr;   // [chunk_cap] every row-block's chunks (round 1)
+    uint64_t* chunks[2] = {nullptr, nullptr};   // [chunk_cap] next round's chunks
+    int32_t* rbl[2] = {nullptr, nullptr};       // [nI] next round's active row-blocks
     uint32_t* alive = nullptr;        // [nI] undecided rows
-    uint64_t* cand = nullptr;         // [nI] (round << 32) | candidate mask
+    uint32_t* blocked = nullptr;      // [nI] rows with an undecided higher-priority neighbour (this round)
+    uint32_t* hit = nullptr;          // [nI] rows with a candidate neighbour (this round)
     uint32_t* inmask = nullptr;       // [nI] rows in the set
     int32_t* dround = nullptr;        // [nI*tile] round in which each row was decided
-    uint64_t* part = nullptr;         // [2*nI] (segments done << 32 | partial mask) of multi-segment row-blocks
 };
 
 namespace tcmis {

@@ -11,12 +11,6 @@ __device__ inline void wave_sync_lds() {
     __builtin_amdgcn_wave_barrier();
 }
 
-// Sum of a per-lane value over the wave, added with one atomic.
-__device__ inline void wave_add(int64_t* p, int64_t x) {
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
-    if (lane_id() == 0 && x) atomicAdd((unsigned long long*)p, (unsigned long long)x);
-}
-
 // Per-wave LDS staging buffer for list appends: items collect in LDS and are
 // written with one atomic per 64 items.  `pend` is wave-uniform.
 __device__ inline void lbuf_flush(int32_t* lbuf, int& pend, int32_t* list, int64_t* count) {
@@ -43,32 +37,66 @@ __device__ inline int64_t atomic_read(int64_t* p) {
     return (int64_t)__hip_atomic_load((unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Closes round r (one thread): moves its counters into the trace ring and advances
-// `round` and `alive`.  A round that is already closed, or that ran after every
-// vertex was decided, is left alone.
-__device__ inline void close_round(Ctrl* ctrl, TraceRec* trace, int r) {
-    if (r < 1 || ctrl->round != r - 1 || ctrl->alive == 0) return;
-    int64_t* c = ctrl->cnt[r & 1];
-    TraceRec rec;
-    rec.c = atomic_read(&c[0]);
-    rec.x = atomic_read(&c[1]);
-    rec.alive = ctrl->alive - rec.c - rec.x;
-    rec.round = r;
-    for (int i = 0; i < 4; ++i) rec.u[i] = atomic_read(&c[2 + i]);
-    trace[(r - 1) % kTraceCap] = rec;
-    for (int i = 0; i < 6; ++i) c[i] = 0;
-    ctrl->n_in += rec.c;
-    ctrl->alive = rec.alive;
-    ctrl->round = r;
+// Adds per-thread counts to round r's counters: a wave sum, a workgroup sum in LDS,
+// then one atomic per counter into the workgroup's stripe.  Every thread of the
+// workgroup must call it (it synchronises the workgroup).
+template <int N>
+__device__ inline void block_count(int64_t* stripes, int r, const int (&idx)[N], int64_t (&x)[N]) {
+    __shared__ int64_t part[kBlock / kWave][N];
+    const int lane = lane_id(), wid = threadIdx.x / kWave;
+    #pragma unroll
+    for (int i = 0; i < N; ++i) {
+        for (int off = kWave / 2; off > 0; off >>= 1) x[i] += __shfl_xor(x[i], off, kWave);
+        if (lane == 0) part[wid][i] = x[i];
+    }
+    __syncthreads();
+    if (threadIdx.x < N) {
+        int64_t sum = 0;
+        for (int w = 0; w < kBlock / kWave; ++w) sum += part[w][threadIdx.x];
+        int64_t* st = stripes + ((int64_t)(r & 1) * kStripes + blockIdx.x % kStripes) * kStripeWords;
+        if (sum) atomicAdd((unsigned long long*)&st[idx[threadIdx.x]], (unsigned long long)sum);
+    }
 }
 
-// Round prologue run by the first thread of round r's candidate kernel: closes
-// round r-1 and empties the list that round r's exclusion kernel fills.
-__device__ inline void open_round(Ctrl* ctrl, TraceRec* trace, int r) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        close_round(ctrl, trace, r - 1);
-        ctrl->n_act[r & 1][0] = 0;
-        ctrl->n_act[r & 1][1] = 0;
+// Closes round r (one full wave, uniform control flow): sums and clears the
+// round's counter stripes, writes its trace record and advances `round` and
+// `alive`.  A round that is already closed, or that ran after every vertex was
+// decided, is left alone.
+__device__ inline void close_round(Ctrl* ctrl, int64_t* stripes, TraceRec* trace, int r) {
+    if (r < 1 || ctrl->round != r - 1 || ctrl->alive == 0) return;
+    const int lane = lane_id();
+    int64_t* st = stripes + ((int64_t)(r & 1) * kStripes + lane) * kStripeWords;
+    int64_t v[2 + kUnits];
+    #pragma unroll
+    for (int i = 0; i < 2 + kUnits; ++i) v[i] = lane < kStripes ? atomic_read(&st[i]) : 0;
+    #pragma unroll
+    for (int i = 0; i < 2 + kUnits; ++i) {
+        if (lane < kStripes) st[i] = 0;
+        for (int off = kWave / 2; off > 0; off >>= 1) v[i] += __shfl_xor(v[i], off, kWave);
+    }
+    if (lane == 0) {
+        TraceRec rec;
+        rec.c = v[0];
+        rec.x = v[1];
+        rec.alive = ctrl->alive - rec.c - rec.x;
+        rec.round = r;
+        for (int i = 0; i < kUnits; ++i) rec.u[i] = v[2 + i];
+        trace[(r - 1) % kTraceCap] = rec;
+        ctrl->n_in += rec.c;
+        ctrl->alive = rec.alive;
+        ctrl->round = r;
+    }
+}
+
+// Round prologue run by the first wave of round r's first kernel: closes round
+// r-1 and empties the lists that round r's last kernel fills.
+__device__ inline void open_round(Ctrl* ctrl, int64_t* stripes, TraceRec* trace, int r) {
+    if (blockIdx.x == 0 && threadIdx.x < kWave) {
+        close_round(ctrl, stripes, trace, r - 1);
+        if (threadIdx.x == 0) {
+            ctrl->n_act[r & 1][0] = 0;
+            ctrl->n_act[r & 1][1] = 0;
+        }
     }
 }
 

@@ -26,6 +26,7 @@ struct CsrArgs {
     uint64_t* ak;
     uint32_t* st;
     Ctrl* ctrl;
+    int64_t* stripes;
     TraceRec* trace;
     const int32_t* master[2];   // initial light / heavy lists (round 1)
     const Meta* meta;           // meta->n_light: length of the light list
@@ -47,7 +48,7 @@ __device__ inline void round_lists(const CsrArgs& a, int r, const int32_t** in_l
 
 __global__ void __launch_bounds__(kBlock) k_csr_cand(CsrArgs a, int ri) {
     const int r = a.ctrl->rbase + ri;   // round number (the batch base is on the device)
-    open_round(a.ctrl, a.trace, r);
+    open_round(a.ctrl, a.stripes, a.trace, r);
     const int32_t *L, *H;
     int64_t nl, nh;
     round_lists(a, r, &L, &nl, &H, &nh);
@@ -89,10 +90,8 @@ __global__ void __launch_bounds__(kBlock) k_csr_cand(CsrArgs a, int ri) {
             if (!blocked) { a.st[v] = tag(r, kIn); ++n_cand; }
         }
     }
-    int64_t* cnt = a.ctrl->cnt[r & 1];
-    wave_add(&cnt[0], n_cand);
-    wave_add(&cnt[2], edges);
-    wave_add(&cnt[3], verts);
+    int64_t x[3] = {n_cand, edges, verts};
+    block_count(a.stripes, r, {0, 2, 3}, x);
 }
 
 __global__ void __launch_bounds__(kBlock) k_csr_excl(CsrArgs a, int ri) {
@@ -163,10 +162,8 @@ __global__ void __launch_bounds__(kBlock) k_csr_excl(CsrArgs a, int ri) {
         lbuf_push(bufH, pendH, nextH, cntH, lane == 0 && !hit, v);
     }
     lbuf_flush(bufH, pendH, nextH, cntH);
-    int64_t* cnt = a.ctrl->cnt[r & 1];
-    wave_add(&cnt[1], n_out);
-    wave_add(&cnt[4], edges);
-    wave_add(&cnt[5], verts);
+    int64_t x[3] = {n_out, edges, verts};
+    block_count(a.stripes, r, {1, 4, 5}, x);
 }
 
 __global__ void k_csr_init(const uint64_t* key, uint64_t* ak, uint32_t* st, int64_t n) {
@@ -184,7 +181,7 @@ __global__ void k_csr_output(const uint32_t* st, int64_t n, uint8_t* in_set) {
 CsrArgs make_args(mis_graph* g) {
     CsrArgs a;
     a.rp = g->row_ptr; a.ci = g->col_idx; a.key = g->key; a.ak = g->ak; a.st = g->st;
-    a.ctrl = g->ctrl; a.trace = g->trace;
+    a.ctrl = g->ctrl; a.stripes = g->stripes; a.trace = g->trace;
     a.master[0] = g->light; a.master[1] = g->heavy;
     a.meta = g->meta; a.n = g->n;
     for (int b = 0; b < 2; ++b)

@@ -1,41 +1,43 @@
 // Tile path: the rounds of Algorithm 2 over nonzero T x T bit tiles (T = 16, 32).
 //
 // Layout (new vertex order, row-block I = rows I*T .. I*T+T-1):
-//   rb_ptr[I] .. rb_ptr[I+1]  tiles of row-block I, column block tile_col[t]
+//   tile slots                tile_col[t] column block, tile_bits bitmap; a row-block's
+//                             tiles are described by its chunks, chunks_all[rb_chunk[I]
+//                             .. rb_chunk[I+1]) (round 1 lists them all)
 //   tile_bits                 T=16: 8 words per tile, word w = rows 2w (low 16 bits)
 //                             and 2w+1 (high 16 bits); T=32: 32 words, one per row
 //   alive[I]                  undecided rows of row-block I (bit r)
-//   cand[I]                   (round << 32) | rows of I that are candidates in `round`
-// Work is split into segments of at most kSegTiles tiles of one row-block; a
-// row-block with several segments combines their partial masks with one atomic OR
-// each, and the segment that finishes last completes the row-block.
+//   blocked[I], hit[I]        this round's Phase-1 and Phase-2 row masks, built with
+//                             atomic ORs and cleared by the finalize kernel
 //
-// A wave takes one segment at a time and streams its tiles 64 lanes wide: each
-// lane owns one tile (T=16) or a quarter tile (T=32: rows 8k..8k+7) and loads 32
-// contiguous bytes of bitmap, so a wave keeps 64 tiles of independent loads in
-// flight.  Bitmaps are only read for tiles whose column block can matter (alive
-// rows for Phase 1, candidate rows for Phase 2).
+// Each round is three kernels over a list of tile chunks: at most 64 tiles (T=16)
+// or 16 tiles (T=32) of one row-block, described by one word (first tile, length,
+// row-block).  Round 1 takes every row-block's chunks (listed once by the build),
+// later rounds the chunks of row-blocks that still have undecided rows.  A wave
+// takes a contiguous share of the list, so it meets a row-block's chunks one after
+// another: once the row-block has nothing left to learn in the phase, its further
+// chunks are skipped without touching memory.
 //
-// Candidate kernel (Phase 1, Section 3.1): a row is blocked when it has a set bit
-// in a column that is alive and
-//   orient = 1: unconditionally (the tiles hold only edges to higher-priority
-//               neighbours, so no keys are read);
-//   orient = 0: whose key beats the row's key (the row keys of the segment's
-//               row-block are staged in LDS once per segment, neighbour keys are
-//               gathered per set alive bit).
-// Blocked rows are OR-reduced across the wave; candidates = alive & ~blocked.
+//   candidate (Phase 1, Section 3.1)  blocked[I] |= rows with a set bit in an
+//       undecided column; with key orientation the tiles keep only edges to
+//       higher-priority neighbours, so no key is read, and in round 1 (everything
+//       undecided) the blocked rows are the rows with any entry, recorded by the
+//       build, so round 1 has no candidate pass over the tiles.  Without
+//       orientation the neighbour's key must beat the row's key.
+//   exclusion (Phase 2, Section 3.2)  N_c = A x C on the matrix cores as an int8 x
+//       int8 -> int32 product (exact: every count is <= the degree).  The chunk's
+//       tiles whose column block holds a candidate (C = alive & ~blocked) are
+//       compacted into LDS and fed to v_mfma_i32_16x16x64_i8 four tiles at a time
+//       (A: lane = row, K = the four tiles' columns; B: the four candidate vectors,
+//       equal in every column) or to v_mfma_i32_32x32x32_i8 one 32x32 tile at a
+//       time; bits are expanded to 0/1 bytes in registers.
+//   finalize (Phase 3)  per listed row-block: candidates join the set, hit
+//       non-candidates leave it, the rest stay; blocked/hit are cleared and the
+//       row-block's chunks are appended to the next round's list.
 //
-// Exclusion kernel (Phases 2 and 3, Section 3.2): N_c = A x C on the matrix cores
-// as an int8 x int8 -> int32 product (exact: every count is <= the degree).  The
-// tiles of an iteration whose candidate segment is non-empty (the paper's early
-// exit skips the rest) are compacted into LDS, then fed to
-// v_mfma_i32_16x16x64_i8 four tiles at a time (A: lane = row, k-group = tile; B:
-// the four candidate segments, equal in all 16 columns) or to
-// v_mfma_i32_32x32x32_i8 one 32x32 tile at a time.  Bits are expanded to 0/1
-// bytes in registers.  A row-block stops as soon as every alive non-candidate row
-// has a candidate neighbour.  Phase 3 is fused: the wave that completes a
-// row-block writes its new alive mask, its members and, if rows remain, its
-// segments to the next round's active list.
+// Every lane works on one tile (T=16) or a quarter tile (T=32: rows 8k..8k+7), so a
+// wave keeps 64 independent tile loads in flight; a chunk's row masks are OR-reduced
+// across the wave and applied with one atomic.
 #include "round.hpp"
 
 namespace tcmis {
@@ -48,31 +50,31 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 constexpr int kWpb = kBlock / kWave;   // waves per block
 
 struct TileArgs {
-    const int32_t* seg_rb;
-    const int64_t* seg_t0;
-    const int64_t* seg_t1;
-    const int32_t* rb_seg0;
-    const int32_t* rb_nseg;
+    const int64_t* rb_chunk;
     const int32_t* tile_col;
     const uint32_t* bits;
     const uint64_t* key_p;
+    const uint32_t* hrows;
     uint32_t* alive;
-    uint64_t* cand;
+    uint32_t* blocked;
+    uint32_t* hit;
     uint32_t* inmask;
-    uint64_t* part;     // [2*nI]: candidate-phase and exclusion-phase (count << 32 | mask) words
-    const int32_t* seg_all;
-    int32_t* seglist[2];
     int32_t* dround;
+    const uint64_t* chunks_all;
+    uint64_t* chunks[2];
+    int32_t* rbl[2];
     const Meta* meta;
+    int64_t n;
     int64_t nI;
     Ctrl* ctrl;
+    int64_t* stripes;
     TraceRec* trace;
 };
 
 template <int T>
 struct Geo {
     static constexpr int kLpt = T == 16 ? 1 : 4;      // lanes per tile
-    static constexpr int kTpi = kWave / kLpt;          // tiles per wave iteration
+    static constexpr int kTpi = kWave / kLpt;          // tiles per chunk
     static constexpr int kWpt = T * T / 32;            // bitmap words per tile
 };
 
@@ -105,19 +107,42 @@ __device__ inline uint32_t rows_hit(const uint32_t w[8], uint32_t colmask, int k
     return r;
 }
 
+// Round r's chunk list: round 1 takes every row-block's chunks (built once), later
+// rounds the list the previous finalize wrote.
+__device__ inline void round_chunks(const TileArgs& a, int r, const uint64_t** list, int64_t* n) {
+    if (r == 1) { *list = a.chunks_all; *n = a.meta->nchunks; }
+    else { *list = a.chunks[(r - 1) & 1]; *n = a.ctrl->n_act[(r - 1) & 1][0]; }
+}
+
+// Chunks [*c0, *c1) of this wave: a contiguous share, so a wave meets the chunks of
+// one row-block one after another and can skip them once the row-block is done.
+// The wave index is read through readfirstlane so that chunk descriptors and
+// row-block words load as wave-uniform (scalar) values.
+__device__ inline void wave_range(int64_t nch, int64_t* c0, int64_t* c1) {
+    const int64_t nwaves = (int64_t)gridDim.x * kWpb;
+    const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    const int64_t w = (int64_t)blockIdx.x * kWpb + wid;
+    const int64_t per = (nch + nwaves - 1) / nwaves;
+    *c0 = min(nch, w * per);
+    *c1 = min(nch, *c0 + per);
+}
+
+struct Chunk {
+    int64_t t0, I;
+    int len;
+};
+
+__device__ inline Chunk decode(uint64_t w) {
+    Chunk c;
+    c.t0 = (int64_t)(w >> 33);
+    c.len = (int)((w >> 27) & 63u) + 1;
+    c.I = (int64_t)(w & ((1ull << 27) - 1));
+    return c;
+}
+
 __device__ inline uint32_t wave_or(uint32_t x) {
     for (int off = kWave / 2; off > 0; off >>= 1) x |= (uint32_t)__shfl_xor((int)x, off, kWave);
     return x;
-}
-
-__device__ inline void active_list(const TileArgs& a, int r, const int32_t** list, int64_t* n) {
-    if (r == 1) { *list = a.seg_all; *n = a.meta->nseg; }
-    else { *list = a.seglist[(r - 1) & 1]; *n = a.ctrl->n_act[(r - 1) & 1][0]; }
-}
-
-__device__ inline uint32_t cand_of(const uint64_t* cand, int64_t J, int r) {
-    const uint64_t w = cand[J];
-    return (uint32_t)(w >> 32) == (uint32_t)r ? (uint32_t)w : 0u;
 }
 
 // 16 bits -> 16 bytes of 0/1 (byte i = bit i)
@@ -130,94 +155,76 @@ __device__ inline v4i expand16(uint32_t x) {
     return o;
 }
 
-// Completes a row-block's mask: single-segment row-blocks use the wave's own mask;
-// otherwise each segment folds its partial mask and a completion count into one
-// 64-bit word (count << 32 | mask) with compare-and-swap, and the segment that
-// brings the count to nseg receives the OR of all partials and resets the word.
-// One atomic word carries both, so no fence is needed between them.
-__device__ inline bool combine(uint64_t* part, int64_t I, int nseg, uint32_t mine, uint32_t* total) {
-    if (nseg == 1) { *total = mine; return true; }
-    unsigned long long* w = (unsigned long long*)&part[I];
-    unsigned long long old = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), seen;
-    do {
-        seen = old;
-        const unsigned long long nw = ((seen >> 32) + 1) << 32 | ((uint32_t)seen | mine);
-        old = atomicCAS(w, seen, nw);
-    } while (old != seen);
-    if ((int64_t)(seen >> 32) + 1 != nseg) return false;
-    *total = (uint32_t)seen | mine;
-    atomicExch(w, 0ull);
-    return true;
-}
-
 template <int T, int ORIENT>
 __global__ void __launch_bounds__(kBlock) k_tile_cand(TileArgs a, int ri) {
     const int r = a.ctrl->rbase + ri;   // round number (the batch base is on the device)
     using G = Geo<T>;
-    __shared__ uint64_t rkeys[kWpb][32];
-    open_round(a.ctrl, a.trace, r);
-    const int32_t* list;
-    int64_t nact;
-    active_list(a, r, &list, &nact);
+    open_round(a.ctrl, a.stripes, a.trace, r);
+    if (ORIENT && r == 1) return;       // blocked = rows with any entry, set at solve start
+    __shared__ uint64_t rkeys[kWpb][T];   // orient = 0: the chunk's row keys
+    const uint64_t* list;
+    int64_t nch, c, c1;
+    round_chunks(a, r, &list, &nch);
+    wave_range(nch, &c, &c1);
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     const int sub = lane / G::kLpt, k = lane % G::kLpt;
     uint64_t* rk = rkeys[wid];
-    const int64_t nwaves = (int64_t)gridDim.x * kWpb;
-    int64_t n_cand = 0, tiles = 0, keys = 0;
-    for (int64_t w = (int64_t)blockIdx.x * kWpb + wid; w < nact; w += nwaves) {
-        const int s = list[w];
-        const int64_t I = a.seg_rb[s];
-        const int64_t t0 = a.seg_t0[s], t1 = a.seg_t1[s];
-        const uint32_t al = a.alive[I];
-        if (!ORIENT) {
-            wave_sync_lds();
-            if (lane < T) rk[lane] = a.key_p[I * T + lane];
-            wave_sync_lds();
-        }
-        uint32_t blocked = 0;
-        for (int64_t tb = t0; tb < t1; tb += G::kTpi) {
-            const int64_t t = tb + sub;
-            const bool valid = t < t1;
-            const int64_t J = valid ? a.tile_col[t] : 0;
-            const uint32_t aJ = valid ? a.alive[J] : 0u;
-            tiles += valid && k == 0;
-            if (aJ) {
-                uint32_t wd[8];
-                load8<T>(a.bits, t, k, wd);
-                if (ORIENT) {
-                    blocked |= rows_hit<T>(wd, aJ, k);
-                } else {
-                    #pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        uint32_t x = wd[j] & (T == 16 ? (aJ | (aJ << 16)) : aJ);
-                        while (x) {
-                            const int b = __builtin_ctz(x);
-                            x &= x - 1;
-                            const int row = T == 16 ? 2 * j + (b >> 4) : 8 * k + j;
-                            const int col = T == 16 ? (b & 15) : b;
-                            if ((blocked >> row) & 1u) continue;
-                            ++keys;
-                            if (a.key_p[J * T + col] > rk[row]) blocked |= 1u << row;
+    int64_t words = 0, bytes = 0;
+    int64_t prev_I = -1;
+    uint32_t prev_open = 0;
+    for (; c < c1; ++c) {
+        const Chunk ch = decode(list[c]);
+        words += lane == 0 ? 2 : 0;
+        // a row-block whose undecided rows are all blocked stays so for the rest of
+        // this kernel (blocked only grows): skip its further chunks without a load
+        if (ch.I == prev_I && prev_open == 0) continue;
+        uint32_t open = a.alive[ch.I] & ~a.blocked[ch.I];   // undecided rows not yet blocked
+        words += lane == 0 ? 2 : 0;
+        if (open) {
+            if (!ORIENT && ch.I != prev_I) {   // stage the row-block's keys once
+                wave_sync_lds();
+                if (lane < T) rk[lane] = a.key_p[ch.I * T + lane];
+                bytes += lane == 0 ? 8 * T : 0;
+                wave_sync_lds();
+            }
+            uint32_t m = 0;
+            if (sub < ch.len) {
+                const int64_t t = ch.t0 + sub;
+                const int32_t J = a.tile_col[t];
+                const uint32_t aJ = a.alive[J];
+                words += k == 0 ? 2 : 0;
+                if (aJ) {
+                    uint32_t wd[8];
+                    load8<T>(a.bits, t, k, wd);
+                    bytes += 32;
+                    if (ORIENT) {
+                        m = rows_hit<T>(wd, aJ, k) & open;
+                    } else {
+                        #pragma unroll
+                        for (int j = 0; j < 8; ++j) {
+                            uint32_t x = wd[j] & (T == 16 ? (aJ | (aJ << 16)) : aJ);
+                            while (x) {
+                                const int b = __builtin_ctz(x);
+                                x &= x - 1;
+                                const int row = T == 16 ? 2 * j + (b >> 4) : 8 * k + j;
+                                const int col = T == 16 ? (b & 15) : b;
+                                if (!((open >> row) & 1u) || ((m >> row) & 1u)) continue;
+                                bytes += 8;
+                                if (a.key_p[(int64_t)J * T + col] > rk[row]) m |= 1u << row;
+                            }
                         }
                     }
                 }
             }
-            if ((wave_or(blocked) & al) == al) break;
+            m = wave_or(m);
+            if (m && lane == 0) atomicOr(&a.blocked[ch.I], m);
+            open &= ~m;
         }
-        blocked = wave_or(blocked);
-        if (lane == 0) {
-            uint32_t total;
-            if (combine(a.part, I, a.rb_nseg[I], blocked, &total)) {
-                const uint32_t c = al & ~total;
-                a.cand[I] = ((uint64_t)(uint32_t)r << 32) | c;
-                n_cand += __popc(c);
-            }
-        }
+        prev_I = ch.I;
+        prev_open = open;
     }
-    int64_t* cnt = a.ctrl->cnt[r & 1];
-    wave_add(&cnt[0], n_cand);
-    wave_add(&cnt[2], tiles);
-    wave_add(&cnt[3], keys);
+    int64_t x[2] = {words, bytes};
+    block_count(a.stripes, r, {2, 3}, x);
 }
 
 // rows with N_c > 0 from the accumulator (all B columns are equal, so any column works)
@@ -249,51 +256,41 @@ __device__ inline uint32_t hits32(const v16i& acc) {
 }
 
 template <int T>
-struct Acc;
-template <>
-struct Acc<16> { typedef v4i type; };
-template <>
-struct Acc<32> { typedef v16i type; };
-
-template <int T, int ORIENT>
 __global__ void __launch_bounds__(kBlock) k_tile_excl(TileArgs a, int ri) {
-    const int r = a.ctrl->rbase + ri;   // round number (the batch base is on the device)
+    const int r = a.ctrl->rbase + ri;
     using G = Geo<T>;
     __shared__ uint32_t sbits[kWpb][G::kTpi * G::kWpt];
     __shared__ uint32_t scand[kWpb][G::kTpi];
-    __shared__ int32_t lbuf[kWpb][kWave];
-    const int32_t* list;
-    int64_t nact;
-    active_list(a, r, &list, &nact);
-    int32_t* next = a.seglist[r & 1];
-    int64_t* next_cnt = &a.ctrl->n_act[r & 1][0];
+    const uint64_t* list;
+    int64_t nch, c, c1;
+    round_chunks(a, r, &list, &nch);
+    wave_range(nch, &c, &c1);
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     const int sub = lane / G::kLpt, k = lane % G::kLpt;
     uint32_t* sb = sbits[wid];
     uint32_t* sc = scand[wid];
-    int32_t* buf = lbuf[wid];
-    int pend = 0;
-    const int64_t nwaves = (int64_t)gridDim.x * kWpb;
-    int64_t n_out = 0, scanned = 0, mult = 0;
-    for (int64_t w = (int64_t)blockIdx.x * kWpb + wid; w < nact; w += nwaves) {
-        const int s = list[w];
-        const int64_t I = a.seg_rb[s];
-        const int64_t t0 = a.seg_t0[s], t1 = a.seg_t1[s];
-        const uint32_t al = a.alive[I];
-        const uint32_t cI = cand_of(a.cand, I, r);
-        const uint32_t rest = al & ~cI;     // undecided non-candidates
-        uint32_t hit = 0;
+    int64_t words = 0, mult = 0;
+    int64_t prev_I = -1;
+    uint32_t prev_rest = 0;
+    for (; c < c1; ++c) {
+        const Chunk ch = decode(list[c]);
+        words += lane == 0 ? 2 : 0;
+        // a row-block whose undecided non-candidates all have a candidate neighbour
+        // stays so for the rest of this kernel (hit only grows): skip its chunks
+        if (ch.I == prev_I && prev_rest == 0) continue;
+        uint32_t rest = a.alive[ch.I] & a.blocked[ch.I] & ~a.hit[ch.I];
+        words += lane == 0 ? 3 : 0;
         if (rest) {
-            typename Acc<T>::type acc = {};
-            for (int64_t tb = t0; tb < t1; tb += G::kTpi) {
-                const int64_t t = tb + sub;
-                const bool valid = t < t1;
-                const int64_t J = valid ? a.tile_col[t] : 0;
-                const uint32_t cJ = valid ? cand_of(a.cand, J, r) : 0u;
-                scanned += valid && k == 0;
-                const uint64_t heads = ballot(cJ != 0 && k == 0);
-                if (!heads) continue;
-                // compact the tiles with candidates into LDS
+            const int64_t t = ch.t0 + sub;
+            uint32_t cJ = 0;
+            if (sub < ch.len) {
+                const int32_t J = a.tile_col[t];
+                cJ = a.alive[J] & ~a.blocked[J];   // candidates of the column block
+                words += k == 0 ? 3 : 0;
+            }
+            const uint64_t heads = ballot(cJ != 0 && k == 0);
+            if (heads) {
+                // compact the tiles that meet a candidate into LDS
                 wave_sync_lds();
                 if (cJ) {
                     const int slot = __popcll(heads & ((1ull << (lane - k)) - 1ull));
@@ -307,66 +304,127 @@ __global__ void __launch_bounds__(kBlock) k_tile_excl(TileArgs a, int ri) {
                 wave_sync_lds();
                 const int ntc = __popcll(heads);
                 mult += lane == 0 ? ntc : 0;
+                uint32_t hit;
                 if constexpr (T == 16) {
+                    // four tiles per product: A = lane's row of tile g along K, B = tile g's
+                    // candidate vector in every column; the sum over all groups is N_c
                     const int g = lane >> 4, row = lane & 15;
+                    v4i acc = {0, 0, 0, 0};
                     for (int base = 0; base < ntc; base += 4) {
                         const int sl = base + g;
                         const bool v = sl < ntc;
                         const uint32_t m = v ? (sb[sl * 8 + (row >> 1)] >> ((row & 1) << 4)) & 0xFFFFu : 0u;
-                        const uint32_t c = v ? sc[sl] : 0u;
-                        acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(expand16(m), expand16(c), acc, 0, 0, 0);
+                        const uint32_t cv = v ? sc[sl] : 0u;
+                        acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(expand16(m), expand16(cv), acc, 0, 0, 0);
                     }
                     hit = hits16(acc);
                 } else {
                     const int h = lane >> 5, row = lane & 31;
+                    v16i acc = {};
                     for (int sl = 0; sl < ntc; ++sl) {
                         const uint32_t m = sb[sl * 32 + row];
-                        const uint32_t c = sc[sl];
-                        acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(expand16(m >> (16 * h)), expand16(c >> (16 * h)),
+                        const uint32_t cv = sc[sl];
+                        acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(expand16(m >> (16 * h)), expand16(cv >> (16 * h)),
                                                                    acc, 0, 0, 0);
                     }
                     hit = hits32(acc);
                 }
-                if ((hit & rest) == rest) break;
+                hit &= rest;
+                if (hit && lane == 0) atomicOr(&a.hit[ch.I], hit);
+                rest &= ~hit;
             }
         }
-        bool keep_rb = false;
-        int nseg_I = 0;
-        uint32_t decided = 0;
-        if (lane == 0) {
-            uint32_t total;
-            nseg_I = a.rb_nseg[I];
-            if (combine(a.part + a.nI, I, nseg_I, hit & rest, &total)) {
-                const uint32_t out = rest & total;
-                const uint32_t na = rest & ~total;
-                a.alive[I] = na;
-                if (cI) a.inmask[I] |= cI;
-                n_out += __popc(out);
-                keep_rb = na != 0;
-                decided = cI | out;
-            }
-        }
-        // rows decided this round record the round; the next round's active list
-        // takes single-segment row-blocks through the wave buffer, longer ones directly
-        nseg_I = __shfl(nseg_I, 0, kWave);
-        keep_rb = __shfl((int)keep_rb, 0, kWave) != 0;
-        decided = (uint32_t)__shfl((int)decided, 0, kWave);
-        if (lane < T && ((decided >> lane) & 1u)) a.dround[I * T + lane] = r;
-        if (keep_rb && nseg_I > 1) {
-            if (lane == 0) {
-                const unsigned long long p = atomicAdd((unsigned long long*)next_cnt, (unsigned long long)nseg_I);
-                const int s0 = a.rb_seg0[I];
-                for (int q = 0; q < nseg_I; ++q) next[p + q] = s0 + q;
-            }
-        } else {
-            lbuf_push(buf, pend, next, next_cnt, keep_rb && lane == 0, s);
-        }
+        prev_I = ch.I;
+        prev_rest = rest;
     }
-    lbuf_flush(buf, pend, next, next_cnt);
-    int64_t* cnt = a.ctrl->cnt[r & 1];
-    wave_add(&cnt[1], n_out);
-    wave_add(&cnt[4], scanned);
-    wave_add(&cnt[5], mult);
+    int64_t x[2] = {words, mult};
+    block_count(a.stripes, r, {4, 5}, x);
+}
+
+// Phase 3 for the row-blocks of round r (round 1: all), one lane per row-block.
+template <int T>
+__global__ void __launch_bounds__(kBlock) k_tile_fin(TileArgs a, int ri) {
+    const int r = a.ctrl->rbase + ri;
+    __shared__ int64_t spre[kWpb][kWave + 1];
+    __shared__ int64_t st0[kWpb][kWave];
+    const int64_t nrb = r == 1 ? a.nI : a.ctrl->n_act[(r - 1) & 1][1];
+    const int32_t* list = a.rbl[(r - 1) & 1];
+    uint64_t* next_ch = a.chunks[r & 1];
+    int32_t* next_rb = a.rbl[r & 1];
+    int64_t* next_cnt = a.ctrl->n_act[r & 1];
+    const int lane = lane_id(), wid = threadIdx.x / kWave;
+    int64_t* pre = spre[wid];
+    int64_t* s0 = st0[wid];
+    int64_t n_cand = 0, n_out = 0, rbs = 0, written = 0;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t base = (int64_t)blockIdx.x * kBlock + wid * kWave; base < nrb; base += stride) {
+        const int64_t idx = base + lane;
+        bool keep = false;
+        int64_t I = -1, t0 = 0, t1 = 0;
+        if (idx < nrb) {
+            I = r == 1 ? idx : list[idx];
+            const uint32_t al = a.alive[I];
+            if (al) {
+                const uint32_t b = a.blocked[I], h = a.hit[I];
+                const uint32_t c = al & ~b, out = al & b & h, na = al & b & ~h;
+                a.alive[I] = na;
+                if (c) a.inmask[I] |= c;
+                a.blocked[I] = 0;
+                a.hit[I] = 0;
+                uint32_t dec = a.dround ? c | out : 0u;   // per-row rounds: batches only
+                while (dec) {
+                    const int row = __builtin_ctz(dec);
+                    dec &= dec - 1;
+                    a.dround[I * T + row] = r;
+                }
+                n_cand += __popc(c);
+                n_out += __popc(out);
+                ++rbs;
+                if (na) {
+                    keep = true;
+                    t0 = a.rb_chunk[I];
+                    t1 = a.rb_chunk[I + 1];
+                }
+            }
+        }
+        // the row-block and its chunks go to the next round's lists; the wave
+        // reserves space once and writes the chunks cooperatively
+        const uint64_t kb = ballot(keep);
+        if (!kb) continue;
+        const int64_t nc = keep ? t1 - t0 : 0;   // the row-block's round-1 chunks
+        int64_t incl = nc;
+        #pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int64_t o = __shfl_up(incl, off, kWave);
+            if (lane >= off) incl += o;
+        }
+        const int64_t total = __shfl(incl, kWave - 1, kWave);
+        unsigned long long cb = 0, rb = 0;
+        if (lane == 0) {
+            cb = atomicAdd((unsigned long long*)&next_cnt[0], (unsigned long long)total);
+            rb = atomicAdd((unsigned long long*)&next_cnt[1], (unsigned long long)__popcll(kb));
+        }
+        cb = __shfl(cb, 0, kWave);
+        rb = __shfl(rb, 0, kWave);
+        if (keep) next_rb[rb + __popcll(kb & lanes_below())] = (int32_t)I;
+        wave_sync_lds();
+        pre[lane + 1] = incl;
+        if (lane == 0) pre[0] = 0;
+        s0[lane] = t0;
+        wave_sync_lds();
+        for (int64_t q = lane; q < total; q += kWave) {
+            int lo = 0, hi = kWave - 1;   // owner: last lane with pre[owner] <= q
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (pre[mid] <= q) lo = mid; else hi = mid - 1;
+            }
+            next_ch[cb + q] = a.chunks_all[s0[lo] + (q - pre[lo])];
+        }
+        written += lane == 0 ? total : 0;
+        wave_sync_lds();
+    }
+    int64_t x[4] = {n_cand, n_out, rbs, written};
+    block_count(a.stripes, r, {0, 1, 6, 7}, x);
 }
 
 __global__ void k_tile_output(const int32_t* new_id, const uint32_t* inmask, int64_t n, int tshift, uint8_t* in_set) {
@@ -376,27 +434,42 @@ __global__ void k_tile_output(const int32_t* new_id, const uint32_t* inmask, int
     }
 }
 
-__global__ void k_tile_init(const uint32_t* alive0, uint32_t* alive, uint64_t* cand, uint32_t* inmask, uint64_t* part,
-                            int64_t nI) {
+// round state before round 1: every existing row undecided; with key orientation
+// round 1's blocked rows are the rows with any entry
+__global__ void k_tile_init(const uint32_t* hrows, uint32_t* alive, uint32_t* blocked, uint32_t* hit, uint32_t* inmask,
+                            int64_t n, int64_t nI, int T, int orient) {
     for (int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; I < nI; I += (int64_t)gridDim.x * blockDim.x) {
-        alive[I] = alive0[I];
-        cand[I] = 0;
+        const int64_t rows = min((int64_t)T, n - I * T);
+        alive[I] = rows >= 32 ? 0xFFFFFFFFu : ((1u << rows) - 1u);
+        blocked[I] = orient ? hrows[I] : 0u;
+        hit[I] = 0;
         inmask[I] = 0;
-        part[I] = 0;
-        part[nI + I] = 0;
     }
 }
 
 TileArgs make_args(mis_graph* g) {
     TileArgs a;
-    a.seg_rb = g->seg_rb; a.seg_t0 = g->seg_t0; a.seg_t1 = g->seg_t1;
-    a.rb_seg0 = g->rb_seg0; a.rb_nseg = g->rb_nseg;
-    a.tile_col = g->tile_col; a.bits = g->tile_bits; a.key_p = g->key_p;
-    a.alive = g->alive; a.cand = g->cand; a.inmask = g->inmask; a.part = g->part;
-    a.seg_all = g->seg_all; a.seglist[0] = g->seglist[0]; a.seglist[1] = g->seglist[1];
-    a.dround = g->dround;
-    a.meta = g->meta; a.nI = g->nI;
-    a.ctrl = g->ctrl; a.trace = g->trace;
+    a.rb_chunk = g->rb_chunk;
+    a.tile_col = g->tile_col;
+    a.bits = g->tile_bits;
+    a.key_p = g->key_p;
+    a.hrows = g->hrows;
+    a.alive = g->alive;
+    a.blocked = g->blocked;
+    a.hit = g->hit;
+    a.inmask = g->inmask;
+    a.dround = g->count > 0 ? g->dround : nullptr;
+    a.chunks_all = g->chunks_all;
+    a.chunks[0] = g->chunks[0];
+    a.chunks[1] = g->chunks[1];
+    a.rbl[0] = g->rbl[0];
+    a.rbl[1] = g->rbl[1];
+    a.meta = g->meta;
+    a.n = g->n;
+    a.nI = g->nI;
+    a.ctrl = g->ctrl;
+    a.stripes = g->stripes;
+    a.trace = g->trace;
     return a;
 }
 
@@ -404,20 +477,21 @@ template <int T, int ORIENT>
 void launch_phase(mis_graph* g, int phase, int r, hipStream_t s) {
     TileArgs a = make_args(g);
     if (phase == 0) hipLaunchKernelGGL((k_tile_cand<T, ORIENT>), dim3(g->grid_blocks), dim3(kBlock), 0, s, a, r);
-    else hipLaunchKernelGGL((k_tile_excl<T, ORIENT>), dim3(g->grid_blocks), dim3(kBlock), 0, s, a, r);
+    else if (phase == 1) hipLaunchKernelGGL((k_tile_excl<T>), dim3(g->grid_blocks), dim3(kBlock), 0, s, a, r);
+    else hipLaunchKernelGGL((k_tile_fin<T>), dim3(g->grid_blocks), dim3(kBlock), 0, s, a, r);
 }
 
 }  // namespace
 
 int tile_init(mis_graph* g, hipStream_t s) {
     if (g->nI > 0)
-        hipLaunchKernelGGL(k_tile_init, dim3(stream_grid(g->nI)), dim3(kBlock), 0, s, g->alive0, g->alive, g->cand,
-                           g->inmask, g->part, g->nI);
+        hipLaunchKernelGGL(k_tile_init, dim3(stream_grid(g->nI)), dim3(kBlock), 0, s, g->hrows, g->alive, g->blocked,
+                           g->hit, g->inmask, g->n, g->nI, g->tile, g->orient);
     TC_HIP(hipGetLastError());
     return MIS_OK;
 }
 
-// phase 0 = candidate kernel, 1 = exclusion kernel (which closes the round)
+// phase 0 = candidate kernel, 1 = exclusion kernel, 2 = finalize kernel
 int tile_enqueue_phase(mis_graph* g, int phase, int r, hipStream_t s) {
     if (g->tile == 16) {
         if (g->orient) launch_phase<16, 1>(g, phase, r, s); else launch_phase<16, 0>(g, phase, r, s);

@@ -100,13 +100,15 @@ def test_session_mix_equals_alone_and_oracle():
 def test_session_one_at_a_time_device_inputs_and_per_request_options():
     t = T()
     graphs = mixed_requests(10, seed=33)
-    sess = t.Session(arena_bytes=max(footprint(g) for g in graphs) * 2, max_live=1, rounds_per_step=3)
+    options = [dict(path="tile", tile=32, reorder="degree", seed=5), dict(path="csr", seed=5)]
+    need = max(footprint(g, **{k: v for k, v in o.items() if k != "seed"}) for g in graphs for o in options)
+    sess = t.Session(arena_bytes=2 * need, max_live=1, rounds_per_step=3)
     outs = {}
     for i, g in enumerate(graphs):
         rp = torch.from_numpy(g.row_ptr).cuda()
         ci = torch.from_numpy(g.col_idx).cuda()
         out = torch.zeros(max(g.n, 1), dtype=torch.uint8, device="cuda")
-        opts = dict(path="csr", seed=5) if i % 2 else dict(path="tile", tile=32, reorder="degree", seed=5)
+        opts = options[i % 2]
         assert sess.admit(rp, ci, tag=100 + i, out=out, opts=opts)
         assert not sess.admit(rp, ci, tag=999, out=out)         # the one slot is taken
         (d,) = sess.progress(wait=True)
