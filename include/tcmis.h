@@ -64,8 +64,11 @@ enum {
 /* How the rounds are launched (results are identical). */
 enum {
     MIS_LAUNCH_AUTO = 0,      /* hipGraph when capture works, else direct */
-    MIS_LAUNCH_DIRECT = 1,    /* two kernel launches per round, enqueued back to back */
-    MIS_LAUNCH_GRAPH = 2      /* poll_rounds rounds captured once as a hipGraph and replayed */
+    MIS_LAUNCH_DIRECT = 1,    /* one kernel launch per phase (2 CSR, 3 tiles), enqueued back to back */
+    MIS_LAUNCH_GRAPH = 2,     /* poll_rounds rounds captured once as a hipGraph and replayed */
+    MIS_LAUNCH_PERSISTENT = 3 /* poll_rounds rounds per cooperative launch, grid barriers between
+                                 phases (workgroups stay resident; every barrier wait is bounded and
+                                 a timeout is reported as MIS_EINTERNAL) */
 };
 
 /* Input graph: undirected, simple, symmetric CSR, rows sorted ascending. */
@@ -124,7 +127,8 @@ typedef struct {
                                  kernels (the CSR path has no finalize kernel) */
     int32_t launches;         /* timing = 1: rounds enqueued (each launches every kernel once) */
     int32_t trace_cap;        /* in: rounds the trace buffer holds (0 = no trace) */
-    int32_t graph;            /* 1 if full batches of rounds ran as a replayed hipGraph */
+    int32_t graph;            /* 1 if full batches of rounds ran as a replayed hipGraph, 2 if as
+                                 persistent cooperative launches */
     int32_t pad3_;
     int64_t* trace;           /* in: optional HOST int64[3*trace_cap]; out: per round |C_r|,
                                  vertices removed as neighbours of candidates, alive after */

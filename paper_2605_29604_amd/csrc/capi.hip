@@ -21,6 +21,8 @@ int csr_output(mis_graph* g, uint8_t* in_set, hipStream_t s);
 int tile_init(mis_graph* g, hipStream_t s);
 int tile_enqueue_phase(mis_graph* g, int phase, int r, hipStream_t s);
 int tile_output(mis_graph* g, uint8_t* in_set, hipStream_t s);
+int tile_enqueue_rounds(mis_graph* g, int k, hipStream_t s);
+int csr_enqueue_rounds(mis_graph* g, int k, hipStream_t s);
 
 namespace {
 thread_local std::string g_last_error;
@@ -84,7 +86,7 @@ int resolve(const mis_csr* csr, const mis_build_opts* opts, mis_build_opts* o, i
     if (o->reorder < MIS_REORDER_AUTO || o->reorder > MIS_REORDER_RCM) return fail(MIS_EINVAL, "bad reorder");
     if (o->orient < -1 || o->orient > 1) return fail(MIS_EINVAL, "orient must be -1, 0 or 1");
     if (o->poll_rounds < 0 || o->poll_rounds > kTraceCap) return fail(MIS_EINVAL, "poll_rounds out of range");
-    if (o->launch < MIS_LAUNCH_AUTO || o->launch > MIS_LAUNCH_GRAPH) return fail(MIS_EINVAL, "bad launch mode");
+    if (o->launch < MIS_LAUNCH_AUTO || o->launch > MIS_LAUNCH_PERSISTENT) return fail(MIS_EINVAL, "bad launch mode");
     if (o->blocks_per_cu < 0 || o->blocks_per_cu > 32) return fail(MIS_EINVAL, "blocks_per_cu must be in [0, 32]");
     if (count < 0) return fail(MIS_EINVAL, "count must be >= 0");
     if (count > 0) {
@@ -230,7 +232,26 @@ int solve_begin(mis_graph* g, hipStream_t s) {
     return g->path == MIS_PATH_TILE ? tile_init(g, s) : csr_init(g, s);
 }
 
+// Sizes the cooperative grid once per handle (every workgroup must be resident:
+// at most two per compute unit, within what the kernel's resources allow) and
+// launches a persistent round kernel taking (args, k).
+int launch_cooperative(const void* kernel, mis_graph* g, void* args, int k, hipStream_t s) {
+    if (g->coop_blocks == 0) {
+        int dev = 0, cus = 0, per = 0;
+        TC_HIP(hipGetDevice(&dev));
+        TC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        TC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, 0));
+        if (per < 1 || cus < 1) return fail(MIS_EHIP, "the persistent round kernel cannot be resident");
+        g->coop_blocks = cus * std::min(per, 2);
+    }
+    void* kargs[2] = {args, &k};
+    TC_HIP(hipLaunchCooperativeKernel(kernel, dim3((unsigned)g->coop_blocks), dim3(kBlock), kargs, 0, s));
+    return MIS_OK;
+}
+
 int solve_rounds(mis_graph* g, int64_t k, bool allow_graph, hipStream_t s) {
+    if (g->launch == MIS_LAUNCH_PERSISTENT)
+        return g->path == MIS_PATH_TILE ? tile_enqueue_rounds(g, (int)k, s) : csr_enqueue_rounds(g, (int)k, s);
     if (allow_graph && g->launch != MIS_LAUNCH_DIRECT && k == g->poll_rounds && ensure_graph(g)) {
         if (hipGraphLaunch(g->graph_exec, s) != hipSuccess) return fail(MIS_EHIP, "hipGraphLaunch failed");
         return MIS_OK;
@@ -427,6 +448,8 @@ int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, mis_stats* st, 
     }
     for (auto& e : ev) (void)hipEventDestroy(e);
     if (rc != MIS_OK) return rc;
+    if (g->n > 0 && (sg->ctrl->error & kErrBarrier))
+        return fail(MIS_EINTERNAL, "a grid barrier of the persistent round kernel timed out");
     if (g->n > 0) TC_CHECK(solve_output(g, in_set, s));
     if (g->n == 0) {   // nothing ran: no staging contents of this graph
         sg->ctrl->round = 0;
@@ -451,7 +474,7 @@ int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, mis_stats* st, 
         st->alg_bytes = ab;
         for (int ph = 0; ph < 3; ++ph) st->kernel_ms[ph] = (float)kms[ph];
         st->launches = (int32_t)launches;
-        st->graph = g->graph_exec != nullptr && !timing && g->launch != MIS_LAUNCH_DIRECT;
+        st->graph = timing ? 0 : g->launch == MIS_LAUNCH_PERSISTENT ? 2 : (g->graph_exec != nullptr && g->launch != MIS_LAUNCH_DIRECT);
     }
     return MIS_OK;
 }

@@ -30,6 +30,7 @@ struct Ctrl {
     int64_t alive;          // undecided vertices after `round` rounds
     int64_t n_in;           // vertices in the set so far
     int64_t n_act[2][2];    // active work items per list buffer (CSR: [light, heavy]; tile: [chunks, row-blocks])
+    unsigned long long bar; // grid-barrier arrivals of persistent launches (only grows)
 };
 // Counter words of a stripe: |C|, removed neighbours, work units u0..u5.
 
@@ -88,6 +89,7 @@ struct mis_graph {
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
     }
     int grid_blocks = 2048;           // persistent grid of the round kernels
+    int coop_blocks = 0;              // grid of the cooperative round kernels (0 = not sized yet)
 
     // workspace (caller-owned device memory)
     char* ws = nullptr;

@@ -148,8 +148,17 @@ __global__ void __launch_bounds__(kBlock) k_radix_hist(const uint64_t* keys, int
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     const int len = block_len(counts, dense_total, count, blockIdx.x);
-    for (int i = threadIdx.x; i < len; i += kBlock)
-        atomicAdd(&cnt[wid][(keys[base + i] >> shift) & (D - 1)], 1);
+    // every key of the thread is loaded before the first counter update
+    constexpr int kIt = kSortTile / kBlock;
+    uint64_t kk[kIt];
+    #pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int i = it * kBlock + threadIdx.x;
+        kk[it] = i < len ? keys[base + i] : 0;
+    }
+    #pragma unroll
+    for (int it = 0; it < kIt; ++it)
+        if (it * kBlock + (int)threadIdx.x < len) atomicAdd(&cnt[wid][(kk[it] >> shift) & (D - 1)], 1);
     __syncthreads();
     for (int d = threadIdx.x; d < D; d += kBlock) {
         int tot = 0;
@@ -178,11 +187,23 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint64_t* keys, 
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     const int len = block_len(counts, dense_total, count, blockIdx.x);
     const int iters = (len + kBlock - 1) / kBlock;
-    for (int it = 0; it < iters; ++it) {
+    // every key (and value) of the thread is loaded before the ranking passes
+    constexpr int kIt = kSortTile / kBlock;
+    uint64_t kk[kIt];
+    uint32_t vv[kIt];
+    #pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int i = it * kBlock + t;
+        kk[it] = i < len ? keys[base + i] : 0;
+        vv[it] = (kVals && i < len) ? vals[base + i] : 0;
+    }
+    #pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        if (it >= iters) continue;   // block-uniform
         const int i = it * kBlock + t;
         const bool valid = i < len;
-        const uint64_t k = valid ? keys[base + i] : 0;
-        const uint32_t val = (kVals && valid) ? vals[base + i] : 0;
+        const uint64_t k = kk[it];
+        const uint32_t val = vv[it];
         const int d = (int)((k >> shift) & (D - 1));
         uint64_t match = ballot(valid);
         #pragma unroll

@@ -100,4 +100,47 @@ __device__ inline void open_round(Ctrl* ctrl, int64_t* stripes, TraceRec* trace,
     }
 }
 
+constexpr uint32_t kErrBarrier = 1u << 8;   // Ctrl::error: a grid barrier wait hit its bound
+constexpr uint32_t kBarrierSpin = 1u << 22;  // polls (each after a short sleep) before giving up
+
+// Grid-wide barrier of a cooperative launch (every workgroup is co-resident).  The
+// arrival counter only grows, so the barrier needs no reset and no generation word:
+// the workgroup whose arrival completes a multiple of the grid size releases the
+// others.  An agent-scope fence before arriving and after leaving makes every
+// workgroup's writes of the phase visible to all workgroups of the next one.  The
+// wait is bounded: after kBarrierSpin polls a workgroup raises kErrBarrier and goes
+// on, so every wave always reaches the end of the kernel.
+__device__ inline void grid_barrier(Ctrl* ctrl) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned long long n = gridDim.x;
+        const unsigned long long old = atomicAdd(&ctrl->bar, 1ull);
+        const unsigned long long target = (old / n + 1) * n;
+        uint32_t spins = 0;
+        while (__hip_atomic_load(&ctrl->bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (++spins > kBarrierSpin) {
+                atomicOr(&ctrl->error, kErrBarrier);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+// End of a persistent batch of k rounds from base rb (after the last barrier):
+// closes round rb + k and moves the base past it.
+__device__ inline void finish_rounds(Ctrl* ctrl, int64_t* stripes, TraceRec* trace, int rb, int k) {
+    if (blockIdx.x == 0 && threadIdx.x < kWave) {
+        close_round(ctrl, stripes, trace, rb + k);
+        if (threadIdx.x == 0) ctrl->rbase = rb + k;
+    }
+}
+
+// Cooperative launch of a persistent round kernel taking (args, k); defined with
+// the round loop.
+int launch_cooperative(const void* kernel, mis_graph* g, void* args, int k, hipStream_t s);
+
 }  // namespace tcmis

@@ -46,8 +46,7 @@ __device__ inline void round_lists(const CsrArgs& a, int r, const int32_t** in_l
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_csr_cand(CsrArgs a, int ri) {
-    const int r = a.ctrl->rbase + ri;   // round number (the batch base is on the device)
+__device__ void csr_cand(const CsrArgs& a, int r) {
     open_round(a.ctrl, a.stripes, a.trace, r);
     const int32_t *L, *H;
     int64_t nl, nh;
@@ -94,8 +93,7 @@ __global__ void __launch_bounds__(kBlock) k_csr_cand(CsrArgs a, int ri) {
     block_count(a.stripes, r, {0, 2, 3}, x);
 }
 
-__global__ void __launch_bounds__(kBlock) k_csr_excl(CsrArgs a, int ri) {
-    const int r = a.ctrl->rbase + ri;   // round number (the batch base is on the device)
+__device__ void csr_excl(const CsrArgs& a, int r) {
     __shared__ int32_t lbuf[kBlock / kWave][2][kWave];
     const uint32_t in_r = tag(r, kIn), out_r = tag(r, kOut);
     const int32_t *L, *H;
@@ -166,6 +164,23 @@ __global__ void __launch_bounds__(kBlock) k_csr_excl(CsrArgs a, int ri) {
     block_count(a.stripes, r, {1, 4, 5}, x);
 }
 
+// One kernel per phase; round r = the batch base on the device + ri.
+__global__ void __launch_bounds__(kBlock) k_csr_cand(CsrArgs a, int ri) { csr_cand(a, a.ctrl->rbase + ri); }
+__global__ void __launch_bounds__(kBlock) k_csr_excl(CsrArgs a, int ri) { csr_excl(a, a.ctrl->rbase + ri); }
+
+// Persistent variant: k rounds in one cooperative launch, a grid barrier after
+// every phase; the last round is closed and the base advanced at the end.
+__global__ void __launch_bounds__(kBlock) k_csr_rounds(CsrArgs a, int k) {
+    const int rb = a.ctrl->rbase;
+    for (int ri = 1; ri <= k; ++ri) {
+        csr_cand(a, rb + ri);
+        grid_barrier(a.ctrl);
+        csr_excl(a, rb + ri);
+        grid_barrier(a.ctrl);
+    }
+    finish_rounds(a.ctrl, a.stripes, a.trace, rb, k);
+}
+
 __global__ void k_csr_init(const uint64_t* key, uint64_t* ak, uint32_t* st, int64_t n) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         ak[v] = key[v];
@@ -190,6 +205,12 @@ CsrArgs make_args(mis_graph* g) {
 }
 
 }  // namespace
+
+// k rounds as one cooperative launch (see k_csr_rounds)
+int csr_enqueue_rounds(mis_graph* g, int k, hipStream_t s) {
+    CsrArgs a = make_args(g);
+    return launch_cooperative((const void*)k_csr_rounds, g, &a, k, s);
+}
 
 int csr_init(mis_graph* g, hipStream_t s) {
     if (g->n > 0)

@@ -156,8 +156,7 @@ __device__ inline v4i expand16(uint32_t x) {
 }
 
 template <int T, int ORIENT>
-__global__ void __launch_bounds__(kBlock) k_tile_cand(TileArgs a, int ri) {
-    const int r = a.ctrl->rbase + ri;   // round number (the batch base is on the device)
+__device__ void tile_cand(const TileArgs& a, int r) {
     using G = Geo<T>;
     open_round(a.ctrl, a.stripes, a.trace, r);
     if (ORIENT && r == 1) return;       // blocked = rows with any entry, set at solve start
@@ -256,8 +255,7 @@ __device__ inline uint32_t hits32(const v16i& acc) {
 }
 
 template <int T>
-__global__ void __launch_bounds__(kBlock) k_tile_excl(TileArgs a, int ri) {
-    const int r = a.ctrl->rbase + ri;
+__device__ void tile_excl(const TileArgs& a, int r) {
     using G = Geo<T>;
     __shared__ uint32_t sbits[kWpb][G::kTpi * G::kWpt];
     __shared__ uint32_t scand[kWpb][G::kTpi];
@@ -343,8 +341,7 @@ __global__ void __launch_bounds__(kBlock) k_tile_excl(TileArgs a, int ri) {
 
 // Phase 3 for the row-blocks of round r (round 1: all), one lane per row-block.
 template <int T>
-__global__ void __launch_bounds__(kBlock) k_tile_fin(TileArgs a, int ri) {
-    const int r = a.ctrl->rbase + ri;
+__device__ void tile_fin(const TileArgs& a, int r) {
     __shared__ int64_t spre[kWpb][kWave + 1];
     __shared__ int64_t st0[kWpb][kWave];
     const int64_t nrb = r == 1 ? a.nI : a.ctrl->n_act[(r - 1) & 1][1];
@@ -427,6 +424,30 @@ __global__ void __launch_bounds__(kBlock) k_tile_fin(TileArgs a, int ri) {
     block_count(a.stripes, r, {0, 1, 6, 7}, x);
 }
 
+// One kernel per phase; round r = the batch base on the device + ri.
+template <int T, int ORIENT>
+__global__ void __launch_bounds__(kBlock) k_tile_cand(TileArgs a, int ri) { tile_cand<T, ORIENT>(a, a.ctrl->rbase + ri); }
+template <int T>
+__global__ void __launch_bounds__(kBlock) k_tile_excl(TileArgs a, int ri) { tile_excl<T>(a, a.ctrl->rbase + ri); }
+template <int T>
+__global__ void __launch_bounds__(kBlock) k_tile_fin(TileArgs a, int ri) { tile_fin<T>(a, a.ctrl->rbase + ri); }
+
+// Persistent variant: k rounds in one cooperative launch, a grid barrier after
+// every phase; the last round is closed and the base advanced at the end.
+template <int T, int ORIENT>
+__global__ void __launch_bounds__(kBlock) k_tile_rounds(TileArgs a, int k) {
+    const int rb = a.ctrl->rbase;
+    for (int ri = 1; ri <= k; ++ri) {
+        tile_cand<T, ORIENT>(a, rb + ri);
+        grid_barrier(a.ctrl);
+        tile_excl<T>(a, rb + ri);
+        grid_barrier(a.ctrl);
+        tile_fin<T>(a, rb + ri);
+        grid_barrier(a.ctrl);
+    }
+    finish_rounds(a.ctrl, a.stripes, a.trace, rb, k);
+}
+
 __global__ void k_tile_output(const int32_t* new_id, const uint32_t* inmask, int64_t n, int tshift, uint8_t* in_set) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         const int64_t p = new_id[v];
@@ -481,7 +502,19 @@ void launch_phase(mis_graph* g, int phase, int r, hipStream_t s) {
     else hipLaunchKernelGGL((k_tile_fin<T>), dim3(g->grid_blocks), dim3(kBlock), 0, s, a, r);
 }
 
+template <int T, int ORIENT>
+int launch_rounds(mis_graph* g, int k, hipStream_t s) {
+    TileArgs a = make_args(g);
+    return launch_cooperative((const void*)k_tile_rounds<T, ORIENT>, g, &a, k, s);
+}
+
 }  // namespace
+
+// k rounds as one cooperative launch (see k_tile_rounds)
+int tile_enqueue_rounds(mis_graph* g, int k, hipStream_t s) {
+    if (g->tile == 16) return g->orient ? launch_rounds<16, 1>(g, k, s) : launch_rounds<16, 0>(g, k, s);
+    return g->orient ? launch_rounds<32, 1>(g, k, s) : launch_rounds<32, 0>(g, k, s);
+}
 
 int tile_init(mis_graph* g, hipStream_t s) {
     if (g->nI > 0)

@@ -21,7 +21,7 @@ PATH_AUTO, PATH_TILE, PATH_CSR = 0, 1, 2
 REORDER_AUTO, REORDER_NONE, REORDER_DEGREE, REORDER_KEY, REORDER_RCM = 0, 1, 2, 3, 4
 
 PATHS = {"auto": PATH_AUTO, "tile": PATH_TILE, "csr": PATH_CSR}
-LAUNCHES = {"auto": 0, "direct": 1, "graph": 2}
+LAUNCHES = {"auto": 0, "direct": 1, "graph": 2, "persistent": 3}
 REORDERS = {"auto": REORDER_AUTO, "none": REORDER_NONE, "degree": REORDER_DEGREE,
             "key": REORDER_KEY, "rcm": REORDER_RCM}
 

@@ -228,6 +228,45 @@ def test_launch_modes_and_graph_replays(cfg):
         T.mis_free_tiles(h)
 
 
+@pytest.mark.parametrize("cfg", FAST_CONFIGS, ids=lambda c: "-".join(map(str, c)))
+def test_persistent_cooperative_rounds(cfg):
+    # poll_rounds rounds per cooperative launch with grid barriers between phases:
+    # same set, round count and trace as the oracle, over several solves per handle,
+    # with a round limit, and for a batch
+    T = tcmis_mod()
+    for name in ("er10k", "grid24", "rmat12"):
+        g = gen.workload(name, seed=3)
+        k = oracle.keys(g.row_ptr, 6)
+        want, rounds, trace = expected(g.row_ptr, g.col_idx, k)
+        drp, dci = to_dev(g.row_ptr, g.col_idx)
+        h = T.mis_build_tiles(drp, dci, path=cfg[0], tile=cfg[1], reorder=cfg[2], orient=cfg[3], seed=6,
+                              poll_rounds=3, launch="persistent")
+        for rep in range(2):
+            print(f"case persistent {name} cfg={cfg} rep={rep}", flush=True)
+            out, st = T.mis_solve(h)
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy(), want), f"{name} rep {rep}"
+            assert np.array_equal(st["trace"], trace) and st["rounds"] == rounds and st["graph"] == 2
+        if rounds > 1:
+            part, r1, _ = expected(g.row_ptr, g.col_idx, k, max_rounds=rounds - 1)
+            out, st = T.mis_solve(h, max_rounds=rounds - 1)
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy(), part) and st["rounds"] == r1
+        T.mis_free_tiles(h)
+    graphs = [gen.make(*s) for s in gen.batch_spec(12, seed=4, n_min=30, n_max=3000)]
+    rp, ci, off = gen.union(graphs)
+    drp, dci = to_dev(rp, ci)
+    h = T.mis_build_batch(drp, dci, off, path=cfg[0], tile=cfg[1], reorder=cfg[2], orient=cfg[3], seed=2,
+                          launch="persistent")
+    out, st, rounds, sizes = T.mis_solve_batch(h)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    for i, g in enumerate(graphs):
+        want, r, _ = expected(g.row_ptr, g.col_idx, oracle.keys(g.row_ptr, 2))
+        assert np.array_equal(got[off[i]:off[i + 1]], want) and rounds[i] == r, f"batch graph {i}"
+    T.mis_free_tiles(h)
+
+
 BATCH_CONFIGS = [("csr", 0, "none", 0), ("tile", 16, "key", 1), ("tile", 32, "degree", 0), ("tile", 16, "rcm", 1)]
 
 
