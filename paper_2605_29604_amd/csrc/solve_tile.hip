@@ -114,18 +114,11 @@ __device__ inline void round_chunks(const TileArgs& a, int r, const uint64_t** l
     else { *list = a.chunks[(r - 1) & 1]; *n = a.ctrl->n_act[(r - 1) & 1][0]; }
 }
 
-// Chunks [*c0, *c1) of this wave: a contiguous share, so a wave meets the chunks of
-// one row-block one after another and can skip them once the row-block is done.
-// The wave index is read through readfirstlane so that chunk descriptors and
-// row-block words load as wave-uniform (scalar) values.
-__device__ inline void wave_range(int64_t nch, int64_t* c0, int64_t* c1) {
-    const int64_t nwaves = (int64_t)gridDim.x * kWpb;
-    const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-    const int64_t w = (int64_t)blockIdx.x * kWpb + wid;
-    const int64_t per = (nch + nwaves - 1) / nwaves;
-    *c0 = min(nch, w * per);
-    *c1 = min(nch, *c0 + per);
-}
+// Waves take runs of kChunkRun consecutive chunks, runs dealt out cyclically: a run
+// keeps a row-block's chunks together, so once the row-block has nothing left to
+// learn the rest of the run is skipped from registers, while the cyclic deal spreads
+// the row-blocks that must be scanned to the end over all waves.
+constexpr int kChunkRun = 8;
 
 struct Chunk {
     int64_t t0, I;
@@ -139,6 +132,17 @@ __device__ inline Chunk decode(uint64_t w) {
     c.I = (int64_t)(w & ((1ull << 27) - 1));
     return c;
 }
+
+// lane j's 64-bit value, as a wave-uniform (scalar) value; j must be uniform
+__device__ inline uint64_t lane_word(uint64_t x, int j) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, j);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), j);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// keeps a loaded value from being sunk into the branch that uses it, so the load is
+// issued together with the ones before the branch
+__device__ inline void issue_now(int32_t x) { asm volatile("" ::"v"(x)); }
 
 __device__ inline uint32_t wave_or(uint32_t x) {
     for (int off = kWave / 2; off > 0; off >>= 1) x |= (uint32_t)__shfl_xor((int)x, off, kWave);
@@ -162,21 +166,31 @@ __device__ void tile_cand(const TileArgs& a, int r) {
     if (ORIENT && r == 1) return;       // blocked = rows with any entry, set at solve start
     __shared__ uint64_t rkeys[kWpb][T];   // orient = 0: the chunk's row keys
     const uint64_t* list;
-    int64_t nch, c, c1;
+    int64_t nch;
     round_chunks(a, r, &list, &nch);
-    wave_range(nch, &c, &c1);
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     const int sub = lane / G::kLpt, k = lane % G::kLpt;
     uint64_t* rk = rkeys[wid];
     int64_t words = 0, bytes = 0;
     int64_t prev_I = -1;
     uint32_t prev_open = 0;
-    for (; c < c1; ++c) {
-        const Chunk ch = decode(list[c]);
-        words += lane == 0 ? 2 : 0;
+    const int64_t nwaves = (int64_t)gridDim.x * kWpb;
+    const int64_t w0 = (int64_t)blockIdx.x * kWpb + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    for (int64_t cb = w0 * kChunkRun; cb < nch; cb += nwaves * kChunkRun) {
+      // the wave's next run of chunk descriptors in one load
+      const int64_t c1 = min(nch, cb + kChunkRun);
+      const uint64_t dl = cb + lane < c1 ? list[cb + lane] : 0;
+      const int nb = (int)(c1 - cb);
+      words += lane == 0 ? 2 * nb : 0;
+      for (int jc = 0; jc < nb; ++jc) {
+        const Chunk ch = decode(lane_word(dl, jc));
         // a row-block whose undecided rows are all blocked stays so for the rest of
         // this kernel (blocked only grows): skip its further chunks without a load
         if (ch.I == prev_I && prev_open == 0) continue;
+        const int64_t t = ch.t0 + sub;
+        const bool v = sub < ch.len;
+        const int32_t J = v ? a.tile_col[t] : 0;   // loads with the row-block masks
+        issue_now(J);
         uint32_t open = a.alive[ch.I] & ~a.blocked[ch.I];   // undecided rows not yet blocked
         words += lane == 0 ? 2 : 0;
         if (open) {
@@ -187,9 +201,7 @@ __device__ void tile_cand(const TileArgs& a, int r) {
                 wave_sync_lds();
             }
             uint32_t m = 0;
-            if (sub < ch.len) {
-                const int64_t t = ch.t0 + sub;
-                const int32_t J = a.tile_col[t];
+            if (v) {
                 const uint32_t aJ = a.alive[J];
                 words += k == 0 ? 2 : 0;
                 if (aJ) {
@@ -221,6 +233,7 @@ __device__ void tile_cand(const TileArgs& a, int r) {
         }
         prev_I = ch.I;
         prev_open = open;
+      }
     }
     int64_t x[2] = {words, bytes};
     block_count(a.stripes, r, {2, 3}, x);
@@ -260,9 +273,8 @@ __device__ void tile_excl(const TileArgs& a, int r) {
     __shared__ uint32_t sbits[kWpb][G::kTpi * G::kWpt];
     __shared__ uint32_t scand[kWpb][G::kTpi];
     const uint64_t* list;
-    int64_t nch, c, c1;
+    int64_t nch;
     round_chunks(a, r, &list, &nch);
-    wave_range(nch, &c, &c1);
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     const int sub = lane / G::kLpt, k = lane % G::kLpt;
     uint32_t* sb = sbits[wid];
@@ -270,19 +282,28 @@ __device__ void tile_excl(const TileArgs& a, int r) {
     int64_t words = 0, mult = 0;
     int64_t prev_I = -1;
     uint32_t prev_rest = 0;
-    for (; c < c1; ++c) {
-        const Chunk ch = decode(list[c]);
-        words += lane == 0 ? 2 : 0;
+    const int64_t nwaves = (int64_t)gridDim.x * kWpb;
+    const int64_t w0 = (int64_t)blockIdx.x * kWpb + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    for (int64_t cb = w0 * kChunkRun; cb < nch; cb += nwaves * kChunkRun) {
+      // the wave's next run of chunk descriptors in one load
+      const int64_t c1 = min(nch, cb + kChunkRun);
+      const uint64_t dl = cb + lane < c1 ? list[cb + lane] : 0;
+      const int nb = (int)(c1 - cb);
+      words += lane == 0 ? 2 * nb : 0;
+      for (int jc = 0; jc < nb; ++jc) {
+        const Chunk ch = decode(lane_word(dl, jc));
         // a row-block whose undecided non-candidates all have a candidate neighbour
         // stays so for the rest of this kernel (hit only grows): skip its chunks
         if (ch.I == prev_I && prev_rest == 0) continue;
+        const int64_t t = ch.t0 + sub;
+        const bool v = sub < ch.len;
+        const int32_t J = v ? a.tile_col[t] : 0;   // loads with the row-block masks
+        issue_now(J);
         uint32_t rest = a.alive[ch.I] & a.blocked[ch.I] & ~a.hit[ch.I];
         words += lane == 0 ? 3 : 0;
         if (rest) {
-            const int64_t t = ch.t0 + sub;
             uint32_t cJ = 0;
-            if (sub < ch.len) {
-                const int32_t J = a.tile_col[t];
+            if (v) {
                 cJ = a.alive[J] & ~a.blocked[J];   // candidates of the column block
                 words += k == 0 ? 3 : 0;
             }
@@ -334,6 +355,7 @@ __device__ void tile_excl(const TileArgs& a, int r) {
         }
         prev_I = ch.I;
         prev_rest = rest;
+      }
     }
     int64_t x[2] = {words, mult};
     block_count(a.stripes, r, {4, 5}, x);
