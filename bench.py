@@ -38,6 +38,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "tile_exclusion_rmat22_traffic.json")
+
+
+def measured_traffic(a):
+    """HBM bytes per launch of the tile exclusion kernel from the committed counter
+    record (rocprofv3 FETCH_SIZE / WRITE_SIZE, calibrated on a device copy), or None
+    when the configuration differs or the kernel sources changed since the counters
+    were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_RECORD))
+    except (OSError, ValueError):
+        return None
+    if (rec.get("workload"), rec.get("tile"), rec.get("reorder"), rec.get("orient"), rec.get("seed")) != \
+            (a.workload, a.tile, a.reorder, a.orient, a.seed):
+        return None
+    for name, digest in rec.get("source_sha256", {}).items():
+        path = os.path.join(ROOT, "paper_2605_29604_amd", "csrc", name)
+        if not os.path.exists(path) or hashlib.sha256(open(path, "rb").read()).hexdigest() != digest:
+            return None
+    return rec["traffic_bytes_per_launch"]
 
 
 def parse():
@@ -356,8 +377,10 @@ def main():
     bytes_k = [u[0] * 4 + u[1], u[2] * 4 + u[3] * S, u[4] * 24 + u[5] * 8][k]
     avg_ms = stt["kernel_ms"][k] / launches
     achieved = (bytes_k / launches) / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic(a) if k == 1 else None
     res["roofline"] = {"kernel": names[k], "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                       "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                       "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                       "traffic": None if traffic is None else int(traffic),
                        "avg_launch_us": round(avg_ms * 1e3, 3), "launches": launches,
                        "alg_bytes_per_launch": int(bytes_k / launches)}
 

@@ -3,12 +3,15 @@ of a named workload (the CSR resident on the device), one CSR-path solve, and on
 device-to-device copy of a known size, whose FETCH_SIZE / WRITE_SIZE calibrate the
 counters against bytes actually moved.
 
-    python -m paper_2605_29604_amd.profile_run [--workload rmat22] [--copy-mib 256]
+    python paper_2605_29604_amd/profile_run.py [--workload rmat22] [--copy-mib 256]
 """
 from __future__ import annotations
 
 import argparse
+import os
 import sys
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 
 
 def main() -> int:
