@@ -167,23 +167,26 @@ __global__ void __launch_bounds__(kBlock) k_radix_hist(const uint64_t* keys, int
     }
 }
 
-// Stable scatter of one block: every key gets its rank among equal digits of the
+// Stable scatter of one block.  Every key gets its rank among equal digits of the
 // block (DB ballots inside a wavefront, LDS counters across wavefronts and
-// iterations) and is written straight to its global position.
+// iterations); the keys are first placed in LDS in (digit, rank) order, then
+// written out so that consecutive threads write consecutive positions of one
+// digit's run -- coalesced stores instead of one scattered 8-byte store per key.
 template <int DB, bool kVals>
 __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint64_t* keys, uint64_t* keys_out,
                                                           const uint32_t* vals, uint32_t* vals_out, int64_t count,
                                                           const int32_t* counts, const int32_t* dense_total, int shift,
                                                           int64_t nblocks, const int32_t* offsets) {
     constexpr int D = 1 << DB;
-    __shared__ int32_t base_of[D];
+    constexpr int kPerT = D / kBlock;                 // digits per thread in the local scan
+    __shared__ uint64_t skey[kSortTile];
+    __shared__ uint32_t sval[kVals ? kSortTile : 1];
+    __shared__ int32_t gbase[D];                      // global position of the block's first key of each digit
+    __shared__ int32_t lfirst[D];                     // local position of the block's first key of each digit
+    __shared__ int32_t lrun[D];                       // running local position per digit
     __shared__ int32_t wave_cnt[kWavesPerBlock][D];
+    __shared__ int32_t wsum[kWavesPerBlock];
     const int t = threadIdx.x, lane = lane_id(), wid = t / kWave;
-    for (int d = t; d < D; d += kBlock) {
-        base_of[d] = offsets[(int64_t)d * nblocks + blockIdx.x];
-        for (int w = 0; w < kWavesPerBlock; ++w) wave_cnt[w][d] = 0;
-    }
-    __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     const int len = block_len(counts, dense_total, count, blockIdx.x);
     const int iters = (len + kBlock - 1) / kBlock;
@@ -197,13 +200,48 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint64_t* keys, 
         kk[it] = i < len ? keys[base + i] : 0;
         vv[it] = (kVals && i < len) ? vals[base + i] : 0;
     }
+    for (int d = t; d < D; d += kBlock) {
+        lrun[d] = 0;
+        gbase[d] = offsets[(int64_t)d * nblocks + blockIdx.x];
+        for (int w = 0; w < kWavesPerBlock; ++w) wave_cnt[w][d] = 0;
+    }
+    __syncthreads();
+    // local digit histogram and its exclusive scan
+    #pragma unroll
+    for (int it = 0; it < kIt; ++it)
+        if (it * kBlock + t < len) atomicAdd(&lrun[(int)((kk[it] >> shift) & (D - 1))], 1);
+    __syncthreads();
+    int mine[kPerT > 0 ? kPerT : 1];
+    int local = 0;
+    #pragma unroll
+    for (int j = 0; j < kPerT; ++j) {
+        mine[j] = lrun[t * kPerT + j];
+        local += mine[j];
+    }
+    int incl = local;
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int o = __shfl_up(incl, off, kWave);
+        if (lane >= off) incl += o;
+    }
+    if (lane == kWave - 1) wsum[wid] = incl;
+    __syncthreads();
+    int before = incl - local;
+    for (int w = 0; w < wid; ++w) before += wsum[w];
+    #pragma unroll
+    for (int j = 0; j < kPerT; ++j) {
+        lfirst[t * kPerT + j] = before;
+        lrun[t * kPerT + j] = before;
+        before += mine[j];
+    }
+    __syncthreads();
+    // stable ranks: local position = digit's running position + rank among the
+    // block's earlier keys of that digit
     #pragma unroll
     for (int it = 0; it < kIt; ++it) {
         if (it >= iters) continue;   // block-uniform
         const int i = it * kBlock + t;
         const bool valid = i < len;
         const uint64_t k = kk[it];
-        const uint32_t val = vv[it];
         const int d = (int)((k >> shift) & (D - 1));
         uint64_t match = ballot(valid);
         #pragma unroll
@@ -217,10 +255,10 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint64_t* keys, 
         if (valid && lane == leader) wave_cnt[wid][d] = __popcll(match);
         __syncthreads();
         if (valid) {
-            int64_t dst = (int64_t)base_of[d] + rank;
-            for (int w = 0; w < wid; ++w) dst += wave_cnt[w][d];
-            keys_out[dst] = k;
-            if (kVals) vals_out[dst] = val;
+            int pos = lrun[d] + rank;
+            for (int w = 0; w < wid; ++w) pos += wave_cnt[w][d];
+            skey[pos] = k;
+            if (kVals) sval[pos] = vv[it];
         }
         __syncthreads();
         for (int dd = t; dd < D; dd += kBlock) {
@@ -229,9 +267,17 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint64_t* keys, 
                 add += wave_cnt[w][dd];
                 wave_cnt[w][dd] = 0;
             }
-            base_of[dd] += add;
+            lrun[dd] += add;
         }
         __syncthreads();
+    }
+    // coalesced write-out in (digit, rank) order
+    for (int j = t; j < len; j += kBlock) {
+        const uint64_t k = skey[j];
+        const int d = (int)((k >> shift) & (D - 1));
+        const int64_t dst = (int64_t)gbase[d] + (j - lfirst[d]);
+        keys_out[dst] = k;
+        if (kVals) vals_out[dst] = sval[j];
     }
 }
 
