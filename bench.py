@@ -79,6 +79,7 @@ def parse():
     p.add_argument("--serve-requests", type=int, default=2000)
     p.add_argument("--serve-pool", type=int, default=48)
     p.add_argument("--serve-live", type=int, default=8)
+    p.add_argument("--no-tune", action="store_true")
     return p.parse_args()
 
 
@@ -88,6 +89,42 @@ def log(msg):
 
 def pct(x, q):
     return round(float(np.percentile(np.asarray(x), q)), 3) if len(x) else None
+
+
+def bench_tune(a, torch, gen, tcmis, rp, ci):
+    """The autotuner's pick (path, tile size, order, workgroups per CU) for the R-MAT
+    graph and for the 256^3 mesh, with the build + solve time of the pick."""
+    out = {}
+    tcmis.mis_autotune_clear()
+    cases = [(a.workload, rp, ci)]
+    t0 = time.perf_counter()
+    grid = gen.workload("grid256", seed=1)
+    log(f"autotune: grid256 generated in {time.perf_counter() - t0:.1f}s")
+    cases.append(("grid256", torch.from_numpy(grid.row_ptr).cuda(), torch.from_numpy(grid.col_idx).cuda()))
+    for name, r, c in cases:
+        t = time.perf_counter()
+        opts, cached = tcmis.mis_autotune(r, c, seed=a.seed)
+        tune_s = time.perf_counter() - t
+        for _ in range(2):
+            h = tcmis.mis_build_tiles(r, c, **opts)
+            tcmis.mis_solve(h, trace_cap=0)
+            tcmis.mis_free_tiles(h)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(3):
+            h = tcmis.mis_build_tiles(r, c, **opts)
+            tcmis.mis_solve(h, trace_cap=0)
+            tcmis.mis_free_tiles(h)
+        torch.cuda.synchronize()
+        step = (time.perf_counter() - t) / 3
+        edges = c.numel() // 2
+        out[name] = {"pick": {k: opts[k] for k in ("path", "tile", "reorder", "orient", "blocks_per_cu")},
+                     "tune_s": round(tune_s, 3), "step_ms": round(step * 1e3, 4),
+                     "step_medges_s": round(edges / step / 1e6, 1)}
+        log(f"autotune {name}: {out[name]}")
+    del cases, grid
+    torch.cuda.empty_cache()
+    return out
 
 
 def bench_batch(a, torch, gen, tcmis):
@@ -383,6 +420,16 @@ def main():
                        "traffic": None if traffic is None else int(traffic),
                        "avg_launch_us": round(avg_ms * 1e3, 3), "launches": launches,
                        "alg_bytes_per_launch": int(bytes_k / launches)}
+
+    # round-loop launch modes of the same solve (identical results)
+    modes = {}
+    for launch in ("direct", "graph", "persistent"):
+        lt, lo, lst, _, _ = time_solve(dict(tile_cfg, launch=launch), max(a.steps, 10), a.warmup)
+        modes[launch] = {"solve_ms": round(lt * 1e3, 4), "same_set": bool(torch.equal(lo, out_tile)),
+                         "graph_flag": lst["graph"]}
+    res["launch_modes"] = modes
+    if not a.no_tune:
+        res["autotune"] = bench_tune(a, torch, gen, tcmis, rp, ci)
 
     if not a.no_batch:
         res["batch"] = bench_batch(a, torch, gen, tcmis)
