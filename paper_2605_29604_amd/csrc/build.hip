@@ -502,8 +502,7 @@ size_t layout(mis_graph* g, char* base) {
         take(&g->chunks[b], (size_t)g->chunk_cap * 8);
         take(&g->rbl[b], (size_t)nI * 4);
     }
-    take(&g->alive, (size_t)nI * 4);
-    take(&g->blocked, (size_t)nI * 4);
+    take(&g->rs, (size_t)nI * 8);
     take(&g->hit, (size_t)nI * 4);
     take(&g->inmask, (size_t)nI * 4);
     take(&g->dround, (size_t)nI * T * 4);

@@ -65,6 +65,13 @@ struct Meta {
 
 }  // namespace tcmis
 
+// A row-block's round state on the tile path, kept together so that one 8-byte load
+// reads both masks of a column block (bit r = row r of the block).
+struct RowState {
+    uint32_t alive;     // undecided rows
+    uint32_t blocked;   // rows with an undecided higher-priority neighbour (this round)
+};
+
 struct mis_graph {
     // input (caller-owned device CSR)
     int64_t n = 0, nnz = 0;
@@ -145,8 +152,7 @@ struct mis_graph {
     uint64_t* chunks_all = nullptr;   // [chunk_cap] every row-block's chunks (round 1)
     uint64_t* chunks[2] = {nullptr, nullptr};   // [chunk_cap] next round's chunks
     int32_t* rbl[2] = {nullptr, nullptr};       // [nI] next round's active row-blocks
-    uint32_t* alive = nullptr;        // [nI] undecided rows
-    uint32_t* blocked = nullptr;      // [nI] rows with an undecided higher-priority neighbour (this round)
+    RowState* rs = nullptr;           // [nI] undecided rows and this round's blocked rows
     uint32_t* hit = nullptr;          // [nI] rows with a candidate neighbour (this round)
     uint32_t* inmask = nullptr;       // [nI] rows in the set
     int32_t* dround = nullptr;        // [nI*tile] round in which each row was decided

@@ -6,9 +6,11 @@
 //                             .. rb_chunk[I+1]) (round 1 lists them all)
 //   tile_bits                 T=16: 8 words per tile, word w = rows 2w (low 16 bits)
 //                             and 2w+1 (high 16 bits); T=32: 32 words, one per row
-//   alive[I]                  undecided rows of row-block I (bit r)
-//   blocked[I], hit[I]        this round's Phase-1 and Phase-2 row masks, built with
-//                             atomic ORs and cleared by the finalize kernel
+//   rs[I] = {alive, blocked}  undecided rows of row-block I (bit r) and this round's
+//                             Phase-1 mask, side by side so that one 8-byte load
+//                             reads a column block's candidates
+//   hit[I]                    this round's Phase-2 mask; blocked and hit are built
+//                             with atomic ORs and cleared by the finalize kernel
 //
 // Each round is three kernels over a list of tile chunks: at most 64 tiles (T=16)
 // or 16 tiles (T=32) of one row-block, described by one word (first tile, length,
@@ -55,8 +57,7 @@ struct TileArgs {
     const uint32_t* bits;
     const uint64_t* key_p;
     const uint32_t* hrows;
-    uint32_t* alive;
-    uint32_t* blocked;
+    RowState* rs;
     uint32_t* hit;
     uint32_t* inmask;
     int32_t* dround;
@@ -140,9 +141,21 @@ __device__ inline uint64_t lane_word(uint64_t x, int j) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-// keeps a loaded value from being sunk into the branch that uses it, so the load is
-// issued together with the ones before the branch
-__device__ inline void issue_now(int32_t x) { asm volatile("" ::"v"(x)); }
+// A wave-uniform word through the scalar cache, which takes no vector address
+// processing (the limit of the round kernels, whose tile loads and column-block
+// gathers keep the address units busy).  Only for row-block masks that no wave
+// writes during the pass, in the one-phase kernels: the scalar cache is refreshed
+// at each launch but not at the grid barriers of the persistent kernel.
+template <bool kScalar>
+__device__ inline uint32_t mask_load(const uint32_t* p) {
+    if constexpr (kScalar) return *(const __attribute__((address_space(4))) uint32_t*)p;
+    else return *p;
+}
+
+// keeps the loads issued so far where they are (no wait is implied): a load whose
+// only use sits behind a branch would otherwise be moved into the branch, after the
+// loads it was meant to overlap
+__device__ inline void keep_issued() { asm volatile("" ::: "memory"); }
 
 __device__ inline uint32_t wave_or(uint32_t x) {
     for (int off = kWave / 2; off > 0; off >>= 1) x |= (uint32_t)__shfl_xor((int)x, off, kWave);
@@ -159,7 +172,7 @@ __device__ inline v4i expand16(uint32_t x) {
     return o;
 }
 
-template <int T, int ORIENT>
+template <int T, int ORIENT, bool kScalar>
 __device__ void tile_cand(const TileArgs& a, int r) {
     using G = Geo<T>;
     open_round(a.ctrl, a.stripes, a.trace, r);
@@ -187,11 +200,14 @@ __device__ void tile_cand(const TileArgs& a, int r) {
         // a row-block whose undecided rows are all blocked stays so for the rest of
         // this kernel (blocked only grows): skip its further chunks without a load
         if (ch.I == prev_I && prev_open == 0) continue;
-        const int64_t t = ch.t0 + sub;
+        // lanes past the chunk's end repeat its last tile (no branch around the load)
         const bool v = sub < ch.len;
-        const int32_t J = v ? a.tile_col[t] : 0;   // loads with the row-block masks
-        issue_now(J);
-        uint32_t open = a.alive[ch.I] & ~a.blocked[ch.I];   // undecided rows not yet blocked
+        const int64_t t = ch.t0 + min(sub, ch.len - 1);
+        const uint32_t J = (uint32_t)a.tile_col[t];   // in flight with the row-block masks
+        keep_issued();
+        // undecided rows not yet blocked: alive is fixed during the pass, blocked is
+        // read through the vector path, where other waves' ORs show up sooner
+        uint32_t open = mask_load<kScalar>(&a.rs[ch.I].alive) & ~a.rs[ch.I].blocked;
         words += lane == 0 ? 2 : 0;
         if (open) {
             if (!ORIENT && ch.I != prev_I) {   // stage the row-block's keys once
@@ -201,9 +217,9 @@ __device__ void tile_cand(const TileArgs& a, int r) {
                 wave_sync_lds();
             }
             uint32_t m = 0;
-            if (v) {
-                const uint32_t aJ = a.alive[J];
-                words += k == 0 ? 2 : 0;
+            const uint32_t aJ = v ? a.rs[J].alive : 0u;
+            words += k == 0 && v ? 2 : 0;
+            {
                 if (aJ) {
                     uint32_t wd[8];
                     load8<T>(a.bits, t, k, wd);
@@ -228,7 +244,7 @@ __device__ void tile_cand(const TileArgs& a, int r) {
                 }
             }
             m = wave_or(m);
-            if (m && lane == 0) atomicOr(&a.blocked[ch.I], m);
+            if (m && lane == 0) atomicOr(&a.rs[ch.I].blocked, m);
             open &= ~m;
         }
         prev_I = ch.I;
@@ -267,7 +283,7 @@ __device__ inline uint32_t hits32(const v16i& acc) {
     return h;
 }
 
-template <int T>
+template <int T, bool kScalar>
 __device__ void tile_excl(const TileArgs& a, int r) {
     using G = Geo<T>;
     __shared__ uint32_t sbits[kWpb][G::kTpi * G::kWpt];
@@ -295,18 +311,20 @@ __device__ void tile_excl(const TileArgs& a, int r) {
         // a row-block whose undecided non-candidates all have a candidate neighbour
         // stays so for the rest of this kernel (hit only grows): skip its chunks
         if (ch.I == prev_I && prev_rest == 0) continue;
-        const int64_t t = ch.t0 + sub;
+        // lanes past the chunk's end repeat its last tile (no branch around the load)
         const bool v = sub < ch.len;
-        const int32_t J = v ? a.tile_col[t] : 0;   // loads with the row-block masks
-        issue_now(J);
-        uint32_t rest = a.alive[ch.I] & a.blocked[ch.I] & ~a.hit[ch.I];
+        const int64_t t = ch.t0 + min(sub, ch.len - 1);
+        const uint32_t J = (uint32_t)a.tile_col[t];   // in flight with the row-block masks
+        keep_issued();
+        // alive and blocked are fixed during the pass; hit is read through the vector
+        // path, where other waves' ORs show up sooner
+        uint32_t rest = mask_load<kScalar>(&a.rs[ch.I].alive) & mask_load<kScalar>(&a.rs[ch.I].blocked) &
+                        ~a.hit[ch.I];
         words += lane == 0 ? 3 : 0;
         if (rest) {
-            uint32_t cJ = 0;
-            if (v) {
-                cJ = a.alive[J] & ~a.blocked[J];   // candidates of the column block
-                words += k == 0 ? 3 : 0;
-            }
+            const uint2 sJ = *reinterpret_cast<const uint2*>(&a.rs[J]);
+            const uint32_t cJ = v ? sJ.x & ~sJ.y : 0u;   // candidates of the column block
+            words += k == 0 && v ? 3 : 0;
             const uint64_t heads = ballot(cJ != 0 && k == 0);
             if (heads) {
                 // compact the tiles that meet a candidate into LDS
@@ -382,13 +400,13 @@ __device__ void tile_fin(const TileArgs& a, int r) {
         int64_t I = -1, t0 = 0, t1 = 0;
         if (idx < nrb) {
             I = r == 1 ? idx : list[idx];
-            const uint32_t al = a.alive[I];
+            const RowState st = a.rs[I];
+            const uint32_t al = st.alive;
             if (al) {
-                const uint32_t b = a.blocked[I], h = a.hit[I];
+                const uint32_t b = st.blocked, h = a.hit[I];
                 const uint32_t c = al & ~b, out = al & b & h, na = al & b & ~h;
-                a.alive[I] = na;
+                a.rs[I] = RowState{na, 0u};
                 if (c) a.inmask[I] |= c;
-                a.blocked[I] = 0;
                 a.hit[I] = 0;
                 uint32_t dec = a.dround ? c | out : 0u;   // per-row rounds: batches only
                 while (dec) {
@@ -448,9 +466,9 @@ __device__ void tile_fin(const TileArgs& a, int r) {
 
 // One kernel per phase; round r = the batch base on the device + ri.
 template <int T, int ORIENT>
-__global__ void __launch_bounds__(kBlock) k_tile_cand(TileArgs a, int ri) { tile_cand<T, ORIENT>(a, a.ctrl->rbase + ri); }
+__global__ void __launch_bounds__(kBlock) k_tile_cand(TileArgs a, int ri) { tile_cand<T, ORIENT, true>(a, a.ctrl->rbase + ri); }
 template <int T>
-__global__ void __launch_bounds__(kBlock) k_tile_excl(TileArgs a, int ri) { tile_excl<T>(a, a.ctrl->rbase + ri); }
+__global__ void __launch_bounds__(kBlock) k_tile_excl(TileArgs a, int ri) { tile_excl<T, true>(a, a.ctrl->rbase + ri); }
 template <int T>
 __global__ void __launch_bounds__(kBlock) k_tile_fin(TileArgs a, int ri) { tile_fin<T>(a, a.ctrl->rbase + ri); }
 
@@ -460,9 +478,9 @@ template <int T, int ORIENT>
 __global__ void __launch_bounds__(kBlock) k_tile_rounds(TileArgs a, int k) {
     const int rb = a.ctrl->rbase;
     for (int ri = 1; ri <= k; ++ri) {
-        tile_cand<T, ORIENT>(a, rb + ri);
+        tile_cand<T, ORIENT, false>(a, rb + ri);
         grid_barrier(a.ctrl);
-        tile_excl<T>(a, rb + ri);
+        tile_excl<T, false>(a, rb + ri);
         grid_barrier(a.ctrl);
         tile_fin<T>(a, rb + ri);
         grid_barrier(a.ctrl);
@@ -479,12 +497,11 @@ __global__ void k_tile_output(const int32_t* new_id, const uint32_t* inmask, int
 
 // round state before round 1: every existing row undecided; with key orientation
 // round 1's blocked rows are the rows with any entry
-__global__ void k_tile_init(const uint32_t* hrows, uint32_t* alive, uint32_t* blocked, uint32_t* hit, uint32_t* inmask,
-                            int64_t n, int64_t nI, int T, int orient) {
+__global__ void k_tile_init(const uint32_t* hrows, RowState* rs, uint32_t* hit, uint32_t* inmask, int64_t n, int64_t nI,
+                            int T, int orient) {
     for (int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; I < nI; I += (int64_t)gridDim.x * blockDim.x) {
         const int64_t rows = min((int64_t)T, n - I * T);
-        alive[I] = rows >= 32 ? 0xFFFFFFFFu : ((1u << rows) - 1u);
-        blocked[I] = orient ? hrows[I] : 0u;
+        rs[I] = RowState{rows >= 32 ? 0xFFFFFFFFu : ((1u << rows) - 1u), orient ? hrows[I] : 0u};
         hit[I] = 0;
         inmask[I] = 0;
     }
@@ -497,8 +514,7 @@ TileArgs make_args(mis_graph* g) {
     a.bits = g->tile_bits;
     a.key_p = g->key_p;
     a.hrows = g->hrows;
-    a.alive = g->alive;
-    a.blocked = g->blocked;
+    a.rs = g->rs;
     a.hit = g->hit;
     a.inmask = g->inmask;
     a.dround = g->count > 0 ? g->dround : nullptr;
@@ -540,8 +556,8 @@ int tile_enqueue_rounds(mis_graph* g, int k, hipStream_t s) {
 
 int tile_init(mis_graph* g, hipStream_t s) {
     if (g->nI > 0)
-        hipLaunchKernelGGL(k_tile_init, dim3(stream_grid(g->nI)), dim3(kBlock), 0, s, g->hrows, g->alive, g->blocked,
-                           g->hit, g->inmask, g->n, g->nI, g->tile, g->orient);
+        hipLaunchKernelGGL(k_tile_init, dim3(stream_grid(g->nI)), dim3(kBlock), 0, s, g->hrows, g->rs, g->hit,
+                           g->inmask, g->n, g->nI, g->tile, g->orient);
     TC_HIP(hipGetLastError());
     return MIS_OK;
 }
