@@ -63,7 +63,8 @@ enum {
 
 /* How the rounds are launched (results are identical). */
 enum {
-    MIS_LAUNCH_AUTO = 0,      /* hipGraph when capture works, else direct */
+    MIS_LAUNCH_AUTO = 0,      /* direct on a handle's first solve; from its second solve on a
+                                 hipGraph (captured then, once) when capture works */
     MIS_LAUNCH_DIRECT = 1,    /* one kernel launch per phase (2 CSR, 3 tiles), enqueued back to back */
     MIS_LAUNCH_GRAPH = 2,     /* poll_rounds rounds captured once as a hipGraph and replayed */
     MIS_LAUNCH_PERSISTENT = 3 /* poll_rounds rounds per cooperative launch, grid barriers between

@@ -252,7 +252,10 @@ int launch_cooperative(const void* kernel, mis_graph* g, void* args, int k, hipS
 int solve_rounds(mis_graph* g, int64_t k, bool allow_graph, hipStream_t s) {
     if (g->launch == MIS_LAUNCH_PERSISTENT)
         return g->path == MIS_PATH_TILE ? tile_enqueue_rounds(g, (int)k, s) : csr_enqueue_rounds(g, (int)k, s);
-    if (allow_graph && g->launch != MIS_LAUNCH_DIRECT && k == g->poll_rounds && ensure_graph(g)) {
+    // auto: a handle solved once gains nothing from a capture, which costs more than
+    // the launches it replaces; capture when it is solved again
+    const bool graph = g->launch == MIS_LAUNCH_GRAPH || (g->launch == MIS_LAUNCH_AUTO && g->solves > 1);
+    if (allow_graph && graph && k == g->poll_rounds && ensure_graph(g)) {
         if (hipGraphLaunch(g->graph_exec, s) != hipSuccess) return fail(MIS_EHIP, "hipGraphLaunch failed");
         return MIS_OK;
     }
@@ -387,6 +390,7 @@ int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, mis_stats* st, 
 
     Staging* sg = nullptr;
     TC_CHECK(staging(&sg));
+    ++g->solves;
     TC_CHECK(solve_begin(g, s));
 
     const int P = phases(g);

@@ -89,6 +89,7 @@ struct mis_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     bool graph_failed = false;
+    int64_t solves = 0;               // mis_solve calls on this handle (auto launch captures from the 2nd)
 
     ~mis_graph() {
         if (graph_exec) (void)hipGraphExecDestroy(graph_exec);

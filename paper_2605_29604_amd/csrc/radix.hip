@@ -4,11 +4,11 @@
 // scan_scratch_elems / sort_scratch_bytes, and results stay on the device.
 //
 // Scans: reduce-then-scan over tiles of 2048 items (256 threads x 8), recursive on
-// the tile totals.  Radix sort: 8-bit digits, three kernels per pass (per-block
-// digit histogram, exclusive scan of the digit-major histogram, stable scatter);
-// the scatter ranks equal digits inside a wavefront with eight ballots and across
-// the block's wavefronts and iterations through LDS counters, which keeps every
-// pass stable.
+// the tile totals.  Radix sort: 8- to 10-bit digits, three kernels per pass
+// (per-block digit histogram, exclusive scan of the digit-major histogram, stable
+// scatter); within a block every wavefront ranks a contiguous run of keys with
+// one ballot per digit bit and counters of its own, which keeps every pass stable
+// with two block-wide barriers.
 #include <utility>
 
 #include "common.hpp"
@@ -136,29 +136,48 @@ __device__ inline int block_len(const int32_t* counts, const int32_t* dense_tota
     return (int)(rest < 0 ? 0 : (rest < kSortTile ? rest : kSortTile));
 }
 
-// Digit histogram of one block; per-wave LDS counters.
+// Lanes of the wavefront whose valid key has digit d (d < 2^DB), including this
+// lane; empty for an invalid key.  DB ballots, no LDS.
+template <int DB>
+__device__ inline uint64_t digit_peers(bool valid, int d) {
+    uint64_t m = ballot(valid);
+    #pragma unroll
+    for (int b = 0; b < DB; ++b) {
+        const bool bit = (d >> b) & 1;
+        const uint64_t bb = ballot(bit);
+        m &= bit ? bb : ~bb;
+    }
+    return valid ? m : 0ull;
+}
+
+// Keys of a block are split into one contiguous run of kSortTile / 4 keys per
+// wavefront (block order = wavefront, iteration, lane), so every wavefront counts
+// and ranks its keys with counters of its own and no block-wide barrier.
+constexpr int kRunPerWave = kSortTile / kWavesPerBlock;   // 1024
+constexpr int kRunIters = kRunPerWave / kWave;            // 16
+
+// Digit histogram of one block: per-wavefront LDS counters.
 template <int DB>
 __global__ void __launch_bounds__(kBlock) k_radix_hist(const uint64_t* keys, int64_t count, const int32_t* counts,
                                                        const int32_t* dense_total, int shift, int64_t nblocks,
                                                        int32_t* hist) {
     constexpr int D = 1 << DB;
     __shared__ int cnt[kWavesPerBlock][D];
-    const int wid = threadIdx.x / kWave;
+    const int lane = lane_id(), wid = threadIdx.x / kWave;
     for (int i = threadIdx.x; i < kWavesPerBlock * D; i += kBlock) (&cnt[0][0])[i] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     const int len = block_len(counts, dense_total, count, blockIdx.x);
-    // every key of the thread is loaded before the first counter update
-    constexpr int kIt = kSortTile / kBlock;
-    uint64_t kk[kIt];
+    // every key of the lane is loaded before the first counter update
+    uint64_t kk[kRunIters];
     #pragma unroll
-    for (int it = 0; it < kIt; ++it) {
-        const int i = it * kBlock + threadIdx.x;
+    for (int it = 0; it < kRunIters; ++it) {
+        const int i = wid * kRunPerWave + it * kWave + lane;
         kk[it] = i < len ? keys[base + i] : 0;
     }
     #pragma unroll
-    for (int it = 0; it < kIt; ++it)
-        if (it * kBlock + (int)threadIdx.x < len) atomicAdd(&cnt[wid][(kk[it] >> shift) & (D - 1)], 1);
+    for (int it = 0; it < kRunIters; ++it)
+        if (wid * kRunPerWave + it * kWave + lane < len) atomicAdd(&cnt[wid][(kk[it] >> shift) & (D - 1)], 1);
     __syncthreads();
     for (int d = threadIdx.x; d < D; d += kBlock) {
         int tot = 0;
@@ -167,56 +186,68 @@ __global__ void __launch_bounds__(kBlock) k_radix_hist(const uint64_t* keys, int
     }
 }
 
-// Stable scatter of one block.  Every key gets its rank among equal digits of the
-// block (DB ballots inside a wavefront, LDS counters across wavefronts and
-// iterations); the keys are first placed in LDS in (digit, rank) order, then
-// written out so that consecutive threads write consecutive positions of one
-// digit's run -- coalesced stores instead of one scattered 8-byte store per key.
+// Stable scatter of one block.  Each wavefront ranks its run's keys among its own
+// earlier keys of the same digit; one pass over the digits then turns the
+// per-wavefront counts into first positions (block order: digit, wavefront), the
+// keys are placed in LDS in (digit, original order) and written out so that
+// consecutive threads write consecutive positions of one digit's run -- coalesced
+// stores instead of one scattered 8-byte store per key.
 template <int DB, bool kVals>
 __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint64_t* keys, uint64_t* keys_out,
                                                           const uint32_t* vals, uint32_t* vals_out, int64_t count,
                                                           const int32_t* counts, const int32_t* dense_total, int shift,
                                                           int64_t nblocks, const int32_t* offsets) {
     constexpr int D = 1 << DB;
-    constexpr int kPerT = D / kBlock;                 // digits per thread in the local scan
+    constexpr int kPerT = D / kBlock > 0 ? D / kBlock : 1;   // digits per thread in the digit pass
     __shared__ uint64_t skey[kSortTile];
     __shared__ uint32_t sval[kVals ? kSortTile : 1];
-    __shared__ int32_t gbase[D];                      // global position of the block's first key of each digit
-    __shared__ int32_t lfirst[D];                     // local position of the block's first key of each digit
-    __shared__ int32_t lrun[D];                       // running local position per digit
-    __shared__ int32_t wave_cnt[kWavesPerBlock][D];
+    __shared__ int32_t wpos[kWavesPerBlock][D];   // per-wavefront counts, then first positions
+    __shared__ int32_t gdelta[D];                 // global minus local position of each digit's keys
     __shared__ int32_t wsum[kWavesPerBlock];
     const int t = threadIdx.x, lane = lane_id(), wid = t / kWave;
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     const int len = block_len(counts, dense_total, count, blockIdx.x);
-    const int iters = (len + kBlock - 1) / kBlock;
-    // every key (and value) of the thread is loaded before the ranking passes
-    constexpr int kIt = kSortTile / kBlock;
-    uint64_t kk[kIt];
-    uint32_t vv[kIt];
+    int32_t* wc = wpos[wid];
+    for (int d = lane; d < D; d += kWave) wc[d] = 0;
+    // every key (and value) of the lane is loaded before the ranking pass
+    uint64_t kk[kRunIters];
+    uint32_t vv[kRunIters];
     #pragma unroll
-    for (int it = 0; it < kIt; ++it) {
-        const int i = it * kBlock + t;
+    for (int it = 0; it < kRunIters; ++it) {
+        const int i = wid * kRunPerWave + it * kWave + lane;
         kk[it] = i < len ? keys[base + i] : 0;
         vv[it] = (kVals && i < len) ? vals[base + i] : 0;
     }
-    for (int d = t; d < D; d += kBlock) {
-        lrun[d] = 0;
-        gbase[d] = offsets[(int64_t)d * nblocks + blockIdx.x];
-        for (int w = 0; w < kWavesPerBlock; ++w) wave_cnt[w][d] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // rank of each key among the wavefront's earlier keys of its digit
+    int rk[kRunIters];
+    #pragma unroll
+    for (int it = 0; it < kRunIters; ++it) {
+        const int i = wid * kRunPerWave + it * kWave + lane;
+        const int d = (int)((kk[it] >> shift) & (D - 1));
+        const uint64_t m = digit_peers<DB>(i < len, d);
+        const int below = __popcll(m & lanes_below());
+        const int prior = m ? wc[d] : 0;
+        rk[it] = prior + below;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (m && below == 0) wc[d] = prior + __popcll(m);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    // local digit histogram and its exclusive scan
-    #pragma unroll
-    for (int it = 0; it < kIt; ++it)
-        if (it * kBlock + t < len) atomicAdd(&lrun[(int)((kk[it] >> shift) & (D - 1))], 1);
-    __syncthreads();
-    int mine[kPerT > 0 ? kPerT : 1];
+    // digit pass: block totals, their exclusive scan, each wavefront's first position
+    int tot[kPerT];
     int local = 0;
     #pragma unroll
     for (int j = 0; j < kPerT; ++j) {
-        mine[j] = lrun[t * kPerT + j];
-        local += mine[j];
+        const int d = t * kPerT + j;
+        int sum = 0;
+        if (d < D)
+            for (int w = 0; w < kWavesPerBlock; ++w) sum += wpos[w][d];
+        tot[j] = sum;
+        local += sum;
     }
     int incl = local;
     for (int off = 1; off < kWave; off <<= 1) {
@@ -229,53 +260,33 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint64_t* keys, 
     for (int w = 0; w < wid; ++w) before += wsum[w];
     #pragma unroll
     for (int j = 0; j < kPerT; ++j) {
-        lfirst[t * kPerT + j] = before;
-        lrun[t * kPerT + j] = before;
-        before += mine[j];
+        const int d = t * kPerT + j;
+        if (d < D) {
+            gdelta[d] = offsets[(int64_t)d * nblocks + blockIdx.x] - before;
+            int run = before;
+            for (int w = 0; w < kWavesPerBlock; ++w) {
+                const int c = wpos[w][d];
+                wpos[w][d] = run;
+                run += c;
+            }
+        }
+        before += tot[j];
     }
     __syncthreads();
-    // stable ranks: local position = digit's running position + rank among the
-    // block's earlier keys of that digit
     #pragma unroll
-    for (int it = 0; it < kIt; ++it) {
-        if (it >= iters) continue;   // block-uniform
-        const int i = it * kBlock + t;
-        const bool valid = i < len;
-        const uint64_t k = kk[it];
-        const int d = (int)((k >> shift) & (D - 1));
-        uint64_t match = ballot(valid);
-        #pragma unroll
-        for (int b = 0; b < DB; ++b) {
-            const bool bit = (d >> b) & 1;
-            const uint64_t bb = ballot(bit);
-            match &= bit ? bb : ~bb;
-        }
-        const int rank = __popcll(match & lanes_below());
-        const int leader = match ? __builtin_ctzll(match) : 0;
-        if (valid && lane == leader) wave_cnt[wid][d] = __popcll(match);
-        __syncthreads();
-        if (valid) {
-            int pos = lrun[d] + rank;
-            for (int w = 0; w < wid; ++w) pos += wave_cnt[w][d];
-            skey[pos] = k;
+    for (int it = 0; it < kRunIters; ++it) {
+        const int i = wid * kRunPerWave + it * kWave + lane;
+        if (i < len) {
+            const int pos = wc[(int)((kk[it] >> shift) & (D - 1))] + rk[it];
+            skey[pos] = kk[it];
             if (kVals) sval[pos] = vv[it];
         }
-        __syncthreads();
-        for (int dd = t; dd < D; dd += kBlock) {
-            int add = 0;
-            for (int w = 0; w < kWavesPerBlock; ++w) {
-                add += wave_cnt[w][dd];
-                wave_cnt[w][dd] = 0;
-            }
-            lrun[dd] += add;
-        }
-        __syncthreads();
     }
-    // coalesced write-out in (digit, rank) order
+    __syncthreads();
+    // coalesced write-out in (digit, original order)
     for (int j = t; j < len; j += kBlock) {
         const uint64_t k = skey[j];
-        const int d = (int)((k >> shift) & (D - 1));
-        const int64_t dst = (int64_t)gbase[d] + (j - lfirst[d]);
+        const int64_t dst = (int64_t)gdelta[(int)((k >> shift) & (D - 1))] + j;
         keys_out[dst] = k;
         if (kVals) vals_out[dst] = sval[j];
     }
@@ -335,6 +346,13 @@ size_t sort_scratch_bytes(int64_t count) {
     return (size_t)(h + 64 + scan_scratch_elems(h)) * sizeof(int32_t);
 }
 
+// 8-bit digits, or 9/10-bit digits when that saves a pass
+static int digit_bits(int lo_bit, int hi_bit) {
+    const int bits = hi_bit - lo_bit;
+    if (bits > 8 && ceil_div(bits, 10) < ceil_div(bits, 8)) return ceil_div(bits, 9) == ceil_div(bits, 10) ? 9 : 10;
+    return 8;
+}
+
 int radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, int64_t count,
                    const int32_t* counts, int lo_bit, int hi_bit, void* scratch, bool* result_in_alt, hipStream_t s) {
     *result_in_alt = false;
@@ -350,15 +368,13 @@ int radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t*
     int32_t* scan_tmp = total + 64;
     uint64_t *src = keys, *dst = keys_alt;
     uint32_t *vsrc = vals, *vdst = vals_alt;
-    // 8-bit digits, or 9/10-bit digits when that saves a pass
-    const int bits = hi_bit - lo_bit;
-    if (bits > 8 && ceil_div(bits, 10) < ceil_div(bits, 8)) {
-        if (ceil_div(bits, 9) == ceil_div(bits, 10))
-            return sort_passes<9>(&src, &dst, &vsrc, &vdst, count, counts, lo_bit, hi_bit, hist, total,
-                                  scan_tmp, result_in_alt, s);
+    const int db = digit_bits(lo_bit, hi_bit);
+    if (db == 9)
+        return sort_passes<9>(&src, &dst, &vsrc, &vdst, count, counts, lo_bit, hi_bit, hist, total, scan_tmp,
+                              result_in_alt, s);
+    if (db == 10)
         return sort_passes<10>(&src, &dst, &vsrc, &vdst, count, counts, lo_bit, hi_bit, hist, total, scan_tmp,
                                result_in_alt, s);
-    }
     return sort_passes<8>(&src, &dst, &vsrc, &vdst, count, counts, lo_bit, hi_bit, hist, total, scan_tmp,
                           result_in_alt, s);
 }
