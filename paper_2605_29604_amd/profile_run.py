@@ -4,14 +4,101 @@ device-to-device copy of a known size, whose FETCH_SIZE / WRITE_SIZE calibrate t
 counters against bytes actually moved.
 
     python paper_2605_29604_amd/profile_run.py [--workload rmat22] [--copy-mib 256]
+
+With --summarize FETCH_DIR WRITE_DIR (the output folders of one FETCH_SIZE and one
+WRITE_SIZE run of this program) it reads the counters instead, on any machine, and
+writes the exclusion kernel's per-launch HBM traffic to profiles/ (a JSON record
+that bench.py reports while the kernel sources are unchanged, and a short summary).
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import hashlib
+import json
 import os
 import sys
 
-sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+# the sources the exclusion kernel is built from; its record is void once any changes
+TRAFFIC_SOURCES = ("solve_tile.hip", "round.hpp", "graph.hpp")
+
+sys.path.insert(0, ROOT)
+
+
+def _counter(folder: str, name: str, kernel: str):
+    """(first device copy's value, values of every dispatch of `kernel`) in KiB."""
+    copy, vals = None, []
+    with open(os.path.join(folder, "run_counter_collection.csv")) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] != name:
+                continue
+            k, v = r["Kernel_Name"], float(r["Counter_Value"])
+            if "__amd_rocclr_copyBuffer" in k and copy is None:
+                copy = v
+            elif kernel in k:
+                vals.append(v)
+    if copy is None or not vals:
+        raise SystemExit(f"{folder}: no copy or no {kernel} dispatch with {name}")
+    return copy, vals
+
+
+def summarize(a) -> int:
+    kernel = f"k_tile_excl<{a.tile}>"
+    fdir, wdir = a.summarize
+    cf, fetch = _counter(fdir, "FETCH_SIZE", kernel)
+    cw, write = _counter(wdir, "WRITE_SIZE", kernel)
+    if len(fetch) != len(write):
+        raise SystemExit("the two runs dispatched the kernel a different number of times")
+    moved = a.copy_mib * 1024.0
+    ff, wf = moved / cf, moved / cw
+    per = [(f * ff + w * wf) * 1024.0 for f, w in zip(fetch, write)]
+    sha = {}
+    for name in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2605_29604_amd", "csrc", name), "rb") as fh:
+            sha[name] = hashlib.sha256(fh.read()).hexdigest()
+    rec = {"kernel": "tile_exclusion_mfma", "symbol": kernel, "workload": a.workload, "seed": 1, "tile": a.tile,
+           "reorder": a.reorder, "orient": a.orient, "dispatches": len(per), "fetch_kib": fetch, "write_kib": write,
+           "copy_mib": a.copy_mib, "copy_fetch_kib": cf, "copy_write_kib": cw, "fetch_factor": ff,
+           "write_factor": wf, "traffic_bytes_per_dispatch": per, "traffic_bytes_per_launch": sum(per) / len(per),
+           "source_sha256": sha}
+    base = os.path.join(ROOT, "profiles", f"tile_exclusion_{a.workload}_traffic")
+    with open(base + ".json", "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    rows = "\n".join(f"| {i + 1} | {f:.1f} | {w:.1f} | {b / 1e6:.1f} MB |"
+                     for i, (f, w, b) in enumerate(zip(fetch, write, per)))
+    md = f"""# {a.workload}: HBM traffic of the tile exclusion kernel (FETCH_SIZE / WRITE_SIZE)
+
+Commands (two passes, one counter each, from /tmp on the GPU host; REPO = the repository root):
+
+```
+rocprofv3 --pmc FETCH_SIZE --kernel-trace --output-format csv -d $REPO/gpurun_out/pmc_fetch -o run -- \\
+    python3 $REPO/paper_2605_29604_amd/profile_run.py
+rocprofv3 --pmc WRITE_SIZE --kernel-trace --output-format csv -d $REPO/gpurun_out/pmc_write -o run -- \\
+    python3 $REPO/paper_2605_29604_amd/profile_run.py
+python3 paper_2605_29604_amd/profile_run.py --summarize gpurun_out/pmc_fetch gpurun_out/pmc_write
+```
+
+`profile_run.py` copies {a.copy_mib} MiB device to device, then builds and solves {a.workload} on the tile path
+(T={a.tile}, {a.reorder} order, orient={a.orient}, direct launches) and on the CSR path.
+
+Calibration (the {a.copy_mib} MiB copy): FETCH_SIZE reads {cf:.1f} KiB, WRITE_SIZE {cw:.1f} KiB for {moved:.0f} KiB
+moved each way, so FETCH_SIZE is scaled by {ff:.4f} and WRITE_SIZE by {wf:.4f}.
+
+| Round | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes (scaled) |
+|---:|---:|---:|---:|
+{rows}
+
+Average per launch: {sum(per) / len(per) / 1e6:.2f} MB.
+
+`{os.path.basename(base)}.json` holds these figures with the SHA-256 of the kernel sources they were taken on;
+`bench.py` reports `roofline.traffic` only while those sources are unchanged.
+"""
+    with open(base + ".md", "w") as fh:
+        fh.write(md)
+    print(f"{base}.json: {len(per)} launches, {sum(per) / len(per) / 1e6:.2f} MB per launch")
+    return 0
 
 
 def main() -> int:
@@ -21,7 +108,10 @@ def main() -> int:
     p.add_argument("--reorder", default="key")
     p.add_argument("--orient", type=int, default=1)
     p.add_argument("--copy-mib", type=int, default=256)
+    p.add_argument("--summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     a = p.parse_args()
+    if a.summarize:
+        return summarize(a)
     import torch
     from paper_2605_29604_amd import gen, tcmis
 
