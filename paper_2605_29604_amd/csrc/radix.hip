@@ -4,11 +4,12 @@
 // scan_scratch_elems / sort_scratch_bytes, and results stay on the device.
 //
 // Scans: reduce-then-scan over tiles of 2048 items (256 threads x 8), recursive on
-// the tile totals.  Radix sort: 8- to 10-bit digits, three kernels per pass
-// (per-block digit histogram, exclusive scan of the digit-major histogram, stable
-// scatter); within a block every wavefront ranks a contiguous run of keys with
-// one ballot per digit bit and counters of its own, which keeps every pass stable
-// with two block-wide barriers.
+// the tile totals.  Radix sort: 8- to 10-bit digits, five kernels per pass
+// (per-block digit histogram stored block-major, chunk sums, a per-digit scan of
+// the chunk sums, positions in place of the counts, stable scatter); within a block every wavefront ranks a
+// contiguous run of keys with one ballot per digit bit and counters of its own,
+// which keeps every pass stable with two block-wide barriers.
+#include <algorithm>
 #include <utility>
 
 #include "common.hpp"
@@ -182,7 +183,87 @@ __global__ void __launch_bounds__(kBlock) k_radix_hist(const uint64_t* keys, int
     for (int d = threadIdx.x; d < D; d += kBlock) {
         int tot = 0;
         for (int w = 0; w < kWavesPerBlock; ++w) tot += cnt[w][d];
-        hist[(int64_t)d * nblocks + blockIdx.x] = tot;
+        hist[(int64_t)blockIdx.x * D + d] = tot;   // row per block: one coalesced store
+    }
+}
+
+// The histogram is block-major (row b = block b's digit counts), so every block
+// writes and reads its row with coalesced accesses.  Block b's first position for
+// digit d is (keys of smaller digits) + (keys of digit d in earlier blocks); the
+// second term is split into chunks of `chunk` rows: sums per chunk, a per-digit
+// scan of those, then each chunk's rows are turned into positions in place.  The
+// chunk grows with the number of blocks (1 .. 16 rows), so that the chunk kernels
+// have about a thousand workgroups.
+inline int64_t hist_chunk(int64_t nblocks) { return std::min<int64_t>(16, std::max<int64_t>(1, nblocks / 1024)); }
+
+// csum[c * D + d] = digit d's keys in blocks c * chunk .. + chunk - 1
+template <int DB>
+__global__ void __launch_bounds__(kBlock) k_hist_chunk_sum(const int32_t* hist, int64_t nblocks, int64_t chunk,
+                                                           int32_t* csum) {
+    constexpr int D = 1 << DB;
+    const int64_t c = blockIdx.x, b0 = c * chunk, b1 = min(nblocks, b0 + chunk);
+    for (int d = threadIdx.x; d < D; d += kBlock) {
+        int sum = 0;
+        for (int64_t b = b0; b < b1; ++b) sum += hist[b * D + d];
+        csum[c * D + d] = sum;
+    }
+}
+
+// One workgroup per digit d: column d of csum becomes its exclusive scan over the
+// chunks, and dtot[d] the digit's total.
+template <int DB>
+__global__ void __launch_bounds__(kBlock) k_hist_col_scan(int32_t* csum, int64_t nchunks, int32_t* dtot) {
+    constexpr int D = 1 << DB;
+    __shared__ int32_t lw[kWavesPerBlock];
+    const int d = blockIdx.x;
+    const int64_t per = (nchunks + kBlock - 1) / kBlock;
+    const int64_t c0 = threadIdx.x * per, c1 = min(nchunks, c0 + per);
+    int sum = 0;
+    for (int64_t c = c0; c < c1; ++c) sum += csum[c * D + d];
+    int total;
+    const int incl = block_scan<int, OpAdd>(sum, lw, &total);
+    int run = incl - sum;
+    for (int64_t c = c0; c < c1; ++c) {
+        const int x = csum[c * D + d];
+        csum[c * D + d] = run;
+        run += x;
+    }
+    if (threadIdx.x == 0) dtot[d] = total;
+}
+
+// One workgroup per chunk: its rows of the histogram become the blocks' first
+// positions per digit (in place); workgroup 0 also writes the number of keys.
+template <int DB>
+__global__ void __launch_bounds__(kBlock) k_hist_apply(int32_t* hist, const int32_t* csum, const int32_t* dtot,
+                                                       int64_t nblocks, int64_t chunk, int32_t* dense_out) {
+    constexpr int D = 1 << DB;
+    constexpr int kPerT = D / kBlock > 0 ? D / kBlock : 1;
+    __shared__ int32_t lw[kWavesPerBlock];
+    const int t = threadIdx.x;
+    const int64_t c = blockIdx.x, b0 = c * chunk, b1 = min(nblocks, b0 + chunk);
+    // exclusive scan of the digit totals (digits t * kPerT .. are this thread's)
+    int x[kPerT], loc = 0;
+    #pragma unroll
+    for (int j = 0; j < kPerT; ++j) {
+        const int d = t * kPerT + j;
+        x[j] = d < D ? dtot[d] : 0;
+        loc += x[j];
+    }
+    int all;
+    int run = block_scan<int, OpAdd>(loc, lw, &all) - loc;
+    if (dense_out && c == 0 && t == 0) *dense_out = all;
+    #pragma unroll
+    for (int j = 0; j < kPerT; ++j) {
+        const int d = t * kPerT + j;
+        if (d < D) {
+            int pos = run + csum[c * D + d];
+            for (int64_t b = b0; b < b1; ++b) {
+                const int n = hist[b * D + d];
+                hist[b * D + d] = pos;
+                pos += n;
+            }
+        }
+        run += x[j];
     }
 }
 
@@ -208,6 +289,13 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint64_t* keys, 
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     const int len = block_len(counts, dense_total, count, blockIdx.x);
     int32_t* wc = wpos[wid];
+    // this block's global first position of each of the thread's digits (its row)
+    int gb[kPerT];
+    #pragma unroll
+    for (int j = 0; j < kPerT; ++j) {
+        const int d = t * kPerT + j;
+        gb[j] = d < D ? offsets[(int64_t)blockIdx.x * D + d] : 0;
+    }
     for (int d = lane; d < D; d += kWave) wc[d] = 0;
     // every key (and value) of the lane is loaded before the ranking pass
     uint64_t kk[kRunIters];
@@ -262,7 +350,7 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint64_t* keys, 
     for (int j = 0; j < kPerT; ++j) {
         const int d = t * kPerT + j;
         if (d < D) {
-            gdelta[d] = offsets[(int64_t)d * nblocks + blockIdx.x] - before;
+            gdelta[d] = gb[j] - before;
             int run = before;
             for (int w = 0; w < kWavesPerBlock; ++w) {
                 const int c = wpos[w][d];
@@ -294,21 +382,30 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint64_t* keys, 
 
 template <int DB>
 int sort_passes(uint64_t** src, uint64_t** dst, uint32_t** vsrc, uint32_t** vdst, int64_t count,
-                const int32_t* counts, int lo_bit, int hi_bit, int32_t* hist, int32_t* total, int32_t* scan_tmp,
-                bool* alt, hipStream_t s) {
-    const int64_t nb = ceil_div(count, kSortTile);
+                const int32_t* counts, int lo_bit, int hi_bit, int32_t* hist, int32_t* csum, int32_t* dtot,
+                int32_t* total, bool* alt, hipStream_t s) {
+    const int64_t nb = ceil_div(count, kSortTile), chunk = hist_chunk(nb), nchunks = ceil_div(nb, chunk);
     const int32_t* dense = nullptr;
     for (int shift = lo_bit; shift < hi_bit; shift += DB) {
         hipLaunchKernelGGL((k_radix_hist<DB>), dim3((unsigned)nb), dim3(kBlock), 0, s, *src, count, counts, dense, shift,
                            nb, hist);
         TC_HIP(hipGetLastError());
-        TC_CHECK(scan_excl_i32(hist, hist, nb * (1 << DB), counts ? total : nullptr, scan_tmp, s));
+        hipLaunchKernelGGL((k_hist_chunk_sum<DB>), dim3((unsigned)nchunks), dim3(kBlock), 0, s, (const int32_t*)hist,
+                           nb, chunk, csum);
+        TC_HIP(hipGetLastError());
+        hipLaunchKernelGGL((k_hist_col_scan<DB>), dim3(1u << DB), dim3(kBlock), 0, s, csum, nchunks, dtot);
+        TC_HIP(hipGetLastError());
+        int32_t* dense_out = counts ? total : nullptr;   // the first pass counts the kept keys
+        hipLaunchKernelGGL((k_hist_apply<DB>), dim3((unsigned)nchunks), dim3(kBlock), 0, s, hist, (const int32_t*)csum,
+                           (const int32_t*)dtot, nb, chunk, dense_out);
+        TC_HIP(hipGetLastError());
         if (*vsrc)
             hipLaunchKernelGGL((k_radix_scatter<DB, true>), dim3((unsigned)nb), dim3(kBlock), 0, s, *src, *dst, *vsrc,
-                               *vdst, count, counts, dense, shift, nb, hist);
+                               *vdst, count, counts, dense, shift, nb, (const int32_t*)hist);
         else
             hipLaunchKernelGGL((k_radix_scatter<DB, false>), dim3((unsigned)nb), dim3(kBlock), 0, s, *src, *dst,
-                               (const uint32_t*)nullptr, (uint32_t*)nullptr, count, counts, dense, shift, nb, hist);
+                               (const uint32_t*)nullptr, (uint32_t*)nullptr, count, counts, dense, shift, nb,
+                               (const int32_t*)hist);
         TC_HIP(hipGetLastError());
         std::swap(*src, *dst);
         std::swap(*vsrc, *vdst);
@@ -340,10 +437,12 @@ int scan_incl_max_i32(const int32_t* in, int32_t* out, int64_t count, int32_t* s
     return scan_impl<int32_t, OpMax, true>(in, out, count, (int32_t*)nullptr, scratch, s);
 }
 
+// scratch: block-major histogram (nb rows of up to 1024 digits), chunk sums, digit
+// totals, the kept-key count
 size_t sort_scratch_bytes(int64_t count) {
     const int64_t nb = ceil_div(count > 0 ? count : 1, kSortTile);
-    const int64_t h = nb * 1024;   // up to 10-bit digits
-    return (size_t)(h + 64 + scan_scratch_elems(h)) * sizeof(int32_t);
+    const int64_t h = nb * 1024, c = ceil_div(nb, hist_chunk(nb)) * 1024;
+    return (size_t)(h + c + 1024 + 64) * sizeof(int32_t);
 }
 
 // 8-bit digits, or 9/10-bit digits when that saves a pass
@@ -364,19 +463,20 @@ int radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t*
     }
     const int64_t nb = ceil_div(count, kSortTile);
     int32_t* hist = (int32_t*)scratch;
-    int32_t* total = hist + nb * 1024;
-    int32_t* scan_tmp = total + 64;
+    int32_t* csum = hist + nb * 1024;
+    int32_t* dtot = csum + ceil_div(nb, hist_chunk(nb)) * 1024;
+    int32_t* total = dtot + 1024;
     uint64_t *src = keys, *dst = keys_alt;
     uint32_t *vsrc = vals, *vdst = vals_alt;
     const int db = digit_bits(lo_bit, hi_bit);
     if (db == 9)
-        return sort_passes<9>(&src, &dst, &vsrc, &vdst, count, counts, lo_bit, hi_bit, hist, total, scan_tmp,
-                              result_in_alt, s);
+        return sort_passes<9>(&src, &dst, &vsrc, &vdst, count, counts, lo_bit, hi_bit, hist, csum, dtot,
+                              total, result_in_alt, s);
     if (db == 10)
-        return sort_passes<10>(&src, &dst, &vsrc, &vdst, count, counts, lo_bit, hi_bit, hist, total, scan_tmp,
-                               result_in_alt, s);
-    return sort_passes<8>(&src, &dst, &vsrc, &vdst, count, counts, lo_bit, hi_bit, hist, total, scan_tmp,
-                          result_in_alt, s);
+        return sort_passes<10>(&src, &dst, &vsrc, &vdst, count, counts, lo_bit, hi_bit, hist, csum, dtot,
+                               total, result_in_alt, s);
+    return sort_passes<8>(&src, &dst, &vsrc, &vdst, count, counts, lo_bit, hi_bit, hist, csum, dtot,
+                          total, result_in_alt, s);
 }
 
 }  // namespace tcmis
