@@ -384,6 +384,7 @@ template <int T>
 __device__ void tile_fin(const TileArgs& a, int r) {
     __shared__ int64_t spre[kWpb][kWave + 1];
     __shared__ int64_t st0[kWpb][kWave];
+    __shared__ int64_t wres[2][kWpb];   // per wave: chunks and row-blocks to append, then their first slots
     const int64_t nrb = r == 1 ? a.nI : a.ctrl->n_act[(r - 1) & 1][1];
     const int32_t* list = a.rbl[(r - 1) & 1];
     uint64_t* next_ch = a.chunks[r & 1];
@@ -394,8 +395,9 @@ __device__ void tile_fin(const TileArgs& a, int r) {
     int64_t* s0 = st0[wid];
     int64_t n_cand = 0, n_out = 0, rbs = 0, written = 0;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t base = (int64_t)blockIdx.x * kBlock + wid * kWave; base < nrb; base += stride) {
-        const int64_t idx = base + lane;
+    // block-uniform trip count: the workgroup reserves list space once per pass
+    for (int64_t bb = (int64_t)blockIdx.x * kBlock; bb < nrb; bb += stride) {
+        const int64_t idx = bb + wid * kWave + lane;
         bool keep = false;
         int64_t I = -1, t0 = 0, t1 = 0;
         if (idx < nrb) {
@@ -424,10 +426,10 @@ __device__ void tile_fin(const TileArgs& a, int r) {
                 }
             }
         }
-        // the row-block and its chunks go to the next round's lists; the wave
-        // reserves space once and writes the chunks cooperatively
+        // the row-block and its chunks go to the next round's lists; the workgroup
+        // reserves space with one atomic per list and each wave writes its chunks
+        // cooperatively
         const uint64_t kb = ballot(keep);
-        if (!kb) continue;
         const int64_t nc = keep ? t1 - t0 : 0;   // the row-block's round-1 chunks
         int64_t incl = nc;
         #pragma unroll
@@ -436,13 +438,32 @@ __device__ void tile_fin(const TileArgs& a, int r) {
             if (lane >= off) incl += o;
         }
         const int64_t total = __shfl(incl, kWave - 1, kWave);
-        unsigned long long cb = 0, rb = 0;
         if (lane == 0) {
-            cb = atomicAdd((unsigned long long*)&next_cnt[0], (unsigned long long)total);
-            rb = atomicAdd((unsigned long long*)&next_cnt[1], (unsigned long long)__popcll(kb));
+            wres[0][wid] = total;
+            wres[1][wid] = __popcll(kb);
         }
-        cb = __shfl(cb, 0, kWave);
-        rb = __shfl(rb, 0, kWave);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int64_t c = 0, n = 0;
+            for (int w = 0; w < kWpb; ++w) {
+                c += wres[0][w];
+                n += wres[1][w];
+            }
+            unsigned long long c0 = 0, n0 = 0;
+            if (c) c0 = atomicAdd((unsigned long long*)&next_cnt[0], (unsigned long long)c);
+            if (n) n0 = atomicAdd((unsigned long long*)&next_cnt[1], (unsigned long long)n);
+            for (int w = 0; w < kWpb; ++w) {
+                const int64_t cw = wres[0][w], nw = wres[1][w];
+                wres[0][w] = (int64_t)c0;
+                wres[1][w] = (int64_t)n0;
+                c0 += cw;
+                n0 += nw;
+            }
+        }
+        __syncthreads();
+        const int64_t cb = wres[0][wid], rb = wres[1][wid];
+        __syncthreads();   // wres is rewritten by the next pass
+        if (!kb) continue;
         if (keep) next_rb[rb + __popcll(kb & lanes_below())] = (int32_t)I;
         wave_sync_lds();
         pre[lane + 1] = incl;
