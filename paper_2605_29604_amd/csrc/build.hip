@@ -393,8 +393,12 @@ __global__ void k_chunk_count(const int64_t* rb_ptr, int64_t nI, int tpi, int64_
 }
 
 // chunk q belongs to the last row-block whose first chunk is <= q
+// every chunk of the round-1 list twice over: in row-block order (out), and with each
+// row-block's first chunk ahead of all later ones (r1: first chunks at [I], later
+// chunks at nI + their index, holes elsewhere), so that round 1 settles most
+// row-blocks before their later chunks are reached and those are skipped
 __global__ void k_chunk_fill(const int64_t* first, const int64_t* rb_ptr, const Meta* meta, int64_t nI, int tpi,
-                             int64_t cap, uint64_t* out) {
+                             int64_t cap, uint64_t* out, uint64_t* r1) {
     const int64_t total = meta->nchunks;
     GRID_STRIDE(q, cap) {
         if (q >= total) break;
@@ -404,7 +408,9 @@ __global__ void k_chunk_fill(const int64_t* first, const int64_t* rb_ptr, const 
             if (first[mid] <= q) lo = mid; else hi = mid - 1;
         }
         const int64_t t0 = rb_ptr[lo] + (q - first[lo]) * tpi;
-        out[q] = chunk_word(t0, min((int64_t)tpi, rb_ptr[lo + 1] - t0), lo);
+        const uint64_t w = chunk_word(t0, min((int64_t)tpi, rb_ptr[lo + 1] - t0), lo);
+        out[q] = w;
+        r1[q == first[lo] ? lo : nI + q] = w;
     }
 }
 
@@ -498,6 +504,7 @@ size_t layout(mis_graph* g, char* base) {
     if (!g->orient) take(&g->key_p, (size_t)nI * T * 8);
     take(&g->hrows, (size_t)nI * 4);
     take(&g->chunks_all, (size_t)g->chunk_cap * 8);
+    take(&g->chunks_r1, (size_t)(nI + g->chunk_cap) * 8);
     for (int b = 0; b < 2; ++b) {
         take(&g->chunks[b], (size_t)g->chunk_cap * 8);
         take(&g->rbl[b], (size_t)nI * 4);
@@ -640,7 +647,9 @@ int build_tiles_t(mis_graph* g, hipStream_t s) {
     constexpr int kTpi = T == 16 ? 64 : 16;
     LAUNCH(k_chunk_count, nI, g->rb_ptr, nI, kTpi, g->rb_chunk);
     TC_CHECK(scan_excl_i64(g->rb_chunk, g->rb_chunk, nI, &g->meta->nchunks, (int64_t*)g->scan_tmp, s));
-    LAUNCH(k_chunk_fill, g->chunk_cap, g->rb_chunk, g->rb_ptr, g->meta, nI, kTpi, g->chunk_cap, g->chunks_all);
+    TC_HIP(hipMemsetAsync(g->chunks_r1, 0xFF, (size_t)(nI + g->chunk_cap) * 8, s));   // all holes (kChunkHole)
+    LAUNCH(k_chunk_fill, g->chunk_cap, g->rb_chunk, g->rb_ptr, g->meta, nI, kTpi, g->chunk_cap, g->chunks_all,
+           g->chunks_r1);
     hipLaunchKernelGGL(k_rb_chunk_end, dim3(1), dim3(1), 0, s, g->meta, nI, g->rb_chunk);
     TC_HIP(hipGetLastError());
     if (!g->orient) {

@@ -39,6 +39,8 @@ struct Ctrl {
 __host__ __device__ inline uint64_t chunk_word(int64_t t0, int64_t len, int64_t I) {
     return ((uint64_t)t0 << 33) | ((uint64_t)(len - 1) << 27) | (uint64_t)I;
 }
+// an unused slot of a chunk list (no chunk has all bits set: tile indices stay below 2^31 - 1)
+constexpr uint64_t kChunkHole = ~0ull;
 
 // Per-round trace record in the device ring.
 //   c, x, alive : |C_r|, vertices removed as neighbours of candidates, undecided after r
@@ -150,7 +152,9 @@ struct mis_graph {
     uint32_t* tile_bits = nullptr;    // [tile_cap * tile*tile/32] row masks (T=16: two rows per word)
     uint64_t* key_p = nullptr;        // [nI*tile] keys in new order, padding 0 (orient = 0)
     uint32_t* hrows = nullptr;        // [nI] rows with at least one tile entry
-    uint64_t* chunks_all = nullptr;   // [chunk_cap] every row-block's chunks (round 1)
+    uint64_t* chunks_all = nullptr;   // [chunk_cap] every row-block's chunks, row-block order
+    uint64_t* chunks_r1 = nullptr;    // [nI + chunk_cap] round 1's list: row-block I's first chunk at
+                                      // [I], its later chunks at nI + their index, kChunkHole elsewhere
     uint64_t* chunks[2] = {nullptr, nullptr};   // [chunk_cap] next round's chunks
     int32_t* rbl[2] = {nullptr, nullptr};       // [nI] next round's active row-blocks
     RowState* rs = nullptr;           // [nI] undecided rows and this round's blocked rows

@@ -62,6 +62,7 @@ struct TileArgs {
     uint32_t* inmask;
     int32_t* dround;
     const uint64_t* chunks_all;
+    const uint64_t* chunks_r1;
     uint64_t* chunks[2];
     int32_t* rbl[2];
     const Meta* meta;
@@ -108,10 +109,11 @@ __device__ inline uint32_t rows_hit(const uint32_t w[8], uint32_t colmask, int k
     return r;
 }
 
-// Round r's chunk list: round 1 takes every row-block's chunks (built once), later
-// rounds the list the previous finalize wrote.
+// Round r's chunk list: round 1 takes every row-block's chunks, first chunks ahead
+// of later ones, with holes (built once); later rounds the list the previous
+// finalize wrote.
 __device__ inline void round_chunks(const TileArgs& a, int r, const uint64_t** list, int64_t* n) {
-    if (r == 1) { *list = a.chunks_all; *n = a.meta->nchunks; }
+    if (r == 1) { *list = a.chunks_r1; *n = a.nI + a.meta->nchunks; }
     else { *list = a.chunks[(r - 1) & 1]; *n = a.ctrl->n_act[(r - 1) & 1][0]; }
 }
 
@@ -196,7 +198,9 @@ __device__ void tile_cand(const TileArgs& a, int r) {
       const int nb = (int)(c1 - cb);
       words += lane == 0 ? 2 * nb : 0;
       for (int jc = 0; jc < nb; ++jc) {
-        const Chunk ch = decode(lane_word(dl, jc));
+        const uint64_t cw = lane_word(dl, jc);
+        if (cw == kChunkHole) continue;   // an unused slot of the round-1 list
+        const Chunk ch = decode(cw);
         // a row-block whose undecided rows are all blocked stays so for the rest of
         // this kernel (blocked only grows): skip its further chunks without a load
         if (ch.I == prev_I && prev_open == 0) continue;
@@ -307,7 +311,9 @@ __device__ void tile_excl(const TileArgs& a, int r) {
       const int nb = (int)(c1 - cb);
       words += lane == 0 ? 2 * nb : 0;
       for (int jc = 0; jc < nb; ++jc) {
-        const Chunk ch = decode(lane_word(dl, jc));
+        const uint64_t cw = lane_word(dl, jc);
+        if (cw == kChunkHole) continue;   // an unused slot of the round-1 list
+        const Chunk ch = decode(cw);
         // a row-block whose undecided non-candidates all have a candidate neighbour
         // stays so for the rest of this kernel (hit only grows): skip its chunks
         if (ch.I == prev_I && prev_rest == 0) continue;
@@ -540,6 +546,7 @@ TileArgs make_args(mis_graph* g) {
     a.inmask = g->inmask;
     a.dround = g->count > 0 ? g->dround : nullptr;
     a.chunks_all = g->chunks_all;
+    a.chunks_r1 = g->chunks_r1;
     a.chunks[0] = g->chunks[0];
     a.chunks[1] = g->chunks[1];
     a.rbl[0] = g->rbl[0];
