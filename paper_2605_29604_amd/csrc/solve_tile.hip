@@ -515,11 +515,27 @@ __global__ void __launch_bounds__(kBlock) k_tile_rounds(TileArgs a, int k) {
     finish_rounds(a.ctrl, a.stripes, a.trace, rb, k);
 }
 
+__device__ inline uint32_t in_bit(const uint32_t* inmask, int64_t p, int tshift) {
+    return (inmask[p >> tshift] >> (p & ((1 << tshift) - 1))) & 1u;
+}
+
 __global__ void k_tile_output(const int32_t* new_id, const uint32_t* inmask, int64_t n, int tshift, uint8_t* in_set) {
-    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t p = new_id[v];
-        in_set[v] = (uint8_t)((inmask[p >> tshift] >> (p & ((1 << tshift) - 1))) & 1u);
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        in_set[v] = (uint8_t)in_bit(inmask, new_id[v], tshift);
+}
+
+// four vertices per thread: one 16-byte load of new ids, one 4-byte store (in_set
+// 4-byte aligned); the last n % 4 vertices by the first thread
+__global__ void k_tile_output4(const int32_t* new_id, const uint32_t* inmask, int64_t n, int tshift, uint8_t* in_set) {
+    const int64_t nq = n >> 2;
+    const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    for (int64_t i = t0; i < nq; i += (int64_t)gridDim.x * blockDim.x) {
+        const int4 p = reinterpret_cast<const int4*>(new_id)[i];
+        reinterpret_cast<uint32_t*>(in_set)[i] = in_bit(inmask, p.x, tshift) | in_bit(inmask, p.y, tshift) << 8 |
+                                                 in_bit(inmask, p.z, tshift) << 16 | in_bit(inmask, p.w, tshift) << 24;
     }
+    if (t0 == 0)
+        for (int64_t v = nq << 2; v < n; ++v) in_set[v] = (uint8_t)in_bit(inmask, new_id[v], tshift);
 }
 
 // round state before round 1: every existing row undecided; with key orientation
@@ -602,9 +618,13 @@ int tile_enqueue_phase(mis_graph* g, int phase, int r, hipStream_t s) {
 }
 
 int tile_output(mis_graph* g, uint8_t* in_set, hipStream_t s) {
-    if (g->n > 0)
+    const int tshift = g->tile == 16 ? 4 : 5;
+    if (g->n > 0 && ((uintptr_t)in_set & 3) == 0)   // new_id is a 256-byte aligned workspace array
+        hipLaunchKernelGGL(k_tile_output4, dim3(stream_grid(ceil_div(g->n, 4))), dim3(kBlock), 0, s, g->new_id,
+                           g->inmask, g->n, tshift, in_set);
+    else if (g->n > 0)
         hipLaunchKernelGGL(k_tile_output, dim3(stream_grid(g->n)), dim3(kBlock), 0, s, g->new_id, g->inmask, g->n,
-                           g->tile == 16 ? 4 : 5, in_set);
+                           tshift, in_set);
     TC_HIP(hipGetLastError());
     return MIS_OK;
 }

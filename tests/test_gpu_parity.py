@@ -215,7 +215,7 @@ def test_launch_modes_and_graph_replays(cfg):
     k = oracle.keys(g.row_ptr, 6)
     want, rounds, trace = expected(g.row_ptr, g.col_idx, k)
     drp, dci = to_dev(g.row_ptr, g.col_idx)
-    for launch in ("direct", "graph"):
+    for launch in ("direct", "graph", "auto"):
         h = T.mis_build_tiles(drp, dci, path=cfg[0], tile=cfg[1], reorder=cfg[2], orient=cfg[3], seed=6,
                               poll_rounds=2, launch=launch)
         for rep in range(4):
@@ -223,9 +223,42 @@ def test_launch_modes_and_graph_replays(cfg):
             torch.cuda.synchronize()
             assert np.array_equal(out.cpu().numpy(), want), f"{launch} replay {rep}"
             assert np.array_equal(st["trace"], trace) and st["rounds"] == rounds
-            assert st["graph"] == (1 if launch == "graph" else 0)
+            # auto: a handle's first solve is launched directly, later ones replay a capture
+            graph = 1 if launch == "graph" or (launch == "auto" and rep > 0) else 0
+            assert st["graph"] == graph, f"{launch} replay {rep}: graph flag {st['graph']}"
             _ = torch.ones(1000, device="cuda").sum().item()   # unrelated eager work between replays
         T.mis_free_tiles(h)
+
+
+@pytest.mark.parametrize("cfg", FAST_CONFIGS, ids=lambda c: "-".join(map(str, c)))
+def test_output_at_any_alignment(cfg):
+    # the result vector may start at any byte: the tile path writes four results per
+    # store when it is 4-byte aligned and one per store otherwise; n is not a
+    # multiple of 4, so the aligned case also has a tail
+    T = tcmis_mod()
+    g = gen.workload("er10k", seed=7)
+    n = g.n - 3
+    rp = g.row_ptr[: n + 1]
+    keep = g.col_idx[: rp[-1]] < n
+    src = np.repeat(np.arange(n), np.diff(rp))[keep]
+    ci_ = g.col_idx[: rp[-1]][keep]
+    rp2 = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rp2, src + 1, 1)
+    rp2 = np.cumsum(rp2)
+    assert n % 4 != 0
+    k = oracle.keys(rp2, 2)
+    want, _, _ = expected(rp2, ci_, k)
+    drp, dci = to_dev(rp2, ci_)
+    h = T.mis_build_tiles(drp, dci, path=cfg[0], tile=cfg[1], reorder=cfg[2], orient=cfg[3], seed=2, validate=True)
+    base = torch.full((n + 8,), 7, dtype=torch.uint8, device="cuda")
+    for off in range(4):
+        base.fill_(7)
+        out, _ = T.mis_solve(h, out=base[off:off + n])
+        torch.cuda.synchronize()
+        b = base.cpu().numpy()
+        assert np.array_equal(b[off:off + n], want), f"offset {off}"
+        assert (b[:off] == 7).all() and (b[off + n:] == 7).all(), f"offset {off}: wrote outside the result"
+    T.mis_free_tiles(h)
 
 
 @pytest.mark.parametrize("cfg", FAST_CONFIGS, ids=lambda c: "-".join(map(str, c)))
