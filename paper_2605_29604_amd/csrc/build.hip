@@ -122,8 +122,17 @@ __global__ void k_order_keys(const int64_t* rp, const uint64_t* key, int64_t n, 
         } else {
             const int64_t v = n - 1 - i;
             sk[i] = ~key[v];
-            payload[i] = (uint32_t)v;
+            if (payload) payload[i] = (uint32_t)v;
         }
+    }
+}
+
+// order and new ids from sorted ~keys that carry the vertex id in their low 24 bits
+__global__ void k_scatter_order_keys(const uint64_t* sorted_sk, int64_t n, int32_t* order, int32_t* new_id) {
+    GRID_STRIDE(p, n) {
+        const int32_t v = (int32_t)(~sorted_sk[p] & 0xFFFFFFull);
+        order[p] = v;
+        new_id[v] = (int32_t)p;
     }
 }
 
@@ -583,10 +592,18 @@ int build_order(mis_graph* g, hipStream_t s) {
         TC_HIP(hipStreamSynchronize(s));   // nid is freed on return
         return MIS_OK;
     }
-    LAUNCH(k_order_keys, n, g->row_ptr, g->key, n, g->reorder, g->sk, g->pl);
+    // default keys of a single graph hold the vertex id in their low 24 bits: the sort
+    // then moves the keys alone and the order is read back from them
+    const bool ids_in_key = g->reorder == MIS_REORDER_KEY && !g->user_keys && g->count == 0 && n <= (1 << 24);
+    LAUNCH(k_order_keys, n, g->row_ptr, g->key, n, g->reorder, g->sk, ids_in_key ? nullptr : g->pl);
     bool alt = false;
     const int lo = g->reorder == MIS_REORDER_DEGREE ? 0 : (g->user_keys ? 0 : 24);
     const int hi = g->reorder == MIS_REORDER_DEGREE ? 8 : 64;
+    if (ids_in_key) {
+        TC_CHECK(radix_sort_u64(g->sk, g->sk2, nullptr, nullptr, n, nullptr, lo, hi, g->sort_tmp, &alt, s));
+        LAUNCH(k_scatter_order_keys, n, alt ? g->sk2 : g->sk, n, g->order, g->new_id);
+        return MIS_OK;
+    }
     TC_CHECK(radix_sort_u64(g->sk, g->sk2, g->pl, g->pl2, n, nullptr, lo, hi, g->sort_tmp, &alt, s));
     LAUNCH(k_scatter_order, n, alt ? g->pl2 : g->pl, n, g->order, g->new_id);
     return MIS_OK;

@@ -192,9 +192,9 @@ __global__ void __launch_bounds__(kBlock) k_radix_hist(const uint64_t* keys, int
 // digit d is (keys of smaller digits) + (keys of digit d in earlier blocks); the
 // second term is split into chunks of `chunk` rows: sums per chunk, a per-digit
 // scan of those, then each chunk's rows are turned into positions in place.  The
-// chunk grows with the number of blocks (1 .. 16 rows), so that the chunk kernels
-// have about a thousand workgroups.
-inline int64_t hist_chunk(int64_t nblocks) { return std::min<int64_t>(16, std::max<int64_t>(1, nblocks / 1024)); }
+// chunk grows with the number of blocks (1 .. 16 rows), so that the per-digit scan
+// has a few hundred chunks to scan and the chunk kernels enough workgroups.
+inline int64_t hist_chunk(int64_t nblocks) { return std::min<int64_t>(16, std::max<int64_t>(1, nblocks / 256)); }
 
 // csum[c * D + d] = digit d's keys in blocks c * chunk .. + chunk - 1
 template <int DB>
