@@ -98,12 +98,22 @@ __global__ void k_keys(const int64_t* rp, int64_t n, uint64_t seed, const int64_
     }
 }
 
-__global__ void k_identity_order(int32_t* order, int32_t* new_id, int64_t n) {
-    GRID_STRIDE(v, n) { order[v] = (int32_t)v; new_id[v] = (int32_t)v; }
+// Every kernel that fixes the vertex order also writes ndeg[p], the degree of the
+// vertex at new position p (the new row pointer is its exclusive scan).
+__global__ void k_identity_order(const int64_t* rp, int32_t* order, int32_t* new_id, int32_t* ndeg, int64_t n) {
+    GRID_STRIDE(v, n) {
+        order[v] = (int32_t)v;
+        new_id[v] = (int32_t)v;
+        ndeg[v] = (int32_t)(rp[v + 1] - rp[v]);
+    }
 }
 
-__global__ void k_invert(const int32_t* new_id, int32_t* order, int64_t n) {
-    GRID_STRIDE(v, n) order[new_id[v]] = (int32_t)v;
+__global__ void k_invert(const int64_t* rp, const int32_t* new_id, int32_t* order, int32_t* ndeg, int64_t n) {
+    GRID_STRIDE(v, n) {
+        const int32_t p = new_id[v];
+        order[p] = (int32_t)v;
+        ndeg[p] = (int32_t)(rp[v + 1] - rp[v]);
+    }
 }
 
 // Sort keys of the degree-class and priority orders (ascending, stable sort).
@@ -128,25 +138,22 @@ __global__ void k_order_keys(const int64_t* rp, const uint64_t* key, int64_t n, 
 }
 
 // order and new ids from sorted ~keys that carry the vertex id in their low 24 bits
-__global__ void k_scatter_order_keys(const uint64_t* sorted_sk, int64_t n, int32_t* order, int32_t* new_id) {
+__global__ void k_scatter_order_keys(const int64_t* rp, const uint64_t* sorted_sk, int64_t n, int32_t* order,
+                                     int32_t* new_id, int32_t* ndeg) {
     GRID_STRIDE(p, n) {
         const int32_t v = (int32_t)(~sorted_sk[p] & 0xFFFFFFull);
         order[p] = v;
         new_id[v] = (int32_t)p;
+        ndeg[p] = (int32_t)(rp[v + 1] - rp[v]);
     }
 }
 
-__global__ void k_scatter_order(const uint32_t* sorted_payload, int64_t n, int32_t* order, int32_t* new_id) {
+__global__ void k_scatter_order(const int64_t* rp, const uint32_t* sorted_payload, int64_t n, int32_t* order,
+                                int32_t* new_id, int32_t* ndeg) {
     GRID_STRIDE(p, n) {
         const int32_t v = (int32_t)sorted_payload[p];
         order[p] = v;
         new_id[v] = (int32_t)p;
-    }
-}
-
-__global__ void k_new_degrees(const int64_t* rp, const int32_t* order, int64_t n, int32_t* ndeg) {
-    GRID_STRIDE(p, n) {
-        const int32_t v = order[p];
         ndeg[p] = (int32_t)(rp[v + 1] - rp[v]);
     }
 }
@@ -576,7 +583,7 @@ int build_order(mis_graph* g, hipStream_t s) {
     const int64_t n = g->n;
     if (n == 0) return MIS_OK;
     if (g->reorder == MIS_REORDER_NONE) {
-        LAUNCH(k_identity_order, n, g->order, g->new_id, n);
+        LAUNCH(k_identity_order, n, g->row_ptr, g->order, g->new_id, g->ndeg, n);
         return MIS_OK;
     }
     if (g->reorder == MIS_REORDER_RCM) {
@@ -588,7 +595,7 @@ int build_order(mis_graph* g, hipStream_t s) {
         std::vector<int32_t> nid;
         TC_CHECK(host_rcm(rp.data(), ci.data(), n, nid));
         TC_HIP(hipMemcpyAsync(g->new_id, nid.data(), n * 4, hipMemcpyHostToDevice, s));
-        LAUNCH(k_invert, n, g->new_id, g->order, n);
+        LAUNCH(k_invert, n, g->row_ptr, g->new_id, g->order, g->ndeg, n);
         TC_HIP(hipStreamSynchronize(s));   // nid is freed on return
         return MIS_OK;
     }
@@ -601,11 +608,11 @@ int build_order(mis_graph* g, hipStream_t s) {
     const int hi = g->reorder == MIS_REORDER_DEGREE ? 8 : 64;
     if (ids_in_key) {
         TC_CHECK(radix_sort_u64(g->sk, g->sk2, nullptr, nullptr, n, nullptr, lo, hi, g->sort_tmp, &alt, s));
-        LAUNCH(k_scatter_order_keys, n, alt ? g->sk2 : g->sk, n, g->order, g->new_id);
+        LAUNCH(k_scatter_order_keys, n, g->row_ptr, alt ? g->sk2 : g->sk, n, g->order, g->new_id, g->ndeg);
         return MIS_OK;
     }
     TC_CHECK(radix_sort_u64(g->sk, g->sk2, g->pl, g->pl2, n, nullptr, lo, hi, g->sort_tmp, &alt, s));
-    LAUNCH(k_scatter_order, n, alt ? g->pl2 : g->pl, n, g->order, g->new_id);
+    LAUNCH(k_scatter_order, n, g->row_ptr, alt ? g->pl2 : g->pl, n, g->order, g->new_id, g->ndeg);
     return MIS_OK;
 }
 
@@ -614,8 +621,7 @@ int build_tiles_t(mis_graph* g, hipStream_t s) {
     constexpr int kTshift = T == 16 ? 4 : 5;
     const int64_t n = g->n, nnz = g->nnz, nI = g->nI;
     TC_HIP(hipMemsetAsync(g->meta, 0, sizeof(Meta), s));
-    // 1. new row pointer
-    LAUNCH(k_new_degrees, n, g->row_ptr, g->order, n, g->ndeg);
+    // 1. new row pointer (the degrees in new order were written with the order)
     TC_CHECK(scan_excl_i32(g->ndeg, g->ndeg, n, g->ndeg + n, (int32_t*)g->scan_tmp, s));
     // 2. entries in new-row order, one lane per entry
     const int mode = !g->orient ? 0 : (g->reorder == MIS_REORDER_KEY ? 1 : 2);
