@@ -341,53 +341,91 @@ __global__ void __launch_bounds__(kBlock) k_head_write(const uint64_t* ent, cons
 // one lane per tile (T=16) or per quarter tile (T=32, rows 8k..8k+7): OR the
 // tile's entries into 8 registers, store them, and OR the rows that have an entry
 // into hrows of the tile's row-block (lanes of one row-block combine first)
+// Tile bitmaps and the rows with entries.  A wavefront takes 64 consecutive tiles,
+// reads their sorted entries together (coalesced), finds each entry's tile by a
+// binary search over the 64 tile starts in LDS, ORs the entry's bit into that
+// tile's bitmap in LDS, and writes the 64 bitmaps out as one contiguous run.  Bit
+// (row r, column c) of a tile is bit r * T + c of its words.
 template <int T>
-__global__ void k_tile_bits(const uint64_t* ent, const int32_t* tile_start, const int32_t* tile_row, const Meta* meta,
-                            int64_t cap, uint32_t* bits, uint32_t* hrows) {
-    constexpr int L = T == 16 ? 1 : 4;
-    const int64_t nt = meta->ntiles;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    // wave-uniform trip count: every lane reaches the combine step of every pass
-    for (int64_t base = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~(kWave - 1)); base < cap * L;
-         base += stride) {
-        const int64_t gid = base + lane_id();
-        const int64_t t = gid / L;
-        const int k = (int)(gid % L);
-        int32_t I = -1;
-        uint32_t rm = 0;
-        if (gid < cap * L && t < nt) {
-            const int64_t e0 = tile_start[t];
-            const int64_t e1 = t + 1 < nt ? tile_start[t + 1] : meta->nvalid;
-            uint32_t w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            for (int64_t e = e0; e < e1; ++e) {
-                const uint64_t x = ent[e];
-                const uint32_t r = (uint32_t)(x & (T - 1));
-                const uint32_t c = (uint32_t)((x >> 5) & (T - 1));
-                if (T == 16) {
-                    const uint32_t word = r >> 1, bit = 1u << (((r & 1) << 4) | c);
-                    #pragma unroll
-                    for (int j = 0; j < 8; ++j) w[j] |= word == (uint32_t)j ? bit : 0u;
-                } else {
-                    if ((int)(r >> 3) != k) continue;
-                    #pragma unroll
-                    for (int j = 0; j < 8; ++j) w[j] |= (r & 7) == (uint32_t)j ? (1u << c) : 0u;
-                }
-            }
-            uint4* dst = (uint4*)(bits + t * (T * T / 32) + 8 * k);
-            dst[0] = make_uint4(w[0], w[1], w[2], w[3]);
-            dst[1] = make_uint4(w[4], w[5], w[6], w[7]);
+__global__ void __launch_bounds__(kBlock) k_tile_bits(const uint64_t* ent, const int32_t* tile_start,
+                                                      const int32_t* tile_row, const Meta* meta, uint32_t* bits,
+                                                      uint32_t* hrows) {
+    constexpr int W = T * T / 32;   // bitmap words per tile
+    constexpr int kWpb = kBlock / kWave;
+    __shared__ uint32_t sbits[kWpb][kWave * W];
+    __shared__ int32_t sstart[kWpb][kWave];
+    const int lane = lane_id(), wid = threadIdx.x / kWave;
+    uint32_t* sb = sbits[wid];
+    int32_t* ss = sstart[wid];
+    const int64_t nt = meta->ntiles, nvalid = meta->nvalid;
+    const int64_t ntask = (nt + kWave - 1) / kWave;
+    const int64_t tstride = (int64_t)gridDim.x * kWpb;
+    // a task's tile starts, row-blocks and entry bound, loaded one task ahead
+    int32_t n_start = 0, n_row = -1;
+    int64_t n_hi = 0;
+    auto fetch = [&](int64_t task) {
+        if (task >= ntask) return;
+        const int64_t t0 = task * kWave;
+        const int ntl = (int)min<int64_t>(kWave, nt - t0);
+        n_start = lane < ntl ? tile_start[t0 + lane] : 0x7FFFFFFF;
+        n_row = lane < ntl ? tile_row[t0 + lane] : -1;
+        n_hi = t0 + ntl < nt ? (int64_t)tile_start[t0 + ntl] : nvalid;
+    };
+    int64_t task = (int64_t)blockIdx.x * kWpb + wid;
+    fetch(task);
+    for (; task < ntask; task += tstride) {
+        const int64_t t0 = task * kWave;
+        const int ntl = (int)min<int64_t>(kWave, nt - t0);   // tiles of this task
+        const int32_t start = n_start, row = n_row;
+        const int64_t e_hi = n_hi;
+        fetch(task + tstride);
+        const int64_t e_lo = __shfl(start, 0, kWave);
+        ss[lane] = start;
+        #pragma unroll
+        for (int q = 0; q < W; ++q) sb[q * kWave + lane] = 0;
+        wave_sync_lds();
+        for (int64_t eb = e_lo; eb < e_hi; eb += 4 * kWave) {
+            uint64_t xs[4];
             #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                if (T == 16) {
-                    rm |= (uint32_t)((w[j] & 0xFFFFu) != 0) << (2 * j);
-                    rm |= (uint32_t)((w[j] >> 16) != 0) << (2 * j + 1);
-                } else {
-                    rm |= (uint32_t)(w[j] != 0) << (8 * k + j);
+            for (int u = 0; u < 4; ++u) {   // four entry loads in flight per lane
+                const int64_t e = eb + u * kWave + lane;
+                xs[u] = e < e_hi ? ent[e] : 0;
+            }
+            #pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t e = eb + u * kWave + lane;
+                if (e < e_hi) {
+                    int lo = 0, hi = ntl - 1;   // the last tile whose start is <= e
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (ss[mid] <= e) lo = mid; else hi = mid - 1;
+                    }
+                    const uint64_t x = xs[u];
+                    const int b = (int)((x & (T - 1)) * T + ((x >> 5) & (T - 1)));
+                    atomicOr(&sb[lo * W + (b >> 5)], 1u << (b & 31));
                 }
             }
-            I = tile_row[t];
         }
-        run_or(I, rm, hrows);
+        wave_sync_lds();
+        // the task's bitmaps: one contiguous run of ntl * W words, 16 bytes per store
+        uint4* dst = reinterpret_cast<uint4*>(bits + t0 * W);
+        const uint4* src = reinterpret_cast<const uint4*>(sb);
+        for (int k = lane; k < ntl * W / 4; k += kWave) dst[k] = src[k];
+        uint32_t rm = 0;
+        if (lane < ntl) {
+            #pragma unroll
+            for (int j = 0; j < W; ++j) {
+                const uint32_t wj = sb[lane * W + j];
+                if (T == 16) {
+                    rm |= (uint32_t)((wj & 0xFFFFu) != 0) << (2 * j);
+                    rm |= (uint32_t)((wj >> 16) != 0) << (2 * j + 1);
+                } else {
+                    rm |= (uint32_t)(wj != 0) << j;
+                }
+            }
+        }
+        run_or(lane < ntl ? row : -1, rm, hrows);
+        wave_sync_lds();   // the next task clears sb
     }
 }
 
@@ -660,10 +698,13 @@ int build_tiles_t(mis_graph* g, hipStream_t s) {
                            g->hsums, g->tile_start, g->tile_col, g->tile_row);
         TC_HIP(hipGetLastError());
     }
-    constexpr int L = T == 16 ? 1 : 4;
     TC_HIP(hipMemsetAsync(g->hrows, 0, (size_t)nI * 4, s));
-    LAUNCH((k_tile_bits<T>), g->tile_cap * L, sorted, g->tile_start, g->tile_row, g->meta, g->tile_cap, g->tile_bits,
-           g->hrows);
+    if (nheads > 0) {   // one wavefront per 64 tiles (the tile count is on the device: sized by capacity)
+        const int64_t blocks = std::min<int64_t>(ceil_div(ceil_div(g->tile_cap, kWave), kBlock / kWave), 8192);
+        hipLaunchKernelGGL((k_tile_bits<T>), dim3((unsigned)blocks), dim3(kBlock), 0, s, sorted, g->tile_start,
+                           g->tile_row, g->meta, g->tile_bits, g->hrows);
+        TC_HIP(hipGetLastError());
+    }
     LAUNCH(k_rb_ptr, nI + 1, g->tile_row, g->meta, nI, g->rb_ptr);
     // 5. the round-1 chunk list: every row-block's tiles in chunks of kTpi; rb_chunk
     //    holds each row-block's first chunk

@@ -49,6 +49,13 @@ __device__ inline int lane_id() { return (int)__lane_id(); }
 __device__ inline uint64_t ballot(bool p) { return __ballot(p); }
 __device__ inline uint64_t lanes_below() { return (1ull << lane_id()) - 1ull; }
 
+// Makes this wave's earlier LDS writes visible to its other lanes and keeps the
+// compiler from moving LDS accesses across the point.
+__device__ inline void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // Lanes that share a key I are adjacent (I < 0: none).  ORs each run's masks in
 // registers (segmented suffix scan) and lets the run's first lane apply the result
 // to dst[I] with one atomic OR.  Every lane of the wave must call it.

@@ -4,13 +4,6 @@
 
 namespace tcmis {
 
-// Makes this wave's earlier LDS writes visible to its other lanes and keeps the
-// compiler from moving LDS accesses across the point.
-__device__ inline void wave_sync_lds() {
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
 // Per-wave LDS staging buffer for list appends: items collect in LDS and are
 // written with one atomic per 64 items.  `pend` is wave-uniform.
 __device__ inline void lbuf_flush(int32_t* lbuf, int& pend, int32_t* list, int64_t* count) {
