@@ -17,10 +17,10 @@ int build_order(mis_graph* g, hipStream_t s);
 int build_tiles(mis_graph* g, hipStream_t s);
 int csr_init(mis_graph* g, hipStream_t s);
 int csr_enqueue_phase(mis_graph* g, int phase, int r, hipStream_t s);
-int csr_output(mis_graph* g, uint8_t* in_set, hipStream_t s);
+int csr_output(mis_graph* g, uint8_t* in_set, bool if_done, hipStream_t s);
 int tile_init(mis_graph* g, hipStream_t s);
 int tile_enqueue_phase(mis_graph* g, int phase, int r, hipStream_t s);
-int tile_output(mis_graph* g, uint8_t* in_set, hipStream_t s);
+int tile_output(mis_graph* g, uint8_t* in_set, bool if_done, hipStream_t s);
 int tile_enqueue_rounds(mis_graph* g, int k, hipStream_t s);
 int csr_enqueue_rounds(mis_graph* g, int k, hipStream_t s);
 
@@ -262,8 +262,8 @@ int solve_rounds(mis_graph* g, int64_t k, bool allow_graph, hipStream_t s) {
     return enqueue_batch(g, k, s, nullptr);
 }
 
-int solve_output(mis_graph* g, uint8_t* in_set, hipStream_t s) {
-    return g->path == MIS_PATH_TILE ? tile_output(g, in_set, s) : csr_output(g, in_set, s);
+int solve_output(mis_graph* g, uint8_t* in_set, hipStream_t s, bool if_done) {
+    return g->path == MIS_PATH_TILE ? tile_output(g, in_set, if_done, s) : csr_output(g, in_set, if_done, s);
 }
 
 }  // namespace tcmis
@@ -409,6 +409,8 @@ int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, mis_stats* st, 
             int64_t k = g->poll_rounds;
             if (max_rounds > 0) k = std::min<int64_t>(k, max_rounds - enq);
             rc = timing ? enqueue_batch(g, k, s, ev.data()) : solve_rounds(g, k, true, s);
+            // the result, written by the device only if this batch decided the last vertex
+            if (rc == MIS_OK) rc = solve_output(g, in_set, s, true);
             if (rc != MIS_OK) break;
             // ring slots of rounds drained+1 .. enq
             const int64_t first = drained % kTraceCap, cnt = enq + k - drained;
@@ -454,7 +456,8 @@ int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, mis_stats* st, 
     if (rc != MIS_OK) return rc;
     if (g->n > 0 && (sg->ctrl->error & kErrBarrier))
         return fail(MIS_EINTERNAL, "a grid barrier of the persistent round kernel timed out");
-    if (g->n > 0) TC_CHECK(solve_output(g, in_set, s));
+    // a solve stopped by max_rounds still writes the result of the rounds it ran
+    if (g->n > 0 && sg->ctrl->alive != 0) TC_CHECK(solve_output(g, in_set, s));
     if (g->n == 0) {   // nothing ran: no staging contents of this graph
         sg->ctrl->round = 0;
         sg->ctrl->n_in = 0;

@@ -173,5 +173,5 @@ size_t layout(mis_graph* g, char* base);
 // solve_output writes the in/out vector in input ids.
 int solve_begin(mis_graph* g, hipStream_t s);
 int solve_rounds(mis_graph* g, int64_t k, bool allow_graph, hipStream_t s);
-int solve_output(mis_graph* g, uint8_t* in_set, hipStream_t s);
+int solve_output(mis_graph* g, uint8_t* in_set, hipStream_t s, bool if_done = false);
 }  // namespace tcmis

@@ -188,7 +188,9 @@ __global__ void k_csr_init(const uint64_t* key, uint64_t* ak, uint32_t* st, int6
     }
 }
 
-__global__ void k_csr_output(const uint32_t* st, int64_t n, uint8_t* in_set) {
+// with `gate`: only once every vertex is decided (see k_tile_output)
+__global__ void k_csr_output(const Ctrl* gate, const uint32_t* st, int64_t n, uint8_t* in_set) {
+    if (gate && gate->alive != 0) return;
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
         in_set[v] = (st[v] & 3u) == kIn ? 1 : 0;
 }
@@ -228,9 +230,10 @@ int csr_enqueue_phase(mis_graph* g, int phase, int r, hipStream_t s) {
     return MIS_OK;
 }
 
-int csr_output(mis_graph* g, uint8_t* in_set, hipStream_t s) {
+int csr_output(mis_graph* g, uint8_t* in_set, bool if_done, hipStream_t s) {
     if (g->n > 0)
-        hipLaunchKernelGGL(k_csr_output, dim3(stream_grid(g->n)), dim3(kBlock), 0, s, g->st, g->n, in_set);
+        hipLaunchKernelGGL(k_csr_output, dim3(stream_grid(g->n)), dim3(kBlock), 0, s, if_done ? g->ctrl : nullptr,
+                           g->st, g->n, in_set);
     TC_HIP(hipGetLastError());
     return MIS_OK;
 }

@@ -519,14 +519,21 @@ __device__ inline uint32_t in_bit(const uint32_t* inmask, int64_t p, int tshift)
     return (inmask[p >> tshift] >> (p & ((1 << tshift) - 1))) & 1u;
 }
 
-__global__ void k_tile_output(const int32_t* new_id, const uint32_t* inmask, int64_t n, int tshift, uint8_t* in_set) {
+// With `gate`, the result is written only once every vertex is decided (the kernel
+// is enqueued after each batch of rounds, so a finished solve needs no further host
+// round trip).
+__global__ void k_tile_output(const Ctrl* gate, const int32_t* new_id, const uint32_t* inmask, int64_t n, int tshift,
+                              uint8_t* in_set) {
+    if (gate && gate->alive != 0) return;
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
         in_set[v] = (uint8_t)in_bit(inmask, new_id[v], tshift);
 }
 
 // four vertices per thread: one 16-byte load of new ids, one 4-byte store (in_set
 // 4-byte aligned); the last n % 4 vertices by the first thread
-__global__ void k_tile_output4(const int32_t* new_id, const uint32_t* inmask, int64_t n, int tshift, uint8_t* in_set) {
+__global__ void k_tile_output4(const Ctrl* gate, const int32_t* new_id, const uint32_t* inmask, int64_t n, int tshift,
+                               uint8_t* in_set) {
+    if (gate && gate->alive != 0) return;
     const int64_t nq = n >> 2;
     const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     for (int64_t i = t0; i < nq; i += (int64_t)gridDim.x * blockDim.x) {
@@ -617,14 +624,15 @@ int tile_enqueue_phase(mis_graph* g, int phase, int r, hipStream_t s) {
     return MIS_OK;
 }
 
-int tile_output(mis_graph* g, uint8_t* in_set, hipStream_t s) {
+int tile_output(mis_graph* g, uint8_t* in_set, bool if_done, hipStream_t s) {
     const int tshift = g->tile == 16 ? 4 : 5;
+    const Ctrl* gate = if_done ? g->ctrl : nullptr;
     if (g->n > 0 && ((uintptr_t)in_set & 3) == 0)   // new_id is a 256-byte aligned workspace array
-        hipLaunchKernelGGL(k_tile_output4, dim3(stream_grid(ceil_div(g->n, 4))), dim3(kBlock), 0, s, g->new_id,
+        hipLaunchKernelGGL(k_tile_output4, dim3(stream_grid(ceil_div(g->n, 4))), dim3(kBlock), 0, s, gate, g->new_id,
                            g->inmask, g->n, tshift, in_set);
     else if (g->n > 0)
-        hipLaunchKernelGGL(k_tile_output, dim3(stream_grid(g->n)), dim3(kBlock), 0, s, g->new_id, g->inmask, g->n,
-                           tshift, in_set);
+        hipLaunchKernelGGL(k_tile_output, dim3(stream_grid(g->n)), dim3(kBlock), 0, s, gate, g->new_id, g->inmask,
+                           g->n, tshift, in_set);
     TC_HIP(hipGetLastError());
     return MIS_OK;
 }
