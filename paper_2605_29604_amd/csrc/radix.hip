@@ -141,14 +141,21 @@ __device__ inline int block_len(const int32_t* counts, const int32_t* dense_tota
 // lane; empty for an invalid key.  DB ballots, no LDS.
 template <int DB>
 __device__ inline uint64_t digit_peers(bool valid, int d) {
-    uint64_t m = ballot(valid);
+    const uint64_t v = ballot(valid);
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
     #pragma unroll
     for (int b = 0; b < DB; ++b) {
-        const bool bit = (d >> b) & 1;
-        const uint64_t bb = ballot(bit);
-        m &= bit ? bb : ~bb;
+        // the lanes whose bit b equals this lane's: m & ~(ballot ^ s), s = this lane's
+        // bit spread over the word, as one three-input logic op per half.  m is the
+        // middle operand and the function is symmetric in the outer two, so the truth
+        // table (m = 1 and the outer two equal: 0x84) does not depend on which outer
+        // operand is the high index bit.
+        const uint32_t s = (uint32_t)(((int32_t)((uint32_t)d << (31 - b))) >> 31);
+        const uint64_t bb = ballot(s != 0);
+        lo = __builtin_amdgcn_bitop3_b32((uint32_t)bb, lo, s, 0x84);
+        hi = __builtin_amdgcn_bitop3_b32((uint32_t)(bb >> 32), hi, s, 0x84);
     }
-    return valid ? m : 0ull;
+    return valid ? ((uint64_t)hi << 32 | lo) : 0ull;
 }
 
 // Keys of a block are split into one contiguous run of kSortTile / 4 keys per
