@@ -289,8 +289,11 @@ __device__ inline bool is_head(const uint64_t* ent, int64_t e, int64_t nvalid, u
 }
 
 template <int kTshift>
-__global__ void __launch_bounds__(kBlock) k_head_count(const uint64_t* ent, const Meta* meta, int32_t* sums) {
+// heads per chunk of sorted entries; also clears hrows (n_rows words) for the bitmap pass
+__global__ void __launch_bounds__(kBlock) k_head_count(const uint64_t* ent, const Meta* meta, int32_t* sums,
+                                                       uint32_t* hrows, int64_t n_rows) {
     __shared__ int32_t wsum[kBlock / kWave];
+    GRID_STRIDE(I, n_rows) hrows[I] = 0;
     const int64_t nvalid = meta->nvalid;
     const int64_t base = (int64_t)blockIdx.x * kHeadChunk;
     int c = 0;
@@ -442,8 +445,11 @@ __global__ void k_rb_ptr(const int32_t* tile_row, const Meta* meta, int64_t nI, 
 }
 
 // chunks of each row-block (at most tpi tiles each)
-__global__ void k_chunk_count(const int64_t* rb_ptr, int64_t nI, int tpi, int64_t* cnt) {
+// chunks per row-block; also marks every slot of the round-1 list a hole (r1 has
+// r1_len slots), before the chunk fill writes the chunks
+__global__ void k_chunk_count(const int64_t* rb_ptr, int64_t nI, int tpi, int64_t* cnt, uint64_t* r1, int64_t r1_len) {
     GRID_STRIDE(I, nI) cnt[I] = (rb_ptr[I + 1] - rb_ptr[I] + tpi - 1) / tpi;
+    GRID_STRIDE(q, r1_len) r1[q] = kChunkHole;
 }
 
 // chunk q belongs to the last row-block whose first chunk is <= q
@@ -451,9 +457,12 @@ __global__ void k_chunk_count(const int64_t* rb_ptr, int64_t nI, int tpi, int64_
 // row-block's first chunk ahead of all later ones (r1: first chunks at [I], later
 // chunks at nI + their index, holes elsewhere), so that round 1 settles most
 // row-blocks before their later chunks are reached and those are skipped
-__global__ void k_chunk_fill(const int64_t* first, const int64_t* rb_ptr, const Meta* meta, int64_t nI, int tpi,
+// (first[nI], the end of the last row-block's range, is written here too; the
+// searches read first[0 .. nI - 1] only)
+__global__ void k_chunk_fill(int64_t* first, const int64_t* rb_ptr, const Meta* meta, int64_t nI, int tpi,
                              int64_t cap, uint64_t* out, uint64_t* r1) {
     const int64_t total = meta->nchunks;
+    if (blockIdx.x == 0 && threadIdx.x == 0) first[nI] = total;
     GRID_STRIDE(q, cap) {
         if (q >= total) break;
         int64_t lo = 0, hi = nI - 1;
@@ -467,8 +476,6 @@ __global__ void k_chunk_fill(const int64_t* first, const int64_t* rb_ptr, const 
         r1[q == first[lo] ? lo : nI + q] = w;
     }
 }
-
-__global__ void k_rb_chunk_end(const Meta* meta, int64_t nI, int64_t* rb_chunk) { rb_chunk[nI] = meta->nchunks; }
 
 __global__ void k_permute_keys(const uint64_t* key, const int32_t* new_id, int64_t n, uint64_t* key_p) {
     GRID_STRIDE(v, n) key_p[new_id[v]] = key[v];
@@ -691,14 +698,14 @@ int build_tiles_t(mis_graph* g, hipStream_t s) {
     const int64_t nheads = ceil_div(nnz, kHeadChunk);
     if (nheads > 0) {
         hipLaunchKernelGGL((k_head_count<kTshift>), dim3((unsigned)nheads), dim3(kBlock), 0, s, sorted, g->meta,
-                           g->hsums);
+                           g->hsums, g->hrows, nI);
         TC_HIP(hipGetLastError());
         TC_CHECK(scan_excl_i32(g->hsums, g->hsums, nheads, &g->meta->ntiles, (int32_t*)g->scan_tmp, s));
         hipLaunchKernelGGL((k_head_write<kTshift>), dim3((unsigned)nheads), dim3(kBlock), 0, s, sorted, g->meta,
                            g->hsums, g->tile_start, g->tile_col, g->tile_row);
         TC_HIP(hipGetLastError());
     }
-    TC_HIP(hipMemsetAsync(g->hrows, 0, (size_t)nI * 4, s));
+    if (nheads == 0) TC_HIP(hipMemsetAsync(g->hrows, 0, (size_t)nI * 4, s));   // else cleared by the head count
     if (nheads > 0) {   // one wavefront per 64 tiles (the tile count is on the device: sized by capacity)
         const int64_t blocks = std::min<int64_t>(ceil_div(ceil_div(g->tile_cap, kWave), kBlock / kWave), 8192);
         hipLaunchKernelGGL((k_tile_bits<T>), dim3((unsigned)blocks), dim3(kBlock), 0, s, sorted, g->tile_start,
@@ -709,13 +716,10 @@ int build_tiles_t(mis_graph* g, hipStream_t s) {
     // 5. the round-1 chunk list: every row-block's tiles in chunks of kTpi; rb_chunk
     //    holds each row-block's first chunk
     constexpr int kTpi = T == 16 ? 64 : 16;
-    LAUNCH(k_chunk_count, nI, g->rb_ptr, nI, kTpi, g->rb_chunk);
+    LAUNCH(k_chunk_count, nI, g->rb_ptr, nI, kTpi, g->rb_chunk, g->chunks_r1, nI + g->chunk_cap);
     TC_CHECK(scan_excl_i64(g->rb_chunk, g->rb_chunk, nI, &g->meta->nchunks, (int64_t*)g->scan_tmp, s));
-    TC_HIP(hipMemsetAsync(g->chunks_r1, 0xFF, (size_t)(nI + g->chunk_cap) * 8, s));   // all holes (kChunkHole)
     LAUNCH(k_chunk_fill, g->chunk_cap, g->rb_chunk, g->rb_ptr, g->meta, nI, kTpi, g->chunk_cap, g->chunks_all,
            g->chunks_r1);
-    hipLaunchKernelGGL(k_rb_chunk_end, dim3(1), dim3(1), 0, s, g->meta, nI, g->rb_chunk);
-    TC_HIP(hipGetLastError());
     if (!g->orient) {
         TC_HIP(hipMemsetAsync(g->key_p, 0, (size_t)nI * T * 8, s));
         LAUNCH(k_permute_keys, n, g->key, g->new_id, n, g->key_p);

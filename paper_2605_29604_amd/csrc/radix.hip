@@ -69,11 +69,22 @@ __global__ void __launch_bounds__(kBlock) k_scan_reduce(const T* in, int64_t cou
 }
 
 // exclusive (kIncl = false) or inclusive scan of each tile, seeded with the
-// exclusive scan of the tile totals
+// exclusive scan of the tile totals (tile_prefix), or, with tile_sums instead, with
+// the total of the tiles before this one, which the block adds up itself (at most
+// kScanTile tiles)
 template <typename T, typename Op, bool kIncl>
 __global__ void __launch_bounds__(kBlock) k_scan_apply(const T* in, T* out, int64_t count, const T* tile_prefix,
-                                                       T* d_total) {
+                                                       T* d_total, const T* tile_sums) {
     __shared__ T lds[kWavesPerBlock];
+    __shared__ T seed;
+    if (tile_sums) {
+        T part = Op::template identity<T>();
+        for (int64_t i = threadIdx.x; i < blockIdx.x; i += kBlock) part = Op::apply(part, tile_sums[i]);
+        T all;
+        block_scan<T, Op>(part, lds, &all);
+        if (threadIdx.x == 0) seed = all;
+        __syncthreads();
+    }
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     T v[kScanItems];
     T s = Op::template identity<T>();
@@ -90,6 +101,7 @@ __global__ void __launch_bounds__(kBlock) k_scan_apply(const T* in, T* out, int6
     __syncthreads();
     T run = threadIdx.x == 0 ? Op::template identity<T>() : lds_incl[threadIdx.x - 1];
     if (tile_prefix) run = Op::apply(tile_prefix[blockIdx.x], run);
+    if (tile_sums) run = Op::apply(seed, run);
     for (int i = 0; i < kScanItems; ++i) {
         const int64_t idx = base + i;
         if (kIncl) {
@@ -109,7 +121,7 @@ int scan_impl(const T* in, T* out, int64_t count, T* d_total, T* scratch, hipStr
     const int64_t nb = ceil_div(count, kScanTile);
     if (nb == 1) {
         hipLaunchKernelGGL((k_scan_apply<T, Op, kIncl>), dim3(1), dim3(kBlock), 0, s, in, out, count, (const T*)nullptr,
-                           d_total);
+                           d_total, (const T*)nullptr);
         TC_HIP(hipGetLastError());
         return MIS_OK;
     }
@@ -117,9 +129,15 @@ int scan_impl(const T* in, T* out, int64_t count, T* d_total, T* scratch, hipStr
     T* rest = scratch + nb;
     hipLaunchKernelGGL((k_scan_reduce<T, Op>), dim3((unsigned)nb), dim3(kBlock), 0, s, in, count, sums);
     TC_HIP(hipGetLastError());
+    if (nb <= kScanTile) {   // two kernels: each tile adds up the totals before it
+        hipLaunchKernelGGL((k_scan_apply<T, Op, kIncl>), dim3((unsigned)nb), dim3(kBlock), 0, s, in, out, count,
+                           (const T*)nullptr, d_total, (const T*)sums);
+        TC_HIP(hipGetLastError());
+        return MIS_OK;
+    }
     TC_CHECK((scan_impl<T, Op, false>(sums, sums, nb, (T*)nullptr, rest, s)));
     hipLaunchKernelGGL((k_scan_apply<T, Op, kIncl>), dim3((unsigned)nb), dim3(kBlock), 0, s, in, out, count,
-                       (const T*)sums, d_total);
+                       (const T*)sums, d_total, (const T*)nullptr);
     TC_HIP(hipGetLastError());
     return MIS_OK;
 }
