@@ -39,6 +39,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "tile_exclusion_rmat22_traffic.json")
+MFMA_RECORD = os.path.join(ROOT, "profiles", "tile_exclusion_rmat22_mfma.json")
 
 
 def measured_traffic(a):
@@ -59,6 +60,26 @@ def measured_traffic(a):
         if not os.path.exists(path) or hashlib.sha256(open(path, "rb").read()).hexdigest() != digest:
             return None
     return rec["traffic_bytes_per_launch"]
+
+
+def measured_mfma(a):
+    """int8 matrix-core use of the tile exclusion kernel from the committed counter
+    record (rocprofv3 MFMA counters), or None when the configuration differs or the
+    kernel sources changed since the counters were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(MFMA_RECORD))
+    except (OSError, ValueError):
+        return None
+    if (rec.get("workload"), rec.get("tile"), rec.get("reorder"), rec.get("orient"), rec.get("seed")) != \
+            (a.workload, a.tile, a.reorder, a.orient, a.seed):
+        return None
+    for name, digest in rec.get("source_sha256", {}).items():
+        path = os.path.join(ROOT, "paper_2605_29604_amd", "csrc", name)
+        if not os.path.exists(path) or hashlib.sha256(open(path, "rb").read()).hexdigest() != digest:
+            return None
+    return {"achieved": round(rec["int8_tops"], 2), "peak": rec["int8_peak_tops"], "unit": "TOPS (int8)",
+            "frac": round(rec["frac_of_peak"], 4), "busy": round(rec["mfma_util"], 4)}
 
 
 def parse():
@@ -419,7 +440,8 @@ def main():
                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                        "traffic": None if traffic is None else int(traffic),
                        "avg_launch_us": round(avg_ms * 1e3, 3), "launches": launches,
-                       "alg_bytes_per_launch": int(bytes_k / launches)}
+                       "alg_bytes_per_launch": int(bytes_k / launches),
+                       "mfma": measured_mfma(a) if k == 1 else None}
 
     # round-loop launch modes of the same solve (identical results)
     modes = {}

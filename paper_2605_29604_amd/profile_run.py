@@ -9,6 +9,8 @@ With --summarize FETCH_DIR WRITE_DIR (the output folders of one FETCH_SIZE and o
 WRITE_SIZE run of this program) it reads the counters instead, on any machine, and
 writes the exclusion kernel's per-launch HBM traffic to profiles/ (a JSON record
 that bench.py reports while the kernel sources are unchanged, and a short summary).
+With --summarize-mfma DIR (one run with the MFMA counters, see the summary it
+writes) it does the same for the kernel's int8 matrix-core use.
 """
 from __future__ import annotations
 
@@ -43,6 +45,93 @@ def _counter(folder: str, name: str, kernel: str):
     return copy, vals
 
 
+def _dispatches(folder: str, kernel: str):
+    """{dispatch id: (duration ns, {counter: value})} of every dispatch of `kernel`."""
+    out = {}
+    with open(os.path.join(folder, "run_counter_collection.csv")) as f:
+        for r in csv.DictReader(f):
+            if kernel not in r["Kernel_Name"]:
+                continue
+            d = out.setdefault(int(r["Dispatch_Id"]),
+                               (int(r["End_Timestamp"]) - int(r["Start_Timestamp"]), {}))
+            d[1][r["Counter_Name"]] = float(r["Counter_Value"])
+    return [out[k] for k in sorted(out)]
+
+
+def _sources_sha():
+    sha = {}
+    for name in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2605_29604_amd", "csrc", name), "rb") as fh:
+            sha[name] = hashlib.sha256(fh.read()).hexdigest()
+    return sha
+
+
+# MI355X: 8 XCDs, 256 compute units of 4 SIMDs; dense int8 matrix peak 5.0 POP/s.
+# GRBM_GUI_ACTIVE reads as the sum over the XCDs (8 x the clock over a dispatch).
+XCDS = 8
+SIMDS = 1024
+INT8_PEAK_TOPS = 5000.0
+
+
+def summarize_mfma(a) -> int:
+    kernel = f"k_tile_excl<{a.tile}>"
+    rows = _dispatches(a.summarize_mfma, kernel)
+    if not rows:
+        raise SystemExit(f"{a.summarize_mfma}: no {kernel} dispatch")
+    per = []
+    for ns, c in rows:
+        ops = c.get("SQ_INSTS_VALU_MFMA_MOPS_I8", 0.0) * 512.0
+        busy = c.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0)
+        gui = c.get("GRBM_GUI_ACTIVE", 0.0)
+        per.append({"us": ns / 1e3, "mfma_i8": c.get("SQ_INSTS_VALU_MFMA_I8", 0.0), "ops": ops, "busy_cycles": busy,
+                    "gui_active": gui, "tops": ops / ns / 1e3 if ns else 0.0})
+    ops = sum(p["ops"] for p in per)
+    ns = sum(p["us"] for p in per) * 1e3
+    busy = sum(p["busy_cycles"] for p in per)
+    gui = sum(p["gui_active"] for p in per)
+    util = busy / (gui / XCDS * SIMDS) if gui else 0.0   # MFMA-busy share of SIMD cycles
+    tops = ops / ns / 1e3 if ns else 0.0
+    rec = {"kernel": "tile_exclusion_mfma", "symbol": kernel, "workload": a.workload, "seed": 1, "tile": a.tile,
+           "reorder": a.reorder, "orient": a.orient, "dispatches": per, "mfma_util": util, "int8_tops": tops,
+           "int8_peak_tops": INT8_PEAK_TOPS, "frac_of_peak": tops / INT8_PEAK_TOPS, "source_sha256": _sources_sha()}
+    base = os.path.join(ROOT, "profiles", f"tile_exclusion_{a.workload}_mfma")
+    with open(base + ".json", "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    lines = "\n".join(f"| {i + 1} | {p['us']:.1f} | {p['mfma_i8']:.0f} | {p['ops'] / 1e9:.2f} | {p['tops']:.1f} |"
+                       for i, p in enumerate(per))
+    md = f"""# {a.workload}: int8 matrix-core use of the tile exclusion kernel
+
+Command (one counter pass from /tmp on the GPU host; REPO = the repository root):
+
+```
+rocprofv3 --pmc SQ_VALU_MFMA_BUSY_CYCLES SQ_INSTS_VALU_MFMA_MOPS_I8 SQ_INSTS_VALU_MFMA_I8 SQ_INSTS_MFMA \\
+    GRBM_GUI_ACTIVE --kernel-trace --output-format csv -d $REPO/gpurun_out/pmc_mfma -o run -- \\
+    python3 $REPO/paper_2605_29604_amd/profile_run.py
+python3 paper_2605_29604_amd/profile_run.py --summarize-mfma gpurun_out/pmc_mfma
+```
+
+Each `v_mfma_i32_16x16x64_i8` is 32,768 integer operations (SQ_INSTS_VALU_MFMA_MOPS_I8 counts them / 512).
+
+| Round | µs | MFMA i8 | G int ops | TOPS |
+|---:|---:|---:|---:|---:|
+{lines}
+
+Over the solve: {tops:.1f} TOPS, {100 * tops / INT8_PEAK_TOPS:.2f}% of the {INT8_PEAK_TOPS:.0f} TOPS dense int8 peak;
+MFMA busy {100 * util:.2f}% of SIMD cycles (busy cycles over GUI-active cycles per XCD x 1024 SIMDs).
+The products are matrix-vector: the B operand repeats one candidate vector in all 16 columns, so 1/16 of
+these operations is the algorithm's work.  The kernel is bound by memory latency and address processing,
+not by the matrix cores.
+
+`{os.path.basename(base)}.json` holds these figures with the SHA-256 of the kernel sources they were taken
+on; `bench.py` reports them (`roofline.mfma`) only while those sources are unchanged.
+"""
+    with open(base + ".md", "w") as fh:
+        fh.write(md)
+    print(f"{base}.json: {tops:.1f} TOPS, util {100 * util:.2f}%")
+    return 0
+
+
 def summarize(a) -> int:
     kernel = f"k_tile_excl<{a.tile}>"
     fdir, wdir = a.summarize
@@ -53,10 +142,7 @@ def summarize(a) -> int:
     moved = a.copy_mib * 1024.0
     ff, wf = moved / cf, moved / cw
     per = [(f * ff + w * wf) * 1024.0 for f, w in zip(fetch, write)]
-    sha = {}
-    for name in TRAFFIC_SOURCES:
-        with open(os.path.join(ROOT, "paper_2605_29604_amd", "csrc", name), "rb") as fh:
-            sha[name] = hashlib.sha256(fh.read()).hexdigest()
+    sha = _sources_sha()
     rec = {"kernel": "tile_exclusion_mfma", "symbol": kernel, "workload": a.workload, "seed": 1, "tile": a.tile,
            "reorder": a.reorder, "orient": a.orient, "dispatches": len(per), "fetch_kib": fetch, "write_kib": write,
            "copy_mib": a.copy_mib, "copy_fetch_kib": cf, "copy_write_kib": cw, "fetch_factor": ff,
@@ -109,9 +195,12 @@ def main() -> int:
     p.add_argument("--orient", type=int, default=1)
     p.add_argument("--copy-mib", type=int, default=256)
     p.add_argument("--summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    p.add_argument("--summarize-mfma", metavar="DIR")
     a = p.parse_args()
     if a.summarize:
         return summarize(a)
+    if a.summarize_mfma:
+        return summarize_mfma(a)
     import torch
     from paper_2605_29604_amd import gen, tcmis
 
