@@ -174,7 +174,8 @@ __device__ inline bool make_entry(int32_t p, int32_t q, uint64_t kv, uint64_t ku
 
 constexpr int kEntIters = 16;
 constexpr int kEntBlock = kBlock * kEntIters;   // new-order entries per workgroup (= one sort block)
-constexpr int kEntWindow = 4096;                // new rows a workgroup keeps in LDS
+constexpr int kEntWindow = 2048;                // new rows a workgroup keeps in LDS
+constexpr int kEntSteps = 11;                   // 2^kEntSteps = kEntWindow
 
 // largest row p in [lo, hi] with nrp[p] <= e (the row that holds new-order entry e)
 __device__ inline int32_t find_row(const int32_t* nrp, int64_t lo, int64_t hi, int64_t e) {
@@ -193,56 +194,85 @@ __global__ void k_block_rows(const int32_t* nrp, int64_t n, int64_t nnz, int64_t
     }
 }
 
-// One candidate entry per adjacency entry in new-row order, coalesced over entries;
-// the rows of the workgroup's range are looked up in an LDS copy of the new row
-// pointer.  Every thread first issues the column reads and the new-id (and key)
-// gathers of all its kEntIters entries, so they are in flight together; the kept
-// entries are then compacted to the front of the workgroup's range (order
-// preserved) and their number goes to cnt[block].
+// One candidate entry per adjacency entry in new-row order, coalesced over entries.
+// When the workgroup's rows fit in LDS (the common case), their new and old row
+// starts (and, for key orientation, vertices) are staged there first; each thread
+// then finds the rows of its kEntIters entries with a fixed-step search in LDS and
+// issues all their column reads, then all their new-id (and key) gathers, so that
+// every stage has kEntIters loads in flight instead of a chain of dependent loads
+// per entry.  The column reads and the entry stores are non-temporal: the caches
+// are left to the randomly gathered new ids.  The kept entries are compacted to the
+// front of the workgroup's range (order preserved) and their number goes to
+// cnt[block].
 template <int kTshift, int kMode>
 __global__ void __launch_bounds__(kBlock) k_entries(const int64_t* rp, const int32_t* ci, const int32_t* order,
                                                     const int32_t* nrp, const int32_t* brow, const int32_t* new_id,
                                                     const uint64_t* key, int64_t nnz, uint64_t* ent, int32_t* cnt) {
-    __shared__ int32_t win[kEntWindow];
+    constexpr bool kVert = kMode == 2;   // the row's vertex is needed beyond its old row start
+    __shared__ int32_t win[kEntWindow];                 // new row starts
+    __shared__ int32_t wold[kEntWindow];                // old row starts (nnz < 2^31)
+    __shared__ int32_t wver[kVert ? kEntWindow : 1];    // row vertices
     __shared__ int32_t wcnt[kEntIters][kBlock / kWave];
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     const int64_t base = (int64_t)blockIdx.x * kEntBlock;
     const int64_t p0 = brow[blockIdx.x], p1 = brow[blockIdx.x + 1];
     const int64_t w = p1 - p0 + 1;
-    const bool in_lds = w <= kEntWindow;
+    const bool in_lds = w <= kEntWindow;   // uniform over the workgroup
     if (in_lds)
-        for (int64_t i = threadIdx.x; i < w; i += kBlock) win[i] = nrp[p0 + i];
+        for (int64_t i = threadIdx.x; i < w; i += kBlock) {
+            const int32_t v = order[p0 + i];
+            win[i] = nrp[p0 + i];
+            wold[i] = (int32_t)rp[v];
+            if (kVert) wver[i] = v;
+        }
     __syncthreads();
-    int32_t pr[kEntIters], qv[kEntIters];
+    int32_t pr[kEntIters], uu[kEntIters], vv[kEntIters];   // row (-1: none), column, row vertex
+    if (in_lds) {
+        const int wl = (int)w - 1;
+        int li[kEntIters];
+        #pragma unroll
+        for (int it = 0; it < kEntIters; ++it) {
+            const int32_t e = (int32_t)std::min<int64_t>(base + (int64_t)it * kBlock + threadIdx.x, nnz - 1);
+            int lo = 0;   // win[0] <= e: row p0 holds the workgroup's first entry
+            #pragma unroll
+            for (int k = kEntSteps - 1; k >= 0; --k) {
+                const int c = lo + (1 << k);
+                const int32_t wc = win[std::min(c, wl)];
+                lo = ((c <= wl) & (wc <= e)) ? c : lo;
+            }
+            li[it] = lo;
+        }
+        #pragma unroll
+        for (int it = 0; it < kEntIters; ++it) {
+            const int64_t e = base + (int64_t)it * kBlock + threadIdx.x;
+            const int32_t ec = (int32_t)std::min<int64_t>(e, nnz - 1);
+            uu[it] = __builtin_nontemporal_load(&ci[wold[li[it]] + (ec - win[li[it]])]);
+            vv[it] = kVert ? wver[li[it]] : 0;
+            pr[it] = e < nnz ? (int32_t)(p0 + li[it]) : -1;
+        }
+    } else {
+        #pragma unroll
+        for (int it = 0; it < kEntIters; ++it) {
+            const int64_t e = base + (int64_t)it * kBlock + threadIdx.x;
+            pr[it] = -1;
+            uu[it] = vv[it] = 0;
+            if (e < nnz) {
+                const int32_t p = find_row(nrp, p0, p1, e);
+                const int32_t v = order[p];
+                uu[it] = ci[rp[v] + (e - nrp[p])];
+                vv[it] = v;
+                pr[it] = p;
+            }
+        }
+    }
+    // every uu / vv is a valid vertex here (entries past the end repeat the last one)
+    int32_t qv[kEntIters];
     uint64_t kv[kEntIters], ku[kEntIters];
     #pragma unroll
     for (int it = 0; it < kEntIters; ++it) {
-        const int64_t e = base + (int64_t)it * kBlock + threadIdx.x;
-        pr[it] = -1;
-        qv[it] = 0;
-        kv[it] = ku[it] = 0;
-        if (e < nnz) {
-            int32_t p;
-            if (in_lds) {
-                int lo = 0, hi = (int)w - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (win[mid] <= e) lo = mid; else hi = mid - 1;
-                }
-                p = (int32_t)(p0 + lo);
-            } else {
-                p = find_row(nrp, p0, p1, e);
-            }
-            const int32_t v = order[p];
-            const int64_t off = e - (in_lds ? win[p - p0] : nrp[p]);
-            const int32_t u = ci[rp[v] + off];
-            pr[it] = p;
-            qv[it] = new_id[u];
-            if (kMode == 2) {
-                kv[it] = key[v];
-                ku[it] = key[u];
-            }
-        }
+        qv[it] = new_id[uu[it]];
+        kv[it] = kMode == 2 ? key[vv[it]] : 0;
+        ku[it] = kMode == 2 ? key[uu[it]] : 0;
     }
     uint64_t kept = 0;   // bit it: entry it is kept
     uint64_t x[kEntIters];
@@ -266,7 +296,7 @@ __global__ void __launch_bounds__(kBlock) k_entries(const int64_t* rp, const int
             total += wcnt[it][q];
         }
         const uint64_t b = ballot((kept >> it) & 1);
-        if ((kept >> it) & 1) ent[base + before + __popcll(b & lanes_below())] = x[it];
+        if ((kept >> it) & 1) __builtin_nontemporal_store(x[it], &ent[base + before + __popcll(b & lanes_below())]);
         written = total;
     }
     if (threadIdx.x == 0) cnt[blockIdx.x] = written;
@@ -624,6 +654,12 @@ int build_csr_lists(mis_graph* g, hipStream_t s) {
     return MIS_OK;
 }
 
+// default keys of a single graph hold the vertex id in their low 24 bits: the order
+// sort then moves the keys alone and the order is read back from them
+bool default_keys_in_order(const mis_graph* g) {
+    return g->reorder == MIS_REORDER_KEY && !g->user_keys && g->count == 0 && g->n <= (1 << 24);
+}
+
 int build_order(mis_graph* g, hipStream_t s) {
     const int64_t n = g->n;
     if (n == 0) return MIS_OK;
@@ -644,9 +680,7 @@ int build_order(mis_graph* g, hipStream_t s) {
         TC_HIP(hipStreamSynchronize(s));   // nid is freed on return
         return MIS_OK;
     }
-    // default keys of a single graph hold the vertex id in their low 24 bits: the sort
-    // then moves the keys alone and the order is read back from them
-    const bool ids_in_key = g->reorder == MIS_REORDER_KEY && !g->user_keys && g->count == 0 && n <= (1 << 24);
+    const bool ids_in_key = default_keys_in_order(g);
     LAUNCH(k_order_keys, n, g->row_ptr, g->key, n, g->reorder, g->sk, ids_in_key ? nullptr : g->pl);
     bool alt = false;
     const int lo = g->reorder == MIS_REORDER_DEGREE ? 0 : (g->user_keys ? 0 : 24);
@@ -674,15 +708,13 @@ int build_tiles_t(mis_graph* g, hipStream_t s) {
     if (nnz > 0) {
         LAUNCH(k_block_rows, eblocks + 1, g->ndeg, n, nnz, eblocks, g->brow);
         const dim3 grid((unsigned)eblocks), blk(kBlock);
-        if (mode == 0)
-            hipLaunchKernelGGL((k_entries<kTshift, 0>), grid, blk, 0, s, g->row_ptr, g->col_idx, g->order, g->ndeg,
-                               g->brow, g->new_id, g->key, nnz, g->ent, g->ecnt);
-        if (mode == 1)
-            hipLaunchKernelGGL((k_entries<kTshift, 1>), grid, blk, 0, s, g->row_ptr, g->col_idx, g->order, g->ndeg,
-                               g->brow, g->new_id, g->key, nnz, g->ent, g->ecnt);
-        if (mode == 2)
-            hipLaunchKernelGGL((k_entries<kTshift, 2>), grid, blk, 0, s, g->row_ptr, g->col_idx, g->order, g->ndeg,
-                               g->brow, g->new_id, g->key, nnz, g->ent, g->ecnt);
+#define TC_ENTRIES(M)                                                                                     \
+    hipLaunchKernelGGL((k_entries<kTshift, M>), grid, blk, 0, s, g->row_ptr, g->col_idx, g->order, g->ndeg, \
+                       g->brow, g->new_id, g->key, nnz, g->ent, g->ecnt)
+        if (mode == 0) TC_ENTRIES(0);
+        if (mode == 1) TC_ENTRIES(1);
+        if (mode == 2) TC_ENTRIES(2);
+#undef TC_ENTRIES
         TC_HIP(hipGetLastError());
         // number of kept entries
         TC_CHECK(scan_excl_i32(g->ecnt, g->hsums, eblocks, &g->meta->nvalid, (int32_t*)g->scan_tmp, s));

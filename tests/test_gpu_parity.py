@@ -124,6 +124,32 @@ def test_deep_path_custom_keys(cfg):
     check(rp, ci, cfg, keys=keys, label="path301")
 
 
+@pytest.mark.parametrize("cfg", FAST_CONFIGS, ids=lambda c: "-".join(map(str, c)))
+def test_entry_windows(cfg):
+    # the entry pass stages a workgroup's rows in LDS when they fit (2048 rows per
+    # 4096 entries) and looks them up in global memory otherwise: degree-2 rows put
+    # the row span on either side of that bound, degree-1 and isolated rows far above
+    for n in (6001, 6145, 8193):
+        rp, ci = csr_from_edges(n, [(i, i + 1) for i in range(n - 1)])
+        check(rp, ci, cfg, label=f"path{n}")
+    m = 3000   # caterpillar: a path with one leaf on every vertex
+    rp, ci = csr_from_edges(2 * m, [(i, i + 1) for i in range(m - 1)] + [(i, m + i) for i in range(m)])
+    check(rp, ci, cfg, label="caterpillar3000")
+    c = 5000   # a cycle on the even vertices, every odd vertex isolated
+    rp, ci = csr_from_edges(2 * c, [(2 * i, 2 * ((i + 1) % c)) for i in range(c)])
+    check(rp, ci, cfg, label="cycle5000-isolated")
+
+
+@pytest.mark.parametrize("tile", [16, 32])
+def test_default_keys_given_by_caller(tile):
+    # the default keys passed in explicitly: the order sort then carries vertex ids
+    # as a payload over all 64 key bits instead of reading them from the keys
+    g = gen.rmat(1 << 14, 8 << 14, seed=4)
+    keys = oracle.keys(g.row_ptr, 9)
+    check(g.row_ptr, g.col_idx, ("tile", tile, "key", 1), seed=9, keys=keys, label="rmat14-keys")
+    check(g.row_ptr, g.col_idx, ("tile", tile, "key", 1), seed=9, label="rmat14-default")
+
+
 def test_empty_graph():
     T = tcmis_mod()
     drp = torch.zeros(1, dtype=torch.int64, device="cuda")
