@@ -546,10 +546,11 @@ size_t layout(mis_graph* g, char* base) {
         off += bytes ? bytes : 8;
     };
     const int64_t n = g->n, nnz = g->nnz;
+    // ctrl, meta and the trace ring first and together: a solve reads them back with one copy
     take(&g->ctrl, sizeof(Ctrl));
-    take(&g->stripes, sizeof(int64_t) * 2 * kStripes * kStripeWords);
     take(&g->meta, sizeof(Meta));
     take(&g->trace, sizeof(TraceRec) * kTraceCap);
+    take(&g->stripes, sizeof(int64_t) * 2 * kStripes * kStripeWords);
     take(&g->key, (size_t)n * 8);
     if (g->count > 0) {
         take(&g->goff, (size_t)(g->count + 1) * 8);
@@ -699,7 +700,8 @@ template <int T>
 int build_tiles_t(mis_graph* g, hipStream_t s) {
     constexpr int kTshift = T == 16 ? 4 : 5;
     const int64_t n = g->n, nnz = g->nnz, nI = g->nI;
-    TC_HIP(hipMemsetAsync(g->meta, 0, sizeof(Meta), s));
+    // with entries, every Meta field is the total of a scan below before anything reads it
+    if (nnz == 0) TC_HIP(hipMemsetAsync(g->meta, 0, sizeof(Meta), s));
     // 1. new row pointer (the degrees in new order were written with the order)
     TC_CHECK(scan_excl_i32(g->ndeg, g->ndeg, n, g->ndeg + n, (int32_t*)g->scan_tmp, s));
     // 2. entries in new-row order, one lane per entry

@@ -37,26 +37,35 @@ int fail(int code, const std::string& msg) {
     return code;
 }
 
-// Pinned host staging for the round-loop polls, one per host thread.
+// Pinned host staging for the round-loop polls, one per host thread: a mirror of the
+// workspace span that holds ctrl, meta and the trace ring (adjacent in the layout),
+// so that one copy brings back all three.
 struct Staging {
+    char* base = nullptr;
+    size_t off_meta = 0, off_trace = 0;
     Ctrl* ctrl = nullptr;
     Meta* meta = nullptr;
     TraceRec* trace = nullptr;
     ~Staging() {
-        if (ctrl) (void)hipHostFree(ctrl);
-        if (meta) (void)hipHostFree(meta);
-        if (trace) (void)hipHostFree(trace);
+        if (base) (void)hipHostFree(base);
     }
 };
 thread_local Staging t_stage;
 
-int staging(Staging** out) {
+int staging(const mis_graph* g, Staging** out) {
     Staging& st = t_stage;
-    if (!st.ctrl) {
-        if (hipHostMalloc((void**)&st.ctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc((void**)&st.meta, sizeof(Meta), hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc((void**)&st.trace, sizeof(TraceRec) * kTraceCap, hipHostMallocDefault) != hipSuccess)
+    const size_t om = (size_t)((const char*)g->meta - (const char*)g->ctrl);
+    const size_t ot = (size_t)((const char*)g->trace - (const char*)g->ctrl);
+    if (!st.base || st.off_meta != om || st.off_trace != ot) {
+        if (st.base) (void)hipHostFree(st.base);
+        st.base = nullptr;
+        if (hipHostMalloc((void**)&st.base, ot + sizeof(TraceRec) * kTraceCap, hipHostMallocDefault) != hipSuccess)
             return fail(MIS_ENOMEM, "pinned host allocation failed");
+        st.off_meta = om;
+        st.off_trace = ot;
+        st.ctrl = reinterpret_cast<Ctrl*>(st.base);
+        st.meta = reinterpret_cast<Meta*>(st.base + om);
+        st.trace = reinterpret_cast<TraceRec*>(st.base + ot);
     }
     *out = &st;
     return MIS_OK;
@@ -389,7 +398,7 @@ int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, mis_stats* st, 
     const bool timing = st && st->timing;
 
     Staging* sg = nullptr;
-    TC_CHECK(staging(&sg));
+    TC_CHECK(staging(g, &sg));
     ++g->solves;
     TC_CHECK(solve_begin(g, s));
 
@@ -412,16 +421,14 @@ int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, mis_stats* st, 
             // the result, written by the device only if this batch decided the last vertex
             if (rc == MIS_OK) rc = solve_output(g, in_set, s, true);
             if (rc != MIS_OK) break;
-            // ring slots of rounds drained+1 .. enq
+            // ring slots of rounds drained+1 .. enq (ring order; all slots once it wraps),
+            // with ctrl and meta in front of them: one copy
             const int64_t first = drained % kTraceCap, cnt = enq + k - drained;
             enq += k;
-            const int64_t a1 = std::min<int64_t>(cnt, kTraceCap - first);
-            if (hipMemcpyAsync(sg->trace + first, g->trace + first, a1 * sizeof(TraceRec), hipMemcpyDeviceToHost, s) !=
-                    hipSuccess ||
-                (cnt > a1 && hipMemcpyAsync(sg->trace, g->trace, (cnt - a1) * sizeof(TraceRec), hipMemcpyDeviceToHost,
-                                            s) != hipSuccess) ||
-                hipMemcpyAsync(sg->ctrl, g->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
-                hipMemcpyAsync(sg->meta, g->meta, sizeof(Meta), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            const int64_t slots = std::min<int64_t>(first + cnt, kTraceCap);
+            const size_t span = sg->off_trace + (size_t)kTraceCap * sizeof(TraceRec);
+            const size_t bytes = std::min(span, (sg->off_trace + (size_t)slots * sizeof(TraceRec) + 255) & ~(size_t)255);
+            if (hipMemcpyAsync(sg->base, g->ctrl, bytes, hipMemcpyDeviceToHost, s) != hipSuccess ||
                 hipStreamSynchronize(s) != hipSuccess) {
                 rc = fail(MIS_EHIP, std::string("round loop: ") + hipGetErrorString(hipGetLastError()));
                 break;
