@@ -64,6 +64,16 @@ def measured_traffic(a):
     return rec["traffic_bytes_per_launch"]
 
 
+def stored_quality(a):
+    """MIS sizes of the benchmark graph under the sequential min-degree greedy heuristic and
+    the greedy pass in key order, stored by tests/golden/make_quality.py (seed-1 graph,
+    default keys of seed 1), or None for another workload."""
+    path = os.path.join(ROOT, "tests", "golden", "rmat22_quality.json")
+    if a.workload != "rmat22" or a.seed != 1 or not os.path.exists(path):
+        return None
+    return json.load(open(path))
+
+
 def measured_mfma(a):
     """int8 matrix-core use of the tile exclusion kernel from the committed counter
     record (rocprofv3 MFMA counters), or None when the configuration differs or the
@@ -428,6 +438,12 @@ def main():
         "mis_size": int(st_tile["n_in"]),
         "tile_equals_csr": same,
     }
+    q = stored_quality(a)
+    if q is not None:   # set size against the sequential min-degree greedy heuristic
+        res["quality"] = {"mis_size": res["mis_size"], "mindeg_greedy_size": q["mindeg_greedy_size"],
+                          "ratio_to_mindeg_greedy": round(res["mis_size"] / q["mindeg_greedy_size"], 5),
+                          "equals_key_greedy": res["mis_size"] == q["key_greedy_size"],
+                          "source": "tests/golden/rmat22_quality.json"}
     # roofline of the dominant round kernel (HIP events on the solve stream)
     names = ["tile_candidate", "tile_exclusion_mfma", "tile_finalize"]
     k = int(np.argmax(stt["kernel_ms"]))

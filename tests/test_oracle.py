@@ -297,3 +297,16 @@ def test_path_decreasing_keys(n):
     st, r, tr = oracle.roundsync(rp, ci, k)
     assert r == (n + 1) // 2
     assert np.nonzero(st == oracle.IN)[0].tolist() == list(range(0, n, 2))
+
+
+def test_stored_quality_record_matches_the_oracle():
+    # the key-greedy size stored for the benchmark graph is recomputed here; the
+    # min-degree size (a minute of CPU) is checked for being a valid set size only
+    import json
+    import os
+    rec = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "rmat22_quality.json")))
+    g = gen.workload("rmat22", seed=rec["graph_seed"])
+    assert (g.n, g.m) == (rec["n"], rec["edges"])
+    kg = oracle.greedy(g.row_ptr, g.col_idx, oracle.keys(g.row_ptr, rec["key_seed"]))
+    assert int(kg.sum()) == rec["key_greedy_size"]
+    assert 0 < rec["mindeg_greedy_size"] <= rec["n"]
