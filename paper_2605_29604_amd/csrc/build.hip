@@ -137,14 +137,31 @@ __global__ void k_order_keys(const int64_t* rp, const uint64_t* key, int64_t n, 
     }
 }
 
-// order and new ids from sorted ~keys that carry the vertex id in their low 24 bits
-__global__ void k_scatter_order_keys(const int64_t* rp, const uint64_t* sorted_sk, int64_t n, int32_t* order,
-                                     int32_t* new_id, int32_t* ndeg) {
+// Order and new ids from sorted ~keys that carry the vertex id in their low 24 bits.
+// The keys were sorted on bits [lo, 64) only: a key inside a run of keys equal in
+// those bits goes to the run's start plus its rank in the run by the whole key (the
+// ids make the keys distinct).  The sorted keys are only read, so the runs need no
+// coordination between threads; they are short (the bits below lo hold hash bits
+// and the id).
+__global__ void k_scatter_order_keys(const int64_t* rp, const uint64_t* sorted_sk, int64_t n, int lo,
+                                     int32_t* order, int32_t* new_id, int32_t* ndeg) {
     GRID_STRIDE(p, n) {
-        const int32_t v = (int32_t)(~sorted_sk[p] & 0xFFFFFFull);
-        order[p] = v;
-        new_id[v] = (int32_t)p;
-        ndeg[p] = (int32_t)(rp[v + 1] - rp[v]);
+        // the key and both neighbours (clamped indices) in one round trip
+        const uint64_t x = sorted_sk[p], xp = sorted_sk[p > 0 ? p - 1 : p], xn = sorted_sk[p + 1 < n ? p + 1 : p];
+        const uint64_t t = x >> lo;
+        int64_t q = p;
+        if ((p > 0 && (xp >> lo) == t) || (p + 1 < n && (xn >> lo) == t)) {
+            int64_t s0 = p, e = p + 1;
+            while (s0 > 0 && (sorted_sk[s0 - 1] >> lo) == t) --s0;
+            while (e < n && (sorted_sk[e] >> lo) == t) ++e;
+            int64_t rank = 0;
+            for (int64_t j = s0; j < e; ++j) rank += sorted_sk[j] < x;
+            q = s0 + rank;
+        }
+        const int32_t v = (int32_t)(~x & 0xFFFFFFull);
+        order[q] = v;
+        new_id[v] = (int32_t)q;
+        ndeg[q] = (int32_t)(rp[v + 1] - rp[v]);
     }
 }
 
@@ -687,8 +704,11 @@ int build_order(mis_graph* g, hipStream_t s) {
     const int lo = g->reorder == MIS_REORDER_DEGREE ? 0 : (g->user_keys ? 0 : 24);
     const int hi = g->reorder == MIS_REORDER_DEGREE ? 8 : 64;
     if (ids_in_key) {
-        TC_CHECK(radix_sort_u64(g->sk, g->sk2, nullptr, nullptr, n, nullptr, lo, hi, g->sort_tmp, &alt, s));
-        LAUNCH(k_scatter_order_keys, n, g->row_ptr, alt ? g->sk2 : g->sk, n, g->order, g->new_id, g->ndeg);
+        // bits 34..63 (degree class and 22 hash bits) in three 10-bit passes, then the
+        // runs that tie on them are ordered on the rest (10 hash bits and the id)
+        constexpr int kTieBits = 34;
+        TC_CHECK(radix_sort_u64(g->sk, g->sk2, nullptr, nullptr, n, nullptr, kTieBits, hi, g->sort_tmp, &alt, s));
+        LAUNCH(k_scatter_order_keys, n, g->row_ptr, alt ? g->sk2 : g->sk, n, kTieBits, g->order, g->new_id, g->ndeg);
         return MIS_OK;
     }
     TC_CHECK(radix_sort_u64(g->sk, g->sk2, g->pl, g->pl2, n, nullptr, lo, hi, g->sort_tmp, &alt, s));

@@ -150,6 +150,17 @@ def test_default_keys_given_by_caller(tile):
     check(g.row_ptr, g.col_idx, ("tile", tile, "key", 1), seed=9, label="rmat14-default")
 
 
+def test_one_degree_class_key_order():
+    # every vertex of a cycle has degree 2, so all keys share their degree class: the
+    # order sort's ties on the class and 22 hash bits come in runs averaging two,
+    # thousands of them eight or longer (the path that sorts a run in memory)
+    n = 1 << 23
+    rp = np.arange(0, 2 * n + 1, 2, dtype=np.int64)
+    nb = np.stack([(np.arange(n) - 1) % n, (np.arange(n) + 1) % n], axis=1)
+    ci = np.sort(nb, axis=1).astype(np.int32).ravel()
+    check(rp, ci, ("tile", 16, "key", 1), seed=5, label="cycle2^23")
+
+
 def test_empty_graph():
     T = tcmis_mod()
     drp = torch.zeros(1, dtype=torch.int64, device="cuda")
