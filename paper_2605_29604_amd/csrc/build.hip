@@ -335,12 +335,16 @@ __device__ inline bool is_head(const uint64_t* ent, int64_t e, int64_t nvalid, u
     return e == 0 || tile_key<kTshift>(*x) != tile_key<kTshift>(ent[e - 1]);
 }
 
+// heads per chunk of sorted entries; also clears hrows (n_rows words) and the
+// row-block tile counts (n_rows + 1 words) that the bitmap pass adds up
 template <int kTshift>
-// heads per chunk of sorted entries; also clears hrows (n_rows words) for the bitmap pass
 __global__ void __launch_bounds__(kBlock) k_head_count(const uint64_t* ent, const Meta* meta, int32_t* sums,
-                                                       uint32_t* hrows, int64_t n_rows) {
+                                                       uint32_t* hrows, int64_t* rb_cnt, int64_t n_rows) {
     __shared__ int32_t wsum[kBlock / kWave];
-    GRID_STRIDE(I, n_rows) hrows[I] = 0;
+    GRID_STRIDE(I, n_rows + 1) {
+        if (I < n_rows) hrows[I] = 0;
+        rb_cnt[I] = 0;
+    }
     const int64_t nvalid = meta->nvalid;
     const int64_t base = (int64_t)blockIdx.x * kHeadChunk;
     int c = 0;
@@ -359,7 +363,7 @@ __global__ void __launch_bounds__(kBlock) k_head_count(const uint64_t* ent, cons
 
 template <int kTshift>
 __global__ void __launch_bounds__(kBlock) k_head_write(const uint64_t* ent, const Meta* meta, const int32_t* chunk_off,
-                                                       int32_t* tile_start, int32_t* tile_col, int32_t* tile_row) {
+                                                       int32_t* tile_start, int32_t* tile_col) {
     __shared__ int32_t wcnt[kBlock / kWave];
     const int64_t nvalid = meta->nvalid;
     const int lane = lane_id(), wid = threadIdx.x / kWave;
@@ -381,44 +385,43 @@ __global__ void __launch_bounds__(kBlock) k_head_write(const uint64_t* ent, cons
             const int t = before + __popcll(b & lanes_below());
             tile_start[t] = (int32_t)e;
             tile_col[t] = (int32_t)(((x >> 5) & 0x7FFFFFFFull) >> kTshift);
-            tile_row[t] = (int32_t)(x >> 36);
         }
         run = total;
         __syncthreads();
     }
 }
 
-// one lane per tile (T=16) or per quarter tile (T=32, rows 8k..8k+7): OR the
-// tile's entries into 8 registers, store them, and OR the rows that have an entry
-// into hrows of the tile's row-block (lanes of one row-block combine first)
-// Tile bitmaps and the rows with entries.  A wavefront takes 64 consecutive tiles,
-// reads their sorted entries together (coalesced), finds each entry's tile by a
-// binary search over the 64 tile starts in LDS, ORs the entry's bit into that
-// tile's bitmap in LDS, and writes the 64 bitmaps out as one contiguous run.  Bit
-// (row r, column c) of a tile is bit r * T + c of its words.
+// Tile bitmaps, the rows with entries and the tiles of each row-block.  A wavefront
+// takes 64 consecutive tiles, reads their sorted entries together (coalesced), finds
+// each entry's tile by a binary search over the 64 tile starts in LDS, ORs the
+// entry's bit into that tile's bitmap in LDS (a tile's first entry also gives its
+// row-block), and writes the 64 bitmaps out as one contiguous run.  Bit (row r,
+// column c) of a tile is bit r * T + c of its words.  Lanes of one row-block
+// combine their rows into hrows and their tile count into rb_cnt, one atomic each.
 template <int T>
 __global__ void __launch_bounds__(kBlock) k_tile_bits(const uint64_t* ent, const int32_t* tile_start,
-                                                      const int32_t* tile_row, const Meta* meta, uint32_t* bits,
-                                                      uint32_t* hrows) {
+                                                      const Meta* meta, uint32_t* bits, uint32_t* hrows,
+                                                      int64_t* rb_cnt) {
     constexpr int W = T * T / 32;   // bitmap words per tile
     constexpr int kWpb = kBlock / kWave;
     __shared__ uint32_t sbits[kWpb][kWave * W];
     __shared__ int32_t sstart[kWpb][kWave];
+    __shared__ int32_t srow[kWpb][kWave];
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     uint32_t* sb = sbits[wid];
     int32_t* ss = sstart[wid];
+    int32_t* sr = srow[wid];
     const int64_t nt = meta->ntiles, nvalid = meta->nvalid;
     const int64_t ntask = (nt + kWave - 1) / kWave;
     const int64_t tstride = (int64_t)gridDim.x * kWpb;
-    // a task's tile starts, row-blocks and entry bound, loaded one task ahead
-    int32_t n_start = 0, n_row = -1;
+    // a task's tile starts and entry bound, loaded one task ahead
+    int32_t n_start = 0;
     int64_t n_hi = 0;
     auto fetch = [&](int64_t task) {
         if (task >= ntask) return;
         const int64_t t0 = task * kWave;
         const int ntl = (int)min<int64_t>(kWave, nt - t0);
         n_start = lane < ntl ? tile_start[t0 + lane] : 0x7FFFFFFF;
-        n_row = lane < ntl ? tile_row[t0 + lane] : -1;
         n_hi = t0 + ntl < nt ? (int64_t)tile_start[t0 + ntl] : nvalid;
     };
     int64_t task = (int64_t)blockIdx.x * kWpb + wid;
@@ -426,7 +429,7 @@ __global__ void __launch_bounds__(kBlock) k_tile_bits(const uint64_t* ent, const
     for (; task < ntask; task += tstride) {
         const int64_t t0 = task * kWave;
         const int ntl = (int)min<int64_t>(kWave, nt - t0);   // tiles of this task
-        const int32_t start = n_start, row = n_row;
+        const int32_t start = n_start;
         const int64_t e_hi = n_hi;
         fetch(task + tstride);
         const int64_t e_lo = __shfl(start, 0, kWave);
@@ -453,6 +456,7 @@ __global__ void __launch_bounds__(kBlock) k_tile_bits(const uint64_t* ent, const
                     const uint64_t x = xs[u];
                     const int b = (int)((x & (T - 1)) * T + ((x >> 5) & (T - 1)));
                     atomicOr(&sb[lo * W + (b >> 5)], 1u << (b & 31));
+                    if (e == ss[lo]) sr[lo] = (int32_t)(x >> 36);   // the tile's first entry
                 }
             }
         }
@@ -474,20 +478,10 @@ __global__ void __launch_bounds__(kBlock) k_tile_bits(const uint64_t* ent, const
                 }
             }
         }
-        run_or(lane < ntl ? row : -1, rm, hrows);
+        const int32_t row = lane < ntl ? sr[lane] : -1;
+        run_or(row, rm, hrows);
+        run_add(row, 1, rb_cnt);
         wave_sync_lds();   // the next task clears sb
-    }
-}
-
-__global__ void k_rb_ptr(const int32_t* tile_row, const Meta* meta, int64_t nI, int64_t* rb_ptr) {
-    const int64_t nt = meta->ntiles;
-    GRID_STRIDE(I, nI + 1) {
-        int64_t lo = 0, hi = nt;
-        while (lo < hi) {
-            const int64_t mid = (lo + hi) >> 1;
-            if (tile_row[mid] < I) lo = mid + 1; else hi = mid;
-        }
-        rb_ptr[I] = lo;
     }
 }
 
@@ -607,7 +601,6 @@ size_t layout(mis_graph* g, char* base) {
     take(&g->rb_ptr, (size_t)(nI + 1) * 8);
     take(&g->rb_chunk, (size_t)(nI + 1) * 8);
     take(&g->tile_col, (size_t)cap * 4);
-    take(&g->tile_row, (size_t)cap * 4);
     take(&g->tile_start, (size_t)cap * 4);
     take(&g->tile_bits, (size_t)cap * (T * T / 32) * 4);
     if (!g->orient) take(&g->key_p, (size_t)nI * T * 8);
@@ -752,21 +745,25 @@ int build_tiles_t(mis_graph* g, hipStream_t s) {
     const int64_t nheads = ceil_div(nnz, kHeadChunk);
     if (nheads > 0) {
         hipLaunchKernelGGL((k_head_count<kTshift>), dim3((unsigned)nheads), dim3(kBlock), 0, s, sorted, g->meta,
-                           g->hsums, g->hrows, nI);
+                           g->hsums, g->hrows, g->rb_ptr, nI);
         TC_HIP(hipGetLastError());
         TC_CHECK(scan_excl_i32(g->hsums, g->hsums, nheads, &g->meta->ntiles, (int32_t*)g->scan_tmp, s));
         hipLaunchKernelGGL((k_head_write<kTshift>), dim3((unsigned)nheads), dim3(kBlock), 0, s, sorted, g->meta,
-                           g->hsums, g->tile_start, g->tile_col, g->tile_row);
+                           g->hsums, g->tile_start, g->tile_col);
         TC_HIP(hipGetLastError());
     }
-    if (nheads == 0) TC_HIP(hipMemsetAsync(g->hrows, 0, (size_t)nI * 4, s));   // else cleared by the head count
+    if (nheads == 0) {   // else cleared by the head count
+        TC_HIP(hipMemsetAsync(g->hrows, 0, (size_t)nI * 4, s));
+        TC_HIP(hipMemsetAsync(g->rb_ptr, 0, (size_t)(nI + 1) * 8, s));
+    }
     if (nheads > 0) {   // one wavefront per 64 tiles (the tile count is on the device: sized by capacity)
         const int64_t blocks = std::min<int64_t>(ceil_div(ceil_div(g->tile_cap, kWave), kBlock / kWave), 8192);
         hipLaunchKernelGGL((k_tile_bits<T>), dim3((unsigned)blocks), dim3(kBlock), 0, s, sorted, g->tile_start,
-                           g->tile_row, g->meta, g->tile_bits, g->hrows);
+                           g->meta, g->tile_bits, g->hrows, g->rb_ptr);
         TC_HIP(hipGetLastError());
     }
-    LAUNCH(k_rb_ptr, nI + 1, g->tile_row, g->meta, nI, g->rb_ptr);
+    // row-block tile counts -> each row-block's first tile (rb_ptr[nI] = all tiles)
+    TC_CHECK(scan_excl_i64(g->rb_ptr, g->rb_ptr, nI + 1, (int64_t*)nullptr, (int64_t*)g->scan_tmp, s));
     // 5. the round-1 chunk list: every row-block's tiles in chunks of kTpi; rb_chunk
     //    holds each row-block's first chunk
     constexpr int kTpi = T == 16 ? 64 : 16;

@@ -147,7 +147,6 @@ struct mis_graph {
     int64_t* rb_ptr = nullptr;        // [nI+1] tile range of each row-block
     int64_t* rb_chunk = nullptr;      // [nI+1] first round-1 chunk of each row-block
     int32_t* tile_col = nullptr;      // [tile_cap] column block J
-    int32_t* tile_row = nullptr;      // [tile_cap] row block I
     int32_t* tile_start = nullptr;    // [tile_cap] first sorted entry of each tile
     uint32_t* tile_bits = nullptr;    // [tile_cap * tile*tile/32] row masks (T=16: two rows per word)
     uint64_t* key_p = nullptr;        // [nI*tile] keys in new order, padding 0 (orient = 0)
