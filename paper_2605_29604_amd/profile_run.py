@@ -102,13 +102,13 @@ def summarize_mfma(a) -> int:
                        for i, p in enumerate(per))
     md = f"""# {a.workload}: int8 matrix-core use of the tile exclusion kernel
 
-Command (one counter pass from /tmp on the GPU host; REPO = the repository root):
+Command (one counter pass, run from /tmp; REPO = the repository root, OUT = a directory for the output):
 
 ```
 rocprofv3 --pmc SQ_VALU_MFMA_BUSY_CYCLES SQ_INSTS_VALU_MFMA_MOPS_I8 SQ_INSTS_VALU_MFMA_I8 SQ_INSTS_MFMA \\
-    GRBM_GUI_ACTIVE --kernel-trace --output-format csv -d $REPO/gpurun_out/pmc_mfma -o run -- \\
+    GRBM_GUI_ACTIVE --kernel-trace --output-format csv -d $OUT/pmc_mfma -o run -- \\
     python3 $REPO/paper_2605_29604_amd/profile_run.py
-python3 paper_2605_29604_amd/profile_run.py --summarize-mfma gpurun_out/pmc_mfma
+python3 paper_2605_29604_amd/profile_run.py --summarize-mfma $OUT/pmc_mfma
 ```
 
 Each `v_mfma_i32_16x16x64_i8` is 32,768 integer operations (SQ_INSTS_VALU_MFMA_MOPS_I8 counts them / 512).
@@ -156,14 +156,15 @@ def summarize(a) -> int:
                      for i, (f, w, b) in enumerate(zip(fetch, write, per)))
     md = f"""# {a.workload}: HBM traffic of the tile exclusion kernel (FETCH_SIZE / WRITE_SIZE)
 
-Commands (two passes, one counter each, from /tmp on the GPU host; REPO = the repository root):
+Commands (two passes, one counter each, run from /tmp; REPO = the repository root, OUT = a directory for
+the output):
 
 ```
-rocprofv3 --pmc FETCH_SIZE --kernel-trace --output-format csv -d $REPO/gpurun_out/pmc_fetch -o run -- \\
+rocprofv3 --pmc FETCH_SIZE --kernel-trace --output-format csv -d $OUT/pmc_fetch -o run -- \\
     python3 $REPO/paper_2605_29604_amd/profile_run.py
-rocprofv3 --pmc WRITE_SIZE --kernel-trace --output-format csv -d $REPO/gpurun_out/pmc_write -o run -- \\
+rocprofv3 --pmc WRITE_SIZE --kernel-trace --output-format csv -d $OUT/pmc_write -o run -- \\
     python3 $REPO/paper_2605_29604_amd/profile_run.py
-python3 paper_2605_29604_amd/profile_run.py --summarize gpurun_out/pmc_fetch gpurun_out/pmc_write
+python3 paper_2605_29604_amd/profile_run.py --summarize $OUT/pmc_fetch $OUT/pmc_write
 ```
 
 `profile_run.py` copies {a.copy_mib} MiB device to device, then builds and solves {a.workload} on the tile path
