@@ -328,6 +328,8 @@ __device__ inline uint64_t tile_key(uint64_t x) {
 }
 
 // does sorted entry e start a tile (its (row block, column block) differs from e-1's)?
+// (both loads issued together; loading e-1 costs less than taking it from the lane
+// below, whose shuffle would wait for this lane's load)
 template <int kTshift>
 __device__ inline bool is_head(const uint64_t* ent, int64_t e, int64_t nvalid, uint64_t* x) {
     if (e >= nvalid) return false;
@@ -480,7 +482,14 @@ __global__ void __launch_bounds__(kBlock) k_tile_bits(const uint64_t* ent, const
         }
         const int32_t row = lane < ntl ? sr[lane] : -1;
         run_or(row, rm, hrows);
-        run_add(row, 1, rb_cnt);
+        // tiles of each row-block in the task: from a run's first lane to the next run's
+        const bool first = lane < ntl && (lane == 0 || sr[lane - 1] != row);
+        const uint64_t firsts = ballot(first);
+        if (first) {
+            const uint64_t above = lane == kWave - 1 ? 0ull : firsts & (~0ull << (lane + 1));
+            const int next = above ? __ffsll((long long)above) - 1 : ntl;
+            atomicAdd((unsigned long long*)&rb_cnt[row], (unsigned long long)(next - lane));
+        }
         wave_sync_lds();   // the next task clears sb
     }
 }

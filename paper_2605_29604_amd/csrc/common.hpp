@@ -71,21 +71,6 @@ __device__ inline void run_or(int32_t I, uint32_t m, uint32_t* dst) {
     if ((lane == 0 || Ip != I) && I >= 0 && m) atomicOr(&dst[I], m);
 }
 
-// Lanes that share a key I are adjacent (I < 0: none).  Adds each run's values in
-// registers and lets the run's first lane add the sum to dst[I] with one atomic.
-// Every lane of the wave must call it.
-__device__ inline void run_add(int32_t I, int32_t c, int64_t* dst) {
-    const int lane = lane_id();
-    #pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        const int32_t co = __shfl_down(c, off, kWave);
-        const int32_t Io = __shfl_down(I, off, kWave);
-        if (lane + off < kWave && Io == I) c += co;
-    }
-    const int32_t Ip = __shfl_up(I, 1, kWave);
-    if ((lane == 0 || Ip != I) && I >= 0 && c) atomicAdd((unsigned long long*)&dst[I], (unsigned long long)c);
-}
-
 // Prefix scans (no allocation; `scratch` holds scan_scratch_elems(count) elements
 // of the scanned type; d_total, if given, receives the grand total on the device).
 int64_t scan_scratch_elems(int64_t count);
