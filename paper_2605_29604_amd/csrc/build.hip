@@ -88,13 +88,18 @@ __global__ void k_validate_edges(const int64_t* rp, const int32_t* ci, int64_t n
 // q(d) = floor(255 / (1 + d)) (lower degree wins) and hash = top 32 bits of output
 // v+1 of the SplitMix64 stream seeded with `seed` (the random perturbation).
 // In a batch the id in the key is graph-local (v - goff[g]).
-__global__ void k_keys(const int64_t* rp, int64_t n, uint64_t seed, const int64_t* goff, int64_t count, uint64_t* key) {
+// With `sk` the kernel also writes the priority order's sort keys (k_order_keys'
+// layout: ~key at position n-1-v), saving that pass a read of the keys.
+__global__ void k_keys(const int64_t* rp, int64_t n, uint64_t seed, const int64_t* goff, int64_t count, uint64_t* key,
+                       uint64_t* sk) {
     GRID_STRIDE(v, n) {
         const int64_t deg = rp[v + 1] - rp[v];
         const uint64_t q = (uint64_t)(255 / (1 + deg));
         const int64_t lv = goff ? v - goff[graph_of(goff, count, v)] : v;
         const uint64_t h = splitmix_at(seed, (uint64_t)lv + 1) >> 32;
-        key[v] = (q << 56) | (h << 24) | (uint64_t)lv;
+        const uint64_t k = (q << 56) | (h << 24) | (uint64_t)lv;
+        key[v] = k;
+        if (sk) sk[n - 1 - v] = ~k;
     }
 }
 
@@ -655,12 +660,20 @@ int validate_graph(const mis_csr* csr, const uint64_t* user_keys, const int64_t*
     return MIS_OK;
 }
 
+// default keys of a single graph hold the vertex id in their low 24 bits: the order
+// sort then moves the keys alone and the order is read back from them
+bool default_keys_in_order(const mis_graph* g) {
+    return g->reorder == MIS_REORDER_KEY && !g->user_keys && g->count == 0 && g->n <= (1 << 24);
+}
+
 int build_keys(mis_graph* g, const mis_build_opts* o, hipStream_t s) {
     if (g->n == 0) return MIS_OK;
     if (o->keys) {
         TC_HIP(hipMemcpyAsync(g->key, o->keys, (size_t)g->n * 8, hipMemcpyDeviceToDevice, s));
     } else {
-        LAUNCH(k_keys, g->n, g->row_ptr, g->n, o->seed, g->goff, (int64_t)g->count, g->key);
+        // the key order of one graph with default keys: the sort keys come with the keys
+        uint64_t* sk = g->path == MIS_PATH_TILE && default_keys_in_order(g) ? g->sk : nullptr;
+        LAUNCH(k_keys, g->n, g->row_ptr, g->n, o->seed, g->goff, (int64_t)g->count, g->key, sk);
     }
     return MIS_OK;
 }
@@ -674,11 +687,6 @@ int build_csr_lists(mis_graph* g, hipStream_t s) {
     return MIS_OK;
 }
 
-// default keys of a single graph hold the vertex id in their low 24 bits: the order
-// sort then moves the keys alone and the order is read back from them
-bool default_keys_in_order(const mis_graph* g) {
-    return g->reorder == MIS_REORDER_KEY && !g->user_keys && g->count == 0 && g->n <= (1 << 24);
-}
 
 int build_order(mis_graph* g, hipStream_t s) {
     const int64_t n = g->n;
@@ -701,7 +709,8 @@ int build_order(mis_graph* g, hipStream_t s) {
         return MIS_OK;
     }
     const bool ids_in_key = default_keys_in_order(g);
-    LAUNCH(k_order_keys, n, g->row_ptr, g->key, n, g->reorder, g->sk, ids_in_key ? nullptr : g->pl);
+    if (!ids_in_key)   // (with default keys of one graph k_keys wrote the sort keys)
+        LAUNCH(k_order_keys, n, g->row_ptr, g->key, n, g->reorder, g->sk, g->pl);
     bool alt = false;
     const int lo = g->reorder == MIS_REORDER_DEGREE ? 0 : (g->user_keys ? 0 : 24);
     const int hi = g->reorder == MIS_REORDER_DEGREE ? 8 : 64;
