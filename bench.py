@@ -74,6 +74,25 @@ def stored_quality(a):
     return json.load(open(path))
 
 
+def measured_stalls(a):
+    """Wait share of the tile exclusion kernel's waves and busy share of its address units
+    from the committed counter record, or None when the configuration differs or the
+    kernel sources changed since the counters were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "tile_exclusion_rmat22_stalls.json")))
+    except (OSError, ValueError):
+        return None
+    if (rec.get("workload"), rec.get("tile"), rec.get("reorder"), rec.get("orient"), rec.get("seed")) != \
+            (a.workload, a.tile, a.reorder, a.orient, a.seed):
+        return None
+    for name, digest in rec.get("source_sha256", {}).items():
+        path = os.path.join(ROOT, "paper_2605_29604_amd", "csrc", name)
+        if not os.path.exists(path) or hashlib.sha256(open(path, "rb").read()).hexdigest() != digest:
+            return None
+    return {"wait_share": round(rec["wait_share"], 4), "ta_busy_share": round(rec["ta_busy_share"], 4)}
+
+
 def measured_mfma(a):
     """int8 matrix-core use of the tile exclusion kernel from the committed counter
     record (rocprofv3 MFMA counters), or None when the configuration differs or the
@@ -459,7 +478,8 @@ def main():
                        "traffic": None if traffic is None else int(traffic),
                        "avg_launch_us": round(avg_ms * 1e3, 3), "launches": launches,
                        "alg_bytes_per_launch": int(bytes_k / launches),
-                       "mfma": measured_mfma(a) if k == 1 else None}
+                       "mfma": measured_mfma(a) if k == 1 else None,
+                       "stalls": measured_stalls(a) if k == 1 else None}
 
     # round-loop launch modes of the same solve (identical results)
     modes = {}
