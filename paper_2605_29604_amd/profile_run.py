@@ -191,6 +191,71 @@ processing of the divergent column-state gathers (64 different lines per instruc
     return 0
 
 
+def summarize_build(a) -> int:
+    """HBM bytes of every kernel of one build + solve (the same two counter runs as the
+    exclusion kernel's traffic record), scaled like it, with each kernel's duration
+    from the runs' kernel trace."""
+    import re
+    fdir, wdir = a.summarize_build
+    cf, _ = _counter(fdir, "FETCH_SIZE", f"k_tile_excl<{a.tile}>")
+    cw, _ = _counter(wdir, "WRITE_SIZE", f"k_tile_excl<{a.tile}>")
+    copy_kib = a.copy_mib * 1024.0
+    sf, sw = copy_kib / cf, copy_kib / cw
+
+    def per_kernel(folder, counter):
+        out = {}
+        with open(os.path.join(folder, "run_counter_collection.csv")) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != counter:
+                    continue
+                m = re.search(r"(k_\w+(<[^>]*>)?)", r["Kernel_Name"])
+                if not m:
+                    continue
+                ns = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+                out.setdefault(m.group(1), []).append((float(r["Counter_Value"]), ns))
+        return out
+
+    fk, wk = per_kernel(fdir, "FETCH_SIZE"), per_kernel(wdir, "WRITE_SIZE")
+    rows = []
+    for k, lst in fk.items():
+        f_kib, ns = max(lst)                       # the tile path's largest dispatch
+        w_kib = max(v for v, _ in wk.get(k, [(0.0, 0)]))
+        mb = (f_kib * sf + w_kib * sw) * 1024 / 1e6
+        rows.append((mb, k, f_kib * sf * 1024 / 1e6, w_kib * sw * 1024 / 1e6, ns / 1e3))
+    rows.sort(reverse=True)
+    lines = "\n".join(f"| `{k}` | {fm:.0f} | {wm:.0f} | {us:.0f} | {mb / us:.2f} |"
+                       for mb, k, fm, wm, us in rows[:14] if us > 0)
+    md = f"""# {a.workload}: HBM traffic of the build and solve kernels
+
+From the same two counter passes as `tile_exclusion_{a.workload}_traffic.md` (REPO = the repository root,
+OUT = a directory for the output; run from /tmp):
+
+```
+rocprofv3 --pmc FETCH_SIZE --kernel-trace --output-format csv -d $OUT/pmc_fetch -o run -- \\
+    python3 $REPO/paper_2605_29604_amd/profile_run.py
+rocprofv3 --pmc WRITE_SIZE --kernel-trace --output-format csv -d $OUT/pmc_write -o run -- \\
+    python3 $REPO/paper_2605_29604_amd/profile_run.py
+python3 paper_2605_29604_amd/profile_run.py --summarize-build $OUT/pmc_fetch $OUT/pmc_write
+```
+
+FETCH_SIZE scaled by {sf:.4f} and WRITE_SIZE by {sw:.4f} (a {a.copy_mib} MiB copy); for each kernel its largest
+dispatch (the exclusion kernel: round 1), with that dispatch's duration under the counter pass.
+
+| Kernel | fetched MB | written MB | µs | TB/s |
+|---|---:|---:|---:|---:|
+{{lines}}
+
+`k_entries` moves about 5 GB (its 67 M random 4-byte new-id gathers each bring a 64-byte line) at close to
+the 8 TB/s HBM peak: it is bound by the bytes those gathers move, 16 times the bytes they use.
+"""
+    md = md.replace("{lines}", lines)
+    path = os.path.join(ROOT, "profiles", f"{a.workload}_build_traffic.md")
+    with open(path, "w") as fh:
+        fh.write(md)
+    print(path)
+    return 0
+
+
 def summarize(a) -> int:
     kernel = f"k_tile_excl<{a.tile}>"
     fdir, wdir = a.summarize
@@ -257,6 +322,7 @@ def main() -> int:
     p.add_argument("--summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     p.add_argument("--summarize-mfma", metavar="DIR")
     p.add_argument("--summarize-stalls", metavar="DIR")
+    p.add_argument("--summarize-build", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     a = p.parse_args()
     if a.summarize:
         return summarize(a)
@@ -264,6 +330,8 @@ def main() -> int:
         return summarize_mfma(a)
     if a.summarize_stalls:
         return summarize_stalls(a)
+    if a.summarize_build:
+        return summarize_build(a)
     import torch
     from paper_2605_29604_amd import gen, tcmis
 
