@@ -250,12 +250,15 @@ typedef struct {
     size_t arena_bytes;
     int32_t max_live;         /* requests on the device at once, 1..256 */
     int32_t rounds_per_step;  /* rounds enqueued per request between polls (0 = 4) */
-    mis_build_opts opts;      /* build options of requests admitted without their own */
+    mis_build_opts opts;      /* build options of requests admitted without their own
+                                 (launch must not be MIS_LAUNCH_PERSISTENT) */
 } mis_session_config;
 
 typedef struct {
     uint64_t tag;             /* the caller's tag from mis_session_admit */
-    int32_t status;           /* MIS_OK, or MIS_EINTERNAL if the round bound was exceeded */
+    int32_t status;           /* MIS_OK, or MIS_EINTERNAL if the round bound was exceeded or a
+                                 device-side check raised an error flag (the output is then
+                                 not a valid result) */
     int32_t rounds;           /* rounds the request took */
     int64_t n;                /* vertices */
     int64_t n_in;             /* size of its independent set */
@@ -275,7 +278,9 @@ int mis_session_create(const mis_session_config* cfg, mis_session** out);
  *           (at least one of d_out / h_out).
  * Returns MIS_EBUSY, with nothing enqueued, when no slot or no arena region of the
  * request's footprint is free (retry after mis_session_progress retires requests),
- * and MIS_EINVAL when the footprint exceeds the whole arena.  Validation options
+ * and MIS_EINVAL when the footprint exceeds the whole arena or opts asks for
+ * MIS_LAUNCH_PERSISTENT (cooperative grids of concurrent requests could not all be
+ * resident).  Validation options
  * (validate = 1, reorder = MIS_REORDER_RCM) synchronise the request's stream.
  */
 int mis_session_admit(mis_session* s, const mis_csr* csr, int32_t csr_on_host, const mis_build_opts* opts,
@@ -297,6 +302,15 @@ void mis_session_destroy(mis_session* s);
 
 /* Releases the handle (host memory only; the workspace stays the caller's). */
 void mis_free_tiles(mis_graph* g);
+
+/*
+ * Frees the pinned host buffers that idle solves keep for their round-loop polls
+ * (solves take one from a process-wide pool and give it back).  Optional: call it
+ * before the HIP runtime is shut down, e.g. at the end of a program; no library
+ * code frees host or device memory from a static destructor.  Solves running on
+ * other threads keep their buffers; a later solve allocates a new one.
+ */
+void mis_release_host_buffers(void);
 
 /* Static text for a status code. */
 const char* mis_status_string(int status);

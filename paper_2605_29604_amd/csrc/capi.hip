@@ -1,5 +1,6 @@
 // C ABI: argument checking, option resolution, the handle, and the polled round loop.
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <cstring>
 #include <string>
@@ -37,38 +38,73 @@ int fail(int code, const std::string& msg) {
     return code;
 }
 
-// Pinned host staging for the round-loop polls, one per host thread: a mirror of the
-// workspace span that holds ctrl, meta and the trace ring (adjacent in the layout),
-// so that one copy brings back all three.
+// Pinned host staging for the round-loop polls: a mirror of the workspace span that
+// holds ctrl, meta and the trace ring (adjacent in the layout), so that one copy
+// brings back all three.  Buffers come from a process-wide pool (a solve takes one
+// and gives it back), so concurrent solves on different threads never share one.
+// Nothing frees them from a static or thread-local destructor: those run inside
+// exit(), when the HIP runtime may already be gone.  mis_release_host_buffers()
+// frees the idle ones explicitly; whatever is left is returned with the process.
 struct Staging {
     char* base = nullptr;
+    size_t bytes = 0;
     size_t off_meta = 0, off_trace = 0;
     Ctrl* ctrl = nullptr;
     Meta* meta = nullptr;
     TraceRec* trace = nullptr;
-    ~Staging() {
-        if (base) (void)hipHostFree(base);
-    }
 };
-thread_local Staging t_stage;
 
-int staging(const mis_graph* g, Staging** out) {
-    Staging& st = t_stage;
+struct StagingPool {
+    std::mutex mu;
+    std::vector<Staging*> idle;
+};
+// deliberately never destroyed (see above)
+StagingPool& staging_pool() {
+    static StagingPool* p = new StagingPool();
+    return *p;
+}
+
+// Takes a staging buffer laid out for g (allocating one if no idle buffer is big
+// enough); give it back with staging_put.
+int staging_get(const mis_graph* g, Staging** out) {
     const size_t om = (size_t)((const char*)g->meta - (const char*)g->ctrl);
     const size_t ot = (size_t)((const char*)g->trace - (const char*)g->ctrl);
-    if (!st.base || st.off_meta != om || st.off_trace != ot) {
-        if (st.base) (void)hipHostFree(st.base);
-        st.base = nullptr;
-        if (hipHostMalloc((void**)&st.base, ot + sizeof(TraceRec) * kTraceCap, hipHostMallocDefault) != hipSuccess)
-            return fail(MIS_ENOMEM, "pinned host allocation failed");
-        st.off_meta = om;
-        st.off_trace = ot;
-        st.ctrl = reinterpret_cast<Ctrl*>(st.base);
-        st.meta = reinterpret_cast<Meta*>(st.base + om);
-        st.trace = reinterpret_cast<TraceRec*>(st.base + ot);
+    const size_t need = ot + sizeof(TraceRec) * kTraceCap;
+    Staging* st = nullptr;
+    {
+        StagingPool& P = staging_pool();
+        std::lock_guard<std::mutex> lock(P.mu);
+        for (size_t i = 0; i < P.idle.size(); ++i) {
+            if (P.idle[i]->bytes >= need) {
+                st = P.idle[i];
+                P.idle.erase(P.idle.begin() + (std::ptrdiff_t)i);
+                break;
+            }
+        }
     }
-    *out = &st;
+    if (!st) {
+        st = new (std::nothrow) Staging();
+        if (!st) return fail(MIS_ENOMEM, "host allocation failed");
+        if (hipHostMalloc((void**)&st->base, need, hipHostMallocDefault) != hipSuccess) {
+            delete st;
+            return fail(MIS_ENOMEM, "pinned host allocation failed");
+        }
+        st->bytes = need;
+    }
+    st->off_meta = om;
+    st->off_trace = ot;
+    st->ctrl = reinterpret_cast<Ctrl*>(st->base);
+    st->meta = reinterpret_cast<Meta*>(st->base + om);
+    st->trace = reinterpret_cast<TraceRec*>(st->base + ot);
+    *out = st;
     return MIS_OK;
+}
+
+void staging_put(Staging* st) {
+    if (!st) return;
+    StagingPool& P = staging_pool();
+    std::lock_guard<std::mutex> lock(P.mu);
+    P.idle.push_back(st);
 }
 
 __global__ void k_ctrl_init(Ctrl* ctrl, int64_t* stripes, int64_t n) {
@@ -398,7 +434,11 @@ int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, mis_stats* st, 
     const bool timing = st && st->timing;
 
     Staging* sg = nullptr;
-    TC_CHECK(staging(g, &sg));
+    TC_CHECK(staging_get(g, &sg));
+    struct Give {   // the buffer goes back to the pool on every return path
+        Staging* s;
+        ~Give() { staging_put(s); }
+    } give{sg};
     ++g->solves;
     TC_CHECK(solve_begin(g, s));
 
@@ -515,5 +555,15 @@ int mis_solve_batch(mis_graph* g, uint8_t* in_set, mis_stats* stats, int32_t* gr
 }
 
 void mis_free_tiles(mis_graph* g) { delete g; }
+
+void mis_release_host_buffers(void) {
+    StagingPool& P = staging_pool();
+    std::lock_guard<std::mutex> lock(P.mu);
+    for (Staging* st : P.idle) {
+        (void)hipHostFree(st->base);
+        delete st;
+    }
+    P.idle.clear();
+}
 
 }  // extern "C"

@@ -106,6 +106,8 @@ int mis_session_create(const mis_session_config* cfg, mis_session** out) {
     if (cfg->max_live < 1 || cfg->max_live > 256) return sfail(MIS_EINVAL, "max_live must be in [1, 256]");
     if (cfg->rounds_per_step < 0 || cfg->rounds_per_step > 1024)
         return sfail(MIS_EINVAL, "rounds_per_step must be in [0, 1024]");
+    if (cfg->opts.launch == MIS_LAUNCH_PERSISTENT)
+        return sfail(MIS_EINVAL, "a session does not run persistent (cooperative) launches");
     mis_session* S = new (std::nothrow) mis_session();
     if (!S) return sfail(MIS_ENOMEM, "host allocation failed");
     S->cfg = *cfg;
@@ -138,6 +140,10 @@ int mis_session_admit(mis_session* S, const mis_csr* csr, int32_t csr_on_host, c
     if (!d_out && !h_out) return sfail(MIS_EINVAL, "either d_out or h_out is required");
     mis_build_opts o = opts ? *opts : S->cfg.opts;
     o.poll_rounds = S->cfg.rounds_per_step;
+    // every live request runs on its own stream; cooperative grids sized to fill the
+    // device could not all be resident at once
+    if (o.launch == MIS_LAUNCH_PERSISTENT)
+        return sfail(MIS_EINVAL, "a session does not run persistent (cooperative) launches");
     size_t build_bytes = 0;
     TC_CHECK(mis_build_bytes(csr, &o, &build_bytes));
     const int64_t n = csr->n, nnz = csr->nnz;
@@ -208,7 +214,10 @@ int mis_session_progress(mis_session* S, int32_t wait, mis_done* done, int32_t c
             if (sl.phase == Phase::Rounds) {
                 sl.rounds = sl.h_ctrl->round;
                 sl.n_in = sl.h_ctrl->n_in;
-                if (sl.h_ctrl->alive == 0) {
+                if (sl.h_ctrl->error != 0) {
+                    sl.status = MIS_EINTERNAL;   // a device-side invariant check failed
+                    TC_CHECK(enqueue_output(sl));
+                } else if (sl.h_ctrl->alive == 0) {
                     TC_CHECK(enqueue_output(sl));
                 } else if (sl.h_ctrl->round > sl.n + 1) {
                     sl.status = MIS_EINTERNAL;   // a strict key order decides a vertex every round

@@ -29,7 +29,8 @@ REORDERS = {"auto": REORDER_AUTO, "none": REORDER_NONE, "degree": REORDER_DEGREE
 EXPORTS = ["mis_default_opts", "mis_build_bytes", "mis_build_tiles", "mis_build_batch_bytes", "mis_build_batch",
            "mis_graph_bytes", "mis_solve", "mis_solve_batch", "mis_free_tiles", "mis_status_string", "mis_last_error",
            "mis_version", "mis_autotune_bytes", "mis_autotune", "mis_autotune_clear", "mis_session_create",
-           "mis_session_admit", "mis_session_progress", "mis_session_query", "mis_session_destroy"]
+           "mis_session_admit", "mis_session_progress", "mis_session_query", "mis_session_destroy",
+           "mis_release_host_buffers"]
 
 
 class MisCsr(ctypes.Structure):
@@ -128,6 +129,8 @@ def lib():
     L.mis_session_destroy.restype = None
     L.mis_free_tiles.argtypes = [vp]
     L.mis_free_tiles.restype = None
+    L.mis_release_host_buffers.argtypes = []
+    L.mis_release_host_buffers.restype = None
     L.mis_status_string.argtypes = [ctypes.c_int]
     L.mis_status_string.restype = ctypes.c_char_p
     L.mis_last_error.argtypes = []
@@ -352,6 +355,11 @@ def mis_autotune(row_ptr, col_idx, offsets=None, path="auto", tile=0, blocks_per
 
 def mis_autotune_clear():
     lib().mis_autotune_clear()
+
+
+def mis_release_host_buffers() -> None:
+    """Frees the idle pinned staging buffers of the round-loop polls."""
+    lib().mis_release_host_buffers()
 
 
 def mis_free_tiles(g: MisGraph):

@@ -133,3 +133,17 @@ def test_session_refuses_requests_larger_than_the_arena():
     st, rounds, _ = oracle.roundsync(small.row_ptr, small.col_idx, oracle.keys(small.row_ptr, 1))
     assert np.array_equal(h, (st == oracle.IN).astype(np.uint8)) and d["rounds"] == rounds
     sess.close()
+
+
+def test_session_refuses_persistent_launch():
+    # concurrent requests each on their own stream cannot all hold a device-filling
+    # cooperative grid, so the session refuses persistent launches before any work
+    t = T()
+    small = gen.er(500, 2000, 1)
+    sess = t.Session(arena_bytes=4 * footprint(small), max_live=2)
+    with pytest.raises(t.MisError) as ei:
+        sess.admit(small.row_ptr, small.col_idx, tag=1, host_out=np.zeros(small.n, np.uint8),
+                   opts=dict(launch="persistent"))
+    assert ei.value.code == t.MIS_EINVAL
+    assert sess.query()[0] == 0
+    sess.close()

@@ -193,6 +193,15 @@ def test_min_degree_greedy_is_mis():
     assert oracle.mindeg_greedy(rp, ci).tolist() == [0, 1, 1, 1, 1, 1]
 
 
+def test_min_degree_greedy_uses_residual_degrees():
+    # hand-derived case where keeping the initial degrees picks a different set
+    rec = golden("mindeg_residual6.json")
+    rp, ci = csr_from_edges(rec["n"], [tuple(e) for e in rec["edges"]])
+    got = oracle.mindeg_greedy(rp, ci).tolist()
+    assert got == rec["in_set"]
+    assert got != rec["static_degree_in_set"]
+
+
 # --------------------------------------------------------------- special cases
 
 def test_edgeless_graph():

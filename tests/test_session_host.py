@@ -37,6 +37,12 @@ def test_session_argument_errors(L):
         setattr(bad, field, value)
         assert L.mis_session_create(ctypes.byref(bad), ctypes.byref(h)) == tcmis.MIS_EINVAL, field
         assert not h.value
+    # persistent (cooperative) launches cannot run as concurrent requests: refused on the host
+    bad = tcmis.MisSessionConfig()
+    ctypes.pointer(bad)[0] = cfg
+    bad.opts.launch = tcmis.LAUNCHES["persistent"]
+    assert L.mis_session_create(ctypes.byref(bad), ctypes.byref(h)) == tcmis.MIS_EINVAL
+    assert not h.value
     csr = tcmis.MisCsr(10, 0, ctypes.c_void_p(256), None)
     assert L.mis_session_admit(None, ctypes.byref(csr), 0, None, ctypes.c_void_p(256), None, 1) == tcmis.MIS_EINVAL
     n = ctypes.c_int32(0)
