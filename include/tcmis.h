@@ -47,9 +47,14 @@ typedef enum {
 
 /* Path through the round kernels. */
 enum {
-    MIS_PATH_AUTO = 0,    /* tile path, T = 16, key order (mis_autotune picks per graph) */
-    MIS_PATH_TILE = 1,    /* T x T bit tiles: LDS-staged candidate phase + int8 MFMA exclusion */
-    MIS_PATH_CSR = 2      /* scalar CSR path (the plain GPU method) */
+    MIS_PATH_AUTO = 0,    /* hybrid path (mis_autotune picks per graph) */
+    MIS_PATH_TILE = 1,    /* every edge in T x T bit tiles: LDS-staged candidate phase + int8 MFMA
+                             exclusion, on a reordered vertex set */
+    MIS_PATH_CSR = 2,     /* scalar CSR path (the plain GPU method) */
+    MIS_PATH_HYBRID = 3   /* per 16-row block of the input order: the edges to higher-priority
+                             neighbours as 16 x 16 bit tiles on int8 MFMA where the block is dense
+                             (opts.dense_min), as sorted entry lists otherwise; both phases read
+                             alive / in-set bitmaps (Section 3.2, memory footprint trade-offs) */
 };
 
 /* Vertex order used to lay out tiles (results are always in input ids). */
@@ -59,6 +64,19 @@ enum {
     MIS_REORDER_DEGREE = 2,  /* decreasing degree class floor(255 / (1 + deg)), ties by id */
     MIS_REORDER_KEY = 3,     /* decreasing priority key: tile column < row <=> higher key */
     MIS_REORDER_RCM = 4      /* reverse Cuthill-McKee (host), banded meshes */
+};
+
+/* Priority rule of the default keys (Section 3.3; all are 64-bit keys
+ * q << 56 | h << 24 | v with h the top 32 bits of output v+1 of the SplitMix64
+ * stream seeded with opts.seed, v the (graph-local) id; higher key wins). */
+enum {
+    MIS_KEY_DEGREE = 0,   /* q = floor(255 / (1 + deg v)): the degree-aware priority (H2/H3 order) */
+    MIS_KEY_HASH = 1,     /* q = 0: the purely random priority P(v) = hash(v) (H1) */
+    MIS_KEY_EQ1 = 2       /* q = min(255, floor(255 D / (D + 256 deg v - e))) with D = floor(256 nnz / n)
+                             (the average degree, 8 fractional bits) and e the low 8 bits of the
+                             same SplitMix64 output (the perturbation, in 1/256): Eq. 1,
+                             d / (d + deg v - eps), scaled and discretised; q = 255 where the
+                             denominator is not positive.  In a batch, n and nnz are the graph's own */
 };
 
 /* How the rounds are launched (results are identical). */
@@ -92,6 +110,15 @@ typedef struct {
     int32_t launch;           /* MIS_LAUNCH_* */
     int32_t blocks_per_cu;    /* workgroups per compute unit of the persistent round kernels
                                  (0 = default 8, at most 32) */
+    int32_t dense_min;        /* hybrid path: a 16-row block whose higher-priority edges average at
+                                 least this many per nonzero 16 x 16 tile (and fit 64 tiles) is
+                                 stored as bit tiles, every other block as entry lists.
+                                 0 = default (9: a 36-byte tile then costs no more than the
+                                 entries' 4-byte indices), -1 = entry lists only */
+    int32_t key_rule;         /* default priority rule when keys == NULL (MIS_KEY_*; Section 3.3) */
+    int32_t timing;           /* 1 = record HIP events between the build's stages on the build
+                                 stream (read them with mis_build_times) */
+    int32_t pad_;             /* unused */
     uint64_t seed;            /* priority seed (default key rule) */
     const uint64_t* keys;     /* optional DEVICE uint64[n], pairwise distinct priorities
                                  (higher wins); NULL = default key rule, needs n <= 2^24 */
@@ -208,16 +235,19 @@ int mis_solve_batch(mis_graph* batch, uint8_t* in_set, mis_stats* stats, int32_t
                     void* stream);
 
 /*
- * Autotuning of implementation choices that leave the result unchanged (tile size,
- * vertex order, CSR-vs-tile path, grid size of the round kernels).  Measures the
- * degree profile of the graph (or batch: count/offsets as for mis_build_batch,
- * count = 0 for one graph) on the device, rounds it to a bucket, and on the first
- * graph of a bucket builds and solves every candidate -- path CSR or tiles, tile 16
- * or 32, key-sorted or input order, 4/8/16 workgroups per CU -- twice in the
- * workspace, timing the second run of build + solve with HIP events.  The fastest
- * candidate is cached per bucket (process-wide, thread-safe) and written to *out as
- * complete build options (base's seed, keys, validate, poll_rounds and launch are
- * kept).  A nonzero path, tile or blocks_per_cu in `base` fixes that choice.
+ * Autotuning of implementation choices that leave the result unchanged (path,
+ * tile size, vertex order, the hybrid path's dense-block threshold, grid size of the
+ * round kernels).  Measures the degree profile of the graph (or batch: count/offsets
+ * as for mis_build_batch, count = 0 for one graph) on the device, rounds it to a
+ * bucket, and on the first graph of a bucket builds and solves every candidate --
+ * the CSR path; the hybrid path with dense_min -1 (entry lists only), 4, 9 or 16;
+ * the tile path with tile 16 or 32 in key, degree or input order (and RCM order,
+ * at one grid size, when the maximum degree is at most four times the average) --
+ * at 4/8/16 workgroups per CU, twice in the workspace, timing the second run of
+ * build + solve with HIP events.  The fastest candidate is cached per bucket
+ * (process-wide, thread-safe) and written to *out as complete build options (base's
+ * seed, keys, validate, poll_rounds and launch are kept).  A nonzero path, tile,
+ * blocks_per_cu or dense_min in `base` fixes that choice.
  *   workspace : DEVICE, 256-byte aligned, at least mis_autotune_bytes bytes; its
  *               contents are scratch.  from_cache (HOST, optional): 1 if no trial ran.
  * Synchronises `stream`.  Every candidate computes the same set; only time differs.

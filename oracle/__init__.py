@@ -51,6 +51,8 @@ def _load():
     lib.orc_key.restype = u64
     lib.orc_keys.argtypes = [i64, p, u64, p]
     lib.orc_keys.restype = i32
+    lib.orc_keys_rule.argtypes = [i64, p, u64, i32, p]
+    lib.orc_keys_rule.restype = i32
     lib.orc_validate.argtypes = [i64, p, p]
     lib.orc_validate.restype = i32
     lib.orc_roundsync.argtypes = [i64, p, p, p, i64, p, p, i64]
@@ -95,6 +97,20 @@ def keys(row_ptr, seed: int) -> np.ndarray:
     out = np.zeros(max(n, 1), dtype=np.uint64)
     if _load().orc_keys(n, rp.ctypes.data, seed & (2**64 - 1), out.ctypes.data) != 0:
         raise ValueError("default key rule needs n <= 2^24")
+    return out[:n]
+
+
+KEY_RULES = {"degree": 0, "hash": 1, "eq1": 2}
+
+
+def keys_rule(row_ptr, seed: int, rule: str) -> np.ndarray:
+    """Keys of one graph under a priority heuristic of Section 3.3 (see orc_keys_rule)."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    n = rp.size - 1
+    out = np.zeros(max(n, 1), dtype=np.uint64)
+    rc = _load().orc_keys_rule(n, rp.ctypes.data, seed & (2**64 - 1), KEY_RULES[rule], out.ctypes.data)
+    if rc != 0:
+        raise ValueError("key rule needs n <= 2^24 and a known rule")
     return out[:n]
 
 

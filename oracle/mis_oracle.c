@@ -63,6 +63,46 @@ int orc_keys(int64_t n, const int64_t* row_ptr, uint64_t seed, uint64_t* keys) {
     return 0;
 }
 
+/* The three priority heuristics of Section 3.3, as key rules (rule 0 is orc_keys):
+ *   0  degree-aware: q = floor(255 / (1 + deg))
+ *   1  H1, purely random priority P(v) = hash(v): q = 0, the key is the hash and id
+ *   2  Eq. 1, P(v) = dbar / (dbar + deg(v) - eps(v)), scaled to 255 and discretised.
+ *      Reading (the paper gives no constants): dbar is taken with 8 fractional
+ *      bits, D = floor(256 nnz / n); eps = e / 256 with e the low 8 bits of the same
+ *      SplitMix64 output whose top 32 bits are the hash; then
+ *      q = floor(255 * D / (D + 256 deg - e)), at most 255, and 255 when that
+ *      denominator is not positive (an isolated vertex: P >= 1).
+ * In every rule key(v) = q << 56 | hash << 24 | v, as for rule 0.  The graph here
+ * is one graph (a batch applies the rule per graph with its own n and nnz).
+ * Returns -1 if n > 2^24, -2 for an unknown rule. */
+int orc_keys_rule(int64_t n, const int64_t* row_ptr, uint64_t seed, int rule, uint64_t* keys) {
+    if (n > (1ll << 24)) return -1;
+    if (rule < 0 || rule > 2) return -2;
+    const int64_t nnz = n > 0 ? row_ptr[n] - row_ptr[0] : 0;
+    const int64_t D = n > 0 ? (256 * nnz) / n : 0;
+    for (int64_t v = 0; v < n; ++v) {
+        const int64_t deg = row_ptr[v + 1] - row_ptr[v];
+        const uint64_t z = orc_splitmix(seed, (uint64_t)v + 1);
+        uint64_t q;
+        if (rule == 0) {
+            q = orc_q(deg);
+        } else if (rule == 1) {
+            q = 0;
+        } else {
+            const int64_t e = (int64_t)(z & 0xFF);
+            const int64_t den = D + 256 * deg - e;
+            if (den <= 0) {
+                q = 255;
+            } else {
+                const int64_t x = (255 * D) / den;
+                q = (uint64_t)(x > 255 ? 255 : x);
+            }
+        }
+        keys[v] = (q << 56) | ((z >> 32) << 24) | (uint64_t)v;
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------ validation */
 
 /* 0 ok; -5 index out of range / bad row_ptr; -3 self-loop; -4 duplicate; -2 asymmetric.

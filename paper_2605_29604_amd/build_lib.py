@@ -16,7 +16,8 @@ LIB = os.path.join(HERE, "libtcmis.so")
 ARCH = os.environ.get("TCMIS_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["radix.hip", "build.hip", "solve_csr.hip", "solve_tile.hip", "capi.hip", "tune.hip", "session.hip", "rcm.cpp"]
+SOURCES = ["radix.hip", "build.hip", "hyb.hip", "solve_csr.hip", "solve_tile.hip", "capi.hip", "tune.hip", "session.hip",
+           "rcm.cpp"]
 
 FLAGS = [
     "-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",

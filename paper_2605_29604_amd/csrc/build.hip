@@ -28,16 +28,6 @@ namespace {
 
 enum : uint32_t { kErrRange = 1, kErrLoop = 2, kErrDup = 4, kErrAsym = 8, kErrTie = 16, kErrCross = 32 };
 
-#define GRID_STRIDE(i, count) \
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (count); i += (int64_t)gridDim.x * blockDim.x)
-
-// SplitMix64 (Steele, Lea, Flood 2014): output i of the stream seeded with s
-__device__ inline uint64_t splitmix_at(uint64_t s, uint64_t i) {
-    uint64_t z = s + i * 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
 
 __device__ inline int64_t row_of(const int64_t* rp, int64_t n, int64_t e) {
     int64_t lo = 0, hi = n;
@@ -84,22 +74,48 @@ __global__ void k_validate_edges(const int64_t* rp, const int32_t* ci, int64_t n
     }
 }
 
-// Default priority key (Eq. 1, discretised): q(deg) << 56 | hash << 24 | v with
-// q(d) = floor(255 / (1 + d)) (lower degree wins) and hash = top 32 bits of output
-// v+1 of the SplitMix64 stream seeded with `seed` (the random perturbation).
-// In a batch the id in the key is graph-local (v - goff[g]).
+// Default priority keys (Section 3.3): q << 56 | hash << 24 | v with hash = top 32
+// bits of output v+1 of the SplitMix64 stream seeded with `seed` (the random
+// perturbation) and q by the rule:
+//   MIS_KEY_DEGREE  floor(255 / (1 + deg)) (lower degree wins)
+//   MIS_KEY_HASH    0 (purely random priority, H1)
+//   MIS_KEY_EQ1     Eq. 1, d / (d + deg - eps), scaled to 255 and discretised in
+//                   integers: D = floor(256 nnz / n) is the average degree with 8
+//                   fractional bits, e = the low 8 bits of the same SplitMix64
+//                   output is eps in 1/256, q = min(255, floor(255 D / (D + 256 deg -
+//                   e))), 255 where that denominator is not positive
+// In a batch the id in the key is graph-local (v - goff[g]) and n, nnz are graph g's.
 // With `sk` the kernel also writes the priority order's sort keys (k_order_keys'
-// layout: ~key at position n-1-v), saving that pass a read of the keys.
-__global__ void k_keys(const int64_t* rp, int64_t n, uint64_t seed, const int64_t* goff, int64_t count, uint64_t* key,
-                       uint64_t* sk) {
+// layout: ~key at position n-1-v), saving that pass a read of the keys.  With `q8`
+// it also writes q alone, one byte per vertex (the hybrid path's orientation
+// compares classes from this table and rebuilds the hash in registers on a tie).
+__device__ inline uint64_t key_class(int rule, int64_t deg, int64_t gn, int64_t gnnz, uint64_t z) {
+    if (rule == MIS_KEY_HASH) return 0;
+    if (rule == MIS_KEY_DEGREE) return (uint64_t)(255 / (1 + deg));
+    const int64_t D = gn > 0 ? (256 * gnnz) / gn : 0;
+    const int64_t den = D + 256 * deg - (int64_t)(z & 0xFFu);
+    if (den <= 0) return 255;
+    const int64_t q = (255 * D) / den;
+    return (uint64_t)(q < 255 ? q : 255);
+}
+
+__global__ void k_keys(const int64_t* rp, int64_t n, uint64_t seed, const int64_t* goff, int64_t count, int rule,
+                       uint64_t* key, uint64_t* sk, uint8_t* q8) {
     GRID_STRIDE(v, n) {
         const int64_t deg = rp[v + 1] - rp[v];
-        const uint64_t q = (uint64_t)(255 / (1 + deg));
-        const int64_t lv = goff ? v - goff[graph_of(goff, count, v)] : v;
-        const uint64_t h = splitmix_at(seed, (uint64_t)lv + 1) >> 32;
-        const uint64_t k = (q << 56) | (h << 24) | (uint64_t)lv;
+        int64_t lv = v, gn = n, gnnz = rp[n] - rp[0];
+        if (goff) {
+            const int64_t g = graph_of(goff, count, v);
+            lv = v - goff[g];
+            gn = goff[g + 1] - goff[g];
+            gnnz = rp[goff[g + 1]] - rp[goff[g]];
+        }
+        const uint64_t z = splitmix_at(seed, (uint64_t)lv + 1);
+        const uint64_t q = key_class(rule, deg, gn, gnnz, z);
+        const uint64_t k = (q << 56) | ((z >> 32) << 24) | (uint64_t)lv;
         key[v] = k;
         if (sk) sk[n - 1 - v] = ~k;
+        if (q8) q8[v] = (uint8_t)q;
     }
 }
 
@@ -562,6 +578,7 @@ int bits_for(int64_t x) {   // bits to hold 0..x, so x itself is never all ones
 }  // namespace
 
 int host_rcm(const int64_t* rp, const int32_t* ci, int64_t n, std::vector<int32_t>& new_id);
+int64_t hyb_blocks(int64_t nnz);
 
 size_t layout(mis_graph* g, char* base) {
     size_t off = 0;
@@ -583,6 +600,43 @@ size_t layout(mis_graph* g, char* base) {
         take(&g->g_in, (size_t)g->count * 8);
     }
     take(&g->scan_tmp, (size_t)scan_scratch_elems(std::max(n, nnz) + 1) * 8);
+    if (g->path == MIS_PATH_HYBRID) {
+        g->nI = ceil_div(n, 16);
+        const int64_t nI = g->nI, nw = ceil_div(n, 64) * 2 + 2;   // bitmap words (whole waves)
+        take(&g->q8, (size_t)n);
+        take(&g->hbrow, (size_t)(hyb_blocks(nnz) + 2) * 4);
+        take(&g->hbase, (size_t)n * 4);
+        take(&g->hoff, (size_t)n * 4);
+        take(&g->hcol, (size_t)nnz * 4);
+        take(&g->hcnt, (size_t)n * 4);
+        take(&g->hflag, (size_t)n * 8);
+        take(&g->hpos, (size_t)(n + 1) * 8);
+        take(&g->hl1[0], (size_t)n * 4);
+        take(&g->hl1[1], (size_t)n * 4);
+        take(&g->s1, (size_t)nw * 4);
+        take(&g->a1, (size_t)nw * 4);
+        if (g->dense_min > 0) {
+            const int64_t tcap = nnz / 2 + 1;   // a dense tile holds at least one oriented entry
+            take(&g->dflag, (size_t)nI * 4);
+            take(&g->dpos, (size_t)(nI + 1) * 4);
+            take(&g->dtcnt, (size_t)(nI + 1) * 4);
+            take(&g->dslot, (size_t)nI * 4);
+            take(&g->drb, (size_t)nI * 4);
+            take(&g->dptr, (size_t)(nI + 1) * 4);
+            take(&g->dcol, (size_t)tcap * 4);
+            take(&g->dbits, (size_t)tcap * 32);
+        }
+        // per-solve round state
+        take(&g->hA, (size_t)nw * 4);
+        take(&g->hS, (size_t)nw * 4);
+        for (int b = 0; b < 2; ++b) {
+            take(&g->hact[b][0], (size_t)n * 4);
+            take(&g->hact[b][1], (size_t)n * 4);
+            take(&g->hact[b][2], (size_t)(g->dense_min > 0 ? nI : 0) * 4);
+        }
+        if (g->count > 0) take(&g->dround, (size_t)n * 4);
+        return off;
+    }
     if (g->path == MIS_PATH_CSR) {
         take(&g->light, (size_t)n * 4);
         take(&g->heavy, (size_t)n * 4);
@@ -673,7 +727,8 @@ int build_keys(mis_graph* g, const mis_build_opts* o, hipStream_t s) {
     } else {
         // the key order of one graph with default keys: the sort keys come with the keys
         uint64_t* sk = g->path == MIS_PATH_TILE && default_keys_in_order(g) ? g->sk : nullptr;
-        LAUNCH(k_keys, g->n, g->row_ptr, g->n, o->seed, g->goff, (int64_t)g->count, g->key, sk);
+        LAUNCH(k_keys, g->n, g->row_ptr, g->n, o->seed, g->goff, (int64_t)g->count, o->key_rule, g->key, sk,
+               g->path == MIS_PATH_HYBRID ? g->q8 : nullptr);
     }
     return MIS_OK;
 }

@@ -24,6 +24,11 @@ int tile_enqueue_phase(mis_graph* g, int phase, int r, hipStream_t s);
 int tile_output(mis_graph* g, uint8_t* in_set, bool if_done, hipStream_t s);
 int tile_enqueue_rounds(mis_graph* g, int k, hipStream_t s);
 int csr_enqueue_rounds(mis_graph* g, int k, hipStream_t s);
+int build_hybrid(mis_graph* g, hipStream_t s);
+int hyb_init(mis_graph* g, hipStream_t s);
+int hyb_enqueue_phase(mis_graph* g, int phase, int r, hipStream_t s);
+int hyb_output(mis_graph* g, uint8_t* in_set, bool if_done, hipStream_t s);
+int hyb_enqueue_rounds(mis_graph* g, int k, hipStream_t s);
 
 namespace {
 thread_local std::string g_last_error;
@@ -126,7 +131,10 @@ int resolve(const mis_csr* csr, const mis_build_opts* opts, mis_build_opts* o, i
     if (!csr->row_ptr) return fail(MIS_EINVAL, "row_ptr is null");
     if (csr->nnz > 0 && !csr->col_idx) return fail(MIS_EINVAL, "col_idx is null");
     if (opts) *o = *opts; else mis_default_opts(o);
-    if (o->path < MIS_PATH_AUTO || o->path > MIS_PATH_CSR) return fail(MIS_EINVAL, "bad path");
+    if (o->path < MIS_PATH_AUTO || o->path > MIS_PATH_HYBRID) return fail(MIS_EINVAL, "bad path");
+    if (o->dense_min < -1) return fail(MIS_EINVAL, "dense_min must be >= -1");
+    if (o->key_rule < MIS_KEY_DEGREE || o->key_rule > MIS_KEY_EQ1) return fail(MIS_EINVAL, "bad key_rule");
+    if (o->timing < 0 || o->timing > 1) return fail(MIS_EINVAL, "timing must be 0 or 1");
     if (o->tile != 0 && o->tile != 16 && o->tile != 32) return fail(MIS_EINVAL, "tile must be 0, 16 or 32");
     if (o->reorder < MIS_REORDER_AUTO || o->reorder > MIS_REORDER_RCM) return fail(MIS_EINVAL, "bad reorder");
     if (o->orient < -1 || o->orient > 1) return fail(MIS_EINVAL, "orient must be -1, 0 or 1");
@@ -145,8 +153,17 @@ int resolve(const mis_csr* csr, const mis_build_opts* opts, mis_build_opts* o, i
     } else if (!o->keys && csr->n > (1ll << 24)) {
         return fail(MIS_EINVAL, "the default key rule needs n <= 2^24; pass keys");
     }
-    if (o->path == MIS_PATH_AUTO) o->path = MIS_PATH_TILE;
-    if (o->path == MIS_PATH_TILE) {
+    if (o->path == MIS_PATH_AUTO) o->path = MIS_PATH_HYBRID;
+    if (o->path == MIS_PATH_HYBRID) {
+        if (o->tile != 0 && o->tile != 16) return fail(MIS_EINVAL, "the hybrid path uses 16 x 16 tiles");
+        if (o->reorder != MIS_REORDER_AUTO && o->reorder != MIS_REORDER_NONE)
+            return fail(MIS_EINVAL, "the hybrid path keeps the input order");
+        if (o->orient == 0) return fail(MIS_EINVAL, "the hybrid path stores higher-priority edges only");
+        o->tile = 16;
+        o->reorder = MIS_REORDER_NONE;
+        o->orient = 1;
+        if (o->dense_min == 0) o->dense_min = kDenseMinDefault;
+    } else if (o->path == MIS_PATH_TILE) {
         if (o->tile == 0) o->tile = 16;
         if (o->reorder == MIS_REORDER_AUTO) o->reorder = MIS_REORDER_KEY;
         if (o->orient < 0) o->orient = 1;
@@ -171,12 +188,16 @@ void configure(mis_graph* g, const mis_csr* csr, const mis_build_opts& o) {
     g->poll_rounds = o.poll_rounds;
     g->launch = o.launch;
     g->user_keys = o.keys != nullptr;
+    g->seed = o.seed;
+    g->dense_min = o.path == MIS_PATH_HYBRID && o.dense_min > 0 ? o.dense_min : 0;
 }
 
-// kernels per round: tile path candidate / exclusion / finalize, CSR path candidate / exclusion
+// kernels per round: tile path candidate / exclusion / finalize, CSR and hybrid paths
+// candidate / exclusion
 int phases(const mis_graph* g) { return g->path == MIS_PATH_TILE ? 3 : 2; }
 
 int enqueue_phase(mis_graph* g, int phase, int r, hipStream_t s) {
+    if (g->path == MIS_PATH_HYBRID) return hyb_enqueue_phase(g, phase, r, s);
     return g->path == MIS_PATH_TILE ? tile_enqueue_phase(g, phase, r, s) : csr_enqueue_phase(g, phase, r, s);
 }
 
@@ -191,7 +212,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_stats(const int64_t* goff, con
     int32_t mx = 0;
     int64_t sum = 0;
     for (int64_t v = goff[g] + threadIdx.x; v < goff[g + 1]; v += kBlock) {
-        const int32_t r = new_id ? dround[new_id[v]] : (int32_t)(st[v] >> 2);
+        const int32_t r = new_id ? dround[new_id[v]] : st ? (int32_t)(st[v] >> 2) : dround[v];
         mx = max(mx, r);
         sum += in_set[v];
     }
@@ -262,6 +283,13 @@ int64_t unit_bytes(const mis_graph* g, int k) {
         static const int64_t b[kUnits] = {12, 28, 8, 24, 0, 0};
         return b[k];
     }
+    if (g->path == MIS_PATH_HYBRID) {
+        // entries read (4-byte index + the bitmap word it selects), rows examined (list
+        // slot, row start, entry count), tiles multiplied (bitmap + column block),
+        // dense blocks examined (list slot, block slot, tile range, its two bitmap words)
+        static const int64_t b[kUnits] = {8, 16, 8, 16, 36, 24};
+        return b[k];
+    }
     // tile path: 4-byte words, bytes, 4-byte words, bitmaps multiplied, row-blocks
     // finalized (alive, blocked, hit read and written), chunk entries written
     const int64_t S = (int64_t)g->tile * g->tile / 8;
@@ -274,6 +302,7 @@ int64_t unit_bytes(const mis_graph* g, int k) {
 int solve_begin(mis_graph* g, hipStream_t s) {
     hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(256), 0, s, g->ctrl, g->stripes, g->n);
     TC_HIP(hipGetLastError());
+    if (g->path == MIS_PATH_HYBRID) return hyb_init(g, s);
     return g->path == MIS_PATH_TILE ? tile_init(g, s) : csr_init(g, s);
 }
 
@@ -295,8 +324,10 @@ int launch_cooperative(const void* kernel, mis_graph* g, void* args, int k, hipS
 }
 
 int solve_rounds(mis_graph* g, int64_t k, bool allow_graph, hipStream_t s) {
-    if (g->launch == MIS_LAUNCH_PERSISTENT)
+    if (g->launch == MIS_LAUNCH_PERSISTENT) {
+        if (g->path == MIS_PATH_HYBRID) return hyb_enqueue_rounds(g, (int)k, s);
         return g->path == MIS_PATH_TILE ? tile_enqueue_rounds(g, (int)k, s) : csr_enqueue_rounds(g, (int)k, s);
+    }
     // auto: a handle solved once gains nothing from a capture, which costs more than
     // the launches it replaces; capture when it is solved again
     const bool graph = g->launch == MIS_LAUNCH_GRAPH || (g->launch == MIS_LAUNCH_AUTO && g->solves > 1);
@@ -308,6 +339,7 @@ int solve_rounds(mis_graph* g, int64_t k, bool allow_graph, hipStream_t s) {
 }
 
 int solve_output(mis_graph* g, uint8_t* in_set, hipStream_t s, bool if_done) {
+    if (g->path == MIS_PATH_HYBRID) return hyb_output(g, in_set, if_done, s);
     return g->path == MIS_PATH_TILE ? tile_output(g, in_set, if_done, s) : csr_output(g, in_set, if_done, s);
 }
 
@@ -405,6 +437,7 @@ int mis_build_batch(const mis_csr* csr, int32_t count, const int64_t* offsets, c
     if (rc == MIS_OK) rc = build_keys(g, &o, s);
     if (rc == MIS_OK) {
         if (g->path == MIS_PATH_CSR) rc = build_csr_lists(g, s);
+        else if (g->path == MIS_PATH_HYBRID) rc = build_hybrid(g, s);
         else {
             rc = build_order(g, s);
             if (rc == MIS_OK) rc = build_tiles(g, s);
@@ -509,6 +542,7 @@ int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, mis_stats* st, 
         sg->ctrl->round = 0;
         sg->ctrl->n_in = 0;
         sg->meta->ntiles = 0;
+        sg->meta->n_dtiles = 0;
     }
     if (st) {
         st->rounds = sg->ctrl->round;
@@ -517,7 +551,8 @@ int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, mis_stats* st, 
         st->reorder = g->reorder;
         st->orient = g->orient;
         st->n_in = sg->ctrl->n_in;
-        const int64_t nt = g->path == MIS_PATH_TILE ? sg->meta->ntiles : 0;
+        const int64_t nt = g->path == MIS_PATH_TILE ? sg->meta->ntiles
+                           : g->path == MIS_PATH_HYBRID ? sg->meta->n_dtiles : 0;
         st->tiles = nt;
         st->tile_bytes = nt * ((int64_t)g->tile * g->tile / 8 + 4);
         int64_t ab = 0;
@@ -542,7 +577,8 @@ int mis_solve_batch(mis_graph* g, uint8_t* in_set, mis_stats* stats, int32_t* gr
     hipStream_t s = (hipStream_t)stream;
     if (g->n > 0) {
         hipLaunchKernelGGL(k_batch_stats, dim3((unsigned)g->count), dim3(kBlock), 0, s, g->goff, in_set,
-                           g->path == MIS_PATH_TILE ? g->new_id : nullptr, g->dround, g->st, g->g_rounds, g->g_in);
+                           g->path == MIS_PATH_TILE ? g->new_id : nullptr, g->dround,
+                           g->path == MIS_PATH_CSR ? g->st : nullptr, g->g_rounds, g->g_in);
         TC_HIP(hipGetLastError());
     } else {
         TC_HIP(hipMemsetAsync(g->g_rounds, 0, (size_t)g->count * 4, s));

@@ -44,6 +44,17 @@ inline unsigned stream_grid(int64_t work, int per_thread = 1) {
     return (unsigned)blocks;
 }
 
+#define GRID_STRIDE(i, count) \
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (count); i += (int64_t)gridDim.x * blockDim.x)
+
+// SplitMix64 (Steele, Lea, Flood 2014): output i of the stream seeded with s
+__device__ inline uint64_t splitmix_at(uint64_t s, uint64_t i) {
+    uint64_t z = s + i * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
 // ---- wave primitives -------------------------------------------------------
 __device__ inline int lane_id() { return (int)__lane_id(); }
 __device__ inline uint64_t ballot(bool p) { return __ballot(p); }

@@ -13,6 +13,7 @@ constexpr int kTraceCap = 4096;     // device trace ring (rounds); the host drai
 constexpr int kUnits = 6;           // work-unit counters per round (TraceRec::u)
 constexpr int kStripes = 32;        // round counters are spread over this many cache lines
 constexpr int kStripeWords = 16;    // int64 words per stripe (one 128-byte line)
+constexpr int kDenseMinDefault = 9; // hybrid: a 36-byte 16x16 tile costs no more than 9 entry indices
 
 // Device control block of the round loop.  Round r's kernels take r as an
 // argument and count into the round-parity half of the counter stripes (each
@@ -29,7 +30,8 @@ struct Ctrl {
     int32_t pad0;
     int64_t alive;          // undecided vertices after `round` rounds
     int64_t n_in;           // vertices in the set so far
-    int64_t n_act[2][2];    // active work items per list buffer (CSR: [light, heavy]; tile: [chunks, row-blocks])
+    int64_t n_act[2][4];    // active work items per list buffer (CSR: [light, heavy]; tile: [chunks,
+                            // row-blocks]; hybrid: [light rows, heavy rows, dense row-blocks])
     unsigned long long bar; // grid-barrier arrivals of persistent launches (only grows)
 };
 // Counter words of a stripe: |C|, removed neighbours, work units u0..u5.
@@ -63,6 +65,11 @@ struct Meta {
     int64_t nchunks;        // tile path: chunks of the round-1 list
     int32_t n_light;        // CSR path: vertices with degree <= kLightDeg
     int32_t pad;
+    // hybrid path
+    int64_t n_c1;           // round-1 candidates (vertices without a higher-priority neighbour)
+    int64_t n_hl[2];        // round-1 entry-list rows: [light, heavy]
+    int32_t n_dense;        // dense row-blocks (bit tiles)
+    int32_t n_dtiles;       // their tiles
 };
 
 }  // namespace tcmis
@@ -159,7 +166,33 @@ struct mis_graph {
     RowState* rs = nullptr;           // [nI] undecided rows and this round's blocked rows
     uint32_t* hit = nullptr;          // [nI] rows with a candidate neighbour (this round)
     uint32_t* inmask = nullptr;       // [nI] rows in the set
-    int32_t* dround = nullptr;        // [nI*tile] round in which each row was decided
+    int32_t* dround = nullptr;        // [nI*tile] round in which each row was decided (hybrid: [n])
+
+    // ---- hybrid path (input order; row-block I = vertices 16I .. 16I+15)
+    int dense_min = 0;                // entries per tile from which a row-block takes bit tiles (0: never)
+    uint64_t seed = 1;                // default key rule's seed
+    uint8_t* q8 = nullptr;            // [n] degree class floor(255 / (1 + deg)) of every vertex
+    int32_t* hbrow = nullptr;         // [nnz/kHybE + 2] first row of each orientation workgroup
+    int32_t* hbase = nullptr;         // [n] orientation scratch (workgroups whose rows exceed LDS)
+    int32_t* hoff = nullptr;          // [n] orientation scratch
+    int32_t* hcol = nullptr;          // [nnz] oriented entries: row v's are hcol[rp[v] .. rp[v] + hcnt[v])
+    int32_t* hcnt = nullptr;          // [n] higher-priority neighbours of each vertex
+    int64_t* hflag = nullptr;         // [n] list class (light 1, heavy 1 << 32, else 0)
+    int64_t* hpos = nullptr;          // [n+1] its exclusive scan: list positions (light low, heavy high half)
+    int32_t* hl1[2] = {nullptr, nullptr};   // [n] round-1 light / heavy rows
+    uint32_t* s1 = nullptr;           // [nw] round-1 candidates (bitmap)
+    uint32_t* a1 = nullptr;           // [nw] undecided after them (bitmap)
+    int32_t* dflag = nullptr;         // [nI] dense row-block flags
+    int32_t* dpos = nullptr;          // [nI+1] their scan: list slot of each dense row-block
+    int32_t* dtcnt = nullptr;         // [nI+1] tiles per dense row-block -> first tile
+    int32_t* dslot = nullptr;         // [nI] list slot of each dense row-block (-1: entry lists)
+    int32_t* drb = nullptr;           // [nI] dense row-blocks
+    int32_t* dptr = nullptr;          // [nI+1] tile range of each dense row-block (by list position)
+    int32_t* dcol = nullptr;          // [tile cap] column block of each dense tile
+    uint32_t* dbits = nullptr;        // [tile cap * 8] 16x16 bitmaps (word w: rows 2w, 2w+1)
+    uint32_t* hA = nullptr;           // [nw] undecided vertices (bitmap)
+    uint32_t* hS = nullptr;           // [nw] vertices in the set (bitmap)
+    int32_t* hact[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};   // next rounds' lists
 };
 
 namespace tcmis {

@@ -86,10 +86,7 @@ __device__ inline void close_round(Ctrl* ctrl, int64_t* stripes, TraceRec* trace
 __device__ inline void open_round(Ctrl* ctrl, int64_t* stripes, TraceRec* trace, int r) {
     if (blockIdx.x == 0 && threadIdx.x < kWave) {
         close_round(ctrl, stripes, trace, r - 1);
-        if (threadIdx.x == 0) {
-            ctrl->n_act[r & 1][0] = 0;
-            ctrl->n_act[r & 1][1] = 0;
-        }
+        if (threadIdx.x < 4) ctrl->n_act[r & 1][threadIdx.x] = 0;
     }
 }
 

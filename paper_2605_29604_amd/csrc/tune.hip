@@ -1,5 +1,6 @@
-// Autotuner: picks the path (CSR lists or bit tiles), the tile size, the vertex order
-// and the persistent grid size of the round kernels for a graph's degree profile.
+// Autotuner: picks the path (CSR lists, bit tiles, or the hybrid of both), the tile
+// size, the vertex order, the hybrid's dense-block threshold and the grid size of
+// the round kernels for a graph's degree profile.
 //
 // The profile (vertex count, average degree, maximum over average degree, share of
 // isolated vertices, graphs in the batch) is measured on the device and rounded to a
@@ -41,23 +42,34 @@ __global__ void k_degree_profile(const int64_t* rp, int64_t n, unsigned long lon
 }
 
 struct Candidate {
-    int path, tile, reorder, orient, blocks_per_cu;
+    int path, tile, reorder, orient, blocks_per_cu, dense_min;
 };
 
-// Trial configurations allowed by the caller's options: a fixed path, tile size or
-// grid size in `base` restricts the search to it.
-std::vector<Candidate> candidates(const mis_build_opts& base) {
+// Trial configurations allowed by the caller's options: a fixed path, tile size,
+// grid size or dense threshold in `base` restricts the search to it.  `mesh`: the
+// degree profile is flat (maximum at most four times the average), where a
+// bandwidth-reducing order (RCM, computed on the host) can pay for itself; it is
+// tried at one grid size.
+std::vector<Candidate> candidates(const mis_build_opts& base, bool mesh) {
     std::vector<Candidate> c;
     std::vector<int> grids = {4, 8, 16};
     if (base.blocks_per_cu) grids = {base.blocks_per_cu};
     std::vector<int> tiles = {16, 32};
     if (base.tile) tiles = {base.tile};
+    std::vector<int> dense = {-1, 4, 9, 16};
+    if (base.dense_min) dense = {base.dense_min};
+    const bool any = base.path == MIS_PATH_AUTO;
     for (int b : grids) {
-        if (base.path != MIS_PATH_TILE) c.push_back({MIS_PATH_CSR, 0, MIS_REORDER_NONE, 0, b});
-        if (base.path != MIS_PATH_CSR)
+        if (any || base.path == MIS_PATH_CSR) c.push_back({MIS_PATH_CSR, 0, MIS_REORDER_NONE, 0, b, 0});
+        if (any || base.path == MIS_PATH_HYBRID)
+            if (!base.tile || base.tile == 16)
+                for (int d : dense) c.push_back({MIS_PATH_HYBRID, 16, MIS_REORDER_NONE, 1, b, d});
+        if (any || base.path == MIS_PATH_TILE)
             for (int t : tiles) {
-                c.push_back({MIS_PATH_TILE, t, MIS_REORDER_KEY, 1, b});
-                c.push_back({MIS_PATH_TILE, t, MIS_REORDER_NONE, 1, b});
+                c.push_back({MIS_PATH_TILE, t, MIS_REORDER_KEY, 1, b, 0});
+                c.push_back({MIS_PATH_TILE, t, MIS_REORDER_NONE, 1, b, 0});
+                c.push_back({MIS_PATH_TILE, t, MIS_REORDER_DEGREE, 1, b, 0});
+                if (mesh && b == grids[grids.size() / 2]) c.push_back({MIS_PATH_TILE, t, MIS_REORDER_RCM, 1, b, 0});
             }
     }
     return c;
@@ -70,17 +82,18 @@ mis_build_opts apply(const mis_build_opts& base, const Candidate& c) {
     o.reorder = c.reorder;
     o.orient = c.orient;
     o.blocks_per_cu = c.blocks_per_cu;
+    o.dense_min = c.dense_min;
     return o;
 }
 
-using Bucket = std::tuple<int, int, int, int, int, int, int, int>;
+using Bucket = std::tuple<int, int, int, int, int, int, int, int, int>;
 std::mutex g_mu;
 std::map<Bucket, Candidate> g_cache;
 
 // largest build footprint over the candidates (or an error)
 int trial_bytes(const mis_csr* csr, int32_t count, const int64_t* offsets, const mis_build_opts& b, size_t* most) {
     *most = 0;
-    for (const Candidate& c : candidates(b)) {
+    for (const Candidate& c : candidates(b, true)) {
         const mis_build_opts o = apply(b, c);
         size_t need = 0;
         TC_CHECK(mis_build_batch_bytes(csr, count, offsets, &o, &need));
@@ -141,7 +154,8 @@ int mis_autotune(const mis_csr* csr, int32_t count, const int64_t* offsets, cons
     const int per_graph = count > 0 ? count : 1;
     const Bucket key{(int)std::ceil(std::log2(n)), (int)std::lround(2.0 * std::log2(avg + 1.0)),
                      (int)std::lround(std::log2(skew + 1.0)), (int)(8.0 * (double)h[1] / n),
-                     (int)std::ceil(std::log2((double)per_graph)), b.path, b.tile, b.blocks_per_cu};
+                     (int)std::ceil(std::log2((double)per_graph)), b.path, b.tile, b.blocks_per_cu, b.dense_min};
+    const bool mesh = skew <= 4.0 && count == 0;
     Candidate best{};
     bool cached = false, found = false;
     {
@@ -158,7 +172,7 @@ int mis_autotune(const mis_csr* csr, int32_t count, const int64_t* offsets, cons
             return MIS_EHIP;
         }
         float best_ms = 0.f;
-        for (const Candidate& c : candidates(b)) {
+        for (const Candidate& c : candidates(b, mesh)) {
             mis_build_opts o = apply(b, c);
             o.validate = 0;
             float ms = 0.f;

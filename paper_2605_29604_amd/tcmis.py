@@ -17,10 +17,10 @@ LIB_PATH = os.path.join(_HERE, "libtcmis.so")
 
 MIS_OK, MIS_EINVAL, MIS_ENOTSYM, MIS_ESELFLOOP, MIS_EDUP, MIS_ERANGE = 0, -1, -2, -3, -4, -5
 MIS_ENOMEM, MIS_EBUSY, MIS_EHIP, MIS_EINTERNAL = -6, -7, -8, -9
-PATH_AUTO, PATH_TILE, PATH_CSR = 0, 1, 2
+PATH_AUTO, PATH_TILE, PATH_CSR, PATH_HYBRID = 0, 1, 2, 3
 REORDER_AUTO, REORDER_NONE, REORDER_DEGREE, REORDER_KEY, REORDER_RCM = 0, 1, 2, 3, 4
 
-PATHS = {"auto": PATH_AUTO, "tile": PATH_TILE, "csr": PATH_CSR}
+PATHS = {"auto": PATH_AUTO, "tile": PATH_TILE, "csr": PATH_CSR, "hybrid": PATH_HYBRID}
 LAUNCHES = {"auto": 0, "direct": 1, "graph": 2, "persistent": 3}
 REORDERS = {"auto": REORDER_AUTO, "none": REORDER_NONE, "degree": REORDER_DEGREE,
             "key": REORDER_KEY, "rcm": REORDER_RCM}
@@ -42,6 +42,8 @@ class MisBuildOpts(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("tile", ctypes.c_int32), ("reorder", ctypes.c_int32),
                 ("orient", ctypes.c_int32), ("validate", ctypes.c_int32), ("poll_rounds", ctypes.c_int32),
                 ("launch", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("dense_min", ctypes.c_int32), ("key_rule", ctypes.c_int32), ("timing", ctypes.c_int32),
+                ("pad_", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("keys", ctypes.c_void_p)]
 
 
@@ -182,7 +184,7 @@ class MisGraph:
 
 
 def _opts(path="auto", tile=0, reorder="auto", orient=-1, validate=False, seed=1, keys=None, poll_rounds=0,
-          launch="auto", blocks_per_cu=0):
+          launch="auto", blocks_per_cu=0, dense_min=0):
     o = MisBuildOpts()
     lib().mis_default_opts(ctypes.byref(o))
     o.path = PATHS[path] if isinstance(path, str) else int(path)
@@ -193,6 +195,7 @@ def _opts(path="auto", tile=0, reorder="auto", orient=-1, validate=False, seed=1
     o.poll_rounds = int(poll_rounds)
     o.launch = LAUNCHES[launch] if isinstance(launch, str) else int(launch)
     o.blocks_per_cu = int(blocks_per_cu)
+    o.dense_min = int(dense_min)
     o.seed = int(seed) & (2**64 - 1)
     o.keys = _ptr(keys)
     return o
@@ -209,7 +212,7 @@ def mis_build_bytes(n: int, nnz: int, **opts) -> int:
 
 def mis_build_tiles(row_ptr, col_idx, path="auto", tile=0, reorder="auto", orient=-1, validate=False,
                     seed=1, keys=None, poll_rounds=0, launch="auto", blocks_per_cu=0, workspace=None,
-                    stream=None) -> MisGraph:
+                    stream=None, dense_min=0) -> MisGraph:
     """row_ptr: cuda int64[n+1]; col_idx: cuda int32[nnz]; keys: optional cuda uint64[n] (as int64).
 
     The device workspace comes from torch's allocator unless one is passed (a cuda
@@ -220,7 +223,7 @@ def mis_build_tiles(row_ptr, col_idx, path="auto", tile=0, reorder="auto", orien
     n = row_ptr.numel() - 1
     nnz = col_idx.numel()
     csr = MisCsr(n, nnz, _ptr(row_ptr), _ptr(col_idx) if nnz else None)
-    o = _opts(path, tile, reorder, orient, validate, seed, keys, poll_rounds, launch, blocks_per_cu)
+    o = _opts(path, tile, reorder, orient, validate, seed, keys, poll_rounds, launch, blocks_per_cu, dense_min)
     need = ctypes.c_size_t(0)
     _check(L.mis_build_bytes(ctypes.byref(csr), ctypes.byref(o), ctypes.byref(need)))
     if workspace is None:
@@ -282,7 +285,7 @@ def mis_build_batch_bytes(n: int, nnz: int, offsets, **opts) -> int:
 
 def mis_build_batch(row_ptr, col_idx, offsets, path="auto", tile=0, reorder="auto", orient=-1, validate=False,
                     seed=1, keys=None, poll_rounds=0, launch="auto", blocks_per_cu=0, workspace=None,
-                    stream=None) -> MisGraph:
+                    stream=None, dense_min=0) -> MisGraph:
     """A batch of independent graphs given as their disjoint union (cuda CSR) and host
     vertex offsets (count+1).  Priorities use graph-local ids."""
     import torch
@@ -291,7 +294,7 @@ def mis_build_batch(row_ptr, col_idx, offsets, path="auto", tile=0, reorder="aut
     nnz = col_idx.numel()
     csr = MisCsr(n, nnz, _ptr(row_ptr), _ptr(col_idx) if nnz else None)
     off, offp = _offsets(offsets)
-    o = _opts(path, tile, reorder, orient, validate, seed, keys, poll_rounds, launch, blocks_per_cu)
+    o = _opts(path, tile, reorder, orient, validate, seed, keys, poll_rounds, launch, blocks_per_cu, dense_min)
     need = ctypes.c_size_t(0)
     _check(L.mis_build_batch_bytes(ctypes.byref(csr), len(off) - 1, offp, ctypes.byref(o), ctypes.byref(need)))
     if workspace is None:
@@ -325,7 +328,7 @@ _REORDER_NAMES = {v: k for k, v in REORDERS.items()}
 
 
 def mis_autotune(row_ptr, col_idx, offsets=None, path="auto", tile=0, blocks_per_cu=0, seed=1, keys=None,
-                 poll_rounds=0, launch="auto", workspace=None, stream=None):
+                 poll_rounds=0, launch="auto", workspace=None, stream=None, dense_min=0):
     """Tuned build options for this graph (or batch, with host offsets) as a dict of
     mis_build_tiles / mis_build_batch keyword arguments, plus whether the profile
     bucket was already cached: (opts, from_cache)."""
@@ -338,7 +341,7 @@ def mis_autotune(row_ptr, col_idx, offsets=None, path="auto", tile=0, blocks_per
     if offsets is not None:
         off, offp = _offsets(offsets)
         count = len(off) - 1
-    o = _opts(path, tile, "auto", -1, False, seed, keys, poll_rounds, launch, blocks_per_cu)
+    o = _opts(path, tile, "auto", -1, False, seed, keys, poll_rounds, launch, blocks_per_cu, dense_min)
     need = ctypes.c_size_t(0)
     _check(L.mis_autotune_bytes(ctypes.byref(csr), count, offp, ctypes.byref(o), ctypes.byref(need)))
     if workspace is None:
@@ -348,8 +351,8 @@ def mis_autotune(row_ptr, col_idx, offsets=None, path="auto", tile=0, blocks_per
     _check(L.mis_autotune(ctypes.byref(csr), count, offp, ctypes.byref(o), _ptr(workspace), workspace.numel(),
                           ctypes.c_void_p(_stream(stream)), ctypes.byref(res), ctypes.byref(cached)))
     opts = dict(path=_PATH_NAMES[res.path], tile=res.tile, reorder=_REORDER_NAMES[res.reorder],
-                orient=res.orient, blocks_per_cu=res.blocks_per_cu, seed=seed, keys=keys,
-                poll_rounds=poll_rounds, launch=launch)
+                orient=res.orient, blocks_per_cu=res.blocks_per_cu, dense_min=res.dense_min, seed=seed,
+                keys=keys, poll_rounds=poll_rounds, launch=launch)
     return opts, bool(cached.value)
 
 

@@ -15,11 +15,23 @@ from paper_2605_29604_amd import gen
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
+# (path, tile, reorder, orient[, dense_min]); the hybrid path's dense_min: -1 = entry
+# lists only, 1 = every block that fits 64 tiles is dense (bit tiles on the matrix
+# cores wherever possible), 9 = the default split
+HYBRID_CONFIGS = [("hybrid", 16, "none", 1, d) for d in (-1, 1, 9)]
 ALL_CONFIGS = [("csr", 0, "none", 0)] + [
     ("tile", t, r, o) for t in (16, 32) for r in ("none", "degree", "key", "rcm") for o in (0, 1)
-]
+] + HYBRID_CONFIGS
 FAST_CONFIGS = [("csr", 0, "none", 0), ("tile", 16, "key", 1), ("tile", 16, "none", 0),
-                ("tile", 32, "degree", 1), ("tile", 32, "rcm", 0)]
+                ("tile", 32, "degree", 1), ("tile", 32, "rcm", 0)] + HYBRID_CONFIGS
+
+
+def kw(cfg):
+    """Build keyword arguments of a config tuple."""
+    d = dict(path=cfg[0], tile=cfg[1], reorder=cfg[2], orient=cfg[3])
+    if len(cfg) > 4:
+        d["dense_min"] = cfg[4]
+    return d
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -47,11 +59,9 @@ def expected(rp, ci, keys, max_rounds=0):
 
 def run(rp, ci, cfg, seed=1, keys=None, max_rounds=0, validate=True, poll_rounds=0):
     T = tcmis_mod()
-    path, tile, reorder, orient = cfg
     drp, dci = to_dev(rp, ci)
     dkeys = None if keys is None else torch.from_numpy(keys.view(np.int64)).cuda()
-    h = T.mis_build_tiles(drp, dci, path=path, tile=tile, reorder=reorder, orient=orient, seed=seed,
-                          keys=dkeys, validate=validate, poll_rounds=poll_rounds)
+    h = T.mis_build_tiles(drp, dci, seed=seed, keys=dkeys, validate=validate, poll_rounds=poll_rounds, **kw(cfg))
     out, st = T.mis_solve(h, max_rounds=max_rounds)
     torch.cuda.synchronize()
     got = out.cpu().numpy()
@@ -138,6 +148,12 @@ def test_entry_windows(cfg):
     c = 5000   # a cycle on the even vertices, every odd vertex isolated
     rp, ci = csr_from_edges(2 * c, [(2 * i, 2 * ((i + 1) % c)) for i in range(c)])
     check(rp, ci, cfg, label="cycle5000-isolated")
+    # the hybrid orientation stages 512 rows per 2048 entries: a 2D mesh (degree 4
+    # inside, 2-3 on the rim) puts its windows on both sides of that bound
+    s = 70
+    rp, ci = csr_from_edges(s * s, [(y * s + x, y * s + x + 1) for y in range(s) for x in range(s - 1)] +
+                            [(y * s + x, (y + 1) * s + x) for y in range(s - 1) for x in range(s)])
+    check(rp, ci, cfg, label="mesh70x70")
 
 
 @pytest.mark.parametrize("tile", [16, 32])
@@ -148,6 +164,9 @@ def test_default_keys_given_by_caller(tile):
     keys = oracle.keys(g.row_ptr, 9)
     check(g.row_ptr, g.col_idx, ("tile", tile, "key", 1), seed=9, keys=keys, label="rmat14-keys")
     check(g.row_ptr, g.col_idx, ("tile", tile, "key", 1), seed=9, label="rmat14-default")
+    # the hybrid path then compares gathered keys instead of degree classes and hashes
+    for d in (-1, 1):
+        check(g.row_ptr, g.col_idx, ("hybrid", 16, "none", 1, d), seed=9, keys=keys, label="rmat14-keys-hybrid")
 
 
 def test_one_degree_class_key_order():
@@ -165,7 +184,7 @@ def test_empty_graph():
     T = tcmis_mod()
     drp = torch.zeros(1, dtype=torch.int64, device="cuda")
     dci = torch.zeros(0, dtype=torch.int32, device="cuda")
-    for path in ("csr", "tile"):
+    for path in ("csr", "tile", "hybrid"):
         h = T.mis_build_tiles(drp, dci, path=path, validate=True)
         out, st = T.mis_solve(h)
         assert out.numel() == 0 and st["rounds"] == 0
@@ -192,7 +211,7 @@ def test_repeat_and_poll_interval_deterministic():
     drp, dci = to_dev(g.row_ptr, g.col_idx)
     for cfg in FAST_CONFIGS:
         for poll in (1, 2, 5):
-            h = T.mis_build_tiles(drp, dci, path=cfg[0], tile=cfg[1], reorder=cfg[2], orient=cfg[3], seed=9,
+            h = T.mis_build_tiles(drp, dci, **kw(cfg), seed=9,
                                   poll_rounds=poll)
             for _ in range(3):
                 out, st = T.mis_solve(h)
@@ -220,7 +239,7 @@ def test_validation_errors(bad):
         keys = np.array([5, 5, 1, 2, 3, 4], dtype=np.uint64)
     drp, dci = to_dev(rp, ci)
     dkeys = None if keys is None else torch.from_numpy(keys.view(np.int64)).cuda()
-    for path in ("csr", "tile"):
+    for path in ("csr", "tile", "hybrid"):
         with pytest.raises(T.MisError) as ei:
             T.mis_build_tiles(drp, dci, path=path, keys=dkeys, validate=True)
         assert ei.value.code == want
@@ -228,7 +247,8 @@ def test_validation_errors(bad):
 
 @pytest.mark.slow
 @pytest.mark.parametrize("cfg", [("csr", 0, "none", 0), ("tile", 16, "key", 1), ("tile", 16, "key", 0),
-                                 ("tile", 32, "key", 1)], ids=lambda c: "-".join(map(str, c)))
+                                 ("tile", 32, "key", 1), ("hybrid", 16, "none", 1, 9),
+                                 ("hybrid", 16, "none", 1, 1)], ids=lambda c: "-".join(map(str, c)))
 def test_rmat22_full(cfg):
     g = gen.workload("rmat22", seed=1)
     check(g.row_ptr, g.col_idx, cfg, seed=1, label="rmat22")
@@ -236,7 +256,8 @@ def test_rmat22_full(cfg):
 
 @pytest.mark.slow
 @pytest.mark.parametrize("cfg", [("csr", 0, "none", 0), ("tile", 16, "none", 1), ("tile", 32, "rcm", 1),
-                                 ("tile", 16, "rcm", 0)], ids=lambda c: "-".join(map(str, c)))
+                                 ("tile", 16, "rcm", 0), ("hybrid", 16, "none", 1, 9),
+                                 ("hybrid", 16, "none", 1, -1)], ids=lambda c: "-".join(map(str, c)))
 def test_grid256_full(cfg):
     g = gen.workload("grid256", seed=1)
     check(g.row_ptr, g.col_idx, cfg, seed=1, label="grid256")
@@ -253,7 +274,7 @@ def test_launch_modes_and_graph_replays(cfg):
     want, rounds, trace = expected(g.row_ptr, g.col_idx, k)
     drp, dci = to_dev(g.row_ptr, g.col_idx)
     for launch in ("direct", "graph", "auto"):
-        h = T.mis_build_tiles(drp, dci, path=cfg[0], tile=cfg[1], reorder=cfg[2], orient=cfg[3], seed=6,
+        h = T.mis_build_tiles(drp, dci, **kw(cfg), seed=6,
                               poll_rounds=2, launch=launch)
         for rep in range(4):
             out, st = T.mis_solve(h)
@@ -286,7 +307,7 @@ def test_output_at_any_alignment(cfg):
     k = oracle.keys(rp2, 2)
     want, _, _ = expected(rp2, ci_, k)
     drp, dci = to_dev(rp2, ci_)
-    h = T.mis_build_tiles(drp, dci, path=cfg[0], tile=cfg[1], reorder=cfg[2], orient=cfg[3], seed=2, validate=True)
+    h = T.mis_build_tiles(drp, dci, **kw(cfg), seed=2, validate=True)
     base = torch.full((n + 8,), 7, dtype=torch.uint8, device="cuda")
     for off in range(4):
         base.fill_(7)
@@ -309,7 +330,7 @@ def test_persistent_cooperative_rounds(cfg):
         k = oracle.keys(g.row_ptr, 6)
         want, rounds, trace = expected(g.row_ptr, g.col_idx, k)
         drp, dci = to_dev(g.row_ptr, g.col_idx)
-        h = T.mis_build_tiles(drp, dci, path=cfg[0], tile=cfg[1], reorder=cfg[2], orient=cfg[3], seed=6,
+        h = T.mis_build_tiles(drp, dci, **kw(cfg), seed=6,
                               poll_rounds=3, launch="persistent")
         for rep in range(2):
             print(f"case persistent {name} cfg={cfg} rep={rep}", flush=True)
@@ -326,7 +347,7 @@ def test_persistent_cooperative_rounds(cfg):
     graphs = [gen.make(*s) for s in gen.batch_spec(12, seed=4, n_min=30, n_max=3000)]
     rp, ci, off = gen.union(graphs)
     drp, dci = to_dev(rp, ci)
-    h = T.mis_build_batch(drp, dci, off, path=cfg[0], tile=cfg[1], reorder=cfg[2], orient=cfg[3], seed=2,
+    h = T.mis_build_batch(drp, dci, off, **kw(cfg), seed=2,
                           launch="persistent")
     out, st, rounds, sizes = T.mis_solve_batch(h)
     torch.cuda.synchronize()
@@ -337,14 +358,15 @@ def test_persistent_cooperative_rounds(cfg):
     T.mis_free_tiles(h)
 
 
-BATCH_CONFIGS = [("csr", 0, "none", 0), ("tile", 16, "key", 1), ("tile", 32, "degree", 0), ("tile", 16, "rcm", 1)]
+BATCH_CONFIGS = [("csr", 0, "none", 0), ("tile", 16, "key", 1), ("tile", 32, "degree", 0), ("tile", 16, "rcm", 1),
+                 ("hybrid", 16, "none", 1, -1), ("hybrid", 16, "none", 1, 1)]
 
 
 def solve_batch(graphs, cfg, seed):
     T = tcmis_mod()
     rp, ci, off = gen.union(graphs)
     drp, dci = to_dev(rp, ci)
-    h = T.mis_build_batch(drp, dci, off, path=cfg[0], tile=cfg[1], reorder=cfg[2], orient=cfg[3], seed=seed,
+    h = T.mis_build_batch(drp, dci, off, **kw(cfg), seed=seed,
                           validate=True, poll_rounds=3)
     out, st, rounds, sizes = T.mis_solve_batch(h)
     torch.cuda.synchronize()
@@ -391,9 +413,11 @@ def test_autotune_picks_a_valid_config_and_caches_it():
         print(f"case autotune {name} -> {opts['path']} T={opts['tile']} {opts['reorder']} "
               f"bpc={opts['blocks_per_cu']} cached={cached}", flush=True)
         assert not cached
-        assert opts["path"] in ("tile", "csr") and opts["blocks_per_cu"] in (4, 8, 16)
+        assert opts["path"] in ("tile", "csr", "hybrid") and opts["blocks_per_cu"] in (4, 8, 16)
         if opts["path"] == "tile":
-            assert opts["tile"] in (16, 32) and opts["reorder"] in ("key", "none")
+            assert opts["tile"] in (16, 32) and opts["reorder"] in ("key", "none", "degree", "rcm")
+        if opts["path"] == "hybrid":
+            assert opts["tile"] == 16 and opts["dense_min"] in (-1, 4, 9, 16)
         again, cached = T.mis_autotune(drp, dci, seed=4)
         assert cached and again == opts
         h = T.mis_build_tiles(drp, dci, validate=True, **opts)

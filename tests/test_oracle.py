@@ -56,6 +56,59 @@ def test_keys_distinct_and_degree_ordered():
         oracle.keys(np.zeros((1 << 24) + 2, dtype=np.int64), 1)
 
 
+def test_key_rules_degree_and_h1_against_vector():
+    # the degree rule is orc_keys; H1 (Section 3.3: P(v) = hash(v)) keeps only the
+    # published SplitMix64 output's top half and the id
+    vec = [int(x) for x in golden("splitmix64_seed1234567.txt")]
+    rp, ci = csr_from_edges(5, [(0, 1), (0, 2), (0, 3), (3, 4)])
+    assert np.array_equal(oracle.keys_rule(rp, 1234567, "degree"), oracle.keys(rp, 1234567))
+    k = oracle.keys_rule(rp, 1234567, "hash")
+    for v in range(5):
+        assert int(k[v]) == ((vec[v] >> 32) << 24) | v
+
+
+def _eq1_reference(deg, nnz, n, z):
+    # Eq. 1, P = dbar / (dbar + deg - eps), with exact rationals: dbar = nnz / n and
+    # eps = (low byte of the SplitMix64 output) / 256; scaled by 255, floored, capped
+    from fractions import Fraction
+    dbar = Fraction(nnz, n)
+    den = dbar + deg - Fraction(z & 0xFF, 256)
+    if den <= 0:
+        return 255
+    return min(255, int((255 * dbar / den).__floor__()))
+
+
+def test_key_rule_eq1_against_exact_rationals():
+    vec = [int(x) for x in golden("splitmix64_seed1234567.txt")]
+    # 256 nnz / n is an integer (n = 256, and n = 4096 with nnz a multiple of 16): the
+    # discretised average degree is exact, so q equals the rational formula exactly
+    cases = [gen.er(256, 900, 3), gen.er(4096, 16000, 5)]
+    rp, ci = csr_from_edges(256, [(0, i) for i in range(1, 256)])   # a star: isolated-free, skewed
+    cases.append(gen.Graph(256, rp, ci))
+    for g in cases:
+        assert (256 * g.nnz) % g.n == 0
+        k = oracle.keys_rule(g.row_ptr, 1234567, "eq1")
+        z = oracle.splitmix64(1234567, g.n)
+        assert [int(x) for x in z[:len(vec)]] == vec   # the stream is the published one
+        d = g.degrees()
+        for v in range(g.n):
+            assert int(k[v]) >> 56 == _eq1_reference(int(d[v]), g.nnz, g.n, int(z[v])), v
+            assert (int(k[v]) >> 24) & 0xFFFFFFFF == int(z[v]) >> 32 and int(k[v]) & 0xFFFFFF == v
+    # otherwise the 8-fractional-bit average is below the exact one: q never exceeds the
+    # rational value and (average degree 8 here) stays within one of it
+    g = gen.er(3001, 12007, 7)
+    k = oracle.keys_rule(g.row_ptr, 1234567, "eq1")
+    z = oracle.splitmix64(1234567, g.n)
+    d = g.degrees()
+    for v in range(g.n):
+        ref = _eq1_reference(int(d[v]), g.nnz, g.n, int(z[v]))
+        assert ref - 1 <= int(k[v]) >> 56 <= ref, v
+    # isolated vertices take the top class; degree order is kept for equal perturbation
+    rp = np.array([0, 0, 1, 2], dtype=np.int64)
+    ci = np.array([2, 1], dtype=np.int32)
+    assert int(oracle.keys_rule(rp, 1, "eq1")[0]) >> 56 == 255
+
+
 # ------------------------------------------------------------ paper example
 
 def test_worked_example_section_3_1():
