@@ -330,6 +330,46 @@ int mis_session_query(const mis_session* s, int32_t* live, size_t* bytes_in_use,
 /* Waits for the session's device work, then releases it (the arena stays the caller's). */
 void mis_session_destroy(mis_session* s);
 
+/*
+ * Durations (HOST float[cap], milliseconds, from HIP events on the build stream) of
+ * the build stages of a handle built with opts.timing = 1; *count receives the
+ * number of stages.  Stages (after validation, which is not timed): keys, then
+ *   hybrid path: orientation row search (with clearing the counts), orientation
+ *                (the orientation pass alone), dense blocks (0 if none), round-1
+ *                classes and lists (an empty graph has the keys stage only);
+ *   tile path:   vertex order, tiles;
+ *   CSR path:    vertex lists.
+ * Synchronises the last event.  Errors: MIS_EINVAL (no timing), MIS_EHIP.
+ */
+int mis_build_times(const mis_graph* g, float* ms, int32_t cap, int32_t* count);
+
+/*
+ * Build + solve in one call that allocates nothing: for callers that cannot allocate
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * allocation).  It computes what mis_build_tiles + mis_solve compute for the same
+ * graph and options, with the solver structure and round state in a device array
+ * of mis_noalloc_max_bytes() bytes (64 MiB) that the library holds on every GPU it
+ * runs on until the process ends.  It calls no device or host allocation routine:
+ * no workspace argument, no pooled pinned buffers (the round loop polls into host
+ * stack memory), no captured graph (rounds are launched directly).
+ *   csr, opts : as for mis_build_tiles (opts NULL = defaults); the CSR stays the
+ *               caller's.  Refused with MIS_EINVAL: reorder = MIS_REORDER_RCM (host
+ *               buffers), timing = 1 (events), launch graph or persistent, and any
+ *               graph whose structure (mis_build_bytes) exceeds the array.
+ *   in_set    : DEVICE uint8[n], as for mis_solve.
+ *   rounds, n_in : HOST, optional: rounds run and the set's size.
+ * Synchronises `stream`.  All calls on one GPU share its array (the last call's
+ * contents stay there; every call rebuilds what it reads), so calls that may
+ * overlap on one GPU -- from several threads, or on streams not ordered with each
+ * other -- race and must be serialised by the caller.
+ * Errors: as mis_build_tiles and mis_solve.
+ */
+int mis_solve_noalloc(const mis_csr* csr, const mis_build_opts* opts, uint8_t* in_set, int32_t* rounds, int64_t* n_in,
+                      void* stream);
+
+/* Bytes of the per-GPU array behind mis_solve_noalloc. */
+size_t mis_noalloc_max_bytes(void);
+
 /* Releases the handle (host memory only; the workspace stays the caller's). */
 void mis_free_tiles(mis_graph* g);
 

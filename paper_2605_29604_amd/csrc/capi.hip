@@ -176,6 +176,21 @@ int resolve(const mis_csr* csr, const mis_build_opts* opts, mis_build_opts* o, i
     return MIS_OK;
 }
 
+}  // namespace
+
+void build_mark(mis_graph* g, hipStream_t s) {
+    if (!g->btiming) return;
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    if (hipEventRecord(e, s) != hipSuccess) {
+        (void)hipEventDestroy(e);
+        return;
+    }
+    g->bev.push_back(e);
+}
+
+namespace {
+
 void configure(mis_graph* g, const mis_csr* csr, const mis_build_opts& o) {
     g->n = csr->n;
     g->nnz = csr->nnz;
@@ -189,6 +204,7 @@ void configure(mis_graph* g, const mis_csr* csr, const mis_build_opts& o) {
     g->launch = o.launch;
     g->user_keys = o.keys != nullptr;
     g->seed = o.seed;
+    g->btiming = o.timing != 0;
     g->dense_min = o.path == MIS_PATH_HYBRID && o.dense_min > 0 ? o.dense_min : 0;
 }
 
@@ -338,6 +354,45 @@ int solve_rounds(mis_graph* g, int64_t k, bool allow_graph, hipStream_t s) {
     return enqueue_batch(g, k, s, nullptr);
 }
 
+int resolve_opts(const mis_csr* csr, const mis_build_opts* opts, mis_build_opts* o, int32_t count,
+                 const int64_t* offsets) {
+    return resolve(csr, opts, o, count, offsets);
+}
+
+void configure_graph(mis_graph* g, const mis_csr* csr, const mis_build_opts& o, int32_t count) {
+    configure(g, csr, o);
+    g->count = count;
+}
+
+int build_into(mis_graph* g, const mis_csr* csr, const mis_build_opts& o, int32_t count, const int64_t* offsets,
+               char* ws, size_t need, hipStream_t s) {
+    g->ws = ws;
+    g->ws_bytes = need;
+    layout(g, g->ws);
+    int dev = 0, cus = 256;
+    TC_HIP(hipGetDevice(&dev));
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    g->grid_blocks = std::max(1, cus) * (o.blocks_per_cu ? o.blocks_per_cu : 8);
+    int rc = MIS_OK;
+    if (count > 0 && hipMemcpyAsync(g->goff, offsets, (size_t)(count + 1) * 8, hipMemcpyHostToDevice, s) != hipSuccess)
+        rc = fail(MIS_EHIP, "copy of the batch offsets failed");
+    if (rc == MIS_OK && o.validate) rc = validate_graph(csr, o.keys, g->goff, count, &g->ctrl->error, s);
+    build_mark(g, s);
+    if (rc == MIS_OK) rc = build_keys(g, &o, s);
+    build_mark(g, s);
+    if (rc == MIS_OK) {
+        if (g->path == MIS_PATH_CSR) rc = build_csr_lists(g, s);
+        else if (g->path == MIS_PATH_HYBRID) rc = build_hybrid(g, s);
+        else {
+            rc = build_order(g, s);
+            build_mark(g, s);
+            if (rc == MIS_OK) rc = build_tiles(g, s);
+        }
+    }
+    build_mark(g, s);
+    return rc;
+}
+
 int solve_output(mis_graph* g, uint8_t* in_set, hipStream_t s, bool if_done) {
     if (g->path == MIS_PATH_HYBRID) return hyb_output(g, in_set, if_done, s);
     return g->path == MIS_PATH_TILE ? tile_output(g, in_set, if_done, s) : csr_output(g, in_set, if_done, s);
@@ -421,28 +476,7 @@ int mis_build_batch(const mis_csr* csr, int32_t count, const int64_t* offsets, c
         return fail(MIS_EINVAL, "workspace must be 256-byte aligned device memory of at least " +
                                     std::to_string(need) + " bytes (mis_build_bytes)");
     }
-    g->ws = (char*)workspace;
-    g->ws_bytes = need;
-    layout(g, g->ws);
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) != hipSuccess) { delete g; return fail(MIS_EHIP, "hipGetDevice failed"); }
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    g->grid_blocks = std::max(1, cus) * (o.blocks_per_cu ? o.blocks_per_cu : 8);
-
-    hipStream_t s = (hipStream_t)stream;
-    int rc = MIS_OK;
-    if (count > 0 && hipMemcpyAsync(g->goff, offsets, (size_t)(count + 1) * 8, hipMemcpyHostToDevice, s) != hipSuccess)
-        rc = fail(MIS_EHIP, "copy of the batch offsets failed");
-    if (rc == MIS_OK && o.validate) rc = validate_graph(csr, o.keys, g->goff, count, &g->ctrl->error, s);
-    if (rc == MIS_OK) rc = build_keys(g, &o, s);
-    if (rc == MIS_OK) {
-        if (g->path == MIS_PATH_CSR) rc = build_csr_lists(g, s);
-        else if (g->path == MIS_PATH_HYBRID) rc = build_hybrid(g, s);
-        else {
-            rc = build_order(g, s);
-            if (rc == MIS_OK) rc = build_tiles(g, s);
-        }
-    }
+    const int rc = build_into(g, csr, o, count, offsets, (char*)workspace, need, (hipStream_t)stream);
     if (rc != MIS_OK) {
         delete g;
         return rc;
@@ -591,6 +625,16 @@ int mis_solve_batch(mis_graph* g, uint8_t* in_set, mis_stats* stats, int32_t* gr
 }
 
 void mis_free_tiles(mis_graph* g) { delete g; }
+
+int mis_build_times(const mis_graph* g, float* ms, int32_t cap, int32_t* count) {
+    if (!g || !count || cap < 0 || (cap > 0 && !ms)) return fail(MIS_EINVAL, "bad argument");
+    if (!g->btiming) return fail(MIS_EINVAL, "the handle was not built with timing = 1");
+    const int32_t k = g->bev.empty() ? 0 : (int32_t)g->bev.size() - 1;
+    *count = k;
+    if (k > 0) TC_HIP(hipEventSynchronize(g->bev.back()));
+    for (int32_t i = 0; i < k && i < cap; ++i) TC_HIP(hipEventElapsedTime(&ms[i], g->bev[i], g->bev[i + 1]));
+    return MIS_OK;
+}
 
 void mis_release_host_buffers(void) {
     StagingPool& P = staging_pool();

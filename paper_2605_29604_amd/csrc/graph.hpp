@@ -100,10 +100,15 @@ struct mis_graph {
     bool graph_failed = false;
     int64_t solves = 0;               // mis_solve calls on this handle (auto launch captures from the 2nd)
 
+    // build-stage events (opts.timing = 1), recorded on the build stream
+    bool btiming = false;
+    std::vector<hipEvent_t> bev;
+
     ~mis_graph() {
         if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
         if (graph) (void)hipGraphDestroy(graph);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        for (hipEvent_t e : bev) (void)hipEventDestroy(e);
     }
     int grid_blocks = 2048;           // persistent grid of the round kernels
     int coop_blocks = 0;              // grid of the cooperative round kernels (0 = not sized yet)
@@ -196,6 +201,9 @@ struct mis_graph {
 };
 
 namespace tcmis {
+// Records a build-stage boundary on s when the handle was built with timing.
+void build_mark(mis_graph* g, hipStream_t s);
+
 // Assigns every workspace array of g (base == nullptr: only computes the size).
 size_t layout(mis_graph* g, char* base);
 
@@ -204,6 +212,14 @@ size_t layout(mis_graph* g, char* base);
 // captured hipGraph when k == poll_rounds and graph launch is allowed) and
 // solve_output writes the in/out vector in input ids.
 int solve_begin(mis_graph* g, hipStream_t s);
+
+// Option checks and defaults (host-only), the handle's configuration, and the build
+// into a workspace of `need` bytes (layout() of the configured handle).
+int resolve_opts(const mis_csr* csr, const mis_build_opts* opts, mis_build_opts* o, int32_t count,
+                 const int64_t* offsets);
+void configure_graph(mis_graph* g, const mis_csr* csr, const mis_build_opts& o, int32_t count);
+int build_into(mis_graph* g, const mis_csr* csr, const mis_build_opts& o, int32_t count, const int64_t* offsets,
+               char* ws, size_t need, hipStream_t s);
 int solve_rounds(mis_graph* g, int64_t k, bool allow_graph, hipStream_t s);
 int solve_output(mis_graph* g, uint8_t* in_set, hipStream_t s, bool if_done = false);
 }  // namespace tcmis

@@ -770,11 +770,12 @@ int build_hybrid(mis_graph* g, hipStream_t s) {
     const int64_t n = g->n, nnz = g->nnz, nI = g->nI;
     TC_HIP(hipMemsetAsync(g->meta, 0, sizeof(Meta), s));
     if (n == 0) return MIS_OK;
-    // 1. orientation
+    // 1. orientation (stages: row search, orientation, dense blocks, lists)
     TC_HIP(hipMemsetAsync(g->hcnt, 0, (size_t)n * 4, s));
     const int64_t nb = hyb_blocks(nnz);
+    if (nnz > 0) HLAUNCH(k_orient_rows, nb + 1, g->row_ptr, n, nnz, nb, g->hbrow);
+    build_mark(g, s);
     if (nnz > 0) {
-        HLAUNCH(k_orient_rows, nb + 1, g->row_ptr, n, nnz, nb, g->hbrow);
         if (g->user_keys)
             hipLaunchKernelGGL(k_orient<true>, dim3((unsigned)nb), dim3(kBlock), 0, s, g->row_ptr, g->col_idx, g->key,
                                g->q8, g->seed, nnz, g->hbrow, g->hcol, g->hcnt, g->hbase, g->hoff);
@@ -783,6 +784,7 @@ int build_hybrid(mis_graph* g, hipStream_t s) {
                                g->key, g->q8, g->seed, nnz, g->hbrow, g->hcol, g->hcnt, g->hbase, g->hoff);
         TC_HIP(hipGetLastError());
     }
+    build_mark(g, s);
     // 2. dense blocks
     const bool dense = g->dense_min > 0 && nnz > 0;
     if (dense) {
@@ -801,6 +803,7 @@ int build_hybrid(mis_graph* g, hipStream_t s) {
         TC_HIP(hipGetLastError());
         HLAUNCH(k_dense_slots, nI, g->dflag, g->dpos, nI, g->dslot);
     }
+    build_mark(g, s);
     // 3. round-1 classes and lists
     HLAUNCH(k_hyb_class, n, g->hcnt, dense ? g->dflag : nullptr, n, g->hflag, g->s1, g->a1, &g->meta->n_c1);
     TC_CHECK(scan_excl_i64(g->hflag, g->hpos, n, g->hpos + n, (int64_t*)g->scan_tmp, s));

@@ -22,6 +22,7 @@ REORDER_AUTO, REORDER_NONE, REORDER_DEGREE, REORDER_KEY, REORDER_RCM = 0, 1, 2, 
 
 PATHS = {"auto": PATH_AUTO, "tile": PATH_TILE, "csr": PATH_CSR, "hybrid": PATH_HYBRID}
 LAUNCHES = {"auto": 0, "direct": 1, "graph": 2, "persistent": 3}
+KEY_RULES = {"degree": 0, "hash": 1, "eq1": 2}
 REORDERS = {"auto": REORDER_AUTO, "none": REORDER_NONE, "degree": REORDER_DEGREE,
             "key": REORDER_KEY, "rcm": REORDER_RCM}
 
@@ -30,7 +31,7 @@ EXPORTS = ["mis_default_opts", "mis_build_bytes", "mis_build_tiles", "mis_build_
            "mis_graph_bytes", "mis_solve", "mis_solve_batch", "mis_free_tiles", "mis_status_string", "mis_last_error",
            "mis_version", "mis_autotune_bytes", "mis_autotune", "mis_autotune_clear", "mis_session_create",
            "mis_session_admit", "mis_session_progress", "mis_session_query", "mis_session_destroy",
-           "mis_release_host_buffers"]
+           "mis_release_host_buffers", "mis_build_times", "mis_solve_noalloc", "mis_noalloc_max_bytes"]
 
 
 class MisCsr(ctypes.Structure):
@@ -131,6 +132,13 @@ def lib():
     L.mis_session_destroy.restype = None
     L.mis_free_tiles.argtypes = [vp]
     L.mis_free_tiles.restype = None
+    L.mis_build_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32, ctypes.POINTER(ctypes.c_int32)]
+    L.mis_build_times.restype = ctypes.c_int
+    L.mis_solve_noalloc.argtypes = [ctypes.POINTER(MisCsr), ctypes.POINTER(MisBuildOpts), vp,
+                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64), vp]
+    L.mis_solve_noalloc.restype = ctypes.c_int
+    L.mis_noalloc_max_bytes.argtypes = []
+    L.mis_noalloc_max_bytes.restype = ctypes.c_size_t
     L.mis_release_host_buffers.argtypes = []
     L.mis_release_host_buffers.restype = None
     L.mis_status_string.argtypes = [ctypes.c_int]
@@ -184,7 +192,7 @@ class MisGraph:
 
 
 def _opts(path="auto", tile=0, reorder="auto", orient=-1, validate=False, seed=1, keys=None, poll_rounds=0,
-          launch="auto", blocks_per_cu=0, dense_min=0):
+          launch="auto", blocks_per_cu=0, dense_min=0, key_rule="degree", timing=False):
     o = MisBuildOpts()
     lib().mis_default_opts(ctypes.byref(o))
     o.path = PATHS[path] if isinstance(path, str) else int(path)
@@ -196,6 +204,8 @@ def _opts(path="auto", tile=0, reorder="auto", orient=-1, validate=False, seed=1
     o.launch = LAUNCHES[launch] if isinstance(launch, str) else int(launch)
     o.blocks_per_cu = int(blocks_per_cu)
     o.dense_min = int(dense_min)
+    o.key_rule = KEY_RULES[key_rule] if isinstance(key_rule, str) else int(key_rule)
+    o.timing = int(bool(timing))
     o.seed = int(seed) & (2**64 - 1)
     o.keys = _ptr(keys)
     return o
@@ -212,7 +222,7 @@ def mis_build_bytes(n: int, nnz: int, **opts) -> int:
 
 def mis_build_tiles(row_ptr, col_idx, path="auto", tile=0, reorder="auto", orient=-1, validate=False,
                     seed=1, keys=None, poll_rounds=0, launch="auto", blocks_per_cu=0, workspace=None,
-                    stream=None, dense_min=0) -> MisGraph:
+                    stream=None, dense_min=0, key_rule="degree", timing=False) -> MisGraph:
     """row_ptr: cuda int64[n+1]; col_idx: cuda int32[nnz]; keys: optional cuda uint64[n] (as int64).
 
     The device workspace comes from torch's allocator unless one is passed (a cuda
@@ -223,7 +233,8 @@ def mis_build_tiles(row_ptr, col_idx, path="auto", tile=0, reorder="auto", orien
     n = row_ptr.numel() - 1
     nnz = col_idx.numel()
     csr = MisCsr(n, nnz, _ptr(row_ptr), _ptr(col_idx) if nnz else None)
-    o = _opts(path, tile, reorder, orient, validate, seed, keys, poll_rounds, launch, blocks_per_cu, dense_min)
+    o = _opts(path, tile, reorder, orient, validate, seed, keys, poll_rounds, launch, blocks_per_cu, dense_min,
+              key_rule, timing)
     need = ctypes.c_size_t(0)
     _check(L.mis_build_bytes(ctypes.byref(csr), ctypes.byref(o), ctypes.byref(need)))
     if workspace is None:
@@ -285,7 +296,7 @@ def mis_build_batch_bytes(n: int, nnz: int, offsets, **opts) -> int:
 
 def mis_build_batch(row_ptr, col_idx, offsets, path="auto", tile=0, reorder="auto", orient=-1, validate=False,
                     seed=1, keys=None, poll_rounds=0, launch="auto", blocks_per_cu=0, workspace=None,
-                    stream=None, dense_min=0) -> MisGraph:
+                    stream=None, dense_min=0, key_rule="degree", timing=False) -> MisGraph:
     """A batch of independent graphs given as their disjoint union (cuda CSR) and host
     vertex offsets (count+1).  Priorities use graph-local ids."""
     import torch
@@ -294,7 +305,8 @@ def mis_build_batch(row_ptr, col_idx, offsets, path="auto", tile=0, reorder="aut
     nnz = col_idx.numel()
     csr = MisCsr(n, nnz, _ptr(row_ptr), _ptr(col_idx) if nnz else None)
     off, offp = _offsets(offsets)
-    o = _opts(path, tile, reorder, orient, validate, seed, keys, poll_rounds, launch, blocks_per_cu, dense_min)
+    o = _opts(path, tile, reorder, orient, validate, seed, keys, poll_rounds, launch, blocks_per_cu, dense_min,
+              key_rule, timing)
     need = ctypes.c_size_t(0)
     _check(L.mis_build_batch_bytes(ctypes.byref(csr), len(off) - 1, offp, ctypes.byref(o), ctypes.byref(need)))
     if workspace is None:
@@ -328,7 +340,7 @@ _REORDER_NAMES = {v: k for k, v in REORDERS.items()}
 
 
 def mis_autotune(row_ptr, col_idx, offsets=None, path="auto", tile=0, blocks_per_cu=0, seed=1, keys=None,
-                 poll_rounds=0, launch="auto", workspace=None, stream=None, dense_min=0):
+                 poll_rounds=0, launch="auto", workspace=None, stream=None, dense_min=0, key_rule="degree"):
     """Tuned build options for this graph (or batch, with host offsets) as a dict of
     mis_build_tiles / mis_build_batch keyword arguments, plus whether the profile
     bucket was already cached: (opts, from_cache)."""
@@ -341,7 +353,7 @@ def mis_autotune(row_ptr, col_idx, offsets=None, path="auto", tile=0, blocks_per
     if offsets is not None:
         off, offp = _offsets(offsets)
         count = len(off) - 1
-    o = _opts(path, tile, "auto", -1, False, seed, keys, poll_rounds, launch, blocks_per_cu, dense_min)
+    o = _opts(path, tile, "auto", -1, False, seed, keys, poll_rounds, launch, blocks_per_cu, dense_min, key_rule)
     need = ctypes.c_size_t(0)
     _check(L.mis_autotune_bytes(ctypes.byref(csr), count, offp, ctypes.byref(o), ctypes.byref(need)))
     if workspace is None:
@@ -352,12 +364,34 @@ def mis_autotune(row_ptr, col_idx, offsets=None, path="auto", tile=0, blocks_per
                           ctypes.c_void_p(_stream(stream)), ctypes.byref(res), ctypes.byref(cached)))
     opts = dict(path=_PATH_NAMES[res.path], tile=res.tile, reorder=_REORDER_NAMES[res.reorder],
                 orient=res.orient, blocks_per_cu=res.blocks_per_cu, dense_min=res.dense_min, seed=seed,
-                keys=keys, poll_rounds=poll_rounds, launch=launch)
+                keys=keys, poll_rounds=poll_rounds, launch=launch, key_rule=key_rule)
     return opts, bool(cached.value)
 
 
 def mis_autotune_clear():
     lib().mis_autotune_clear()
+
+
+def mis_build_times(g: MisGraph) -> list:
+    """Build-stage durations in ms of a handle built with timing=True (see the header)."""
+    buf = (ctypes.c_float * 16)()
+    cnt = ctypes.c_int32(0)
+    _check(lib().mis_build_times(g.handle, buf, 16, ctypes.byref(cnt)))
+    return [float(buf[i]) for i in range(min(cnt.value, 16))]
+
+
+def mis_solve_noalloc(row_ptr, col_idx, out, stream=None, **opts):
+    """Build + solve with no allocation (the library's per-GPU array); out: cuda uint8[n].
+    Returns (rounds, set size)."""
+    n = row_ptr.numel() - 1
+    nnz = col_idx.numel()
+    csr = MisCsr(n, nnz, _ptr(row_ptr), _ptr(col_idx) if nnz else None)
+    o = _opts(**opts)
+    r = ctypes.c_int32(0)
+    k = ctypes.c_int64(0)
+    _check(lib().mis_solve_noalloc(ctypes.byref(csr), ctypes.byref(o), _ptr(out) if n else None, ctypes.byref(r),
+                                   ctypes.byref(k), ctypes.c_void_p(_stream(stream))))
+    return int(r.value), int(k.value)
 
 
 def mis_release_host_buffers() -> None:

@@ -57,11 +57,12 @@ def expected(rp, ci, keys, max_rounds=0):
     return (st == oracle.IN).astype(np.uint8), r, tr
 
 
-def run(rp, ci, cfg, seed=1, keys=None, max_rounds=0, validate=True, poll_rounds=0):
+def run(rp, ci, cfg, seed=1, keys=None, max_rounds=0, validate=True, poll_rounds=0, key_rule="degree"):
     T = tcmis_mod()
     drp, dci = to_dev(rp, ci)
     dkeys = None if keys is None else torch.from_numpy(keys.view(np.int64)).cuda()
-    h = T.mis_build_tiles(drp, dci, seed=seed, keys=dkeys, validate=validate, poll_rounds=poll_rounds, **kw(cfg))
+    h = T.mis_build_tiles(drp, dci, seed=seed, keys=dkeys, validate=validate, poll_rounds=poll_rounds,
+                          key_rule=key_rule, **kw(cfg))
     out, st = T.mis_solve(h, max_rounds=max_rounds)
     torch.cuda.synchronize()
     got = out.cpu().numpy()
@@ -69,10 +70,10 @@ def run(rp, ci, cfg, seed=1, keys=None, max_rounds=0, validate=True, poll_rounds
     return got, st
 
 
-def check(rp, ci, cfg, seed=1, keys=None, label=""):
-    k = oracle.keys(rp, seed) if keys is None else keys
+def check(rp, ci, cfg, seed=1, keys=None, label="", key_rule="degree"):
+    k = oracle.keys_rule(rp, seed, key_rule) if keys is None else keys
     want, rounds, trace = expected(rp, ci, k)
-    got, st = run(rp, ci, cfg, seed=seed, keys=keys)
+    got, st = run(rp, ci, cfg, seed=seed, keys=keys, key_rule=key_rule)
     print(f"case {label} cfg={cfg} n={len(rp) - 1} rounds={rounds}", flush=True)
     assert np.array_equal(got, want), f"{label} {cfg}: {int((got != want).sum())} vertices differ"
     assert st["rounds"] == rounds, f"{label} {cfg}: rounds {st['rounds']} != {rounds}"
@@ -167,6 +168,16 @@ def test_default_keys_given_by_caller(tile):
     # the hybrid path then compares gathered keys instead of degree classes and hashes
     for d in (-1, 1):
         check(g.row_ptr, g.col_idx, ("hybrid", 16, "none", 1, d), seed=9, keys=keys, label="rmat14-keys-hybrid")
+
+
+@pytest.mark.parametrize("rule", ["hash", "eq1"])
+@pytest.mark.parametrize("cfg", FAST_CONFIGS, ids=lambda c: "-".join(map(str, c)))
+def test_key_rules(rule, cfg):
+    # the priority heuristics of Section 3.3 computed on the device (H1: hash only;
+    # Eq. 1 discretised) give the oracle's set and trace under the same rule
+    for name in ("rmat14", "grid24"):
+        g = gen.workload(name, seed=2)
+        check(g.row_ptr, g.col_idx, cfg, seed=13, label=f"{name}-{rule}", key_rule=rule)
 
 
 def test_one_degree_class_key_order():
@@ -391,6 +402,25 @@ def test_batch_equals_each_graph_alone(cfg):
         assert rounds[i] == r and sizes[i] == int(want.sum()), f"graph {i}"
         worst = max(worst, r)
     assert st["rounds"] == worst and st["n_in"] == int(sizes.sum())
+
+
+@pytest.mark.parametrize("cfg", [("tile", 16, "key", 1), ("hybrid", 16, "none", 1, 1), ("csr", 0, "none", 0)],
+                         ids=lambda c: "-".join(map(str, c)))
+def test_batch_eq1_rule_uses_each_graphs_own_average(cfg):
+    # Eq. 1's average degree is each graph's own in a batch: graph g's keys are the
+    # oracle's keys of graph g alone
+    T = tcmis_mod()
+    graphs = [gen.make(*s) for s in gen.batch_spec(16, seed=9, n_min=50, n_max=5000)]
+    rp, ci, off = gen.union(graphs)
+    drp, dci = to_dev(rp, ci)
+    h = T.mis_build_batch(drp, dci, off, seed=4, key_rule="eq1", validate=True, **kw(cfg))
+    out, st, rounds, sizes = T.mis_solve_batch(h)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    T.mis_free_tiles(h)
+    for i, g in enumerate(graphs):
+        want, r, _ = expected(g.row_ptr, g.col_idx, oracle.keys_rule(g.row_ptr, 4, "eq1"))
+        assert np.array_equal(got[off[i]:off[i + 1]], want) and rounds[i] == r, f"graph {i}"
 
 
 def test_batch_rejects_cross_edges():
