@@ -1,21 +1,23 @@
-"""Benchmark: MIS Medges/s per graph on one MI355X, tile path vs CSR path.
+"""Benchmark: MIS Medges/s per graph on one MI355X, hybrid tile path vs CSR path.
 
 One step = one pass of the hot path on the R-MAT scale-22 graph (n = 4,194,304,
 |E| = 33,554,432, a,b,c,d = .57,.19,.19,.05, random relabelling) resident in HBM:
-priority keys, vertex reordering and tile construction (mis_build_tiles), then
-the rounds of candidate / int8-MFMA exclusion kernels until every vertex is
+priority keys, the orientation of every edge towards its higher-priority end, the
+dense 16-row blocks as bit tiles and the rest as entry lists (mis_build_tiles, hybrid
+path), then the rounds of candidate / exclusion kernels until every vertex is
 decided (mis_solve).  value = |E| (undirected, counted once) / step time.  The
-device workspace and the output vector are allocated once, before the timed
-steps, and passed to every build and solve (as a serving caller does).
+device workspace and the output vector are allocated once, before the timed steps,
+and passed to every build and solve (as a serving caller does).
 
-Also reported: solve-only throughput (structure built once), the scalar CSR path
-on the same graph, per-kernel HIP-event timings of the round kernels, the
-roofline of the dominant round kernel, and the CPU oracle timed on this host.
+Also reported: solve-only throughput (structure built once), the build's stages,
+the all-tile path (every edge in reordered bit tiles) and the scalar CSR path on the
+same graph, per-kernel HIP-event timings, the roofline of the step's dominant
+kernel, and the CPU oracle and sequential greedy timed on this host.
 
 "batch": 4,096 independent graphs (sizes log-uniform over 500..200,000 vertices,
-half Erdos-Renyi with average degree 4..32, half R-MAT with 8..24) solved as
-block-diagonal batches (mis_build_batch + mis_solve_batch) against one graph per
-build+solve; graphs/s, Medges/s and per-graph completion percentiles.
+half Erdos-Renyi with average degree 4..32, half R-MAT with 8..24) solved as one
+block-diagonal batch (mis_build_batch + mis_solve_batch) against one graph per
+build+solve; graphs/s and Medges/s.
 
 "serving": a pool of requests (log-uniform 1e3..4e6 vertices, Erdos-Renyi / R-MAT /
 3D grid) in pinned host memory; Poisson arrivals at 0.5, 0.8, 1.0 and 1.2 times
@@ -40,28 +42,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "tile_exclusion_rmat22_traffic.json")
-MFMA_RECORD = os.path.join(ROOT, "profiles", "tile_exclusion_rmat22_mfma.json")
 
 
-def measured_traffic(a):
-    """HBM bytes per launch of the tile exclusion kernel from the committed counter
-    record (rocprofv3 FETCH_SIZE / WRITE_SIZE, calibrated on a device copy), or None
-    when the configuration differs or the kernel sources changed since the counters
-    were taken."""
+def measured_traffic(a, kernel):
+    """HBM bytes per launch of `kernel` from its committed counter record
+    (profiles/<kernel>_<workload>_traffic.json: rocprofv3 FETCH_SIZE / WRITE_SIZE,
+    each scaled by the counter's reading for a copy of known size), or None when the
+    record is missing, was taken on another configuration, or the kernel sources
+    changed since the counters were taken."""
     import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{a.workload}_traffic.json")
     try:
-        rec = json.load(open(TRAFFIC_RECORD))
+        rec = json.load(open(path))
     except (OSError, ValueError):
         return None
-    if (rec.get("workload"), rec.get("tile"), rec.get("reorder"), rec.get("orient"), rec.get("seed")) != \
-            (a.workload, a.tile, a.reorder, a.orient, a.seed):
+    if (rec.get("workload"), rec.get("seed"), rec.get("dense_min")) != (a.workload, a.seed, a.dense_min):
         return None
     for name, digest in rec.get("source_sha256", {}).items():
-        path = os.path.join(ROOT, "paper_2605_29604_amd", "csrc", name)
-        if not os.path.exists(path) or hashlib.sha256(open(path, "rb").read()).hexdigest() != digest:
+        src = os.path.join(ROOT, "paper_2605_29604_amd", "csrc", name)
+        if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != digest:
             return None
-    return rec["traffic_bytes_per_launch"]
+    return int(rec["traffic_bytes_per_launch"])
 
 
 def stored_quality(a):
@@ -74,45 +75,6 @@ def stored_quality(a):
     return json.load(open(path))
 
 
-def measured_stalls(a):
-    """Wait share of the tile exclusion kernel's waves and busy share of its address units
-    from the committed counter record, or None when the configuration differs or the
-    kernel sources changed since the counters were taken."""
-    import hashlib
-    try:
-        rec = json.load(open(os.path.join(ROOT, "profiles", "tile_exclusion_rmat22_stalls.json")))
-    except (OSError, ValueError):
-        return None
-    if (rec.get("workload"), rec.get("tile"), rec.get("reorder"), rec.get("orient"), rec.get("seed")) != \
-            (a.workload, a.tile, a.reorder, a.orient, a.seed):
-        return None
-    for name, digest in rec.get("source_sha256", {}).items():
-        path = os.path.join(ROOT, "paper_2605_29604_amd", "csrc", name)
-        if not os.path.exists(path) or hashlib.sha256(open(path, "rb").read()).hexdigest() != digest:
-            return None
-    return {"wait_share": round(rec["wait_share"], 4), "ta_busy_share": round(rec["ta_busy_share"], 4)}
-
-
-def measured_mfma(a):
-    """int8 matrix-core use of the tile exclusion kernel from the committed counter
-    record (rocprofv3 MFMA counters), or None when the configuration differs or the
-    kernel sources changed since the counters were taken."""
-    import hashlib
-    try:
-        rec = json.load(open(MFMA_RECORD))
-    except (OSError, ValueError):
-        return None
-    if (rec.get("workload"), rec.get("tile"), rec.get("reorder"), rec.get("orient"), rec.get("seed")) != \
-            (a.workload, a.tile, a.reorder, a.orient, a.seed):
-        return None
-    for name, digest in rec.get("source_sha256", {}).items():
-        path = os.path.join(ROOT, "paper_2605_29604_amd", "csrc", name)
-        if not os.path.exists(path) or hashlib.sha256(open(path, "rb").read()).hexdigest() != digest:
-            return None
-    return {"achieved": round(rec["int8_tops"], 2), "peak": rec["int8_peak_tops"], "unit": "TOPS (int8)",
-            "frac": round(rec["frac_of_peak"], 4), "busy": round(rec["mfma_util"], 4)}
-
-
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -123,7 +85,7 @@ def parse():
     p.add_argument("--tile", type=int, default=16)
     p.add_argument("--reorder", default="key")
     p.add_argument("--orient", type=int, default=1)
-    p.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU oracle sample")
+    p.add_argument("--dense-min", type=int, default=0, help="hybrid path's dense-block threshold (0 = default)")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-batch", action="store_true")
     p.add_argument("--no-serve", action="store_true")
@@ -180,58 +142,51 @@ def bench_tune(a, torch, gen, tcmis, rp, ci):
 
 
 def bench_batch(a, torch, gen, tcmis):
-    """Block-diagonal batches vs one graph per build+solve on the 4,096-graph mix."""
+    """The 4,096-graph mix as one block-diagonal hybrid batch (64-bit entry offsets: one
+    handle, every round kernel covering all graphs) vs one graph per build + solve.
+    The step (build + solve) is timed with direct launches; solve-only is timed again
+    with the round loop replayed as a captured hipGraph (the handle's second solve on)."""
     t0 = time.perf_counter()
     spec = gen.batch_spec(a.batch_graphs, seed=1)
     rp_h, ci_h, off = gen.batch_union(spec)
     log(f"batch: {len(spec)} graphs, n={off[-1]} nnz={ci_h.size} generated in {time.perf_counter() - t0:.1f}s")
-    cfg = dict(path="tile", tile=a.tile, reorder=a.reorder, orient=a.orient, seed=a.seed)
-    # handles index entries with 32-bit offsets: split into consecutive sub-batches of < 2^31 entries
-    limit = (1 << 31) - 1
-    groups, start = [], 0
-    for g in range(1, len(spec) + 1):
-        if rp_h[off[g]] - rp_h[off[start]] > limit:
-            groups.append((start, g - 1))
-            start = g - 1
-    groups.append((start, len(spec)))
-    subs = []
-    for (ga, gb) in groups:
-        va, vb = int(off[ga]), int(off[gb])
-        ea, eb = int(rp_h[va]), int(rp_h[vb])
-        rp = torch.from_numpy(rp_h[va:vb + 1] - ea).cuda()
-        ci = torch.from_numpy(ci_h[ea:eb]).cuda()
-        ci -= va
-        subs.append((rp, ci, off[ga:gb + 1] - va))
-    ws_bytes = max(tcmis.mis_build_batch_bytes(s[0].numel() - 1, s[1].numel(), s[2], **cfg) for s in subs)
-    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
-    outs = [torch.empty(s[0].numel() - 1, dtype=torch.uint8, device="cuda") for s in subs]
+    cfg = dict(path="hybrid", dense_min=a.dense_min, seed=a.seed)
+    rp = torch.from_numpy(rp_h).cuda()
+    ci = torch.from_numpy(ci_h).cuda()
+    ws = torch.empty(tcmis.mis_build_batch_bytes(rp.numel() - 1, ci.numel(), off, **cfg), dtype=torch.uint8,
+                     device="cuda")
+    out = torch.empty(rp.numel() - 1, dtype=torch.uint8, device="cuda")
 
     def batched():
-        done_t, rounds = [], []
         t = time.perf_counter()
-        for (rp, ci, o), out in zip(subs, outs):
-            h = tcmis.mis_build_batch(rp, ci, o, workspace=ws, **cfg)
-            _, st, r, _ = tcmis.mis_solve_batch(h, out=out, trace_cap=0)
-            tcmis.mis_free_tiles(h)
-            done_t += [time.perf_counter() - t] * (len(o) - 1)
-            rounds.append(int(st["rounds"]))
-        return time.perf_counter() - t, done_t, rounds
+        h = tcmis.mis_build_batch(rp, ci, off, workspace=ws, launch="direct", **cfg)
+        _, st, r, _ = tcmis.mis_solve_batch(h, out=out, trace_cap=0)
+        tcmis.mis_free_tiles(h)
+        return time.perf_counter() - t, int(st["rounds"]), r
 
     batched()
     torch.cuda.synchronize()
     reps = [batched() for _ in range(3)]
-    b_s = float(np.mean([r[0] for r in reps]))
-    b_done = reps[-1][1]
+    b_s = float(np.median([r[0] for r in reps]))
+    g_rounds = reps[-1][2]
+    # solve only, the round loop captured once and replayed
+    h = tcmis.mis_build_batch(rp, ci, off, workspace=ws, launch="graph", **cfg)
+    tcmis.mis_solve_batch(h, out=out, trace_cap=0)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(3):
+        t = time.perf_counter()
+        _, st_g, _, _ = tcmis.mis_solve_batch(h, out=out, trace_cap=0)
+        ts.append(time.perf_counter() - t)
+    g_solve_s = float(np.median(ts))
+    graph_flag = st_g["graph"]
+    tcmis.mis_free_tiles(h)
     # one graph per build + solve, on per-graph device copies of the same CSR
-    singles, where = [], []
-    for si, (ga, gb) in enumerate(groups):
-        for g in range(ga, gb):
-            va, vb = int(off[g]), int(off[g + 1])
-            ea, eb = int(rp_h[va]), int(rp_h[vb])
-            base_v, base_e = int(off[ga]), int(rp_h[off[ga]])
-            rp_s, ci_s = subs[si][0], subs[si][1]
-            singles.append((rp_s[va - base_v:vb - base_v + 1] - (ea - base_e), ci_s[ea - base_e:eb - base_e] - (va - base_v)))
-            where.append((si, va - base_v, vb - base_v))
+    singles = []
+    for gi in range(len(spec)):
+        va, vb = int(off[gi]), int(off[gi + 1])
+        ea, eb = int(rp_h[va]), int(rp_h[vb])
+        singles.append((rp[va:vb + 1] - ea, ci[ea:eb] - va))
     torch.cuda.synchronize()
     one_ws = torch.empty(max(tcmis.mis_build_bytes(r.numel() - 1, c.numel(), **cfg) for r, c in singles),
                          dtype=torch.uint8, device="cuda")
@@ -240,37 +195,40 @@ def bench_batch(a, torch, gen, tcmis):
     def one_by_one(k):
         done_t = []
         t = time.perf_counter()
-        for rp, ci in singles[:k]:
-            h = tcmis.mis_build_tiles(rp, ci, workspace=one_ws, **cfg)
-            tcmis.mis_solve(h, out=one_out[: rp.numel() - 1], trace_cap=0)
-            tcmis.mis_free_tiles(h)
+        for rps, cis in singles[:k]:
+            hh = tcmis.mis_build_tiles(rps, cis, workspace=one_ws, **cfg)
+            tcmis.mis_solve(hh, out=one_out[: rps.numel() - 1], trace_cap=0)
+            tcmis.mis_free_tiles(hh)
             done_t.append(time.perf_counter() - t)
         return time.perf_counter() - t, done_t
 
     one_by_one(64)
     torch.cuda.synchronize()
     o_s, o_done = one_by_one(len(singles))
-    # spot parity: graphs solved in the batch equal the same graphs solved alone
+    # every 16th graph of the batch equals the same graph solved alone
     same = True
-    for gi in range(0, len(singles), max(1, len(singles) // 16)):
-        rp, ci = singles[gi]
-        h = tcmis.mis_build_tiles(rp, ci, workspace=one_ws, **cfg)
-        alone, _ = tcmis.mis_solve(h, out=one_out[: rp.numel() - 1], trace_cap=0)
-        tcmis.mis_free_tiles(h)
-        si, a0, a1 = where[gi]
-        same &= bool(torch.equal(alone, outs[si][a0:a1]))
+    for gi in range(0, len(singles), 16):
+        rps, cis = singles[gi]
+        hh = tcmis.mis_build_tiles(rps, cis, workspace=one_ws, **cfg)
+        alone, _ = tcmis.mis_solve(hh, out=one_out[: rps.numel() - 1], trace_cap=0)
+        tcmis.mis_free_tiles(hh)
+        same &= bool(torch.equal(alone, out[int(off[gi]):int(off[gi + 1])]))
     edges = int(ci_h.size) // 2
-    res = {"graphs": len(spec), "vertices": int(off[-1]), "edges": edges, "launch_groups": len(subs),
-           "config": f"tile {a.tile}, reorder {a.reorder}, orient {a.orient}",
+    res = {"graphs": len(spec), "vertices": int(off[-1]), "edges": edges, "handles": 1,
+           "config": f"hybrid, dense_min {a.dense_min}",
            "batched": {"s": round(b_s, 4), "graphs_s": round(len(spec) / b_s, 1),
-                       "medges_s": round(edges / b_s / 1e6, 1), "rounds": reps[-1][2],
-                       "p50_ms": pct(np.array(b_done) * 1e3, 50), "p99_ms": pct(np.array(b_done) * 1e3, 99)},
+                       "medges_s": round(edges / b_s / 1e6, 1), "rounds": reps[-1][1],
+                       "graph_rounds_p50": pct(g_rounds, 50), "graph_rounds_max": int(np.max(g_rounds)),
+                       "latency_ms": round(b_s * 1e3, 3),
+                       "note": "one launch group: every graph finishes with the batch"},
+           "batched_solve_graph_replay": {"s": round(g_solve_s, 4), "graph_flag": graph_flag,
+                                          "medges_s": round(edges / g_solve_s / 1e6, 1)},
            "one_graph_per_launch": {"s": round(o_s, 4), "graphs_s": round(len(singles) / o_s, 1),
                                     "medges_s": round(edges / o_s / 1e6, 1),
                                     "p50_ms": pct(np.array(o_done) * 1e3, 50),
                                     "p99_ms": pct(np.array(o_done) * 1e3, 99)},
            "speedup": round(o_s / b_s, 2), "batch_equals_alone_sampled": same}
-    del subs, outs, ws, singles, one_ws, one_out
+    del singles, one_ws, one_out, ws, out, rp, ci
     torch.cuda.empty_cache()
     return res
 
@@ -357,6 +315,34 @@ def bench_serve(a, torch, gen, tcmis):
             "mix_equals_alone": mism == 0, "latency": "arrival to result in pinned host memory"}
 
 
+def orient_alg_bytes(n, nnz, kept):
+    """Algorithmic bytes of one orientation pass: every adjacency index read (4 B) with
+    its neighbour's one-byte degree class, every row start (8 B) and row key (8 B)
+    read once, the higher-priority entries written (4 B each) and every row's count
+    written (4 B)."""
+    return 5 * nnz + 4 * kept + 20 * n + 8
+
+
+def cpu_leg(fn, reps=3):
+    """Median of `reps` timings of fn() (seconds) on this host's cores."""
+    ts = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t)
+    return float(np.median(ts))
+
+
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -372,12 +358,12 @@ def main():
     t0 = time.perf_counter()
     g = gen.workload(a.workload, seed=1)
     gen_s = time.perf_counter() - t0
-    print(f"# workload {a.workload}: n={g.n} |E|={g.m} generated in {gen_s:.1f}s", file=sys.stderr, flush=True)
+    log(f"workload {a.workload}: n={g.n} |E|={g.m} generated in {gen_s:.1f}s")
     rp = torch.from_numpy(g.row_ptr).to(dev)
     ci = torch.from_numpy(g.col_idx).to(dev)
     torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
 
+    hyb_cfg = dict(path="hybrid", dense_min=a.dense_min, seed=a.seed)
     tile_cfg = dict(path="tile", tile=a.tile, reorder=a.reorder, orient=a.orient, seed=a.seed)
     csr_cfg = dict(path="csr", seed=a.seed)
 
@@ -418,15 +404,34 @@ def main():
         tcmis.mis_free_tiles(h)
         return dt, out, st, stt, nbytes
 
-    # ---- tile path: end-to-end step (timed region = K steps) and solve-only
-    step_s, out_tile, st_tile = time_steps(tile_cfg, a.steps, a.warmup)
-    solve_s, out2, st2, stt, tile_mem = time_solve(tile_cfg, max(a.steps, 10), a.warmup)
-    # ---- CSR path
-    csr_step_s, out_csr, st_csr = time_steps(csr_cfg, a.steps, a.warmup)
-    csr_solve_s, _, _, sttc, _ = time_solve(csr_cfg, max(a.steps, 10), a.warmup)
+    def build_stages(cfg, reps):
+        # per-stage HIP-event durations of the build (same stream as its kernels)
+        ws = torch.empty(tcmis.mis_build_bytes(g.n, int(ci.numel()), **cfg), dtype=torch.uint8, device=dev)
+        acc = None
+        for _ in range(reps + 1):
+            h = tcmis.mis_build_tiles(rp, ci, workspace=ws, timing=True, **cfg)
+            ms = tcmis.mis_build_times(h)
+            tcmis.mis_free_tiles(h)
+            if acc is None:
+                acc = [0.0] * len(ms)   # the first build warms up and is not counted
+                continue
+            acc = [x + y for x, y in zip(acc, ms)]
+        return [x / reps for x in acc]
 
-    same = bool(torch.equal(out_tile, out_csr) and torch.equal(out_tile, out2))
+    # ---- the hybrid path (headline): end-to-end steps (timed region = K steps), solve only
+    step_s, out_h, st_h = time_steps(hyb_cfg, a.steps, a.warmup)
+    solve_s, out_h2, st_h2, stt_h, hyb_mem = time_solve(hyb_cfg, max(a.steps, 10), a.warmup)
+    stages = build_stages(hyb_cfg, 5)
+    # ---- every edge in bit tiles (the reordered all-tile path)
+    t_step_s, out_t, st_t = time_steps(tile_cfg, a.steps, a.warmup)
+    t_solve_s, _, _, stt_t, tile_mem = time_solve(tile_cfg, max(a.steps, 10), a.warmup)
+    # ---- the scalar CSR path
+    csr_step_s, out_csr, st_csr = time_steps(csr_cfg, a.steps, a.warmup)
+    csr_solve_s, _, _, stt_c, _ = time_solve(csr_cfg, max(a.steps, 10), a.warmup)
+
+    same = bool(torch.equal(out_h, out_csr) and torch.equal(out_h, out_t) and torch.equal(out_h, out_h2))
     m = g.m
+    hyb_names = ["keys", "orientation row search", "orientation", "dense blocks", "classes and lists"]
     res = {
         "metric": "MIS Medges/s per graph at 1 GPU (tile vs CSR); batched graphs/s + p50/p99",
         "value": round(m / step_s / 1e6, 3),
@@ -442,20 +447,29 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{a.workload} R-MAT scale 22, avg degree 16, random relabelling"
                    if a.workload == "rmat22" else a.workload,
-                   "n": g.n, "edges": m, "path": "tile", "tile": a.tile, "reorder": a.reorder,
-                   "orient": a.orient, "step": "build tiles + solve, CSR resident in HBM"},
-        "tile": {"step_ms": round(step_s * 1e3, 4), "solve_ms": round(solve_s * 1e3, 4),
-                 "solve_medges_s": round(m / solve_s / 1e6, 3), "build_ms": round((step_s - solve_s) * 1e3, 4),
-                 "rounds": st_tile["rounds"], "tiles": st_tile["tiles"], "tile_bytes": st_tile["tile_bytes"],
-                 "density_nnz_per_tile": round((g.nnz / (2 if a.orient else 1)) / max(1, st_tile["tiles"]), 3),
-                 "device_bytes": tile_mem, "kernel_ms": [round(x, 4) for x in stt["kernel_ms"]],
-                 "units": stt["units"], "alg_bytes": stt["alg_bytes"]},
+                   "n": g.n, "edges": m, "path": "hybrid", "tile": 16, "dense_min": a.dense_min,
+                   "step": "keys + orientation + dense-block tiles + lists, then the rounds; CSR resident in HBM"},
+        "hybrid": {"step_ms": round(step_s * 1e3, 4), "solve_ms": round(solve_s * 1e3, 4),
+                   "solve_medges_s": round(m / solve_s / 1e6, 3),
+                   "build_ms": round((step_s - solve_s) * 1e3, 4),
+                   "build_stages_ms": {k: round(v, 4) for k, v in zip(hyb_names, stages[: len(hyb_names)])},
+                   "rounds": st_h["rounds"], "dense_tiles": st_h["tiles"], "device_bytes": hyb_mem,
+                   "kernel_ms": [round(x, 4) for x in stt_h["kernel_ms"]], "units": stt_h["units"],
+                   "alg_bytes": stt_h["alg_bytes"]},
+        "tile": {"step_ms": round(t_step_s * 1e3, 4), "solve_ms": round(t_solve_s * 1e3, 4),
+                 "solve_medges_s": round(m / t_solve_s / 1e6, 3), "build_ms": round((t_step_s - t_solve_s) * 1e3, 4),
+                 "config": f"tile {a.tile}, reorder {a.reorder}, orient {a.orient}",
+                 "rounds": st_t["rounds"], "tiles": st_t["tiles"], "tile_bytes": st_t["tile_bytes"],
+                 "density_nnz_per_tile": round((g.nnz / (2 if a.orient else 1)) / max(1, st_t["tiles"]), 3),
+                 "device_bytes": tile_mem, "kernel_ms": [round(x, 4) for x in stt_t["kernel_ms"]],
+                 "units": stt_t["units"], "alg_bytes": stt_t["alg_bytes"]},
         "csr": {"step_ms": round(csr_step_s * 1e3, 4), "step_medges_s": round(m / csr_step_s / 1e6, 3),
                 "solve_ms": round(csr_solve_s * 1e3, 4), "solve_medges_s": round(m / csr_solve_s / 1e6, 3),
-                "kernel_ms": [round(x, 4) for x in sttc["kernel_ms"]], "units": sttc["units"],
-                "alg_bytes": sttc["alg_bytes"]},
-        "mis_size": int(st_tile["n_in"]),
-        "tile_equals_csr": same,
+                "kernel_ms": [round(x, 4) for x in stt_c["kernel_ms"]], "units": stt_c["units"],
+                "alg_bytes": stt_c["alg_bytes"]},
+        "speedup_vs_csr_step": round(csr_step_s / step_s, 3),
+        "mis_size": int(st_h["n_in"]),
+        "paths_agree": same,
     }
     q = stored_quality(a)
     if q is not None:   # set size against the sequential min-degree greedy heuristic
@@ -463,29 +477,34 @@ def main():
                           "ratio_to_mindeg_greedy": round(res["mis_size"] / q["mindeg_greedy_size"], 5),
                           "equals_key_greedy": res["mis_size"] == q["key_greedy_size"],
                           "source": "tests/golden/rmat22_quality.json"}
-    # roofline of the dominant round kernel (HIP events on the solve stream)
-    names = ["tile_candidate", "tile_exclusion_mfma", "tile_finalize"]
-    k = int(np.argmax(stt["kernel_ms"]))
-    launches = max(1, stt["launches"])
-    u = stt["units"]
-    S = a.tile * a.tile // 8
-    bytes_k = [u[0] * 4 + u[1], u[2] * 4 + u[3] * S, u[4] * 24 + u[5] * 8][k]
-    avg_ms = stt["kernel_ms"][k] / launches
-    achieved = (bytes_k / launches) / (avg_ms * 1e-3) / 1e9
-    traffic = measured_traffic(a) if k == 1 else None
-    res["roofline"] = {"kernel": names[k], "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+    # roofline of the step's dominant kernel, from HIP events on the stream it runs on:
+    # the orientation pass (build) or one of the two round kernels (solve)
+    u = stt_h["units"]
+    launches = max(1, stt_h["launches"])
+    kept = g.nnz // 2
+    cands = {
+        "hybrid_orientation": (stages[2], 1, orient_alg_bytes(g.n, g.nnz, kept)),
+        "hybrid_candidate": (stt_h["kernel_ms"][0], launches, u[0] * 8 + u[1] * 16 + u[4] * 36 + u[6] * 24),
+        "hybrid_exclusion": (stt_h["kernel_ms"][1], launches, u[2] * 8 + u[3] * 16 + u[5] * 36 + u[7] * 24),
+    }
+    name = max(cands, key=lambda k: cands[k][0] / cands[k][1])
+    tot_ms, nl, nbytes = cands[name]
+    avg_ms = tot_ms / nl
+    achieved = (nbytes / nl) / (avg_ms * 1e-3) / 1e9
+    res["roofline"] = {"kernel": name, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                       "traffic": None if traffic is None else int(traffic),
-                       "avg_launch_us": round(avg_ms * 1e3, 3), "launches": launches,
-                       "alg_bytes_per_launch": int(bytes_k / launches),
-                       "mfma": measured_mfma(a) if k == 1 else None,
-                       "stalls": measured_stalls(a) if k == 1 else None}
+                       "traffic": measured_traffic(a, name),
+                       "avg_launch_us": round(avg_ms * 1e3, 3), "launches": nl,
+                       "alg_bytes_per_launch": int(nbytes / nl),
+                       "others": {k: {"avg_launch_us": round(v[0] / v[1] * 1e3, 3),
+                                      "achieved": round((v[2] / v[1]) / (v[0] / v[1] * 1e-3) / 1e9, 2)
+                                      if v[0] > 0 else None} for k, v in cands.items() if k != name}}
 
     # round-loop launch modes of the same solve (identical results)
     modes = {}
     for launch in ("direct", "graph", "persistent"):
-        lt, lo, lst, _, _ = time_solve(dict(tile_cfg, launch=launch), max(a.steps, 10), a.warmup)
-        modes[launch] = {"solve_ms": round(lt * 1e3, 4), "same_set": bool(torch.equal(lo, out_tile)),
+        lt, lo, lst, _, _ = time_solve(dict(hyb_cfg, launch=launch), max(a.steps, 10), a.warmup)
+        modes[launch] = {"solve_ms": round(lt * 1e3, 4), "same_set": bool(torch.equal(lo, out_h)),
                          "graph_flag": lst["graph"]}
     res["launch_modes"] = modes
     if not a.no_tune:
@@ -499,19 +518,26 @@ def main():
     if not a.no_cpu:
         import oracle
         key = oracle.keys(g.row_ptr, a.seed)
-        runs, t = 0, time.perf_counter()
-        while True:
-            st_o, r_o, tr_o = oracle.roundsync(g.row_ptr, g.col_idx, key)
-            runs += 1
-            if time.perf_counter() - t >= a.cpu_seconds or runs >= 20:
-                break
-        cpu_s = (time.perf_counter() - t) / runs
-        want = (st_o == oracle.IN).astype(np.uint8)
-        res["parity_vs_oracle"] = bool(np.array_equal(out_tile.cpu().numpy(), want))
-        res["cpu_baseline"] = {"value": round(m / cpu_s / 1e6, 3), "unit": "Medges/s", "cores": 1,
+        holder = {}
+
+        def rs():
+            holder["rs"] = oracle.roundsync(g.row_ptr, g.col_idx, key)
+
+        def gr():
+            holder["gr"] = oracle.greedy(g.row_ptr, g.col_idx, key)
+
+        rs_s = cpu_leg(rs)
+        gr_s = cpu_leg(gr)
+        want = (holder["rs"][0] == oracle.IN).astype(np.uint8)
+        res["parity_vs_oracle"] = bool(np.array_equal(out_h.cpu().numpy(), want))
+        res["cpu_baseline"] = {"value": round(m / rs_s / 1e6, 3), "unit": "Medges/s", "cores": 1,
                                "kind": "oracle",
-                               "sample": f"{runs} full round-synchronous oracle solves of {a.workload} "
-                                         f"(keys precomputed), {cpu_s:.3f}s each, single thread"}
+                               "sample": f"the round-synchronous oracle on the whole {a.workload} graph (keys "
+                                         f"precomputed), median of 3 runs of {rs_s:.3f}s, one thread",
+                               "host_cores": len(os.sched_getaffinity(0)), "cpu_model": cpu_model(),
+                               "sequential_greedy": {"value": round(m / gr_s / 1e6, 3), "unit": "Medges/s",
+                                                     "seconds": round(gr_s, 4), "cores": 1,
+                                                     "same_set": bool(np.array_equal(holder["gr"], want))}}
     print(json.dumps(res))
 
 

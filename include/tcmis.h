@@ -93,7 +93,8 @@ enum {
 /* Input graph: undirected, simple, symmetric CSR, rows sorted ascending. */
 typedef struct {
     int64_t n;                /* vertices, 0 <= n < 2^31 */
-    int64_t nnz;              /* directed entries = 2 |E| = row_ptr[n] */
+    int64_t nnz;              /* directed entries = 2 |E| = row_ptr[n]; < 2^31 on the tile and CSR
+                                 paths, < 2^40 on the hybrid path */
     const int64_t* row_ptr;   /* DEVICE int64[n+1] */
     const int32_t* col_idx;   /* DEVICE int32[nnz] */
 } mis_csr;
@@ -140,17 +141,23 @@ typedef struct {
     int64_t tiles;            /* nonzero tiles (0 on the CSR path) */
     int64_t tile_bytes;       /* bytes of the tile stream: tiles * (T*T/8 bitmap + 4 index) */
     int64_t alg_bytes;        /* algorithmic bytes: sum over rounds of units[k] * bytes per unit */
-    int64_t units[6];         /* work units summed over rounds.  CSR path: adjacency entries read
+    int64_t units[8];         /* work units summed over rounds.  CSR path: adjacency entries read
                                  by the candidate kernel (12 B each: index + neighbour key),
                                  vertices it examined (28 B), entries read by the exclusion
                                  kernel (8 B: index + neighbour state), vertices it examined
-                                 (24 B), units[4] = units[5] = 0.  Tile path: 4-byte index and
+                                 (24 B), units[4..7] = 0.  Tile path: 4-byte index and
                                  row-mask words the candidate kernel read (4 B), bytes of
                                  bitmaps and neighbour keys it read (1 B), 4-byte words the
                                  exclusion kernel read (4 B), tiles it multiplied on the matrix
                                  cores (T*T/8 B), row-blocks the finalize kernel updated (24 B:
                                  three row masks read and written), chunk list entries it
-                                 wrote (8 B). */
+                                 wrote (8 B), units[6..7] = 0.  Hybrid path: entries the
+                                 candidate kernel read (8 B: index + the bitmap word it
+                                 selects), rows it examined (16 B: list slot, row start, count),
+                                 the same two for the exclusion kernel, tiles multiplied on the
+                                 matrix cores by the candidate and by the exclusion kernel
+                                 (36 B: bitmap + column block), dense row-blocks each examined
+                                 (24 B: list slot, block slot, tile range, two bitmap words). */
     float kernel_ms[3];       /* timing = 1: total ms of the candidate / exclusion / finalize
                                  kernels (the CSR path has no finalize kernel) */
     int32_t launches;         /* timing = 1: rounds enqueued (each launches every kernel once) */

@@ -127,7 +127,7 @@ int resolve(const mis_csr* csr, const mis_build_opts* opts, mis_build_opts* o, i
             const int64_t* offsets = nullptr) {
     if (!csr) return fail(MIS_EINVAL, "csr is null");
     if (csr->n < 0 || csr->n >= (1ll << 31)) return fail(MIS_EINVAL, "n must be in [0, 2^31)");
-    if (csr->nnz < 0 || csr->nnz >= (1ll << 31)) return fail(MIS_EINVAL, "nnz must be in [0, 2^31)");
+    if (csr->nnz < 0 || csr->nnz >= (1ll << 40)) return fail(MIS_EINVAL, "nnz must be in [0, 2^40)");
     if (!csr->row_ptr) return fail(MIS_EINVAL, "row_ptr is null");
     if (csr->nnz > 0 && !csr->col_idx) return fail(MIS_EINVAL, "col_idx is null");
     if (opts) *o = *opts; else mis_default_opts(o);
@@ -154,6 +154,10 @@ int resolve(const mis_csr* csr, const mis_build_opts* opts, mis_build_opts* o, i
         return fail(MIS_EINVAL, "the default key rule needs n <= 2^24; pass keys");
     }
     if (o->path == MIS_PATH_AUTO) o->path = MIS_PATH_HYBRID;
+    // the tile and CSR paths index adjacency entries with 32-bit offsets; the hybrid
+    // path's entry offsets are 64-bit (the caller's row pointer)
+    if (o->path != MIS_PATH_HYBRID && csr->nnz >= (1ll << 31))
+        return fail(MIS_EINVAL, "the tile and CSR paths need nnz < 2^31 (the hybrid path takes more)");
     if (o->path == MIS_PATH_HYBRID) {
         if (o->tile != 0 && o->tile != 16) return fail(MIS_EINVAL, "the hybrid path uses 16 x 16 tiles");
         if (o->reorder != MIS_REORDER_AUTO && o->reorder != MIS_REORDER_NONE)
@@ -296,20 +300,20 @@ bool ensure_graph(mis_graph* g) {
 // bytes the kernels must move per work unit (see TraceRec::u)
 int64_t unit_bytes(const mis_graph* g, int k) {
     if (g->path == MIS_PATH_CSR) {
-        static const int64_t b[kUnits] = {12, 28, 8, 24, 0, 0};
+        static const int64_t b[kUnits] = {12, 28, 8, 24, 0, 0, 0, 0};
         return b[k];
     }
     if (g->path == MIS_PATH_HYBRID) {
         // entries read (4-byte index + the bitmap word it selects), rows examined (list
         // slot, row start, entry count), tiles multiplied (bitmap + column block),
         // dense blocks examined (list slot, block slot, tile range, its two bitmap words)
-        static const int64_t b[kUnits] = {8, 16, 8, 16, 36, 24};
+        static const int64_t b[kUnits] = {8, 16, 8, 16, 36, 36, 24, 24};
         return b[k];
     }
     // tile path: 4-byte words, bytes, 4-byte words, bitmaps multiplied, row-blocks
     // finalized (alive, blocked, hit read and written), chunk entries written
     const int64_t S = (int64_t)g->tile * g->tile / 8;
-    static const int64_t b[kUnits] = {4, 1, 4, 0, 24, 8};
+    static const int64_t b[kUnits] = {4, 1, 4, 0, 24, 8, 0, 0};
     return k == 3 ? S : b[k];
 }
 
@@ -517,7 +521,7 @@ int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, mis_stats* st, 
     }
     double kms[3] = {0.0, 0.0, 0.0};
     int64_t launches = 0;
-    int64_t units[kUnits] = {0, 0, 0, 0, 0, 0};
+    int64_t units[kUnits] = {};
     int64_t enq = 0, drained = 0;
     int rc = MIS_OK;
     if (g->n > 0) {

@@ -10,7 +10,7 @@ namespace tcmis {
 
 constexpr int kLightDeg = 32;       // CSR path: thread per vertex up to this degree, wave above
 constexpr int kTraceCap = 4096;     // device trace ring (rounds); the host drains it at every poll
-constexpr int kUnits = 6;           // work-unit counters per round (TraceRec::u)
+constexpr int kUnits = 8;           // work-unit counters per round (TraceRec::u)
 constexpr int kStripes = 32;        // round counters are spread over this many cache lines
 constexpr int kStripeWords = 16;    // int64 words per stripe (one 128-byte line)
 constexpr int kDenseMinDefault = 9; // hybrid: a 36-byte 16x16 tile costs no more than 9 entry indices
@@ -46,13 +46,16 @@ constexpr uint64_t kChunkHole = ~0ull;
 
 // Per-round trace record in the device ring.
 //   c, x, alive : |C_r|, vertices removed as neighbours of candidates, undecided after r
-//   u[0..5]     : work units.  CSR path: adjacency entries read by the candidate
+//   u[0..7]     : work units.  CSR path: adjacency entries read by the candidate
 //                 kernel, vertices it examined, entries read by the exclusion kernel,
-//                 vertices it examined (u4 = u5 = 0).  Tile path: 4-byte index and
+//                 vertices it examined (u4..u7 = 0).  Tile path: 4-byte index and
 //                 mask words the candidate kernel read, bytes of bitmaps and keys it
 //                 read, 4-byte words the exclusion kernel read, tiles it multiplied on
 //                 the matrix cores, row-blocks the finalize kernel updated, chunk list
-//                 entries it wrote.
+//                 entries it wrote (u6 = u7 = 0).  Hybrid path: entries read and rows
+//                 examined by the candidate kernel, the same for the exclusion kernel,
+//                 tiles multiplied by the candidate and by the exclusion kernel, dense
+//                 row-blocks examined by each.
 struct TraceRec {
     int64_t c, x, alive, round;
     int64_t u[kUnits];

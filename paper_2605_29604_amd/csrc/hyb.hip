@@ -581,7 +581,7 @@ __device__ void hyb_p1(const HybArgs& a, int r) {
         }
     }
     int64_t x[5] = {n_cand, ent, verts, mult, blocks};
-    block_count(a.stripes, r, {0, 2, 3, 6, 7}, x);
+    block_count(a.stripes, r, {0, 2, 3, 6, 8}, x);
 }
 
 // Phases 2 and 3 of round r: retire candidates, remove their neighbours, list the rest.
@@ -678,7 +678,7 @@ __device__ void hyb_p2(const HybArgs& a, int r) {
     }
     lbuf_flush(lbuf[wid][2], pend[2], next[2], cnt[2]);
     int64_t x[5] = {n_out, ent, verts, mult, blocks};
-    block_count(a.stripes, r, {1, 4, 5, 6, 7}, x);
+    block_count(a.stripes, r, {1, 4, 5, 7, 9}, x);
 }
 
 __global__ void __launch_bounds__(kBlock) k_hyb_p1(HybArgs a, int ri) { hyb_p1(a, a.ctrl->rbase + ri); }

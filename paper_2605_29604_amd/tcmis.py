@@ -52,7 +52,7 @@ class MisStats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int32), ("path", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("reorder", ctypes.c_int32), ("orient", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("n_in", ctypes.c_int64), ("tiles", ctypes.c_int64), ("tile_bytes", ctypes.c_int64),
-                ("alg_bytes", ctypes.c_int64), ("units", ctypes.c_int64 * 6),
+                ("alg_bytes", ctypes.c_int64), ("units", ctypes.c_int64 * 8),
                 ("kernel_ms", ctypes.c_float * 3), ("launches", ctypes.c_int32),
                 ("trace_cap", ctypes.c_int32), ("graph", ctypes.c_int32), ("pad3_", ctypes.c_int32),
                 ("trace", ctypes.POINTER(ctypes.c_int64))]

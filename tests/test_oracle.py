@@ -372,3 +372,25 @@ def test_stored_quality_record_matches_the_oracle():
     kg = oracle.greedy(g.row_ptr, g.col_idx, oracle.keys(g.row_ptr, rec["key_seed"]))
     assert int(kg.sum()) == rec["key_greedy_size"]
     assert 0 < rec["mindeg_greedy_size"] <= rec["n"]
+
+
+def test_stored_heuristic_quality_study():
+    # the quality table of the Section 3.3 heuristics (written by
+    # tests/golden/make_heuristic_quality.py from the oracle alone): the small
+    # workload is recomputed in full; on every workload the purely random priority
+    # (H1) gives the smallest set, and the sizes agree with the min-degree greedy
+    # heuristic's order of magnitude
+    rec = golden("heuristic_quality.json")
+    er = rec["workloads"]["er10k"]
+    g = gen.workload("er10k", seed=rec["graph_seed"])
+    assert int(oracle.mindeg_greedy(g.row_ptr, g.col_idx).sum()) == er["mindeg_greedy_size"]
+    for rule, row in er["rules"].items():
+        k = oracle.keys_rule(g.row_ptr, rec["key_seed"], rule)
+        st, rounds, _ = oracle.roundsync(g.row_ptr, g.col_idx, k)
+        assert int((st == oracle.IN).sum()) == row["size"] and rounds == row["rounds"], rule
+        assert int(oracle.greedy(g.row_ptr, g.col_idx, k).sum()) == row["size"]
+    for name, w in rec["workloads"].items():
+        sizes = {r: v["size"] for r, v in w["rules"].items()}
+        assert sizes["hash"] < sizes["degree"] and sizes["hash"] < sizes["eq1"], name
+        assert all(0 < s <= w["n"] for s in sizes.values())
+    assert rec["workloads"]["rmat22"]["rules"]["degree"]["size"] == golden("rmat22_quality.json")["key_greedy_size"]
