@@ -119,7 +119,10 @@ typedef struct {
     int32_t key_rule;         /* default priority rule when keys == NULL (MIS_KEY_*; Section 3.3) */
     int32_t timing;           /* 1 = record HIP events between the build's stages on the build
                                  stream (read them with mis_build_times) */
-    int32_t pad_;             /* unused */
+    int32_t dyn_slack;        /* hybrid path, one graph, dense_min -1: > 0 makes the handle
+                                 dynamic (mis_update_edges): both orientations kept in rows of
+                                 its own with this many free slots per row and orientation;
+                                 0 = static handle */
     uint64_t seed;            /* priority seed (default key rule) */
     const uint64_t* keys;     /* optional DEVICE uint64[n], pairwise distinct priorities
                                  (higher wins); NULL = default key rule, needs n <= 2^24 */
@@ -376,6 +379,28 @@ int mis_solve_noalloc(const mis_csr* csr, const mis_build_opts* opts, uint8_t* i
 
 /* Bytes of the per-GPU array behind mis_solve_noalloc. */
 size_t mis_noalloc_max_bytes(void);
+
+/*
+ * Edge insertions and deletions on a dynamic handle (hybrid path, built with
+ * dyn_slack > 0), and the repair of its set (Section 5's dynamic setting).
+ * Priorities stay those of the build, so the result is the set the
+ * round-synchronous rule gives on the edited graph with the build's keys; only the
+ * lower-priority ends of the edited edges and the vertices below a vertex whose
+ * status changes are decided again.
+ *   edges  : DEVICE int32[2*count], edge i = {edges[2i], edges[2i+1]} (either order)
+ *   ops    : DEVICE int8[count], 1 = insert (the edge must be absent), 0 = delete
+ *            (the edge must be present); an edge appears at most once per batch
+ *   in_set : DEVICE uint8[n]; in: the handle's current result (from mis_solve or the
+ *            previous update), out: the result on the edited graph
+ *   stats  : optional HOST: rounds of the repair, n_in, units[0] = entries read
+ * Deletes apply before inserts.  The handle's rows change in place, and a later
+ * mis_solve solves the edited graph from scratch.  Synchronises `stream`.
+ * Errors: MIS_EINVAL (not a dynamic handle; an edit out of range, a self-loop or a
+ * missing edge), MIS_ENOMEM (a row ran out of slots: the handle no longer holds
+ * that edge -- rebuild with a larger dyn_slack), MIS_EHIP.
+ */
+int mis_update_edges(mis_graph* g, const int32_t* edges, const int8_t* ops, int64_t count, uint8_t* in_set,
+                     mis_stats* stats, void* stream);
 
 /* Releases the handle (host memory only; the workspace stays the caller's). */
 void mis_free_tiles(mis_graph* g);

@@ -17,7 +17,7 @@ ARCH = os.environ.get("TCMIS_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["radix.hip", "build.hip", "hyb.hip", "solve_csr.hip", "solve_tile.hip", "capi.hip", "tune.hip", "session.hip",
-           "noalloc.hip", "rcm.cpp"]
+           "noalloc.hip", "dyn.hip", "rcm.cpp"]
 
 FLAGS = [
     "-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",

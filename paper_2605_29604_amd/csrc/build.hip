@@ -579,6 +579,7 @@ int bits_for(int64_t x) {   // bits to hold 0..x, so x itself is never all ones
 
 int host_rcm(const int64_t* rp, const int32_t* ci, int64_t n, std::vector<int32_t>& new_id);
 int64_t hyb_blocks(int64_t nnz);
+int64_t dyn_counter_words();
 
 size_t layout(mis_graph* g, char* base) {
     size_t off = 0;
@@ -607,8 +608,23 @@ size_t layout(mis_graph* g, char* base) {
         take(&g->hbrow, (size_t)(hyb_blocks(nnz) + 2) * 4);
         take(&g->hbase, (size_t)n * 4);
         take(&g->hoff, (size_t)n * 4);
-        take(&g->hcol, (size_t)nnz * 4);
+        const int64_t rows = g->dyn_slack > 0 ? nnz + n * (int64_t)g->dyn_slack : nnz;   // slots per orientation
+        take(&g->hcol, (size_t)rows * 4);
         take(&g->hcnt, (size_t)n * 4);
+        if (g->dyn_slack > 0) {
+            take(&g->drp, (size_t)(n + 1) * 8);
+            take(&g->lcol, (size_t)rows * 4);
+            take(&g->lcnt, (size_t)n * 4);
+            take(&g->hloff, (size_t)n * 4);
+            take(&g->rS, (size_t)nw * 4);
+            take(&g->rP, (size_t)nw * 4);
+            take(&g->rC, (size_t)nw * 4);
+            take(&g->rlist[0], (size_t)n * 4);
+            take(&g->rlist[1], (size_t)n * 4);
+            take(&g->rflip, (size_t)n * 4);
+            take(&g->rdec, (size_t)n * 4);
+            take(&g->rcnt, (size_t)dyn_counter_words() * 8);
+        }
         take(&g->hflag, (size_t)n * 8);
         take(&g->hpos, (size_t)(n + 1) * 8);
         take(&g->hl1[0], (size_t)n * 4);

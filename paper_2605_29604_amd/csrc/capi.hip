@@ -166,7 +166,15 @@ int resolve(const mis_csr* csr, const mis_build_opts* opts, mis_build_opts* o, i
         o->tile = 16;
         o->reorder = MIS_REORDER_NONE;
         o->orient = 1;
+        if (o->dyn_slack < 0) return fail(MIS_EINVAL, "dyn_slack must be >= 0");
+        if (o->dyn_slack > 0) {
+            if (count > 0) return fail(MIS_EINVAL, "a dynamic handle holds one graph");
+            if (o->dense_min > 0) return fail(MIS_EINVAL, "a dynamic handle keeps entry lists only (dense_min -1)");
+            o->dense_min = -1;
+        }
         if (o->dense_min == 0) o->dense_min = kDenseMinDefault;
+    } else if (o->dyn_slack != 0) {
+        return fail(MIS_EINVAL, "dyn_slack needs the hybrid path");
     } else if (o->path == MIS_PATH_TILE) {
         if (o->tile == 0) o->tile = 16;
         if (o->reorder == MIS_REORDER_AUTO) o->reorder = MIS_REORDER_KEY;
@@ -210,6 +218,7 @@ void configure(mis_graph* g, const mis_csr* csr, const mis_build_opts& o) {
     g->seed = o.seed;
     g->btiming = o.timing != 0;
     g->dense_min = o.path == MIS_PATH_HYBRID && o.dense_min > 0 ? o.dense_min : 0;
+    g->dyn_slack = o.path == MIS_PATH_HYBRID ? o.dyn_slack : 0;
 }
 
 // kernels per round: tile path candidate / exclusion / finalize, CSR and hybrid paths

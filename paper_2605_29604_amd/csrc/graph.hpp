@@ -201,6 +201,23 @@ struct mis_graph {
     uint32_t* hA = nullptr;           // [nw] undecided vertices (bitmap)
     uint32_t* hS = nullptr;           // [nw] vertices in the set (bitmap)
     int32_t* hact[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};   // next rounds' lists
+    const int64_t* hrp = nullptr;     // row starts of hcol (the input row pointer, or drp)
+
+    // ---- dynamic handles (hybrid path, dyn_slack > 0): both orientations in rows of
+    // their own with room for inserted edges; deleted entries read -1
+    int dyn_slack = 0;
+    int64_t* drp = nullptr;           // [n+1] row starts: exclusive scan of deg + slack
+    int32_t* lcol = nullptr;          // [drp[n]] lower-priority neighbours
+    int32_t* lcnt = nullptr;          // [n] slots used in lcol rows
+    int32_t* hloff = nullptr;         // [n] orientation scratch
+    bool dyn_edited = false;          // edges changed since the rows were classified
+    uint32_t* rS = nullptr;           // [nw] repair: in the set
+    uint32_t* rP = nullptr;           // [nw] repair: pending (status to recompute)
+    uint32_t* rC = nullptr;           // [nw] repair: this round's candidates
+    int32_t* rlist[2] = {nullptr, nullptr};   // [n] pending vertices by round parity
+    int32_t* rflip = nullptr;         // [n] vertices whose status changed this round
+    int32_t* rdec = nullptr;          // [n] this round's decisions
+    int64_t* rcnt = nullptr;          // repair counters (see dyn.hip)
 };
 
 namespace tcmis {

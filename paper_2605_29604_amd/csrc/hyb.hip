@@ -118,11 +118,27 @@ __device__ inline bool higher(int64_t u, int64_t v, uint64_t kv, const uint64_t*
 // kept entries of a row piece are ranked by a workgroup prefix count in entry
 // order; a row wholly inside the range is written from its row start, a piece of a
 // longer row from the offset its atomic add returned.
+// Where the orientation writes: the higher-priority entries of row v go to
+// hcol[hrp[v] + ...] (hrp = the input row pointer, or the dynamic layout's own);
+// with lcol (dynamic handles) the lower-priority ones go to lcol[hrp[v] + ...].
+struct OrientOut {
+    const int64_t* hrp;
+    int32_t* hcol;
+    int32_t* hcnt;
+    int32_t* lcol;      // nullptr: higher-priority entries only
+    int32_t* lcnt;
+    int32_t* g_base;    // [n] scratch of workgroups whose rows exceed LDS
+    int32_t* g_off;
+    int32_t* g_loff;
+};
+
 template <bool kUserKeys, bool kLds>
 __device__ void orient_body(const int64_t* rp, const int32_t* ci, const uint64_t* key, const uint8_t* q8,
-                            uint64_t seed, int64_t nnz, int64_t u0, int64_t u1, int32_t* hcol, int32_t* hcnt,
-                            int32_t* g_base, int32_t* g_off, int32_t* wst, uint64_t* wkey, int32_t* wbase,
-                            int32_t* woff) {
+                            uint64_t seed, int64_t nnz, int64_t u0, int64_t u1, const OrientOut& o, int32_t* wst,
+                            uint64_t* wkey, int32_t* wbase, int32_t* woff, int32_t* wloff) {
+    int32_t* g_base = o.g_base;
+    int32_t* g_off = o.g_off;
+    int32_t* hcnt = o.hcnt;
     __shared__ int32_t wcnt[kHIters][kWpb];
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     const int64_t base = (int64_t)blockIdx.x * kHE;
@@ -198,6 +214,7 @@ __device__ void orient_body(const int64_t* rp, const int32_t* ci, const uint64_t
     }
     __syncthreads();
     // a row piece's last entry: its kept count; a whole row stores it, a piece adds it
+    // (and the same for the lower-priority entries of a dynamic handle)
     #pragma unroll
     for (int it = 0; it < kHIters; ++it) {
         const int64_t e = base + it * kBlock + (int64_t)threadIdx.x;
@@ -207,33 +224,48 @@ __device__ void orient_body(const int64_t* rp, const int32_t* ci, const uint64_t
             if (e == min(r1, end) - 1) {
                 const int32_t b0 = kLds ? wbase[li[it]] : g_base[v];
                 const int32_t cnt = pre[it] + (int32_t)((keep >> it) & 1u) - b0;
-                int32_t off = 0;
-                if (r0 >= base && r1 <= end) hcnt[v] = cnt;
+                const int32_t lc = (int32_t)(e + 1 - max(r0, base)) - cnt;
+                const bool whole = r0 >= base && r1 <= end;
+                int32_t off = 0, loff = 0;
+                if (whole) hcnt[v] = cnt;
                 else if (cnt > 0) off = atomicAdd(&hcnt[v], cnt);
-                if (kLds) woff[li[it]] = off; else g_off[v] = off;
+                if (o.lcol) {
+                    if (whole) o.lcnt[v] = lc;
+                    else if (lc > 0) loff = atomicAdd(&o.lcnt[v], lc);
+                }
+                if (kLds) { woff[li[it]] = off; wloff[li[it]] = loff; }
+                else { g_off[v] = off; if (o.lcol) o.g_loff[v] = loff; }
             }
         }
     }
     __syncthreads();
     #pragma unroll
     for (int it = 0; it < kHIters; ++it) {
-        if (!((keep >> it) & 1u)) continue;
+        const int64_t e = base + it * kBlock + (int64_t)threadIdx.x;
+        const bool kept = (keep >> it) & 1u;
+        if (!kept && (!o.lcol || e >= end)) continue;
         const int64_t v = u0 + li[it];
         const int32_t b0 = kLds ? wbase[li[it]] : g_base[v];
-        const int32_t off = kLds ? woff[li[it]] : g_off[v];
-        hcol[rp[v] + off + (pre[it] - b0)] = cu[it];
+        if (kept) {
+            const int32_t off = kLds ? woff[li[it]] : g_off[v];
+            o.hcol[o.hrp[v] + off + (pre[it] - b0)] = cu[it];
+        } else {
+            const int32_t loff = kLds ? wloff[li[it]] : o.g_loff[v];
+            const int32_t rank = (int32_t)(e - max(rp[v], base)) - (pre[it] - b0);
+            o.lcol[o.hrp[v] + loff + rank] = cu[it];
+        }
     }
 }
 
 template <bool kUserKeys>
 __global__ void __launch_bounds__(kBlock) k_orient(const int64_t* rp, const int32_t* ci, const uint64_t* key,
                                                    const uint8_t* q8, uint64_t seed, int64_t nnz,
-                                                   const int32_t* brow, int32_t* hcol, int32_t* hcnt, int32_t* g_base,
-                                                   int32_t* g_off) {
+                                                   const int32_t* brow, OrientOut o) {
     __shared__ int32_t wst[kHWin];      // row starts relative to the range (the first row: <= 0)
     __shared__ uint64_t wkey[kHWin];    // row keys
     __shared__ int32_t wbase[kHWin];    // prefix at each row piece's first entry
     __shared__ int32_t woff[kHWin];     // offset of each row piece inside its row
+    __shared__ int32_t wloff[kHWin];    // the same for the lower-priority entries (dynamic handles)
     const int64_t base = (int64_t)blockIdx.x * kHE;
     const int64_t u0 = brow[blockIdx.x], u1 = brow[blockIdx.x + 1];
     const int64_t w = u1 - u0 + 1;
@@ -243,11 +275,9 @@ __global__ void __launch_bounds__(kBlock) k_orient(const int64_t* rp, const int3
             wkey[i] = key[u0 + i];
         }
         __syncthreads();
-        orient_body<kUserKeys, true>(rp, ci, key, q8, seed, nnz, u0, u1, hcol, hcnt, g_base, g_off, wst, wkey,
-                                     wbase, woff);
+        orient_body<kUserKeys, true>(rp, ci, key, q8, seed, nnz, u0, u1, o, wst, wkey, wbase, woff, wloff);
     } else {
-        orient_body<kUserKeys, false>(rp, ci, key, q8, seed, nnz, u0, u1, hcol, hcnt, g_base, g_off, wst, wkey,
-                                      wbase, woff);
+        orient_body<kUserKeys, false>(rp, ci, key, q8, seed, nnz, u0, u1, o, wst, wkey, wbase, woff, wloff);
     }
 }
 
@@ -359,6 +389,19 @@ __global__ void __launch_bounds__(kBlock) k_dense(const int64_t* rp, const int32
         }
         wave_sync_lds();
     }
+}
+
+// a dynamic handle classifies its rows again after edits: the counters start at zero
+__global__ void k_hyb_meta_clear(Meta* meta) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        meta->n_c1 = 0;
+        meta->n_hl[0] = meta->n_hl[1] = 0;
+    }
+}
+
+// row capacities of a dynamic handle (each orientation: its degree plus the slack)
+__global__ void k_dyn_caps(const int64_t* rp, int64_t n, int slack, int64_t* cap) {
+    GRID_STRIDE(v, n) cap[v] = rp[v + 1] - rp[v] + slack;
 }
 
 __global__ void k_dense_end(const Meta* meta, int32_t* dptr) {
@@ -541,7 +584,8 @@ __device__ void hyb_p1(const HybArgs& a, int r) {
             int32_t k = 0;
             bool blocked = false;
             for (; k < c; ++k) {
-                if (bit_of(a.A, a.hcol[e0 + k])) { blocked = true; ++k; break; }
+                const int32_t u = a.hcol[e0 + k];
+                if (u >= 0 && bit_of(a.A, u)) { blocked = true; ++k; break; }
             }
             ent += k;
             ++verts;
@@ -557,7 +601,8 @@ __device__ void hyb_p1(const HybArgs& a, int r) {
         bool blocked = false;
         int32_t k = 0;
         for (; k < c; k += kWave) {
-            const bool b = k + lane < c && bit_of(a.A, a.hcol[e0 + k + lane]);
+            const int32_t u = k + lane < c ? a.hcol[e0 + k + lane] : -1;
+            const bool b = u >= 0 && bit_of(a.A, u);
             if (ballot(b)) { blocked = true; k += kWave; break; }
         }
         if (lane == 0) {
@@ -621,7 +666,8 @@ __device__ void hyb_p2(const HybArgs& a, int r) {
                 int32_t k = 0;
                 bool hit = false;
                 for (; k < c; ++k) {
-                    if (bit_of(a.S, a.hcol[e0 + k])) { hit = true; ++k; break; }
+                    const int32_t u = a.hcol[e0 + k];
+                    if (u >= 0 && bit_of(a.S, u)) { hit = true; ++k; break; }
                 }
                 ent += k;
                 ++verts;
@@ -647,7 +693,8 @@ __device__ void hyb_p2(const HybArgs& a, int r) {
             const int32_t c = a.hcnt[v];
             int32_t k = 0;
             for (; k < c; k += kWave) {
-                const bool b = k + lane < c && bit_of(a.S, a.hcol[e0 + k + lane]);
+                const int32_t u = k + lane < c ? a.hcol[e0 + k + lane] : -1;
+                const bool b = u >= 0 && bit_of(a.S, u);
                 if (ballot(b)) { hit = true; k += kWave; break; }
             }
             if (lane == 0) { ent += min(k, c); ++verts; }
@@ -730,7 +777,7 @@ __global__ void k_hyb_output4(const Ctrl* gate, const uint32_t* S, int64_t n, ui
 
 HybArgs make_args(mis_graph* g) {
     HybArgs a;
-    a.rp = g->row_ptr;
+    a.rp = g->hrp;
     a.hcol = g->hcol;
     a.hcnt = g->hcnt;
     a.A = g->hA;
@@ -772,16 +819,26 @@ int build_hybrid(mis_graph* g, hipStream_t s) {
     if (n == 0) return MIS_OK;
     // 1. orientation (stages: row search, orientation, dense blocks, lists)
     TC_HIP(hipMemsetAsync(g->hcnt, 0, (size_t)n * 4, s));
+    g->hrp = g->row_ptr;
+    if (g->dyn_slack > 0) {
+        // dynamic handle: rows of its own, deg + slack slots for each orientation
+        TC_HIP(hipMemsetAsync(g->lcnt, 0, (size_t)n * 4, s));
+        HLAUNCH(k_dyn_caps, n, g->row_ptr, n, g->dyn_slack, g->hflag);
+        TC_CHECK(scan_excl_i64(g->hflag, g->drp, n, g->drp + n, (int64_t*)g->scan_tmp, s));
+        g->hrp = g->drp;
+    }
     const int64_t nb = hyb_blocks(nnz);
     if (nnz > 0) HLAUNCH(k_orient_rows, nb + 1, g->row_ptr, n, nnz, nb, g->hbrow);
     build_mark(g, s);
     if (nnz > 0) {
+        OrientOut o{g->hrp, g->hcol, g->hcnt, g->dyn_slack > 0 ? g->lcol : nullptr, g->lcnt, g->hbase, g->hoff,
+                    g->hloff};
         if (g->user_keys)
             hipLaunchKernelGGL(k_orient<true>, dim3((unsigned)nb), dim3(kBlock), 0, s, g->row_ptr, g->col_idx, g->key,
-                               g->q8, g->seed, nnz, g->hbrow, g->hcol, g->hcnt, g->hbase, g->hoff);
+                               g->q8, g->seed, nnz, g->hbrow, o);
         else
             hipLaunchKernelGGL(k_orient<false>, dim3((unsigned)nb), dim3(kBlock), 0, s, g->row_ptr, g->col_idx,
-                               g->key, g->q8, g->seed, nnz, g->hbrow, g->hcol, g->hcnt, g->hbase, g->hoff);
+                               g->key, g->q8, g->seed, nnz, g->hbrow, o);
         TC_HIP(hipGetLastError());
     }
     build_mark(g, s);
@@ -811,7 +868,23 @@ int build_hybrid(mis_graph* g, hipStream_t s) {
     return MIS_OK;
 }
 
+int hyb_classify(mis_graph* g, hipStream_t s);
+
+// round-1 classes and lists from the rows' current counts
+int hyb_classify(mis_graph* g, hipStream_t s) {
+    const int64_t n = g->n;
+    HLAUNCH(k_hyb_meta_clear, 1, g->meta);
+    HLAUNCH(k_hyb_class, n, g->hcnt, g->dense_min > 0 ? g->dflag : nullptr, n, g->hflag, g->s1, g->a1, &g->meta->n_c1);
+    TC_CHECK(scan_excl_i64(g->hflag, g->hpos, n, g->hpos + n, (int64_t*)g->scan_tmp, s));
+    HLAUNCH(k_hyb_lists, n, g->hflag, g->hpos, n, g->hl1[0], g->hl1[1], g->meta);
+    return MIS_OK;
+}
+
 int hyb_init(mis_graph* g, hipStream_t s) {
+    if (g->dyn_edited && g->n > 0) {   // a dynamic handle's rows changed since they were classified
+        TC_CHECK(hyb_classify(g, s));
+        g->dyn_edited = false;
+    }
     const int64_t nw = ceil_div(g->n, 32);
     if (g->n > 0)
         hipLaunchKernelGGL(k_hyb_init, dim3(stream_grid(std::max(nw, g->count > 0 ? g->n : 0))), dim3(kBlock), 0, s,

@@ -31,7 +31,8 @@ EXPORTS = ["mis_default_opts", "mis_build_bytes", "mis_build_tiles", "mis_build_
            "mis_graph_bytes", "mis_solve", "mis_solve_batch", "mis_free_tiles", "mis_status_string", "mis_last_error",
            "mis_version", "mis_autotune_bytes", "mis_autotune", "mis_autotune_clear", "mis_session_create",
            "mis_session_admit", "mis_session_progress", "mis_session_query", "mis_session_destroy",
-           "mis_release_host_buffers", "mis_build_times", "mis_solve_noalloc", "mis_noalloc_max_bytes"]
+           "mis_release_host_buffers", "mis_build_times", "mis_solve_noalloc", "mis_noalloc_max_bytes",
+           "mis_update_edges"]
 
 
 class MisCsr(ctypes.Structure):
@@ -44,7 +45,7 @@ class MisBuildOpts(ctypes.Structure):
                 ("orient", ctypes.c_int32), ("validate", ctypes.c_int32), ("poll_rounds", ctypes.c_int32),
                 ("launch", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("dense_min", ctypes.c_int32), ("key_rule", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("pad_", ctypes.c_int32),
+                ("dyn_slack", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("keys", ctypes.c_void_p)]
 
 
@@ -139,6 +140,8 @@ def lib():
     L.mis_solve_noalloc.restype = ctypes.c_int
     L.mis_noalloc_max_bytes.argtypes = []
     L.mis_noalloc_max_bytes.restype = ctypes.c_size_t
+    L.mis_update_edges.argtypes = [vp, vp, vp, ctypes.c_int64, vp, ctypes.POINTER(MisStats), vp]
+    L.mis_update_edges.restype = ctypes.c_int
     L.mis_release_host_buffers.argtypes = []
     L.mis_release_host_buffers.restype = None
     L.mis_status_string.argtypes = [ctypes.c_int]
@@ -192,7 +195,7 @@ class MisGraph:
 
 
 def _opts(path="auto", tile=0, reorder="auto", orient=-1, validate=False, seed=1, keys=None, poll_rounds=0,
-          launch="auto", blocks_per_cu=0, dense_min=0, key_rule="degree", timing=False):
+          launch="auto", blocks_per_cu=0, dense_min=0, key_rule="degree", timing=False, dyn_slack=0):
     o = MisBuildOpts()
     lib().mis_default_opts(ctypes.byref(o))
     o.path = PATHS[path] if isinstance(path, str) else int(path)
@@ -206,6 +209,7 @@ def _opts(path="auto", tile=0, reorder="auto", orient=-1, validate=False, seed=1
     o.dense_min = int(dense_min)
     o.key_rule = KEY_RULES[key_rule] if isinstance(key_rule, str) else int(key_rule)
     o.timing = int(bool(timing))
+    o.dyn_slack = int(dyn_slack)
     o.seed = int(seed) & (2**64 - 1)
     o.keys = _ptr(keys)
     return o
@@ -222,7 +226,7 @@ def mis_build_bytes(n: int, nnz: int, **opts) -> int:
 
 def mis_build_tiles(row_ptr, col_idx, path="auto", tile=0, reorder="auto", orient=-1, validate=False,
                     seed=1, keys=None, poll_rounds=0, launch="auto", blocks_per_cu=0, workspace=None,
-                    stream=None, dense_min=0, key_rule="degree", timing=False) -> MisGraph:
+                    stream=None, dense_min=0, key_rule="degree", timing=False, dyn_slack=0) -> MisGraph:
     """row_ptr: cuda int64[n+1]; col_idx: cuda int32[nnz]; keys: optional cuda uint64[n] (as int64).
 
     The device workspace comes from torch's allocator unless one is passed (a cuda
@@ -234,7 +238,7 @@ def mis_build_tiles(row_ptr, col_idx, path="auto", tile=0, reorder="auto", orien
     nnz = col_idx.numel()
     csr = MisCsr(n, nnz, _ptr(row_ptr), _ptr(col_idx) if nnz else None)
     o = _opts(path, tile, reorder, orient, validate, seed, keys, poll_rounds, launch, blocks_per_cu, dense_min,
-              key_rule, timing)
+              key_rule, timing, dyn_slack)
     need = ctypes.c_size_t(0)
     _check(L.mis_build_bytes(ctypes.byref(csr), ctypes.byref(o), ctypes.byref(need)))
     if workspace is None:
@@ -296,7 +300,7 @@ def mis_build_batch_bytes(n: int, nnz: int, offsets, **opts) -> int:
 
 def mis_build_batch(row_ptr, col_idx, offsets, path="auto", tile=0, reorder="auto", orient=-1, validate=False,
                     seed=1, keys=None, poll_rounds=0, launch="auto", blocks_per_cu=0, workspace=None,
-                    stream=None, dense_min=0, key_rule="degree", timing=False) -> MisGraph:
+                    stream=None, dense_min=0, key_rule="degree", timing=False, dyn_slack=0) -> MisGraph:
     """A batch of independent graphs given as their disjoint union (cuda CSR) and host
     vertex offsets (count+1).  Priorities use graph-local ids."""
     import torch
@@ -306,7 +310,7 @@ def mis_build_batch(row_ptr, col_idx, offsets, path="auto", tile=0, reorder="aut
     csr = MisCsr(n, nnz, _ptr(row_ptr), _ptr(col_idx) if nnz else None)
     off, offp = _offsets(offsets)
     o = _opts(path, tile, reorder, orient, validate, seed, keys, poll_rounds, launch, blocks_per_cu, dense_min,
-              key_rule, timing)
+              key_rule, timing, dyn_slack)
     need = ctypes.c_size_t(0)
     _check(L.mis_build_batch_bytes(ctypes.byref(csr), len(off) - 1, offp, ctypes.byref(o), ctypes.byref(need)))
     if workspace is None:
@@ -392,6 +396,16 @@ def mis_solve_noalloc(row_ptr, col_idx, out, stream=None, **opts):
     _check(lib().mis_solve_noalloc(ctypes.byref(csr), ctypes.byref(o), _ptr(out) if n else None, ctypes.byref(r),
                                    ctypes.byref(k), ctypes.c_void_p(_stream(stream))))
     return int(r.value), int(k.value)
+
+
+def mis_update_edges(g: MisGraph, edges, ops, in_set, stream=None) -> dict:
+    """Edge edits on a dynamic handle and the repair of in_set (cuda uint8[n], updated in
+    place).  edges: cuda int32[count, 2]; ops: cuda int8[count] (1 insert, 0 delete)."""
+    st = MisStats()
+    k = int(ops.numel())
+    _check(lib().mis_update_edges(g.handle, _ptr(edges) if k else None, _ptr(ops) if k else None, k,
+                                  _ptr(in_set) if g.n else None, ctypes.byref(st), ctypes.c_void_p(_stream(stream))))
+    return {"rounds": st.rounds, "n_in": st.n_in, "entries_read": st.units[0]}
 
 
 def mis_release_host_buffers() -> None:

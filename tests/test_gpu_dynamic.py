@@ -1,0 +1,134 @@
+"""Dynamic graphs on the GPU: batches of edge insertions and deletions applied to a
+dynamic hybrid handle, and the repaired set, against the oracle's solve of the
+edited graph with the build's keys (priorities are fixed once computed); then a full
+solve of the edited handle against the oracle's set and round trace."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_29604_amd import gen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def T():
+    from paper_2605_29604_amd import tcmis
+    return tcmis
+
+
+def csr_of(n, edges):
+    e = np.array(sorted(edges), dtype=np.int64).reshape(-1, 2)
+    src = np.concatenate([e[:, 0], e[:, 1]])
+    dst = np.concatenate([e[:, 1], e[:, 0]])
+    order = np.lexsort((dst, src))
+    src, dst = src[order], dst[order]
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rp, src + 1, 1)
+    return np.cumsum(rp), dst.astype(np.int32)
+
+
+def edge_set(g):
+    src = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    m = src < g.col_idx
+    return set(zip(src[m].tolist(), g.col_idx[m].tolist()))
+
+
+def random_edits(rng, n, edges, k_del, k_ins, hub=None):
+    cur = sorted(edges)
+    dels = [cur[i] for i in rng.choice(len(cur), size=min(k_del, len(cur)), replace=False)]
+    ins = set()
+    while len(ins) < k_ins:
+        u = int(hub if hub is not None and rng.random() < 0.3 else rng.integers(n))
+        v = int(rng.integers(n))
+        if u == v:
+            continue
+        e = (min(u, v), max(u, v))
+        if e not in edges and e not in ins:
+            ins.add(e)
+    return dels, sorted(ins)
+
+
+@pytest.mark.parametrize("name", ["rmat12", "grid12", "er3000"])
+def test_edit_batches_repair_to_the_oracle(name):
+    t = T()
+    g = gen.er(3000, 12000, 4) if name == "er3000" else gen.workload(name, seed=3)
+    keys0 = oracle.keys(g.row_ptr, 5)
+    rp0 = torch.from_numpy(g.row_ptr).cuda()
+    ci0 = torch.from_numpy(g.col_idx).cuda()
+    h = t.mis_build_tiles(rp0, ci0, path="hybrid", dyn_slack=16, seed=5, validate=True)
+    out, st = t.mis_solve(h)
+    st0, r0, tr0 = oracle.roundsync(g.row_ptr, g.col_idx, keys0)
+    assert np.array_equal(out.cpu().numpy(), (st0 == oracle.IN).astype(np.uint8))
+    assert np.array_equal(st["trace"], tr0)
+    edges = edge_set(g)
+    rng = np.random.default_rng(11)
+    hub = int(np.argmax(np.diff(g.row_ptr)))
+    for b in range(4):
+        dels, ins = random_edits(rng, g.n, edges, 40 * (b + 1), 40 * (b + 1), hub=hub)
+        edges = (edges - set(dels)) | set(ins)
+        pairs = np.array(dels + ins, dtype=np.int32).reshape(-1, 2)
+        flip = rng.random(len(pairs)) < 0.5              # either endpoint order
+        pairs[flip] = pairs[flip][:, ::-1]
+        ops = np.array([0] * len(dels) + [1] * len(ins), dtype=np.int8)
+        perm = rng.permutation(len(ops))                 # deletes and inserts interleaved
+        d_pairs = torch.from_numpy(np.ascontiguousarray(pairs[perm])).cuda()
+        d_ops = torch.from_numpy(ops[perm]).cuda()
+        info = t.mis_update_edges(h, d_pairs, d_ops, out)
+        torch.cuda.synchronize()
+        rp1, ci1 = csr_of(g.n, edges)
+        want, _, _ = oracle.roundsync(rp1, ci1, keys0)
+        want = (want == oracle.IN).astype(np.uint8)
+        got = out.cpu().numpy()
+        print(f"case dynamic {name} batch {b}: {len(dels)} deletes {len(ins)} inserts, repair rounds "
+              f"{info['rounds']}, entries read {info['entries_read']}", flush=True)
+        assert np.array_equal(got, want), f"batch {b}: {int((got != want).sum())} vertices differ"
+        assert info["n_in"] == int(want.sum())
+    # a full solve of the edited handle: same set and round trace as the oracle
+    out2, st2 = t.mis_solve(h)
+    torch.cuda.synchronize()
+    want2, r2, tr2 = oracle.roundsync(rp1, ci1, keys0)
+    assert np.array_equal(out2.cpu().numpy(), (want2 == oracle.IN).astype(np.uint8))
+    assert st2["rounds"] == r2 and np.array_equal(st2["trace"], tr2)
+    t.mis_free_tiles(h)
+
+
+def test_edit_errors():
+    t = T()
+    g = gen.er(500, 1500, 2)
+    rp = torch.from_numpy(g.row_ptr).cuda()
+    ci = torch.from_numpy(g.col_idx).cuda()
+    static = t.mis_build_tiles(rp, ci, path="hybrid")
+    out, _ = t.mis_solve(static)
+    one = torch.tensor([[0, 1]], dtype=torch.int32, device="cuda")
+    ins = torch.ones(1, dtype=torch.int8, device="cuda")
+    with pytest.raises(t.MisError) as ei:   # not a dynamic handle
+        t.mis_update_edges(static, one, ins, out)
+    assert ei.value.code == t.MIS_EINVAL
+    with pytest.raises(t.MisError):          # dynamic handles keep entry lists only
+        t.mis_build_tiles(rp, ci, path="hybrid", dyn_slack=4, dense_min=9)
+    h = t.mis_build_tiles(rp, ci, path="hybrid", dyn_slack=1, seed=3)
+    out, _ = t.mis_solve(h)
+    edges = edge_set(g)
+    missing = next((u, v) for u in range(g.n) for v in range(u + 1, g.n) if (u, v) not in edges)
+    with pytest.raises(t.MisError) as ei:   # deleting an absent edge
+        t.mis_update_edges(h, torch.tensor([missing], dtype=torch.int32, device="cuda"),
+                           torch.zeros(1, dtype=torch.int8, device="cuda"), out)
+    assert ei.value.code == t.MIS_EINVAL
+    h2 = t.mis_build_tiles(rp, ci, path="hybrid", dyn_slack=1, seed=3)
+    out2, _ = t.mis_solve(h2)
+    # the lowest-priority vertex gets more new higher-priority neighbours than its row holds
+    k = oracle.keys(g.row_ptr, 3)
+    lo = int(np.argmin(k))
+    room = int(np.diff(g.row_ptr)[lo]) + 1
+    new = [(lo, v) for v in range(g.n) if v != lo and (min(lo, v), max(lo, v)) not in edges][: room + 2]
+    with pytest.raises(t.MisError) as ei:
+        t.mis_update_edges(h2, torch.tensor(new, dtype=torch.int32, device="cuda"),
+                           torch.ones(len(new), dtype=torch.int8, device="cuda"), out2)
+    assert ei.value.code == t.MIS_ENOMEM

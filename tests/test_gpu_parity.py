@@ -476,3 +476,79 @@ def test_autotune_batch():
     for i, g in enumerate(graphs):
         want, r, _ = expected(g.row_ptr, g.col_idx, oracle.keys(g.row_ptr, 3))
         assert np.array_equal(got[off[i]:off[i + 1]], want) and rounds[i] == r, f"graph {i}"
+
+
+def _oracle_slices(rp_h, ci_h, off, seed, rule="degree", threads=16):
+    """Oracle in/out vector and rounds of every graph of a union, graphs in parallel
+    (the oracle's C calls release the interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(gi):
+        va, vb = int(off[gi]), int(off[gi + 1])
+        ea, eb = int(rp_h[va]), int(rp_h[vb])
+        grp = rp_h[va:vb + 1] - ea
+        gci = ci_h[ea:eb] - va
+        st, r, _ = oracle.roundsync(grp, gci, oracle.keys_rule(grp, seed, rule))
+        return (st == oracle.IN).astype(np.uint8), r
+
+    with ThreadPoolExecutor(threads) as ex:
+        return list(ex.map(one, range(len(off) - 1)))
+
+
+@pytest.mark.slow
+def test_batch4096_full_against_oracle():
+    # the full 4,096-graph batch workload (log-uniform 500..200,000 vertices, half
+    # Erdos-Renyi, half R-MAT; 2.2e9 adjacency entries) as ONE hybrid handle: every
+    # graph's slice and round count equal the oracle's solve of that graph alone
+    T = tcmis_mod()
+    spec = gen.batch_spec(4096, seed=1)
+    rp_h, ci_h, off = gen.batch_union(spec)
+    print(f"case batch4096 n={off[-1]} nnz={ci_h.size}", flush=True)
+    drp, dci = to_dev(rp_h, ci_h)
+    h = T.mis_build_batch(drp, dci, off, path="hybrid", seed=1)
+    out, st, rounds, sizes = T.mis_solve_batch(h)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    T.mis_free_tiles(h)
+    del drp, dci
+    torch.cuda.empty_cache()
+    want = _oracle_slices(rp_h, ci_h, off, 1)
+    for gi, (w, r) in enumerate(want):
+        assert np.array_equal(got[off[gi]:off[gi + 1]], w), f"graph {gi} {spec[gi]}"
+        assert rounds[gi] == r and sizes[gi] == int(w.sum()), f"graph {gi}"
+    assert st["rounds"] == max(r for _, r in want)
+
+
+@pytest.mark.slow
+def test_serving_pool_full_against_oracle():
+    # every graph of the serving workload's request pool (log-uniform 1e3..4e6
+    # vertices, Erdos-Renyi / R-MAT / 3D grid) through a continuous-batching session,
+    # admitted all at once as far as the arena allows: each result equals the oracle
+    T = tcmis_mod()
+    spec = gen.serve_spec(48, seed=1)
+    rp_h, ci_h, off = gen.batch_union(spec)
+    want = _oracle_slices(rp_h, ci_h, off, 1)
+    pool = []
+    for i in range(len(spec)):
+        va, vb = int(off[i]), int(off[i + 1])
+        ea, eb = int(rp_h[va]), int(rp_h[vb])
+        pool.append((torch.from_numpy(rp_h[va:vb + 1] - ea).pin_memory(),
+                     torch.from_numpy(ci_h[ea:eb] - va).pin_memory(), vb - va))
+    r = lambda x: (x + 255) // 256 * 256
+    foot = max(r(T.mis_build_bytes(p[2], p[1].numel())) + r((p[2] + 1) * 8) + r(p[1].numel() * 4) + r(p[2])
+               for p in pool)
+    sess = T.Session(arena_bytes=3 * foot, max_live=8, rounds_per_step=4)
+    outs = {i: torch.zeros(max(p[2], 1), dtype=torch.uint8).pin_memory() for i, p in enumerate(pool)}
+    pending, done = list(range(len(pool))), {}
+    while pending or sess.query()[0] > 0:
+        while pending and sess.admit(pool[pending[0]][0], pool[pending[0]][1], tag=pending[0],
+                                     host_out=outs[pending[0]][: pool[pending[0]][2]]):
+            print(f"admit pool graph {pending[0]} n={pool[pending[0]][2]}", flush=True)
+            pending.pop(0)
+        for d in sess.progress(wait=True):
+            assert d["status"] == 0
+            done[d["tag"]] = d
+    sess.close()
+    for i, (w, rr) in enumerate(want):
+        assert np.array_equal(outs[i].numpy()[: pool[i][2]], w), f"pool graph {i} {spec[i]}"
+        assert done[i]["rounds"] == rr, f"pool graph {i}"
