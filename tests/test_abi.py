@@ -59,10 +59,17 @@ def test_host_argument_errors(L):
     assert build(L, csr, None, ws, 1 << 40, None) == tcmis.MIS_EINVAL
     assert build(L, None, None, ws, 1 << 40, hp) == tcmis.MIS_EINVAL
     for bad in (tcmis.MisCsr(-1, 0, ctypes.c_void_p(256), None), tcmis.MisCsr(10, 5, None, None),
-                tcmis.MisCsr(10, 5, ctypes.c_void_p(256), None), tcmis.MisCsr(10, 1 << 31, ctypes.c_void_p(256),
+                tcmis.MisCsr(10, 5, ctypes.c_void_p(256), None), tcmis.MisCsr(10, 1 << 40, ctypes.c_void_p(256),
                                                                                ctypes.c_void_p(256))):
         assert build(L, bad, None, ws, 1 << 40, hp) == tcmis.MIS_EINVAL
-    for field, value in (("tile", 8), ("path", 7), ("reorder", 9), ("orient", 2), ("poll_rounds", -1)):
+    # 2^31 entries and more: the hybrid path only (64-bit entry offsets)
+    wide = tcmis.MisCsr(10, 1 << 31, ctypes.c_void_p(256), ctypes.c_void_p(256))
+    for path in ("tile", "csr"):
+        assert build(L, wide, tcmis._opts(path=path), ws, 1 << 40, hp) == tcmis.MIS_EINVAL
+        assert "2^31" in L.mis_last_error().decode()
+    assert tcmis.mis_build_bytes(10, 1 << 31, path="hybrid") > (1 << 33)
+    for field, value in (("tile", 8), ("path", 7), ("reorder", 9), ("orient", 2), ("poll_rounds", -1),
+                         ("dense_min", -2), ("key_rule", 3), ("timing", 2), ("dyn_slack", -1)):
         o = tcmis.MisBuildOpts()
         L.mis_default_opts(ctypes.byref(o))
         setattr(o, field, value)
