@@ -47,7 +47,6 @@ namespace tcmis {
 namespace {
 
 constexpr int kHE = 2048;                 // adjacency entries per orientation workgroup
-constexpr int kHIters = kHE / kBlock;     // entries per thread
 constexpr int kHWin = 512;                // rows a workgroup stages in LDS
 constexpr int kHSteps = 9;                // 2^kHSteps = kHWin
 constexpr int kHLight = 32;               // rows with at most this many entries take one lane
@@ -111,13 +110,6 @@ __device__ inline bool higher(int64_t u, int64_t v, uint64_t kv, const uint64_t*
     return hu != hv ? hu > hv : lu > lv;
 }
 
-// Orientation.  Workgroup b takes entries [b*kHE, (b+1)*kHE), thread t entries
-// b*kHE + it*kBlock + t.  With the workgroup's rows staged in LDS (row starts
-// relative to the range, row keys), each thread finds its entries' rows with a
-// fixed-step search, issues its column reads, then its degree-class gathers.  The
-// kept entries of a row piece are ranked by a workgroup prefix count in entry
-// order; a row wholly inside the range is written from its row start, a piece of a
-// longer row from the offset its atomic add returned.
 // Where the orientation writes: the higher-priority entries of row v go to
 // hcol[hrp[v] + ...] (hrp = the input row pointer, or the dynamic layout's own);
 // with lcol (dynamic handles) the lower-priority ones go to lcol[hrp[v] + ...].
@@ -132,127 +124,149 @@ struct OrientOut {
     int32_t* g_loff;
 };
 
+// Row bounds of a workgroup's rows relative to its range start: from LDS when they
+// were staged there (wst[i] = start of row u0+i, wst[w] = end of row u1; the first
+// start may be negative), else from the input row pointer.
+template <bool kLds>
+struct Rows {
+    const int64_t* rp;
+    int64_t u0, base;
+    const int32_t* wst;
+    __device__ int64_t start(int li) const { return kLds ? (int64_t)wst[li] : rp[u0 + li] - base; }
+    __device__ int64_t stop(int li) const { return kLds ? (int64_t)wst[li + 1] : rp[u0 + li + 1] - base; }
+};
+
+// Orientation.  Workgroup b takes entries [b*kHE, (b+1)*kHE), thread t the eight
+// consecutive entries b*kHE + 8t .. 8t+7 (two 16-byte column loads).  The thread
+// finds the row of its first entry with a fixed-step search over the staged row
+// starts and walks forward for the other seven, then issues its eight degree-class
+// gathers.  The kept entries of a row piece are ranked by a workgroup prefix count
+// in entry order; a row wholly inside the range is written from its row start, a
+// piece of a longer row from the offset its atomic add returned.
 template <bool kUserKeys, bool kLds>
 __device__ void orient_body(const int64_t* rp, const int32_t* ci, const uint64_t* key, const uint8_t* q8,
-                            uint64_t seed, int64_t nnz, int64_t u0, int64_t u1, const OrientOut& o, int32_t* wst,
-                            uint64_t* wkey, int32_t* wbase, int32_t* woff, int32_t* wloff) {
-    int32_t* g_base = o.g_base;
-    int32_t* g_off = o.g_off;
-    int32_t* hcnt = o.hcnt;
-    __shared__ int32_t wcnt[kHIters][kWpb];
+                            uint64_t seed, int64_t nnz, int64_t u0, int64_t u1, const OrientOut& o, const int32_t* wst,
+                            const uint64_t* wkey, int32_t* wbase, int32_t* woff, int32_t* wloff) {
+    constexpr int kPer = kHE / kBlock;   // 8 consecutive entries per thread
+    __shared__ int32_t wsum[kWpb];
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     const int64_t base = (int64_t)blockIdx.x * kHE;
     const int64_t end = min(nnz, base + kHE);
+    const int64_t erel = end - base;     // entries of the range
     const int w = (int)(u1 - u0 + 1);
-    int li[kHIters];   // row of each entry, relative to u0
-    int32_t cu[kHIters];
-    #pragma unroll
-    for (int it = 0; it < kHIters; ++it) {
-        const int64_t e = min(base + it * kBlock + (int64_t)threadIdx.x, end - 1);
+    const Rows<kLds> R{rp, u0, base, wst};
+    const int64_t t0 = (int64_t)threadIdx.x * kPer;   // first entry of the thread, relative
+    // columns: two 16-byte loads when the thread's eight entries are all in range and aligned
+    int32_t cu[kPer];
+    const int32_t* src = ci + base + t0;
+    if (t0 + kPer <= erel && (((uintptr_t)src) & 15) == 0) {
+        const v4i a = __builtin_nontemporal_load(reinterpret_cast<const v4i*>(src));
+        const v4i b = __builtin_nontemporal_load(reinterpret_cast<const v4i*>(src) + 1);
+        #pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            cu[j] = a[j];
+            cu[4 + j] = b[j];
+        }
+    } else {
+        #pragma unroll
+        for (int j = 0; j < kPer; ++j) cu[j] = ci[base + min(t0 + j, erel - 1)];
+    }
+    // the row of each entry
+    int li[kPer];
+    {
+        const int64_t e0 = min(t0, erel - 1);
+        int lo = 0;
         if (kLds) {
-            const int32_t er = (int32_t)(e - base);
-            int lo = 0;   // wst[0] <= 0 <= er
             #pragma unroll
             for (int k = kHSteps - 1; k >= 0; --k) {
                 const int c = lo + (1 << k);
                 const int32_t wc = wst[min(c, w - 1)];
-                lo = ((c <= w - 1) & (wc <= er)) ? c : lo;
+                lo = ((c <= w - 1) & (wc <= e0)) ? c : lo;
             }
-            li[it] = lo;
         } else {
-            int64_t lo = u0, hi = u1;
-            while (lo < hi) {
-                const int64_t mid = (lo + hi + 1) >> 1;
-                if (rp[mid] <= e) lo = mid; else hi = mid - 1;
+            int64_t a = u0, b = u1;
+            while (a < b) {
+                const int64_t mid = (a + b + 1) >> 1;
+                if (rp[mid] <= base + e0) a = mid; else b = mid - 1;
             }
-            li[it] = (int)(lo - u0);
+            lo = (int)(a - u0);
         }
-    }
-    #pragma unroll
-    for (int it = 0; it < kHIters; ++it) {
-        const int64_t e = min(base + it * kBlock + (int64_t)threadIdx.x, end - 1);
-        cu[it] = __builtin_nontemporal_load(&ci[e]);
-    }
-    uint32_t keep = 0;   // bit it: entry it is kept
-    #pragma unroll
-    for (int it = 0; it < kHIters; ++it) {
-        const int64_t e = base + it * kBlock + (int64_t)threadIdx.x;
-        const int64_t v = u0 + li[it];
-        const uint64_t kv = kLds ? wkey[li[it]] : key[v];
-        if (e < end && higher<kUserKeys>(cu[it], v, kv, key, q8, seed)) keep |= 1u << it;
-    }
-    #pragma unroll
-    for (int it = 0; it < kHIters; ++it) {
-        const uint64_t b = ballot((keep >> it) & 1u);
-        if (lane == 0) wcnt[it][wid] = __popcll(b);
-    }
-    __syncthreads();
-    // exclusive prefix count of kept entries at each of the thread's entries
-    int32_t pre[kHIters];
-    {
-        int run = 0;
         #pragma unroll
-        for (int it = 0; it < kHIters; ++it) {
-            int before = run, total = run;
-            for (int q = 0; q < kWpb; ++q) {
-                if (q < wid) before += wcnt[it][q];
-                total += wcnt[it][q];
-            }
-            const uint64_t b = ballot((keep >> it) & 1u);
-            pre[it] = before + __popcll(b & lanes_below());
-            run = total;
+        for (int j = 0; j < kPer; ++j) {
+            const int64_t e = min(t0 + j, erel - 1);
+            while (lo + 1 < w && R.start(lo + 1) <= e) ++lo;
+            li[j] = lo;
         }
     }
+    uint32_t keep = 0;   // bit j: entry j is kept
+    #pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int64_t v = u0 + li[j];
+        const uint64_t kv = kLds ? wkey[li[j]] : key[v];
+        if (t0 + j < erel && higher<kUserKeys>(cu[j], v, kv, key, q8, seed)) keep |= 1u << j;
+    }
+    // exclusive prefix count of kept entries at the thread's first entry (entry order)
+    const int cnt = __popc(keep);
+    int incl = cnt;
+    #pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int x = __shfl_up(incl, off, kWave);
+        if (lane >= off) incl += x;
+    }
+    if (lane == kWave - 1) wsum[wid] = incl;
+    __syncthreads();
+    int pre0 = incl - cnt;
+    for (int q = 0; q < wid; ++q) pre0 += wsum[q];
+    auto pre = [&](int j) { return pre0 + __popc(keep & ((1u << j) - 1u)); };
     // a row piece's first entry records the prefix there
     #pragma unroll
-    for (int it = 0; it < kHIters; ++it) {
-        const int64_t e = base + it * kBlock + (int64_t)threadIdx.x;
-        const int64_t v = u0 + li[it];
-        if (e < end && e == max(rp[v], base)) {
-            if (kLds) wbase[li[it]] = pre[it]; else g_base[v] = pre[it];
+    for (int j = 0; j < kPer; ++j) {
+        const int64_t e = t0 + j;
+        if (e < erel && e == max(R.start(li[j]), (int64_t)0)) {
+            if (kLds) wbase[li[j]] = pre(j); else o.g_base[u0 + li[j]] = pre(j);
         }
     }
     __syncthreads();
     // a row piece's last entry: its kept count; a whole row stores it, a piece adds it
     // (and the same for the lower-priority entries of a dynamic handle)
     #pragma unroll
-    for (int it = 0; it < kHIters; ++it) {
-        const int64_t e = base + it * kBlock + (int64_t)threadIdx.x;
-        const int64_t v = u0 + li[it];
-        if (e < end) {
-            const int64_t r0 = rp[v], r1 = rp[v + 1];
-            if (e == min(r1, end) - 1) {
-                const int32_t b0 = kLds ? wbase[li[it]] : g_base[v];
-                const int32_t cnt = pre[it] + (int32_t)((keep >> it) & 1u) - b0;
-                const int32_t lc = (int32_t)(e + 1 - max(r0, base)) - cnt;
-                const bool whole = r0 >= base && r1 <= end;
-                int32_t off = 0, loff = 0;
-                if (whole) hcnt[v] = cnt;
-                else if (cnt > 0) off = atomicAdd(&hcnt[v], cnt);
-                if (o.lcol) {
-                    if (whole) o.lcnt[v] = lc;
-                    else if (lc > 0) loff = atomicAdd(&o.lcnt[v], lc);
-                }
-                if (kLds) { woff[li[it]] = off; wloff[li[it]] = loff; }
-                else { g_off[v] = off; if (o.lcol) o.g_loff[v] = loff; }
-            }
+    for (int j = 0; j < kPer; ++j) {
+        const int64_t e = t0 + j;
+        if (e >= erel) continue;
+        const int64_t r0 = R.start(li[j]), r1 = R.stop(li[j]);
+        if (e != min(r1, erel) - 1) continue;
+        const int64_t v = u0 + li[j];
+        const int32_t b0 = kLds ? wbase[li[j]] : o.g_base[v];
+        const int32_t c = pre(j) + (int32_t)((keep >> j) & 1u) - b0;
+        const int32_t lc = (int32_t)(e + 1 - max(r0, (int64_t)0)) - c;
+        const bool whole = r0 >= 0 && r1 <= erel;
+        int32_t off = 0, loff = 0;
+        if (whole) o.hcnt[v] = c;
+        else if (c > 0) off = atomicAdd(&o.hcnt[v], c);
+        if (o.lcol) {
+            if (whole) o.lcnt[v] = lc;
+            else if (lc > 0) loff = atomicAdd(&o.lcnt[v], lc);
         }
+        if (kLds) { woff[li[j]] = off; wloff[li[j]] = loff; }
+        else { o.g_off[v] = off; if (o.lcol) o.g_loff[v] = loff; }
     }
     __syncthreads();
     #pragma unroll
-    for (int it = 0; it < kHIters; ++it) {
-        const int64_t e = base + it * kBlock + (int64_t)threadIdx.x;
-        const bool kept = (keep >> it) & 1u;
-        if (!kept && (!o.lcol || e >= end)) continue;
-        const int64_t v = u0 + li[it];
-        const int32_t b0 = kLds ? wbase[li[it]] : g_base[v];
+    for (int j = 0; j < kPer; ++j) {
+        const int64_t e = t0 + j;
+        const bool kept = (keep >> j) & 1u;
+        if (!kept && (!o.lcol || e >= erel)) continue;
+        const int64_t v = u0 + li[j];
+        const int32_t b0 = kLds ? wbase[li[j]] : o.g_base[v];
+        // the row's first slot: the input row start, or the dynamic layout's own
+        const int64_t rs = o.hrp == rp ? (li[j] == 0 ? rp[u0] : base + R.start(li[j])) : o.hrp[v];
         if (kept) {
-            const int32_t off = kLds ? woff[li[it]] : g_off[v];
-            o.hcol[o.hrp[v] + off + (pre[it] - b0)] = cu[it];
+            const int32_t off = kLds ? woff[li[j]] : o.g_off[v];
+            o.hcol[rs + off + (pre(j) - b0)] = cu[j];
         } else {
-            const int32_t loff = kLds ? wloff[li[it]] : o.g_loff[v];
-            const int32_t rank = (int32_t)(e - max(rp[v], base)) - (pre[it] - b0);
-            o.lcol[o.hrp[v] + loff + rank] = cu[it];
+            const int32_t loff = kLds ? wloff[li[j]] : o.g_loff[v];
+            const int32_t rank = (int32_t)(e - max(R.start(li[j]), (int64_t)0)) - (pre(j) - b0);
+            o.lcol[rs + loff + rank] = cu[j];
         }
     }
 }
@@ -261,7 +275,8 @@ template <bool kUserKeys>
 __global__ void __launch_bounds__(kBlock) k_orient(const int64_t* rp, const int32_t* ci, const uint64_t* key,
                                                    const uint8_t* q8, uint64_t seed, int64_t nnz,
                                                    const int32_t* brow, OrientOut o) {
-    __shared__ int32_t wst[kHWin];      // row starts relative to the range (the first row: <= 0)
+    __shared__ int32_t wst[kHWin + 1];  // row starts relative to the range (the first: <= 0), then the
+                                        // last row's end (beyond the range: kHE + 1)
     __shared__ uint64_t wkey[kHWin];    // row keys
     __shared__ int32_t wbase[kHWin];    // prefix at each row piece's first entry
     __shared__ int32_t woff[kHWin];     // offset of each row piece inside its row
@@ -270,9 +285,11 @@ __global__ void __launch_bounds__(kBlock) k_orient(const int64_t* rp, const int3
     const int64_t u0 = brow[blockIdx.x], u1 = brow[blockIdx.x + 1];
     const int64_t w = u1 - u0 + 1;
     if (w <= kHWin) {   // uniform over the workgroup
-        for (int64_t i = threadIdx.x; i < w; i += kBlock) {
-            wst[i] = (int32_t)max<int64_t>(rp[u0 + i] - base, i == 0 ? INT32_MIN : 0);
-            wkey[i] = key[u0 + i];
+        for (int64_t i = threadIdx.x; i <= w; i += kBlock) {
+            const int64_t r = rp[u0 + i] - base;   // i = w: the end of row u1
+            // past the range: kHE + 1 (a row running past the range is not whole)
+            wst[i] = (int32_t)(i == 0 ? max<int64_t>(r, INT32_MIN) : min<int64_t>(r, kHE + 1));
+            if (i < w) wkey[i] = key[u0 + i];
         }
         __syncthreads();
         orient_body<kUserKeys, true>(rp, ci, key, q8, seed, nnz, u0, u1, o, wst, wkey, wbase, woff, wloff);
@@ -281,26 +298,21 @@ __global__ void __launch_bounds__(kBlock) k_orient(const int64_t* rp, const int3
     }
 }
 
-// Dense-block test, one wave per 16-row block: the block's oriented entries as
-// (column block << 4 | row) keys in LDS, sorted (bitonic), nonzero tiles = distinct
-// column blocks.  dflag[I] = 1 and dtcnt[I] = tiles if the block is dense.
-// kFill: for dense blocks (dflag already scanned into dpos, dtcnt into dfirst), writes
-// the tiles' column blocks and bitmaps and the block's list slot.
-template <bool kFill>
-__global__ void __launch_bounds__(kBlock) k_dense(const int64_t* rp, const int32_t* hcol, const int32_t* hcnt,
-                                                  int64_t n, int64_t nI, int dense_min, int32_t* dflag,
-                                                  int32_t* dtcnt, const int32_t* dpos, int32_t* drb, int32_t* dptr,
-                                                  int32_t* dcol, uint32_t* dbits) {
-    __shared__ uint64_t skey[kWpb][kDenseCap];
-    __shared__ uint32_t sbits[kWpb][kDenseTiles * 8];
+// Dense-block test, one wave per 16-row block: the number of nonzero tiles is the
+// number of distinct column blocks among the block's oriented entries, counted with
+// an open-addressing set in LDS.  dflag[I] = 1 and dtcnt[I] = tiles if the block is
+// dense (at most 64 tiles, at least dense_min entries per tile on average).
+__global__ void __launch_bounds__(kBlock) k_dense_test(const int64_t* rp, const int32_t* hcol, const int32_t* hcnt,
+                                                       int64_t n, int64_t nI, int dense_min, int32_t* dflag,
+                                                       int32_t* dtcnt) {
+    constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+    __shared__ uint32_t tab[kWpb][2 * kDenseCap];
     __shared__ int32_t srow[kWpb][17];
     const int lane = lane_id(), wid = threadIdx.x / kWave;
-    uint64_t* sk = skey[wid];
+    uint32_t* T = tab[wid];
     int32_t* sr = srow[wid];
     const int64_t nwaves = (int64_t)gridDim.x * kWpb;
     for (int64_t I = (int64_t)blockIdx.x * kWpb + wid; I < nI; I += nwaves) {
-        if (kFill && !dflag[I]) continue;
-        // entries per row of the block and their prefix (lanes 0..15)
         const int64_t v = I * 16 + lane;
         const int32_t c = lane < 16 && v < n ? hcnt[v] : 0;
         int32_t incl = c;
@@ -310,12 +322,64 @@ __global__ void __launch_bounds__(kBlock) k_dense(const int64_t* rp, const int32
             if (lane >= off) incl += o;
         }
         const int32_t total = __shfl(incl, 15, kWave);
-        if (!kFill) {
-            if (total == 0 || total > kDenseCap) {
-                if (lane == 0) { dflag[I] = 0; dtcnt[I] = 0; }
-                continue;
+        // a dense block holds at least dense_min entries (one tile) and at most the cap
+        if (total == 0 || total > kDenseCap || total < dense_min) {
+            if (lane == 0) { dflag[I] = 0; dtcnt[I] = 0; }
+            continue;
+        }
+        int bits = 6;
+        while ((1 << bits) < 2 * total) ++bits;   // table of 2^bits >= 2 * total slots
+        const uint32_t mask = (1u << bits) - 1u;
+        wave_sync_lds();
+        if (lane < 16) sr[lane + 1] = incl;
+        if (lane == 0) sr[0] = 0;
+        for (int k = lane; k <= (int)mask; k += kWave) T[k] = kEmpty;
+        wave_sync_lds();
+        int fresh = 0;
+        for (int k = lane; k < total; k += kWave) {
+            int r = 0;
+            while (sr[r + 1] <= k) ++r;
+            const uint32_t J = (uint32_t)hcol[rp[I * 16 + r] + (k - sr[r])] >> 4;
+            uint32_t h = (J * 2654435761u) >> (32 - bits);
+            for (;;) {
+                const uint32_t old = atomicCAS(&T[h], kEmpty, J);
+                if (old == kEmpty) { ++fresh; break; }
+                if (old == J) break;
+                h = (h + 1) & mask;
             }
         }
+        for (int off = kWave / 2; off > 0; off >>= 1) fresh += __shfl_xor(fresh, off, kWave);
+        const bool dense = fresh <= kDenseTiles && (int64_t)total >= (int64_t)dense_min * fresh;
+        if (lane == 0) { dflag[I] = dense ? 1 : 0; dtcnt[I] = dense ? fresh : 0; }
+    }
+}
+
+// Tiles of the dense blocks (dflag set; dpos = their list slots, dtcnt = their first
+// tiles), one wave per block: the block's entries as (column << 4 | row) keys in
+// LDS, sorted (bitonic), tile = run of one column block; bitmaps built in LDS and
+// written out, with the tiles' column blocks and the block's list slot.
+__global__ void __launch_bounds__(kBlock) k_dense_fill(const int64_t* rp, const int32_t* hcol, const int32_t* hcnt,
+                                                       int64_t n, int64_t nI, const int32_t* dflag, const int32_t* dtcnt,
+                                                       const int32_t* dpos, int32_t* drb, int32_t* dptr, int32_t* dcol,
+                                                       uint32_t* dbits) {
+    __shared__ uint64_t skey[kWpb][kDenseCap];
+    __shared__ uint32_t sbits[kWpb][kDenseTiles * 8];
+    __shared__ int32_t srow[kWpb][17];
+    const int lane = lane_id(), wid = threadIdx.x / kWave;
+    uint64_t* sk = skey[wid];
+    int32_t* sr = srow[wid];
+    const int64_t nwaves = (int64_t)gridDim.x * kWpb;
+    for (int64_t I = (int64_t)blockIdx.x * kWpb + wid; I < nI; I += nwaves) {
+        if (!dflag[I]) continue;
+        const int64_t v = I * 16 + lane;
+        const int32_t c = lane < 16 && v < n ? hcnt[v] : 0;
+        int32_t incl = c;
+        #pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+            const int32_t o = __shfl_up(incl, off, kWave);
+            if (lane >= off) incl += o;
+        }
+        const int32_t total = __shfl(incl, 15, kWave);
         wave_sync_lds();
         if (lane < 16) sr[lane + 1] = incl;
         if (lane == 0) sr[0] = 0;
@@ -348,19 +412,7 @@ __global__ void __launch_bounds__(kBlock) k_dense(const int64_t* rp, const int32
                 wave_sync_lds();
             }
         }
-        // tiles = distinct column blocks among the first `total` keys
-        int tiles = 0;
-        for (int k0 = 0; k0 < total; k0 += kWave) {
-            const int k = k0 + lane;
-            const bool head = k < total && (k == 0 || (sk[k] >> 8) != (sk[k - 1] >> 8));
-            tiles += __popcll(ballot(head));
-        }
-        if (!kFill) {
-            const bool dense = tiles <= kDenseTiles && (int64_t)total >= (int64_t)dense_min * tiles;
-            if (lane == 0) { dflag[I] = dense ? 1 : 0; dtcnt[I] = dense ? tiles : 0; }
-            continue;
-        }
-        // fill: tile of each key = number of heads at or before it, minus one
+        // tile of each key = number of heads at or before it, minus one
         for (int k = lane; k < kDenseTiles * 8; k += kWave) sbits[wid][k] = 0;
         wave_sync_lds();
         const int32_t t0 = dtcnt[I];   // first tile (scanned)
@@ -381,7 +433,7 @@ __global__ void __launch_bounds__(kBlock) k_dense(const int64_t* rp, const int32
             seen += __popcll(hb);
         }
         wave_sync_lds();
-        for (int k = lane; k < tiles * 8; k += kWave) dbits[(int64_t)t0 * 8 + k] = sbits[wid][k];
+        for (int k = lane; k < seen * 8; k += kWave) dbits[(int64_t)t0 * 8 + k] = sbits[wid][k];
         if (lane == 0) {
             const int32_t p = dpos[I];
             drb[p] = (int32_t)I;
@@ -432,8 +484,16 @@ __global__ void k_hyb_class(const int32_t* hcnt, const int32_t* dflag, int64_t n
             }
         }
     }
+    // one atomic per workgroup (a same-address atomic per wave serialises the kernel)
+    __shared__ int64_t part[kWpb];
     for (int off = kWave / 2; off > 0; off >>= 1) c1 += __shfl_xor(c1, off, kWave);
-    if (lane_id() == 0 && c1) atomicAdd((unsigned long long*)n_c1, (unsigned long long)c1);
+    if (lane_id() == 0) part[threadIdx.x / kWave] = c1;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int q = 0; q < kWpb; ++q) t += part[q];
+        if (t) atomicAdd((unsigned long long*)n_c1, (unsigned long long)t);
+    }
 }
 
 __global__ void k_hyb_lists(const int64_t* flag, const int64_t* pos, int64_t n, int32_t* light, int32_t* heavy,
@@ -552,6 +612,24 @@ __device__ inline uint32_t dense_product(const HybArgs& a, int64_t t0, int nt, c
     return rows_of(acc);
 }
 
+// Does a row of c entries name a vertex whose bit is set in m?  One lane scans the
+// row four entries at a time (four loads, then four bit gathers in flight) and stops
+// after the group that holds the first hit; *read counts the entries loaded.
+// Deleted entries of a dynamic handle (-1) are skipped.
+__device__ inline bool scan4(const int32_t* row, int32_t c, const uint32_t* m, int64_t* read) {
+    for (int32_t k = 0; k < c; k += 4) {
+        int32_t u[4];
+        #pragma unroll
+        for (int j = 0; j < 4; ++j) u[j] = k + j < c ? row[k + j] : -1;
+        bool hit = false;
+        #pragma unroll
+        for (int j = 0; j < 4; ++j) hit |= u[j] >= 0 && bit_of(m, u[j]);
+        *read += min(c - k, 4);
+        if (hit) return true;
+    }
+    return false;
+}
+
 // Phase 1 of round r >= 2 (round 1's candidates come from the build).
 __device__ void hyb_p1(const HybArgs& a, int r) {
     __shared__ uint32_t sbits[kWpb][kDenseTiles * 8];
@@ -579,15 +657,7 @@ __device__ void hyb_p1(const HybArgs& a, int r) {
         uint32_t m = 0;
         if (i < nl[0]) {
             const int32_t v = L[0][i];
-            const int64_t e0 = a.rp[v];
-            const int32_t c = a.hcnt[v];
-            int32_t k = 0;
-            bool blocked = false;
-            for (; k < c; ++k) {
-                const int32_t u = a.hcol[e0 + k];
-                if (u >= 0 && bit_of(a.A, u)) { blocked = true; ++k; break; }
-            }
-            ent += k;
+            const bool blocked = scan4(a.hcol + a.rp[v], a.hcnt[v], a.A, &ent);
             ++verts;
             if (!blocked) { w = v >> 5; m = 1u << (v & 31); ++n_cand; }
         }
@@ -661,15 +731,7 @@ __device__ void hyb_p2(const HybArgs& a, int r) {
                 w = v >> 5; m = 1u << (v & 31);
                 if (a.dround) a.dround[v] = r;
             } else {
-                const int64_t e0 = a.rp[v];
-                const int32_t c = a.hcnt[v];
-                int32_t k = 0;
-                bool hit = false;
-                for (; k < c; ++k) {
-                    const int32_t u = a.hcol[e0 + k];
-                    if (u >= 0 && bit_of(a.S, u)) { hit = true; ++k; break; }
-                }
-                ent += k;
+                const bool hit = scan4(a.hcol + a.rp[v], a.hcnt[v], a.S, &ent);
                 ++verts;
                 if (hit) {
                     w = v >> 5; m = 1u << (v & 31); ++n_out;
@@ -813,6 +875,20 @@ __global__ void k_dense_slots(const int32_t* dflag, const int32_t* dpos, int64_t
 
 int64_t hyb_blocks(int64_t nnz) { return ceil_div(nnz, kHE); }
 
+// round-1 classes (bitmaps, candidate count) and the light / heavy row lists
+int hyb_lists_build(mis_graph* g, const int32_t* dflag, hipStream_t s) {
+    const int64_t n = g->n;
+    if (n > 0) {
+        const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(n, kBlock), 1024);
+        hipLaunchKernelGGL(k_hyb_class, dim3(blocks), dim3(kBlock), 0, s, g->hcnt, dflag, n, g->hflag, g->s1, g->a1,
+                           &g->meta->n_c1);
+        TC_HIP(hipGetLastError());
+    }
+    TC_CHECK(scan_excl_i64(g->hflag, g->hpos, n, g->hpos + n, (int64_t*)g->scan_tmp, s));
+    HLAUNCH(k_hyb_lists, n, g->hflag, g->hpos, n, g->hl1[0], g->hl1[1], g->meta);
+    return MIS_OK;
+}
+
 int build_hybrid(mis_graph* g, hipStream_t s) {
     const int64_t n = g->n, nnz = g->nnz, nI = g->nI;
     TC_HIP(hipMemsetAsync(g->meta, 0, sizeof(Meta), s));
@@ -846,15 +922,14 @@ int build_hybrid(mis_graph* g, hipStream_t s) {
     const bool dense = g->dense_min > 0 && nnz > 0;
     if (dense) {
         const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(nI, kWpb), 16384);
-        hipLaunchKernelGGL(k_dense<false>, dim3(blocks), dim3(kBlock), 0, s, g->row_ptr, g->hcol, g->hcnt, n, nI,
-                           g->dense_min, g->dflag, g->dtcnt, (const int32_t*)nullptr, (int32_t*)nullptr,
-                           (int32_t*)nullptr, (int32_t*)nullptr, (uint32_t*)nullptr);
+        hipLaunchKernelGGL(k_dense_test, dim3(blocks), dim3(kBlock), 0, s, g->row_ptr, g->hcol, g->hcnt, n, nI,
+                           g->dense_min, g->dflag, g->dtcnt);
         TC_HIP(hipGetLastError());
         // list slots of dense blocks and their first tiles (dflag keeps the flags)
         TC_CHECK(scan_excl_i32(g->dflag, g->dpos, nI, &g->meta->n_dense, (int32_t*)g->scan_tmp, s));
         TC_CHECK(scan_excl_i32(g->dtcnt, g->dtcnt, nI, &g->meta->n_dtiles, (int32_t*)g->scan_tmp, s));
-        hipLaunchKernelGGL(k_dense<true>, dim3(blocks), dim3(kBlock), 0, s, g->row_ptr, g->hcol, g->hcnt, n, nI,
-                           g->dense_min, g->dflag, g->dtcnt, g->dpos, g->drb, g->dptr, g->dcol, g->dbits);
+        hipLaunchKernelGGL(k_dense_fill, dim3(blocks), dim3(kBlock), 0, s, g->row_ptr, g->hcol, g->hcnt, n, nI,
+                           g->dflag, g->dtcnt, g->dpos, g->drb, g->dptr, g->dcol, g->dbits);
         TC_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_dense_end, dim3(1), dim3(1), 0, s, g->meta, g->dptr);
         TC_HIP(hipGetLastError());
@@ -862,22 +937,16 @@ int build_hybrid(mis_graph* g, hipStream_t s) {
     }
     build_mark(g, s);
     // 3. round-1 classes and lists
-    HLAUNCH(k_hyb_class, n, g->hcnt, dense ? g->dflag : nullptr, n, g->hflag, g->s1, g->a1, &g->meta->n_c1);
-    TC_CHECK(scan_excl_i64(g->hflag, g->hpos, n, g->hpos + n, (int64_t*)g->scan_tmp, s));
-    HLAUNCH(k_hyb_lists, n, g->hflag, g->hpos, n, g->hl1[0], g->hl1[1], g->meta);
+    TC_CHECK(hyb_lists_build(g, dense ? g->dflag : nullptr, s));
     return MIS_OK;
 }
 
 int hyb_classify(mis_graph* g, hipStream_t s);
 
-// round-1 classes and lists from the rows' current counts
+// round-1 classes and lists from the rows' current counts (after edits)
 int hyb_classify(mis_graph* g, hipStream_t s) {
-    const int64_t n = g->n;
     HLAUNCH(k_hyb_meta_clear, 1, g->meta);
-    HLAUNCH(k_hyb_class, n, g->hcnt, g->dense_min > 0 ? g->dflag : nullptr, n, g->hflag, g->s1, g->a1, &g->meta->n_c1);
-    TC_CHECK(scan_excl_i64(g->hflag, g->hpos, n, g->hpos + n, (int64_t*)g->scan_tmp, s));
-    HLAUNCH(k_hyb_lists, n, g->hflag, g->hpos, n, g->hl1[0], g->hl1[1], g->meta);
-    return MIS_OK;
+    return hyb_lists_build(g, g->dense_min > 0 ? g->dflag : nullptr, s);
 }
 
 int hyb_init(mis_graph* g, hipStream_t s) {
