@@ -16,7 +16,7 @@ kernel, and the CPU oracle and sequential greedy timed on this host.
 
 "batch": 4,096 independent graphs (sizes log-uniform over 500..200,000 vertices,
 half Erdos-Renyi with average degree 4..32, half R-MAT with 8..24) solved as one
-block-diagonal batch (mis_build_batch + mis_solve_batch) against one graph per
+block-diagonal batch (mis_build_batch + mis_solve_union) against one graph per
 build+solve; graphs/s and Medges/s.
 
 "serving": a pool of requests (log-uniform 1e3..4e6 vertices, Erdos-Renyi / R-MAT /
@@ -160,7 +160,7 @@ def bench_batch(a, torch, gen, tcmis):
     def batched():
         t = time.perf_counter()
         h = tcmis.mis_build_batch(rp, ci, off, workspace=ws, launch="direct", **cfg)
-        _, st, r, _ = tcmis.mis_solve_batch(h, out=out, trace_cap=0)
+        _, st, r, _ = tcmis.mis_solve_union(h, out=out, trace_cap=0)
         tcmis.mis_free_tiles(h)
         return time.perf_counter() - t, int(st["rounds"]), r
 
@@ -171,12 +171,12 @@ def bench_batch(a, torch, gen, tcmis):
     g_rounds = reps[-1][2]
     # solve only, the round loop captured once and replayed
     h = tcmis.mis_build_batch(rp, ci, off, workspace=ws, launch="graph", **cfg)
-    tcmis.mis_solve_batch(h, out=out, trace_cap=0)
+    tcmis.mis_solve_union(h, out=out, trace_cap=0)
     torch.cuda.synchronize()
     ts = []
     for _ in range(3):
         t = time.perf_counter()
-        _, st_g, _, _ = tcmis.mis_solve_batch(h, out=out, trace_cap=0)
+        _, st_g, _, _ = tcmis.mis_solve_union(h, out=out, trace_cap=0)
         ts.append(time.perf_counter() - t)
     g_solve_s = float(np.median(ts))
     graph_flag = st_g["graph"]
@@ -431,7 +431,7 @@ def main():
 
     same = bool(torch.equal(out_h, out_csr) and torch.equal(out_h, out_t) and torch.equal(out_h, out_h2))
     m = g.m
-    hyb_names = ["keys", "orientation row search", "orientation", "dense blocks", "classes and lists"]
+    hyb_names = ["keys", "orientation row search", "orientation", "dense blocks"]
     res = {
         "metric": "MIS Medges/s per graph at 1 GPU (tile vs CSR); batched graphs/s + p50/p99",
         "value": round(m / step_s / 1e6, 3),

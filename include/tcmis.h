@@ -19,8 +19,12 @@
  *   - Return value: MIS_OK (0) or a negative mis_status.  Argument errors are
  *     detected on the host before any device work is enqueued.  After an error
  *     mis_last_error() returns a thread-local message with details.
- *   - Handles are not thread-safe: one solve at a time per handle (a handle owns
- *     its per-round state).  Different handles may be used concurrently.
+ *   - A built handle's structure is read-only to solves.  A solve keeps its round
+ *     state either in a caller's scratch (mis_solve with scratch != NULL: any
+ *     number of such solves of one handle may run concurrently, on different
+ *     streams or threads, each with its own scratch) or in the handle's own
+ *     round state (scratch == NULL: one such solve at a time per handle).
+ *     mis_update_edges changes a handle and must not overlap any solve of it.
  */
 #ifndef TCMIS_H
 #define TCMIS_H
@@ -209,14 +213,36 @@ int mis_build_tiles(const mis_csr* csr, const mis_build_opts* opts, void* worksp
 int mis_graph_bytes(const mis_graph* g, size_t* bytes);
 
 /*
- * Solves: writes in_set[v] = 1 if vertex v (input id) is in the independent set,
- * else 0.  in_set: DEVICE uint8[n].  stats: optional HOST.
+ * Device bytes of one solve's round state for this handle (control block, trace
+ * ring, counters, per-vertex status bitmaps or words, next-round work lists), the
+ * scratch that mis_solve takes.  Host-only.  Errors: MIS_EINVAL (null argument).
+ */
+int mis_solve_scratch_bytes(const mis_graph* g, size_t* bytes);
+
+/*
+ * Runs the rounds of Algorithm 2 (Section 3.1: Phase 1 candidates, Phase 2
+ * N_c = A x C, Phase 3 updates, until no vertex is undecided) over a built handle
+ * and writes in_set[v] = 1 if vertex v (input id) is in the independent set, else 0.
+ *   in_set        : DEVICE uint8[n], caller-owned.
+ *   max_rounds    : > 0 stops after that many rounds (vertices still undecided are
+ *                   written as 0; stats->rounds tells how many ran); 0 = run to
+ *                   completion.
+ *   scratch       : DEVICE, 256-byte aligned, at least mis_solve_scratch_bytes
+ *                   bytes, caller-owned; holds this solve's round state, so that
+ *                   the handle is only read and concurrent solves of one handle
+ *                   with different scratch buffers are allowed.  NULL = the round
+ *                   state inside the handle's workspace (then one solve at a time
+ *                   per handle, and repeated solves may replay a captured graph of
+ *                   the round loop, launch = AUTO or GRAPH).
+ *   scratch_bytes : its size (ignored when scratch is NULL).
+ *   stats         : optional HOST.
  * Enqueues `poll_rounds` rounds at a time and synchronises `stream` after each
  * batch to read the alive counter; returns when every vertex is decided.
- * max_rounds > 0 stops after that many rounds (vertices still undecided are
- * written as 0; stats->rounds tells how many ran); 0 = run to completion.
+ * Errors: MIS_EINVAL (null handle or output, negative max_rounds, scratch too small
+ * or misaligned), MIS_EINTERNAL (round limit, device-side check), MIS_EHIP.
  */
-int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, mis_stats* stats, void* stream);
+int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, void* scratch, size_t scratch_bytes,
+              mis_stats* stats, void* stream);
 
 /*
  * Batches: `count` independent graphs solved together as one block-diagonal graph.
@@ -235,14 +261,44 @@ int mis_build_batch(const mis_csr* csr, int32_t count, const int64_t* offsets, c
                     void* workspace, size_t workspace_bytes, void* stream, mis_graph** out);
 
 /*
- * Solves a batch built with mis_build_batch.  in_set: DEVICE uint8[csr->n] (graph g's
+ * Solves a batch built with mis_build_batch (the rounds of Algorithm 2 over the
+ * block-diagonal union; Section 3.1).  in_set: DEVICE uint8[csr->n] (graph g's
  * answer is in_set[offsets[g] .. offsets[g+1]-1]).  stats: optional HOST, for the
  * whole batch (rounds = the largest per-graph round count).  graph_rounds (HOST
  * int32[count]) and graph_in (HOST int64[count]), optional: each graph's own number
- * of rounds and set size.  Synchronises `stream`.
+ * of rounds and set size.  Uses the handle's own round state.  Synchronises `stream`.
+ * Errors: MIS_EINVAL (null handle, or one not built by mis_build_batch), MIS_EHIP,
+ * MIS_EINTERNAL.
  */
-int mis_solve_batch(mis_graph* batch, uint8_t* in_set, mis_stats* stats, int32_t* graph_rounds, int64_t* graph_in,
+int mis_solve_union(mis_graph* batch, uint8_t* in_set, mis_stats* stats, int32_t* graph_rounds, int64_t* graph_in,
                     void* stream);
+
+/*
+ * Solves independently built handles together, without concatenating or rebuilding
+ * anything: the rounds of Algorithm 2 (Section 3.1) run for all graphs at once, every
+ * round kernel one launch whose workgroups are split into per-graph shares over each
+ * handle's own (read-only) structure, with every graph's round state in `scratch`.
+ * Graphs share no edge, so each graph's result and number of rounds equal its solve
+ * alone.
+ *   graphs        : HOST array of `count` single-graph handles built by
+ *                   mis_build_tiles with the hybrid path (they may differ in size,
+ *                   options and dense-block threshold).
+ *   in_sets       : HOST array of `count` DEVICE uint8 outputs, in_sets[i] of
+ *                   graphs[i]'s n bytes (input ids).
+ *   scratch       : DEVICE, 256-byte aligned, at least mis_solve_batch_scratch_bytes
+ *                   for these handles, caller-owned.
+ *   stats         : optional HOST, for the whole batch (rounds = the largest
+ *                   per-graph round count, n_in = the total set size).
+ *   graph_rounds  : optional HOST int32[count]; graph_in: optional HOST int64[count].
+ * Rounds are enqueued poll_rounds (the largest of the handles') at a time; the
+ * stream is synchronised after each batch of rounds.  The handles are only read, so
+ * they may be solved elsewhere at the same time with other scratch.
+ * Errors: MIS_EINVAL (a null or non-hybrid or batch handle, a null output, scratch
+ * too small or misaligned), MIS_EINTERNAL (round limit, device-side check), MIS_EHIP.
+ */
+int mis_solve_batch_scratch_bytes(mis_graph* const* graphs, int32_t count, size_t* bytes);
+int mis_solve_batch(mis_graph* const* graphs, int32_t count, uint8_t* const* in_sets, void* scratch,
+                    size_t scratch_bytes, mis_stats* stats, int32_t* graph_rounds, int64_t* graph_in, void* stream);
 
 /*
  * Autotuning of implementation choices that leave the result unchanged (path,
@@ -334,6 +390,20 @@ int mis_session_admit(mis_session* s, const mis_csr* csr, int32_t csr_on_host, c
  */
 int mis_session_progress(mis_session* s, int32_t wait, mis_done* done, int32_t cap, int32_t* n_done);
 
+/*
+ * The two halves of mis_session_progress, for callers that drive them separately.
+ * mis_session_step advances, without waiting, every live request whose last enqueued
+ * rounds have finished: its next rounds_per_step rounds (the rounds stay on the
+ * device between steps), or its output once no vertex is undecided; *advanced
+ * (HOST, optional) receives how many it advanced.  mis_session_poll retires
+ * requests whose output has landed into done[0 .. *n_done-1] (HOST, at most cap),
+ * freeing their slot and arena region; it enqueues nothing.  wait = 1 returns once
+ * at least one request retired or no request is waiting for its output.
+ * Errors: MIS_EINVAL, MIS_EHIP.
+ */
+int mis_session_step(mis_session* s, int32_t* advanced);
+int mis_session_poll(mis_session* s, int32_t wait, mis_done* done, int32_t cap, int32_t* n_done);
+
 /* Live requests, arena bytes in use and the largest free arena region (HOST, each optional). */
 int mis_session_query(const mis_session* s, int32_t* live, size_t* bytes_in_use, size_t* largest_free);
 
@@ -344,9 +414,10 @@ void mis_session_destroy(mis_session* s);
  * Durations (HOST float[cap], milliseconds, from HIP events on the build stream) of
  * the build stages of a handle built with opts.timing = 1; *count receives the
  * number of stages.  Stages (after validation, which is not timed): keys, then
- *   hybrid path: orientation row search (with clearing the counts), orientation
- *                (the orientation pass alone), dense blocks (0 if none), round-1
- *                classes and lists (an empty graph has the keys stage only);
+ *   hybrid path: orientation row search (with clearing the counts and the
+ *                blocks' column signatures), orientation (the orientation pass
+ *                alone), dense blocks (0 if none); an empty graph has the keys
+ *                stage only;
  *   tile path:   vertex order, tiles;
  *   CSR path:    vertex lists.
  * Synchronises the last event.  Errors: MIS_EINVAL (no timing), MIS_EHIP.

@@ -581,125 +581,147 @@ int host_rcm(const int64_t* rp, const int32_t* ci, int64_t n, std::vector<int32_
 int64_t hyb_blocks(int64_t nnz);
 int64_t dyn_counter_words();
 
-size_t layout(mis_graph* g, char* base) {
+namespace {
+// hands out 256-byte aligned arrays from base (base == nullptr: sizes only)
+struct Carver {
+    char* base;
     size_t off = 0;
-    auto take = [&](auto** p, size_t bytes) {
+    template <typename P>
+    void take(P** p, size_t bytes) {
         off = (off + 255) & ~(size_t)255;
-        if (base) *p = reinterpret_cast<std::remove_pointer_t<decltype(p)>>(base + off);
+        if (base) *p = reinterpret_cast<P*>(base + off);
         off += bytes ? bytes : 8;
-    };
-    const int64_t n = g->n, nnz = g->nnz;
-    // ctrl, meta and the trace ring first and together: a solve reads them back with one copy
-    take(&g->ctrl, sizeof(Ctrl));
-    take(&g->meta, sizeof(Meta));
-    take(&g->trace, sizeof(TraceRec) * kTraceCap);
-    take(&g->stripes, sizeof(int64_t) * 2 * kStripes * kStripeWords);
-    take(&g->key, (size_t)n * 8);
-    if (g->count > 0) {
-        take(&g->goff, (size_t)(g->count + 1) * 8);
-        take(&g->g_rounds, (size_t)g->count * 4);
-        take(&g->g_in, (size_t)g->count * 8);
     }
-    take(&g->scan_tmp, (size_t)scan_scratch_elems(std::max(n, nnz) + 1) * 8);
+};
+}  // namespace
+
+size_t layout_state(GraphCore* g, char* base, bool with_trace) {
+    Carver c{base};
+    const int64_t n = g->n;
+    // ctrl, the sizes and the trace ring first and together: a solve reads them back
+    // with one copy
+    c.take(&g->ctrl, sizeof(Ctrl));
+    c.take(&g->smeta, sizeof(Meta));
+    if (with_trace) c.take(&g->trace, sizeof(TraceRec) * kTraceCap);
+    else g->trace = nullptr;
+    c.take(&g->stripes, sizeof(int64_t) * 2 * kStripes * kStripeWords);
+    if (g->count > 0) {
+        c.take(&g->g_rounds, (size_t)g->count * 4);
+        c.take(&g->g_in, (size_t)g->count * 8);
+    }
+    if (g->path == MIS_PATH_HYBRID) {
+        const int64_t nI = ceil_div(n, 16), nw = ceil_div(n, 64) * 2 + 2;   // bitmap words (whole waves)
+        c.take(&g->hA, (size_t)nw * 4);
+        c.take(&g->hS, (size_t)nw * 4);
+        for (int b = 0; b < 2; ++b) {
+            c.take(&g->hact[b][0], (size_t)n * 4);
+            c.take(&g->hact[b][1], (size_t)n * 4);
+            c.take(&g->hact[b][2], (size_t)(g->dense_min > 0 ? nI : 0) * 4);
+        }
+        if (g->count > 0) c.take(&g->dround, (size_t)n * 4);
+    } else if (g->path == MIS_PATH_CSR) {
+        for (int b = 0; b < 2; ++b)
+            for (int k = 0; k < 2; ++k) c.take(&g->act[b][k], (size_t)n * 4);
+        c.take(&g->st, (size_t)n * 4);
+        c.take(&g->ak, (size_t)n * 8);
+    } else {
+        const int T = g->tile;
+        const int64_t nI = ceil_div(n, T);
+        const int64_t chunk_cap = (g->orient ? g->nnz / 2 + 1 : g->nnz + 1) / (T == 16 ? 64 : 16) + nI + 1;
+        for (int b = 0; b < 2; ++b) {
+            c.take(&g->chunks[b], (size_t)chunk_cap * 8);
+            c.take(&g->rbl[b], (size_t)nI * 4);
+        }
+        c.take(&g->rs, (size_t)nI * 8);
+        c.take(&g->hit, (size_t)nI * 4);
+        c.take(&g->inmask, (size_t)nI * 4);
+        c.take(&g->dround, (size_t)nI * T * 4);
+    }
+    return (c.off + 255) & ~(size_t)255;
+}
+
+size_t layout(GraphCore* g, char* base) {
+    Carver c{base};
+    const int64_t n = g->n, nnz = g->nnz;
+    c.take(&g->meta, sizeof(Meta));
+    c.take(&g->key, (size_t)n * 8);
+    if (g->count > 0) c.take(&g->goff, (size_t)(g->count + 1) * 8);
+    c.take(&g->scan_tmp, (size_t)scan_scratch_elems(std::max(n, nnz) + 1) * 8);
     if (g->path == MIS_PATH_HYBRID) {
         g->nI = ceil_div(n, 16);
         const int64_t nI = g->nI, nw = ceil_div(n, 64) * 2 + 2;   // bitmap words (whole waves)
-        take(&g->q8, (size_t)n);
-        take(&g->hbrow, (size_t)(hyb_blocks(nnz) + 2) * 4);
-        take(&g->hbase, (size_t)n * 4);
-        take(&g->hoff, (size_t)n * 4);
+        c.take(&g->q8, (size_t)n);
+        c.take(&g->hbrow, (size_t)(hyb_blocks(nnz) + 2) * 4);
+        c.take(&g->hbase, (size_t)n * 4);
+        c.take(&g->hoff, (size_t)n * 4);
         const int64_t rows = g->dyn_slack > 0 ? nnz + n * (int64_t)g->dyn_slack : nnz;   // slots per orientation
-        take(&g->hcol, (size_t)rows * 4);
-        take(&g->hcnt, (size_t)n * 4);
+        c.take(&g->hcol, (size_t)rows * 4);
+        c.take(&g->hcnt, (size_t)n * 4);
         if (g->dyn_slack > 0) {
-            take(&g->drp, (size_t)(n + 1) * 8);
-            take(&g->lcol, (size_t)rows * 4);
-            take(&g->lcnt, (size_t)n * 4);
-            take(&g->hloff, (size_t)n * 4);
-            take(&g->rS, (size_t)nw * 4);
-            take(&g->rP, (size_t)nw * 4);
-            take(&g->rC, (size_t)nw * 4);
-            take(&g->rlist[0], (size_t)n * 4);
-            take(&g->rlist[1], (size_t)n * 4);
-            take(&g->rflip, (size_t)n * 4);
-            take(&g->rdec, (size_t)n * 4);
-            take(&g->rcnt, (size_t)dyn_counter_words() * 8);
+            c.take(&g->drp, (size_t)(n + 1) * 8);
+            c.take(&g->lcol, (size_t)rows * 4);
+            c.take(&g->lcnt, (size_t)n * 4);
+            c.take(&g->hloff, (size_t)n * 4);
+            c.take(&g->rS, (size_t)nw * 4);
+            c.take(&g->rP, (size_t)nw * 4);
+            c.take(&g->rC, (size_t)nw * 4);
+            c.take(&g->rlist[0], (size_t)n * 4);
+            c.take(&g->rlist[1], (size_t)n * 4);
+            c.take(&g->rflip, (size_t)n * 4);
+            c.take(&g->rdec, (size_t)n * 4);
+            c.take(&g->rcnt, (size_t)dyn_counter_words() * 8);
+            c.take(&g->hflag, (size_t)n * 8);
         }
-        take(&g->hflag, (size_t)n * 8);
-        take(&g->hpos, (size_t)(n + 1) * 8);
-        take(&g->hl1[0], (size_t)n * 4);
-        take(&g->hl1[1], (size_t)n * 4);
-        take(&g->s1, (size_t)nw * 4);
-        take(&g->a1, (size_t)nw * 4);
         if (g->dense_min > 0) {
+            c.take(&g->hsig, (size_t)nI * 8);
             const int64_t tcap = nnz / 2 + 1;   // a dense tile holds at least one oriented entry
-            take(&g->dflag, (size_t)nI * 4);
-            take(&g->dpos, (size_t)(nI + 1) * 4);
-            take(&g->dtcnt, (size_t)(nI + 1) * 4);
-            take(&g->dslot, (size_t)nI * 4);
-            take(&g->drb, (size_t)nI * 4);
-            take(&g->dptr, (size_t)(nI + 1) * 4);
-            take(&g->dcol, (size_t)tcap * 4);
-            take(&g->dbits, (size_t)tcap * 32);
+            c.take(&g->dflag, (size_t)nI * 4);
+            c.take(&g->dpos, (size_t)(nI + 1) * 4);
+            c.take(&g->dtcnt, (size_t)(nI + 1) * 4);
+            c.take(&g->dslot, (size_t)nI * 4);
+            c.take(&g->drb, (size_t)nI * 4);
+            c.take(&g->dptr, (size_t)(nI + 1) * 4);
+            c.take(&g->dcol, (size_t)tcap * 4);
+            c.take(&g->dbits, (size_t)tcap * 32);
         }
-        // per-solve round state
-        take(&g->hA, (size_t)nw * 4);
-        take(&g->hS, (size_t)nw * 4);
-        for (int b = 0; b < 2; ++b) {
-            take(&g->hact[b][0], (size_t)n * 4);
-            take(&g->hact[b][1], (size_t)n * 4);
-            take(&g->hact[b][2], (size_t)(g->dense_min > 0 ? nI : 0) * 4);
-        }
-        if (g->count > 0) take(&g->dround, (size_t)n * 4);
-        return off;
+    } else if (g->path == MIS_PATH_CSR) {
+        c.take(&g->light, (size_t)n * 4);
+        c.take(&g->heavy, (size_t)n * 4);
+        c.take(&g->flag32, (size_t)n * 4);
+    } else {
+        const int T = g->tile;
+        g->nI = ceil_div(n, T);
+        const int64_t nI = g->nI;
+        g->tile_cap = g->orient ? nnz / 2 + 1 : nnz + 1;
+        g->chunk_cap = g->tile_cap / (T == 16 ? 64 : 16) + nI + 1;
+        const int64_t cap = g->tile_cap;
+        c.take(&g->new_id, (size_t)n * 4);
+        c.take(&g->order, (size_t)n * 4);
+        c.take(&g->sk, (size_t)n * 8);
+        c.take(&g->sk2, (size_t)n * 8);
+        c.take(&g->pl, (size_t)n * 4);
+        c.take(&g->pl2, (size_t)n * 4);
+        c.take(&g->sort_tmp, sort_scratch_bytes(std::max(n, nnz)));
+        c.take(&g->ndeg, (size_t)(n + 1) * 4);
+        c.take(&g->brow, (size_t)(ceil_div(nnz, kEntBlock) + 2) * 4);
+        c.take(&g->ent, (size_t)nnz * 8);
+        c.take(&g->ent2, (size_t)nnz * 8);
+        c.take(&g->hsums, (size_t)(ceil_div(nnz, 2048) + 2) * 4);
+        c.take(&g->ecnt, (size_t)(ceil_div(nnz, kEntBlock) + 1) * 4);
+        c.take(&g->rb_ptr, (size_t)(nI + 1) * 8);
+        c.take(&g->rb_chunk, (size_t)(nI + 1) * 8);
+        c.take(&g->tile_col, (size_t)cap * 4);
+        c.take(&g->tile_start, (size_t)cap * 4);
+        c.take(&g->tile_bits, (size_t)cap * (T * T / 32) * 4);
+        if (!g->orient) c.take(&g->key_p, (size_t)nI * T * 8);
+        c.take(&g->hrows, (size_t)nI * 4);
+        c.take(&g->chunks_all, (size_t)g->chunk_cap * 8);
+        c.take(&g->chunks_r1, (size_t)(nI + g->chunk_cap) * 8);
     }
-    if (g->path == MIS_PATH_CSR) {
-        take(&g->light, (size_t)n * 4);
-        take(&g->heavy, (size_t)n * 4);
-        for (int b = 0; b < 2; ++b)
-            for (int k = 0; k < 2; ++k) take(&g->act[b][k], (size_t)n * 4);
-        take(&g->st, (size_t)n * 4);
-        take(&g->ak, (size_t)n * 8);
-        take(&g->flag32, (size_t)n * 4);
-        return off;
-    }
-    const int T = g->tile;
-    g->nI = ceil_div(n, T);
-    const int64_t nI = g->nI;
-    g->tile_cap = g->orient ? nnz / 2 + 1 : nnz + 1;
-    g->chunk_cap = g->tile_cap / (T == 16 ? 64 : 16) + nI + 1;
-    const int64_t cap = g->tile_cap;
-    take(&g->new_id, (size_t)n * 4);
-    take(&g->order, (size_t)n * 4);
-    take(&g->sk, (size_t)n * 8);
-    take(&g->sk2, (size_t)n * 8);
-    take(&g->pl, (size_t)n * 4);
-    take(&g->pl2, (size_t)n * 4);
-    take(&g->sort_tmp, sort_scratch_bytes(std::max(n, nnz)));
-    take(&g->ndeg, (size_t)(n + 1) * 4);
-    take(&g->brow, (size_t)(ceil_div(nnz, kEntBlock) + 2) * 4);
-    take(&g->ent, (size_t)nnz * 8);
-    take(&g->ent2, (size_t)nnz * 8);
-    take(&g->hsums, (size_t)(ceil_div(nnz, 2048) + 2) * 4);
-    take(&g->ecnt, (size_t)(ceil_div(nnz, kEntBlock) + 1) * 4);
-    take(&g->rb_ptr, (size_t)(nI + 1) * 8);
-    take(&g->rb_chunk, (size_t)(nI + 1) * 8);
-    take(&g->tile_col, (size_t)cap * 4);
-    take(&g->tile_start, (size_t)cap * 4);
-    take(&g->tile_bits, (size_t)cap * (T * T / 32) * 4);
-    if (!g->orient) take(&g->key_p, (size_t)nI * T * 8);
-    take(&g->hrows, (size_t)nI * 4);
-    take(&g->chunks_all, (size_t)g->chunk_cap * 8);
-    take(&g->chunks_r1, (size_t)(nI + g->chunk_cap) * 8);
-    for (int b = 0; b < 2; ++b) {
-        take(&g->chunks[b], (size_t)g->chunk_cap * 8);
-        take(&g->rbl[b], (size_t)nI * 4);
-    }
-    take(&g->rs, (size_t)nI * 8);
-    take(&g->hit, (size_t)nI * 4);
-    take(&g->inmask, (size_t)nI * 4);
-    take(&g->dround, (size_t)nI * T * 4);
-    return off;
+    // the handle's own round state follows the structure
+    const size_t so = (c.off + 255) & ~(size_t)255;
+    g->state_off = so;
+    return so + layout_state(g, base ? base + so : nullptr);
 }
 
 int validate_graph(const mis_csr* csr, const uint64_t* user_keys, const int64_t* goff, int64_t count, uint32_t* d_err,

@@ -16,19 +16,19 @@ int build_keys(mis_graph* g, const mis_build_opts* o, hipStream_t s);
 int build_csr_lists(mis_graph* g, hipStream_t s);
 int build_order(mis_graph* g, hipStream_t s);
 int build_tiles(mis_graph* g, hipStream_t s);
-int csr_init(mis_graph* g, hipStream_t s);
-int csr_enqueue_phase(mis_graph* g, int phase, int r, hipStream_t s);
-int csr_output(mis_graph* g, uint8_t* in_set, bool if_done, hipStream_t s);
-int tile_init(mis_graph* g, hipStream_t s);
-int tile_enqueue_phase(mis_graph* g, int phase, int r, hipStream_t s);
-int tile_output(mis_graph* g, uint8_t* in_set, bool if_done, hipStream_t s);
-int tile_enqueue_rounds(mis_graph* g, int k, hipStream_t s);
-int csr_enqueue_rounds(mis_graph* g, int k, hipStream_t s);
+int csr_init(GraphCore* g, hipStream_t s);
+int csr_enqueue_phase(GraphCore* g, int phase, int r, hipStream_t s);
+int csr_output(GraphCore* g, uint8_t* in_set, bool if_done, hipStream_t s);
+int tile_init(GraphCore* g, hipStream_t s);
+int tile_enqueue_phase(GraphCore* g, int phase, int r, hipStream_t s);
+int tile_output(GraphCore* g, uint8_t* in_set, bool if_done, hipStream_t s);
+int tile_enqueue_rounds(GraphCore* g, int k, hipStream_t s);
+int csr_enqueue_rounds(GraphCore* g, int k, hipStream_t s);
 int build_hybrid(mis_graph* g, hipStream_t s);
-int hyb_init(mis_graph* g, hipStream_t s);
-int hyb_enqueue_phase(mis_graph* g, int phase, int r, hipStream_t s);
-int hyb_output(mis_graph* g, uint8_t* in_set, bool if_done, hipStream_t s);
-int hyb_enqueue_rounds(mis_graph* g, int k, hipStream_t s);
+int hyb_init(GraphCore* g, hipStream_t s);
+int hyb_enqueue_phase(GraphCore* g, int phase, int r, hipStream_t s);
+int hyb_output(GraphCore* g, uint8_t* in_set, bool if_done, hipStream_t s);
+int hyb_enqueue_rounds(GraphCore* g, int k, hipStream_t s);
 
 namespace {
 thread_local std::string g_last_error;
@@ -71,8 +71,8 @@ StagingPool& staging_pool() {
 
 // Takes a staging buffer laid out for g (allocating one if no idle buffer is big
 // enough); give it back with staging_put.
-int staging_get(const mis_graph* g, Staging** out) {
-    const size_t om = (size_t)((const char*)g->meta - (const char*)g->ctrl);
+int staging_get(const GraphCore* g, Staging** out) {
+    const size_t om = (size_t)((const char*)g->smeta - (const char*)g->ctrl);
     const size_t ot = (size_t)((const char*)g->trace - (const char*)g->ctrl);
     const size_t need = ot + sizeof(TraceRec) * kTraceCap;
     Staging* st = nullptr;
@@ -112,12 +112,13 @@ void staging_put(Staging* st) {
     P.idle.push_back(st);
 }
 
-__global__ void k_ctrl_init(Ctrl* ctrl, int64_t* stripes, int64_t n) {
+__global__ void k_ctrl_init(Ctrl* ctrl, Meta* smeta, const Meta* meta, int64_t* stripes, int64_t n) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         Ctrl c;
         memset(&c, 0, sizeof(c));
         c.alive = n;
         *ctrl = c;
+        *smeta = *meta;
     }
     for (int i = threadIdx.x; i < 2 * kStripes * kStripeWords; i += blockDim.x) stripes[i] = 0;
 }
@@ -203,7 +204,7 @@ void build_mark(mis_graph* g, hipStream_t s) {
 
 namespace {
 
-void configure(mis_graph* g, const mis_csr* csr, const mis_build_opts& o) {
+void configure(GraphCore* g, const mis_csr* csr, const mis_build_opts& o) {
     g->n = csr->n;
     g->nnz = csr->nnz;
     g->row_ptr = csr->row_ptr;
@@ -223,9 +224,9 @@ void configure(mis_graph* g, const mis_csr* csr, const mis_build_opts& o) {
 
 // kernels per round: tile path candidate / exclusion / finalize, CSR and hybrid paths
 // candidate / exclusion
-int phases(const mis_graph* g) { return g->path == MIS_PATH_TILE ? 3 : 2; }
+int phases(const GraphCore* g) { return g->path == MIS_PATH_TILE ? 3 : 2; }
 
-int enqueue_phase(mis_graph* g, int phase, int r, hipStream_t s) {
+int enqueue_phase(GraphCore* g, int phase, int r, hipStream_t s) {
     if (g->path == MIS_PATH_HYBRID) return hyb_enqueue_phase(g, phase, r, s);
     return g->path == MIS_PATH_TILE ? tile_enqueue_phase(g, phase, r, s) : csr_enqueue_phase(g, phase, r, s);
 }
@@ -268,7 +269,7 @@ __global__ void k_close(Ctrl* ctrl, int64_t* stripes, TraceRec* trace, int k) {
 
 // enqueues a batch of k rounds (round indices 1..k after the device-side base) and
 // the close kernel
-int enqueue_batch(mis_graph* g, int64_t k, hipStream_t s, hipEvent_t* ev) {
+int enqueue_batch(GraphCore* g, int64_t k, hipStream_t s, hipEvent_t* ev) {
     for (int64_t i = 0; i < k; ++i) {
         const int P = phases(g);
         for (int ph = 0; ph < P; ++ph) {
@@ -307,7 +308,7 @@ bool ensure_graph(mis_graph* g) {
 }
 
 // bytes the kernels must move per work unit (see TraceRec::u)
-int64_t unit_bytes(const mis_graph* g, int k) {
+int64_t unit_bytes(const GraphCore* g, int k) {
     if (g->path == MIS_PATH_CSR) {
         static const int64_t b[kUnits] = {12, 28, 8, 24, 0, 0, 0, 0};
         return b[k];
@@ -328,40 +329,40 @@ int64_t unit_bytes(const mis_graph* g, int k) {
 
 }  // namespace
 
-int solve_begin(mis_graph* g, hipStream_t s) {
-    hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(256), 0, s, g->ctrl, g->stripes, g->n);
+int solve_begin(GraphCore* g, hipStream_t s) {
+    hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(256), 0, s, g->ctrl, g->smeta, g->meta, g->stripes, g->n);
     TC_HIP(hipGetLastError());
     if (g->path == MIS_PATH_HYBRID) return hyb_init(g, s);
     return g->path == MIS_PATH_TILE ? tile_init(g, s) : csr_init(g, s);
 }
 
-// Sizes the cooperative grid once per handle (every workgroup must be resident:
-// at most two per compute unit, within what the kernel's resources allow) and
-// launches a persistent round kernel taking (args, k).
-int launch_cooperative(const void* kernel, mis_graph* g, void* args, int k, hipStream_t s) {
-    if (g->coop_blocks == 0) {
-        int dev = 0, cus = 0, per = 0;
-        TC_HIP(hipGetDevice(&dev));
-        TC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        TC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, 0));
-        if (per < 1 || cus < 1) return fail(MIS_EHIP, "the persistent round kernel cannot be resident");
-        g->coop_blocks = cus * std::min(per, 2);
-    }
+// Launches a persistent round kernel taking (args, k) on the cooperative grid: every
+// workgroup must be resident, at most two per compute unit within what the kernel's
+// resources allow (sized from the kernel on each launch, so that concurrent solves
+// share no host state).
+int launch_cooperative(const void* kernel, GraphCore* g, void* args, int k, hipStream_t s) {
+    int dev = 0, cus = 0, per = 0;
+    TC_HIP(hipGetDevice(&dev));
+    TC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    TC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, 0));
+    if (per < 1 || cus < 1) return fail(MIS_EHIP, "the persistent round kernel cannot be resident");
+    const int blocks = cus * std::min(per, 2);
     void* kargs[2] = {args, &k};
-    TC_HIP(hipLaunchCooperativeKernel(kernel, dim3((unsigned)g->coop_blocks), dim3(kBlock), kargs, 0, s));
+    TC_HIP(hipLaunchCooperativeKernel(kernel, dim3((unsigned)blocks), dim3(kBlock), kargs, 0, s));
     return MIS_OK;
 }
 
-int solve_rounds(mis_graph* g, int64_t k, bool allow_graph, hipStream_t s) {
+int solve_rounds(GraphCore* g, int64_t k, bool allow_graph, hipStream_t s, mis_graph* owner) {
     if (g->launch == MIS_LAUNCH_PERSISTENT) {
         if (g->path == MIS_PATH_HYBRID) return hyb_enqueue_rounds(g, (int)k, s);
         return g->path == MIS_PATH_TILE ? tile_enqueue_rounds(g, (int)k, s) : csr_enqueue_rounds(g, (int)k, s);
     }
     // auto: a handle solved once gains nothing from a capture, which costs more than
     // the launches it replaces; capture when it is solved again
-    const bool graph = g->launch == MIS_LAUNCH_GRAPH || (g->launch == MIS_LAUNCH_AUTO && g->solves > 1);
-    if (allow_graph && graph && k == g->poll_rounds && ensure_graph(g)) {
-        if (hipGraphLaunch(g->graph_exec, s) != hipSuccess) return fail(MIS_EHIP, "hipGraphLaunch failed");
+    // (only over the handle's own round state: a captured graph holds its addresses)
+    const bool graph = owner && (g->launch == MIS_LAUNCH_GRAPH || (g->launch == MIS_LAUNCH_AUTO && owner->solves > 1));
+    if (allow_graph && graph && k == g->poll_rounds && ensure_graph(owner)) {
+        if (hipGraphLaunch(owner->graph_exec, s) != hipSuccess) return fail(MIS_EHIP, "hipGraphLaunch failed");
         return MIS_OK;
     }
     return enqueue_batch(g, k, s, nullptr);
@@ -372,7 +373,7 @@ int resolve_opts(const mis_csr* csr, const mis_build_opts* opts, mis_build_opts*
     return resolve(csr, opts, o, count, offsets);
 }
 
-void configure_graph(mis_graph* g, const mis_csr* csr, const mis_build_opts& o, int32_t count) {
+void configure_graph(GraphCore* g, const mis_csr* csr, const mis_build_opts& o, int32_t count) {
     configure(g, csr, o);
     g->count = count;
 }
@@ -406,7 +407,7 @@ int build_into(mis_graph* g, const mis_csr* csr, const mis_build_opts& o, int32_
     return rc;
 }
 
-int solve_output(mis_graph* g, uint8_t* in_set, hipStream_t s, bool if_done) {
+int solve_output(GraphCore* g, uint8_t* in_set, hipStream_t s, bool if_done) {
     if (g->path == MIS_PATH_HYBRID) return hyb_output(g, in_set, if_done, s);
     return g->path == MIS_PATH_TILE ? tile_output(g, in_set, if_done, s) : csr_output(g, in_set, if_done, s);
 }
@@ -504,22 +505,23 @@ int mis_graph_bytes(const mis_graph* g, size_t* bytes) {
     return MIS_OK;
 }
 
-int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, mis_stats* st, void* stream) {
-    g_last_error.clear();
-    if (!g) return fail(MIS_EINVAL, "graph is null");
-    if (g->n > 0 && !in_set) return fail(MIS_EINVAL, "in_set is null");
-    if (max_rounds < 0) return fail(MIS_EINVAL, "max_rounds must be >= 0");
-    if (st && st->trace_cap > 0 && !st->trace) return fail(MIS_EINVAL, "stats trace buffer is null");
-    hipStream_t s = (hipStream_t)stream;
-    const bool timing = st && st->timing;
+}  // extern "C"
 
+namespace tcmis {
+namespace {
+
+// The round loop of one solve over g's round state (the handle's own when owner is
+// the handle: then the loop may replay a captured graph of it; a caller's scratch
+// otherwise).
+int solve_loop(GraphCore* g, mis_graph* owner, uint8_t* in_set, int32_t max_rounds, mis_stats* st, hipStream_t s) {
+    const bool timing = st && st->timing;
     Staging* sg = nullptr;
     TC_CHECK(staging_get(g, &sg));
     struct Give {   // the buffer goes back to the pool on every return path
         Staging* s;
         ~Give() { staging_put(s); }
     } give{sg};
-    ++g->solves;
+    if (owner) ++owner->solves;
     TC_CHECK(solve_begin(g, s));
 
     const int P = phases(g);
@@ -537,7 +539,7 @@ int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, mis_stats* st, 
         for (;;) {
             int64_t k = g->poll_rounds;
             if (max_rounds > 0) k = std::min<int64_t>(k, max_rounds - enq);
-            rc = timing ? enqueue_batch(g, k, s, ev.data()) : solve_rounds(g, k, true, s);
+            rc = timing ? enqueue_batch(g, k, s, ev.data()) : solve_rounds(g, k, true, s, owner);
             // the result, written by the device only if this batch decided the last vertex
             if (rc == MIS_OK) rc = solve_output(g, in_set, s, true);
             if (rc != MIS_OK) break;
@@ -610,17 +612,47 @@ int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, mis_stats* st, 
         st->alg_bytes = ab;
         for (int ph = 0; ph < 3; ++ph) st->kernel_ms[ph] = (float)kms[ph];
         st->launches = (int32_t)launches;
-        st->graph = timing ? 0 : g->launch == MIS_LAUNCH_PERSISTENT ? 2 : (g->graph_exec != nullptr && g->launch != MIS_LAUNCH_DIRECT);
+        st->graph = timing ? 0 : g->launch == MIS_LAUNCH_PERSISTENT ? 2
+                  : (owner && owner->graph_exec != nullptr && g->launch != MIS_LAUNCH_DIRECT);
     }
     return MIS_OK;
 }
 
-int mis_solve_batch(mis_graph* g, uint8_t* in_set, mis_stats* stats, int32_t* graph_rounds, int64_t* graph_in,
+}  // namespace
+}  // namespace tcmis
+
+extern "C" {
+
+int mis_solve_scratch_bytes(const mis_graph* g, size_t* bytes) {
+    if (!g || !bytes) return fail(MIS_EINVAL, "null argument");
+    GraphCore v = *g;
+    *bytes = layout_state(&v, nullptr);
+    return MIS_OK;
+}
+
+int mis_solve(mis_graph* g, uint8_t* in_set, int32_t max_rounds, void* scratch, size_t scratch_bytes, mis_stats* st,
+              void* stream) {
+    g_last_error.clear();
+    if (!g) return fail(MIS_EINVAL, "graph is null");
+    if (g->n > 0 && !in_set) return fail(MIS_EINVAL, "in_set is null");
+    if (max_rounds < 0) return fail(MIS_EINVAL, "max_rounds must be >= 0");
+    if (st && st->trace_cap > 0 && !st->trace) return fail(MIS_EINVAL, "stats trace buffer is null");
+    if (!scratch) return solve_loop(g, g, in_set, max_rounds, st, (hipStream_t)stream);
+    GraphCore v = *g;   // the structure's pointers, the round state in the caller's scratch
+    const size_t need = layout_state(&v, nullptr);
+    if (((uintptr_t)scratch & 255) || scratch_bytes < need)
+        return fail(MIS_EINVAL, "scratch must be 256-byte aligned device memory of at least " + std::to_string(need) +
+                                    " bytes (mis_solve_scratch_bytes)");
+    layout_state(&v, (char*)scratch);
+    return solve_loop(&v, nullptr, in_set, max_rounds, st, (hipStream_t)stream);
+}
+
+int mis_solve_union(mis_graph* g, uint8_t* in_set, mis_stats* stats, int32_t* graph_rounds, int64_t* graph_in,
                     void* stream) {
     g_last_error.clear();
     if (!g) return fail(MIS_EINVAL, "batch is null");
     if (g->count <= 0) return fail(MIS_EINVAL, "the handle was not built with mis_build_batch");
-    TC_CHECK(mis_solve(g, in_set, 0, stats, stream));
+    TC_CHECK(mis_solve(g, in_set, 0, nullptr, 0, stats, stream));
     hipStream_t s = (hipStream_t)stream;
     if (g->n > 0) {
         hipLaunchKernelGGL(k_batch_stats, dim3((unsigned)g->count), dim3(kBlock), 0, s, g->goff, in_set,

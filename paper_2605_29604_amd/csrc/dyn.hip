@@ -317,7 +317,6 @@ int mis_update_edges(mis_graph* g, const int32_t* edges, const int8_t* ops, int6
     DLAUNCH(k_dyn_unclaim, nw, a.C, nw);
     DLAUNCH(k_dyn_insert, count, a, edges, ops, count);
     DLAUNCH(k_dyn_load, nw, in_set, n, a.S);
-    g->dyn_edited = true;   // a later mis_solve classifies the rows again
     const dim3 grid((unsigned)std::max(1, g->grid_blocks)), blk(kBlock);
     int64_t h[kRcWords] = {};
     int r = 0;

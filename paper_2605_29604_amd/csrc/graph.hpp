@@ -1,6 +1,7 @@
 // The opaque handle behind mis_graph, its device workspace layout and the
 // device-side round control block.
 #pragma once
+#include <atomic>
 #include <type_traits>
 #include <vector>
 
@@ -69,8 +70,6 @@ struct Meta {
     int32_t n_light;        // CSR path: vertices with degree <= kLightDeg
     int32_t pad;
     // hybrid path
-    int64_t n_c1;           // round-1 candidates (vertices without a higher-priority neighbour)
-    int64_t n_hl[2];        // round-1 entry-list rows: [light, heavy]
     int32_t n_dense;        // dense row-blocks (bit tiles)
     int32_t n_dtiles;       // their tiles
 };
@@ -84,7 +83,11 @@ struct RowState {
     uint32_t blocked;   // rows with an undecided higher-priority neighbour (this round)
 };
 
-struct mis_graph {
+// Everything a build or a solve reads: the configuration, the structure's arrays in
+// the build workspace and the arrays of one solve's round state.  Plain data: a
+// solve with a caller's scratch runs on a copy whose round-state pointers point into
+// that scratch (layout_state), so the structure is only ever read by a solve.
+struct GraphCore {
     // input (caller-owned device CSR)
     int64_t n = 0, nnz = 0;
     const int64_t* row_ptr = nullptr;
@@ -96,34 +99,24 @@ struct mis_graph {
     int launch = MIS_LAUNCH_AUTO;
     bool user_keys = false;           // priorities supplied by the caller
 
-    // captured round loop (launch = graph): poll_rounds rounds and the close kernel
-    hipStream_t cap_stream = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
-    bool graph_failed = false;
-    int64_t solves = 0;               // mis_solve calls on this handle (auto launch captures from the 2nd)
-
-    // build-stage events (opts.timing = 1), recorded on the build stream
-    bool btiming = false;
-    std::vector<hipEvent_t> bev;
-
-    ~mis_graph() {
-        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
-        if (graph) (void)hipGraphDestroy(graph);
-        if (cap_stream) (void)hipStreamDestroy(cap_stream);
-        for (hipEvent_t e : bev) (void)hipEventDestroy(e);
-    }
+    bool btiming = false;             // build-stage events (opts.timing = 1)
     int grid_blocks = 2048;           // persistent grid of the round kernels
-    int coop_blocks = 0;              // grid of the cooperative round kernels (0 = not sized yet)
+    int coop_blocks = 0;              // grid of the cooperative round kernels (sized at build)
 
-    // workspace (caller-owned device memory)
+    // workspace (caller-owned device memory): the structure, then the handle's own
+    // round state (state_off .. ws_bytes)
     char* ws = nullptr;
     size_t ws_bytes = 0;
+    size_t state_off = 0;
 
+    // round state (per solve): control block, a copy of the build's sizes and the trace
+    // ring side by side (one copy brings all three back), the counter stripes
     tcmis::Ctrl* ctrl = nullptr;
-    int64_t* stripes = nullptr;       // [2][kStripes][kStripeWords] round counters
-    tcmis::Meta* meta = nullptr;
+    tcmis::Meta* smeta = nullptr;     // copy of *meta taken when a solve starts
     tcmis::TraceRec* trace = nullptr;
+    int64_t* stripes = nullptr;       // [2][kStripes][kStripeWords] round counters
+
+    tcmis::Meta* meta = nullptr;      // sizes the build produced (structure)
     char* scan_tmp = nullptr;         // scan scratch (int64 elements)
     char* sort_tmp = nullptr;         // radix sort scratch
 
@@ -185,11 +178,7 @@ struct mis_graph {
     int32_t* hoff = nullptr;          // [n] orientation scratch
     int32_t* hcol = nullptr;          // [nnz] oriented entries: row v's are hcol[rp[v] .. rp[v] + hcnt[v])
     int32_t* hcnt = nullptr;          // [n] higher-priority neighbours of each vertex
-    int64_t* hflag = nullptr;         // [n] list class (light 1, heavy 1 << 32, else 0)
-    int64_t* hpos = nullptr;          // [n+1] its exclusive scan: list positions (light low, heavy high half)
-    int32_t* hl1[2] = {nullptr, nullptr};   // [n] round-1 light / heavy rows
-    uint32_t* s1 = nullptr;           // [nw] round-1 candidates (bitmap)
-    uint32_t* a1 = nullptr;           // [nw] undecided after them (bitmap)
+    uint64_t* hsig = nullptr;         // [nI] column-block signature of each 16-row block (dense test)
     int32_t* dflag = nullptr;         // [nI] dense row-block flags
     int32_t* dpos = nullptr;          // [nI+1] their scan: list slot of each dense row-block
     int32_t* dtcnt = nullptr;         // [nI+1] tiles per dense row-block -> first tile
@@ -210,7 +199,6 @@ struct mis_graph {
     int32_t* lcol = nullptr;          // [drp[n]] lower-priority neighbours
     int32_t* lcnt = nullptr;          // [n] slots used in lcol rows
     int32_t* hloff = nullptr;         // [n] orientation scratch
-    bool dyn_edited = false;          // edges changed since the rows were classified
     uint32_t* rS = nullptr;           // [nw] repair: in the set
     uint32_t* rP = nullptr;           // [nw] repair: pending (status to recompute)
     uint32_t* rC = nullptr;           // [nw] repair: this round's candidates
@@ -218,28 +206,55 @@ struct mis_graph {
     int32_t* rflip = nullptr;         // [n] vertices whose status changed this round
     int32_t* rdec = nullptr;          // [n] this round's decisions
     int64_t* rcnt = nullptr;          // repair counters (see dyn.hip)
+    int64_t* hflag = nullptr;         // [n] build temporary (row capacities)
+};
+
+struct mis_graph : GraphCore {
+    // captured round loop (launch = graph) over the handle's own round state:
+    // poll_rounds rounds and the close kernel
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    bool graph_failed = false;
+    std::atomic<int64_t> solves{0};   // solves over the handle's own state (auto launch captures from the 2nd)
+
+    std::vector<hipEvent_t> bev;      // build-stage events, recorded on the build stream
+
+    mis_graph() = default;
+    mis_graph(const mis_graph&) = delete;
+    mis_graph& operator=(const mis_graph&) = delete;
+    ~mis_graph() {
+        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        for (hipEvent_t e : bev) (void)hipEventDestroy(e);
+    }
 };
 
 namespace tcmis {
 // Records a build-stage boundary on s when the handle was built with timing.
 void build_mark(mis_graph* g, hipStream_t s);
 
-// Assigns every workspace array of g (base == nullptr: only computes the size).
-size_t layout(mis_graph* g, char* base);
+// Assigns every workspace array of g: the structure, then the handle's own round
+// state (base == nullptr: only computes the size).
+size_t layout(GraphCore* g, char* base);
+// Assigns the arrays of one solve's round state from base (nullptr: size only);
+// without the trace ring when with_trace is false.
+size_t layout_state(GraphCore* g, char* base, bool with_trace = true);
 
 // Pieces of the round loop, enqueued on `s` without synchronising it:
 // solve_begin resets the round state, solve_rounds enqueues k more rounds (as the
 // captured hipGraph when k == poll_rounds and graph launch is allowed) and
 // solve_output writes the in/out vector in input ids.
-int solve_begin(mis_graph* g, hipStream_t s);
+int solve_begin(GraphCore* g, hipStream_t s);
 
 // Option checks and defaults (host-only), the handle's configuration, and the build
 // into a workspace of `need` bytes (layout() of the configured handle).
 int resolve_opts(const mis_csr* csr, const mis_build_opts* opts, mis_build_opts* o, int32_t count,
                  const int64_t* offsets);
-void configure_graph(mis_graph* g, const mis_csr* csr, const mis_build_opts& o, int32_t count);
+void configure_graph(GraphCore* g, const mis_csr* csr, const mis_build_opts& o, int32_t count);
 int build_into(mis_graph* g, const mis_csr* csr, const mis_build_opts& o, int32_t count, const int64_t* offsets,
                char* ws, size_t need, hipStream_t s);
-int solve_rounds(mis_graph* g, int64_t k, bool allow_graph, hipStream_t s);
-int solve_output(mis_graph* g, uint8_t* in_set, hipStream_t s, bool if_done = false);
+int solve_rounds(GraphCore* g, int64_t k, bool allow_graph, hipStream_t s, mis_graph* owner = nullptr);
+int solve_output(GraphCore* g, uint8_t* in_set, hipStream_t s, bool if_done = false);
 }  // namespace tcmis

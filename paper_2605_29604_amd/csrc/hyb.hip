@@ -81,19 +81,20 @@ __device__ inline void run_apply(int64_t w, uint32_t m, uint32_t* dst) {
 
 // ---------------------------------------------------------------- build
 
-// first row of every orientation workgroup's entry range (the last slot: the row of
-// the last entry)
+// First row of every orientation workgroup's entry range (the last slot: the row of
+// the last entry), one thread per row: row v owns the workgroups whose first entry
+// b * kHE falls inside it.
 __global__ void k_orient_rows(const int64_t* rp, int64_t n, int64_t nnz, int64_t nblocks, int32_t* brow) {
-    GRID_STRIDE(b, nblocks + 1) {
-        const int64_t e = b < nblocks ? b * kHE : nnz - 1;
-        int64_t lo = 0, hi = n - 1;   // largest row whose start is <= e
-        while (lo < hi) {
-            const int64_t mid = (lo + hi + 1) >> 1;
-            if (rp[mid] <= e) lo = mid; else hi = mid - 1;
-        }
-        brow[b] = (int32_t)lo;
+    GRID_STRIDE(v, n) {
+        const int64_t e0 = rp[v], e1 = rp[v + 1];
+        if (e1 <= e0) continue;
+        for (int64_t b = (e0 + kHE - 1) / kHE; b * kHE < e1; ++b) brow[b] = (int32_t)v;
+        if (e0 <= nnz - 1 && nnz - 1 < e1) brow[nblocks] = (int32_t)v;
     }
 }
+
+// a column block's bit in a row-block's 64-bit signature
+__device__ inline uint64_t sig_bit(int64_t J) { return 1ull << (((uint64_t)J * 0x9E3779B97F4A7C15ull) >> 58); }
 
 // does column u out-rank row v?  kUserKeys: compare the keys; else the default key
 // rule: the degree class decides unless it ties, then the hash of the graph-local
@@ -113,6 +114,9 @@ __device__ inline bool higher(int64_t u, int64_t v, uint64_t kv, const uint64_t*
 // Where the orientation writes: the higher-priority entries of row v go to
 // hcol[hrp[v] + ...] (hrp = the input row pointer, or the dynamic layout's own);
 // with lcol (dynamic handles) the lower-priority ones go to lcol[hrp[v] + ...].
+// With sig, every 16-row block's higher-priority entries also OR the signature bits of
+// their column blocks into sig[I] (popcount(sig[I]) is a lower bound on the block's
+// nonzero tiles).
 struct OrientOut {
     const int64_t* hrp;
     int32_t* hcol;
@@ -122,6 +126,7 @@ struct OrientOut {
     int32_t* g_base;    // [n] scratch of workgroups whose rows exceed LDS
     int32_t* g_off;
     int32_t* g_loff;
+    uint64_t* sig;      // [nI] or nullptr
 };
 
 // Row bounds of a workgroup's rows relative to its range start: from LDS when they
@@ -204,6 +209,31 @@ __device__ void orient_body(const int64_t* rp, const int32_t* ci, const uint64_t
         const int64_t v = u0 + li[j];
         const uint64_t kv = kLds ? wkey[li[j]] : key[v];
         if (t0 + j < erel && higher<kUserKeys>(cu[j], v, kv, key, q8, seed)) keep |= 1u << j;
+    }
+    if (o.sig) {
+        // the thread's entries lie in at most a few row-blocks (rows are consecutive):
+        // all but the last run are ORed in directly, the last one is combined across
+        // the wave first (adjacent lanes mostly share it)
+        int64_t I = (u0 + li[0]) >> 4;
+        uint64_t m = 0;
+        #pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int64_t Ij = (u0 + li[j]) >> 4;
+            if (Ij != I) {
+                if (m) atomicOr((unsigned long long*)&o.sig[I], (unsigned long long)m);
+                I = Ij;
+                m = 0;
+            }
+            if ((keep >> j) & 1u) m |= sig_bit(cu[j] >> 4);
+        }
+        #pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint64_t mo = __shfl_down(m, off, kWave);
+            const int64_t Io = __shfl_down(I, off, kWave);
+            if (lane + off < kWave && Io == I) m |= mo;
+        }
+        const int64_t Ip = __shfl_up(I, 1, kWave);
+        if ((lane == 0 || Ip != I) && m) atomicOr((unsigned long long*)&o.sig[I], (unsigned long long)m);
     }
     // exclusive prefix count of kept entries at the thread's first entry (entry order)
     const int cnt = __popc(keep);
@@ -301,10 +331,13 @@ __global__ void __launch_bounds__(kBlock) k_orient(const int64_t* rp, const int3
 // Dense-block test, one wave per 16-row block: the number of nonzero tiles is the
 // number of distinct column blocks among the block's oriented entries, counted with
 // an open-addressing set in LDS.  dflag[I] = 1 and dtcnt[I] = tiles if the block is
-// dense (at most 64 tiles, at least dense_min entries per tile on average).
+// dense (at most 64 tiles, at least dense_min entries per tile on average).  The
+// block's signature bounds its tiles from below (distinct column blocks set at least
+// popcount(sig) bits), so a block with fewer than dense_min * popcount(sig) entries is
+// rejected without reading its entries.
 __global__ void __launch_bounds__(kBlock) k_dense_test(const int64_t* rp, const int32_t* hcol, const int32_t* hcnt,
-                                                       int64_t n, int64_t nI, int dense_min, int32_t* dflag,
-                                                       int32_t* dtcnt) {
+                                                       const uint64_t* sig, int64_t n, int64_t nI, int dense_min,
+                                                       int32_t* dflag, int32_t* dtcnt) {
     constexpr uint32_t kEmpty = 0xFFFFFFFFu;
     __shared__ uint32_t tab[kWpb][2 * kDenseCap];
     __shared__ int32_t srow[kWpb][17];
@@ -322,8 +355,9 @@ __global__ void __launch_bounds__(kBlock) k_dense_test(const int64_t* rp, const 
             if (lane >= off) incl += o;
         }
         const int32_t total = __shfl(incl, 15, kWave);
-        // a dense block holds at least dense_min entries (one tile) and at most the cap
-        if (total == 0 || total > kDenseCap || total < dense_min) {
+        // a dense block holds at least dense_min entries per tile and at most the cap
+        const int64_t lower = __popcll(sig[I]);
+        if (total == 0 || total > kDenseCap || (int64_t)total < (int64_t)dense_min * lower) {
             if (lane == 0) { dflag[I] = 0; dtcnt[I] = 0; }
             continue;
         }
@@ -443,14 +477,6 @@ __global__ void __launch_bounds__(kBlock) k_dense_fill(const int64_t* rp, const 
     }
 }
 
-// a dynamic handle classifies its rows again after edits: the counters start at zero
-__global__ void k_hyb_meta_clear(Meta* meta) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        meta->n_c1 = 0;
-        meta->n_hl[0] = meta->n_hl[1] = 0;
-    }
-}
-
 // row capacities of a dynamic handle (each orientation: its degree plus the slack)
 __global__ void k_dyn_caps(const int64_t* rp, int64_t n, int slack, int64_t* cap) {
     GRID_STRIDE(v, n) cap[v] = rp[v + 1] - rp[v] + slack;
@@ -460,66 +486,17 @@ __global__ void k_dense_end(const Meta* meta, int32_t* dptr) {
     if (threadIdx.x == 0 && blockIdx.x == 0) dptr[meta->n_dense] = meta->n_dtiles;
 }
 
-// Round-1 classification of every vertex: no higher-priority neighbour -> candidate
-// of round 1 (bit in s1); else undecided (bit in a1) and, outside dense blocks, a
-// light or heavy list row.  flag packs (light, heavy) as (1, 1 << 32) for the scan.
-__global__ void k_hyb_class(const int32_t* hcnt, const int32_t* dflag, int64_t n, int64_t* flag, uint32_t* s1,
-                            uint32_t* a1, int64_t* n_c1) {
-    int64_t c1 = 0;
-    const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
-    const int64_t nr = (n + kWave - 1) / kWave * kWave;   // whole waves iterate together
-    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nr; v += nthreads) {
-        const bool valid = v < n;
-        const int32_t c = valid ? hcnt[v] : -1;
-        const bool dense = valid && dflag && dflag[v >> 4];
-        if (valid) flag[v] = (c == 0 || dense) ? 0 : (c <= kHLight ? 1ll : (1ll << 32));
-        const uint64_t bc = ballot(c == 0), ba = ballot(c > 0);
-        c1 += lane_id() == 0 ? __popcll(bc) : 0;
-        const int lane = lane_id();
-        if (lane < 2 && v - lane < n) {   // v - lane is the wave's first vertex (a multiple of 64)
-            const int64_t w = (v - lane) / 32 + lane;
-            if (w * 32 < n) {
-                s1[w] = (uint32_t)(bc >> (32 * lane));
-                a1[w] = (uint32_t)(ba >> (32 * lane));
-            }
-        }
-    }
-    // one atomic per workgroup (a same-address atomic per wave serialises the kernel)
-    __shared__ int64_t part[kWpb];
-    for (int off = kWave / 2; off > 0; off >>= 1) c1 += __shfl_xor(c1, off, kWave);
-    if (lane_id() == 0) part[threadIdx.x / kWave] = c1;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t t = 0;
-        for (int q = 0; q < kWpb; ++q) t += part[q];
-        if (t) atomicAdd((unsigned long long*)n_c1, (unsigned long long)t);
-    }
-}
-
-__global__ void k_hyb_lists(const int64_t* flag, const int64_t* pos, int64_t n, int32_t* light, int32_t* heavy,
-                            Meta* meta) {
-    GRID_STRIDE(v, n) {
-        const int64_t f = flag[v], p = pos[v];
-        if (f == 1) light[(uint32_t)p] = (int32_t)v;
-        else if (f) heavy[p >> 32] = (int32_t)v;
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        const int64_t t = pos[n];
-        meta->n_hl[0] = (uint32_t)t;
-        meta->n_hl[1] = t >> 32;
-    }
-}
-
 // ---------------------------------------------------------------- rounds
 
 struct HybArgs {
+    int64_t n;
     const int64_t* rp;
     const int32_t* hcol;
     const int32_t* hcnt;
     uint32_t* A;
     uint32_t* S;
-    const int32_t* l1[3];     // round 1: light rows, heavy rows, dense blocks
-    int32_t* act[2][3];       // later rounds, by round parity
+    const int32_t* drb;       // round 1: the dense blocks (round 1 visits every vertex otherwise)
+    int32_t* act[2][3];       // later rounds, by round parity: light rows, heavy rows, dense blocks
     const int32_t* dptr;      // dense block (by round-1 list slot order of drb) -> first tile
     const int32_t* dslot;     // dense block I -> its slot in drb (for dptr)
     const int32_t* dcol;
@@ -531,18 +508,12 @@ struct HybArgs {
     int32_t* dround;          // batches: round in which each vertex was decided
 };
 
+// the lists of round r >= 2 (written by round r-1's exclusion kernel)
 __device__ inline void hyb_lists(const HybArgs& a, int r, const int32_t* (&L)[3], int64_t (&nl)[3]) {
-    if (r == 1) {
-        for (int k = 0; k < 3; ++k) L[k] = a.l1[k];
-        nl[0] = a.meta->n_hl[0];
-        nl[1] = a.meta->n_hl[1];
-        nl[2] = a.meta->n_dense;
-    } else {
-        const int b = (r - 1) & 1;
-        for (int k = 0; k < 3; ++k) {
-            L[k] = a.act[b][k];
-            nl[k] = a.ctrl->n_act[b][k];
-        }
+    const int b = (r - 1) & 1;
+    for (int k = 0; k < 3; ++k) {
+        L[k] = a.act[b][k];
+        nl[k] = a.ctrl->n_act[b][k];
     }
 }
 
@@ -630,24 +601,20 @@ __device__ inline bool scan4(const int32_t* row, int32_t c, const uint32_t* m, i
     return false;
 }
 
-// Phase 1 of round r >= 2 (round 1's candidates come from the build).
-__device__ void hyb_p1(const HybArgs& a, int r) {
+// Phase 1 of round r >= 2 (round 1's candidates come from the build).  The
+// workgroup is number vb of nvb working on this graph (the launch's grid, or the
+// graph's share of a launch over several graphs).
+__device__ void hyb_p1(const HybArgs& a, int r, int64_t vb, int64_t nvb) {
     __shared__ uint32_t sbits[kWpb][kDenseTiles * 8];
     __shared__ uint32_t svec[kWpb][kDenseTiles];
-    open_round(a.ctrl, a.stripes, a.trace, r);
-    if (r == 1) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            int64_t* st = a.stripes + (int64_t)(r & 1) * kStripes * kStripeWords;
-            if (a.meta->n_c1) atomicAdd((unsigned long long*)&st[0], (unsigned long long)a.meta->n_c1);
-        }
-        return;
-    }
+    open_round(a.ctrl, a.stripes, a.trace, r, vb);
+    if (r == 1) return;   // round 1's candidates were counted when the round state was set up
     const int32_t* L[3];
     int64_t nl[3];
     hyb_lists(a, r, L, nl);
     const int lane = lane_id(), wid = threadIdx.x / kWave;
-    const int64_t nthreads = (int64_t)gridDim.x * kBlock;
-    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t nthreads = nvb * kBlock;
+    const int64_t tid = vb * kBlock + threadIdx.x;
     const int64_t nwaves = nthreads / kWave, wv = tid / kWave;
     int64_t n_cand = 0, ent = 0, verts = 0, mult = 0, blocks = 0;
     // light rows: a lane each (whole waves iterate together for the combined atomics)
@@ -696,17 +663,17 @@ __device__ void hyb_p1(const HybArgs& a, int r) {
         }
     }
     int64_t x[5] = {n_cand, ent, verts, mult, blocks};
-    block_count(a.stripes, r, {0, 2, 3, 6, 8}, x);
+    block_count(a.stripes, r, {0, 2, 3, 6, 8}, x, vb);
 }
 
 // Phases 2 and 3 of round r: retire candidates, remove their neighbours, list the rest.
-__device__ void hyb_p2(const HybArgs& a, int r) {
+__device__ void hyb_p2(const HybArgs& a, int r, int64_t vb, int64_t nvb) {
     __shared__ int32_t lbuf[kWpb][3][kWave];
     __shared__ uint32_t sbits[kWpb][kDenseTiles * 8];
     __shared__ uint32_t svec[kWpb][kDenseTiles];
-    const int32_t* L[3];
-    int64_t nl[3];
-    hyb_lists(a, r, L, nl);
+    const int32_t* L[3] = {nullptr, nullptr, a.drb};
+    int64_t nl[3] = {0, 0, a.dslot ? (int64_t)a.meta->n_dense : 0};
+    if (r > 1) hyb_lists(a, r, L, nl);
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     int pend[3] = {0, 0, 0};
     int32_t* next[3];
@@ -715,10 +682,67 @@ __device__ void hyb_p2(const HybArgs& a, int r) {
         next[k] = a.act[r & 1][k];
         cnt[k] = &a.ctrl->n_act[r & 1][k];
     }
-    const int64_t nthreads = (int64_t)gridDim.x * kBlock;
-    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t nthreads = nvb * kBlock;
+    const int64_t tid = vb * kBlock + threadIdx.x;
     const int64_t nwaves = nthreads / kWave, wv = tid / kWave;
     int64_t n_out = 0, ent = 0, verts = 0, mult = 0, blocks = 0;
+    if (r == 1) {
+        // Every vertex outside the dense blocks: a vertex without a higher-priority
+        // neighbour is a candidate and already in the set (it was never undecided);
+        // any other leaves if one of its higher-priority neighbours is a candidate,
+        // else it goes to round 2's lists.  Light rows take a lane each; the heavy rows
+        // of a wave's 64 vertices are then scanned by the whole wave, one after another.
+        const int64_t nr = (a.n + kWave - 1) / kWave * kWave;   // whole waves iterate together
+        for (int64_t i = tid; i < nr; i += nthreads) {
+            const int32_t v = (int32_t)i;
+            const bool valid = i < a.n;
+            const int32_t c = valid ? a.hcnt[v] : 0;
+            const bool listed = valid && c > 0 && !(a.dslot && a.dslot[v >> 4] >= 0);
+            const bool light = listed && c <= kHLight;
+            int64_t w = -1;
+            uint32_t m = 0;
+            bool keep = false;
+            if (light) {
+                const bool hit = scan4(a.hcol + a.rp[v], c, a.S, &ent);
+                ++verts;
+                if (hit) {
+                    w = v >> 5; m = 1u << (v & 31); ++n_out;
+                    if (a.dround) a.dround[v] = r;
+                } else {
+                    keep = true;
+                }
+            }
+            run_apply<true>(w, m, a.A);
+            lbuf_push(lbuf[wid][0], pend[0], next[0], cnt[0], keep, v);
+            uint64_t hv = ballot(listed && !light);
+            while (hv) {
+                const int l = __builtin_ctzll(hv);
+                hv &= hv - 1;
+                const int32_t vh = __shfl(v, l, kWave);
+                const int64_t e0 = a.rp[vh];
+                const int32_t ch = a.hcnt[vh];
+                bool hit = false;
+                int32_t k = 0;
+                for (; k < ch; k += kWave) {
+                    const int32_t u = k + lane < ch ? a.hcol[e0 + k + lane] : -1;
+                    const bool b = u >= 0 && bit_of(a.S, u);
+                    if (ballot(b)) { hit = true; k += kWave; break; }
+                }
+                if (lane == 0) {
+                    ent += min(k, ch);
+                    ++verts;
+                    if (hit) {
+                        atomicAnd(&a.A[vh >> 5], ~(1u << (vh & 31)));
+                        ++n_out;
+                        if (a.dround) a.dround[vh] = r;
+                    }
+                }
+                lbuf_push(lbuf[wid][1], pend[1], next[1], cnt[1], lane == 0 && !hit, vh);
+            }
+        }
+        lbuf_flush(lbuf[wid][0], pend[0], next[0], cnt[0]);
+        lbuf_flush(lbuf[wid][1], pend[1], next[1], cnt[1]);
+    } else {
     const int64_t nlr = (nl[0] + kWave - 1) / kWave * kWave;
     for (int64_t i = tid; i < nlr; i += nthreads) {
         int64_t w = -1;
@@ -769,6 +793,7 @@ __device__ void hyb_p2(const HybArgs& a, int r) {
         lbuf_push(lbuf[wid][1], pend[1], next[1], cnt[1], lane == 0 && !in && !hit, v);
     }
     lbuf_flush(lbuf[wid][1], pend[1], next[1], cnt[1]);
+    }
     for (int64_t i = wv; i < nl[2]; i += nwaves) {
         const int32_t I = L[2][i];
         const int32_t s = a.dslot[I];
@@ -787,35 +812,71 @@ __device__ void hyb_p2(const HybArgs& a, int r) {
     }
     lbuf_flush(lbuf[wid][2], pend[2], next[2], cnt[2]);
     int64_t x[5] = {n_out, ent, verts, mult, blocks};
-    block_count(a.stripes, r, {1, 4, 5, 7, 9}, x);
+    block_count(a.stripes, r, {1, 4, 5, 7, 9}, x, vb);
 }
 
-__global__ void __launch_bounds__(kBlock) k_hyb_p1(HybArgs a, int ri) { hyb_p1(a, a.ctrl->rbase + ri); }
-__global__ void __launch_bounds__(kBlock) k_hyb_p2(HybArgs a, int ri) { hyb_p2(a, a.ctrl->rbase + ri); }
+__global__ void __launch_bounds__(kBlock) k_hyb_p1(HybArgs a, int ri) {
+    hyb_p1(a, a.ctrl->rbase + ri, blockIdx.x, gridDim.x);
+}
+__global__ void __launch_bounds__(kBlock) k_hyb_p2(HybArgs a, int ri) {
+    hyb_p2(a, a.ctrl->rbase + ri, blockIdx.x, gridDim.x);
+}
 
 // Persistent variant: k rounds in one cooperative launch, a grid barrier after every
 // phase; the last round is closed and the base advanced at the end.
 __global__ void __launch_bounds__(kBlock) k_hyb_rounds(HybArgs a, int k) {
     const int rb = a.ctrl->rbase;
     for (int ri = 1; ri <= k; ++ri) {
-        hyb_p1(a, rb + ri);
+        hyb_p1(a, rb + ri, blockIdx.x, gridDim.x);
         grid_barrier(a.ctrl);
-        hyb_p2(a, rb + ri);
+        hyb_p2(a, rb + ri, blockIdx.x, gridDim.x);
         grid_barrier(a.ctrl);
     }
     finish_rounds(a.ctrl, a.stripes, a.trace, rb, k);
 }
 
-// round state before round 1: the bitmaps of the build; batches: round-1 candidates
-// are decided in round 1, everything else undecided
-__global__ void k_hyb_init(const uint32_t* s1, const uint32_t* a1, uint32_t* S, uint32_t* A, int32_t* dround,
-                           int64_t n, int64_t nw) {
-    GRID_STRIDE(w, nw) {
-        S[w] = s1[w];
-        A[w] = a1[w];
+// Round state before round 1, from the higher-priority neighbour counts: a vertex
+// without one is a candidate of round 1 (in the set, counted into round 1's |C|),
+// every other vertex is undecided.  Batches: round-1 candidates are decided in round
+// 1, everything else later.  vb / nvb: the workgroup's place in the graph's share
+// (the grid, or its part of a launch over several graphs); whole waves iterate
+// together, each writing the two bitmap words of its 64 vertices.
+__device__ void hyb_init_body(const int32_t* hcnt, int64_t n, uint32_t* S, uint32_t* A, int32_t* dround,
+                              int64_t* stripes, int64_t vb, int64_t nvb) {
+    int64_t c1 = 0;
+    const int64_t nthreads = nvb * kBlock;
+    const int64_t nr = (n + kWave - 1) / kWave * kWave;
+    const int lane = lane_id();
+    for (int64_t v = vb * kBlock + threadIdx.x; v < nr; v += nthreads) {
+        const bool valid = v < n;
+        const int32_t c = valid ? hcnt[v] : -1;
+        const uint64_t bc = ballot(c == 0), ba = ballot(c > 0);
+        c1 += lane == 0 ? __popcll(bc) : 0;
+        if (dround && valid) dround[v] = c == 0 ? 1 : 0;
+        if (lane < 2) {   // v - lane is the wave's first vertex (a multiple of 64)
+            const int64_t w = (v - lane) / 32 + lane;
+            if (w * 32 < n) {
+                S[w] = (uint32_t)(bc >> (32 * lane));
+                A[w] = (uint32_t)(ba >> (32 * lane));
+            }
+        }
     }
-    if (dround)
-        GRID_STRIDE(v, n) dround[v] = bit_of(s1, v) ? 1 : 0;
+    // one atomic per workgroup into round 1's |C| counter
+    __shared__ int64_t part[kWpb];
+    for (int off = kWave / 2; off > 0; off >>= 1) c1 += __shfl_xor(c1, off, kWave);
+    if (lane == 0) part[threadIdx.x / kWave] = c1;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int q = 0; q < kWpb; ++q) t += part[q];
+        int64_t* st = stripes + ((int64_t)(1 & 1) * kStripes + vb % kStripes) * kStripeWords;
+        if (t) atomicAdd((unsigned long long*)&st[0], (unsigned long long)t);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_hyb_init(const int32_t* hcnt, int64_t n, uint32_t* S, uint32_t* A,
+                                                     int32_t* dround, int64_t* stripes) {
+    hyb_init_body(hcnt, n, S, A, dround, stripes, blockIdx.x, gridDim.x);
 }
 
 // in_set[v] = S(v); with `gate`, only once every vertex is decided
@@ -837,16 +898,15 @@ __global__ void k_hyb_output4(const Ctrl* gate, const uint32_t* S, int64_t n, ui
         for (int64_t v = nq << 2; v < n; ++v) in_set[v] = (uint8_t)bit_of(S, v);
 }
 
-HybArgs make_args(mis_graph* g) {
+HybArgs make_args(GraphCore* g) {
     HybArgs a;
+    a.n = g->n;
     a.rp = g->hrp;
     a.hcol = g->hcol;
     a.hcnt = g->hcnt;
     a.A = g->hA;
     a.S = g->hS;
-    a.l1[0] = g->hl1[0];
-    a.l1[1] = g->hl1[1];
-    a.l1[2] = g->drb;
+    a.drb = g->drb;
     for (int b = 0; b < 2; ++b)
         for (int k = 0; k < 3; ++k) a.act[b][k] = g->hact[b][k];
     a.dptr = g->dptr;
@@ -875,25 +935,11 @@ __global__ void k_dense_slots(const int32_t* dflag, const int32_t* dpos, int64_t
 
 int64_t hyb_blocks(int64_t nnz) { return ceil_div(nnz, kHE); }
 
-// round-1 classes (bitmaps, candidate count) and the light / heavy row lists
-int hyb_lists_build(mis_graph* g, const int32_t* dflag, hipStream_t s) {
-    const int64_t n = g->n;
-    if (n > 0) {
-        const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(n, kBlock), 1024);
-        hipLaunchKernelGGL(k_hyb_class, dim3(blocks), dim3(kBlock), 0, s, g->hcnt, dflag, n, g->hflag, g->s1, g->a1,
-                           &g->meta->n_c1);
-        TC_HIP(hipGetLastError());
-    }
-    TC_CHECK(scan_excl_i64(g->hflag, g->hpos, n, g->hpos + n, (int64_t*)g->scan_tmp, s));
-    HLAUNCH(k_hyb_lists, n, g->hflag, g->hpos, n, g->hl1[0], g->hl1[1], g->meta);
-    return MIS_OK;
-}
-
 int build_hybrid(mis_graph* g, hipStream_t s) {
     const int64_t n = g->n, nnz = g->nnz, nI = g->nI;
     TC_HIP(hipMemsetAsync(g->meta, 0, sizeof(Meta), s));
     if (n == 0) return MIS_OK;
-    // 1. orientation (stages: row search, orientation, dense blocks, lists)
+    // 1. orientation (stages: row search, orientation, dense blocks)
     TC_HIP(hipMemsetAsync(g->hcnt, 0, (size_t)n * 4, s));
     g->hrp = g->row_ptr;
     if (g->dyn_slack > 0) {
@@ -904,11 +950,13 @@ int build_hybrid(mis_graph* g, hipStream_t s) {
         g->hrp = g->drp;
     }
     const int64_t nb = hyb_blocks(nnz);
-    if (nnz > 0) HLAUNCH(k_orient_rows, nb + 1, g->row_ptr, n, nnz, nb, g->hbrow);
+    const bool dense = g->dense_min > 0 && nnz > 0;
+    if (nnz > 0) HLAUNCH(k_orient_rows, n, g->row_ptr, n, nnz, nb, g->hbrow);
+    if (dense) TC_HIP(hipMemsetAsync(g->hsig, 0, (size_t)nI * 8, s));
     build_mark(g, s);
     if (nnz > 0) {
         OrientOut o{g->hrp, g->hcol, g->hcnt, g->dyn_slack > 0 ? g->lcol : nullptr, g->lcnt, g->hbase, g->hoff,
-                    g->hloff};
+                    g->hloff, dense ? g->hsig : nullptr};
         if (g->user_keys)
             hipLaunchKernelGGL(k_orient<true>, dim3((unsigned)nb), dim3(kBlock), 0, s, g->row_ptr, g->col_idx, g->key,
                                g->q8, g->seed, nnz, g->hbrow, o);
@@ -919,11 +967,10 @@ int build_hybrid(mis_graph* g, hipStream_t s) {
     }
     build_mark(g, s);
     // 2. dense blocks
-    const bool dense = g->dense_min > 0 && nnz > 0;
     if (dense) {
         const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(nI, kWpb), 16384);
-        hipLaunchKernelGGL(k_dense_test, dim3(blocks), dim3(kBlock), 0, s, g->row_ptr, g->hcol, g->hcnt, n, nI,
-                           g->dense_min, g->dflag, g->dtcnt);
+        hipLaunchKernelGGL(k_dense_test, dim3(blocks), dim3(kBlock), 0, s, g->row_ptr, g->hcol, g->hcnt, g->hsig, n,
+                           nI, g->dense_min, g->dflag, g->dtcnt);
         TC_HIP(hipGetLastError());
         // list slots of dense blocks and their first tiles (dflag keeps the flags)
         TC_CHECK(scan_excl_i32(g->dflag, g->dpos, nI, &g->meta->n_dense, (int32_t*)g->scan_tmp, s));
@@ -936,34 +983,19 @@ int build_hybrid(mis_graph* g, hipStream_t s) {
         HLAUNCH(k_dense_slots, nI, g->dflag, g->dpos, nI, g->dslot);
     }
     build_mark(g, s);
-    // 3. round-1 classes and lists
-    TC_CHECK(hyb_lists_build(g, dense ? g->dflag : nullptr, s));
     return MIS_OK;
 }
 
-int hyb_classify(mis_graph* g, hipStream_t s);
-
-// round-1 classes and lists from the rows' current counts (after edits)
-int hyb_classify(mis_graph* g, hipStream_t s) {
-    HLAUNCH(k_hyb_meta_clear, 1, g->meta);
-    return hyb_lists_build(g, g->dense_min > 0 ? g->dflag : nullptr, s);
-}
-
-int hyb_init(mis_graph* g, hipStream_t s) {
-    if (g->dyn_edited && g->n > 0) {   // a dynamic handle's rows changed since they were classified
-        TC_CHECK(hyb_classify(g, s));
-        g->dyn_edited = false;
-    }
-    const int64_t nw = ceil_div(g->n, 32);
+int hyb_init(GraphCore* g, hipStream_t s) {
     if (g->n > 0)
-        hipLaunchKernelGGL(k_hyb_init, dim3(stream_grid(std::max(nw, g->count > 0 ? g->n : 0))), dim3(kBlock), 0, s,
-                           g->s1, g->a1, g->hS, g->hA, g->count > 0 ? g->dround : nullptr, g->n, nw);
+        hipLaunchKernelGGL(k_hyb_init, dim3(stream_grid(g->n)), dim3(kBlock), 0, s, g->hcnt, g->n, g->hS, g->hA,
+                           g->count > 0 ? g->dround : nullptr, g->stripes);
     TC_HIP(hipGetLastError());
     return MIS_OK;
 }
 
 // phase 0 = candidate kernel, 1 = exclusion kernel
-int hyb_enqueue_phase(mis_graph* g, int phase, int r, hipStream_t s) {
+int hyb_enqueue_phase(GraphCore* g, int phase, int r, hipStream_t s) {
     HybArgs a = make_args(g);
     if (phase == 0) hipLaunchKernelGGL(k_hyb_p1, dim3(g->grid_blocks), dim3(kBlock), 0, s, a, r);
     else hipLaunchKernelGGL(k_hyb_p2, dim3(g->grid_blocks), dim3(kBlock), 0, s, a, r);
@@ -972,12 +1004,12 @@ int hyb_enqueue_phase(mis_graph* g, int phase, int r, hipStream_t s) {
 }
 
 // k rounds as one cooperative launch (see k_hyb_rounds)
-int hyb_enqueue_rounds(mis_graph* g, int k, hipStream_t s) {
+int hyb_enqueue_rounds(GraphCore* g, int k, hipStream_t s) {
     HybArgs a = make_args(g);
     return launch_cooperative((const void*)k_hyb_rounds, g, &a, k, s);
 }
 
-int hyb_output(mis_graph* g, uint8_t* in_set, bool if_done, hipStream_t s) {
+int hyb_output(GraphCore* g, uint8_t* in_set, bool if_done, hipStream_t s) {
     const Ctrl* gate = if_done ? g->ctrl : nullptr;
     if (g->n > 0 && ((uintptr_t)in_set & 3) == 0)
         hipLaunchKernelGGL(k_hyb_output4, dim3(stream_grid(ceil_div(g->n, 4))), dim3(kBlock), 0, s, gate, g->hS, g->n,
@@ -988,4 +1020,260 @@ int hyb_output(mis_graph* g, uint8_t* in_set, bool if_done, hipStream_t s) {
     return MIS_OK;
 }
 
+// ---------------------------------------------------------------- batches of handles
+//
+// Independently built hybrid handles solved together: every round kernel is one
+// launch over all graphs.  Each graph keeps its own structure (only read) and gets
+// its own round state in the caller's scratch; a launch's workgroups are split
+// into per-graph shares (bstart: graph g owns workgroups bstart[g] .. bstart[g+1]-1,
+// at least one), and a share runs the single-graph round code as if it were the
+// whole grid.  Graphs share no edge, so each graph's rounds are those it runs
+// alone (its rule reads only its own vertices).
+
+namespace {
+
+struct MultiDesc {
+    HybArgs a;                // the graph's structure and its round state in the scratch
+    const Meta* meta;
+    Meta* smeta;
+    int64_t n;
+    uint8_t* out;             // the caller's in/out vector of this graph
+};
+
+constexpr int64_t kMultiVerts = 4096;   // vertices per workgroup of a graph's share
+
+// the graph of workgroup b (largest g with bstart[g] <= b; b is uniform)
+__device__ inline int graph_of(const int64_t* bstart, int count, int64_t b) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (bstart[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// round state before round 1, every graph: control block and counters (workgroup 0
+// of the graph's share), then the bitmaps and round 1's candidate count (the
+// counters are cleared in a launch before, so that no workgroup adds into a stripe
+// another one is still clearing)
+__global__ void __launch_bounds__(kBlock) k_multi_ctrl(const MultiDesc* d, int count) {
+    const int64_t g = blockIdx.x;
+    if (g >= count) return;
+    const MultiDesc& D = d[g];
+    if (threadIdx.x == 0) {
+        Ctrl c;
+        memset(&c, 0, sizeof(c));
+        c.alive = D.n;
+        *D.a.ctrl = c;
+        *D.smeta = *D.meta;
+    }
+    for (int i = threadIdx.x; i < 2 * kStripes * kStripeWords; i += kBlock) D.a.stripes[i] = 0;
+}
+
+__global__ void __launch_bounds__(kBlock) k_multi_init(const MultiDesc* d, const int64_t* bstart, int count) {
+    const int g = graph_of(bstart, count, blockIdx.x);
+    const MultiDesc& D = d[g];
+    hyb_init_body(D.a.hcnt, D.n, D.a.S, D.a.A, nullptr, D.a.stripes, blockIdx.x - bstart[g], bstart[g + 1] - bstart[g]);
+}
+
+__global__ void __launch_bounds__(kBlock) k_multi_p1(const MultiDesc* d, const int64_t* bstart, int count, int ri) {
+    const int g = graph_of(bstart, count, blockIdx.x);
+    const HybArgs& a = d[g].a;
+    if (a.ctrl->alive == 0) return;   // finished (and its last round closed) in an earlier launch
+    hyb_p1(a, a.ctrl->rbase + ri, blockIdx.x - bstart[g], bstart[g + 1] - bstart[g]);
+}
+
+__global__ void __launch_bounds__(kBlock) k_multi_p2(const MultiDesc* d, const int64_t* bstart, int count, int ri) {
+    const int g = graph_of(bstart, count, blockIdx.x);
+    const HybArgs& a = d[g].a;
+    if (a.ctrl->alive == 0) return;
+    hyb_p2(a, a.ctrl->rbase + ri, blockIdx.x - bstart[g], bstart[g + 1] - bstart[g]);
+}
+
+// after k rounds: a wave per graph closes its last round and moves its base past
+// it; the undecided vertices of all graphs are summed into sum->alive (cleared
+// before), each graph's rounds and set size recorded
+__global__ void __launch_bounds__(kBlock) k_multi_close(const MultiDesc* d, int count, int k, Ctrl* sum,
+                                                        int32_t* g_rounds, int64_t* g_in) {
+    const int64_t g = (int64_t)blockIdx.x * kWpb + threadIdx.x / kWave;
+    if (g >= count) return;
+    const HybArgs& a = d[g].a;
+    const int rb = a.ctrl->rbase;
+    close_round(a.ctrl, a.stripes, nullptr, rb + k);
+    if (lane_id() == 0) {
+        a.ctrl->rbase = rb + k;
+        const int64_t alive = a.ctrl->alive;
+        if (alive) atomicAdd((unsigned long long*)&sum->alive, (unsigned long long)alive);
+        atomicOr(&sum->error, a.ctrl->error);
+        g_rounds[g] = a.ctrl->round;
+        g_in[g] = a.ctrl->n_in;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_multi_output(const MultiDesc* d, const int64_t* bstart, int count) {
+    const int g = graph_of(bstart, count, blockIdx.x);
+    const int64_t vb = blockIdx.x - bstart[g], nvb = bstart[g + 1] - bstart[g];
+    const MultiDesc& D = d[g];
+    for (int64_t v = vb * kBlock + threadIdx.x; v < D.n; v += nvb * kBlock) D.out[v] = (uint8_t)bit_of(D.a.S, v);
+}
+
+}  // namespace
+
+// Scratch of a batch of handles: a summary control block, the per-graph records
+// (rounds, set sizes), the workgroup shares, the descriptors, then every graph's
+// round state.
+struct MultiLayout {
+    size_t sum = 0, rounds = 0, in = 0, bstart = 0, desc = 0;
+    std::vector<size_t> state;
+    size_t total = 0;
+};
+
+static MultiLayout multi_layout(mis_graph* const* gs, int32_t count) {
+    MultiLayout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        off = (off + 255) & ~(size_t)255;
+        const size_t o = off;
+        off += bytes ? bytes : 8;
+        return o;
+    };
+    L.sum = take(sizeof(Ctrl));
+    L.rounds = take((size_t)count * 4);
+    L.in = take((size_t)count * 8);
+    L.bstart = take((size_t)(count + 1) * 8);
+    L.desc = take((size_t)count * sizeof(MultiDesc));
+    L.state.resize((size_t)count);
+    for (int32_t i = 0; i < count; ++i) {
+        GraphCore v = *gs[i];
+        L.state[(size_t)i] = take(layout_state(&v, nullptr, false));
+    }
+    L.total = (off + 255) & ~(size_t)255;
+    return L;
+}
+
 }  // namespace tcmis
+
+using namespace tcmis;
+
+extern "C" {
+
+int mis_solve_batch_scratch_bytes(mis_graph* const* graphs, int32_t count, size_t* bytes) {
+    set_error("");
+    if (!bytes || count < 0 || (count > 0 && !graphs)) {
+        set_error("bad argument");
+        return MIS_EINVAL;
+    }
+    for (int32_t i = 0; i < count; ++i)
+        if (!graphs[i]) { set_error("a handle is null"); return MIS_EINVAL; }
+    *bytes = multi_layout(graphs, count).total;
+    return MIS_OK;
+}
+
+int mis_solve_batch(mis_graph* const* graphs, int32_t count, uint8_t* const* in_sets, void* scratch,
+                    size_t scratch_bytes, mis_stats* st, int32_t* graph_rounds, int64_t* graph_in, void* stream) {
+    set_error("");
+    if (count < 0 || (count > 0 && (!graphs || !in_sets))) {
+        set_error("bad argument");
+        return MIS_EINVAL;
+    }
+    int64_t nmax = 0, ntot = 0;
+    int poll = 4;
+    for (int32_t i = 0; i < count; ++i) {
+        const mis_graph* g = graphs[i];
+        if (!g) { set_error("a handle is null"); return MIS_EINVAL; }
+        if (g->path != MIS_PATH_HYBRID || g->count > 0) {
+            set_error("a batch of handles takes single-graph hybrid handles (mis_build_tiles, path hybrid)");
+            return MIS_EINVAL;
+        }
+        if (g->n > 0 && !in_sets[i]) { set_error("an output vector is null"); return MIS_EINVAL; }
+        nmax = std::max(nmax, g->n);
+        ntot += g->n;
+        poll = std::max(poll, g->poll_rounds);
+    }
+    const MultiLayout L = multi_layout(graphs, count);
+    if (count > 0 && (!scratch || ((uintptr_t)scratch & 255) || scratch_bytes < L.total)) {
+        set_error("scratch must be 256-byte aligned device memory of at least " + std::to_string(L.total) +
+                  " bytes (mis_solve_batch_scratch_bytes)");
+        return MIS_EINVAL;
+    }
+    if (st) {
+        st->rounds = 0;
+        st->n_in = 0;
+        st->path = MIS_PATH_HYBRID;
+        st->tile = 16;
+        st->tiles = 0;
+    }
+    if (count == 0) return MIS_OK;
+    hipStream_t s = (hipStream_t)stream;
+    char* base = (char*)scratch;
+    Ctrl* sum = (Ctrl*)(base + L.sum);
+    int32_t* d_rounds = (int32_t*)(base + L.rounds);
+    int64_t* d_in = (int64_t*)(base + L.in);
+    int64_t* d_bstart = (int64_t*)(base + L.bstart);
+    MultiDesc* d_desc = (MultiDesc*)(base + L.desc);
+    std::vector<MultiDesc> desc((size_t)count);
+    std::vector<int64_t> bstart((size_t)count + 1, 0);
+    for (int32_t i = 0; i < count; ++i) {
+        GraphCore v = *graphs[i];
+        layout_state(&v, base + L.state[(size_t)i], false);
+        MultiDesc& D = desc[(size_t)i];
+        D.a = make_args(&v);
+        D.a.trace = nullptr;
+        D.a.dround = nullptr;
+        D.meta = v.meta;
+        D.smeta = v.smeta;
+        D.n = v.n;
+        D.out = in_sets[i];
+        const int64_t share = std::min<int64_t>(std::max<int64_t>(1, ceil_div(v.n, kMultiVerts)),
+                                                std::max(1, v.grid_blocks));
+        bstart[(size_t)i + 1] = bstart[(size_t)i] + share;
+    }
+    const int64_t nblocks = bstart[(size_t)count];
+    if (nblocks >= (1ll << 31)) { set_error("too many workgroups for one launch"); return MIS_EINVAL; }
+    TC_HIP(hipMemcpyAsync(d_desc, desc.data(), desc.size() * sizeof(MultiDesc), hipMemcpyHostToDevice, s));
+    TC_HIP(hipMemcpyAsync(d_bstart, bstart.data(), bstart.size() * 8, hipMemcpyHostToDevice, s));
+    const dim3 grid((unsigned)nblocks), blk(kBlock), cgrid((unsigned)ceil_div(count, kWpb));
+    hipLaunchKernelGGL(k_multi_ctrl, dim3((unsigned)count), blk, 0, s, d_desc, count);
+    hipLaunchKernelGGL(k_multi_init, grid, blk, 0, s, d_desc, d_bstart, count);
+    TC_HIP(hipGetLastError());
+    Ctrl h;
+    int32_t r = 0;
+    for (;;) {
+        for (int i = 1; i <= poll; ++i) {
+            hipLaunchKernelGGL(k_multi_p1, grid, blk, 0, s, d_desc, d_bstart, count, i);
+            hipLaunchKernelGGL(k_multi_p2, grid, blk, 0, s, d_desc, d_bstart, count, i);
+        }
+        TC_HIP(hipMemsetAsync(sum, 0, sizeof(Ctrl), s));
+        hipLaunchKernelGGL(k_multi_close, cgrid, blk, 0, s, d_desc, count, poll, sum, d_rounds, d_in);
+        TC_HIP(hipGetLastError());
+        TC_HIP(hipMemcpyAsync(&h, sum, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+        TC_HIP(hipStreamSynchronize(s));
+        r += poll;
+        if (h.error) { set_error("a device-side check of the round kernels failed"); return MIS_EINTERNAL; }
+        if (h.alive == 0) break;
+        if (r > nmax + 1 + poll) { set_error("round limit exceeded (equal adjacent keys?)"); return MIS_EINTERNAL; }
+    }
+    hipLaunchKernelGGL(k_multi_output, grid, blk, 0, s, d_desc, d_bstart, count);
+    TC_HIP(hipGetLastError());
+    std::vector<int32_t> hr((size_t)count);
+    std::vector<int64_t> hi((size_t)count);
+    TC_HIP(hipMemcpyAsync(hr.data(), d_rounds, (size_t)count * 4, hipMemcpyDeviceToHost, s));
+    TC_HIP(hipMemcpyAsync(hi.data(), d_in, (size_t)count * 8, hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+    int32_t rmax = 0;
+    int64_t in = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        rmax = std::max(rmax, hr[(size_t)i]);
+        in += hi[(size_t)i];
+    }
+    if (graph_rounds) std::copy(hr.begin(), hr.end(), graph_rounds);
+    if (graph_in) std::copy(hi.begin(), hi.end(), graph_in);
+    if (st) {
+        st->rounds = rmax;
+        st->n_in = in;
+    }
+    (void)ntot;
+    return MIS_OK;
+}
+
+}  // extern "C"

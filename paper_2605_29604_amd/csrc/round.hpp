@@ -33,8 +33,11 @@ __device__ inline int64_t atomic_read(int64_t* p) {
 // Adds per-thread counts to round r's counters: a wave sum, a workgroup sum in LDS,
 // then one atomic per counter into the workgroup's stripe.  Every thread of the
 // workgroup must call it (it synchronises the workgroup).
+// (blk: the workgroup's index within the launch, or within its graph's share of a
+// launch over several graphs)
 template <int N>
-__device__ inline void block_count(int64_t* stripes, int r, const int (&idx)[N], int64_t (&x)[N]) {
+__device__ inline void block_count(int64_t* stripes, int r, const int (&idx)[N], int64_t (&x)[N],
+                                   int64_t blk = -1) {
     __shared__ int64_t part[kBlock / kWave][N];
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     #pragma unroll
@@ -46,7 +49,8 @@ __device__ inline void block_count(int64_t* stripes, int r, const int (&idx)[N],
     if (threadIdx.x < N) {
         int64_t sum = 0;
         for (int w = 0; w < kBlock / kWave; ++w) sum += part[w][threadIdx.x];
-        int64_t* st = stripes + ((int64_t)(r & 1) * kStripes + blockIdx.x % kStripes) * kStripeWords;
+        const int64_t b = blk < 0 ? (int64_t)blockIdx.x : blk;
+        int64_t* st = stripes + ((int64_t)(r & 1) * kStripes + b % kStripes) * kStripeWords;
         if (sum) atomicAdd((unsigned long long*)&st[idx[threadIdx.x]], (unsigned long long)sum);
     }
 }
@@ -54,7 +58,7 @@ __device__ inline void block_count(int64_t* stripes, int r, const int (&idx)[N],
 // Closes round r (one full wave, uniform control flow): sums and clears the
 // round's counter stripes, writes its trace record and advances `round` and
 // `alive`.  A round that is already closed, or that ran after every vertex was
-// decided, is left alone.
+// decided, is left alone.  trace == nullptr: no trace record.
 __device__ inline void close_round(Ctrl* ctrl, int64_t* stripes, TraceRec* trace, int r) {
     if (r < 1 || ctrl->round != r - 1 || ctrl->alive == 0) return;
     const int lane = lane_id();
@@ -74,7 +78,7 @@ __device__ inline void close_round(Ctrl* ctrl, int64_t* stripes, TraceRec* trace
         rec.alive = ctrl->alive - rec.c - rec.x;
         rec.round = r;
         for (int i = 0; i < kUnits; ++i) rec.u[i] = v[2 + i];
-        trace[(r - 1) % kTraceCap] = rec;
+        if (trace) trace[(r - 1) % kTraceCap] = rec;
         ctrl->n_in += rec.c;
         ctrl->alive = rec.alive;
         ctrl->round = r;
@@ -83,8 +87,8 @@ __device__ inline void close_round(Ctrl* ctrl, int64_t* stripes, TraceRec* trace
 
 // Round prologue run by the first wave of round r's first kernel: closes round
 // r-1 and empties the lists that round r's last kernel fills.
-__device__ inline void open_round(Ctrl* ctrl, int64_t* stripes, TraceRec* trace, int r) {
-    if (blockIdx.x == 0 && threadIdx.x < kWave) {
+__device__ inline void open_round(Ctrl* ctrl, int64_t* stripes, TraceRec* trace, int r, int64_t blk = -1) {
+    if ((blk < 0 ? (int64_t)blockIdx.x : blk) == 0 && threadIdx.x < kWave) {
         close_round(ctrl, stripes, trace, r - 1);
         if (threadIdx.x < 4) ctrl->n_act[r & 1][threadIdx.x] = 0;
     }
@@ -131,6 +135,6 @@ __device__ inline void finish_rounds(Ctrl* ctrl, int64_t* stripes, TraceRec* tra
 
 // Cooperative launch of a persistent round kernel taking (args, k); defined with
 // the round loop.
-int launch_cooperative(const void* kernel, mis_graph* g, void* args, int k, hipStream_t s);
+int launch_cooperative(const void* kernel, GraphCore* g, void* args, int k, hipStream_t s);
 
 }  // namespace tcmis

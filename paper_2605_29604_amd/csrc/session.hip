@@ -201,44 +201,88 @@ int mis_session_admit(mis_session* S, const mis_csr* csr, int32_t csr_on_host, c
     return MIS_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// One pass over the slots.  step: a request whose last batch of rounds has drained
+// gets its next batch, or its output once it is done.  poll: a request whose output
+// has landed is retired into done (at most cap).  Returns through *moved whether
+// anything changed.
+int session_pass(mis_session* S, bool step, bool poll, mis_done* done, int32_t cap, int32_t* n_done, int32_t* moved) {
+    for (Slot& sl : S->slots) {
+        if (sl.phase == Phase::Idle) continue;
+        if (sl.phase == Phase::Rounds && !step) continue;
+        if (sl.phase == Phase::Output && (!poll || *n_done >= cap)) continue;
+        const hipError_t q = hipEventQuery(sl.ev);
+        if (q == hipErrorNotReady) continue;
+        if (q != hipSuccess) return sfail(MIS_EHIP, std::string("request event: ") + hipGetErrorString(q));
+        if (sl.phase == Phase::Rounds) {
+            sl.rounds = sl.h_ctrl->round;
+            sl.n_in = sl.h_ctrl->n_in;
+            if (sl.h_ctrl->error != 0) {
+                sl.status = MIS_EINTERNAL;   // a device-side invariant check failed
+                TC_CHECK(enqueue_output(sl));
+            } else if (sl.h_ctrl->alive == 0) {
+                TC_CHECK(enqueue_output(sl));
+            } else if (sl.h_ctrl->round > sl.n + 1) {
+                sl.status = MIS_EINTERNAL;   // a strict key order decides a vertex every round
+                TC_CHECK(enqueue_output(sl));
+            } else {
+                TC_CHECK(enqueue_step(S, sl));
+            }
+        } else {
+            mis_done& d = done[(*n_done)++];
+            d.tag = sl.tag;
+            d.status = sl.status;
+            d.rounds = sl.rounds;
+            d.n = sl.n;
+            d.n_in = sl.n_in;
+            d.admit_s = sl.t_admit;
+            d.done_s = now_s(S->t0);
+            retire(S, sl);
+        }
+        ++*moved;
+    }
+    return MIS_OK;
+}
+
+bool any_in(const mis_session* S, Phase p) {
+    for (const Slot& sl : S->slots)
+        if (sl.phase == p) return true;
+    return false;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mis_session_step(mis_session* S, int32_t* advanced) {
+    if (!S) return sfail(MIS_EINVAL, "session is null");
+    int32_t moved = 0, nd = 0;
+    TC_CHECK(session_pass(S, true, false, nullptr, 0, &nd, &moved));
+    if (advanced) *advanced = moved;
+    return MIS_OK;
+}
+
+int mis_session_poll(mis_session* S, int32_t wait, mis_done* done, int32_t cap, int32_t* n_done) {
+    if (!S || !n_done || cap < 0 || (cap > 0 && !done)) return sfail(MIS_EINVAL, "bad argument");
+    *n_done = 0;
+    for (;;) {
+        int32_t moved = 0;
+        TC_CHECK(session_pass(S, false, true, done, cap, n_done, &moved));
+        if (!wait || *n_done > 0 || *n_done >= cap || !any_in(S, Phase::Output)) break;
+        if (!moved) std::this_thread::yield();
+    }
+    return MIS_OK;
+}
+
 int mis_session_progress(mis_session* S, int32_t wait, mis_done* done, int32_t cap, int32_t* n_done) {
     if (!S || !n_done || cap < 0 || (cap > 0 && !done)) return sfail(MIS_EINVAL, "bad argument");
     *n_done = 0;
     for (;;) {
-        bool moved = false;
-        for (Slot& sl : S->slots) {
-            if (sl.phase == Phase::Idle) continue;
-            const hipError_t q = hipEventQuery(sl.ev);
-            if (q == hipErrorNotReady) continue;
-            if (q != hipSuccess) return sfail(MIS_EHIP, std::string("request event: ") + hipGetErrorString(q));
-            if (sl.phase == Phase::Rounds) {
-                sl.rounds = sl.h_ctrl->round;
-                sl.n_in = sl.h_ctrl->n_in;
-                if (sl.h_ctrl->error != 0) {
-                    sl.status = MIS_EINTERNAL;   // a device-side invariant check failed
-                    TC_CHECK(enqueue_output(sl));
-                } else if (sl.h_ctrl->alive == 0) {
-                    TC_CHECK(enqueue_output(sl));
-                } else if (sl.h_ctrl->round > sl.n + 1) {
-                    sl.status = MIS_EINTERNAL;   // a strict key order decides a vertex every round
-                    TC_CHECK(enqueue_output(sl));
-                } else {
-                    TC_CHECK(enqueue_step(S, sl));
-                }
-                moved = true;
-            } else if (*n_done < cap) {
-                mis_done& d = done[(*n_done)++];
-                d.tag = sl.tag;
-                d.status = sl.status;
-                d.rounds = sl.rounds;
-                d.n = sl.n;
-                d.n_in = sl.n_in;
-                d.admit_s = sl.t_admit;
-                d.done_s = now_s(S->t0);
-                retire(S, sl);
-                moved = true;
-            }
-        }
+        int32_t moved = 0;
+        TC_CHECK(session_pass(S, true, true, done, cap, n_done, &moved));
         if (!wait || *n_done > 0 || S->live == 0 || *n_done >= cap) break;
         if (!moved) std::this_thread::yield();
     }

@@ -195,7 +195,7 @@ __global__ void k_csr_output(const Ctrl* gate, const uint32_t* st, int64_t n, ui
         in_set[v] = (st[v] & 3u) == kIn ? 1 : 0;
 }
 
-CsrArgs make_args(mis_graph* g) {
+CsrArgs make_args(GraphCore* g) {
     CsrArgs a;
     a.rp = g->row_ptr; a.ci = g->col_idx; a.key = g->key; a.ak = g->ak; a.st = g->st;
     a.ctrl = g->ctrl; a.stripes = g->stripes; a.trace = g->trace;
@@ -209,12 +209,12 @@ CsrArgs make_args(mis_graph* g) {
 }  // namespace
 
 // k rounds as one cooperative launch (see k_csr_rounds)
-int csr_enqueue_rounds(mis_graph* g, int k, hipStream_t s) {
+int csr_enqueue_rounds(GraphCore* g, int k, hipStream_t s) {
     CsrArgs a = make_args(g);
     return launch_cooperative((const void*)k_csr_rounds, g, &a, k, s);
 }
 
-int csr_init(mis_graph* g, hipStream_t s) {
+int csr_init(GraphCore* g, hipStream_t s) {
     if (g->n > 0)
         hipLaunchKernelGGL(k_csr_init, dim3(stream_grid(g->n)), dim3(kBlock), 0, s, g->key, g->ak, g->st, g->n);
     TC_HIP(hipGetLastError());
@@ -222,7 +222,7 @@ int csr_init(mis_graph* g, hipStream_t s) {
 }
 
 // phase 0 = candidate kernel, 1 = exclusion kernel (which closes the round)
-int csr_enqueue_phase(mis_graph* g, int phase, int r, hipStream_t s) {
+int csr_enqueue_phase(GraphCore* g, int phase, int r, hipStream_t s) {
     CsrArgs a = make_args(g);
     if (phase == 0) hipLaunchKernelGGL(k_csr_cand, dim3(g->grid_blocks), dim3(kBlock), 0, s, a, r);
     else hipLaunchKernelGGL(k_csr_excl, dim3(g->grid_blocks), dim3(kBlock), 0, s, a, r);
@@ -230,7 +230,7 @@ int csr_enqueue_phase(mis_graph* g, int phase, int r, hipStream_t s) {
     return MIS_OK;
 }
 
-int csr_output(mis_graph* g, uint8_t* in_set, bool if_done, hipStream_t s) {
+int csr_output(GraphCore* g, uint8_t* in_set, bool if_done, hipStream_t s) {
     if (g->n > 0)
         hipLaunchKernelGGL(k_csr_output, dim3(stream_grid(g->n)), dim3(kBlock), 0, s, if_done ? g->ctrl : nullptr,
                            g->st, g->n, in_set);

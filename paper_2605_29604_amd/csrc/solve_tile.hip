@@ -557,7 +557,7 @@ __global__ void k_tile_init(const uint32_t* hrows, RowState* rs, uint32_t* hit, 
     }
 }
 
-TileArgs make_args(mis_graph* g) {
+TileArgs make_args(GraphCore* g) {
     TileArgs a;
     a.rb_chunk = g->rb_chunk;
     a.tile_col = g->tile_col;
@@ -584,7 +584,7 @@ TileArgs make_args(mis_graph* g) {
 }
 
 template <int T, int ORIENT>
-void launch_phase(mis_graph* g, int phase, int r, hipStream_t s) {
+void launch_phase(GraphCore* g, int phase, int r, hipStream_t s) {
     TileArgs a = make_args(g);
     if (phase == 0) hipLaunchKernelGGL((k_tile_cand<T, ORIENT>), dim3(g->grid_blocks), dim3(kBlock), 0, s, a, r);
     else if (phase == 1) hipLaunchKernelGGL((k_tile_excl<T>), dim3(g->grid_blocks), dim3(kBlock), 0, s, a, r);
@@ -592,7 +592,7 @@ void launch_phase(mis_graph* g, int phase, int r, hipStream_t s) {
 }
 
 template <int T, int ORIENT>
-int launch_rounds(mis_graph* g, int k, hipStream_t s) {
+int launch_rounds(GraphCore* g, int k, hipStream_t s) {
     TileArgs a = make_args(g);
     return launch_cooperative((const void*)k_tile_rounds<T, ORIENT>, g, &a, k, s);
 }
@@ -600,12 +600,12 @@ int launch_rounds(mis_graph* g, int k, hipStream_t s) {
 }  // namespace
 
 // k rounds as one cooperative launch (see k_tile_rounds)
-int tile_enqueue_rounds(mis_graph* g, int k, hipStream_t s) {
+int tile_enqueue_rounds(GraphCore* g, int k, hipStream_t s) {
     if (g->tile == 16) return g->orient ? launch_rounds<16, 1>(g, k, s) : launch_rounds<16, 0>(g, k, s);
     return g->orient ? launch_rounds<32, 1>(g, k, s) : launch_rounds<32, 0>(g, k, s);
 }
 
-int tile_init(mis_graph* g, hipStream_t s) {
+int tile_init(GraphCore* g, hipStream_t s) {
     if (g->nI > 0)
         hipLaunchKernelGGL(k_tile_init, dim3(stream_grid(g->nI)), dim3(kBlock), 0, s, g->hrows, g->rs, g->hit,
                            g->inmask, g->n, g->nI, g->tile, g->orient);
@@ -614,7 +614,7 @@ int tile_init(mis_graph* g, hipStream_t s) {
 }
 
 // phase 0 = candidate kernel, 1 = exclusion kernel, 2 = finalize kernel
-int tile_enqueue_phase(mis_graph* g, int phase, int r, hipStream_t s) {
+int tile_enqueue_phase(GraphCore* g, int phase, int r, hipStream_t s) {
     if (g->tile == 16) {
         if (g->orient) launch_phase<16, 1>(g, phase, r, s); else launch_phase<16, 0>(g, phase, r, s);
     } else {
@@ -624,7 +624,7 @@ int tile_enqueue_phase(mis_graph* g, int phase, int r, hipStream_t s) {
     return MIS_OK;
 }
 
-int tile_output(mis_graph* g, uint8_t* in_set, bool if_done, hipStream_t s) {
+int tile_output(GraphCore* g, uint8_t* in_set, bool if_done, hipStream_t s) {
     const int tshift = g->tile == 16 ? 4 : 5;
     const Ctrl* gate = if_done ? g->ctrl : nullptr;
     if (g->n > 0 && ((uintptr_t)in_set & 3) == 0)   // new_id is a 256-byte aligned workspace array

@@ -182,7 +182,7 @@ int mis_autotune(const mis_csr* csr, int32_t count, const int64_t* offsets, cons
                 mis_graph* g = nullptr;
                 ok = hipEventRecord(e0, s) == hipSuccess;
                 if (ok) ok = mis_build_batch(csr, count, offsets, &o, ws, build_bytes, stream, &g) == MIS_OK;
-                if (ok) ok = mis_solve(g, trial_out, 0, nullptr, stream) == MIS_OK;
+                if (ok) ok = mis_solve(g, trial_out, 0, nullptr, 0, nullptr, stream) == MIS_OK;
                 if (ok) ok = hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
                 if (ok) ok = hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
                 mis_free_tiles(g);

@@ -28,9 +28,11 @@ REORDERS = {"auto": REORDER_AUTO, "none": REORDER_NONE, "degree": REORDER_DEGREE
 
 # symbols declared in include/tcmis.h
 EXPORTS = ["mis_default_opts", "mis_build_bytes", "mis_build_tiles", "mis_build_batch_bytes", "mis_build_batch",
-           "mis_graph_bytes", "mis_solve", "mis_solve_batch", "mis_free_tiles", "mis_status_string", "mis_last_error",
+           "mis_graph_bytes", "mis_solve", "mis_solve_scratch_bytes", "mis_solve_union", "mis_solve_batch",
+           "mis_solve_batch_scratch_bytes", "mis_free_tiles", "mis_status_string", "mis_last_error",
            "mis_version", "mis_autotune_bytes", "mis_autotune", "mis_autotune_clear", "mis_session_create",
-           "mis_session_admit", "mis_session_progress", "mis_session_query", "mis_session_destroy",
+           "mis_session_admit", "mis_session_progress", "mis_session_step", "mis_session_poll", "mis_session_query",
+           "mis_session_destroy",
            "mis_release_host_buffers", "mis_build_times", "mis_solve_noalloc", "mis_noalloc_max_bytes",
            "mis_update_edges"]
 
@@ -99,15 +101,23 @@ def lib():
     L.mis_build_tiles.restype = ctypes.c_int
     L.mis_graph_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
     L.mis_graph_bytes.restype = ctypes.c_int
-    L.mis_solve.argtypes = [vp, vp, i32, ctypes.POINTER(MisStats), vp]
+    L.mis_solve.argtypes = [vp, vp, i32, vp, ctypes.c_size_t, ctypes.POINTER(MisStats), vp]
     L.mis_solve.restype = ctypes.c_int
+    L.mis_solve_scratch_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.mis_solve_scratch_bytes.restype = ctypes.c_int
     L.mis_build_batch_bytes.argtypes = [ctypes.POINTER(MisCsr), i32, ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(MisBuildOpts), ctypes.POINTER(ctypes.c_size_t)]
     L.mis_build_batch_bytes.restype = ctypes.c_int
     L.mis_build_batch.argtypes = [ctypes.POINTER(MisCsr), i32, ctypes.POINTER(ctypes.c_int64),
                                   ctypes.POINTER(MisBuildOpts), vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
     L.mis_build_batch.restype = ctypes.c_int
-    L.mis_solve_batch.argtypes = [vp, vp, ctypes.POINTER(MisStats), ctypes.POINTER(ctypes.c_int32),
+    L.mis_solve_union.argtypes = [vp, vp, ctypes.POINTER(MisStats), ctypes.POINTER(ctypes.c_int32),
+                                  ctypes.POINTER(ctypes.c_int64), vp]
+    L.mis_solve_union.restype = ctypes.c_int
+    L.mis_solve_batch_scratch_bytes.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(ctypes.c_size_t)]
+    L.mis_solve_batch_scratch_bytes.restype = ctypes.c_int
+    L.mis_solve_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp), vp, ctypes.c_size_t,
+                                  ctypes.POINTER(MisStats), ctypes.POINTER(ctypes.c_int32),
                                   ctypes.POINTER(ctypes.c_int64), vp]
     L.mis_solve_batch.restype = ctypes.c_int
     L.mis_autotune_bytes.argtypes = [ctypes.POINTER(MisCsr), i32, ctypes.POINTER(ctypes.c_int64),
@@ -126,6 +136,10 @@ def lib():
     L.mis_session_admit.restype = ctypes.c_int
     L.mis_session_progress.argtypes = [vp, i32, ctypes.POINTER(MisDone), i32, ctypes.POINTER(ctypes.c_int32)]
     L.mis_session_progress.restype = ctypes.c_int
+    L.mis_session_step.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.mis_session_step.restype = ctypes.c_int
+    L.mis_session_poll.argtypes = [vp, i32, ctypes.POINTER(MisDone), i32, ctypes.POINTER(ctypes.c_int32)]
+    L.mis_session_poll.restype = ctypes.c_int
     L.mis_session_query.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_size_t),
                                     ctypes.POINTER(ctypes.c_size_t)]
     L.mis_session_query.restype = ctypes.c_int
@@ -273,13 +287,22 @@ def _new_stats(trace_cap: int, timing: bool):
     return st, buf
 
 
-def mis_solve(g: MisGraph, out=None, max_rounds=0, trace_cap=4096, timing=False, stream=None):
-    """Returns (in_set cuda uint8[n], stats dict)."""
+def mis_solve_scratch_bytes(g: MisGraph) -> int:
+    b = ctypes.c_size_t(0)
+    _check(lib().mis_solve_scratch_bytes(g.handle, ctypes.byref(b)))
+    return int(b.value)
+
+
+def mis_solve(g: MisGraph, out=None, max_rounds=0, trace_cap=4096, timing=False, stream=None, scratch=None):
+    """Returns (in_set cuda uint8[n], stats dict).  scratch: a cuda uint8 tensor of at
+    least mis_solve_scratch_bytes(g) bytes for this solve's round state (None: the
+    handle's own)."""
     import torch
     if out is None:
         out = torch.empty(max(g.n, 0), dtype=torch.uint8, device="cuda")
     st, buf = _new_stats(trace_cap, timing)
-    _check(lib().mis_solve(g.handle, _ptr(out) if g.n else None, int(max_rounds), ctypes.byref(st),
+    sp, sb = (None, 0) if scratch is None else (_ptr(scratch), scratch.numel() * scratch.element_size())
+    _check(lib().mis_solve(g.handle, _ptr(out) if g.n else None, int(max_rounds), sp, sb, ctypes.byref(st),
                            ctypes.c_void_p(_stream(stream))))
     return out, _stats_dict(st, buf)
 
@@ -323,20 +346,56 @@ def mis_build_batch(row_ptr, col_idx, offsets, path="auto", tile=0, reorder="aut
     return g
 
 
-def mis_solve_batch(g: MisGraph, out=None, trace_cap=4096, stream=None):
-    """Returns (in_set cuda uint8[n] of the union, batch stats, per-graph rounds int32[count],
-    per-graph set sizes int64[count])."""
+def mis_solve_union(g: MisGraph, out=None, trace_cap=4096, stream=None):
+    """Solves a handle built by mis_build_batch.  Returns (in_set cuda uint8[n] of the
+    union, batch stats, per-graph rounds int32[count], per-graph set sizes int64[count])."""
     import torch
     if out is None:
         out = torch.empty(max(g.n, 0), dtype=torch.uint8, device="cuda")
     st, buf = _new_stats(trace_cap, False)
     rounds = np.zeros(max(g.count, 1), dtype=np.int32)
     sizes = np.zeros(max(g.count, 1), dtype=np.int64)
-    _check(lib().mis_solve_batch(g.handle, _ptr(out) if g.n else None, ctypes.byref(st),
+    _check(lib().mis_solve_union(g.handle, _ptr(out) if g.n else None, ctypes.byref(st),
                                  rounds.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                  sizes.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                  ctypes.c_void_p(_stream(stream))))
     return out, _stats_dict(st, buf), rounds[: g.count], sizes[: g.count]
+
+
+def _handle_array(graphs):
+    arr = (ctypes.c_void_p * max(1, len(graphs)))()
+    for i, g in enumerate(graphs):
+        arr[i] = g.handle.value if isinstance(g.handle, ctypes.c_void_p) else g.handle
+    return arr
+
+
+def mis_solve_batch_scratch_bytes(graphs) -> int:
+    b = ctypes.c_size_t(0)
+    _check(lib().mis_solve_batch_scratch_bytes(_handle_array(graphs), len(graphs), ctypes.byref(b)))
+    return int(b.value)
+
+
+def mis_solve_batch(graphs, outs=None, scratch=None, stream=None):
+    """Solves independently built single-graph hybrid handles together (one launch per
+    round kernel over all of them).  Returns (list of cuda uint8 outputs, batch stats,
+    per-graph rounds int32[count], per-graph set sizes int64[count])."""
+    import torch
+    graphs = list(graphs)
+    if outs is None:
+        outs = [torch.empty(max(g.n, 1), dtype=torch.uint8, device="cuda") for g in graphs]
+    if scratch is None:
+        scratch = torch.empty(max(1, mis_solve_batch_scratch_bytes(graphs)), dtype=torch.uint8, device="cuda")
+    ptrs = (ctypes.c_void_p * max(1, len(graphs)))()
+    for i, o in enumerate(outs):
+        ptrs[i] = o.data_ptr()
+    st, buf = _new_stats(0, False)
+    rounds = np.zeros(max(len(graphs), 1), dtype=np.int32)
+    sizes = np.zeros(max(len(graphs), 1), dtype=np.int64)
+    _check(lib().mis_solve_batch(_handle_array(graphs), len(graphs), ptrs, _ptr(scratch), scratch.numel(),
+                                 ctypes.byref(st), rounds.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                 sizes.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                 ctypes.c_void_p(_stream(stream))))
+    return outs, _stats_dict(st, buf), rounds[: len(graphs)], sizes[: len(graphs)]
 
 
 _PATH_NAMES = {v: k for k, v in PATHS.items()}
@@ -466,9 +525,26 @@ class Session:
         self._keep[int(tag)] = (row_ptr, col_idx, out, host_out, opts)
         return True
 
+    def step(self) -> int:
+        """Enqueues the next rounds (or the output) of every request whose last batch
+        drained; returns how many advanced."""
+        adv = ctypes.c_int32(0)
+        _check(lib().mis_session_step(self.handle, ctypes.byref(adv)))
+        return adv.value
+
+    def poll(self, wait=False):
+        """Retires requests whose output landed (enqueues nothing)."""
+        nd = ctypes.c_int32(0)
+        _check(lib().mis_session_poll(self.handle, int(bool(wait)), self._buf, self.cap, ctypes.byref(nd)))
+        return self._retired(nd.value)
+
     def progress(self, wait=False):
         nd = ctypes.c_int32(0)
         _check(lib().mis_session_progress(self.handle, int(bool(wait)), self._buf, self.cap, ctypes.byref(nd)))
+        return self._retired(nd.value)
+
+    def _retired(self, count):
+        nd = ctypes.c_int32(count)
         res = []
         for i in range(nd.value):
             d = self._buf[i]

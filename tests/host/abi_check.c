@@ -77,8 +77,12 @@ int main(void) {
     o.dyn_slack = 4;
     CHECK(mis_build_batch_bytes(&csr, 3, off, &o, &bytes) == MIS_EINVAL);
     /* calls on null handles */
-    CHECK(mis_solve(NULL, NULL, 0, NULL, NULL) == MIS_EINVAL);
-    CHECK(mis_solve_batch(NULL, NULL, NULL, NULL, NULL, NULL) == MIS_EINVAL);
+    CHECK(mis_solve(NULL, NULL, 0, NULL, 0, NULL, NULL) == MIS_EINVAL);
+    CHECK(mis_solve_union(NULL, NULL, NULL, NULL, NULL, NULL) == MIS_EINVAL);
+    CHECK(mis_solve_batch(NULL, 1, NULL, NULL, 0, NULL, NULL, NULL, NULL) == MIS_EINVAL);
+    CHECK(mis_solve_batch_scratch_bytes(NULL, 1, &bytes) == MIS_EINVAL);
+    CHECK(mis_solve_scratch_bytes(NULL, &bytes) == MIS_EINVAL);
+    CHECK(mis_session_step(NULL, NULL) == MIS_EINVAL);
     CHECK(mis_graph_bytes(NULL, NULL) == MIS_EINVAL);
     float ms[4];
     int32_t cnt = 0;

@@ -86,7 +86,10 @@ def test_host_argument_errors(L):
     assert build(L, csr, None, ctypes.c_void_p((1 << 20) + 64), need.value, hp) == tcmis.MIS_EINVAL
     assert build(L, csr, None, None, need.value, hp) == tcmis.MIS_EINVAL
     assert not h.value
-    assert L.mis_solve(None, None, 0, None, None) == tcmis.MIS_EINVAL
+    assert L.mis_solve(None, None, 0, None, 0, None, None) == tcmis.MIS_EINVAL
+    assert L.mis_solve_scratch_bytes(None, None) == tcmis.MIS_EINVAL
+    assert L.mis_session_step(None, None) == tcmis.MIS_EINVAL
+    assert L.mis_session_poll(None, 0, None, 0, None) == tcmis.MIS_EINVAL
     assert L.mis_graph_bytes(None, None) == tcmis.MIS_EINVAL
     L.mis_free_tiles(None)
 
@@ -112,7 +115,9 @@ def test_batch_argument_errors(L):
     with pytest.raises(tcmis.MisError):
         tcmis.mis_build_batch_bytes((1 << 24) + 10, 0, [0, (1 << 24) + 10])   # one graph too large for the key rule
     assert tcmis.mis_build_batch_bytes((1 << 24) + 10, 0, [0, 1 << 23, (1 << 24) + 10]) > 0
-    assert L.mis_solve_batch(None, None, None, None, None, None) == tcmis.MIS_EINVAL
+    assert L.mis_solve_union(None, None, None, None, None, None) == tcmis.MIS_EINVAL
+    assert L.mis_solve_batch(None, 1, None, None, 0, None, None, None, None) == tcmis.MIS_EINVAL
+    assert L.mis_solve_batch_scratch_bytes(None, 1, None) == tcmis.MIS_EINVAL
 
 
 def test_autotune_argument_errors(L):

@@ -231,6 +231,48 @@ def test_repeat_and_poll_interval_deterministic():
             T.mis_free_tiles(h)
 
 
+@pytest.mark.parametrize("cfg", FAST_CONFIGS + [("hybrid", 16, "none", 1, 1)], ids=lambda c: "-".join(map(str, c)))
+def test_concurrent_solves_of_one_handle_with_caller_scratch(cfg):
+    # one built handle, two solves in flight at once on two streams, each with its
+    # own scratch for the round state (the handle is only read); then a third on the
+    # handle's own state: all equal the oracle, set and round trace
+    import threading
+    T = tcmis_mod()
+    g = gen.workload("rmat16", seed=6)
+    k = oracle.keys(g.row_ptr, 3)
+    want, rounds, trace = expected(g.row_ptr, g.col_idx, k)
+    drp, dci = to_dev(g.row_ptr, g.col_idx)
+    h = T.mis_build_tiles(drp, dci, seed=3, **kw(cfg))
+    torch.cuda.synchronize()
+    nb = T.mis_solve_scratch_bytes(h)
+    assert 0 < nb < h.bytes()
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    scratch = [torch.empty(nb, dtype=torch.uint8, device="cuda") for _ in range(2)]
+    outs = [torch.full((g.n,), 7, dtype=torch.uint8, device="cuda") for _ in range(2)]
+    res = [None, None]
+
+    def solve(i):
+        with torch.cuda.stream(streams[i]):
+            res[i] = T.mis_solve(h, out=outs[i], scratch=scratch[i], stream=streams[i])[1]
+
+    th = [threading.Thread(target=solve, args=(i,)) for i in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    torch.cuda.synchronize()
+    print(f"case concurrent scratch cfg={cfg} n={g.n} scratch={nb}", flush=True)
+    for i in range(2):
+        assert np.array_equal(outs[i].cpu().numpy(), want), f"solve {i}"
+        assert res[i]["rounds"] == rounds and np.array_equal(res[i]["trace"], trace)
+    out, st = T.mis_solve(h)
+    assert np.array_equal(out.cpu().numpy(), want) and np.array_equal(st["trace"], trace)
+    with pytest.raises(T.MisError) as ei:   # too small
+        T.mis_solve(h, scratch=scratch[0][: nb - 256])
+    assert ei.value.code == T.MIS_EINVAL
+    T.mis_free_tiles(h)
+
+
 @pytest.mark.parametrize("bad", ["loop", "asym", "dup", "range", "tie"])
 def test_validation_errors(bad):
     T = tcmis_mod()
@@ -360,7 +402,7 @@ def test_persistent_cooperative_rounds(cfg):
     drp, dci = to_dev(rp, ci)
     h = T.mis_build_batch(drp, dci, off, **kw(cfg), seed=2,
                           launch="persistent")
-    out, st, rounds, sizes = T.mis_solve_batch(h)
+    out, st, rounds, sizes = T.mis_solve_union(h)
     torch.cuda.synchronize()
     got = out.cpu().numpy()
     for i, g in enumerate(graphs):
@@ -379,7 +421,7 @@ def solve_batch(graphs, cfg, seed):
     drp, dci = to_dev(rp, ci)
     h = T.mis_build_batch(drp, dci, off, **kw(cfg), seed=seed,
                           validate=True, poll_rounds=3)
-    out, st, rounds, sizes = T.mis_solve_batch(h)
+    out, st, rounds, sizes = T.mis_solve_union(h)
     torch.cuda.synchronize()
     got = out.cpu().numpy()
     T.mis_free_tiles(h)
@@ -414,13 +456,51 @@ def test_batch_eq1_rule_uses_each_graphs_own_average(cfg):
     rp, ci, off = gen.union(graphs)
     drp, dci = to_dev(rp, ci)
     h = T.mis_build_batch(drp, dci, off, seed=4, key_rule="eq1", validate=True, **kw(cfg))
-    out, st, rounds, sizes = T.mis_solve_batch(h)
+    out, st, rounds, sizes = T.mis_solve_union(h)
     torch.cuda.synchronize()
     got = out.cpu().numpy()
     T.mis_free_tiles(h)
     for i, g in enumerate(graphs):
         want, r, _ = expected(g.row_ptr, g.col_idx, oracle.keys_rule(g.row_ptr, 4, "eq1"))
         assert np.array_equal(got[off[i]:off[i + 1]], want) and rounds[i] == r, f"graph {i}"
+
+
+def test_batch_of_prebuilt_handles():
+    # handles built one by one (different sizes, families and dense-block thresholds,
+    # an empty graph and a single vertex among them) solved together without any
+    # concatenation: every graph's set and round count equal the oracle's, the same
+    # handles solve alone to the same sets, and a non-hybrid handle is refused
+    T = tcmis_mod()
+    spec = gen.batch_spec(24, seed=9, n_min=50, n_max=30000)
+    graphs = [gen.make(*sp) for sp in spec] + [gen.grid(9, 10, 11, 0.01, 4), gen.er(0, 0, 1), gen.er(1, 0, 1)]
+    dense = [-1, 1, 9, 4]
+    hs, keep = [], []
+    for i, g in enumerate(graphs):
+        drp, dci = to_dev(g.row_ptr, g.col_idx)
+        keep.append((drp, dci))
+        hs.append(T.mis_build_tiles(drp, dci, path="hybrid", dense_min=dense[i % 4], seed=11))
+    torch.cuda.synchronize()
+    outs, st, rounds, sizes = T.mis_solve_batch(hs)
+    torch.cuda.synchronize()
+    print(f"case handles batch: {len(hs)} graphs, rounds {st['rounds']}", flush=True)
+    for i, g in enumerate(graphs):
+        want, r, _ = expected(g.row_ptr, g.col_idx, oracle.keys(g.row_ptr, 11))
+        assert np.array_equal(outs[i].cpu().numpy()[: g.n], want), f"graph {i} {spec[i] if i < len(spec) else ''}"
+        assert rounds[i] == r and sizes[i] == int(want.sum()), f"graph {i}"
+        if i % 5 == 0:
+            alone, st1 = T.mis_solve(hs[i])
+            assert np.array_equal(alone.cpu().numpy(), want[: g.n]) and st1["rounds"] == r
+    assert st["rounds"] == int(rounds.max()) and st["n_in"] == int(sizes.sum())
+    # a second solve of the same handles with the same scratch: identical
+    outs2, _, rounds2, _ = T.mis_solve_batch(hs)
+    assert all(torch.equal(a, b) for a, b in zip(outs, outs2)) and np.array_equal(rounds, rounds2)
+    drp, dci = keep[0]
+    other = T.mis_build_tiles(drp, dci, path="csr", seed=11)
+    with pytest.raises(T.MisError) as ei:
+        T.mis_solve_batch([hs[0], other])
+    assert ei.value.code == T.MIS_EINVAL
+    for h in hs + [other]:
+        T.mis_free_tiles(h)
 
 
 def test_batch_rejects_cross_edges():
@@ -469,7 +549,7 @@ def test_autotune_batch():
     drp, dci = to_dev(rp, ci)
     opts, _ = T.mis_autotune(drp, dci, off, seed=3)
     h = T.mis_build_batch(drp, dci, off, validate=True, **opts)
-    out, st, rounds, sizes = T.mis_solve_batch(h)
+    out, st, rounds, sizes = T.mis_solve_union(h)
     torch.cuda.synchronize()
     got = out.cpu().numpy()
     T.mis_free_tiles(h)
@@ -506,7 +586,7 @@ def test_batch4096_full_against_oracle():
     print(f"case batch4096 n={off[-1]} nnz={ci_h.size}", flush=True)
     drp, dci = to_dev(rp_h, ci_h)
     h = T.mis_build_batch(drp, dci, off, path="hybrid", seed=1)
-    out, st, rounds, sizes = T.mis_solve_batch(h)
+    out, st, rounds, sizes = T.mis_solve_union(h)
     torch.cuda.synchronize()
     got = out.cpu().numpy()
     T.mis_free_tiles(h)

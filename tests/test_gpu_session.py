@@ -40,9 +40,10 @@ def pinned(a):
     return torch.from_numpy(np.ascontiguousarray(a)).pin_memory()
 
 
-def drive(sess, graphs, opts_of=lambda i: None):
+def drive(sess, graphs, opts_of=lambda i: None, step_poll=False):
     """Admits requests in order as the session accepts them; returns per-request
-    (host result, done record), how often admission was refused, the most live."""
+    (host result, done record), how often admission was refused, the most live.
+    step_poll: drive the session with separate step and poll calls instead of progress."""
     pending = list(range(len(graphs)))
     outs, done = {}, {}
     busy = most_live = 0
@@ -58,7 +59,12 @@ def drive(sess, graphs, opts_of=lambda i: None):
             pending.pop(0)
             print(f"admit request {i} n={graphs[i].n}", flush=True)
         most_live = max(most_live, sess.query()[0])
-        for d in sess.progress(wait=True):
+        if step_poll:
+            sess.step()
+            retired = sess.poll(wait=False)
+        else:
+            retired = sess.progress(wait=True)
+        for d in retired:
             assert d["status"] == 0
             done[d["tag"]] = d
     return {i: (outs[i].numpy()[: graphs[i].n], done[i]) for i in outs}, busy, most_live
@@ -94,6 +100,24 @@ def test_session_mix_equals_alone_and_oracle():
             assert np.array_equal(a, got) and r == d["rounds"], f"request {i} alone"
     live, used, largest = sess.query()
     assert live == 0 and used == 0 and largest == sess.arena.numel() // 256 * 256
+    sess.close()
+
+
+def test_session_step_and_poll_driven_separately():
+    # the same continuous batching, driven by separate step (enqueue the next rounds)
+    # and poll (retire) calls: every result equals the oracle's
+    graphs = mixed_requests(16, seed=5)
+    biggest = max(footprint(g) for g in graphs)
+    sess = T().Session(arena_bytes=3 * biggest, max_live=4, rounds_per_step=1)
+    res, busy, most_live = drive(sess, graphs, step_poll=True)
+    print(f"session step/poll: refused {busy} admissions, up to {most_live} live", flush=True)
+    assert most_live > 1
+    for i, g in enumerate(graphs):
+        got, d = res[i]
+        st, rounds, _ = oracle.roundsync(g.row_ptr, g.col_idx, oracle.keys(g.row_ptr, 1))
+        assert np.array_equal(got, (st == oracle.IN).astype(np.uint8)), f"request {i}"
+        assert d["rounds"] == rounds
+    assert sess.step() == 0 and sess.poll(wait=True) == []
     sess.close()
 
 
