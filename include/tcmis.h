@@ -194,7 +194,7 @@ int mis_build_bytes(const mis_csr* csr, const mis_build_opts* opts, size_t* byte
  * only nonzero tiles are stored, in a compressed block format), or the
  * degree-binned vertex lists of the CSR path.
  *   csr       : the graph (DEVICE arrays; must stay alive and unchanged while the
- *               handle is used -- the CSR path reads it during solves).
+ *               handle is used -- the CSR and hybrid paths read it during solves).
  *   opts      : NULL = defaults.
  *   workspace : DEVICE memory of at least mis_build_bytes bytes, 256-byte aligned,
  *               owned by the caller; it must outlive the handle and must not be
@@ -414,10 +414,11 @@ void mis_session_destroy(mis_session* s);
  * Durations (HOST float[cap], milliseconds, from HIP events on the build stream) of
  * the build stages of a handle built with opts.timing = 1; *count receives the
  * number of stages.  Stages (after validation, which is not timed): keys, then
- *   hybrid path: orientation row search (with clearing the counts and the
- *                blocks' column signatures), orientation (the orientation pass
- *                alone), dense blocks (0 if none); an empty graph has the keys
- *                stage only;
+ *   hybrid path: dense-block scan (the blocks' column signatures), dense blocks
+ *                (exact test and bitmaps), and a last empty stage; a dynamic handle
+ *                (dyn_slack > 0): orientation row search (with clearing the
+ *                counts), orientation, and a last empty stage; an empty graph has
+ *                the keys stage only;
  *   tile path:   vertex order, tiles;
  *   CSR path:    vertex lists.
  * Synchronises the last event.  Errors: MIS_EINVAL (no timing), MIS_EHIP.

@@ -613,11 +613,7 @@ size_t layout_state(GraphCore* g, char* base, bool with_trace) {
         const int64_t nI = ceil_div(n, 16), nw = ceil_div(n, 64) * 2 + 2;   // bitmap words (whole waves)
         c.take(&g->hA, (size_t)nw * 4);
         c.take(&g->hS, (size_t)nw * 4);
-        for (int b = 0; b < 2; ++b) {
-            c.take(&g->hact[b][0], (size_t)n * 4);
-            c.take(&g->hact[b][1], (size_t)n * 4);
-            c.take(&g->hact[b][2], (size_t)(g->dense_min > 0 ? nI : 0) * 4);
-        }
+        for (int b = 0; b < 2; ++b) c.take(&g->hdact[b], (size_t)(g->dense_min > 0 ? nI : 0) * 4);
         if (g->count > 0) c.take(&g->dround, (size_t)n * 4);
     } else if (g->path == MIS_PATH_CSR) {
         for (int b = 0; b < 2; ++b)
@@ -651,13 +647,15 @@ size_t layout(GraphCore* g, char* base) {
         g->nI = ceil_div(n, 16);
         const int64_t nI = g->nI, nw = ceil_div(n, 64) * 2 + 2;   // bitmap words (whole waves)
         c.take(&g->q8, (size_t)n);
-        c.take(&g->hbrow, (size_t)(hyb_blocks(nnz) + 2) * 4);
-        c.take(&g->hbase, (size_t)n * 4);
-        c.take(&g->hoff, (size_t)n * 4);
+        // H rows (static handles: those of the vertices round 1 leaves undecided, at
+        // their input row starts; dynamic handles: every row, with slack)
         const int64_t rows = g->dyn_slack > 0 ? nnz + n * (int64_t)g->dyn_slack : nnz;   // slots per orientation
         c.take(&g->hcol, (size_t)rows * 4);
         c.take(&g->hcnt, (size_t)n * 4);
         if (g->dyn_slack > 0) {
+            c.take(&g->hbrow, (size_t)(hyb_blocks(nnz) + 2) * 4);
+            c.take(&g->hbase, (size_t)n * 4);
+            c.take(&g->hoff, (size_t)n * 4);
             c.take(&g->drp, (size_t)(n + 1) * 8);
             c.take(&g->lcol, (size_t)rows * 4);
             c.take(&g->lcnt, (size_t)n * 4);
@@ -673,7 +671,6 @@ size_t layout(GraphCore* g, char* base) {
             c.take(&g->hflag, (size_t)n * 8);
         }
         if (g->dense_min > 0) {
-            c.take(&g->hsig, (size_t)nI * 8);
             const int64_t tcap = nnz / 2 + 1;   // a dense tile holds at least one oriented entry
             c.take(&g->dflag, (size_t)nI * 4);
             c.take(&g->dpos, (size_t)(nI + 1) * 4);

@@ -26,7 +26,7 @@ int tile_enqueue_rounds(GraphCore* g, int k, hipStream_t s);
 int csr_enqueue_rounds(GraphCore* g, int k, hipStream_t s);
 int build_hybrid(mis_graph* g, hipStream_t s);
 int hyb_init(GraphCore* g, hipStream_t s);
-int hyb_enqueue_phase(GraphCore* g, int phase, int r, hipStream_t s);
+int hyb_enqueue_phase(GraphCore* g, int phase, int r, hipStream_t s, bool first);
 int hyb_output(GraphCore* g, uint8_t* in_set, bool if_done, hipStream_t s);
 int hyb_enqueue_rounds(GraphCore* g, int k, hipStream_t s);
 
@@ -226,8 +226,10 @@ void configure(GraphCore* g, const mis_csr* csr, const mis_build_opts& o) {
 // candidate / exclusion
 int phases(const GraphCore* g) { return g->path == MIS_PATH_TILE ? 3 : 2; }
 
-int enqueue_phase(GraphCore* g, int phase, int r, hipStream_t s) {
-    if (g->path == MIS_PATH_HYBRID) return hyb_enqueue_phase(g, phase, r, s);
+// first: the phase belongs to the solve's first round (the hybrid path gives it a
+// thread per vertex)
+int enqueue_phase(GraphCore* g, int phase, int r, hipStream_t s, bool first) {
+    if (g->path == MIS_PATH_HYBRID) return hyb_enqueue_phase(g, phase, r, s, first);
     return g->path == MIS_PATH_TILE ? tile_enqueue_phase(g, phase, r, s) : csr_enqueue_phase(g, phase, r, s);
 }
 
@@ -268,13 +270,13 @@ __global__ void k_close(Ctrl* ctrl, int64_t* stripes, TraceRec* trace, int k) {
 }
 
 // enqueues a batch of k rounds (round indices 1..k after the device-side base) and
-// the close kernel
-int enqueue_batch(GraphCore* g, int64_t k, hipStream_t s, hipEvent_t* ev) {
+// the close kernel; first: the batch opens the solve
+int enqueue_batch(GraphCore* g, int64_t k, hipStream_t s, hipEvent_t* ev, bool first) {
     for (int64_t i = 0; i < k; ++i) {
         const int P = phases(g);
         for (int ph = 0; ph < P; ++ph) {
             if (ev) (void)hipEventRecord(ev[(P + 1) * i + ph], s);
-            TC_CHECK(enqueue_phase(g, ph, (int)(i + 1), s));
+            TC_CHECK(enqueue_phase(g, ph, (int)(i + 1), s, first && i == 0));
         }
         if (ev) (void)hipEventRecord(ev[(P + 1) * i + P], s);
     }
@@ -290,7 +292,7 @@ bool ensure_graph(mis_graph* g) {
     bool ok = hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking) == hipSuccess &&
               hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
     if (ok) {
-        const int rc = enqueue_batch(g, g->poll_rounds, g->cap_stream, nullptr);
+        const int rc = enqueue_batch(g, g->poll_rounds, g->cap_stream, nullptr, false);
         hipGraph_t graph = nullptr;
         ok = hipStreamEndCapture(g->cap_stream, &graph) == hipSuccess && rc == MIS_OK && graph;
         if (ok) {
@@ -314,10 +316,11 @@ int64_t unit_bytes(const GraphCore* g, int k) {
         return b[k];
     }
     if (g->path == MIS_PATH_HYBRID) {
-        // entries read (4-byte index + the bitmap word it selects), rows examined (list
-        // slot, row start, entry count), tiles multiplied (bitmap + column block),
-        // dense blocks examined (list slot, block slot, tile range, its two bitmap words)
-        static const int64_t b[kUnits] = {8, 16, 8, 16, 36, 36, 24, 24};
+        // entries read (the 4-byte index; the neighbour's class or status is a
+        // per-vertex vector), rows examined (row bounds and key or list slot), tiles
+        // multiplied (bitmap + column block), dense blocks examined (list slot, block
+        // slot, tile range, its two bitmap words)
+        static const int64_t b[kUnits] = {4, 16, 4, 16, 36, 36, 24, 24};
         return b[k];
     }
     // tile path: 4-byte words, bytes, 4-byte words, bitmaps multiplied, row-blocks
@@ -330,6 +333,7 @@ int64_t unit_bytes(const GraphCore* g, int k) {
 }  // namespace
 
 int solve_begin(GraphCore* g, hipStream_t s) {
+    g->enq_rounds = 0;
     hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(256), 0, s, g->ctrl, g->smeta, g->meta, g->stripes, g->n);
     TC_HIP(hipGetLastError());
     if (g->path == MIS_PATH_HYBRID) return hyb_init(g, s);
@@ -353,19 +357,23 @@ int launch_cooperative(const void* kernel, GraphCore* g, void* args, int k, hipS
 }
 
 int solve_rounds(GraphCore* g, int64_t k, bool allow_graph, hipStream_t s, mis_graph* owner) {
+    const bool first = g->enq_rounds == 0;
+    g->enq_rounds += k;
     if (g->launch == MIS_LAUNCH_PERSISTENT) {
         if (g->path == MIS_PATH_HYBRID) return hyb_enqueue_rounds(g, (int)k, s);
         return g->path == MIS_PATH_TILE ? tile_enqueue_rounds(g, (int)k, s) : csr_enqueue_rounds(g, (int)k, s);
     }
     // auto: a handle solved once gains nothing from a capture, which costs more than
-    // the launches it replaces; capture when it is solved again
-    // (only over the handle's own round state: a captured graph holds its addresses)
+    // the launches it replaces; capture when it is solved again (only over the
+    // handle's own round state: a captured graph holds its addresses).  The first
+    // batch of a solve is always launched directly: its first round has a launch
+    // shape of its own.
     const bool graph = owner && (g->launch == MIS_LAUNCH_GRAPH || (g->launch == MIS_LAUNCH_AUTO && owner->solves > 1));
-    if (allow_graph && graph && k == g->poll_rounds && ensure_graph(owner)) {
+    if (allow_graph && graph && !first && k == g->poll_rounds && ensure_graph(owner)) {
         if (hipGraphLaunch(owner->graph_exec, s) != hipSuccess) return fail(MIS_EHIP, "hipGraphLaunch failed");
         return MIS_OK;
     }
-    return enqueue_batch(g, k, s, nullptr);
+    return enqueue_batch(g, k, s, nullptr, first);
 }
 
 int resolve_opts(const mis_csr* csr, const mis_build_opts* opts, mis_build_opts* o, int32_t count,
@@ -539,7 +547,12 @@ int solve_loop(GraphCore* g, mis_graph* owner, uint8_t* in_set, int32_t max_roun
         for (;;) {
             int64_t k = g->poll_rounds;
             if (max_rounds > 0) k = std::min<int64_t>(k, max_rounds - enq);
-            rc = timing ? enqueue_batch(g, k, s, ev.data()) : solve_rounds(g, k, true, s, owner);
+            if (timing) {
+                rc = enqueue_batch(g, k, s, ev.data(), g->enq_rounds == 0);
+                g->enq_rounds += k;
+            } else {
+                rc = solve_rounds(g, k, true, s, owner);
+            }
             // the result, written by the device only if this batch decided the last vertex
             if (rc == MIS_OK) rc = solve_output(g, in_set, s, true);
             if (rc != MIS_OK) break;

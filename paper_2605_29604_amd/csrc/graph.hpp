@@ -72,6 +72,8 @@ struct Meta {
     // hybrid path
     int32_t n_dense;        // dense row-blocks (bit tiles)
     int32_t n_dtiles;       // their tiles
+    int32_t n_dcand;        // dense candidates among the sampled row-blocks
+    int32_t pad2;
 };
 
 }  // namespace tcmis
@@ -101,6 +103,7 @@ struct GraphCore {
 
     bool btiming = false;             // build-stage events (opts.timing = 1)
     int grid_blocks = 2048;           // persistent grid of the round kernels
+    int64_t enq_rounds = 0;           // rounds enqueued since the solve began (host side)
     int coop_blocks = 0;              // grid of the cooperative round kernels (sized at build)
 
     // workspace (caller-owned device memory): the structure, then the handle's own
@@ -178,18 +181,17 @@ struct GraphCore {
     int32_t* hoff = nullptr;          // [n] orientation scratch
     int32_t* hcol = nullptr;          // [nnz] oriented entries: row v's are hcol[rp[v] .. rp[v] + hcnt[v])
     int32_t* hcnt = nullptr;          // [n] higher-priority neighbours of each vertex
-    uint64_t* hsig = nullptr;         // [nI] column-block signature of each 16-row block (dense test)
-    int32_t* dflag = nullptr;         // [nI] dense row-block flags
+    int32_t* dflag = nullptr;         // [nI] dense candidate, then dense, flags
     int32_t* dpos = nullptr;          // [nI+1] their scan: list slot of each dense row-block
     int32_t* dtcnt = nullptr;         // [nI+1] tiles per dense row-block -> first tile
     int32_t* dslot = nullptr;         // [nI] list slot of each dense row-block (-1: entry lists)
-    int32_t* drb = nullptr;           // [nI] dense row-blocks
-    int32_t* dptr = nullptr;          // [nI+1] tile range of each dense row-block (by list position)
+    int32_t* drb = nullptr;           // [nI] dense row-blocks by list slot
+    int32_t* dptr = nullptr;          // [nI+1] first tile of each list slot (slot + 1: the end)
     int32_t* dcol = nullptr;          // [tile cap] column block of each dense tile
     uint32_t* dbits = nullptr;        // [tile cap * 8] 16x16 bitmaps (word w: rows 2w, 2w+1)
     uint32_t* hA = nullptr;           // [nw] undecided vertices (bitmap)
     uint32_t* hS = nullptr;           // [nw] vertices in the set (bitmap)
-    int32_t* hact[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};   // next rounds' lists
+    int32_t* hdact[2] = {nullptr, nullptr};   // dense blocks still undecided, by round parity
     const int64_t* hrp = nullptr;     // row starts of hcol (the input row pointer, or drp)
 
     // ---- dynamic handles (hybrid path, dyn_slack > 0): both orientations in rows of

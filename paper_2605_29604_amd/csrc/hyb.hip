@@ -1,40 +1,42 @@
 // Hybrid path: the rounds of Algorithm 2 over the edges to higher-priority
 // neighbours, stored per 16-row block of the input order either as nonzero 16 x 16
-// bit tiles (Section 3.2) or as sorted entry lists (Section 3.2, "Memory Footprint
-// and Representation Trade-offs": a tile only pays where it holds enough edges).
+// bit tiles (Section 3.2) or as entry lists (Section 3.2, "Memory Footprint and
+// Representation Trade-offs": a tile only pays where it holds enough edges).
 //
 // Why only higher-priority neighbours.  A candidate neighbour of an undecided
 // vertex always out-ranks it (a candidate beats every undecided neighbour), and
-// Phase 1 only asks whether an undecided neighbour out-ranks the vertex.  So both
-// phases read only H(v) = { u in N(v) : key(u) > key(v) }, half the adjacency, and
-// neither reads a key:
+// Phase 1 only asks whether an undecided neighbour out-ranks the vertex.  So after
+// round 1 both phases read only H(v) = { u in N(v) : key(u) > key(v) } and neither
+// reads a key:
 //   Phase 1  C(v) = alive(v) and no u in H(v) is alive
 //   Phase 2  v leaves the undecided set if some u in H(v) joined the set this round
 // With the in-set bitmap S, "joined this round" is simply S(u): a neighbour that
 // joined in an earlier round would already have removed v.
 //
-// Build (no reordering, no global sort):
+// Build of a static handle (no reordering, no sort, no pass that compares every
+// edge):
 //   1. keys and the one-byte degree class q(v) of every vertex (k_keys);
-//   2. orientation (k_orient): every adjacency entry (v, u) is compared by priority;
-//      the higher-priority ones are compacted into row v's own range of the input
-//      column array's layout, hcol[rp[v] .. rp[v] + hcnt[v]).  Workgroups take
-//      2048 entries each; a row split between workgroups gets its pieces with one
-//      atomic add per piece (the order inside such a row is unspecified, the set is
-//      not).  Comparing the degree class decides most pairs from a 1-byte table;
-//      only on a tie is the neighbour's hash rebuilt in registers;
-//   3. dense blocks (optional): a wave per 16-row block gathers its oriented
-//      entries, sorts their column blocks in LDS and counts the nonzero tiles; blocks
-//      that average at least dense_min entries per tile (at most 64 tiles) are
-//      written as bitmaps;
-//   4. lists: round 1's candidates are the vertices with no higher-priority
-//      neighbour (known from the orientation, so round 1 has no Phase-1 pass);
-//      the other rows of entry-list blocks go to a light list (at most kHLight
-//      entries: a lane each) or a heavy list (a wavefront each).
+//   2. dense blocks (optional): one streaming pass over the adjacency ORs, per
+//      16-row block, a signature bit of each entry's column block; a block with at
+//      least dense_min entries per signature bit is a candidate.  A wave per
+//      candidate orients its entries (priority comparisons), sorts them in LDS and
+//      counts its nonzero tiles; a block whose higher-priority entries average at
+//      least dense_min per tile (at most 64 tiles) is written as bitmaps.
+// Round 1 then reads the caller's CSR directly: Phase 1 compares each vertex's
+// neighbours with it until one out-ranks it (the degree class decides most pairs
+// from the 1-byte table, a tie rebuilds the neighbour's hash in registers), Phase 2
+// scans for a candidate neighbour; only the vertices still undecided after round 1
+// are oriented (their H rows written to hcol[rp[v] ..]) and listed for round 2.  On
+// the R-MAT workload that is about a tenth of the entries a full orientation reads.
+//
+// A dynamic handle (edges inserted and deleted later) orients every edge at build
+// time instead (k_orient: both orientations, with slack per row), and its round 1
+// starts from the counts of higher-priority neighbours.
 //
 // Round r (two kernels):
-//   P1  (r >= 2)  for every listed row: scan H(v) for an alive neighbour (early
-//       exit); dense blocks: blocked rows = H x alive on the matrix cores (int8 x
-//       int8 -> int32, exact); candidates set their S bit.
+//   P1  listed rows: scan H(v) for an alive neighbour (early exit); dense blocks:
+//       blocked rows = H x alive on the matrix cores (int8 x int8 -> int32, exact);
+//       candidates set their S bit.
 //   P2  listed rows: S(v) -> IN; else scan H(v) for an S neighbour -> OUT; dense
 //       blocks: N_c = H x S on the matrix cores.  Decided vertices clear their
 //       alive bit; the rest go to the next round's lists.
@@ -112,21 +114,17 @@ __device__ inline bool higher(int64_t u, int64_t v, uint64_t kv, const uint64_t*
 }
 
 // Where the orientation writes: the higher-priority entries of row v go to
-// hcol[hrp[v] + ...] (hrp = the input row pointer, or the dynamic layout's own);
-// with lcol (dynamic handles) the lower-priority ones go to lcol[hrp[v] + ...].
-// With sig, every 16-row block's higher-priority entries also OR the signature bits of
-// their column blocks into sig[I] (popcount(sig[I]) is a lower bound on the block's
-// nonzero tiles).
+// hcol[hrp[v] + ...] (hrp = the dynamic layout's row starts), the lower-priority ones
+// to lcol[hrp[v] + ...].
 struct OrientOut {
     const int64_t* hrp;
     int32_t* hcol;
     int32_t* hcnt;
-    int32_t* lcol;      // nullptr: higher-priority entries only
+    int32_t* lcol;
     int32_t* lcnt;
     int32_t* g_base;    // [n] scratch of workgroups whose rows exceed LDS
     int32_t* g_off;
     int32_t* g_loff;
-    uint64_t* sig;      // [nI] or nullptr
 };
 
 // Row bounds of a workgroup's rows relative to its range start: from LDS when they
@@ -209,31 +207,6 @@ __device__ void orient_body(const int64_t* rp, const int32_t* ci, const uint64_t
         const int64_t v = u0 + li[j];
         const uint64_t kv = kLds ? wkey[li[j]] : key[v];
         if (t0 + j < erel && higher<kUserKeys>(cu[j], v, kv, key, q8, seed)) keep |= 1u << j;
-    }
-    if (o.sig) {
-        // the thread's entries lie in at most a few row-blocks (rows are consecutive):
-        // all but the last run are ORed in directly, the last one is combined across
-        // the wave first (adjacent lanes mostly share it)
-        int64_t I = (u0 + li[0]) >> 4;
-        uint64_t m = 0;
-        #pragma unroll
-        for (int j = 0; j < kPer; ++j) {
-            const int64_t Ij = (u0 + li[j]) >> 4;
-            if (Ij != I) {
-                if (m) atomicOr((unsigned long long*)&o.sig[I], (unsigned long long)m);
-                I = Ij;
-                m = 0;
-            }
-            if ((keep >> j) & 1u) m |= sig_bit(cu[j] >> 4);
-        }
-        #pragma unroll
-        for (int off = 1; off < kWave; off <<= 1) {
-            const uint64_t mo = __shfl_down(m, off, kWave);
-            const int64_t Io = __shfl_down(I, off, kWave);
-            if (lane + off < kWave && Io == I) m |= mo;
-        }
-        const int64_t Ip = __shfl_up(I, 1, kWave);
-        if ((lane == 0 || Ip != I) && m) atomicOr((unsigned long long*)&o.sig[I], (unsigned long long)m);
     }
     // exclusive prefix count of kept entries at the thread's first entry (entry order)
     const int cnt = __popc(keep);
@@ -328,128 +301,204 @@ __global__ void __launch_bounds__(kBlock) k_orient(const int64_t* rp, const int3
     }
 }
 
-// Dense-block test, one wave per 16-row block: the number of nonzero tiles is the
-// number of distinct column blocks among the block's oriented entries, counted with
-// an open-addressing set in LDS.  dflag[I] = 1 and dtcnt[I] = tiles if the block is
-// dense (at most 64 tiles, at least dense_min entries per tile on average).  The
-// block's signature bounds its tiles from below (distinct column blocks set at least
-// popcount(sig) bits), so a block with fewer than dense_min * popcount(sig) entries is
-// rejected without reading its entries.
-__global__ void __launch_bounds__(kBlock) k_dense_test(const int64_t* rp, const int32_t* hcol, const int32_t* hcnt,
-                                                       const uint64_t* sig, int64_t n, int64_t nI, int dense_min,
-                                                       int32_t* dflag, int32_t* dtcnt) {
-    constexpr uint32_t kEmpty = 0xFFFFFFFFu;
-    __shared__ uint32_t tab[kWpb][2 * kDenseCap];
-    __shared__ int32_t srow[kWpb][17];
-    const int lane = lane_id(), wid = threadIdx.x / kWave;
-    uint32_t* T = tab[wid];
-    int32_t* sr = srow[wid];
-    const int64_t nwaves = (int64_t)gridDim.x * kWpb;
-    for (int64_t I = (int64_t)blockIdx.x * kWpb + wid; I < nI; I += nwaves) {
-        const int64_t v = I * 16 + lane;
-        const int32_t c = lane < 16 && v < n ? hcnt[v] : 0;
-        int32_t incl = c;
+// ---- dense blocks
+//
+// A block is examined exactly only if its whole adjacency looks concentrated: a
+// wave ORs a 256-bit signature of its entries' column blocks, and linear counting
+// (-256 ln(1 - bits / 256)) estimates its distinct column blocks, i.e. its nonzero
+// tiles.  Its higher-priority half must average dense_min entries per tile, so a
+// block is a candidate when its entries reach dense_min times that estimate (a factor
+// of two of slack) and it has at most 2 * kDenseCap entries.  A sample of blocks
+// decides first whether the graph has such blocks at all (at least 1% of the
+// sample); if not, the full scan only clears the flags.  These tests only choose the
+// representation; the results never depend on them.
+constexpr int kGateSamples = 1024;
+
+__device__ inline int sig_index(int64_t J) { return (int)(((uint64_t)J * 0x9E3779B97F4A7C15ull) >> 56); }
+
+// 1 if block I (entries [b0, b1)) is a dense candidate; every lane of the wave calls it
+__device__ inline int block_candidate(const int32_t* ci, int64_t b0, int64_t b1, int dense_min) {
+    const int64_t tot = b1 - b0;
+    if (tot == 0 || tot > 2 * kDenseCap) return 0;
+    uint64_t s[4] = {0, 0, 0, 0};
+    for (int64_t e = b0 + lane_id(); e < b1; e += 4 * kWave) {
+        int32_t u[4];
         #pragma unroll
-        for (int off = 1; off < 16; off <<= 1) {
-            const int32_t o = __shfl_up(incl, off, kWave);
-            if (lane >= off) incl += o;
+        for (int j = 0; j < 4; ++j) u[j] = e + j * kWave < b1 ? ci[e + j * kWave] : -1;
+        #pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (u[j] < 0) continue;
+            const int k = sig_index(u[j] >> 4);
+            const uint64_t bit = 1ull << (k & 63);
+            if (k < 64) s[0] |= bit;
+            else if (k < 128) s[1] |= bit;
+            else if (k < 192) s[2] |= bit;
+            else s[3] |= bit;
         }
-        const int32_t total = __shfl(incl, 15, kWave);
-        // a dense block holds at least dense_min entries per tile and at most the cap
-        const int64_t lower = __popcll(sig[I]);
-        if (total == 0 || total > kDenseCap || (int64_t)total < (int64_t)dense_min * lower) {
-            if (lane == 0) { dflag[I] = 0; dtcnt[I] = 0; }
-            continue;
+    }
+    int bits = 0;
+    #pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        for (int off = kWave / 2; off > 0; off >>= 1) s[w] |= __shfl_xor(s[w], off, kWave);
+        bits += __popcll(s[w]);
+    }
+    if (bits >= 256) return 0;
+    const float est = -256.0f * logf(1.0f - (float)bits / 256.0f);
+    return est <= 2.0f * kDenseTiles && (float)tot >= (float)dense_min * est ? 1 : 0;
+}
+
+// the sample: every stride-th block, one wave each; candidates counted into meta->n_dcand
+__global__ void __launch_bounds__(kBlock) k_dense_gate(const int64_t* rp, const int32_t* ci, int64_t n, int64_t nI,
+                                                       int64_t stride, int dense_min, Meta* meta) {
+    __shared__ int32_t part[kWpb];
+    const int wid = threadIdx.x / kWave;
+    const int64_t i = (int64_t)blockIdx.x * kWpb + wid;
+    const int64_t I = i * stride;
+    int c = 0;
+    if (i < kGateSamples && I < nI)
+        c = block_candidate(ci, rp[16 * I], rp[min<int64_t>(16 * I + 16, n)], dense_min);
+    if (lane_id() == 0) part[wid] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int q = 0; q < kWpb; ++q) t += part[q];
+        if (t) atomicAdd(&meta->n_dcand, t);
+    }
+}
+
+// did the sample find enough candidates (1% of the sampled blocks)?
+__device__ inline bool gate_on(const Meta* meta, int samples) { return (int64_t)meta->n_dcand * 100 >= samples; }
+
+// every block, one wave each: dflag[I] = candidate (0 everywhere when the sample
+// found too few)
+__global__ void __launch_bounds__(kBlock) k_block_scan(const int64_t* rp, const int32_t* ci, int64_t n, int64_t nI,
+                                                       int samples, int dense_min, const Meta* meta, int32_t* dflag) {
+    const bool on = gate_on(meta, samples);
+    const int64_t nwaves = (int64_t)gridDim.x * kWpb;
+    for (int64_t I = (int64_t)blockIdx.x * kWpb + threadIdx.x / kWave; I < nI; I += nwaves) {
+        const int c = on ? block_candidate(ci, rp[16 * I], rp[min<int64_t>(16 * I + 16, n)], dense_min) : 0;
+        if (lane_id() == 0) dflag[I] = c;
+    }
+}
+
+// Gathers block I's higher-priority entries (priority comparisons with their rows,
+// lanes taking entries in turn) into sk as (column << 4 | row) keys and sorts them
+// (bitonic, padded with ~0); returns their number, or 0 if there are none or more
+// than kDenseCap.  Every lane of the wave calls it.
+template <bool kUserKeys>
+__device__ inline int dense_collect(const int64_t* rp, const int32_t* ci, const uint64_t* key, const uint8_t* q8,
+                                    uint64_t seed, int64_t n, int64_t I, uint64_t* sk, int32_t* sr, uint64_t* skv,
+                                    int32_t* scount) {
+    const int lane = lane_id();
+    const int64_t v0 = 16 * I;
+    const int64_t base = rp[v0];
+    wave_sync_lds();
+    if (lane <= 16) sr[lane] = (int32_t)(rp[min<int64_t>(v0 + lane, n)] - base);
+    if (lane < 16 && v0 + lane < n) skv[lane] = key[v0 + lane];
+    if (lane == 0) *scount = 0;
+    wave_sync_lds();
+    const int32_t tot = sr[16];
+    for (int32_t k = lane; k < tot; k += kWave) {
+        int r = 0;
+        while (sr[r + 1] <= k) ++r;
+        const int32_t u = ci[base + k];
+        if (higher<kUserKeys>(u, v0 + r, skv[r], key, q8, seed)) {
+            const int32_t pos = atomicAdd(scount, 1);
+            if (pos < kDenseCap) sk[pos] = ((uint64_t)(uint32_t)u << 4) | (uint64_t)r;
         }
-        int bits = 6;
-        while ((1 << bits) < 2 * total) ++bits;   // table of 2^bits >= 2 * total slots
-        const uint32_t mask = (1u << bits) - 1u;
-        wave_sync_lds();
-        if (lane < 16) sr[lane + 1] = incl;
-        if (lane == 0) sr[0] = 0;
-        for (int k = lane; k <= (int)mask; k += kWave) T[k] = kEmpty;
-        wave_sync_lds();
-        int fresh = 0;
-        for (int k = lane; k < total; k += kWave) {
-            int r = 0;
-            while (sr[r + 1] <= k) ++r;
-            const uint32_t J = (uint32_t)hcol[rp[I * 16 + r] + (k - sr[r])] >> 4;
-            uint32_t h = (J * 2654435761u) >> (32 - bits);
-            for (;;) {
-                const uint32_t old = atomicCAS(&T[h], kEmpty, J);
-                if (old == kEmpty) { ++fresh; break; }
-                if (old == J) break;
-                h = (h + 1) & mask;
+    }
+    wave_sync_lds();
+    const int32_t total = *scount;
+    if (total == 0 || total > kDenseCap) return 0;
+    int P = 64;
+    while (P < total) P <<= 1;
+    for (int k = total + lane; k < P; k += kWave) sk[k] = ~0ull;
+    wave_sync_lds();
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int k = lane; k < P; k += kWave) {
+                const int j = k ^ stride;
+                if (j > k) {
+                    const uint64_t x = sk[k], y = sk[j];
+                    const bool up = (k & size) == 0;
+                    if ((x > y) == up) { sk[k] = y; sk[j] = x; }
+                }
+            }
+            wave_sync_lds();
+        }
+    }
+    return total;
+}
+
+// tiles among the sorted keys: runs of one column block (key >> 8)
+__device__ inline int dense_tiles(const uint64_t* sk, int total) {
+    int nt = 0;
+    for (int k0 = 0; k0 < total; k0 += kWave) {
+        const int k = k0 + lane_id();
+        nt += __popcll(ballot(k < total && (k == 0 || (sk[k] >> 8) != (sk[k - 1] >> 8))));
+    }
+    return nt;
+}
+
+// Exact test of the candidates, one wave per block: dflag[I] = 1 and dtcnt[I] = tiles
+// if the block has at most 64 tiles and at least dense_min entries per tile.
+template <bool kUserKeys>
+__global__ void __launch_bounds__(kBlock) k_dense_test(const int64_t* rp, const int32_t* ci, const uint64_t* key,
+                                                       const uint8_t* q8, uint64_t seed, int64_t n, int64_t nI,
+                                                       int dense_min, const Meta* meta, int samples, int32_t* dflag,
+                                                       int32_t* dtcnt) {
+    __shared__ uint64_t skey[kWpb][kDenseCap];
+    __shared__ int32_t srow[kWpb][17];
+    __shared__ uint64_t skv[kWpb][16];
+    __shared__ int32_t scount[kWpb];
+    const int wid = threadIdx.x / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * kWpb;
+    if (!gate_on(meta, samples)) {   // the flags are all clear: every tile count is 0
+        GRID_STRIDE(I, nI) dtcnt[I] = 0;
+        return;
+    }
+    for (int64_t I = (int64_t)blockIdx.x * kWpb + wid; I < nI; I += nwaves) {
+        bool dense = false;
+        int nt = 0;
+        if (dflag[I]) {
+            const int total = dense_collect<kUserKeys>(rp, ci, key, q8, seed, n, I, skey[wid], srow[wid], skv[wid],
+                                                       &scount[wid]);
+            if (total > 0) {
+                nt = dense_tiles(skey[wid], total);
+                dense = nt <= kDenseTiles && (int64_t)total >= (int64_t)dense_min * nt;
             }
         }
-        for (int off = kWave / 2; off > 0; off >>= 1) fresh += __shfl_xor(fresh, off, kWave);
-        const bool dense = fresh <= kDenseTiles && (int64_t)total >= (int64_t)dense_min * fresh;
-        if (lane == 0) { dflag[I] = dense ? 1 : 0; dtcnt[I] = dense ? fresh : 0; }
+        if (lane_id() == 0) {
+            dflag[I] = dense ? 1 : 0;
+            dtcnt[I] = dense ? nt : 0;
+        }
     }
 }
 
 // Tiles of the dense blocks (dflag set; dpos = their list slots, dtcnt = their first
-// tiles), one wave per block: the block's entries as (column << 4 | row) keys in
-// LDS, sorted (bitonic), tile = run of one column block; bitmaps built in LDS and
-// written out, with the tiles' column blocks and the block's list slot.
-__global__ void __launch_bounds__(kBlock) k_dense_fill(const int64_t* rp, const int32_t* hcol, const int32_t* hcnt,
-                                                       int64_t n, int64_t nI, const int32_t* dflag, const int32_t* dtcnt,
-                                                       const int32_t* dpos, int32_t* drb, int32_t* dptr, int32_t* dcol,
-                                                       uint32_t* dbits) {
+// tiles), one wave per block: the sorted keys again, bitmaps built in LDS and written
+// out with the tiles' column blocks and the block's list slot.
+template <bool kUserKeys>
+__global__ void __launch_bounds__(kBlock) k_dense_fill(const int64_t* rp, const int32_t* ci, const uint64_t* key,
+                                                       const uint8_t* q8, uint64_t seed, int64_t n, int64_t nI,
+                                                       const Meta* meta, int samples, const int32_t* dflag,
+                                                       const int32_t* dtcnt, const int32_t* dpos, int32_t* drb,
+                                                       int32_t* dptr, int32_t* dcol, uint32_t* dbits) {
     __shared__ uint64_t skey[kWpb][kDenseCap];
     __shared__ uint32_t sbits[kWpb][kDenseTiles * 8];
     __shared__ int32_t srow[kWpb][17];
+    __shared__ uint64_t skv[kWpb][16];
+    __shared__ int32_t scount[kWpb];
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     uint64_t* sk = skey[wid];
-    int32_t* sr = srow[wid];
     const int64_t nwaves = (int64_t)gridDim.x * kWpb;
+    if (!gate_on(meta, samples)) return;   // no dense block
     for (int64_t I = (int64_t)blockIdx.x * kWpb + wid; I < nI; I += nwaves) {
         if (!dflag[I]) continue;
-        const int64_t v = I * 16 + lane;
-        const int32_t c = lane < 16 && v < n ? hcnt[v] : 0;
-        int32_t incl = c;
-        #pragma unroll
-        for (int off = 1; off < 16; off <<= 1) {
-            const int32_t o = __shfl_up(incl, off, kWave);
-            if (lane >= off) incl += o;
-        }
-        const int32_t total = __shfl(incl, 15, kWave);
-        wave_sync_lds();
-        if (lane < 16) sr[lane + 1] = incl;
-        if (lane == 0) sr[0] = 0;
-        wave_sync_lds();
-        // gather: key = column << 4 | row (so column block = key >> 8), padded to a
-        // power of two with ~0
-        int P = 64;
-        while (P < total) P <<= 1;
-        for (int k = lane; k < P; k += kWave) {
-            uint64_t x = ~0ull;
-            if (k < total) {
-                int r = 0;
-                while (sr[r + 1] <= k) ++r;
-                const int32_t u = hcol[rp[I * 16 + r] + (k - sr[r])];
-                x = ((uint64_t)(uint32_t)u << 4) | (uint64_t)r;
-            }
-            sk[k] = x;
-        }
-        wave_sync_lds();
-        for (int size = 2; size <= P; size <<= 1) {
-            for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                for (int k = lane; k < P; k += kWave) {
-                    const int j = k ^ stride;
-                    if (j > k) {
-                        const uint64_t a = sk[k], b = sk[j];
-                        const bool up = (k & size) == 0;
-                        if ((a > b) == up) { sk[k] = b; sk[j] = a; }
-                    }
-                }
-                wave_sync_lds();
-            }
-        }
-        // tile of each key = number of heads at or before it, minus one
+        const int total = dense_collect<kUserKeys>(rp, ci, key, q8, seed, n, I, sk, srow[wid], skv[wid], &scount[wid]);
+        const int32_t t0 = dtcnt[I];   // first tile (scanned)
         for (int k = lane; k < kDenseTiles * 8; k += kWave) sbits[wid][k] = 0;
         wave_sync_lds();
-        const int32_t t0 = dtcnt[I];   // first tile (scanned)
         int seen = 0;
         for (int k0 = 0; k0 < total; k0 += kWave) {
             const int k = k0 + lane;
@@ -477,28 +526,40 @@ __global__ void __launch_bounds__(kBlock) k_dense_fill(const int64_t* rp, const 
     }
 }
 
+__global__ void k_dense_end(const Meta* meta, int32_t* dptr) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) dptr[meta->n_dense] = meta->n_dtiles;
+}
+
+__global__ void k_dense_slots(const int32_t* dflag, const int32_t* dpos, int64_t nI, int32_t* dslot) {
+    GRID_STRIDE(I, nI) dslot[I] = dflag[I] ? dpos[I] : -1;
+}
+
 // row capacities of a dynamic handle (each orientation: its degree plus the slack)
 __global__ void k_dyn_caps(const int64_t* rp, int64_t n, int slack, int64_t* cap) {
     GRID_STRIDE(v, n) cap[v] = rp[v + 1] - rp[v] + slack;
-}
-
-__global__ void k_dense_end(const Meta* meta, int32_t* dptr) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) dptr[meta->n_dense] = meta->n_dtiles;
 }
 
 // ---------------------------------------------------------------- rounds
 
 struct HybArgs {
     int64_t n;
-    const int64_t* rp;
-    const int32_t* hcol;
-    const int32_t* hcnt;
+    const int64_t* rp;        // row starts of H (the input row pointer; a dynamic handle's own)
+    int32_t* hcol;            // H rows (static handles: written for the vertices round 1 leaves undecided)
+    int32_t* hcnt;
+    const int64_t* crp;       // the caller's CSR (round 1 of a static handle reads it)
+    const int32_t* ci;
+    const uint64_t* key;      // priorities, with the one-byte degree classes of the default rule
+    const uint8_t* q8;
+    uint64_t seed;
+    int user_keys;
+    int oriented;             // H of every vertex was built (dynamic handles)
     uint32_t* A;
     uint32_t* S;
     const int32_t* drb;       // round 1: the dense blocks (round 1 visits every vertex otherwise)
-    int32_t* act[2][3];       // later rounds, by round parity: light rows, heavy rows, dense blocks
-    const int32_t* dptr;      // dense block (by round-1 list slot order of drb) -> first tile
-    const int32_t* dslot;     // dense block I -> its slot in drb (for dptr)
+    int32_t* dact[2];         // dense blocks still undecided, listed by round parity for the next round
+    int64_t nI;               // 16-row blocks
+    const int32_t* dptr;      // per list slot: first tile (slot + 1: the end)
+    const int32_t* dslot;     // dense block I -> its list slot (-1: entry lists); nullptr: no dense blocks
     const int32_t* dcol;
     const uint32_t* dbits;
     const Meta* meta;
@@ -508,13 +569,50 @@ struct HybArgs {
     int32_t* dround;          // batches: round in which each vertex was decided
 };
 
-// the lists of round r >= 2 (written by round r-1's exclusion kernel)
-__device__ inline void hyb_lists(const HybArgs& a, int r, const int32_t* (&L)[3], int64_t (&nl)[3]) {
-    const int b = (r - 1) & 1;
-    for (int k = 0; k < 3; ++k) {
-        L[k] = a.act[b][k];
-        nl[k] = a.ctrl->n_act[b][k];
+// does u out-rank v (kv = v's key)?
+__device__ inline bool hi(const HybArgs& a, int64_t u, int64_t v, uint64_t kv) {
+    return a.user_keys ? higher<true>(u, v, kv, a.key, a.q8, a.seed) : higher<false>(u, v, kv, a.key, a.q8, a.seed);
+}
+
+// the dense blocks round r visits: all of them in round 1, else those round r-1's
+// exclusion kernel listed
+__device__ inline void dense_list(const HybArgs& a, int r, const int32_t** L, int64_t* nl) {
+    if (!a.dslot) {
+        *L = nullptr;
+        *nl = 0;
+    } else if (r == 1) {
+        *L = a.drb;
+        *nl = a.meta->n_dense;
+    } else {
+        *L = a.dact[(r - 1) & 1];
+        *nl = a.ctrl->n_act[(r - 1) & 1][2];
     }
+}
+
+// the undecided list rows of bitmap word w (x = its alive bits): the rows of dense
+// blocks are masked out (their blocks are visited through the dense lists)
+__device__ inline uint32_t list_rows(const HybArgs& a, int64_t w, uint32_t x) {
+    if (a.dslot) {
+        const int64_t I0 = 2 * w;   // the word's two 16-row blocks
+        if (I0 < a.nI && a.dslot[I0] >= 0) x &= 0xFFFF0000u;
+        if (I0 + 1 < a.nI && a.dslot[I0 + 1] >= 0) x &= 0x0000FFFFu;
+    }
+    return x;
+}
+
+// Does H(v) (c entries from e0) name a vertex whose bit is set in m?  The whole wave,
+// 64 entries per step, early exit; every lane calls it and gets the answer; *read
+// (lane 0) counts the entries loaded.
+__device__ inline bool wave_scan(const HybArgs& a, int64_t e0, int32_t c, const uint32_t* m, int64_t* read) {
+    const int lane = lane_id();
+    int32_t k = 0;
+    bool hit = false;
+    for (; k < c; k += kWave) {
+        const int32_t u = k + lane < c ? a.hcol[e0 + k + lane] : -1;
+        if (ballot(u >= 0 && bit_of(m, u))) { hit = true; k += kWave; break; }
+    }
+    if (lane == 0) *read += min(k, c);
+    return hit;
 }
 
 // one dense block's product H x x over its tiles (x = alive or in-set bitmap, taken
@@ -601,51 +699,154 @@ __device__ inline bool scan4(const int32_t* row, int32_t c, const uint32_t* m, i
     return false;
 }
 
-// Phase 1 of round r >= 2 (round 1's candidates come from the build).  The
-// workgroup is number vb of nvb working on this graph (the launch's grid, or the
-// graph's share of a launch over several graphs).
+// Does one of the c neighbours row[0 .. c) of v out-rank it?  Eight entries at a time
+// (eight index loads, then eight priority comparisons with their class gathers in
+// flight), stopping after the group that holds the first one; *read counts the
+// entries loaded.
+__device__ inline bool scan_higher8(const HybArgs& a, const int32_t* row, int64_t c, int64_t v, uint64_t kv,
+                                    int64_t* read) {
+    for (int64_t k = 0; k < c; k += 8) {
+        int32_t u[8];
+        #pragma unroll
+        for (int j = 0; j < 8; ++j) u[j] = k + j < c ? row[k + j] : -1;
+        bool h = false;
+        #pragma unroll
+        for (int j = 0; j < 8; ++j) h |= u[j] >= 0 && hi(a, u[j], v, kv);
+        *read += min<int64_t>(c - k, 8);
+        if (h) return true;
+    }
+    return false;
+}
+
+// Does a row of c entries name a vertex whose bit is set in m?  Eight at a time.
+__device__ inline bool scan8(const int32_t* row, int64_t c, const uint32_t* m, int64_t* read) {
+    for (int64_t k = 0; k < c; k += 8) {
+        int32_t u[8];
+        #pragma unroll
+        for (int j = 0; j < 8; ++j) u[j] = k + j < c ? row[k + j] : -1;
+        bool hit = false;
+        #pragma unroll
+        for (int j = 0; j < 8; ++j) hit |= u[j] >= 0 && bit_of(m, u[j]);
+        *read += min<int64_t>(c - k, 8);
+        if (hit) return true;
+    }
+    return false;
+}
+
+// Writes H(v) (the neighbours row[0 .. c) that out-rank v) to hcol[rp[v] ..] and its
+// size to hcnt[v], one lane, eight entries at a time (loads and comparisons of a group
+// issued before its stores); returns the size.
+__device__ inline int32_t orient_row(const HybArgs& a, const int32_t* __restrict__ row, int64_t c, int64_t v,
+                                     uint64_t kv) {
+    int32_t* __restrict__ out = a.hcol + a.rp[v];
+    int32_t m = 0;
+    for (int64_t k = 0; k < c; k += 8) {
+        int32_t u[8];
+        #pragma unroll
+        for (int j = 0; j < 8; ++j) u[j] = k + j < c ? row[k + j] : -1;
+        uint32_t keep = 0;
+        #pragma unroll
+        for (int j = 0; j < 8; ++j) keep |= (u[j] >= 0 && hi(a, u[j], v, kv)) ? 1u << j : 0u;
+        #pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if ((keep >> j) & 1u) out[m++] = u[j];
+    }
+    a.hcnt[v] = m;
+    return m;
+}
+
+// Phase 1 of round r.  The workgroup is number vb of nvb working on this graph (the
+// launch's grid, or the graph's share of a launch over several graphs).
 __device__ void hyb_p1(const HybArgs& a, int r, int64_t vb, int64_t nvb) {
     __shared__ uint32_t sbits[kWpb][kDenseTiles * 8];
     __shared__ uint32_t svec[kWpb][kDenseTiles];
     open_round(a.ctrl, a.stripes, a.trace, r, vb);
-    if (r == 1) return;   // round 1's candidates were counted when the round state was set up
-    const int32_t* L[3];
-    int64_t nl[3];
-    hyb_lists(a, r, L, nl);
+    if (r == 1 && a.oriented) return;   // round 1's candidates were counted when the round state was set up
+    const int32_t* L[3] = {nullptr, nullptr, nullptr};
+    int64_t nl[3] = {0, 0, 0};
+    dense_list(a, r, &L[2], &nl[2]);
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     const int64_t nthreads = nvb * kBlock;
     const int64_t tid = vb * kBlock + threadIdx.x;
     const int64_t nwaves = nthreads / kWave, wv = tid / kWave;
     int64_t n_cand = 0, ent = 0, verts = 0, mult = 0, blocks = 0;
-    // light rows: a lane each (whole waves iterate together for the combined atomics)
-    const int64_t nlr = (nl[0] + kWave - 1) / kWave * kWave;
-    for (int64_t i = tid; i < nlr; i += nthreads) {
-        int64_t w = -1;
-        uint32_t m = 0;
-        if (i < nl[0]) {
-            const int32_t v = L[0][i];
-            const bool blocked = scan4(a.hcol + a.rp[v], a.hcnt[v], a.A, &ent);
-            ++verts;
-            if (!blocked) { w = v >> 5; m = 1u << (v & 31); ++n_cand; }
+    if (r == 1) {
+        // Every vertex outside the dense blocks compares its neighbours in the
+        // caller's CSR with itself until one out-ranks it (every vertex is undecided).
+        // Each lane takes its vertex's first kHLight entries; the longer rows still
+        // undecided after them continue with the whole wave, 64 entries per step, one
+        // after another (most rows meet a higher neighbour early).
+        const int64_t nr = (a.n + kWave - 1) / kWave * kWave;   // whole waves iterate together
+        for (int64_t i = tid; i < nr; i += nthreads) {
+            const int32_t v = (int32_t)i;
+            const bool row = i < a.n && !(a.dslot && a.dslot[v >> 4] >= 0);
+            int64_t e0 = 0, d = 0;
+            uint64_t kv = 0;
+            bool found = false;
+            if (row) {
+                e0 = a.crp[v];
+                d = a.crp[v + 1] - e0;
+                kv = a.key[v];
+                ++verts;
+                found = scan_higher8(a, a.ci + e0, min<int64_t>(d, kHLight), v, kv, &ent);
+            }
+            const bool cont = row && !found && d > kHLight;
+            int64_t w = -1;
+            uint32_t m = 0;
+            if (row && !found && !cont) { w = v >> 5; m = 1u << (v & 31); ++n_cand; }
+            run_apply<false>(w, m, a.S);
+            uint64_t hv = ballot(cont);
+            while (hv) {
+                const int l = __builtin_ctzll(hv);
+                hv &= hv - 1;
+                const int32_t vh = __shfl(v, l, kWave);
+                const int64_t e0h = __shfl(e0, l, kWave), dh = __shfl(d, l, kWave);
+                const uint64_t kvh = __shfl(kv, l, kWave);
+                bool blocked = false;
+                int64_t k = kHLight;
+                for (; k < dh; k += kWave) {
+                    const bool b = k + lane < dh && hi(a, a.ci[e0h + k + lane], vh, kvh);
+                    if (ballot(b)) { blocked = true; k += kWave; break; }
+                }
+                if (lane == 0) {
+                    ent += min(k, dh) - kHLight;
+                    if (!blocked) { atomicOr(&a.S[vh >> 5], 1u << (vh & 31)); ++n_cand; }
+                }
+            }
         }
-        run_apply<false>(w, m, a.S);
-    }
-    // heavy rows: a wave each, 64 entries per step, early exit on the first alive one
-    for (int64_t i = wv; i < nl[1]; i += nwaves) {
-        const int32_t v = L[1][i];
-        const int64_t e0 = a.rp[v];
-        const int32_t c = a.hcnt[v];
-        bool blocked = false;
-        int32_t k = 0;
-        for (; k < c; k += kWave) {
-            const int32_t u = k + lane < c ? a.hcol[e0 + k + lane] : -1;
-            const bool b = u >= 0 && bit_of(a.A, u);
-            if (ballot(b)) { blocked = true; k += kWave; break; }
-        }
-        if (lane == 0) {
-            ent += min(k, c);
-            ++verts;
-            if (!blocked) { atomicOr(&a.S[v >> 5], 1u << (v & 31)); ++n_cand; }
+    } else {
+        // Undecided rows outside the dense blocks, a thread per bitmap word (32
+        // vertices): rows of at most kHLight entries scan H(v) for an alive neighbour
+        // (early exit); the longer rows of a wave's words then take the whole wave, one
+        // after another.  Candidates set their S bits, one atomic per word.
+        const int64_t nwords = (a.n + 31) >> 5;
+        const int64_t nwr = (nwords + kWave - 1) / kWave * kWave;   // whole waves iterate together
+        for (int64_t w = tid; w < nwr; w += nthreads) {
+            const uint32_t rows = w < nwords ? list_rows(a, w, a.A[w]) : 0u;
+            uint32_t cand = 0, heavy = 0;
+            for (uint32_t mm = rows; mm; mm &= mm - 1) {
+                const int b = __builtin_ctz(mm);
+                const int32_t v = (int32_t)(w * 32 + b);
+                const int32_t c = a.hcnt[v];
+                if (c > kHLight) { heavy |= 1u << b; continue; }
+                ++verts;
+                if (!scan4(a.hcol + a.rp[v], c, a.A, &ent)) cand |= 1u << b;
+            }
+            for (uint64_t hb = ballot(heavy != 0); hb; hb = ballot(heavy != 0)) {
+                const int l = __builtin_ctzll(hb);
+                const int b = __builtin_ctz(__shfl(heavy, l, kWave));
+                const int32_t v = (int32_t)(__shfl(w, l, kWave) * 32 + b);
+                const bool blocked = wave_scan(a, a.rp[v], a.hcnt[v], a.A, &ent);
+                if (lane == 0) ++verts;
+                if (lane == l) {
+                    heavy &= ~(1u << b);
+                    if (!blocked) cand |= 1u << b;
+                }
+            }
+            if (cand) {
+                atomicOr(&a.S[w], cand);
+                n_cand += __popc(cand);
+            }
         }
     }
     // dense blocks: blocked rows = H x alive
@@ -668,30 +869,92 @@ __device__ void hyb_p1(const HybArgs& a, int r, int64_t vb, int64_t nvb) {
 
 // Phases 2 and 3 of round r: retire candidates, remove their neighbours, list the rest.
 __device__ void hyb_p2(const HybArgs& a, int r, int64_t vb, int64_t nvb) {
-    __shared__ int32_t lbuf[kWpb][3][kWave];
+    __shared__ int32_t lbuf[kWpb][kWave];
     __shared__ uint32_t sbits[kWpb][kDenseTiles * 8];
     __shared__ uint32_t svec[kWpb][kDenseTiles];
-    const int32_t* L[3] = {nullptr, nullptr, a.drb};
-    int64_t nl[3] = {0, 0, a.dslot ? (int64_t)a.meta->n_dense : 0};
-    if (r > 1) hyb_lists(a, r, L, nl);
+    const int32_t* DL = nullptr;
+    int64_t ndl = 0;
+    dense_list(a, r, &DL, &ndl);
     const int lane = lane_id(), wid = threadIdx.x / kWave;
-    int pend[3] = {0, 0, 0};
-    int32_t* next[3];
-    int64_t* cnt[3];
-    for (int k = 0; k < 3; ++k) {
-        next[k] = a.act[r & 1][k];
-        cnt[k] = &a.ctrl->n_act[r & 1][k];
-    }
+    int pend = 0;
+    int32_t* dnext = a.dact[r & 1];
+    int64_t* dcnt = &a.ctrl->n_act[r & 1][2];
     const int64_t nthreads = nvb * kBlock;
     const int64_t tid = vb * kBlock + threadIdx.x;
     const int64_t nwaves = nthreads / kWave, wv = tid / kWave;
     int64_t n_out = 0, ent = 0, verts = 0, mult = 0, blocks = 0;
-    if (r == 1) {
-        // Every vertex outside the dense blocks: a vertex without a higher-priority
+    if (r == 1 && !a.oriented) {
+        // Every vertex outside the dense blocks: a candidate of round 1 joins the set;
+        // any other scans its row of the caller's CSR for a candidate (a candidate
+        // neighbour always out-ranks it) and leaves on the first.  A vertex with none
+        // stays undecided: its H row is written now, for the later rounds (round 1 is
+        // the only time its whole row is compared).  Each lane takes its vertex's
+        // first kHLight entries; longer rows with no candidate among them continue with
+        // the whole wave, one after another.
+        const int64_t nr = (a.n + kWave - 1) / kWave * kWave;   // whole waves iterate together
+        for (int64_t i = tid; i < nr; i += nthreads) {
+            const int32_t v = (int32_t)i;
+            const bool row = i < a.n && !(a.dslot && a.dslot[v >> 4] >= 0);
+            const bool in = row && bit_of(a.S, v);
+            int64_t e0 = 0, d = 0;
+            bool hit = false;
+            if (row && !in) {
+                e0 = a.crp[v];
+                d = a.crp[v + 1] - e0;
+                ++verts;
+                hit = scan8(a.ci + e0, min<int64_t>(d, kHLight), a.S, &ent);
+            }
+            const bool cont = row && !in && !hit && d > kHLight;
+            int64_t w = -1;
+            uint32_t m = 0;
+            if (in || hit) {
+                w = v >> 5; m = 1u << (v & 31);
+                n_out += hit ? 1 : 0;
+                if (a.dround) a.dround[v] = r;
+            } else if (row && !cont) {
+                orient_row(a, a.ci + e0, d, v, a.key[v]);
+                ent += d;
+            }
+            run_apply<true>(w, m, a.A);
+            for (uint64_t hv = ballot(cont); hv; hv &= hv - 1) {
+                const int l = __builtin_ctzll(hv);
+                const int32_t vh = __shfl(v, l, kWave);
+                const int64_t e0h = __shfl(e0, l, kWave), dh = __shfl(d, l, kWave);
+                bool hit2 = false;
+                int64_t k = kHLight;
+                for (; k < dh; k += kWave) {
+                    const int32_t u = k + lane < dh ? a.ci[e0h + k + lane] : -1;
+                    if (ballot(u >= 0 && bit_of(a.S, u))) { hit2 = true; k += kWave; break; }
+                }
+                if (lane == 0) ent += min(k, dh) - kHLight;
+                if (hit2) {
+                    if (lane == 0) {
+                        atomicAnd(&a.A[vh >> 5], ~(1u << (vh & 31)));
+                        ++n_out;
+                        if (a.dround) a.dround[vh] = r;
+                    }
+                } else {
+                    // H(vh), ballot-compacted 64 entries at a time
+                    const uint64_t kvh = a.key[vh];
+                    int32_t* out = a.hcol + a.rp[vh];
+                    int32_t c = 0;
+                    for (int64_t k2 = 0; k2 < dh; k2 += kWave) {
+                        const int32_t u = k2 + lane < dh ? a.ci[e0h + k2 + lane] : -1;
+                        const bool h = u >= 0 && hi(a, u, vh, kvh);
+                        const uint64_t mk = ballot(h);
+                        if (h) out[c + __popcll(mk & lanes_below())] = u;
+                        c += __popcll(mk);
+                    }
+                    if (lane == 0) { a.hcnt[vh] = c; ent += dh; }
+                }
+            }
+        }
+    } else if (r == 1) {
+        // Dynamic handles (H of every vertex built): a vertex without a higher-priority
         // neighbour is a candidate and already in the set (it was never undecided);
-        // any other leaves if one of its higher-priority neighbours is a candidate,
-        // else it goes to round 2's lists.  Light rows take a lane each; the heavy rows
-        // of a wave's 64 vertices are then scanned by the whole wave, one after another.
+        // any other leaves if one of its higher-priority neighbours is a candidate.
+        // Light rows take a lane each; the heavy rows of a wave's 64 vertices are then
+        // scanned by the whole wave, one after another.
         const int64_t nr = (a.n + kWave - 1) / kWave * kWave;   // whole waves iterate together
         for (int64_t i = tid; i < nr; i += nthreads) {
             const int32_t v = (int32_t)i;
@@ -701,35 +964,20 @@ __device__ void hyb_p2(const HybArgs& a, int r, int64_t vb, int64_t nvb) {
             const bool light = listed && c <= kHLight;
             int64_t w = -1;
             uint32_t m = 0;
-            bool keep = false;
             if (light) {
                 const bool hit = scan4(a.hcol + a.rp[v], c, a.S, &ent);
                 ++verts;
                 if (hit) {
                     w = v >> 5; m = 1u << (v & 31); ++n_out;
                     if (a.dround) a.dround[v] = r;
-                } else {
-                    keep = true;
                 }
             }
             run_apply<true>(w, m, a.A);
-            lbuf_push(lbuf[wid][0], pend[0], next[0], cnt[0], keep, v);
-            uint64_t hv = ballot(listed && !light);
-            while (hv) {
+            for (uint64_t hv = ballot(listed && !light); hv; hv &= hv - 1) {
                 const int l = __builtin_ctzll(hv);
-                hv &= hv - 1;
                 const int32_t vh = __shfl(v, l, kWave);
-                const int64_t e0 = a.rp[vh];
-                const int32_t ch = a.hcnt[vh];
-                bool hit = false;
-                int32_t k = 0;
-                for (; k < ch; k += kWave) {
-                    const int32_t u = k + lane < ch ? a.hcol[e0 + k + lane] : -1;
-                    const bool b = u >= 0 && bit_of(a.S, u);
-                    if (ballot(b)) { hit = true; k += kWave; break; }
-                }
+                const bool hit = wave_scan(a, a.rp[vh], a.hcnt[vh], a.S, &ent);
                 if (lane == 0) {
-                    ent += min(k, ch);
                     ++verts;
                     if (hit) {
                         atomicAnd(&a.A[vh >> 5], ~(1u << (vh & 31)));
@@ -737,65 +985,47 @@ __device__ void hyb_p2(const HybArgs& a, int r, int64_t vb, int64_t nvb) {
                         if (a.dround) a.dround[vh] = r;
                     }
                 }
-                lbuf_push(lbuf[wid][1], pend[1], next[1], cnt[1], lane == 0 && !hit, vh);
             }
         }
-        lbuf_flush(lbuf[wid][0], pend[0], next[0], cnt[0]);
-        lbuf_flush(lbuf[wid][1], pend[1], next[1], cnt[1]);
     } else {
-    const int64_t nlr = (nl[0] + kWave - 1) / kWave * kWave;
-    for (int64_t i = tid; i < nlr; i += nthreads) {
-        int64_t w = -1;
-        uint32_t m = 0;
-        bool keep = false;
-        int32_t v = 0;
-        if (i < nl[0]) {
-            v = L[0][i];
-            if (bit_of(a.S, v)) {
-                w = v >> 5; m = 1u << (v & 31);
-                if (a.dround) a.dround[v] = r;
-            } else {
-                const bool hit = scan4(a.hcol + a.rp[v], a.hcnt[v], a.S, &ent);
+        // Undecided rows outside the dense blocks, a thread per bitmap word:
+        // candidates retire; every other row scans H(v) for a candidate (rows of at
+        // most kHLight entries on their lane, longer ones with the whole wave) and
+        // leaves on the first.  One atomic per word clears the decided rows.
+        const int64_t nwords = (a.n + 31) >> 5;
+        const int64_t nwr = (nwords + kWave - 1) / kWave * kWave;   // whole waves iterate together
+        for (int64_t w = tid; w < nwr; w += nthreads) {
+            const uint32_t rows = w < nwords ? list_rows(a, w, a.A[w]) : 0u;
+            const uint32_t sw = rows ? a.S[w] : 0u;
+            uint32_t dec = rows & sw, heavy = 0;
+            for (uint32_t mm = rows & ~sw; mm; mm &= mm - 1) {
+                const int b = __builtin_ctz(mm);
+                const int32_t v = (int32_t)(w * 32 + b);
+                const int32_t c = a.hcnt[v];
+                if (c > kHLight) { heavy |= 1u << b; continue; }
                 ++verts;
-                if (hit) {
-                    w = v >> 5; m = 1u << (v & 31); ++n_out;
-                    if (a.dround) a.dround[v] = r;
-                } else {
-                    keep = true;
+                if (scan4(a.hcol + a.rp[v], c, a.S, &ent)) { dec |= 1u << b; ++n_out; }
+            }
+            for (uint64_t hb = ballot(heavy != 0); hb; hb = ballot(heavy != 0)) {
+                const int l = __builtin_ctzll(hb);
+                const int b = __builtin_ctz(__shfl(heavy, l, kWave));
+                const int32_t v = (int32_t)(__shfl(w, l, kWave) * 32 + b);
+                const bool hit = wave_scan(a, a.rp[v], a.hcnt[v], a.S, &ent);
+                if (lane == 0) ++verts;
+                if (lane == l) {
+                    heavy &= ~(1u << b);
+                    if (hit) { dec |= 1u << b; ++n_out; }
                 }
             }
-        }
-        run_apply<true>(w, m, a.A);
-        lbuf_push(lbuf[wid][0], pend[0], next[0], cnt[0], keep, v);
-    }
-    lbuf_flush(lbuf[wid][0], pend[0], next[0], cnt[0]);
-    for (int64_t i = wv; i < nl[1]; i += nwaves) {
-        const int32_t v = L[1][i];
-        bool hit = false, in = false;
-        if (bit_of(a.S, v)) {
-            in = true;
-        } else {
-            const int64_t e0 = a.rp[v];
-            const int32_t c = a.hcnt[v];
-            int32_t k = 0;
-            for (; k < c; k += kWave) {
-                const int32_t u = k + lane < c ? a.hcol[e0 + k + lane] : -1;
-                const bool b = u >= 0 && bit_of(a.S, u);
-                if (ballot(b)) { hit = true; k += kWave; break; }
+            if (dec) {
+                atomicAnd(&a.A[w], ~dec);
+                if (a.dround)
+                    for (uint32_t mm = dec; mm; mm &= mm - 1) a.dround[w * 32 + __builtin_ctz(mm)] = r;
             }
-            if (lane == 0) { ent += min(k, c); ++verts; }
         }
-        if (lane == 0 && (in || hit)) {
-            atomicAnd(&a.A[v >> 5], ~(1u << (v & 31)));
-            if (a.dround) a.dround[v] = r;
-            n_out += hit ? 1 : 0;
-        }
-        lbuf_push(lbuf[wid][1], pend[1], next[1], cnt[1], lane == 0 && !in && !hit, v);
     }
-    lbuf_flush(lbuf[wid][1], pend[1], next[1], cnt[1]);
-    }
-    for (int64_t i = wv; i < nl[2]; i += nwaves) {
-        const int32_t I = L[2][i];
+    for (int64_t i = wv; i < ndl; i += nwaves) {
+        const int32_t I = DL[i];
         const int32_t s = a.dslot[I];
         const int64_t t0 = a.dptr[s];
         const int nt = a.dptr[s + 1] - (int)t0;
@@ -808,9 +1038,9 @@ __device__ void hyb_p2(const HybArgs& a, int r, int64_t vb, int64_t nvb) {
             n_out += __popc(out);
         }
         if (a.dround && lane < 16 && ((dec >> lane) & 1u)) a.dround[I * 16 + lane] = r;
-        lbuf_push(lbuf[wid][2], pend[2], next[2], cnt[2], lane == 0 && (al & ~dec) != 0, I);
+        lbuf_push(lbuf[wid], pend, dnext, dcnt, lane == 0 && (al & ~dec) != 0, I);
     }
-    lbuf_flush(lbuf[wid][2], pend[2], next[2], cnt[2]);
+    lbuf_flush(lbuf[wid], pend, dnext, dcnt);
     int64_t x[5] = {n_out, ent, verts, mult, blocks};
     block_count(a.stripes, r, {1, 4, 5, 7, 9}, x, vb);
 }
@@ -835,12 +1065,13 @@ __global__ void __launch_bounds__(kBlock) k_hyb_rounds(HybArgs a, int k) {
     finish_rounds(a.ctrl, a.stripes, a.trace, rb, k);
 }
 
-// Round state before round 1, from the higher-priority neighbour counts: a vertex
-// without one is a candidate of round 1 (in the set, counted into round 1's |C|),
-// every other vertex is undecided.  Batches: round-1 candidates are decided in round
-// 1, everything else later.  vb / nvb: the workgroup's place in the graph's share
-// (the grid, or its part of a launch over several graphs); whole waves iterate
-// together, each writing the two bitmap words of its 64 vertices.
+// Round state before round 1.  Static handles (hcnt == nullptr): every vertex is
+// undecided and nothing is in the set.  Dynamic handles, from the higher-priority
+// neighbour counts: a vertex without one is a candidate of round 1 (in the set,
+// counted into round 1's |C|), every other vertex is undecided; batches record the
+// round-1 candidates as decided in round 1.  vb / nvb: the workgroup's place in the
+// graph's share (the grid, or its part of a launch over several graphs); whole waves
+// iterate together, each writing the two bitmap words of its 64 vertices.
 __device__ void hyb_init_body(const int32_t* hcnt, int64_t n, uint32_t* S, uint32_t* A, int32_t* dround,
                               int64_t* stripes, int64_t vb, int64_t nvb) {
     int64_t c1 = 0;
@@ -849,7 +1080,7 @@ __device__ void hyb_init_body(const int32_t* hcnt, int64_t n, uint32_t* S, uint3
     const int lane = lane_id();
     for (int64_t v = vb * kBlock + threadIdx.x; v < nr; v += nthreads) {
         const bool valid = v < n;
-        const int32_t c = valid ? hcnt[v] : -1;
+        const int32_t c = !valid ? -1 : hcnt ? hcnt[v] : 1;
         const uint64_t bc = ballot(c == 0), ba = ballot(c > 0);
         c1 += lane == 0 ? __popcll(bc) : 0;
         if (dround && valid) dround[v] = c == 0 ? 1 : 0;
@@ -904,13 +1135,20 @@ HybArgs make_args(GraphCore* g) {
     a.rp = g->hrp;
     a.hcol = g->hcol;
     a.hcnt = g->hcnt;
+    a.crp = g->row_ptr;
+    a.ci = g->col_idx;
+    a.key = g->key;
+    a.q8 = g->q8;
+    a.seed = g->seed;
+    a.user_keys = g->user_keys ? 1 : 0;
+    a.oriented = g->dyn_slack > 0 ? 1 : 0;
     a.A = g->hA;
     a.S = g->hS;
     a.drb = g->drb;
-    for (int b = 0; b < 2; ++b)
-        for (int k = 0; k < 3; ++k) a.act[b][k] = g->hact[b][k];
+    for (int b = 0; b < 2; ++b) a.dact[b] = g->hdact[b];
+    a.nI = ceil_div(g->n, 16);
     a.dptr = g->dptr;
-    a.dslot = g->dslot;
+    a.dslot = g->dense_min > 0 && g->nnz > 0 ? g->dslot : nullptr;
     a.dcol = g->dcol;
     a.dbits = g->dbits;
     a.meta = g->meta;
@@ -919,10 +1157,6 @@ HybArgs make_args(GraphCore* g) {
     a.trace = g->trace;
     a.dround = g->count > 0 ? g->dround : nullptr;
     return a;
-}
-
-__global__ void k_dense_slots(const int32_t* dflag, const int32_t* dpos, int64_t nI, int32_t* dslot) {
-    GRID_STRIDE(I, nI) dslot[I] = dflag[I] ? dpos[I] : -1;
 }
 
 #define HLAUNCH(kernel, work, ...)                                                                            \
@@ -939,66 +1173,92 @@ int build_hybrid(mis_graph* g, hipStream_t s) {
     const int64_t n = g->n, nnz = g->nnz, nI = g->nI;
     TC_HIP(hipMemsetAsync(g->meta, 0, sizeof(Meta), s));
     if (n == 0) return MIS_OK;
-    // 1. orientation (stages: row search, orientation, dense blocks)
-    TC_HIP(hipMemsetAsync(g->hcnt, 0, (size_t)n * 4, s));
     g->hrp = g->row_ptr;
     if (g->dyn_slack > 0) {
-        // dynamic handle: rows of its own, deg + slack slots for each orientation
+        // dynamic handle: both orientations of every edge, in rows of its own with
+        // deg + slack slots each (stages: row search, orientation, none)
+        TC_HIP(hipMemsetAsync(g->hcnt, 0, (size_t)n * 4, s));
         TC_HIP(hipMemsetAsync(g->lcnt, 0, (size_t)n * 4, s));
         HLAUNCH(k_dyn_caps, n, g->row_ptr, n, g->dyn_slack, g->hflag);
         TC_CHECK(scan_excl_i64(g->hflag, g->drp, n, g->drp + n, (int64_t*)g->scan_tmp, s));
         g->hrp = g->drp;
+        const int64_t nb = hyb_blocks(nnz);
+        if (nnz > 0) HLAUNCH(k_orient_rows, n, g->row_ptr, n, nnz, nb, g->hbrow);
+        build_mark(g, s);
+        if (nnz > 0) {
+            OrientOut o{g->hrp, g->hcol, g->hcnt, g->lcol, g->lcnt, g->hbase, g->hoff, g->hloff};
+            if (g->user_keys)
+                hipLaunchKernelGGL(k_orient<true>, dim3((unsigned)nb), dim3(kBlock), 0, s, g->row_ptr, g->col_idx,
+                                   g->key, g->q8, g->seed, nnz, g->hbrow, o);
+            else
+                hipLaunchKernelGGL(k_orient<false>, dim3((unsigned)nb), dim3(kBlock), 0, s, g->row_ptr, g->col_idx,
+                                   g->key, g->q8, g->seed, nnz, g->hbrow, o);
+            TC_HIP(hipGetLastError());
+        }
+        build_mark(g, s);
+        build_mark(g, s);
+        return MIS_OK;
     }
-    const int64_t nb = hyb_blocks(nnz);
+    // static handle: the dense blocks only (stages: dense-block scan, dense blocks,
+    // none); everything else is read from the caller's CSR by round 1
     const bool dense = g->dense_min > 0 && nnz > 0;
-    if (nnz > 0) HLAUNCH(k_orient_rows, n, g->row_ptr, n, nnz, nb, g->hbrow);
-    if (dense) TC_HIP(hipMemsetAsync(g->hsig, 0, (size_t)nI * 8, s));
-    build_mark(g, s);
-    if (nnz > 0) {
-        OrientOut o{g->hrp, g->hcol, g->hcnt, g->dyn_slack > 0 ? g->lcol : nullptr, g->lcnt, g->hbase, g->hoff,
-                    g->hloff, dense ? g->hsig : nullptr};
-        if (g->user_keys)
-            hipLaunchKernelGGL(k_orient<true>, dim3((unsigned)nb), dim3(kBlock), 0, s, g->row_ptr, g->col_idx, g->key,
-                               g->q8, g->seed, nnz, g->hbrow, o);
-        else
-            hipLaunchKernelGGL(k_orient<false>, dim3((unsigned)nb), dim3(kBlock), 0, s, g->row_ptr, g->col_idx,
-                               g->key, g->q8, g->seed, nnz, g->hbrow, o);
+    const int64_t stride = std::max<int64_t>(1, nI / kGateSamples);
+    const int samples = (int)std::min<int64_t>(kGateSamples, ceil_div(nI, stride));
+    if (dense) {
+        hipLaunchKernelGGL(k_dense_gate, dim3((unsigned)ceil_div(kGateSamples, kWpb)), dim3(kBlock), 0, s,
+                           g->row_ptr, g->col_idx, n, nI, stride, g->dense_min, g->meta);
+        const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(nI, kWpb), 16384);
+        hipLaunchKernelGGL(k_block_scan, dim3(blocks), dim3(kBlock), 0, s, g->row_ptr, g->col_idx, n, nI, samples,
+                           g->dense_min, g->meta, g->dflag);
         TC_HIP(hipGetLastError());
     }
     build_mark(g, s);
-    // 2. dense blocks
     if (dense) {
         const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(nI, kWpb), 16384);
-        hipLaunchKernelGGL(k_dense_test, dim3(blocks), dim3(kBlock), 0, s, g->row_ptr, g->hcol, g->hcnt, g->hsig, n,
-                           nI, g->dense_min, g->dflag, g->dtcnt);
+        if (g->user_keys)
+            hipLaunchKernelGGL(k_dense_test<true>, dim3(blocks), dim3(kBlock), 0, s, g->row_ptr, g->col_idx, g->key,
+                               g->q8, g->seed, n, nI, g->dense_min, g->meta, samples, g->dflag, g->dtcnt);
+        else
+            hipLaunchKernelGGL(k_dense_test<false>, dim3(blocks), dim3(kBlock), 0, s, g->row_ptr, g->col_idx, g->key,
+                               g->q8, g->seed, n, nI, g->dense_min, g->meta, samples, g->dflag, g->dtcnt);
         TC_HIP(hipGetLastError());
-        // list slots of dense blocks and their first tiles (dflag keeps the flags)
+        // list slots of the dense blocks and their first tiles (dflag keeps the flags)
         TC_CHECK(scan_excl_i32(g->dflag, g->dpos, nI, &g->meta->n_dense, (int32_t*)g->scan_tmp, s));
         TC_CHECK(scan_excl_i32(g->dtcnt, g->dtcnt, nI, &g->meta->n_dtiles, (int32_t*)g->scan_tmp, s));
-        hipLaunchKernelGGL(k_dense_fill, dim3(blocks), dim3(kBlock), 0, s, g->row_ptr, g->hcol, g->hcnt, n, nI,
-                           g->dflag, g->dtcnt, g->dpos, g->drb, g->dptr, g->dcol, g->dbits);
+        if (g->user_keys)
+            hipLaunchKernelGGL(k_dense_fill<true>, dim3(blocks), dim3(kBlock), 0, s, g->row_ptr, g->col_idx, g->key,
+                               g->q8, g->seed, n, nI, g->meta, samples, g->dflag, g->dtcnt, g->dpos, g->drb, g->dptr,
+                               g->dcol, g->dbits);
+        else
+            hipLaunchKernelGGL(k_dense_fill<false>, dim3(blocks), dim3(kBlock), 0, s, g->row_ptr, g->col_idx, g->key,
+                               g->q8, g->seed, n, nI, g->meta, samples, g->dflag, g->dtcnt, g->dpos, g->drb, g->dptr,
+                               g->dcol, g->dbits);
         TC_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_dense_end, dim3(1), dim3(1), 0, s, g->meta, g->dptr);
         TC_HIP(hipGetLastError());
         HLAUNCH(k_dense_slots, nI, g->dflag, g->dpos, nI, g->dslot);
     }
     build_mark(g, s);
+    build_mark(g, s);
     return MIS_OK;
 }
 
 int hyb_init(GraphCore* g, hipStream_t s) {
     if (g->n > 0)
-        hipLaunchKernelGGL(k_hyb_init, dim3(stream_grid(g->n)), dim3(kBlock), 0, s, g->hcnt, g->n, g->hS, g->hA,
+        hipLaunchKernelGGL(k_hyb_init, dim3(stream_grid(g->n)), dim3(kBlock), 0, s,
+                           g->dyn_slack > 0 ? g->hcnt : nullptr, g->n, g->hS, g->hA,
                            g->count > 0 ? g->dround : nullptr, g->stripes);
     TC_HIP(hipGetLastError());
     return MIS_OK;
 }
 
 // phase 0 = candidate kernel, 1 = exclusion kernel
-int hyb_enqueue_phase(GraphCore* g, int phase, int r, hipStream_t s) {
+// (first: round 1 of the solve, which visits every vertex: a thread per vertex)
+int hyb_enqueue_phase(GraphCore* g, int phase, int r, hipStream_t s, bool first) {
     HybArgs a = make_args(g);
-    if (phase == 0) hipLaunchKernelGGL(k_hyb_p1, dim3(g->grid_blocks), dim3(kBlock), 0, s, a, r);
-    else hipLaunchKernelGGL(k_hyb_p2, dim3(g->grid_blocks), dim3(kBlock), 0, s, a, r);
+    const int64_t grid = first ? std::max<int64_t>(g->grid_blocks, ceil_div(g->n, kBlock)) : g->grid_blocks;
+    if (phase == 0) hipLaunchKernelGGL(k_hyb_p1, dim3((unsigned)grid), dim3(kBlock), 0, s, a, r);
+    else hipLaunchKernelGGL(k_hyb_p2, dim3((unsigned)grid), dim3(kBlock), 0, s, a, r);
     TC_HIP(hipGetLastError());
     return MIS_OK;
 }
@@ -1073,7 +1333,8 @@ __global__ void __launch_bounds__(kBlock) k_multi_ctrl(const MultiDesc* d, int c
 __global__ void __launch_bounds__(kBlock) k_multi_init(const MultiDesc* d, const int64_t* bstart, int count) {
     const int g = graph_of(bstart, count, blockIdx.x);
     const MultiDesc& D = d[g];
-    hyb_init_body(D.a.hcnt, D.n, D.a.S, D.a.A, nullptr, D.a.stripes, blockIdx.x - bstart[g], bstart[g + 1] - bstart[g]);
+    hyb_init_body(D.a.oriented ? D.a.hcnt : nullptr, D.n, D.a.S, D.a.A, nullptr, D.a.stripes, blockIdx.x - bstart[g],
+                  bstart[g + 1] - bstart[g]);
 }
 
 __global__ void __launch_bounds__(kBlock) k_multi_p1(const MultiDesc* d, const int64_t* bstart, int count, int ri) {
@@ -1123,7 +1384,7 @@ __global__ void __launch_bounds__(kBlock) k_multi_output(const MultiDesc* d, con
 // (rounds, set sizes), the workgroup shares, the descriptors, then every graph's
 // round state.
 struct MultiLayout {
-    size_t sum = 0, rounds = 0, in = 0, bstart = 0, desc = 0;
+    size_t sum = 0, rounds = 0, in = 0, bstart = 0, bstart1 = 0, desc = 0;
     std::vector<size_t> state;
     size_t total = 0;
 };
@@ -1141,6 +1402,7 @@ static MultiLayout multi_layout(mis_graph* const* gs, int32_t count) {
     L.rounds = take((size_t)count * 4);
     L.in = take((size_t)count * 8);
     L.bstart = take((size_t)(count + 1) * 8);
+    L.bstart1 = take((size_t)(count + 1) * 8);
     L.desc = take((size_t)count * sizeof(MultiDesc));
     L.state.resize((size_t)count);
     for (int32_t i = 0; i < count; ++i) {
@@ -1210,9 +1472,10 @@ int mis_solve_batch(mis_graph* const* graphs, int32_t count, uint8_t* const* in_
     int32_t* d_rounds = (int32_t*)(base + L.rounds);
     int64_t* d_in = (int64_t*)(base + L.in);
     int64_t* d_bstart = (int64_t*)(base + L.bstart);
+    int64_t* d_bstart1 = (int64_t*)(base + L.bstart1);   // round 1: a thread per vertex
     MultiDesc* d_desc = (MultiDesc*)(base + L.desc);
     std::vector<MultiDesc> desc((size_t)count);
-    std::vector<int64_t> bstart((size_t)count + 1, 0);
+    std::vector<int64_t> bstart((size_t)count + 1, 0), bstart1((size_t)count + 1, 0);
     for (int32_t i = 0; i < count; ++i) {
         GraphCore v = *graphs[i];
         layout_state(&v, base + L.state[(size_t)i], false);
@@ -1227,12 +1490,14 @@ int mis_solve_batch(mis_graph* const* graphs, int32_t count, uint8_t* const* in_
         const int64_t share = std::min<int64_t>(std::max<int64_t>(1, ceil_div(v.n, kMultiVerts)),
                                                 std::max(1, v.grid_blocks));
         bstart[(size_t)i + 1] = bstart[(size_t)i] + share;
+        bstart1[(size_t)i + 1] = bstart1[(size_t)i] + std::max<int64_t>(share, ceil_div(v.n, kBlock));
     }
-    const int64_t nblocks = bstart[(size_t)count];
-    if (nblocks >= (1ll << 31)) { set_error("too many workgroups for one launch"); return MIS_EINVAL; }
+    const int64_t nblocks = bstart[(size_t)count], nblocks1 = bstart1[(size_t)count];
+    if (nblocks1 >= (1ll << 31)) { set_error("too many workgroups for one launch"); return MIS_EINVAL; }
     TC_HIP(hipMemcpyAsync(d_desc, desc.data(), desc.size() * sizeof(MultiDesc), hipMemcpyHostToDevice, s));
     TC_HIP(hipMemcpyAsync(d_bstart, bstart.data(), bstart.size() * 8, hipMemcpyHostToDevice, s));
-    const dim3 grid((unsigned)nblocks), blk(kBlock), cgrid((unsigned)ceil_div(count, kWpb));
+    TC_HIP(hipMemcpyAsync(d_bstart1, bstart1.data(), bstart1.size() * 8, hipMemcpyHostToDevice, s));
+    const dim3 grid((unsigned)nblocks), grid1((unsigned)nblocks1), blk(kBlock), cgrid((unsigned)ceil_div(count, kWpb));
     hipLaunchKernelGGL(k_multi_ctrl, dim3((unsigned)count), blk, 0, s, d_desc, count);
     hipLaunchKernelGGL(k_multi_init, grid, blk, 0, s, d_desc, d_bstart, count);
     TC_HIP(hipGetLastError());
@@ -1240,8 +1505,9 @@ int mis_solve_batch(mis_graph* const* graphs, int32_t count, uint8_t* const* in_
     int32_t r = 0;
     for (;;) {
         for (int i = 1; i <= poll; ++i) {
-            hipLaunchKernelGGL(k_multi_p1, grid, blk, 0, s, d_desc, d_bstart, count, i);
-            hipLaunchKernelGGL(k_multi_p2, grid, blk, 0, s, d_desc, d_bstart, count, i);
+            const bool first = r == 0 && i == 1;
+            hipLaunchKernelGGL(k_multi_p1, first ? grid1 : grid, blk, 0, s, d_desc, first ? d_bstart1 : d_bstart, count, i);
+            hipLaunchKernelGGL(k_multi_p2, first ? grid1 : grid, blk, 0, s, d_desc, first ? d_bstart1 : d_bstart, count, i);
         }
         TC_HIP(hipMemsetAsync(sum, 0, sizeof(Ctrl), s));
         hipLaunchKernelGGL(k_multi_close, cgrid, blk, 0, s, d_desc, count, poll, sum, d_rounds, d_in);

@@ -1,9 +1,13 @@
-"""A short program for counter runs under rocprofv3: one tile-path build and solve
-of a named workload (the CSR resident on the device), one CSR-path solve, and one
-device-to-device copy of a known size, whose FETCH_SIZE / WRITE_SIZE calibrate the
-counters against bytes actually moved.
+"""A short program for counter runs under rocprofv3: one tile-path (or, with --path
+hybrid, hybrid-path) build and solve of a named workload (the CSR resident on the
+device), one CSR-path solve, and one device-to-device copy of a known size, whose
+FETCH_SIZE / WRITE_SIZE calibrate the counters against bytes actually moved.
 
-    python paper_2605_29604_amd/profile_run.py [--workload rmat22] [--copy-mib 256]
+    python paper_2605_29604_amd/profile_run.py [--workload rmat22] [--copy-mib 256] [--path hybrid]
+
+With --summarize-kernel RECORD FETCH_DIR WRITE_DIR it writes the per-launch traffic
+record of one hybrid-path kernel (RECORD: hybrid_candidate, hybrid_exclusion,
+hybrid_dense_scan).
 
 With --summarize FETCH_DIR WRITE_DIR (the output folders of one FETCH_SIZE and one
 WRITE_SIZE run of this program) it reads the counters instead, on any machine, and
@@ -312,6 +316,76 @@ Average per launch: {sum(per) / len(per) / 1e6:.2f} MB.
     return 0
 
 
+# the hybrid path's kernels with a traffic record: record name -> (kernel symbol, sources)
+HYBRID_KERNELS = {
+    "hybrid_candidate": ("k_hyb_p1", ("hyb.hip", "round.hpp", "graph.hpp")),
+    "hybrid_exclusion": ("k_hyb_p2", ("hyb.hip", "round.hpp", "graph.hpp")),
+    "hybrid_dense_scan": ("k_block_scan", ("hyb.hip", "graph.hpp")),
+}
+
+
+def summarize_kernel(a) -> int:
+    """Per-launch HBM traffic of one hybrid-path kernel (all its dispatches in one
+    build + solve of profile_run.py --path hybrid), FETCH_SIZE and WRITE_SIZE each
+    scaled by what the counter reads for the copy of known size."""
+    record, fdir, wdir = a.summarize_kernel
+    symbol, sources = HYBRID_KERNELS[record]
+    cf, fetch = _counter(fdir, "FETCH_SIZE", symbol)
+    cw, write = _counter(wdir, "WRITE_SIZE", symbol)
+    if len(fetch) != len(write):
+        raise SystemExit("the two runs dispatched the kernel a different number of times")
+    moved = a.copy_mib * 1024.0
+    ff, wf = moved / cf, moved / cw
+    per = [(f * ff + w * wf) * 1024.0 for f, w in zip(fetch, write)]
+    sha = {}
+    for name in sources:
+        with open(os.path.join(ROOT, "paper_2605_29604_amd", "csrc", name), "rb") as fh:
+            sha[name] = hashlib.sha256(fh.read()).hexdigest()
+    rec = {"kernel": record, "symbol": symbol, "workload": a.workload, "seed": 1, "dense_min": a.dense_min,
+           "dispatches": len(per), "fetch_kib": fetch, "write_kib": write, "copy_mib": a.copy_mib,
+           "copy_fetch_kib": cf, "copy_write_kib": cw, "fetch_factor": ff, "write_factor": wf,
+           "traffic_bytes_per_dispatch": per, "traffic_bytes_per_launch": sum(per) / len(per),
+           "source_sha256": sha}
+    base = os.path.join(ROOT, "profiles", f"{record}_{a.workload}_traffic")
+    with open(base + ".json", "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    rows = "\n".join(f"| {i + 1} | {f:.1f} | {w:.1f} | {b / 1e6:.2f} MB |"
+                     for i, (f, w, b) in enumerate(zip(fetch, write, per)))
+    md = f"""# {a.workload}: HBM traffic of `{symbol}` (FETCH_SIZE / WRITE_SIZE)
+
+Commands (two passes, one counter each, run from /tmp; REPO = the repository root, OUT = a directory for
+the output):
+
+```
+rocprofv3 --pmc FETCH_SIZE --kernel-trace --output-format csv -d $OUT/pmc_fetch -o run -- \\
+    python3 $REPO/paper_2605_29604_amd/profile_run.py --path hybrid
+rocprofv3 --pmc WRITE_SIZE --kernel-trace --output-format csv -d $OUT/pmc_write -o run -- \\
+    python3 $REPO/paper_2605_29604_amd/profile_run.py --path hybrid
+python3 paper_2605_29604_amd/profile_run.py --summarize-kernel {record} $OUT/pmc_fetch $OUT/pmc_write
+```
+
+`profile_run.py --path hybrid` copies {a.copy_mib} MiB device to device, then builds and solves {a.workload} on the
+hybrid path (default dense-block threshold, direct launches).
+
+Calibration (the {a.copy_mib} MiB copy): FETCH_SIZE reads {cf:.1f} KiB, WRITE_SIZE {cw:.1f} KiB for {moved:.0f} KiB
+moved each way, so FETCH_SIZE is scaled by {ff:.4f} and WRITE_SIZE by {wf:.4f}.
+
+| Dispatch | FETCH_SIZE KiB | WRITE_SIZE KiB | bytes (scaled) |
+|---:|---:|---:|---:|
+{rows}
+
+Average per launch: {sum(per) / len(per) / 1e6:.2f} MB.  These counters count lines moved between the L2
+and the memory fabric, which includes hits in the 256 MB Infinity Cache, so they bound HBM traffic from
+above.  `{os.path.basename(base)}.json` holds the figures with the SHA-256 of the kernel's sources;
+`bench.py` reports them (`roofline.traffic`) only while those sources are unchanged.
+"""
+    with open(base + ".md", "w") as fh:
+        fh.write(md)
+    print(f"{base}.json: {len(per)} launches, {sum(per) / len(per) / 1e6:.2f} MB per launch")
+    return 0
+
+
 def main() -> int:
     p = argparse.ArgumentParser()
     p.add_argument("--workload", default="rmat22")
@@ -323,7 +397,12 @@ def main() -> int:
     p.add_argument("--summarize-mfma", metavar="DIR")
     p.add_argument("--summarize-stalls", metavar="DIR")
     p.add_argument("--summarize-build", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    p.add_argument("--summarize-kernel", nargs=3, metavar=("RECORD", "FETCH_DIR", "WRITE_DIR"))
+    p.add_argument("--path", default="tile", choices=("tile", "hybrid"))
+    p.add_argument("--dense-min", type=int, default=0)
     a = p.parse_args()
+    if a.summarize_kernel:
+        return summarize_kernel(a)
     if a.summarize:
         return summarize(a)
     if a.summarize_mfma:
@@ -345,9 +424,13 @@ def main() -> int:
     print(f"copy {a.copy_mib} MiB", flush=True)
     dst.copy_(src)
     torch.cuda.synchronize()
-    print("tile build + solve", flush=True)
-    h = tcmis.mis_build_tiles(rp, ci, path="tile", tile=a.tile, reorder=a.reorder, orient=a.orient, seed=1,
-                              launch="direct")
+    if a.path == "hybrid":
+        print("hybrid build + solve", flush=True)
+        h = tcmis.mis_build_tiles(rp, ci, path="hybrid", dense_min=a.dense_min, seed=1, launch="direct")
+    else:
+        print("tile build + solve", flush=True)
+        h = tcmis.mis_build_tiles(rp, ci, path="tile", tile=a.tile, reorder=a.reorder, orient=a.orient, seed=1,
+                                  launch="direct")
     out, st = tcmis.mis_solve(h, trace_cap=0)
     torch.cuda.synchronize()
     tcmis.mis_free_tiles(h)
@@ -357,7 +440,7 @@ def main() -> int:
     torch.cuda.synchronize()
     tcmis.mis_free_tiles(h)
     same = bool(torch.equal(out, out2))
-    print(f"rounds {st['rounds']} set {st['n_in']} tile==csr {same}", flush=True)
+    print(f"rounds {st['rounds']} set {st['n_in']} {a.path}==csr {same}", flush=True)
     return 0 if same else 1
 
 
