@@ -19,11 +19,14 @@
  *   - Return value: MIS_OK (0) or a negative mis_status.  Argument errors are
  *     detected on the host before any device work is enqueued.  After an error
  *     mis_last_error() returns a thread-local message with details.
- *   - A built handle's structure is read-only to solves.  A solve keeps its round
- *     state either in a caller's scratch (mis_solve with scratch != NULL: any
- *     number of such solves of one handle may run concurrently, on different
- *     streams or threads, each with its own scratch) or in the handle's own
- *     round state (scratch == NULL: one such solve at a time per handle).
+ *   - A solve keeps its round state either in a caller's scratch (mis_solve with
+ *     scratch != NULL: any number of such solves of one handle may run
+ *     concurrently, on different streams or threads, each with its own scratch)
+ *     or in the handle's own round state (scratch == NULL: one such solve at a
+ *     time per handle).  The structure is read-only to solves, except that the
+ *     hybrid path's round 1 writes the higher-priority neighbour rows of the
+ *     vertices it leaves undecided into the handle: every solve of a handle
+ *     writes the same values there, so concurrent solves stay correct.
  *     mis_update_edges changes a handle and must not overlap any solve of it.
  */
 #ifndef TCMIS_H

@@ -12,7 +12,7 @@ namespace tcmis {
 constexpr int kLightDeg = 32;       // CSR path: thread per vertex up to this degree, wave above
 constexpr int kTraceCap = 4096;     // device trace ring (rounds); the host drains it at every poll
 constexpr int kUnits = 8;           // work-unit counters per round (TraceRec::u)
-constexpr int kStripes = 32;        // round counters are spread over this many cache lines
+constexpr int kStripes = 128;       // round counters are spread over this many cache lines (a multiple of 64)
 constexpr int kStripeWords = 16;    // int64 words per stripe (one 128-byte line)
 constexpr int kDenseMinDefault = 9; // hybrid: a 36-byte 16x16 tile costs no more than 9 entry indices
 

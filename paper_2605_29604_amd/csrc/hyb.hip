@@ -52,6 +52,8 @@ constexpr int kHE = 2048;                 // adjacency entries per orientation w
 constexpr int kHWin = 512;                // rows a workgroup stages in LDS
 constexpr int kHSteps = 9;                // 2^kHSteps = kHWin
 constexpr int kHLight = 32;               // rows with at most this many entries take one lane
+constexpr int kP2Words = 8;               // bitmap words a wave takes in round 1's exclusion phase
+constexpr int kGrp = 16;                  // entries a lane loads and compares per step in round 1
 constexpr int kDenseCap = 1024;           // most oriented entries a block may hold to be dense
 constexpr int kDenseTiles = 64;           // most tiles of a dense block (one per lane)
 constexpr int kWpb = kBlock / kWave;
@@ -101,16 +103,21 @@ __device__ inline uint64_t sig_bit(int64_t J) { return 1ull << (((uint64_t)J * 0
 // does column u out-rank row v?  kUserKeys: compare the keys; else the default key
 // rule: the degree class decides unless it ties, then the hash of the graph-local
 // id, then the id (kv is row v's whole key, so its class, hash and local id are known)
-template <bool kUserKeys>
-__device__ inline bool higher(int64_t u, int64_t v, uint64_t kv, const uint64_t* key, const uint8_t* q8, uint64_t seed) {
-    if (kUserKeys) return key[u] > kv;
-    const uint32_t qu = q8[u], qv = (uint32_t)(kv >> 56);
-    if (qu != qv) return qu > qv;
+// the default rule between two vertices of the same degree class
+__device__ inline bool tie_higher(int64_t u, int64_t v, uint64_t kv, uint64_t seed) {
     const int64_t lv = (int64_t)(kv & 0xFFFFFFull);
     const int64_t lu = u - (v - lv);   // same graph: same offset
     const uint32_t hu = (uint32_t)(splitmix_at(seed, (uint64_t)lu + 1) >> 32);
     const uint32_t hv = (uint32_t)(kv >> 24);
     return hu != hv ? hu > hv : lu > lv;
+}
+
+template <bool kUserKeys>
+__device__ inline bool higher(int64_t u, int64_t v, uint64_t kv, const uint64_t* key, const uint8_t* q8, uint64_t seed) {
+    if (kUserKeys) return key[u] > kv;
+    const uint32_t qu = q8[u], qv = (uint32_t)(kv >> 56);
+    if (qu != qv) return qu > qv;
+    return tie_higher(u, v, kv, seed);
 }
 
 // Where the orientation writes: the higher-priority entries of row v go to
@@ -548,6 +555,7 @@ struct HybArgs {
     int32_t* hcnt;
     const int64_t* crp;       // the caller's CSR (round 1 of a static handle reads it)
     const int32_t* ci;
+    int64_t nnz;
     const uint64_t* key;      // priorities, with the one-byte degree classes of the default rule
     const uint8_t* q8;
     uint64_t seed;
@@ -589,10 +597,14 @@ __device__ inline void dense_list(const HybArgs& a, int r, const int32_t** L, in
     }
 }
 
+// does the handle hold dense blocks (wave-uniform; dslot is all -1 when the build
+// found none, so the per-vertex checks are skipped)
+__device__ inline bool dense_on(const HybArgs& a) { return a.dslot && a.meta->n_dense > 0; }
+
 // the undecided list rows of bitmap word w (x = its alive bits): the rows of dense
 // blocks are masked out (their blocks are visited through the dense lists)
-__device__ inline uint32_t list_rows(const HybArgs& a, int64_t w, uint32_t x) {
-    if (a.dslot) {
+__device__ inline uint32_t list_rows(const HybArgs& a, bool dn, int64_t w, uint32_t x) {
+    if (dn) {
         const int64_t I0 = 2 * w;   // the word's two 16-row blocks
         if (I0 < a.nI && a.dslot[I0] >= 0) x &= 0xFFFF0000u;
         if (I0 + 1 < a.nI && a.dslot[I0 + 1] >= 0) x &= 0x0000FFFFu;
@@ -699,64 +711,83 @@ __device__ inline bool scan4(const int32_t* row, int32_t c, const uint32_t* m, i
     return false;
 }
 
-// Does one of the c neighbours row[0 .. c) of v out-rank it?  Eight entries at a time
-// (eight index loads, then eight priority comparisons with their class gathers in
-// flight), stopping after the group that holds the first one; *read counts the
-// entries loaded.
-__device__ inline bool scan_higher8(const HybArgs& a, const int32_t* row, int64_t c, int64_t v, uint64_t kv,
-                                    int64_t* read) {
-    for (int64_t k = 0; k < c; k += 8) {
-        int32_t u[8];
-        #pragma unroll
-        for (int j = 0; j < 8; ++j) u[j] = k + j < c ? row[k + j] : -1;
-        bool h = false;
-        #pragma unroll
-        for (int j = 0; j < 8; ++j) h |= u[j] >= 0 && hi(a, u[j], v, kv);
-        *read += min<int64_t>(c - k, 8);
-        if (h) return true;
+// Round 1 reads a lane's row kGrp entries per step: the step's loads are issued
+// together (a 16-byte load per four entries that start inside the row), then its key
+// or class gathers (one per entry inside the row), then its comparisons.  u[j] =
+// row[k + j] where k + j < c (c: the entries the lane takes), else v itself.  A load
+// may read up to three entries past c (the next rows' entries, replaced by v), so the
+// caller makes sure that row + k + kGrp stays inside the array.
+typedef int32_t i4u __attribute__((ext_vector_type(4), aligned(4)));
+
+__device__ inline void load_grp(const int32_t* __restrict__ row, int k, int c, int32_t v, int32_t (&u)[kGrp]) {
+    #pragma unroll
+    for (int i = 0; i < kGrp / 4; ++i) {
+        i4u x = {v, v, v, v};
+        if (k + 4 * i < c) x = *reinterpret_cast<const i4u*>(row + k + 4 * i);
+        u[4 * i] = x.x;
+        u[4 * i + 1] = x.y;
+        u[4 * i + 2] = x.z;
+        u[4 * i + 3] = x.w;
     }
-    return false;
+    #pragma unroll
+    for (int j = 0; j < kGrp; ++j) u[j] = k + j < c ? u[j] : v;
 }
 
-// Does a row of c entries name a vertex whose bit is set in m?  Eight at a time.
-__device__ inline bool scan8(const int32_t* row, int64_t c, const uint32_t* m, int64_t* read) {
-    for (int64_t k = 0; k < c; k += 8) {
-        int32_t u[8];
+// Bit j (j < kGrp, k + j < c) is set when u[j] out-ranks v (kv = v's key): the default
+// rule gathers the step's class bytes before comparing (a class tie goes to the hash);
+// caller keys are gathered four at a time.
+__device__ inline uint32_t grp_mask(const HybArgs& a, const int32_t (&u)[kGrp], int k, int c, int32_t v,
+                                    uint64_t kv, bool uk) {
+    uint32_t h = 0;
+    if (uk) {
         #pragma unroll
-        for (int j = 0; j < 8; ++j) u[j] = k + j < c ? row[k + j] : -1;
-        bool hit = false;
-        #pragma unroll
-        for (int j = 0; j < 8; ++j) hit |= u[j] >= 0 && bit_of(m, u[j]);
-        *read += min<int64_t>(c - k, 8);
-        if (hit) return true;
+        for (int j0 = 0; j0 < kGrp; j0 += 4) {
+            uint64_t ku[4];
+            #pragma unroll
+            for (int j = 0; j < 4; ++j) ku[j] = k + j0 + j < c ? a.key[(uint32_t)u[j0 + j]] : 0ull;
+            #pragma unroll
+            for (int j = 0; j < 4; ++j) h |= (ku[j] > kv ? 1u : 0u) << (j0 + j);
+        }
+        return h;
     }
-    return false;
+    uint32_t q[kGrp];
+    #pragma unroll
+    for (int j = 0; j < kGrp; ++j) q[j] = k + j < c ? a.q8[(uint32_t)u[j]] : 0u;
+    const uint32_t qv = (uint32_t)(kv >> 56);
+    #pragma unroll
+    for (int j = 0; j < kGrp; ++j) {
+        bool b = false;
+        if (k + j < c) {
+            b = q[j] > qv;
+            if (q[j] == qv) b = tie_higher(u[j], v, kv, a.seed);
+        }
+        h |= (b ? 1u : 0u) << j;
+    }
+    return h;
 }
 
-// Writes H(v) (the neighbours row[0 .. c) that out-rank v) to hcol[rp[v] ..] and its
-// size to hcnt[v], one lane, eight entries at a time (loads and comparisons of a group
-// issued before its stores); returns the size.
-__device__ inline int32_t orient_row(const HybArgs& a, const int32_t* __restrict__ row, int64_t c, int64_t v,
-                                     uint64_t kv) {
-    int32_t* __restrict__ out = a.hcol + a.rp[v];
-    int32_t m = 0;
-    for (int64_t k = 0; k < c; k += 8) {
-        int32_t u[8];
-        #pragma unroll
-        for (int j = 0; j < 8; ++j) u[j] = k + j < c ? row[k + j] : -1;
-        uint32_t keep = 0;
-        #pragma unroll
-        for (int j = 0; j < 8; ++j) keep |= (u[j] >= 0 && hi(a, u[j], v, kv)) ? 1u << j : 0u;
-        #pragma unroll
-        for (int j = 0; j < 8; ++j)
-            if ((keep >> j) & 1u) out[m++] = u[j];
-    }
-    a.hcnt[v] = m;
-    return m;
+// Does one of the entries u[j] (k + j < c) have its bit set in m?  The step's bitmap
+// words are gathered together.
+__device__ inline bool grp_hit(const uint32_t* m, const int32_t (&u)[kGrp], int k, int c) {
+    uint32_t w[kGrp];
+    #pragma unroll
+    for (int j = 0; j < kGrp; ++j) w[j] = k + j < c ? m[(uint32_t)u[j] >> 5] : 0u;
+    uint32_t h = 0;
+    #pragma unroll
+    for (int j = 0; j < kGrp; ++j) h |= w[j] >> (u[j] & 31);
+    return (h & 1u) != 0;
 }
+
+// Which rounds a build of the phase code serves: any round (the persistent kernel and
+// launches over several graphs), the rounds after the first, or round 1 alone (under
+// the default key rule or under caller keys).  Round 1 of a static handle reads the
+// caller's CSR with many loads in flight per lane; its own builds keep that code's
+// registers out of the later rounds' kernels.
+enum : int { kAnyRound = 0, kLaterRounds = 1, kRound1 = 2, kRound1Keys = 3 };
 
 // Phase 1 of round r.  The workgroup is number vb of nvb working on this graph (the
 // launch's grid, or the graph's share of a launch over several graphs).
+template <int kMode>
 __device__ void hyb_p1(const HybArgs& a, int r, int64_t vb, int64_t nvb) {
     __shared__ uint32_t sbits[kWpb][kDenseTiles * 8];
     __shared__ uint32_t svec[kWpb][kDenseTiles];
@@ -770,27 +801,42 @@ __device__ void hyb_p1(const HybArgs& a, int r, int64_t vb, int64_t nvb) {
     const int64_t tid = vb * kBlock + threadIdx.x;
     const int64_t nwaves = nthreads / kWave, wv = tid / kWave;
     int64_t n_cand = 0, ent = 0, verts = 0, mult = 0, blocks = 0;
-    if (r == 1) {
+    const bool first = kMode >= kRound1 || (kMode == kAnyRound && r == 1);
+    const bool uk = kMode == kRound1Keys || (kMode == kAnyRound && a.user_keys);
+    const bool dn = dense_on(a);
+    if (first) {
         // Every vertex outside the dense blocks compares its neighbours in the
         // caller's CSR with itself until one out-ranks it (every vertex is undecided).
         // Each lane takes its vertex's first kHLight entries; the longer rows still
         // undecided after them continue with the whole wave, 64 entries per step, one
-        // after another (most rows meet a higher neighbour early).
+        // after another (most rows meet a higher neighbour early), and so do the rows
+        // of the array's last kHLight entries, from their start.
         const int64_t nr = (a.n + kWave - 1) / kWave * kWave;   // whole waves iterate together
         for (int64_t i = tid; i < nr; i += nthreads) {
             const int32_t v = (int32_t)i;
-            const bool row = i < a.n && !(a.dslot && a.dslot[v >> 4] >= 0);
-            int64_t e0 = 0, d = 0;
+            int64_t e0 = 0, d = 0, k0 = 0;
             uint64_t kv = 0;
-            bool found = false;
-            if (row) {
+            bool row = i < a.n, found = false;
+            if (row) {   // the row bounds, the key and the block's slot in flight together
                 e0 = a.crp[v];
                 d = a.crp[v + 1] - e0;
                 kv = a.key[v];
-                ++verts;
-                found = scan_higher8(a, a.ci + e0, min<int64_t>(d, kHLight), v, kv, &ent);
+                row = !(dn && a.dslot[v >> 4] >= 0);
             }
-            const bool cont = row && !found && d > kHLight;
+            if (row) {
+                ++verts;
+                if (d > 0 && e0 + kHLight <= a.nnz) {
+                    const int c = (int)min<int64_t>(d, kHLight);
+                    for (int k = 0; k < c && !found; k += kGrp) {
+                        int32_t u[kGrp];
+                        load_grp(a.ci + e0, k, c, v, u);
+                        found = grp_mask(a, u, k, c, v, kv, uk) != 0;
+                        ent += min(c - k, kGrp);
+                    }
+                    k0 = kHLight;
+                }
+            }
+            const bool cont = row && !found && d > k0;
             int64_t w = -1;
             uint32_t m = 0;
             if (row && !found && !cont) { w = v >> 5; m = 1u << (v & 31); ++n_cand; }
@@ -800,21 +846,21 @@ __device__ void hyb_p1(const HybArgs& a, int r, int64_t vb, int64_t nvb) {
                 const int l = __builtin_ctzll(hv);
                 hv &= hv - 1;
                 const int32_t vh = __shfl(v, l, kWave);
-                const int64_t e0h = __shfl(e0, l, kWave), dh = __shfl(d, l, kWave);
+                const int64_t e0h = __shfl(e0, l, kWave), dh = __shfl(d, l, kWave), k0h = __shfl(k0, l, kWave);
                 const uint64_t kvh = __shfl(kv, l, kWave);
                 bool blocked = false;
-                int64_t k = kHLight;
+                int64_t k = k0h;
                 for (; k < dh; k += kWave) {
                     const bool b = k + lane < dh && hi(a, a.ci[e0h + k + lane], vh, kvh);
                     if (ballot(b)) { blocked = true; k += kWave; break; }
                 }
                 if (lane == 0) {
-                    ent += min(k, dh) - kHLight;
+                    ent += min(k, dh) - k0h;
                     if (!blocked) { atomicOr(&a.S[vh >> 5], 1u << (vh & 31)); ++n_cand; }
                 }
             }
         }
-    } else {
+    } else if (kMode < kRound1) {
         // Undecided rows outside the dense blocks, a thread per bitmap word (32
         // vertices): rows of at most kHLight entries scan H(v) for an alive neighbour
         // (early exit); the longer rows of a wave's words then take the whole wave, one
@@ -822,7 +868,7 @@ __device__ void hyb_p1(const HybArgs& a, int r, int64_t vb, int64_t nvb) {
         const int64_t nwords = (a.n + 31) >> 5;
         const int64_t nwr = (nwords + kWave - 1) / kWave * kWave;   // whole waves iterate together
         for (int64_t w = tid; w < nwr; w += nthreads) {
-            const uint32_t rows = w < nwords ? list_rows(a, w, a.A[w]) : 0u;
+            const uint32_t rows = w < nwords ? list_rows(a, dn, w, a.A[w]) : 0u;
             uint32_t cand = 0, heavy = 0;
             for (uint32_t mm = rows; mm; mm &= mm - 1) {
                 const int b = __builtin_ctz(mm);
@@ -868,6 +914,7 @@ __device__ void hyb_p1(const HybArgs& a, int r, int64_t vb, int64_t nvb) {
 }
 
 // Phases 2 and 3 of round r: retire candidates, remove their neighbours, list the rest.
+template <int kMode>
 __device__ void hyb_p2(const HybArgs& a, int r, int64_t vb, int64_t nvb) {
     __shared__ int32_t lbuf[kWpb][kWave];
     __shared__ uint32_t sbits[kWpb][kDenseTiles * 8];
@@ -883,73 +930,132 @@ __device__ void hyb_p2(const HybArgs& a, int r, int64_t vb, int64_t nvb) {
     const int64_t tid = vb * kBlock + threadIdx.x;
     const int64_t nwaves = nthreads / kWave, wv = tid / kWave;
     int64_t n_out = 0, ent = 0, verts = 0, mult = 0, blocks = 0;
-    if (r == 1 && !a.oriented) {
+    const bool first = kMode >= kRound1 || (kMode == kAnyRound && r == 1);
+    const bool uk = kMode == kRound1Keys || (kMode == kAnyRound && a.user_keys);
+    const bool dn = dense_on(a);
+    if (first && !a.oriented) {
         // Every vertex outside the dense blocks: a candidate of round 1 joins the set;
         // any other scans its row of the caller's CSR for a candidate (a candidate
         // neighbour always out-ranks it) and leaves on the first.  A vertex with none
         // stays undecided: its H row is written now, for the later rounds (round 1 is
-        // the only time its whole row is compared).  Each lane takes its vertex's
-        // first kHLight entries; longer rows with no candidate among them continue with
-        // the whole wave, one after another.
-        const int64_t nr = (a.n + kWave - 1) / kWave * kWave;   // whole waves iterate together
-        for (int64_t i = tid; i < nr; i += nthreads) {
-            const int32_t v = (int32_t)i;
-            const bool row = i < a.n && !(a.dslot && a.dslot[v >> 4] >= 0);
-            const bool in = row && bit_of(a.S, v);
-            int64_t e0 = 0, d = 0;
-            bool hit = false;
-            if (row && !in) {
-                e0 = a.crp[v];
-                d = a.crp[v + 1] - e0;
-                ++verts;
-                hit = scan8(a.ci + e0, min<int64_t>(d, kHLight), a.S, &ent);
+        // the only time its whole row is compared).  A wave takes kP2Words bitmap words
+        // (their candidates need no work) and packs the other vertices onto its lanes,
+        // one each: a lane scans its vertex's first kHLight entries; longer rows with
+        // no candidate among them, and the rows of the array's last kHLight entries,
+        // continue with the whole wave, one after another.  The decided vertices of the
+        // words collect in LDS; one atomic per word clears their alive bits.
+        __shared__ uint32_t sdec[kWpb][kP2Words];
+        const int64_t nwords = (a.n + 31) >> 5;
+        const int64_t ngroups = (nwords + kP2Words - 1) / kP2Words;
+        for (int64_t gi = wv; gi < ngroups; gi += nwaves) {
+            const int64_t w0 = gi * kP2Words;
+            const bool own = lane < kP2Words && w0 + lane < nwords;   // lane k < kP2Words: word w0 + k
+            const uint32_t rows = own ? list_rows(a, dn, w0 + lane, a.A[w0 + lane]) : 0u;
+            const uint32_t sw = own ? a.S[w0 + lane] : 0u;
+            if (lane < kP2Words) sdec[wid][lane] = 0;
+            uint32_t ncw[kP2Words], pre[kP2Words + 1];
+            pre[0] = 0;
+            #pragma unroll
+            for (int k = 0; k < kP2Words; ++k) {
+                ncw[k] = __builtin_amdgcn_readlane(rows & ~sw, k);
+                pre[k + 1] = pre[k] + __popc(ncw[k]);
             }
-            const bool cont = row && !in && !hit && d > kHLight;
-            int64_t w = -1;
-            uint32_t m = 0;
-            if (in || hit) {
-                w = v >> 5; m = 1u << (v & 31);
-                n_out += hit ? 1 : 0;
-                if (a.dround) a.dround[v] = r;
-            } else if (row && !cont) {
-                orient_row(a, a.ci + e0, d, v, a.key[v]);
-                ent += d;
-            }
-            run_apply<true>(w, m, a.A);
-            for (uint64_t hv = ballot(cont); hv; hv &= hv - 1) {
-                const int l = __builtin_ctzll(hv);
-                const int32_t vh = __shfl(v, l, kWave);
-                const int64_t e0h = __shfl(e0, l, kWave), dh = __shfl(d, l, kWave);
-                bool hit2 = false;
-                int64_t k = kHLight;
-                for (; k < dh; k += kWave) {
-                    const int32_t u = k + lane < dh ? a.ci[e0h + k + lane] : -1;
-                    if (ballot(u >= 0 && bit_of(a.S, u))) { hit2 = true; k += kWave; break; }
+            const int total = (int)pre[kP2Words];
+            wave_sync_lds();
+            for (int p0 = 0; p0 < total; p0 += kWave) {
+                // the j-th vertex outside S among the group's rows
+                const int j = p0 + lane;
+                const bool act = j < total;
+                int k = 0;
+                #pragma unroll
+                for (int kk = 1; kk < kP2Words; ++kk) k += (uint32_t)j >= pre[kk] ? 1 : 0;
+                uint32_t x = ncw[0], rank = (uint32_t)j;
+                #pragma unroll
+                for (int kk = 1; kk < kP2Words; ++kk)
+                    if (k == kk) { x = ncw[kk]; rank = (uint32_t)j - pre[kk]; }
+                int pos = 0;   // bit of x with `rank` set bits below it
+                #pragma unroll
+                for (int sh = 16; sh > 0; sh >>= 1) {
+                    const uint32_t c = __popc(x & ((1u << sh) - 1u));
+                    if (rank >= c) { rank -= c; x >>= sh; pos += sh; }
                 }
-                if (lane == 0) ent += min(k, dh) - kHLight;
-                if (hit2) {
-                    if (lane == 0) {
-                        atomicAnd(&a.A[vh >> 5], ~(1u << (vh & 31)));
-                        ++n_out;
-                        if (a.dround) a.dround[vh] = r;
+                const int32_t v = (int32_t)((w0 + k) * 32 + pos);
+                int64_t e0 = 0, d = 0, k0 = 0;
+                bool hit = false;
+                if (act) {   // d >= 1: a vertex without neighbours is a candidate
+                    e0 = a.crp[v];
+                    d = a.crp[v + 1] - e0;
+                    ++verts;
+                    if (e0 + kHLight <= a.nnz) {
+                        const int c = (int)min<int64_t>(d, kHLight);
+                        for (int k = 0; k < c && !hit; k += kGrp) {
+                            int32_t u[kGrp];
+                            load_grp(a.ci + e0, k, c, v, u);
+                            hit = grp_hit(a.S, u, k, c);
+                            ent += min(c - k, kGrp);
+                        }
+                        if (!hit && d <= kHLight) {   // undecided: write H(v)
+                            const uint64_t kv = a.key[v];
+                            int32_t* __restrict__ out = a.hcol + a.rp[v];
+                            int32_t m = 0;
+                            #pragma nounroll
+                            for (int k = 0; k < c; k += kGrp) {
+                                int32_t u[kGrp];
+                                load_grp(a.ci + e0, k, c, v, u);
+                                const uint32_t keep = grp_mask(a, u, k, c, v, kv, uk);
+                                #pragma unroll
+                                for (int j = 0; j < kGrp; ++j)
+                                    if ((keep >> j) & 1u) out[m++] = u[j];
+                            }
+                            a.hcnt[v] = m;
+                            ent += d;
+                        }
+                        k0 = kHLight;
                     }
-                } else {
-                    // H(vh), ballot-compacted 64 entries at a time
-                    const uint64_t kvh = a.key[vh];
-                    int32_t* out = a.hcol + a.rp[vh];
-                    int32_t c = 0;
-                    for (int64_t k2 = 0; k2 < dh; k2 += kWave) {
-                        const int32_t u = k2 + lane < dh ? a.ci[e0h + k2 + lane] : -1;
-                        const bool h = u >= 0 && hi(a, u, vh, kvh);
-                        const uint64_t mk = ballot(h);
-                        if (h) out[c + __popcll(mk & lanes_below())] = u;
-                        c += __popcll(mk);
+                    if (hit) atomicOr(&sdec[wid][k], 1u << (v & 31));
+                }
+                const bool cont = act && !hit && d > k0;
+                for (uint64_t hv = ballot(cont); hv; hv &= hv - 1) {
+                    const int l = __builtin_ctzll(hv);
+                    const int32_t vh = __shfl(v, l, kWave);
+                    const int64_t e0h = __shfl(e0, l, kWave), dh = __shfl(d, l, kWave), k0h = __shfl(k0, l, kWave);
+                    bool hit2 = false;
+                    int64_t kk = k0h;
+                    for (; kk < dh; kk += kWave) {
+                        const int32_t u = kk + lane < dh ? a.ci[e0h + kk + lane] : -1;
+                        if (ballot(u >= 0 && bit_of(a.S, u))) { hit2 = true; kk += kWave; break; }
                     }
-                    if (lane == 0) { a.hcnt[vh] = c; ent += dh; }
+                    if (lane == 0) ent += min(kk, dh) - k0h;
+                    if (hit2) {
+                        if (lane == 0) atomicOr(&sdec[wid][(vh >> 5) - w0], 1u << (vh & 31));
+                    } else {
+                        // H(vh), ballot-compacted 64 entries at a time
+                        const uint64_t kvh = a.key[vh];
+                        int32_t* out = a.hcol + a.rp[vh];
+                        int32_t c = 0;
+                        for (int64_t k2 = 0; k2 < dh; k2 += kWave) {
+                            const int32_t u = k2 + lane < dh ? a.ci[e0h + k2 + lane] : -1;
+                            const bool h = u >= 0 && hi(a, u, vh, kvh);
+                            const uint64_t mk = ballot(h);
+                            if (h) out[c + __popcll(mk & lanes_below())] = u;
+                            c += __popcll(mk);
+                        }
+                        if (lane == 0) { a.hcnt[vh] = c; ent += dh; }
+                    }
                 }
             }
+            wave_sync_lds();
+            if (own) {
+                const uint32_t hits = sdec[wid][lane];
+                const uint32_t dec = (rows & sw) | hits;
+                if (dec) atomicAnd(&a.A[w0 + lane], ~dec);
+                n_out += __popc(hits);
+                if (a.dround)
+                    for (uint32_t mm = dec; mm; mm &= mm - 1) a.dround[(w0 + lane) * 32 + __builtin_ctz(mm)] = r;
+            }
+            wave_sync_lds();   // sdec is cleared for the next group only after every lane read it
         }
-    } else if (r == 1) {
+    } else if (first) {
         // Dynamic handles (H of every vertex built): a vertex without a higher-priority
         // neighbour is a candidate and already in the set (it was never undecided);
         // any other leaves if one of its higher-priority neighbours is a candidate.
@@ -960,7 +1066,7 @@ __device__ void hyb_p2(const HybArgs& a, int r, int64_t vb, int64_t nvb) {
             const int32_t v = (int32_t)i;
             const bool valid = i < a.n;
             const int32_t c = valid ? a.hcnt[v] : 0;
-            const bool listed = valid && c > 0 && !(a.dslot && a.dslot[v >> 4] >= 0);
+            const bool listed = valid && c > 0 && !(dn && a.dslot[v >> 4] >= 0);
             const bool light = listed && c <= kHLight;
             int64_t w = -1;
             uint32_t m = 0;
@@ -987,7 +1093,7 @@ __device__ void hyb_p2(const HybArgs& a, int r, int64_t vb, int64_t nvb) {
                 }
             }
         }
-    } else {
+    } else if (kMode < kRound1) {
         // Undecided rows outside the dense blocks, a thread per bitmap word:
         // candidates retire; every other row scans H(v) for a candidate (rows of at
         // most kHLight entries on their lane, longer ones with the whole wave) and
@@ -995,7 +1101,7 @@ __device__ void hyb_p2(const HybArgs& a, int r, int64_t vb, int64_t nvb) {
         const int64_t nwords = (a.n + 31) >> 5;
         const int64_t nwr = (nwords + kWave - 1) / kWave * kWave;   // whole waves iterate together
         for (int64_t w = tid; w < nwr; w += nthreads) {
-            const uint32_t rows = w < nwords ? list_rows(a, w, a.A[w]) : 0u;
+            const uint32_t rows = w < nwords ? list_rows(a, dn, w, a.A[w]) : 0u;
             const uint32_t sw = rows ? a.S[w] : 0u;
             uint32_t dec = rows & sw, heavy = 0;
             for (uint32_t mm = rows & ~sw; mm; mm &= mm - 1) {
@@ -1045,11 +1151,13 @@ __device__ void hyb_p2(const HybArgs& a, int r, int64_t vb, int64_t nvb) {
     block_count(a.stripes, r, {1, 4, 5, 7, 9}, x, vb);
 }
 
+template <int kMode>
 __global__ void __launch_bounds__(kBlock) k_hyb_p1(HybArgs a, int ri) {
-    hyb_p1(a, a.ctrl->rbase + ri, blockIdx.x, gridDim.x);
+    hyb_p1<kMode>(a, a.ctrl->rbase + ri, blockIdx.x, gridDim.x);
 }
+template <int kMode>
 __global__ void __launch_bounds__(kBlock) k_hyb_p2(HybArgs a, int ri) {
-    hyb_p2(a, a.ctrl->rbase + ri, blockIdx.x, gridDim.x);
+    hyb_p2<kMode>(a, a.ctrl->rbase + ri, blockIdx.x, gridDim.x);
 }
 
 // Persistent variant: k rounds in one cooperative launch, a grid barrier after every
@@ -1057,9 +1165,9 @@ __global__ void __launch_bounds__(kBlock) k_hyb_p2(HybArgs a, int ri) {
 __global__ void __launch_bounds__(kBlock) k_hyb_rounds(HybArgs a, int k) {
     const int rb = a.ctrl->rbase;
     for (int ri = 1; ri <= k; ++ri) {
-        hyb_p1(a, rb + ri, blockIdx.x, gridDim.x);
+        hyb_p1<kAnyRound>(a, rb + ri, blockIdx.x, gridDim.x);
         grid_barrier(a.ctrl);
-        hyb_p2(a, rb + ri, blockIdx.x, gridDim.x);
+        hyb_p2<kAnyRound>(a, rb + ri, blockIdx.x, gridDim.x);
         grid_barrier(a.ctrl);
     }
     finish_rounds(a.ctrl, a.stripes, a.trace, rb, k);
@@ -1137,6 +1245,7 @@ HybArgs make_args(GraphCore* g) {
     a.hcnt = g->hcnt;
     a.crp = g->row_ptr;
     a.ci = g->col_idx;
+    a.nnz = g->nnz;
     a.key = g->key;
     a.q8 = g->q8;
     a.seed = g->seed;
@@ -1256,9 +1365,21 @@ int hyb_init(GraphCore* g, hipStream_t s) {
 // (first: round 1 of the solve, which visits every vertex: a thread per vertex)
 int hyb_enqueue_phase(GraphCore* g, int phase, int r, hipStream_t s, bool first) {
     HybArgs a = make_args(g);
-    const int64_t grid = first ? std::max<int64_t>(g->grid_blocks, ceil_div(g->n, kBlock)) : g->grid_blocks;
-    if (phase == 0) hipLaunchKernelGGL(k_hyb_p1, dim3((unsigned)grid), dim3(kBlock), 0, s, a, r);
-    else hipLaunchKernelGGL(k_hyb_p2, dim3((unsigned)grid), dim3(kBlock), 0, s, a, r);
+    // the first batch's round 1: a thread per vertex, and in the exclusion phase of a
+    // static handle a wave per kP2Words bitmap words
+    const int64_t per = phase == 1 && g->dyn_slack == 0 ? (int64_t)kBlock * 32 * kP2Words / kWave : kBlock;
+    const int64_t grid = first ? std::max<int64_t>(g->grid_blocks, ceil_div(g->n, per)) : g->grid_blocks;
+    const dim3 gd((unsigned)grid), bd(kBlock);
+    if (!first) {
+        if (phase == 0) hipLaunchKernelGGL(k_hyb_p1<kLaterRounds>, gd, bd, 0, s, a, r);
+        else hipLaunchKernelGGL(k_hyb_p2<kLaterRounds>, gd, bd, 0, s, a, r);
+    } else if (a.user_keys) {
+        if (phase == 0) hipLaunchKernelGGL(k_hyb_p1<kRound1Keys>, gd, bd, 0, s, a, r);
+        else hipLaunchKernelGGL(k_hyb_p2<kRound1Keys>, gd, bd, 0, s, a, r);
+    } else {
+        if (phase == 0) hipLaunchKernelGGL(k_hyb_p1<kRound1>, gd, bd, 0, s, a, r);
+        else hipLaunchKernelGGL(k_hyb_p2<kRound1>, gd, bd, 0, s, a, r);
+    }
     TC_HIP(hipGetLastError());
     return MIS_OK;
 }
@@ -1341,14 +1462,14 @@ __global__ void __launch_bounds__(kBlock) k_multi_p1(const MultiDesc* d, const i
     const int g = graph_of(bstart, count, blockIdx.x);
     const HybArgs& a = d[g].a;
     if (a.ctrl->alive == 0) return;   // finished (and its last round closed) in an earlier launch
-    hyb_p1(a, a.ctrl->rbase + ri, blockIdx.x - bstart[g], bstart[g + 1] - bstart[g]);
+    hyb_p1<kAnyRound>(a, a.ctrl->rbase + ri, blockIdx.x - bstart[g], bstart[g + 1] - bstart[g]);
 }
 
 __global__ void __launch_bounds__(kBlock) k_multi_p2(const MultiDesc* d, const int64_t* bstart, int count, int ri) {
     const int g = graph_of(bstart, count, blockIdx.x);
     const HybArgs& a = d[g].a;
     if (a.ctrl->alive == 0) return;
-    hyb_p2(a, a.ctrl->rbase + ri, blockIdx.x - bstart[g], bstart[g + 1] - bstart[g]);
+    hyb_p2<kAnyRound>(a, a.ctrl->rbase + ri, blockIdx.x - bstart[g], bstart[g + 1] - bstart[g]);
 }
 
 // after k rounds: a wave per graph closes its last round and moves its base past

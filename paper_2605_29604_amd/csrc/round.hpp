@@ -62,15 +62,19 @@ __device__ inline void block_count(int64_t* stripes, int r, const int (&idx)[N],
 __device__ inline void close_round(Ctrl* ctrl, int64_t* stripes, TraceRec* trace, int r) {
     if (r < 1 || ctrl->round != r - 1 || ctrl->alive == 0) return;
     const int lane = lane_id();
-    int64_t* st = stripes + ((int64_t)(r & 1) * kStripes + lane) * kStripeWords;
     int64_t v[2 + kUnits];
     #pragma unroll
-    for (int i = 0; i < 2 + kUnits; ++i) v[i] = lane < kStripes ? atomic_read(&st[i]) : 0;
-    #pragma unroll
-    for (int i = 0; i < 2 + kUnits; ++i) {
-        if (lane < kStripes) st[i] = 0;
-        for (int off = kWave / 2; off > 0; off >>= 1) v[i] += __shfl_xor(v[i], off, kWave);
+    for (int i = 0; i < 2 + kUnits; ++i) v[i] = 0;
+    for (int s = lane; s < kStripes; s += kWave) {   // kStripes / kWave stripes per lane
+        int64_t* st = stripes + ((int64_t)(r & 1) * kStripes + s) * kStripeWords;
+        #pragma unroll
+        for (int i = 0; i < 2 + kUnits; ++i) v[i] += atomic_read(&st[i]);
+        #pragma unroll
+        for (int i = 0; i < 2 + kUnits; ++i) st[i] = 0;
     }
+    #pragma unroll
+    for (int i = 0; i < 2 + kUnits; ++i)
+        for (int off = kWave / 2; off > 0; off >>= 1) v[i] += __shfl_xor(v[i], off, kWave);
     if (lane == 0) {
         TraceRec rec;
         rec.c = v[0];
