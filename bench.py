@@ -423,7 +423,7 @@ def main():
 
     same = bool(torch.equal(out_h, out_csr) and torch.equal(out_h, out_t) and torch.equal(out_h, out_h2))
     m = g.m
-    hyb_names = ["keys", "dense-block scan", "dense blocks"]
+    hyb_names = ["keys", "dense-block sample", "dense blocks"]
     res = {
         "metric": "MIS Medges/s per graph at 1 GPU (tile vs CSR); batched graphs/s + p50/p99",
         "value": round(m / step_s / 1e6, 3),
@@ -471,8 +471,8 @@ def main():
                           "equals_key_greedy": res["mis_size"] == q["key_greedy_size"],
                           "source": "tests/golden/rmat22_quality.json"}
     # roofline of the step's dominant kernel (the most time in the step), from HIP events
-    # on the stream it runs on: the dense-block scan (build) or one of the two round
-    # kernels (solve).  Algorithmic bytes per unit (see DESIGN.md): 4 per adjacency
+    # on the stream it runs on: the dense-block build or one of the two round
+    # kernels (solve).  Algorithmic bytes per unit: 4 per adjacency
     # index read, 16 per row examined (row bounds and key or list slot), 36 per 16x16
     # bit tile multiplied, 24 per dense block examined, and the two per-vertex bitmaps
     # (n/8 bytes each) once per launch; the neighbours' class or status lookups are
@@ -487,8 +487,9 @@ def main():
         "hybrid_exclusion": (stt_h["kernel_ms"][1], launches, u[2] * 4 + u[3] * 16 + u[5] * 36 + u[7] * 24 + vec,
                              u[2] * 4),
     }
-    if len(stages) > 1 and stages[1] > 0:   # streams the column indices and the row pointer once
-        cands["hybrid_dense_scan"] = (stages[1], 1, 4 * g.nnz + 8 * (g.n + 1), 0)
+    if len(stages) > 2 and stages[2] > 0 and st_h["tiles"] > 0:   # the dense-block build streams the
+        # column indices and the row pointer once, and writes the tiles
+        cands["hybrid_dense_build"] = (stages[2], 1, 4 * g.nnz + 8 * (g.n + 1) + 36 * st_h["tiles"], 0)
     name = max(cands, key=lambda k: cands[k][0])
     tot_ms, nl, nbytes, gather = cands[name]
     avg_ms = tot_ms / nl

@@ -417,8 +417,9 @@ void mis_session_destroy(mis_session* s);
  * Durations (HOST float[cap], milliseconds, from HIP events on the build stream) of
  * the build stages of a handle built with opts.timing = 1; *count receives the
  * number of stages.  Stages (after validation, which is not timed): keys, then
- *   hybrid path: dense-block scan (the blocks' column signatures), dense blocks
- *                (exact test and bitmaps), and a last empty stage; a dynamic handle
+ *   hybrid path: dense-block sample (column signatures of sampled blocks), dense
+ *                blocks (every block's test and the bitmaps, or only the empty slot
+ *                map when the sample found too few), and a last empty stage; a dynamic handle
  *                (dyn_slack > 0): orientation row search (with clearing the
  *                counts), orientation, and a last empty stage; an empty graph has
  *                the keys stage only;

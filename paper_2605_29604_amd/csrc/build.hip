@@ -672,9 +672,6 @@ size_t layout(GraphCore* g, char* base) {
         }
         if (g->dense_min > 0) {
             const int64_t tcap = nnz / 2 + 1;   // a dense tile holds at least one oriented entry
-            c.take(&g->dflag, (size_t)nI * 4);
-            c.take(&g->dpos, (size_t)(nI + 1) * 4);
-            c.take(&g->dtcnt, (size_t)(nI + 1) * 4);
             c.take(&g->dslot, (size_t)nI * 4);
             c.take(&g->drb, (size_t)nI * 4);
             c.take(&g->dptr, (size_t)(nI + 1) * 4);

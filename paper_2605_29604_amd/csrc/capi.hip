@@ -113,14 +113,7 @@ void staging_put(Staging* st) {
 }
 
 __global__ void k_ctrl_init(Ctrl* ctrl, Meta* smeta, const Meta* meta, int64_t* stripes, int64_t n) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        Ctrl c;
-        memset(&c, 0, sizeof(c));
-        c.alive = n;
-        *ctrl = c;
-        *smeta = *meta;
-    }
-    for (int i = threadIdx.x; i < 2 * kStripes * kStripeWords; i += blockDim.x) stripes[i] = 0;
+    ctrl_reset(ctrl, smeta, meta, stripes, n);
 }
 
 // Checks arguments and resolves automatic options (host-only).
@@ -334,9 +327,9 @@ int64_t unit_bytes(const GraphCore* g, int k) {
 
 int solve_begin(GraphCore* g, hipStream_t s) {
     g->enq_rounds = 0;
+    if (g->path == MIS_PATH_HYBRID) return hyb_init(g, s);   // resets the control block too
     hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(256), 0, s, g->ctrl, g->smeta, g->meta, g->stripes, g->n);
     TC_HIP(hipGetLastError());
-    if (g->path == MIS_PATH_HYBRID) return hyb_init(g, s);
     return g->path == MIS_PATH_TILE ? tile_init(g, s) : csr_init(g, s);
 }
 

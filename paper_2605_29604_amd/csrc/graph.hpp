@@ -1,6 +1,7 @@
 // The opaque handle behind mis_graph, its device workspace layout and the
 // device-side round control block.
 #pragma once
+#include <cstddef>
 #include <atomic>
 #include <type_traits>
 #include <vector>
@@ -63,7 +64,7 @@ struct TraceRec {
 };
 
 // Sizes the build produces on the device (never read back during the build).
-struct Meta {
+struct alignas(8) Meta {
     int32_t ntiles;         // nonzero tiles
     int32_t nvalid;         // adjacency entries kept in tiles
     int64_t nchunks;        // tile path: chunks of the round-1 list
@@ -71,10 +72,12 @@ struct Meta {
     int32_t pad;
     // hybrid path
     int32_t n_dense;        // dense row-blocks (bit tiles)
-    int32_t n_dtiles;       // their tiles
+    int32_t n_dtiles;       // their tiles (the build reserves both in one 64-bit atomic)
     int32_t n_dcand;        // dense candidates among the sampled row-blocks
-    int32_t pad2;
+    int32_t n_done;         // workgroups of the dense-block build that finished
 };
+static_assert(offsetof(Meta, n_dense) % 8 == 0 && offsetof(Meta, n_dtiles) == offsetof(Meta, n_dense) + 4,
+              "n_dense and n_dtiles form one 8-byte word");
 
 }  // namespace tcmis
 
@@ -181,9 +184,6 @@ struct GraphCore {
     int32_t* hoff = nullptr;          // [n] orientation scratch
     int32_t* hcol = nullptr;          // [nnz] oriented entries: row v's are hcol[rp[v] .. rp[v] + hcnt[v])
     int32_t* hcnt = nullptr;          // [n] higher-priority neighbours of each vertex
-    int32_t* dflag = nullptr;         // [nI] dense candidate, then dense, flags
-    int32_t* dpos = nullptr;          // [nI+1] their scan: list slot of each dense row-block
-    int32_t* dtcnt = nullptr;         // [nI+1] tiles per dense row-block -> first tile
     int32_t* dslot = nullptr;         // [nI] list slot of each dense row-block (-1: entry lists)
     int32_t* drb = nullptr;           // [nI] dense row-blocks by list slot
     int32_t* dptr = nullptr;          // [nI+1] first tile of each list slot (slot + 1: the end)

@@ -54,6 +54,7 @@ constexpr int kHSteps = 9;                // 2^kHSteps = kHWin
 constexpr int kHLight = 32;               // rows with at most this many entries take one lane
 constexpr int kP2Words = 8;               // bitmap words a wave takes in round 1's exclusion phase
 constexpr int kGrp = 16;                  // entries a lane loads and compares per step in round 1
+constexpr int kOGrp = 8;                  // entries per step when a round-1 lane writes an H row
 constexpr int kDenseCap = 1024;           // most oriented entries a block may hold to be dense
 constexpr int kDenseTiles = 64;           // most tiles of a dense block (one per lane)
 constexpr int kWpb = kBlock / kWave;
@@ -376,18 +377,6 @@ __global__ void __launch_bounds__(kBlock) k_dense_gate(const int64_t* rp, const 
 // did the sample find enough candidates (1% of the sampled blocks)?
 __device__ inline bool gate_on(const Meta* meta, int samples) { return (int64_t)meta->n_dcand * 100 >= samples; }
 
-// every block, one wave each: dflag[I] = candidate (0 everywhere when the sample
-// found too few)
-__global__ void __launch_bounds__(kBlock) k_block_scan(const int64_t* rp, const int32_t* ci, int64_t n, int64_t nI,
-                                                       int samples, int dense_min, const Meta* meta, int32_t* dflag) {
-    const bool on = gate_on(meta, samples);
-    const int64_t nwaves = (int64_t)gridDim.x * kWpb;
-    for (int64_t I = (int64_t)blockIdx.x * kWpb + threadIdx.x / kWave; I < nI; I += nwaves) {
-        const int c = on ? block_candidate(ci, rp[16 * I], rp[min<int64_t>(16 * I + 16, n)], dense_min) : 0;
-        if (lane_id() == 0) dflag[I] = c;
-    }
-}
-
 // Gathers block I's higher-priority entries (priority comparisons with their rows,
 // lanes taking entries in turn) into sk as (column << 4 | row) keys and sorts them
 // (bitonic, padded with ~0); returns their number, or 0 if there are none or more
@@ -447,63 +436,79 @@ __device__ inline int dense_tiles(const uint64_t* sk, int total) {
     return nt;
 }
 
-// Exact test of the candidates, one wave per block: dflag[I] = 1 and dtcnt[I] = tiles
-// if the block has at most 64 tiles and at least dense_min entries per tile.
-template <bool kUserKeys>
-__global__ void __launch_bounds__(kBlock) k_dense_test(const int64_t* rp, const int32_t* ci, const uint64_t* key,
-                                                       const uint8_t* q8, uint64_t seed, int64_t n, int64_t nI,
-                                                       int dense_min, const Meta* meta, int samples, int32_t* dflag,
-                                                       int32_t* dtcnt) {
-    __shared__ uint64_t skey[kWpb][kDenseCap];
-    __shared__ int32_t srow[kWpb][17];
-    __shared__ uint64_t skv[kWpb][16];
-    __shared__ int32_t scount[kWpb];
-    const int wid = threadIdx.x / kWave;
-    const int64_t nwaves = (int64_t)gridDim.x * kWpb;
-    if (!gate_on(meta, samples)) {   // the flags are all clear: every tile count is 0
-        GRID_STRIDE(I, nI) dtcnt[I] = 0;
-        return;
-    }
-    for (int64_t I = (int64_t)blockIdx.x * kWpb + wid; I < nI; I += nwaves) {
-        bool dense = false;
-        int nt = 0;
-        if (dflag[I]) {
-            const int total = dense_collect<kUserKeys>(rp, ci, key, q8, seed, n, I, skey[wid], srow[wid], skv[wid],
-                                                       &scount[wid]);
-            if (total > 0) {
-                nt = dense_tiles(skey[wid], total);
-                dense = nt <= kDenseTiles && (int64_t)total >= (int64_t)dense_min * nt;
-            }
-        }
-        if (lane_id() == 0) {
-            dflag[I] = dense ? 1 : 0;
-            dtcnt[I] = dense ? nt : 0;
-        }
-    }
-}
+// The dense blocks, a chunk of kDenseChunk consecutive row-blocks per workgroup, one
+// wave per block: the candidate test (block_candidate), the exact test (the block's
+// higher-priority entries sorted in LDS: at most kDenseTiles tiles and at least
+// dense_min entries per tile), list slots and tile ranges reserved with one 64-bit
+// atomic per workgroup that found any (the list order is the order of those atomics;
+// nothing depends on it), the tiles' bitmaps and column blocks, and dslot for every
+// block of the chunk (-1: not dense).  When the sample found too few candidates only
+// dslot is written.  The last workgroup to finish writes the end of the tile ranges.
+constexpr int kDenseChunk = 128;
 
-// Tiles of the dense blocks (dflag set; dpos = their list slots, dtcnt = their first
-// tiles), one wave per block: the sorted keys again, bitmaps built in LDS and written
-// out with the tiles' column blocks and the block's list slot.
 template <bool kUserKeys>
-__global__ void __launch_bounds__(kBlock) k_dense_fill(const int64_t* rp, const int32_t* ci, const uint64_t* key,
-                                                       const uint8_t* q8, uint64_t seed, int64_t n, int64_t nI,
-                                                       const Meta* meta, int samples, const int32_t* dflag,
-                                                       const int32_t* dtcnt, const int32_t* dpos, int32_t* drb,
-                                                       int32_t* dptr, int32_t* dcol, uint32_t* dbits) {
+__global__ void __launch_bounds__(kBlock) k_dense_build(const int64_t* rp, const int32_t* ci, const uint64_t* key,
+                                                        const uint8_t* q8, uint64_t seed, int64_t n, int64_t nI,
+                                                        int dense_min, int samples, Meta* meta, int32_t* drb,
+                                                        int32_t* dptr, int32_t* dcol, uint32_t* dbits,
+                                                        int32_t* dslot) {
     __shared__ uint64_t skey[kWpb][kDenseCap];
     __shared__ uint32_t sbits[kWpb][kDenseTiles * 8];
     __shared__ int32_t srow[kWpb][17];
     __shared__ uint64_t skv[kWpb][16];
     __shared__ int32_t scount[kWpb];
+    __shared__ int32_t snt[kDenseChunk];    // tiles of the chunk's dense blocks (0: not dense)
+    __shared__ int32_t sslot[kDenseChunk];  // their list slots and first tiles within the chunk
+    __shared__ int32_t stile[kDenseChunk];
+    __shared__ int32_t sbase[2];
     const int lane = lane_id(), wid = threadIdx.x / kWave;
+    const int64_t I0 = (int64_t)blockIdx.x * kDenseChunk;
+    const int nb = (int)min<int64_t>(kDenseChunk, nI - I0);
+    if (!gate_on(meta, samples)) {
+        for (int i = threadIdx.x; i < nb; i += kBlock) dslot[I0 + i] = -1;
+        if (blockIdx.x == 0 && threadIdx.x == 0) dptr[0] = 0;
+        return;
+    }
     uint64_t* sk = skey[wid];
-    const int64_t nwaves = (int64_t)gridDim.x * kWpb;
-    if (!gate_on(meta, samples)) return;   // no dense block
-    for (int64_t I = (int64_t)blockIdx.x * kWpb + wid; I < nI; I += nwaves) {
-        if (!dflag[I]) continue;
+    for (int i = wid; i < nb; i += kWpb) {
+        const int64_t I = I0 + i;
+        int nt = 0;
+        if (block_candidate(ci, rp[16 * I], rp[min<int64_t>(16 * I + 16, n)], dense_min)) {
+            const int total = dense_collect<kUserKeys>(rp, ci, key, q8, seed, n, I, sk, srow[wid], skv[wid],
+                                                       &scount[wid]);
+            if (total > 0) {
+                const int t = dense_tiles(sk, total);
+                if (t <= kDenseTiles && (int64_t)total >= (int64_t)dense_min * t) nt = t;
+            }
+        }
+        if (lane == 0) snt[i] = nt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int c = 0, t = 0;
+        for (int i = 0; i < nb; ++i) {
+            sslot[i] = snt[i] ? c : -1;
+            stile[i] = t;
+            c += snt[i] ? 1 : 0;
+            t += snt[i];
+        }
+        // slots and tiles in one 64-bit atomic (n_dense and n_dtiles are adjacent,
+        // the count in the low word), so that consecutive slots own consecutive tile
+        // ranges and dptr[p + 1] - dptr[p] is slot p's tile count
+        const unsigned long long old =
+            c ? atomicAdd(reinterpret_cast<unsigned long long*>(&meta->n_dense),
+                          ((unsigned long long)(uint32_t)t << 32) | (uint32_t)c)
+              : 0ull;
+        sbase[0] = (int32_t)(uint32_t)old;
+        sbase[1] = (int32_t)(old >> 32);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nb; i += kBlock) dslot[I0 + i] = sslot[i] >= 0 ? sbase[0] + sslot[i] : -1;
+    for (int i = wid; i < nb; i += kWpb) {
+        if (!snt[i]) continue;
+        const int64_t I = I0 + i;
         const int total = dense_collect<kUserKeys>(rp, ci, key, q8, seed, n, I, sk, srow[wid], skv[wid], &scount[wid]);
-        const int32_t t0 = dtcnt[I];   // first tile (scanned)
+        const int32_t t0 = sbase[1] + stile[i];   // the block's first tile
         for (int k = lane; k < kDenseTiles * 8; k += kWave) sbits[wid][k] = 0;
         wave_sync_lds();
         int seen = 0;
@@ -525,20 +530,21 @@ __global__ void __launch_bounds__(kBlock) k_dense_fill(const int64_t* rp, const 
         wave_sync_lds();
         for (int k = lane; k < seen * 8; k += kWave) dbits[(int64_t)t0 * 8 + k] = sbits[wid][k];
         if (lane == 0) {
-            const int32_t p = dpos[I];
+            const int32_t p = sbase[0] + sslot[i];
             drb[p] = (int32_t)I;
             dptr[p] = t0;
         }
         wave_sync_lds();
     }
-}
-
-__global__ void k_dense_end(const Meta* meta, int32_t* dptr) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) dptr[meta->n_dense] = meta->n_dtiles;
-}
-
-__global__ void k_dense_slots(const int32_t* dflag, const int32_t* dpos, int64_t nI, int32_t* dslot) {
-    GRID_STRIDE(I, nI) dslot[I] = dflag[I] ? dpos[I] : -1;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();   // this workgroup's reservations and writes before its arrival
+        if (atomicAdd(&meta->n_done, 1) == (int32_t)gridDim.x - 1) {
+            __threadfence();
+            const int32_t nd = __hip_atomic_load(&meta->n_dense, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            dptr[nd] = __hip_atomic_load(&meta->n_dtiles, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
 }
 
 // row capacities of a dynamic handle (each orientation: its degree plus the slack)
@@ -711,17 +717,19 @@ __device__ inline bool scan4(const int32_t* row, int32_t c, const uint32_t* m, i
     return false;
 }
 
-// Round 1 reads a lane's row kGrp entries per step: the step's loads are issued
-// together (a 16-byte load per four entries that start inside the row), then its key
-// or class gathers (one per entry inside the row), then its comparisons.  u[j] =
-// row[k + j] where k + j < c (c: the entries the lane takes), else v itself.  A load
-// may read up to three entries past c (the next rows' entries, replaced by v), so the
-// caller makes sure that row + k + kGrp stays inside the array.
+// Round 1 reads a lane's row N entries per step (N = kGrp for the scans, kOGrp for
+// writing an H row): the step's loads are issued together (a 16-byte load per four
+// entries that start inside the row), then its key or class gathers (one per entry
+// inside the row), then its comparisons.  u[j] = row[k + j] where k + j < c (c: the
+// entries the lane takes), else v itself.  A load may read up to three entries past c
+// (the next rows' entries, replaced by v), so the caller makes sure that row + k + N
+// stays inside the array.
 typedef int32_t i4u __attribute__((ext_vector_type(4), aligned(4)));
 
-__device__ inline void load_grp(const int32_t* __restrict__ row, int k, int c, int32_t v, int32_t (&u)[kGrp]) {
+template <int N>
+__device__ inline void load_grp(const int32_t* __restrict__ row, int k, int c, int32_t v, int32_t (&u)[N]) {
     #pragma unroll
-    for (int i = 0; i < kGrp / 4; ++i) {
+    for (int i = 0; i < N / 4; ++i) {
         i4u x = {v, v, v, v};
         if (k + 4 * i < c) x = *reinterpret_cast<const i4u*>(row + k + 4 * i);
         u[4 * i] = x.x;
@@ -730,18 +738,19 @@ __device__ inline void load_grp(const int32_t* __restrict__ row, int k, int c, i
         u[4 * i + 3] = x.w;
     }
     #pragma unroll
-    for (int j = 0; j < kGrp; ++j) u[j] = k + j < c ? u[j] : v;
+    for (int j = 0; j < N; ++j) u[j] = k + j < c ? u[j] : v;
 }
 
-// Bit j (j < kGrp, k + j < c) is set when u[j] out-ranks v (kv = v's key): the default
+// Bit j (j < N, k + j < c) is set when u[j] out-ranks v (kv = v's key): the default
 // rule gathers the step's class bytes before comparing (a class tie goes to the hash);
 // caller keys are gathered four at a time.
-__device__ inline uint32_t grp_mask(const HybArgs& a, const int32_t (&u)[kGrp], int k, int c, int32_t v,
-                                    uint64_t kv, bool uk) {
+template <int N>
+__device__ inline uint32_t grp_mask(const HybArgs& a, const int32_t (&u)[N], int k, int c, int32_t v, uint64_t kv,
+                                    bool uk) {
     uint32_t h = 0;
     if (uk) {
         #pragma unroll
-        for (int j0 = 0; j0 < kGrp; j0 += 4) {
+        for (int j0 = 0; j0 < N; j0 += 4) {
             uint64_t ku[4];
             #pragma unroll
             for (int j = 0; j < 4; ++j) ku[j] = k + j0 + j < c ? a.key[(uint32_t)u[j0 + j]] : 0ull;
@@ -750,12 +759,12 @@ __device__ inline uint32_t grp_mask(const HybArgs& a, const int32_t (&u)[kGrp], 
         }
         return h;
     }
-    uint32_t q[kGrp];
+    uint32_t q[N];
     #pragma unroll
-    for (int j = 0; j < kGrp; ++j) q[j] = k + j < c ? a.q8[(uint32_t)u[j]] : 0u;
+    for (int j = 0; j < N; ++j) q[j] = k + j < c ? a.q8[(uint32_t)u[j]] : 0u;
     const uint32_t qv = (uint32_t)(kv >> 56);
     #pragma unroll
-    for (int j = 0; j < kGrp; ++j) {
+    for (int j = 0; j < N; ++j) {
         bool b = false;
         if (k + j < c) {
             b = q[j] > qv;
@@ -768,14 +777,33 @@ __device__ inline uint32_t grp_mask(const HybArgs& a, const int32_t (&u)[kGrp], 
 
 // Does one of the entries u[j] (k + j < c) have its bit set in m?  The step's bitmap
 // words are gathered together.
-__device__ inline bool grp_hit(const uint32_t* m, const int32_t (&u)[kGrp], int k, int c) {
-    uint32_t w[kGrp];
+template <int N>
+__device__ inline bool grp_hit(const uint32_t* m, const int32_t (&u)[N], int k, int c) {
+    uint32_t w[N];
     #pragma unroll
-    for (int j = 0; j < kGrp; ++j) w[j] = k + j < c ? m[(uint32_t)u[j] >> 5] : 0u;
+    for (int j = 0; j < N; ++j) w[j] = k + j < c ? m[(uint32_t)u[j] >> 5] : 0u;
     uint32_t h = 0;
     #pragma unroll
-    for (int j = 0; j < kGrp; ++j) h |= w[j] >> (u[j] & 31);
+    for (int j = 0; j < N; ++j) h |= w[j] >> (u[j] & 31);
     return (h & 1u) != 0;
+}
+
+// Does H(v) (c <= kHLight entries at hcol + rp[v]) name a vertex whose bit is set in
+// m?  Static handles: kGrp entries per step, the step's loads and bitmap gathers in
+// flight together (16-byte loads may read three entries past the row, so a row ending
+// within three entries of the array's end takes four at a time, as do the rows of
+// dynamic handles).  *read counts the entries compared.
+__device__ inline bool scan_h(const HybArgs& a, int32_t v, int32_t c, const uint32_t* m, int64_t* read) {
+    const int64_t e0 = a.rp[v];
+    if (a.oriented || e0 + c + 3 > a.nnz) return scan4(a.hcol + e0, c, m, read);
+    bool hit = false;
+    for (int k = 0; k < c && !hit; k += kGrp) {
+        int32_t u[kGrp];
+        load_grp(a.hcol + e0, k, c, v, u);
+        hit = grp_hit(m, u, k, c);
+        *read += min(c - k, kGrp);
+    }
+    return hit;
 }
 
 // Which rounds a build of the phase code serves: any round (the persistent kernel and
@@ -876,7 +904,7 @@ __device__ void hyb_p1(const HybArgs& a, int r, int64_t vb, int64_t nvb) {
                 const int32_t c = a.hcnt[v];
                 if (c > kHLight) { heavy |= 1u << b; continue; }
                 ++verts;
-                if (!scan4(a.hcol + a.rp[v], c, a.A, &ent)) cand |= 1u << b;
+                if (!scan_h(a, v, c, a.A, &ent)) cand |= 1u << b;
             }
             for (uint64_t hb = ballot(heavy != 0); hb; hb = ballot(heavy != 0)) {
                 const int l = __builtin_ctzll(hb);
@@ -953,26 +981,27 @@ __device__ void hyb_p2(const HybArgs& a, int r, int64_t vb, int64_t nvb) {
             const uint32_t rows = own ? list_rows(a, dn, w0 + lane, a.A[w0 + lane]) : 0u;
             const uint32_t sw = own ? a.S[w0 + lane] : 0u;
             if (lane < kP2Words) sdec[wid][lane] = 0;
-            uint32_t ncw[kP2Words], pre[kP2Words + 1];
-            pre[0] = 0;
+            // lanes k < kP2Words: the word's vertices outside S, and how many come
+            // before them in the group
+            const uint32_t nc = rows & ~sw;
+            int incl = __popc(nc);
             #pragma unroll
-            for (int k = 0; k < kP2Words; ++k) {
-                ncw[k] = __builtin_amdgcn_readlane(rows & ~sw, k);
-                pre[k + 1] = pre[k] + __popc(ncw[k]);
+            for (int sh = 1; sh < kP2Words; sh <<= 1) {
+                const int y = __shfl_up(incl, sh, kWave);
+                if (lane >= sh) incl += y;
             }
-            const int total = (int)pre[kP2Words];
+            const int excl = incl - __popc(nc);
+            const int total = __builtin_amdgcn_readlane(incl, kP2Words - 1);
             wave_sync_lds();
             for (int p0 = 0; p0 < total; p0 += kWave) {
-                // the j-th vertex outside S among the group's rows
+                // the j-th vertex outside S among the group's rows: word k, then the bit
                 const int j = p0 + lane;
                 const bool act = j < total;
                 int k = 0;
                 #pragma unroll
-                for (int kk = 1; kk < kP2Words; ++kk) k += (uint32_t)j >= pre[kk] ? 1 : 0;
-                uint32_t x = ncw[0], rank = (uint32_t)j;
-                #pragma unroll
-                for (int kk = 1; kk < kP2Words; ++kk)
-                    if (k == kk) { x = ncw[kk]; rank = (uint32_t)j - pre[kk]; }
+                for (int kk = 1; kk < kP2Words; ++kk) k += j >= __builtin_amdgcn_readlane(excl, kk) ? 1 : 0;
+                uint32_t x = (uint32_t)__shfl((int)nc, k, kWave);
+                uint32_t rank = (uint32_t)(j - __shfl(excl, k, kWave));
                 int pos = 0;   // bit of x with `rank` set bits below it
                 #pragma unroll
                 for (int sh = 16; sh > 0; sh >>= 1) {
@@ -999,12 +1028,12 @@ __device__ void hyb_p2(const HybArgs& a, int r, int64_t vb, int64_t nvb) {
                             int32_t* __restrict__ out = a.hcol + a.rp[v];
                             int32_t m = 0;
                             #pragma nounroll
-                            for (int k = 0; k < c; k += kGrp) {
-                                int32_t u[kGrp];
+                            for (int k = 0; k < c; k += kOGrp) {
+                                int32_t u[kOGrp];
                                 load_grp(a.ci + e0, k, c, v, u);
                                 const uint32_t keep = grp_mask(a, u, k, c, v, kv, uk);
                                 #pragma unroll
-                                for (int j = 0; j < kGrp; ++j)
+                                for (int j = 0; j < kOGrp; ++j)
                                     if ((keep >> j) & 1u) out[m++] = u[j];
                             }
                             a.hcnt[v] = m;
@@ -1110,7 +1139,7 @@ __device__ void hyb_p2(const HybArgs& a, int r, int64_t vb, int64_t nvb) {
                 const int32_t c = a.hcnt[v];
                 if (c > kHLight) { heavy |= 1u << b; continue; }
                 ++verts;
-                if (scan4(a.hcol + a.rp[v], c, a.S, &ent)) { dec |= 1u << b; ++n_out; }
+                if (scan_h(a, v, c, a.S, &ent)) { dec |= 1u << b; ++n_out; }
             }
             for (uint64_t hb = ballot(heavy != 0); hb; hb = ballot(heavy != 0)) {
                 const int l = __builtin_ctzll(hb);
@@ -1218,6 +1247,24 @@ __global__ void __launch_bounds__(kBlock) k_hyb_init(const int32_t* hcnt, int64_
     hyb_init_body(hcnt, n, S, A, dround, stripes, blockIdx.x, gridDim.x);
 }
 
+__global__ void k_hyb_ctrl(Ctrl* ctrl, Meta* smeta, const Meta* meta, int64_t* stripes, int64_t n) {
+    ctrl_reset(ctrl, smeta, meta, stripes, n);
+}
+
+// Round state of a static handle solved alone before round 1, a thread per bitmap
+// word: nothing in the set, every vertex undecided; workgroup 0 also resets the
+// control block and the counter stripes.
+__global__ void __launch_bounds__(kBlock) k_hyb_init_words(Ctrl* ctrl, Meta* smeta, const Meta* meta,
+                                                           int64_t* stripes, int64_t n, uint32_t* S, uint32_t* A) {
+    if (blockIdx.x == 0) ctrl_reset(ctrl, smeta, meta, stripes, n);
+    const int64_t nw = (n + 31) >> 5;
+    GRID_STRIDE(w, nw) {
+        const int64_t left = n - w * 32;
+        S[w] = 0;
+        A[w] = left >= 32 ? ~0u : (1u << left) - 1u;
+    }
+}
+
 // in_set[v] = S(v); with `gate`, only once every vertex is decided
 __global__ void k_hyb_output(const Ctrl* gate, const uint32_t* S, int64_t n, uint8_t* in_set) {
     if (gate && gate->alive != 0) return;
@@ -1313,39 +1360,22 @@ int build_hybrid(mis_graph* g, hipStream_t s) {
     const bool dense = g->dense_min > 0 && nnz > 0;
     const int64_t stride = std::max<int64_t>(1, nI / kGateSamples);
     const int samples = (int)std::min<int64_t>(kGateSamples, ceil_div(nI, stride));
-    if (dense) {
+    if (dense)
         hipLaunchKernelGGL(k_dense_gate, dim3((unsigned)ceil_div(kGateSamples, kWpb)), dim3(kBlock), 0, s,
                            g->row_ptr, g->col_idx, n, nI, stride, g->dense_min, g->meta);
-        const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(nI, kWpb), 16384);
-        hipLaunchKernelGGL(k_block_scan, dim3(blocks), dim3(kBlock), 0, s, g->row_ptr, g->col_idx, n, nI, samples,
-                           g->dense_min, g->meta, g->dflag);
-        TC_HIP(hipGetLastError());
-    }
+    TC_HIP(hipGetLastError());
     build_mark(g, s);
     if (dense) {
-        const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(nI, kWpb), 16384);
+        const dim3 grid((unsigned)ceil_div(nI, kDenseChunk));
         if (g->user_keys)
-            hipLaunchKernelGGL(k_dense_test<true>, dim3(blocks), dim3(kBlock), 0, s, g->row_ptr, g->col_idx, g->key,
-                               g->q8, g->seed, n, nI, g->dense_min, g->meta, samples, g->dflag, g->dtcnt);
+            hipLaunchKernelGGL(k_dense_build<true>, grid, dim3(kBlock), 0, s, g->row_ptr, g->col_idx, g->key, g->q8,
+                               g->seed, n, nI, g->dense_min, samples, g->meta, g->drb, g->dptr, g->dcol, g->dbits,
+                               g->dslot);
         else
-            hipLaunchKernelGGL(k_dense_test<false>, dim3(blocks), dim3(kBlock), 0, s, g->row_ptr, g->col_idx, g->key,
-                               g->q8, g->seed, n, nI, g->dense_min, g->meta, samples, g->dflag, g->dtcnt);
+            hipLaunchKernelGGL(k_dense_build<false>, grid, dim3(kBlock), 0, s, g->row_ptr, g->col_idx, g->key, g->q8,
+                               g->seed, n, nI, g->dense_min, samples, g->meta, g->drb, g->dptr, g->dcol, g->dbits,
+                               g->dslot);
         TC_HIP(hipGetLastError());
-        // list slots of the dense blocks and their first tiles (dflag keeps the flags)
-        TC_CHECK(scan_excl_i32(g->dflag, g->dpos, nI, &g->meta->n_dense, (int32_t*)g->scan_tmp, s));
-        TC_CHECK(scan_excl_i32(g->dtcnt, g->dtcnt, nI, &g->meta->n_dtiles, (int32_t*)g->scan_tmp, s));
-        if (g->user_keys)
-            hipLaunchKernelGGL(k_dense_fill<true>, dim3(blocks), dim3(kBlock), 0, s, g->row_ptr, g->col_idx, g->key,
-                               g->q8, g->seed, n, nI, g->meta, samples, g->dflag, g->dtcnt, g->dpos, g->drb, g->dptr,
-                               g->dcol, g->dbits);
-        else
-            hipLaunchKernelGGL(k_dense_fill<false>, dim3(blocks), dim3(kBlock), 0, s, g->row_ptr, g->col_idx, g->key,
-                               g->q8, g->seed, n, nI, g->meta, samples, g->dflag, g->dtcnt, g->dpos, g->drb, g->dptr,
-                               g->dcol, g->dbits);
-        TC_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_dense_end, dim3(1), dim3(1), 0, s, g->meta, g->dptr);
-        TC_HIP(hipGetLastError());
-        HLAUNCH(k_dense_slots, nI, g->dflag, g->dpos, nI, g->dslot);
     }
     build_mark(g, s);
     build_mark(g, s);
@@ -1353,6 +1383,14 @@ int build_hybrid(mis_graph* g, hipStream_t s) {
 }
 
 int hyb_init(GraphCore* g, hipStream_t s) {
+    if (g->dyn_slack == 0 && g->count == 0) {   // one launch: a thread per bitmap word
+        hipLaunchKernelGGL(k_hyb_init_words, dim3(stream_grid(ceil_div(g->n, 32))), dim3(kBlock), 0, s, g->ctrl,
+                           g->smeta, g->meta, g->stripes, g->n, g->hS, g->hA);
+        TC_HIP(hipGetLastError());
+        return MIS_OK;
+    }
+    hipLaunchKernelGGL(k_hyb_ctrl, dim3(1), dim3(256), 0, s, g->ctrl, g->smeta, g->meta, g->stripes, g->n);
+    TC_HIP(hipGetLastError());
     if (g->n > 0)
         hipLaunchKernelGGL(k_hyb_init, dim3(stream_grid(g->n)), dim3(kBlock), 0, s,
                            g->dyn_slack > 0 ? g->hcnt : nullptr, g->n, g->hS, g->hA,

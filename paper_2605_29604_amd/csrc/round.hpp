@@ -89,6 +89,19 @@ __device__ inline void close_round(Ctrl* ctrl, int64_t* stripes, TraceRec* trace
     }
 }
 
+// Before round 1: the control block (alive = n, the rest zero), the round's copy of
+// the build sizes, and the counter stripes.  Every thread of one workgroup calls it.
+__device__ inline void ctrl_reset(Ctrl* ctrl, Meta* smeta, const Meta* meta, int64_t* stripes, int64_t n) {
+    if (threadIdx.x == 0) {
+        Ctrl c;
+        memset(&c, 0, sizeof(c));
+        c.alive = n;
+        *ctrl = c;
+        *smeta = *meta;
+    }
+    for (int i = threadIdx.x; i < 2 * kStripes * kStripeWords; i += blockDim.x) stripes[i] = 0;
+}
+
 // Round prologue run by the first wave of round r's first kernel: closes round
 // r-1 and empties the lists that round r's last kernel fills.
 __device__ inline void open_round(Ctrl* ctrl, int64_t* stripes, TraceRec* trace, int r, int64_t blk = -1) {

@@ -7,7 +7,7 @@ FETCH_SIZE / WRITE_SIZE calibrate the counters against bytes actually moved.
 
 With --summarize-kernel RECORD FETCH_DIR WRITE_DIR it writes the per-launch traffic
 record of one hybrid-path kernel (RECORD: hybrid_candidate, hybrid_exclusion,
-hybrid_dense_scan).
+hybrid_dense_build).
 
 With --summarize FETCH_DIR WRITE_DIR (the output folders of one FETCH_SIZE and one
 WRITE_SIZE run of this program) it reads the counters instead, on any machine, and
@@ -320,7 +320,7 @@ Average per launch: {sum(per) / len(per) / 1e6:.2f} MB.
 HYBRID_KERNELS = {
     "hybrid_candidate": ("k_hyb_p1", ("hyb.hip", "round.hpp", "graph.hpp")),
     "hybrid_exclusion": ("k_hyb_p2", ("hyb.hip", "round.hpp", "graph.hpp")),
-    "hybrid_dense_scan": ("k_block_scan", ("hyb.hip", "graph.hpp")),
+    "hybrid_dense_build": ("k_dense_build", ("hyb.hip", "graph.hpp")),
 }
 
 
