@@ -387,7 +387,8 @@ int build_into(mis_graph* g, const mis_csr* csr, const mis_build_opts& o, int32_
     int dev = 0, cus = 256;
     TC_HIP(hipGetDevice(&dev));
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    g->grid_blocks = std::max(1, cus) * (o.blocks_per_cu ? o.blocks_per_cu : 8);
+    g->cus = std::max(1, cus);
+    g->grid_blocks = g->cus * (o.blocks_per_cu ? o.blocks_per_cu : 8);
     int rc = MIS_OK;
     if (count > 0 && hipMemcpyAsync(g->goff, offsets, (size_t)(count + 1) * 8, hipMemcpyHostToDevice, s) != hipSuccess)
         rc = fail(MIS_EHIP, "copy of the batch offsets failed");

@@ -106,6 +106,7 @@ struct GraphCore {
 
     bool btiming = false;             // build-stage events (opts.timing = 1)
     int grid_blocks = 2048;           // persistent grid of the round kernels
+    int cus = 256;                    // compute units of the device the handle was built on
     int64_t enq_rounds = 0;           // rounds enqueued since the solve began (host side)
     int coop_blocks = 0;              // grid of the cooperative round kernels (sized at build)
 

@@ -5,6 +5,9 @@ FETCH_SIZE / WRITE_SIZE calibrate the counters against bytes actually moved.
 
     python paper_2605_29604_amd/profile_run.py [--workload rmat22] [--copy-mib 256] [--path hybrid]
 
+With --summarize-stats DIR NAME BENCH_JSON it writes profiles/NAME.md from one
+rocprofv3 --kernel-trace --stats run of bench.py (DIR) and that run's JSON line.
+
 With --summarize-kernel RECORD FETCH_DIR WRITE_DIR it writes the per-launch traffic
 record of one hybrid-path kernel (RECORD: hybrid_candidate, hybrid_exclusion,
 hybrid_dense_build).
@@ -386,6 +389,88 @@ above.  `{os.path.basename(base)}.json` holds the figures with the SHA-256 of th
     return 0
 
 
+def _short(name: str) -> str:
+    name = name.replace("tcmis::(anonymous namespace)::", "").replace("void ", "")
+    return name.split("(")[0]
+
+
+def summarize_stats(a) -> int:
+    """Kernel statistics of one `rocprofv3 --kernel-trace --stats` run of bench.py (the
+    hybrid path's default workload): the per-kernel table, one build + solve step from
+    the trace, and the roofline kernel's average launch from the trace beside the one
+    bench.py measured with HIP events in the same command (its JSON line)."""
+    folder, name, bench_json = a.summarize_stats
+    with open(os.path.join(folder, "run_kernel_stats.csv")) as fh:
+        stats = list(csv.DictReader(fh))
+    with open(os.path.join(folder, "run_kernel_trace.csv")) as fh:
+        trace = sorted(csv.DictReader(fh), key=lambda r: int(r["Start_Timestamp"]))
+    bench = {}
+    with open(bench_json) as fh:
+        for line in fh:
+            if line.startswith("{"):
+                bench = json.loads(line)
+    rows = "\n".join(f"| `{_short(r['Name'])}` | {int(r['Calls'])} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.3f} | {float(r['Percentage']):.2f} |" for r in stats[:40])
+    # one step: from the second k_keys launch to the first report copy after it
+    keys = [i for i, r in enumerate(trace) if _short(r["Kernel_Name"]) == "k_keys"]
+    step = []
+    if len(keys) > 1:
+        for r in trace[keys[1]:]:
+            step.append(r)
+            if "copyBuffer" in r["Kernel_Name"] and len(step) > 1:
+                break
+    t0 = int(step[0]["Start_Timestamp"]) if step else 0
+    t1 = int(step[-1]["End_Timestamp"]) if step else 0
+    busy = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in step)
+    srows = "\n".join(f"| `{_short(r['Kernel_Name'])}` | {int(r['Grid_Size_X'])} | "
+                      f"{(int(r['End_Timestamp']) - int(r['Start_Timestamp'])) / 1e3:.1f} |" for r in step)
+    roof = bench.get("roofline", {})
+    sym = {"hybrid_candidate": "k_hyb_p1", "hybrid_exclusion": "k_hyb_p2", "hybrid_dense_build": "k_dense_build"}
+    k = roof.get("kernel", "")
+    durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in trace
+            if k in sym and _short(r["Kernel_Name"]).startswith(sym[k])]
+    cmp_line = ""
+    if durs:
+        cmp_line = (f"The roofline kernel `{k}` (`{sym[k]}`, every round): {len(durs)} launches in the trace, "
+                    f"{sum(durs) / len(durs):.1f} µs on average; bench.py's HIP-event figure in the same "
+                    f"command (one timed solve, {roof.get('launches')} launches): {roof.get('avg_launch_us')} µs.")
+    md = f"""# {bench.get('config', {}).get('workload', a.workload)}: kernel statistics of the benchmark run (hybrid path)
+
+Command (run from /tmp; REPO = the repository root, OUT = a directory for the output):
+
+```
+rocprofv3 --kernel-trace --stats --output-format csv -d $OUT/stats -o run -- \\
+    python3 $REPO/bench.py --steps 3 --warmup 1 --no-cpu --no-batch --no-serve --no-tune > $OUT/bench.json
+python3 paper_2605_29604_amd/profile_run.py --summarize-stats $OUT/stats {name} $OUT/bench.json
+```
+
+The run times build + solve steps of the hybrid path, solve-only repeats, one solve with per-kernel HIP
+events, the all-tile and CSR paths the same way, and the three launch modes, so call counts are multiples
+of the repeats.  Durations from the kernel trace; the benchmark's own line (step {bench.get('ms_per_step')} ms
+under the profiler) is measured again without it at the end of every round.
+
+| Kernel | Calls | Avg µs | Total ms | % |
+|---|---:|---:|---:|---:|
+{rows}
+
+{cmp_line}
+
+## One build + solve step from the trace
+
+The second hybrid build + solve of the trace, from `k_keys` to the solve's report copy: {len(step)}
+launches, {busy / 1e3:.1f} µs of kernel time in a span of {(t1 - t0) / 1e3:.1f} µs.
+
+| Kernel | Grid (threads) | µs |
+|---|---:|---:|
+{srows}
+"""
+    out = os.path.join(ROOT, "profiles", f"{name}.md")
+    with open(out, "w") as fh:
+        fh.write(md)
+    print(out)
+    return 0
+
+
 def main() -> int:
     p = argparse.ArgumentParser()
     p.add_argument("--workload", default="rmat22")
@@ -398,11 +483,14 @@ def main() -> int:
     p.add_argument("--summarize-stalls", metavar="DIR")
     p.add_argument("--summarize-build", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     p.add_argument("--summarize-kernel", nargs=3, metavar=("RECORD", "FETCH_DIR", "WRITE_DIR"))
+    p.add_argument("--summarize-stats", nargs=3, metavar=("DIR", "NAME", "BENCH_JSON"))
     p.add_argument("--path", default="tile", choices=("tile", "hybrid"))
     p.add_argument("--dense-min", type=int, default=0)
     a = p.parse_args()
     if a.summarize_kernel:
         return summarize_kernel(a)
+    if a.summarize_stats:
+        return summarize_stats(a)
     if a.summarize:
         return summarize(a)
     if a.summarize_mfma:
