@@ -98,9 +98,6 @@ __global__ void k_orient_rows(const int64_t* rp, int64_t n, int64_t nnz, int64_t
     }
 }
 
-// a column block's bit in a row-block's 64-bit signature
-__device__ inline uint64_t sig_bit(int64_t J) { return 1ull << (((uint64_t)J * 0x9E3779B97F4A7C15ull) >> 58); }
-
 // does column u out-rank row v?  kUserKeys: compare the keys; else the default key
 // rule: the degree class decides unless it ties, then the hash of the graph-local
 // id, then the id (kv is row v's whole key, so its class, hash and local id are known)
