@@ -100,7 +100,8 @@ __device__ inline uint64_t key_class(int rule, int64_t deg, int64_t gn, int64_t 
 }
 
 __global__ void k_keys(const int64_t* rp, int64_t n, uint64_t seed, const int64_t* goff, int64_t count, int rule,
-                       uint64_t* key, uint64_t* sk, uint8_t* q8) {
+                       uint64_t* key, uint64_t* sk, uint8_t* q8, Meta* meta) {
+    if (meta && blockIdx.x == 0 && threadIdx.x == 0) *meta = Meta{};   // the hybrid build's sizes start at 0
     GRID_STRIDE(v, n) {
         const int64_t deg = rp[v + 1] - rp[v];
         int64_t lv = v, gn = n, gnnz = rp[n] - rp[0];
@@ -759,8 +760,9 @@ int build_keys(mis_graph* g, const mis_build_opts* o, hipStream_t s) {
     } else {
         // the key order of one graph with default keys: the sort keys come with the keys
         uint64_t* sk = g->path == MIS_PATH_TILE && default_keys_in_order(g) ? g->sk : nullptr;
+        const bool hyb = g->path == MIS_PATH_HYBRID;
         LAUNCH(k_keys, g->n, g->row_ptr, g->n, o->seed, g->goff, (int64_t)g->count, o->key_rule, g->key, sk,
-               g->path == MIS_PATH_HYBRID ? g->q8 : nullptr);
+               hyb ? g->q8 : nullptr, hyb ? g->meta : nullptr);
     }
     return MIS_OK;
 }

@@ -53,7 +53,7 @@ constexpr int kHWin = 512;                // rows a workgroup stages in LDS
 constexpr int kHSteps = 9;                // 2^kHSteps = kHWin
 constexpr int kHLight = 32;               // rows with at most this many entries take one lane
 constexpr int kP2Words = 8;               // bitmap words a wave takes in round 1's exclusion phase
-constexpr int kGrp = 16;                  // entries a lane loads and compares per step in round 1
+constexpr int kGrp = 16;                  // entries per step of a later round's scan of an H row
 constexpr int kOGrp = 8;                  // entries per step when a round-1 lane writes an H row
 constexpr int kDenseCap = 1024;           // most oriented entries a block may hold to be dense
 constexpr int kDenseTiles = 64;           // most tiles of a dense block (one per lane)
@@ -725,6 +725,7 @@ typedef int32_t i4u __attribute__((ext_vector_type(4), aligned(4)));
 
 template <int N>
 __device__ inline void load_grp(const int32_t* __restrict__ row, int k, int c, int32_t v, int32_t (&u)[N]) {
+    static_assert(N % 4 == 0, "a step loads whole groups of four entries");
     #pragma unroll
     for (int i = 0; i < N / 4; ++i) {
         i4u x = {v, v, v, v};
@@ -783,6 +784,29 @@ __device__ inline bool grp_hit(const uint32_t* m, const int32_t (&u)[N], int k, 
     #pragma unroll
     for (int j = 0; j < N; ++j) h |= w[j] >> (u[j] & 31);
     return (h & 1u) != 0;
+}
+
+// One step of a round-1 scan: entries [K, K + N) of a row of c (<= kHLight) entries.
+// Round 1 takes a row in steps of 4, 12 and 16 entries: most rows of low-priority
+// vertices meet a higher neighbour, and most rows outside S a neighbour in S, among
+// their first few entries, so a short first step saves gathers, while the longer
+// later steps keep the dependent steps of the other rows few.  *ent counts the
+// entries compared.
+template <int K, int N>
+__device__ inline bool r1_higher(const HybArgs& a, const int32_t* row, int c, int32_t v, uint64_t kv, bool uk,
+                                 int64_t* ent) {
+    int32_t u[N];
+    load_grp(row, K, c, v, u);
+    *ent += min(c - K, N);
+    return grp_mask(a, u, K, c, v, kv, uk) != 0;
+}
+
+template <int K, int N>
+__device__ inline bool r1_in_s(const HybArgs& a, const int32_t* row, int c, int32_t v, int64_t* ent) {
+    int32_t u[N];
+    load_grp(row, K, c, v, u);
+    *ent += min(c - K, N);
+    return grp_hit(a.S, u, K, c);
 }
 
 // Does H(v) (c <= kHLight entries at hcol + rp[v]) name a vertex whose bit is set in
@@ -852,12 +876,10 @@ __device__ void hyb_p1(const HybArgs& a, int r, int64_t vb, int64_t nvb) {
                 ++verts;
                 if (d > 0 && e0 + kHLight <= a.nnz) {
                     const int c = (int)min<int64_t>(d, kHLight);
-                    for (int k = 0; k < c && !found; k += kGrp) {
-                        int32_t u[kGrp];
-                        load_grp(a.ci + e0, k, c, v, u);
-                        found = grp_mask(a, u, k, c, v, kv, uk) != 0;
-                        ent += min(c - k, kGrp);
-                    }
+                    const int32_t* row = a.ci + e0;
+                    found = r1_higher<0, 4>(a, row, c, v, kv, uk, &ent);
+                    if (!found && c > 4) found = r1_higher<4, 12>(a, row, c, v, kv, uk, &ent);
+                    if (!found && c > 16) found = r1_higher<16, 16>(a, row, c, v, kv, uk, &ent);
                     k0 = kHLight;
                 }
             }
@@ -1014,12 +1036,10 @@ __device__ void hyb_p2(const HybArgs& a, int r, int64_t vb, int64_t nvb) {
                     ++verts;
                     if (e0 + kHLight <= a.nnz) {
                         const int c = (int)min<int64_t>(d, kHLight);
-                        for (int k = 0; k < c && !hit; k += kGrp) {
-                            int32_t u[kGrp];
-                            load_grp(a.ci + e0, k, c, v, u);
-                            hit = grp_hit(a.S, u, k, c);
-                            ent += min(c - k, kGrp);
-                        }
+                        const int32_t* row = a.ci + e0;
+                        hit = r1_in_s<0, 4>(a, row, c, v, &ent);
+                        if (!hit && c > 4) hit = r1_in_s<4, 12>(a, row, c, v, &ent);
+                        if (!hit && c > 16) hit = r1_in_s<16, 16>(a, row, c, v, &ent);
                         if (!hit && d <= kHLight) {   // undecided: write H(v)
                             const uint64_t kv = a.key[v];
                             int32_t* __restrict__ out = a.hcol + a.rp[v];
@@ -1324,7 +1344,8 @@ int64_t hyb_blocks(int64_t nnz) { return ceil_div(nnz, kHE); }
 
 int build_hybrid(mis_graph* g, hipStream_t s) {
     const int64_t n = g->n, nnz = g->nnz, nI = g->nI;
-    TC_HIP(hipMemsetAsync(g->meta, 0, sizeof(Meta), s));
+    // the key kernel cleared meta unless the keys came from the caller (or n = 0)
+    if (g->user_keys || n == 0) TC_HIP(hipMemsetAsync(g->meta, 0, sizeof(Meta), s));
     if (n == 0) return MIS_OK;
     g->hrp = g->row_ptr;
     if (g->dyn_slack > 0) {
