@@ -423,7 +423,7 @@ def main():
 
     same = bool(torch.equal(out_h, out_csr) and torch.equal(out_h, out_t) and torch.equal(out_h, out_h2))
     m = g.m
-    hyb_names = ["keys", "dense-block sample", "dense blocks"]
+    hyb_names = ["keys and dense-block sample", "dense blocks"]
     res = {
         "metric": "MIS Medges/s per graph at 1 GPU (tile vs CSR); batched graphs/s + p50/p99",
         "value": round(m / step_s / 1e6, 3),
@@ -487,9 +487,9 @@ def main():
         "hybrid_exclusion": (stt_h["kernel_ms"][1], launches, u[2] * 4 + u[3] * 16 + u[5] * 36 + u[7] * 24 + vec,
                              u[2] * 4),
     }
-    if len(stages) > 2 and stages[2] > 0 and st_h["tiles"] > 0:   # the dense-block build streams the
+    if len(stages) > 1 and stages[1] > 0 and st_h["tiles"] > 0:   # the dense-block build streams the
         # column indices and the row pointer once, and writes the tiles
-        cands["hybrid_dense_build"] = (stages[2], 1, 4 * g.nnz + 8 * (g.n + 1) + 36 * st_h["tiles"], 0)
+        cands["hybrid_dense_build"] = (stages[1], 1, 4 * g.nnz + 8 * (g.n + 1) + 36 * st_h["tiles"], 0)
     name = max(cands, key=lambda k: cands[k][0])
     tot_ms, nl, nbytes, gather = cands[name]
     avg_ms = tot_ms / nl

@@ -417,12 +417,11 @@ void mis_session_destroy(mis_session* s);
  * Durations (HOST float[cap], milliseconds, from HIP events on the build stream) of
  * the build stages of a handle built with opts.timing = 1; *count receives the
  * number of stages.  Stages (after validation, which is not timed): keys, then
- *   hybrid path: dense-block sample (column signatures of sampled blocks), dense
- *                blocks (every block's test and the bitmaps, or only the empty slot
- *                map when the sample found too few), and a last empty stage; a dynamic handle
- *                (dyn_slack > 0): orientation row search (with clearing the
- *                counts), orientation, and a last empty stage; an empty graph has
- *                the keys stage only;
+ *   hybrid path: dense blocks (every block's test and the bitmaps, or only the
+ *                empty slot map when the sample of blocks the key stage takes found
+ *                too few), then empty stages; a dynamic handle (dyn_slack > 0):
+ *                orientation row search (with clearing the counts), orientation,
+ *                then empty stages; an empty graph has the keys stage only;
  *   tile path:   vertex order, tiles;
  *   CSR path:    vertex lists.
  * Synchronises the last event.  Errors: MIS_EINVAL (no timing), MIS_EHIP.

@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <vector>
 
+#include "dense.hpp"
 #include "graph.hpp"
 
 namespace tcmis {
@@ -99,8 +100,11 @@ __device__ inline uint64_t key_class(int rule, int64_t deg, int64_t gn, int64_t 
     return (uint64_t)(q < 255 ? q : 255);
 }
 
+// With `samp` (hybrid path with dense blocks) the kernel's waves also take the
+// dense-block sample (dense.hpp), sparing the build a launch.
 __global__ void k_keys(const int64_t* rp, int64_t n, uint64_t seed, const int64_t* goff, int64_t count, int rule,
-                       uint64_t* key, uint64_t* sk, uint8_t* q8, Meta* meta) {
+                       uint64_t* key, uint64_t* sk, uint8_t* q8, Meta* meta, const int32_t* ci, int64_t stride,
+                       int samples, int dense_min, int32_t* samp) {
     if (meta && blockIdx.x == 0 && threadIdx.x == 0) *meta = Meta{};   // the hybrid build's sizes start at 0
     GRID_STRIDE(v, n) {
         const int64_t deg = rp[v + 1] - rp[v];
@@ -118,6 +122,9 @@ __global__ void k_keys(const int64_t* rp, int64_t n, uint64_t seed, const int64_
         if (sk) sk[n - 1 - v] = ~k;
         if (q8) q8[v] = (uint8_t)q;
     }
+    if (samp)
+        dense_sample(rp, ci, n, stride, samples, dense_min, samp, ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave,
+                     (int64_t)gridDim.x * blockDim.x / kWave);
 }
 
 // Every kernel that fixes the vertex order also writes ndeg[p], the degree of the
@@ -673,6 +680,7 @@ size_t layout(GraphCore* g, char* base) {
         }
         if (g->dense_min > 0) {
             const int64_t tcap = nnz / 2 + 1;   // a dense tile holds at least one oriented entry
+            c.take(&g->dsamp, (size_t)kGateSamples * 4);
             c.take(&g->dslot, (size_t)nI * 4);
             c.take(&g->drb, (size_t)nI * 4);
             c.take(&g->dptr, (size_t)(nI + 1) * 4);
@@ -761,8 +769,10 @@ int build_keys(mis_graph* g, const mis_build_opts* o, hipStream_t s) {
         // the key order of one graph with default keys: the sort keys come with the keys
         uint64_t* sk = g->path == MIS_PATH_TILE && default_keys_in_order(g) ? g->sk : nullptr;
         const bool hyb = g->path == MIS_PATH_HYBRID;
+        const bool sample = hyb && g->dense_min > 0 && g->nnz > 0;   // the dense-block sample
         LAUNCH(k_keys, g->n, g->row_ptr, g->n, o->seed, g->goff, (int64_t)g->count, o->key_rule, g->key, sk,
-               hyb ? g->q8 : nullptr, hyb ? g->meta : nullptr);
+               hyb ? g->q8 : nullptr, hyb ? g->meta : nullptr, g->col_idx, dense_stride(g->nI),
+               dense_samples(g->nI), g->dense_min, sample ? g->dsamp : nullptr);
     }
     return MIS_OK;
 }

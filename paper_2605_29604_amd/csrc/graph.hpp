@@ -185,6 +185,7 @@ struct GraphCore {
     int32_t* hoff = nullptr;          // [n] orientation scratch
     int32_t* hcol = nullptr;          // [nnz] oriented entries: row v's are hcol[rp[v] .. rp[v] + hcnt[v])
     int32_t* hcnt = nullptr;          // [n] higher-priority neighbours of each vertex
+    int32_t* dsamp = nullptr;         // [kGateSamples] the dense-block sample's candidate flags
     int32_t* dslot = nullptr;         // [nI] list slot of each dense row-block (-1: entry lists)
     int32_t* drb = nullptr;           // [nI] dense row-blocks by list slot
     int32_t* dptr = nullptr;          // [nI+1] first tile of each list slot (slot + 1: the end)

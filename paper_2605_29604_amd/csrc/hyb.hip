@@ -42,6 +42,7 @@
 //       alive bit; the rest go to the next round's lists.
 // P1 only reads alive and writes S; P2 only reads S and writes alive; every hand-over
 // crosses a kernel boundary (or a grid barrier in the persistent kernel).
+#include "dense.hpp"
 #include "round.hpp"
 
 namespace tcmis {
@@ -55,8 +56,6 @@ constexpr int kHLight = 32;               // rows with at most this many entries
 constexpr int kP2Words = 8;               // bitmap words a wave takes in round 1's exclusion phase
 constexpr int kGrp = 16;                  // entries per step of a later round's scan of an H row
 constexpr int kOGrp = 8;                  // entries per step when a round-1 lane writes an H row
-constexpr int kDenseCap = 1024;           // most oriented entries a block may hold to be dense
-constexpr int kDenseTiles = 64;           // most tiles of a dense block (one per lane)
 constexpr int kWpb = kBlock / kWave;
 
 typedef int v4i __attribute__((ext_vector_type(4)));
@@ -306,73 +305,14 @@ __global__ void __launch_bounds__(kBlock) k_orient(const int64_t* rp, const int3
     }
 }
 
-// ---- dense blocks
-//
-// A block is examined exactly only if its whole adjacency looks concentrated: a
-// wave ORs a 256-bit signature of its entries' column blocks, and linear counting
-// (-256 ln(1 - bits / 256)) estimates its distinct column blocks, i.e. its nonzero
-// tiles.  Its higher-priority half must average dense_min entries per tile, so a
-// block is a candidate when its entries reach dense_min times that estimate (a factor
-// of two of slack) and it has at most 2 * kDenseCap entries.  A sample of blocks
-// decides first whether the graph has such blocks at all (at least 1% of the
-// sample); if not, the full scan only clears the flags.  These tests only choose the
-// representation; the results never depend on them.
-constexpr int kGateSamples = 1024;
+// ---- dense blocks (the candidate test and the sample are in dense.hpp)
 
-__device__ inline int sig_index(int64_t J) { return (int)(((uint64_t)J * 0x9E3779B97F4A7C15ull) >> 56); }
-
-// 1 if block I (entries [b0, b1)) is a dense candidate; every lane of the wave calls it
-__device__ inline int block_candidate(const int32_t* ci, int64_t b0, int64_t b1, int dense_min) {
-    const int64_t tot = b1 - b0;
-    if (tot == 0 || tot > 2 * kDenseCap) return 0;
-    uint64_t s[4] = {0, 0, 0, 0};
-    for (int64_t e = b0 + lane_id(); e < b1; e += 4 * kWave) {
-        int32_t u[4];
-        #pragma unroll
-        for (int j = 0; j < 4; ++j) u[j] = e + j * kWave < b1 ? ci[e + j * kWave] : -1;
-        #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if (u[j] < 0) continue;
-            const int k = sig_index(u[j] >> 4);
-            const uint64_t bit = 1ull << (k & 63);
-            if (k < 64) s[0] |= bit;
-            else if (k < 128) s[1] |= bit;
-            else if (k < 192) s[2] |= bit;
-            else s[3] |= bit;
-        }
-    }
-    int bits = 0;
-    #pragma unroll
-    for (int w = 0; w < 4; ++w) {
-        for (int off = kWave / 2; off > 0; off >>= 1) s[w] |= __shfl_xor(s[w], off, kWave);
-        bits += __popcll(s[w]);
-    }
-    if (bits >= 256) return 0;
-    const float est = -256.0f * logf(1.0f - (float)bits / 256.0f);
-    return est <= 2.0f * kDenseTiles && (float)tot >= (float)dense_min * est ? 1 : 0;
+// the sample when the keys came from the caller (the key kernel takes it otherwise)
+__global__ void __launch_bounds__(kBlock) k_dense_sample(const int64_t* rp, const int32_t* ci, int64_t n,
+                                                         int64_t stride, int samples, int dense_min, int32_t* samp) {
+    dense_sample(rp, ci, n, stride, samples, dense_min, samp, ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave,
+                 (int64_t)gridDim.x * kWpb);
 }
-
-// the sample: every stride-th block, one wave each; candidates counted into meta->n_dcand
-__global__ void __launch_bounds__(kBlock) k_dense_gate(const int64_t* rp, const int32_t* ci, int64_t n, int64_t nI,
-                                                       int64_t stride, int dense_min, Meta* meta) {
-    __shared__ int32_t part[kWpb];
-    const int wid = threadIdx.x / kWave;
-    const int64_t i = (int64_t)blockIdx.x * kWpb + wid;
-    const int64_t I = i * stride;
-    int c = 0;
-    if (i < kGateSamples && I < nI)
-        c = block_candidate(ci, rp[16 * I], rp[min<int64_t>(16 * I + 16, n)], dense_min);
-    if (lane_id() == 0) part[wid] = c;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int t = 0;
-        for (int q = 0; q < kWpb; ++q) t += part[q];
-        if (t) atomicAdd(&meta->n_dcand, t);
-    }
-}
-
-// did the sample find enough candidates (1% of the sampled blocks)?
-__device__ inline bool gate_on(const Meta* meta, int samples) { return (int64_t)meta->n_dcand * 100 >= samples; }
 
 // Gathers block I's higher-priority entries (priority comparisons with their rows,
 // lanes taking entries in turn) into sk as (column << 4 | row) keys and sorts them
@@ -446,8 +386,8 @@ constexpr int kDenseChunk = 128;
 template <bool kUserKeys>
 __global__ void __launch_bounds__(kBlock) k_dense_build(const int64_t* rp, const int32_t* ci, const uint64_t* key,
                                                         const uint8_t* q8, uint64_t seed, int64_t n, int64_t nI,
-                                                        int dense_min, int samples, Meta* meta, int32_t* drb,
-                                                        int32_t* dptr, int32_t* dcol, uint32_t* dbits,
+                                                        int dense_min, const int32_t* samp, int samples, Meta* meta,
+                                                        int32_t* drb, int32_t* dptr, int32_t* dcol, uint32_t* dbits,
                                                         int32_t* dslot) {
     __shared__ uint64_t skey[kWpb][kDenseCap];
     __shared__ uint32_t sbits[kWpb][kDenseTiles * 8];
@@ -458,10 +398,20 @@ __global__ void __launch_bounds__(kBlock) k_dense_build(const int64_t* rp, const
     __shared__ int32_t sslot[kDenseChunk];  // their list slots and first tiles within the chunk
     __shared__ int32_t stile[kDenseChunk];
     __shared__ int32_t sbase[2];
+    __shared__ int32_t scand[kWpb];
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     const int64_t I0 = (int64_t)blockIdx.x * kDenseChunk;
     const int nb = (int)min<int64_t>(kDenseChunk, nI - I0);
-    if (!gate_on(meta, samples)) {
+    // the sample's verdict: at least 1% of the sampled blocks are candidates
+    int cand = 0;
+    for (int i = threadIdx.x; i < samples; i += kBlock) cand += samp[i];
+    for (int off = kWave / 2; off > 0; off >>= 1) cand += __shfl_xor(cand, off, kWave);
+    if (lane == 0) scand[wid] = cand;
+    __syncthreads();
+    cand = 0;
+    for (int q = 0; q < kWpb; ++q) cand += scand[q];
+    if (blockIdx.x == 0 && threadIdx.x == 0) meta->n_dcand = cand;
+    if ((int64_t)cand * 100 < samples) {
         for (int i = threadIdx.x; i < nb; i += kBlock) dslot[I0 + i] = -1;
         if (blockIdx.x == 0 && threadIdx.x == 0) dptr[0] = 0;
         return;
@@ -1373,28 +1323,28 @@ int build_hybrid(mis_graph* g, hipStream_t s) {
         build_mark(g, s);
         return MIS_OK;
     }
-    // static handle: the dense blocks only (stages: dense-block scan, dense blocks,
-    // none); everything else is read from the caller's CSR by round 1
+    // static handle: the dense blocks only (stages: dense blocks, then empty ones, as
+    // many as a dynamic handle has; the key kernel took the dense-block sample);
+    // everything else is read from the caller's CSR by round 1
     const bool dense = g->dense_min > 0 && nnz > 0;
-    const int64_t stride = std::max<int64_t>(1, nI / kGateSamples);
-    const int samples = (int)std::min<int64_t>(kGateSamples, ceil_div(nI, stride));
-    if (dense)
-        hipLaunchKernelGGL(k_dense_gate, dim3((unsigned)ceil_div(kGateSamples, kWpb)), dim3(kBlock), 0, s,
-                           g->row_ptr, g->col_idx, n, nI, stride, g->dense_min, g->meta);
-    TC_HIP(hipGetLastError());
-    build_mark(g, s);
     if (dense) {
+        const int64_t stride = dense_stride(nI);
+        const int samples = dense_samples(nI);
+        if (g->user_keys)   // no key kernel ran
+            hipLaunchKernelGGL(k_dense_sample, dim3((unsigned)ceil_div(samples, kWpb)), dim3(kBlock), 0, s,
+                               g->row_ptr, g->col_idx, n, stride, samples, g->dense_min, g->dsamp);
         const dim3 grid((unsigned)ceil_div(nI, kDenseChunk));
         if (g->user_keys)
             hipLaunchKernelGGL(k_dense_build<true>, grid, dim3(kBlock), 0, s, g->row_ptr, g->col_idx, g->key, g->q8,
-                               g->seed, n, nI, g->dense_min, samples, g->meta, g->drb, g->dptr, g->dcol, g->dbits,
-                               g->dslot);
+                               g->seed, n, nI, g->dense_min, g->dsamp, samples, g->meta, g->drb, g->dptr, g->dcol,
+                               g->dbits, g->dslot);
         else
             hipLaunchKernelGGL(k_dense_build<false>, grid, dim3(kBlock), 0, s, g->row_ptr, g->col_idx, g->key, g->q8,
-                               g->seed, n, nI, g->dense_min, samples, g->meta, g->drb, g->dptr, g->dcol, g->dbits,
-                               g->dslot);
+                               g->seed, n, nI, g->dense_min, g->dsamp, samples, g->meta, g->drb, g->dptr, g->dcol,
+                               g->dbits, g->dslot);
         TC_HIP(hipGetLastError());
     }
+    build_mark(g, s);
     build_mark(g, s);
     build_mark(g, s);
     return MIS_OK;
