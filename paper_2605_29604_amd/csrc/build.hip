@@ -621,6 +621,8 @@ size_t layout_state(GraphCore* g, char* base, bool with_trace) {
         const int64_t nI = ceil_div(n, 16), nw = ceil_div(n, 64) * 2 + 2;   // bitmap words (whole waves)
         c.take(&g->hA, (size_t)nw * 4);
         c.take(&g->hS, (size_t)nw * 4);
+        if (g->dyn_slack == 0) c.take(&g->hblk, (size_t)n * 4);
+        else g->hblk = nullptr;
         for (int b = 0; b < 2; ++b) c.take(&g->hdact[b], (size_t)(g->dense_min > 0 ? nI : 0) * 4);
         if (g->count > 0) c.take(&g->dround, (size_t)n * 4);
     } else if (g->path == MIS_PATH_CSR) {

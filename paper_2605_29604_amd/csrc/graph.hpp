@@ -193,6 +193,8 @@ struct GraphCore {
     uint32_t* dbits = nullptr;        // [tile cap * 8] 16x16 bitmaps (word w: rows 2w, 2w+1)
     uint32_t* hA = nullptr;           // [nw] undecided vertices (bitmap)
     uint32_t* hS = nullptr;           // [nw] vertices in the set (bitmap)
+    int32_t* hblk = nullptr;          // [n] static handles, round 1: the first higher-priority
+                                      // neighbour phase 1 met (vertices that have one)
     int32_t* hdact[2] = {nullptr, nullptr};   // dense blocks still undecided, by round parity
     const int64_t* hrp = nullptr;     // row starts of hcol (the input row pointer, or drp)
 

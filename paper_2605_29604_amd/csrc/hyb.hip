@@ -516,6 +516,7 @@ struct HybArgs {
     int oriented;             // H of every vertex was built (dynamic handles)
     uint32_t* A;
     uint32_t* S;
+    int32_t* blk;             // round 1: a vertex's first higher-priority neighbour (nullptr: none kept)
     const int32_t* drb;       // round 1: the dense blocks (round 1 visits every vertex otherwise)
     int32_t* dact[2];         // dense blocks still undecided, listed by round parity for the next round
     int64_t nI;               // 16-row blocks
@@ -742,13 +743,19 @@ __device__ inline bool grp_hit(const uint32_t* m, const int32_t (&u)[N], int k, 
 // their first few entries, so a short first step saves gathers, while the longer
 // later steps keep the dependent steps of the other rows few.  *ent counts the
 // entries compared.
+// r1_higher returns the first entry of the step that out-ranks v, or -1.
 template <int K, int N>
-__device__ inline bool r1_higher(const HybArgs& a, const int32_t* row, int c, int32_t v, uint64_t kv, bool uk,
-                                 int64_t* ent) {
+__device__ inline int32_t r1_higher(const HybArgs& a, const int32_t* row, int c, int32_t v, uint64_t kv, bool uk,
+                                    int64_t* ent) {
     int32_t u[N];
     load_grp(row, K, c, v, u);
     *ent += min(c - K, N);
-    return grp_mask(a, u, K, c, v, kv, uk) != 0;
+    const uint32_t h = grp_mask(a, u, K, c, v, kv, uk);
+    int32_t b = -1;
+    #pragma unroll
+    for (int j = N - 1; j >= 0; --j)
+        if ((h >> j) & 1u) b = u[j];
+    return b;
 }
 
 template <int K, int N>
@@ -827,9 +834,11 @@ __device__ void hyb_p1(const HybArgs& a, int r, int64_t vb, int64_t nvb) {
                 if (d > 0 && e0 + kHLight <= a.nnz) {
                     const int c = (int)min<int64_t>(d, kHLight);
                     const int32_t* row = a.ci + e0;
-                    found = r1_higher<0, 4>(a, row, c, v, kv, uk, &ent);
-                    if (!found && c > 4) found = r1_higher<4, 12>(a, row, c, v, kv, uk, &ent);
-                    if (!found && c > 16) found = r1_higher<16, 16>(a, row, c, v, kv, uk, &ent);
+                    int32_t b = r1_higher<0, 4>(a, row, c, v, kv, uk, &ent);
+                    if (b < 0 && c > 4) b = r1_higher<4, 12>(a, row, c, v, kv, uk, &ent);
+                    if (b < 0 && c > 16) b = r1_higher<16, 16>(a, row, c, v, kv, uk, &ent);
+                    found = b >= 0;
+                    if (found && a.blk) a.blk[v] = b;   // phase 2 looks at it first
                     k0 = kHLight;
                 }
             }
@@ -848,8 +857,15 @@ __device__ void hyb_p1(const HybArgs& a, int r, int64_t vb, int64_t nvb) {
                 bool blocked = false;
                 int64_t k = k0h;
                 for (; k < dh; k += kWave) {
-                    const bool b = k + lane < dh && hi(a, a.ci[e0h + k + lane], vh, kvh);
-                    if (ballot(b)) { blocked = true; k += kWave; break; }
+                    const int32_t u = k + lane < dh ? a.ci[e0h + k + lane] : -1;
+                    const uint64_t bm = ballot(u >= 0 && hi(a, u, vh, kvh));
+                    if (bm) {
+                        blocked = true;
+                        const int32_t ub = __shfl(u, __builtin_ctzll(bm), kWave);
+                        if (lane == 0 && a.blk) a.blk[vh] = ub;
+                        k += kWave;
+                        break;
+                    }
                 }
                 if (lane == 0) {
                     ent += min(k, dh) - k0h;
@@ -981,10 +997,14 @@ __device__ void hyb_p2(const HybArgs& a, int r, int64_t vb, int64_t nvb) {
                 int64_t e0 = 0, d = 0, k0 = 0;
                 bool hit = false;
                 if (act) {   // d >= 1: a vertex without neighbours is a candidate
+                    // the higher-priority neighbour phase 1 met first is most often a
+                    // candidate: its S bit alone decides, with no row read
+                    const int32_t blk = a.blk ? a.blk[v] : -1;
                     e0 = a.crp[v];
                     d = a.crp[v + 1] - e0;
                     ++verts;
-                    if (e0 + kHLight <= a.nnz) {
+                    hit = blk >= 0 && bit_of(a.S, blk);
+                    if (!hit && e0 + kHLight <= a.nnz) {
                         const int c = (int)min<int64_t>(d, kHLight);
                         const int32_t* row = a.ci + e0;
                         hit = r1_in_s<0, 4>(a, row, c, v, &ent);
@@ -1267,6 +1287,7 @@ HybArgs make_args(GraphCore* g) {
     a.oriented = g->dyn_slack > 0 ? 1 : 0;
     a.A = g->hA;
     a.S = g->hS;
+    a.blk = g->hblk;
     a.drb = g->drb;
     for (int b = 0; b < 2; ++b) a.dact[b] = g->hdact[b];
     a.nI = ceil_div(g->n, 16);

@@ -126,6 +126,47 @@ def test_edge_cases(cfg):
     check(rp, ci, cfg, label="matching")
 
 
+def heavy_tail_graph(seed):
+    """Hubs of degree 33 .. 300 (rows longer than a lane's 32 entries), ordinary
+    vertices of degree 1 .. 40, isolated vertices, and last vertices whose rows end the
+    adjacency array (fewer than 32 entries after their starts)."""
+    rng = np.random.default_rng(seed)
+    n = 3000
+    edges = set()
+    for h in range(12):                      # hubs 0 .. 11
+        for v in rng.choice(np.arange(12, n - 200), size=33 + 24 * h, replace=False):
+            edges.add((h, int(v)))
+    for v in range(12, n - 200):             # ordinary rows; every 7th vertex stays isolated
+        if v % 7 == 0:
+            continue
+        for w in rng.choice(np.arange(12, n - 200), size=int(rng.integers(1, 6)), replace=False):
+            if int(w) != v and int(w) % 7:
+                edges.add((min(v, int(w)), max(v, int(w))))
+    for t in range(1, 6):                    # the last rows of the array
+        for w in rng.choice(np.arange(0, n - 6), size=3 * t, replace=False):
+            if int(w) % 7 or int(w) < 12:
+                edges.add((int(w), n - t))
+    return csr_from_edges(n, sorted(edges))
+
+
+@pytest.mark.parametrize("cfg", HYBRID_CONFIGS + [("csr", 0, "none", 0)], ids=lambda c: "-".join(map(str, c)))
+@pytest.mark.parametrize("keys", ["degree", "random", "hubs_first"])
+def test_round1_heavy_and_last_rows(cfg, keys):
+    # round 1 takes a row's first 32 entries on its lane and longer rows with the whole
+    # wave; rows among the array's last 32 entries take the wave path from their start;
+    # caller keys go through the key-gather variant of the round-1 kernels
+    rp, ci = heavy_tail_graph(11)
+    n = len(rp) - 1
+    rng = np.random.default_rng(5)
+    k = None
+    if keys == "random":
+        k = np.array(rng.permutation(n) + 1, dtype=np.uint64) * np.uint64(0x9E3779B97F4A7C15 >> 16)
+    elif keys == "hubs_first":   # hubs out-rank everything: candidates after scanning whole long rows
+        k = np.array(rng.permutation(n) + 1, dtype=np.uint64)
+        k[:12] = np.uint64(1 << 40) + np.arange(12, dtype=np.uint64)
+    check(rp, ci, cfg, keys=k, label=f"heavy_tail_{keys}")
+
+
 @pytest.mark.parametrize("cfg", FAST_CONFIGS, ids=lambda c: "-".join(map(str, c)))
 def test_deep_path_custom_keys(cfg):
     # keys increase along a path: ceil(n/2) rounds, two decisions per round
