@@ -15,31 +15,34 @@
 //
 // Build of a static handle (no reordering, no sort, no pass that compares every
 // edge):
-//   1. keys and the one-byte degree class q(v) of every vertex (k_keys);
-//   2. dense blocks (optional): one streaming pass over the adjacency ORs, per
-//      16-row block, a signature bit of each entry's column block; a block with at
-//      least dense_min entries per signature bit is a candidate.  A wave per
-//      candidate orients its entries (priority comparisons), sorts them in LDS and
-//      counts its nonzero tiles; a block whose higher-priority entries average at
+//   1. keys and the one-byte degree class q(v) of every vertex; the same kernel's
+//      waves take a sample of 1024 16-row blocks (k_keys, dense.hpp);
+//   2. dense blocks (optional; only the empty slot map unless 1% of the sample
+//      qualified): a wave per block ORs a signature bit of each entry's column
+//      block; a block with at least dense_min entries per estimated tile is a
+//      candidate, whose entries the wave orients (priority comparisons), sorts in
+//      LDS and counts in tiles; a block whose higher-priority entries average at
 //      least dense_min per tile (at most 64 tiles) is written as bitmaps.
 // Round 1 then reads the caller's CSR directly: Phase 1 compares each vertex's
-// neighbours with it until one out-ranks it (the degree class decides most pairs
-// from the 1-byte table, a tie rebuilds the neighbour's hash in registers), Phase 2
-// scans for a candidate neighbour; only the vertices still undecided after round 1
-// are oriented (their H rows written to hcol[rp[v] ..]) and listed for round 2.  On
-// the R-MAT workload that is about a tenth of the entries a full orientation reads.
+// neighbours with it until one out-ranks it, in steps of 4, 12 and 16 entries (the
+// degree class decides most pairs from the 1-byte table, a tie rebuilds the
+// neighbour's hash in registers) and keeps the neighbour that blocked it; Phase 2
+// tests that neighbour's S bit, else scans for a candidate neighbour; only the
+// vertices still undecided after round 1 are oriented (their H rows written to
+// hcol[rp[v] ..]).  On the R-MAT workload that is about a tenth of the entries a
+// full orientation reads.
 //
 // A dynamic handle (edges inserted and deleted later) orients every edge at build
 // time instead (k_orient: both orientations, with slack per row), and its round 1
 // starts from the counts of higher-priority neighbours.
 //
-// Round r (two kernels):
-//   P1  listed rows: scan H(v) for an alive neighbour (early exit); dense blocks:
+// Round r >= 2 (two kernels, a thread per 32-bit word of the alive bitmap):
+//   P1  alive rows: scan H(v) for an alive neighbour (early exit); dense blocks:
 //       blocked rows = H x alive on the matrix cores (int8 x int8 -> int32, exact);
 //       candidates set their S bit.
-//   P2  listed rows: S(v) -> IN; else scan H(v) for an S neighbour -> OUT; dense
+//   P2  alive rows: S(v) -> IN; else scan H(v) for an S neighbour -> OUT; dense
 //       blocks: N_c = H x S on the matrix cores.  Decided vertices clear their
-//       alive bit; the rest go to the next round's lists.
+//       alive bit; undecided dense blocks go to the next round's list.
 // P1 only reads alive and writes S; P2 only reads S and writes alive; every hand-over
 // crosses a kernel boundary (or a grid barrier in the persistent kernel).
 #include "dense.hpp"

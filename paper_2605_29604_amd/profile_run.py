@@ -53,6 +53,22 @@ def _counter(folder: str, name: str, kernel: str):
     return copy, vals
 
 
+def _gather_fetch(folder: str):
+    """FETCH_SIZE (KiB) of the calibration gather: the first dispatch after the first
+    device copy whose kernel is torch's indexing kernel, or None."""
+    seen_copy = False
+    with open(os.path.join(folder, "run_counter_collection.csv")) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] != "FETCH_SIZE":
+                continue
+            k = r["Kernel_Name"]
+            if "__amd_rocclr_copyBuffer" in k:
+                seen_copy = True
+            elif seen_copy and ("index" in k.lower() or "gather" in k.lower()):
+                return float(r["Counter_Value"])
+    return None
+
+
 def _dispatches(folder: str, kernel: str):
     """{dispatch id: (duration ns, {counter: value})} of every dispatch of `kernel`."""
     out = {}
@@ -273,6 +289,13 @@ def summarize(a) -> int:
     moved = a.copy_mib * 1024.0
     ff, wf = moved / cf, moved / cw
     per = [(f * ff + w * wf) * 1024.0 for f, w in zip(fetch, write)]
+    # a random 4-byte gather: FETCH_SIZE bytes it reads beyond its index stream
+    gk = _gather_fetch(fdir)
+    gather = None
+    if gk is not None:
+        line = (gk * 1024.0 - a.gathers * 8 / ff) / a.gathers
+        gather = {"gathers": a.gathers, "array_mib": a.gather_mib, "fetch_kib": gk,
+                  "fetch_bytes_per_gather": line, "scaled_bytes_per_gather": line * ff}
     sha = _sources_sha()
     rec = {"kernel": "tile_exclusion_mfma", "symbol": kernel, "workload": a.workload, "seed": 1, "tile": a.tile,
            "reorder": a.reorder, "orient": a.orient, "dispatches": len(per), "fetch_kib": fetch, "write_kib": write,
@@ -340,6 +363,13 @@ def summarize_kernel(a) -> int:
     moved = a.copy_mib * 1024.0
     ff, wf = moved / cf, moved / cw
     per = [(f * ff + w * wf) * 1024.0 for f, w in zip(fetch, write)]
+    # a random 4-byte gather: FETCH_SIZE bytes it reads beyond its index stream
+    gk = _gather_fetch(fdir)
+    gather = None
+    if gk is not None:
+        line = (gk * 1024.0 - a.gathers * 8 / ff) / a.gathers
+        gather = {"gathers": a.gathers, "array_mib": a.gather_mib, "fetch_kib": gk,
+                  "fetch_bytes_per_gather": line, "scaled_bytes_per_gather": line * ff}
     sha = {}
     for name in sources:
         with open(os.path.join(ROOT, "paper_2605_29604_amd", "csrc", name), "rb") as fh:
@@ -348,13 +378,19 @@ def summarize_kernel(a) -> int:
            "dispatches": len(per), "fetch_kib": fetch, "write_kib": write, "copy_mib": a.copy_mib,
            "copy_fetch_kib": cf, "copy_write_kib": cw, "fetch_factor": ff, "write_factor": wf,
            "traffic_bytes_per_dispatch": per, "traffic_bytes_per_launch": sum(per) / len(per),
-           "source_sha256": sha}
+           "gather_calibration": gather, "source_sha256": sha}
     base = os.path.join(ROOT, "profiles", f"{record}_{a.workload}_traffic")
     with open(base + ".json", "w") as fh:
         json.dump(rec, fh, indent=1)
         fh.write("\n")
     rows = "\n".join(f"| {i + 1} | {f:.1f} | {w:.1f} | {b / 1e6:.2f} MB |"
                      for i, (f, w, b) in enumerate(zip(fetch, write, per)))
+    gtext = ""
+    if gather is not None:
+        gtext = (f"\n\nGather calibration: {a.gathers} random 4-byte reads from a {a.gather_mib} MiB array (far larger "
+                 f"than the\nInfinity Cache) read {gather['fetch_bytes_per_gather']:.1f} bytes of FETCH_SIZE each beyond "
+                 f"their index stream\n({gather['scaled_bytes_per_gather']:.1f} bytes after the copy's factor): what one "
+                 f"isolated gather that misses every cache costs\nin these counters.")
     md = f"""# {a.workload}: HBM traffic of `{symbol}` (FETCH_SIZE / WRITE_SIZE)
 
 Commands (two passes, one counter each, run from /tmp; REPO = the repository root, OUT = a directory for
@@ -380,7 +416,7 @@ moved each way, so FETCH_SIZE is scaled by {ff:.4f} and WRITE_SIZE by {wf:.4f}.
 
 Average per launch: {sum(per) / len(per) / 1e6:.2f} MB.  These counters count lines moved between the L2
 and the memory fabric, which includes hits in the 256 MB Infinity Cache, so they bound HBM traffic from
-above.  `{os.path.basename(base)}.json` holds the figures with the SHA-256 of the kernel's sources;
+above.{gtext}  `{os.path.basename(base)}.json` holds the figures with the SHA-256 of the kernel's sources;
 `bench.py` reports them (`roofline.traffic`) only while those sources are unchanged.
 """
     with open(base + ".md", "w") as fh:
@@ -478,6 +514,8 @@ def main() -> int:
     p.add_argument("--reorder", default="key")
     p.add_argument("--orient", type=int, default=1)
     p.add_argument("--copy-mib", type=int, default=256)
+    p.add_argument("--gather-mib", type=int, default=2048)
+    p.add_argument("--gathers", type=int, default=1 << 22)
     p.add_argument("--summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     p.add_argument("--summarize-mfma", metavar="DIR")
     p.add_argument("--summarize-stalls", metavar="DIR")
@@ -512,6 +550,17 @@ def main() -> int:
     print(f"copy {a.copy_mib} MiB", flush=True)
     dst.copy_(src)
     torch.cuda.synchronize()
+    del src, dst
+    if a.gather_mib > 0:   # random 4-byte gathers of known count from a large array
+        big = torch.zeros(a.gather_mib << 18, dtype=torch.int32, device="cuda")
+        gen_ = torch.Generator(device="cuda")
+        gen_.manual_seed(1)
+        idx = torch.randint(0, big.numel(), (a.gathers,), device="cuda", generator=gen_)
+        torch.cuda.synchronize()
+        print(f"gather {a.gathers} x 4 B from {a.gather_mib} MiB", flush=True)
+        picked = big[idx]
+        torch.cuda.synchronize()
+        del big, idx, picked
     if a.path == "hybrid":
         print("hybrid build + solve", flush=True)
         h = tcmis.mis_build_tiles(rp, ci, path="hybrid", dense_min=a.dense_min, seed=1, launch="direct")
