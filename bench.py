@@ -14,6 +14,11 @@ the all-tile path (every edge in reordered bit tiles) and the scalar CSR path on
 same graph, per-kernel HIP-event timings, the roofline of the step's dominant
 kernel, and the CPU oracle and sequential greedy timed on this host.
 
+"configs": the 10,000-vertex Erdos-Renyi graph (hybrid and CSR paths) and the 256^3
+7-point mesh with 1% long-range pairs (hybrid, CSR, and the all-tile path at 16x16 and
+32x32 tiles in natural and RCM order, with tile density and the exclusion kernel's
+fraction of the HBM roofline); every leg's set is compared with the first leg's.
+
 "batch": 4,096 independent graphs (sizes log-uniform over 500..200,000 vertices,
 half Erdos-Renyi with average degree 4..32, half R-MAT with 8..24) solved as one
 block-diagonal batch (mis_build_batch + mis_solve_union) against one graph per
@@ -27,6 +32,7 @@ and p50/p99 latency from arrival to result in host memory (H2D, build, solve, D2
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rmat22]
                        [--batch-graphs 4096] [--serve-requests 2000] [--no-batch] [--no-serve]
+                       [--no-configs] [--no-tune] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -94,6 +100,7 @@ def parse():
     p.add_argument("--serve-pool", type=int, default=48)
     p.add_argument("--serve-live", type=int, default=8)
     p.add_argument("--no-tune", action="store_true")
+    p.add_argument("--no-configs", action="store_true", help="skip the er10k and grid256 legs")
     return p.parse_args()
 
 
@@ -105,15 +112,99 @@ def pct(x, q):
     return round(float(np.percentile(np.asarray(x), q)), 3) if len(x) else None
 
 
-def bench_tune(a, torch, gen, tcmis, rp, ci):
+def path_leg(torch, tcmis, rp, ci, n, m, cfg, steps, warmup):
+    """One configuration on one resident graph: the build + solve step (workspace and
+    output allocated once), solve only (structure built once), and one more solve with
+    per-kernel HIP events on the solve stream."""
+    ws = torch.empty(tcmis.mis_build_bytes(n, int(ci.numel()), **cfg), dtype=torch.uint8, device="cuda")
+    out = torch.empty(n, dtype=torch.uint8, device="cuda")
+
+    def one():
+        h = tcmis.mis_build_tiles(rp, ci, workspace=ws, **cfg)
+        _, st = tcmis.mis_solve(h, out=out, trace_cap=0)
+        tcmis.mis_free_tiles(h)
+        return st
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        st = one()
+    torch.cuda.synchronize()
+    step = (time.perf_counter() - t) / steps
+    h = tcmis.mis_build_tiles(rp, ci, workspace=ws, **cfg)
+    tcmis.mis_solve(h, out=out, trace_cap=0)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        tcmis.mis_solve(h, out=out, trace_cap=0)
+    torch.cuda.synchronize()
+    solve = (time.perf_counter() - t) / steps
+    _, stt = tcmis.mis_solve(h, out=out, timing=True, trace_cap=0)
+    tcmis.mis_free_tiles(h)
+    rec = {"step_ms": round(step * 1e3, 4), "step_medges_s": round(m / step / 1e6, 1),
+           "solve_ms": round(solve * 1e3, 4), "solve_medges_s": round(m / solve / 1e6, 1),
+           "rounds": st["rounds"], "kernel_ms": [round(x, 4) for x in stt["kernel_ms"]]}
+    if cfg["path"] == "tile":
+        t_ = st["tile"]
+        ents = int(ci.numel()) // (2 if cfg.get("orient", 1) else 1)
+        rec["tiles"] = st["tiles"]
+        rec["density_nnz_per_tile"] = round(ents / max(1, st["tiles"]), 3)
+        # exclusion kernel against the HBM roofline with the per-solve bytes of the
+        # tile stream: T*T/8 bitmap + 4-byte column block per multiplied tile, and the
+        # two per-vertex bitmaps once per launch
+        u = stt["units"]
+        xb = u[3] * (t_ * t_ // 8 + 4) + max(1, stt["launches"]) * (n // 4)
+        if stt["kernel_ms"][1] > 0:
+            gbs = xb / (stt["kernel_ms"][1] * 1e-3) / 1e9
+            rec["exclusion"] = {"alg_bytes": int(xb), "achieved_gbs": round(gbs, 1),
+                                "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    elif cfg["path"] == "hybrid":
+        rec["dense_tiles"] = st["tiles"]
+    return rec, out.clone()
+
+
+def bench_configs(a, torch, gen, tcmis, grid):
+    """The other single-graph workloads: the 10,000-vertex Erdos-Renyi graph (hybrid and
+    CSR paths; launch-bound at this size) and the 256^3 mesh with 1% long-range pairs
+    (hybrid, CSR, and the all-tile path at 16x16 and 32x32 in natural and RCM order,
+    with tile density and the exclusion kernel's roofline fraction)."""
+    res = {}
+    legs = [("hybrid", dict(path="hybrid", seed=a.seed)), ("csr", dict(path="csr", seed=a.seed))]
+    cases = [("er10k", gen.workload("er10k", seed=1), list(legs), 20, 5)]
+    for t_ in (16, 32):
+        for order in ("none", "rcm"):
+            legs.append((f"tile{t_}_{'natural' if order == 'none' else order}",
+                         dict(path="tile", tile=t_, reorder=order, orient=1, seed=a.seed)))
+    cases.append(("grid256", grid, legs, 3, 1))
+    for name, g, legs_, steps, warmup in cases:
+        rp = torch.from_numpy(g.row_ptr).cuda()
+        ci = torch.from_numpy(g.col_idx).cuda()
+        rec = {"n": g.n, "edges": g.m}
+        first = None
+        agree = True
+        for leg, cfg in legs_:
+            r, o = path_leg(torch, tcmis, rp, ci, g.n, g.m, cfg, steps, warmup)
+            if first is None:
+                first = o
+            else:
+                agree = agree and bool(torch.equal(first, o))
+            rec[leg] = r
+            log(f"{name} {leg}: {r}")
+        rec["paths_agree"] = agree
+        res[name] = rec
+        del rp, ci
+        torch.cuda.empty_cache()
+    return res
+
+
+def bench_tune(a, torch, gen, tcmis, rp, ci, grid):
     """The autotuner's pick (path, tile size, order, workgroups per CU) for the R-MAT
     graph and for the 256^3 mesh, with the build + solve time of the pick."""
     out = {}
     tcmis.mis_autotune_clear()
     cases = [(a.workload, rp, ci)]
-    t0 = time.perf_counter()
-    grid = gen.workload("grid256", seed=1)
-    log(f"autotune: grid256 generated in {time.perf_counter() - t0:.1f}s")
     cases.append(("grid256", torch.from_numpy(grid.row_ptr).cuda(), torch.from_numpy(grid.col_idx).cuda()))
     for name, r, c in cases:
         t = time.perf_counter()
@@ -132,11 +223,11 @@ def bench_tune(a, torch, gen, tcmis, rp, ci):
         torch.cuda.synchronize()
         step = (time.perf_counter() - t) / 3
         edges = c.numel() // 2
-        out[name] = {"pick": {k: opts[k] for k in ("path", "tile", "reorder", "orient", "blocks_per_cu")},
+        out[name] = {"pick": {k: opts[k] for k in ("path", "tile", "reorder", "orient", "blocks_per_cu", "dense_min")},
                      "tune_s": round(tune_s, 3), "step_ms": round(step * 1e3, 4),
                      "step_medges_s": round(edges / step / 1e6, 1)}
         log(f"autotune {name}: {out[name]}")
-    del cases, grid
+    del cases
     torch.cuda.empty_cache()
     return out
 
@@ -512,8 +603,16 @@ def main():
         modes[launch] = {"solve_ms": round(lt * 1e3, 4), "same_set": bool(torch.equal(lo, out_h)),
                          "graph_flag": lst["graph"]}
     res["launch_modes"] = modes
+    grid = None
+    if not (a.no_tune and a.no_configs):
+        t0 = time.perf_counter()
+        grid = gen.workload("grid256", seed=1)
+        log(f"grid256 generated in {time.perf_counter() - t0:.1f}s")
+    if not a.no_configs:
+        res["configs"] = bench_configs(a, torch, gen, tcmis, grid)
     if not a.no_tune:
-        res["autotune"] = bench_tune(a, torch, gen, tcmis, rp, ci)
+        res["autotune"] = bench_tune(a, torch, gen, tcmis, rp, ci, grid)
+    del grid
 
     if not a.no_batch:
         res["batch"] = bench_batch(a, torch, gen, tcmis)

@@ -121,8 +121,9 @@ typedef struct {
     int32_t dense_min;        /* hybrid path: a 16-row block whose higher-priority edges average at
                                  least this many per nonzero 16 x 16 tile (and fit 64 tiles) is
                                  stored as bit tiles, every other block as entry lists.
-                                 0 = default (9: a 36-byte tile then costs no more than the
-                                 entries' 4-byte indices), -1 = entry lists only */
+                                 0 = default (16; a 36-byte tile costs no more bytes than 9
+                                 4-byte indices, but blocks near that break-even run faster
+                                 as lists), -1 = entry lists only */
     int32_t key_rule;         /* default priority rule when keys == NULL (MIS_KEY_*; Section 3.3) */
     int32_t timing;           /* 1 = record HIP events between the build's stages on the build
                                  stream (read them with mis_build_times) */

@@ -15,7 +15,11 @@ constexpr int kTraceCap = 4096;     // device trace ring (rounds); the host drai
 constexpr int kUnits = 8;           // work-unit counters per round (TraceRec::u)
 constexpr int kStripes = 128;       // round counters are spread over this many cache lines (a multiple of 64)
 constexpr int kStripeWords = 16;    // int64 words per stripe (one 128-byte line)
-constexpr int kDenseMinDefault = 9; // hybrid: a 36-byte 16x16 tile costs no more than 9 entry indices
+// hybrid: entries per tile from which a 16-row block takes bit tiles by default.  A
+// 36-byte 16x16 tile costs no more bytes than 9 entry indices, but each dense block
+// costs its wave a chain of dependent steps per round, so blocks near that break-even
+// (a 7-point mesh in natural order: about 9.4) run faster as entry lists.
+constexpr int kDenseMinDefault = 16;
 
 // Device control block of the round loop.  Round r's kernels take r as an
 // argument and count into the round-parity half of the counter stripes (each

@@ -769,20 +769,75 @@ __device__ inline bool r1_in_s(const HybArgs& a, const int32_t* row, int c, int3
     return grp_hit(a.S, u, K, c);
 }
 
-// Does H(v) (c <= kHLight entries at hcol + rp[v]) name a vertex whose bit is set in
-// m?  Static handles: kGrp entries per step, the step's loads and bitmap gathers in
+// Does H(v) (c <= kHLight entries at hcol + e0, e0 = rp[v]) name, from its entry k0
+// on, a vertex whose bit is set in m?  Static handles: kGrp entries per step, the step's loads and bitmap gathers in
 // flight together (16-byte loads may read three entries past the row, so a row ending
 // within three entries of the array's end takes four at a time, as do the rows of
 // dynamic handles).  *read counts the entries compared.
-__device__ inline bool scan_h(const HybArgs& a, int32_t v, int32_t c, const uint32_t* m, int64_t* read) {
-    const int64_t e0 = a.rp[v];
-    if (a.oriented || e0 + c + 3 > a.nnz) return scan4(a.hcol + e0, c, m, read);
+__device__ inline bool scan_h_from(const HybArgs& a, int32_t v, int64_t e0, int32_t c, int32_t k0, const uint32_t* m,
+                                   int64_t* read) {
+    if (a.oriented || e0 + c + 3 > a.nnz) return scan4(a.hcol + e0 + k0, c - k0, m, read);
     bool hit = false;
-    for (int k = 0; k < c && !hit; k += kGrp) {
+    for (int k = k0; k < c && !hit; k += kGrp) {
         int32_t u[kGrp];
         load_grp(a.hcol + e0, k, c, v, u);
         hit = grp_hit(m, u, k, c);
         *read += min(c - k, kGrp);
+    }
+    return hit;
+}
+
+// The undecided rows `rows` of bitmap word w in the rounds after the first, four rows
+// at a time on one lane: their entry counts and row starts are loaded together, then
+// the first four entries of each, then those entries' words of m, so that the four
+// rows' dependent steps overlap; a row with more entries and no hit among the first
+// four continues alone (scan_h_from).  Returns the rows whose H row names a vertex set
+// in m.  Rows of more than kHLight entries are left to the caller in *heavy.  Deleted
+// entries of a dynamic handle (-1) are skipped.  *read counts the entries compared,
+// *verts the rows examined.
+__device__ inline uint32_t light_hits(const HybArgs& a, int64_t w, uint32_t rows, const uint32_t* m,
+                                      uint32_t* heavy, int64_t* read, int64_t* verts) {
+    uint32_t hit = 0;
+    for (uint32_t mm = rows; mm;) {
+        int32_t v[4], c[4];
+        int64_t e0[4];
+        #pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            v[j] = mm ? (int32_t)(w * 32 + __builtin_ctz(mm)) : -1;
+            mm &= mm - 1u;
+        }
+        #pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            c[j] = v[j] >= 0 ? a.hcnt[v[j]] : 0;
+            e0[j] = v[j] >= 0 ? a.rp[v[j]] : 0;
+        }
+        int32_t u[4][4];
+        #pragma unroll
+        for (int j = 0; j < 4; ++j)
+            #pragma unroll
+            for (int i = 0; i < 4; ++i) u[j][i] = i < c[j] && c[j] <= kHLight ? a.hcol[e0[j] + i] : -1;
+        uint32_t wd[4][4];
+        #pragma unroll
+        for (int j = 0; j < 4; ++j)
+            #pragma unroll
+            for (int i = 0; i < 4; ++i) wd[j][i] = u[j][i] >= 0 ? m[(uint32_t)u[j][i] >> 5] : 0u;
+        #pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (v[j] < 0) continue;
+            const uint32_t bit = 1u << (v[j] & 31);
+            if (c[j] > kHLight) {
+                *heavy |= bit;
+                continue;
+            }
+            ++*verts;
+            uint32_t h = 0;
+            #pragma unroll
+            for (int i = 0; i < 4; ++i) h |= u[j][i] >= 0 ? wd[j][i] >> (u[j][i] & 31) : 0u;
+            *read += min(c[j], 4);
+            bool got = (h & 1u) != 0;
+            if (!got && c[j] > 4) got = scan_h_from(a, v[j], e0[j], c[j], 4, m, read);
+            if (got) hit |= bit;
+        }
     }
     return hit;
 }
@@ -885,15 +940,9 @@ __device__ void hyb_p1(const HybArgs& a, int r, int64_t vb, int64_t nvb) {
         const int64_t nwr = (nwords + kWave - 1) / kWave * kWave;   // whole waves iterate together
         for (int64_t w = tid; w < nwr; w += nthreads) {
             const uint32_t rows = w < nwords ? list_rows(a, dn, w, a.A[w]) : 0u;
-            uint32_t cand = 0, heavy = 0;
-            for (uint32_t mm = rows; mm; mm &= mm - 1) {
-                const int b = __builtin_ctz(mm);
-                const int32_t v = (int32_t)(w * 32 + b);
-                const int32_t c = a.hcnt[v];
-                if (c > kHLight) { heavy |= 1u << b; continue; }
-                ++verts;
-                if (!scan_h(a, v, c, a.A, &ent)) cand |= 1u << b;
-            }
+            uint32_t heavy = 0;
+            const uint32_t met = light_hits(a, w, rows, a.A, &heavy, &ent, &verts);   // blocked rows
+            uint32_t cand = rows & ~heavy & ~met;
             for (uint64_t hb = ballot(heavy != 0); hb; hb = ballot(heavy != 0)) {
                 const int l = __builtin_ctzll(hb);
                 const int b = __builtin_ctz(__shfl(heavy, l, kWave));
@@ -1122,15 +1171,10 @@ __device__ void hyb_p2(const HybArgs& a, int r, int64_t vb, int64_t nvb) {
         for (int64_t w = tid; w < nwr; w += nthreads) {
             const uint32_t rows = w < nwords ? list_rows(a, dn, w, a.A[w]) : 0u;
             const uint32_t sw = rows ? a.S[w] : 0u;
-            uint32_t dec = rows & sw, heavy = 0;
-            for (uint32_t mm = rows & ~sw; mm; mm &= mm - 1) {
-                const int b = __builtin_ctz(mm);
-                const int32_t v = (int32_t)(w * 32 + b);
-                const int32_t c = a.hcnt[v];
-                if (c > kHLight) { heavy |= 1u << b; continue; }
-                ++verts;
-                if (scan_h(a, v, c, a.S, &ent)) { dec |= 1u << b; ++n_out; }
-            }
+            uint32_t heavy = 0;
+            const uint32_t out = light_hits(a, w, rows & ~sw, a.S, &heavy, &ent, &verts);
+            uint32_t dec = (rows & sw) | out;
+            n_out += __popc(out);
             for (uint64_t hb = ballot(heavy != 0); hb; hb = ballot(heavy != 0)) {
                 const int l = __builtin_ctzll(hb);
                 const int b = __builtin_ctz(__shfl(heavy, l, kWave));

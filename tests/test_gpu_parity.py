@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 # (path, tile, reorder, orient[, dense_min]); the hybrid path's dense_min: -1 = entry
 # lists only, 1 = every block that fits 64 tiles is dense (bit tiles on the matrix
-# cores wherever possible), 9 = the default split
+# cores wherever possible), 9 = the byte break-even of a bit tile against entry indices
 HYBRID_CONFIGS = [("hybrid", 16, "none", 1, d) for d in (-1, 1, 9)]
 ALL_CONFIGS = [("csr", 0, "none", 0)] + [
     ("tile", t, r, o) for t in (16, 32) for r in ("none", "degree", "key", "rcm") for o in (0, 1)
