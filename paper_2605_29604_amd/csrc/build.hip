@@ -100,27 +100,48 @@ __device__ inline uint64_t key_class(int rule, int64_t deg, int64_t gn, int64_t 
     return (uint64_t)(q < 255 ? q : 255);
 }
 
+__device__ inline void key_one(int64_t v, int64_t lv, int64_t gn, int64_t gnnz, const int64_t* rp, int64_t n,
+                               uint64_t seed, int rule, uint64_t* key, uint64_t* sk, uint8_t* q8) {
+    const int64_t deg = rp[v + 1] - rp[v];
+    const uint64_t z = splitmix_at(seed, (uint64_t)lv + 1);
+    const uint64_t q = key_class(rule, deg, gn, gnnz, z);
+    const uint64_t k = (q << 56) | ((z >> 32) << 24) | (uint64_t)lv;
+    key[v] = k;
+    if (sk) sk[n - 1 - v] = ~k;
+    if (q8) q8[v] = (uint8_t)q;
+}
+
+// Batches: a workgroup takes kKeysSpan consecutive vertices (kKeysPer per thread, a
+// workgroup's width apart), finds the graph of the first once and keeps the graph's
+// bounds in registers, stepping to the next graph where a vertex passes its end.
+constexpr int kKeysPer = 16;
+constexpr int64_t kKeysSpan = (int64_t)kBlock * kKeysPer;
+
 // With `samp` (hybrid path with dense blocks) the kernel's waves also take the
 // dense-block sample (dense.hpp), sparing the build a launch.
 __global__ void k_keys(const int64_t* rp, int64_t n, uint64_t seed, const int64_t* goff, int64_t count, int rule,
                        uint64_t* key, uint64_t* sk, uint8_t* q8, Meta* meta, const int32_t* ci, int64_t stride,
                        int samples, int dense_min, int32_t* samp) {
     if (meta && blockIdx.x == 0 && threadIdx.x == 0) *meta = Meta{};   // the hybrid build's sizes start at 0
-    GRID_STRIDE(v, n) {
-        const int64_t deg = rp[v + 1] - rp[v];
-        int64_t lv = v, gn = n, gnnz = rp[n] - rp[0];
-        if (goff) {
-            const int64_t g = graph_of(goff, count, v);
-            lv = v - goff[g];
-            gn = goff[g + 1] - goff[g];
-            gnnz = rp[goff[g + 1]] - rp[goff[g]];
+    if (!goff) {
+        const int64_t nnz = rp[n] - rp[0];
+        GRID_STRIDE(v, n) key_one(v, v, n, nnz, rp, n, seed, rule, key, sk, q8);
+    } else {
+        for (int64_t s0 = (int64_t)blockIdx.x * kKeysSpan; s0 < n; s0 += (int64_t)gridDim.x * kKeysSpan) {
+            int64_t g = graph_of(goff, count, s0);   // the same for the whole workgroup
+            int64_t gs = goff[g], ge = goff[g + 1], gnnz = rp[ge] - rp[gs];
+            for (int i = 0; i < kKeysPer; ++i) {
+                const int64_t v = s0 + (int64_t)i * kBlock + threadIdx.x;
+                if (v >= n) break;
+                if (v >= ge) {
+                    while (g + 1 < count && goff[g + 1] <= v) ++g;
+                    gs = goff[g];
+                    ge = goff[g + 1];
+                    gnnz = rp[ge] - rp[gs];
+                }
+                key_one(v, v - gs, ge - gs, gnnz, rp, n, seed, rule, key, sk, q8);
+            }
         }
-        const uint64_t z = splitmix_at(seed, (uint64_t)lv + 1);
-        const uint64_t q = key_class(rule, deg, gn, gnnz, z);
-        const uint64_t k = (q << 56) | ((z >> 32) << 24) | (uint64_t)lv;
-        key[v] = k;
-        if (sk) sk[n - 1 - v] = ~k;
-        if (q8) q8[v] = (uint8_t)q;
     }
     if (samp)
         dense_sample(rp, ci, n, stride, samples, dense_min, samp, ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave,
@@ -772,9 +793,14 @@ int build_keys(mis_graph* g, const mis_build_opts* o, hipStream_t s) {
         uint64_t* sk = g->path == MIS_PATH_TILE && default_keys_in_order(g) ? g->sk : nullptr;
         const bool hyb = g->path == MIS_PATH_HYBRID;
         const bool sample = hyb && g->dense_min > 0 && g->nnz > 0;   // the dense-block sample
-        LAUNCH(k_keys, g->n, g->row_ptr, g->n, o->seed, g->goff, (int64_t)g->count, o->key_rule, g->key, sk,
-               hyb ? g->q8 : nullptr, hyb ? g->meta : nullptr, g->col_idx, dense_stride(g->nI),
-               dense_samples(g->nI), g->dense_min, sample ? g->dsamp : nullptr);
+        // a batch takes kKeysSpan vertices per workgroup (see k_keys)
+        const unsigned grid = g->count > 0 ? (unsigned)std::min<int64_t>(ceil_div(g->n, kKeysSpan), 65536)
+                                           : stream_grid(g->n);
+        hipLaunchKernelGGL(k_keys, dim3(grid), dim3(kBlock), 0, s, g->row_ptr, g->n, o->seed,
+                           g->count > 0 ? g->goff : nullptr, (int64_t)g->count, o->key_rule, g->key, sk,
+                           hyb ? g->q8 : nullptr, hyb ? g->meta : nullptr, g->col_idx, dense_stride(g->nI),
+                           dense_samples(g->nI), g->dense_min, sample ? g->dsamp : nullptr);
+        TC_HIP(hipGetLastError());
     }
     return MIS_OK;
 }

@@ -227,19 +227,36 @@ int enqueue_phase(GraphCore* g, int phase, int r, hipStream_t s, bool first) {
 }
 
 // per-graph rounds (largest decision round of its vertices) and set sizes; one
-// workgroup per graph of the batch
-__global__ void __launch_bounds__(kBlock) k_batch_stats(const int64_t* goff, const uint8_t* in_set,
-                                                        const int32_t* new_id, const int32_t* dround, const uint32_t* st,
-                                                        int32_t* g_rounds, int64_t* g_in) {
-    __shared__ int32_t smax[kBlock / kWave];
-    __shared__ int64_t ssum[kBlock / kWave];
+// workgroup of kStatsBlock threads per graph, four consecutive vertices per thread and
+// step with their loads in flight together
+constexpr int kStatsBlock = 1024;
+__global__ void __launch_bounds__(kStatsBlock) k_batch_stats(const int64_t* goff, const uint8_t* in_set,
+                                                             const int32_t* new_id, const int32_t* dround,
+                                                             const uint32_t* st, int32_t* g_rounds, int64_t* g_in) {
+    __shared__ int32_t smax[kStatsBlock / kWave];
+    __shared__ int64_t ssum[kStatsBlock / kWave];
     const int64_t g = blockIdx.x;
+    const int64_t v1 = goff[g + 1];
     int32_t mx = 0;
     int64_t sum = 0;
-    for (int64_t v = goff[g] + threadIdx.x; v < goff[g + 1]; v += kBlock) {
-        const int32_t r = new_id ? dround[new_id[v]] : st ? (int32_t)(st[v] >> 2) : dround[v];
-        mx = max(mx, r);
-        sum += in_set[v];
+    for (int64_t b = goff[g] + 4 * (int64_t)threadIdx.x; b < v1; b += 4 * kStatsBlock) {
+        int32_t r[4];
+        uint32_t in[4];
+        #pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t v = b + j;
+            r[j] = 0;
+            in[j] = 0;
+            if (v < v1) {
+                r[j] = new_id ? dround[new_id[v]] : st ? (int32_t)(st[v] >> 2) : dround[v];
+                in[j] = in_set[v];
+            }
+        }
+        #pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            mx = max(mx, r[j]);
+            sum += in[j];
+        }
     }
     for (int off = kWave / 2; off > 0; off >>= 1) {
         mx = max(mx, __shfl_xor(mx, off, kWave));
@@ -248,7 +265,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_stats(const int64_t* goff, con
     if (lane_id() == 0) { smax[threadIdx.x / kWave] = mx; ssum[threadIdx.x / kWave] = sum; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int w = 1; w < kBlock / kWave; ++w) { mx = max(mx, smax[w]); sum += ssum[w]; }
+        for (int w = 1; w < kStatsBlock / kWave; ++w) { mx = max(mx, smax[w]); sum += ssum[w]; }
         g_rounds[g] = mx;
         g_in[g] = sum;
     }
@@ -662,7 +679,7 @@ int mis_solve_union(mis_graph* g, uint8_t* in_set, mis_stats* stats, int32_t* gr
     TC_CHECK(mis_solve(g, in_set, 0, nullptr, 0, stats, stream));
     hipStream_t s = (hipStream_t)stream;
     if (g->n > 0) {
-        hipLaunchKernelGGL(k_batch_stats, dim3((unsigned)g->count), dim3(kBlock), 0, s, g->goff, in_set,
+        hipLaunchKernelGGL(k_batch_stats, dim3((unsigned)g->count), dim3(kStatsBlock), 0, s, g->goff, in_set,
                            g->path == MIS_PATH_TILE ? g->new_id : nullptr, g->dround,
                            g->path == MIS_PATH_CSR ? g->st : nullptr, g->g_rounds, g->g_in);
         TC_HIP(hipGetLastError());

@@ -5,7 +5,6 @@
 // order is reversed.  Sequential by nature, so it runs on the host during the build.
 #include <algorithm>
 #include <cstdint>
-#include <numeric>
 #include <vector>
 
 #include "../../include/tcmis.h"
@@ -16,9 +15,15 @@ int host_rcm(const int64_t* rp, const int32_t* ci, int64_t n, std::vector<int32_
     std::vector<int64_t> deg(n);
     for (int64_t v = 0; v < n; ++v) deg[v] = rp[v + 1] - rp[v];
     auto less = [&](int32_t a, int32_t b) { return deg[a] < deg[b] || (deg[a] == deg[b] && a < b); };
+    // the vertices by increasing degree, then id: a counting sort on the degree (stable,
+    // so ids stay increasing within a degree)
+    int64_t dmax = 0;
+    for (int64_t v = 0; v < n; ++v) dmax = std::max(dmax, deg[v]);
+    std::vector<int64_t> first(dmax + 2, 0);
+    for (int64_t v = 0; v < n; ++v) ++first[deg[v] + 1];
+    for (int64_t d = 0; d <= dmax; ++d) first[d + 1] += first[d];
     std::vector<int32_t> by_deg(n);
-    std::iota(by_deg.begin(), by_deg.end(), 0);
-    std::sort(by_deg.begin(), by_deg.end(), less);
+    for (int64_t v = 0; v < n; ++v) by_deg[first[deg[v]]++] = (int32_t)v;
     std::vector<uint8_t> seen(n, 0);
     std::vector<int32_t> order;
     order.reserve(n);
