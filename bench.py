@@ -19,6 +19,10 @@ kernel, and the CPU oracle and sequential greedy timed on this host.
 32x32 tiles in natural and RCM order, with tile density and the exclusion kernel's
 fraction of the HBM roofline); every leg's set is compared with the first leg's.
 
+"dynamic": batches of 1,000, 10,000 and 100,000 random edge edits (half deletions, half
+insertions) on a dynamic handle of the benchmark graph and of the 256^3 mesh, each applied with its local
+repair, against a full solve of the edited handle (same set required).
+
 "batch": 4,096 independent graphs (sizes log-uniform over 500..200,000 vertices,
 half Erdos-Renyi with average degree 4..32, half R-MAT with 8..24) solved as one
 block-diagonal batch (mis_build_batch + mis_solve_union) against one graph per
@@ -32,7 +36,7 @@ and p50/p99 latency from arrival to result in host memory (H2D, build, solve, D2
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rmat22]
                        [--batch-graphs 4096] [--serve-requests 2000] [--no-batch] [--no-serve]
-                       [--no-configs] [--no-tune] [--no-cpu]
+                       [--no-configs] [--no-tune] [--no-dynamic] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -101,6 +105,7 @@ def parse():
     p.add_argument("--serve-live", type=int, default=8)
     p.add_argument("--no-tune", action="store_true")
     p.add_argument("--no-configs", action="store_true", help="skip the er10k and grid256 legs")
+    p.add_argument("--no-dynamic", action="store_true", help="skip the edge-edit leg")
     return p.parse_args()
 
 
@@ -197,6 +202,81 @@ def bench_configs(a, torch, gen, tcmis, grid):
         res[name] = rec
         del rp, ci
         torch.cuda.empty_cache()
+    return res
+
+
+def bench_dynamic(a, torch, tcmis, graphs):
+    """Dynamic graphs: batches of random edge edits on a dynamic hybrid handle of each
+    graph (half deletions of present edges, half insertions of absent ones), each applied
+    with its local repair (mis_update_edges), against a full solve of the edited handle;
+    the repaired set must equal that solve's."""
+    out = {}
+    for name, g in graphs:
+        rp = torch.from_numpy(g.row_ptr).cuda()
+        ci = torch.from_numpy(g.col_idx).cuda()
+        out[name] = dynamic_leg(a, torch, tcmis, name, g, rp, ci)
+        del rp, ci
+        torch.cuda.empty_cache()
+    return out
+
+
+def dynamic_leg(a, torch, tcmis, name, g, rp, ci):
+    cfg = dict(path="hybrid", dense_min=-1, dyn_slack=8, seed=a.seed)
+    t0 = time.perf_counter()
+    h = tcmis.mis_build_tiles(rp, ci, **cfg)
+    out, _ = tcmis.mis_solve(h, trace_cap=0)
+    torch.cuda.synchronize()
+    res = {"config": "hybrid, entry lists, 8 free slots per row and orientation",
+           "build_and_solve_ms": round((time.perf_counter() - t0) * 1e3, 3), "batches": []}
+    rph, cih = g.row_ptr, g.col_idx
+    rng = np.random.default_rng(7)
+    deleted, inserted = set(), set()
+
+    def present(u, v):
+        if (u, v) in inserted:
+            return True
+        if (u, v) in deleted:
+            return False
+        row = cih[rph[u]:rph[u + 1]]
+        i = int(np.searchsorted(row, v))
+        return i < row.size and int(row[i]) == v
+
+    for k in (1000, 10000, 100000):
+        dels, ins = set(), set()
+        while len(dels) < k // 2:
+            e = int(rng.integers(cih.size))
+            u = int(np.searchsorted(rph, e, side="right")) - 1
+            v = int(cih[e])
+            p = (min(u, v), max(u, v))
+            if p not in dels and p not in deleted:
+                dels.add(p)
+        while len(ins) < k // 2:
+            u, v = int(rng.integers(g.n)), int(rng.integers(g.n))
+            p = (min(u, v), max(u, v))
+            if u != v and p not in ins and p not in dels and not present(*p):
+                ins.add(p)
+        pairs = np.array(sorted(dels) + sorted(ins), dtype=np.int32).reshape(-1, 2)
+        ops = np.array([0] * len(dels) + [1] * len(ins), dtype=np.int8)
+        perm = rng.permutation(len(ops))
+        d_pairs = torch.from_numpy(np.ascontiguousarray(pairs[perm])).cuda()
+        d_ops = torch.from_numpy(ops[perm]).cuda()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        info = tcmis.mis_update_edges(h, d_pairs, d_ops, out)
+        torch.cuda.synchronize()
+        upd = time.perf_counter() - t
+        deleted |= dels - inserted
+        inserted = (inserted - dels) | ins
+        t = time.perf_counter()
+        full, st = tcmis.mis_solve(h, trace_cap=0)
+        torch.cuda.synchronize()
+        fs = time.perf_counter() - t
+        rec = {"edits": len(ops), "update_and_repair_ms": round(upd * 1e3, 3), "repair_rounds": info["rounds"],
+               "entries_read": info["entries_read"], "full_solve_ms": round(fs * 1e3, 3),
+               "same_set_as_full_solve": bool(torch.equal(full, out)), "mis_size": int(st["n_in"])}
+        res["batches"].append(rec)
+        log(f"dynamic {name}: {rec}")
+    tcmis.mis_free_tiles(h)
     return res
 
 
@@ -605,7 +685,7 @@ def main():
                          "graph_flag": lst["graph"]}
     res["launch_modes"] = modes
     grid = None
-    if not (a.no_tune and a.no_configs):
+    if not (a.no_tune and a.no_configs and a.no_dynamic):
         t0 = time.perf_counter()
         grid = gen.workload("grid256", seed=1)
         log(f"grid256 generated in {time.perf_counter() - t0:.1f}s")
@@ -613,6 +693,8 @@ def main():
         res["configs"] = bench_configs(a, torch, gen, tcmis, grid)
     if not a.no_tune:
         res["autotune"] = bench_tune(a, torch, gen, tcmis, rp, ci, grid)
+    if not a.no_dynamic:
+        res["dynamic"] = bench_dynamic(a, torch, tcmis, [(a.workload, g)] + ([("grid256", grid)] if grid else []))
     del grid
 
     if not a.no_batch:

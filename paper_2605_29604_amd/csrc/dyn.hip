@@ -71,16 +71,60 @@ __device__ inline void make_pending(const DynArgs& a, int32_t v, int32_t* list, 
     }
 }
 
-__global__ void k_dyn_clear(uint32_t* P, uint32_t* C, uint32_t* S, int64_t nw, int64_t* rcnt) {
-    GRID_STRIDE(w, nw) {
-        P[w] = 0;
-        C[w] = 0;
-        S[w] = 0;
-    }
-    if (blockIdx.x == 0 && threadIdx.x < kRcWords) rcnt[threadIdx.x] = 0;
+// Rows longer than kDynLight entries (a hub's row holds up to the graph's largest
+// degree) are handled by the whole wave, one after another, 64 entries per step; the
+// shorter ones on their item's lane.  The kernels below take one item (an edit, a
+// pending or a flipped vertex) per thread, and whole waves iterate together
+// (DYN_ITEMS) so that those wave steps can ballot.
+constexpr int32_t kDynLight = 32;
+
+#define DYN_ITEMS(i, count)                                                                                  \
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x,                                          \
+                 i##_end = ((count) + kWave - 1) / kWave * kWave;                                             \
+         i < i##_end; i += (int64_t)gridDim.x * blockDim.x)
+
+// With at most as many items as the launch has waves, each item takes a wave of its
+// own (every row then on 64 lanes), instead of 64 items sharing one wave.
+__device__ inline int64_t wave_index() { return ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; }
+__device__ inline int64_t wave_count() { return (int64_t)gridDim.x * (blockDim.x / kWave); }
+
+// sets the entry x of row[0, c) to -1 (the edge is in the row at most once); true if found
+__device__ inline bool lane_clear(int32_t* row, int32_t c, int32_t x) {
+    for (int32_t j = 0; j < c; ++j)
+        if (row[j] == x) {
+            row[j] = -1;
+            return true;
+        }
+    return false;
 }
 
-// moves a row's live entries (>= 0) to its front; returns the new count
+// The wave forms take kDynUnroll steps of 64 entries at a time, all their loads in
+// flight together (a hub's row takes hundreds of such steps).
+constexpr int kDynUnroll = 8;
+
+__device__ inline bool wave_clear(int32_t* row, int32_t c, int32_t x) {
+    for (int32_t k0 = 0; k0 < c; k0 += kDynUnroll * kWave) {
+        int32_t u[kDynUnroll];
+        #pragma unroll
+        for (int q = 0; q < kDynUnroll; ++q) {
+            const int32_t j = k0 + q * kWave + lane_id();
+            u[q] = j < c ? row[j] : -1;
+        }
+        #pragma unroll
+        for (int q = 0; q < kDynUnroll; ++q) {
+            const uint64_t m = ballot(u[q] == x);
+            if (m) {
+                if (lane_id() == __builtin_ctzll(m)) row[k0 + q * kWave + lane_id()] = -1;
+                return true;
+            }
+        }
+    }
+    return false;
+}
+
+// moves a row's live entries (>= 0) to its front; returns the new count (the wave
+// form: each step's entries are all read before any of them is written, and an entry
+// moves only towards the front)
 __device__ inline int32_t compact_row(int32_t* row, int32_t c) {
     int32_t w = 0;
     for (int32_t j = 0; j < c; ++j) {
@@ -90,17 +134,119 @@ __device__ inline int32_t compact_row(int32_t* row, int32_t c) {
     return w;
 }
 
+__device__ inline int32_t wave_compact(int32_t* row, int32_t c) {
+    constexpr int kU = kDynUnroll / 2;
+    int32_t w = 0;
+    for (int32_t k0 = 0; k0 < c; k0 += kU * kWave) {
+        int32_t x[kU];
+        #pragma unroll
+        for (int q = 0; q < kU; ++q) {
+            const int32_t j = k0 + q * kWave + lane_id();
+            x[q] = j < c ? row[j] : -1;
+        }
+        #pragma unroll
+        for (int q = 0; q < kU; ++q) {
+            const uint64_t m = ballot(x[q] >= 0);
+            if (x[q] >= 0) row[w + __popcll(m & lanes_below())] = x[q];
+            w += __popcll(m);
+        }
+    }
+    return w;
+}
+
+// does row[0, c) name a vertex u (>= 0) with hit(u)?  The whole wave, early exit;
+// *read (lane 0) counts the entries loaded
+template <typename F>
+__device__ inline bool wave_any(const int32_t* row, int32_t c, F hit, int64_t* read) {
+    int32_t k0 = 0;
+    bool any = false;
+    {   // the first 64 entries alone (most rows that hit, hit early)
+        const int32_t u = lane_id() < c ? row[lane_id()] : -1;
+        if (ballot(u >= 0 && hit(u))) any = true;
+        k0 = kWave;
+    }
+    for (; !any && k0 < c; k0 += kDynUnroll * kWave) {
+        int32_t u[kDynUnroll];
+        #pragma unroll
+        for (int q = 0; q < kDynUnroll; ++q) {
+            const int32_t j = k0 + q * kWave + lane_id();
+            u[q] = j < c ? row[j] : -1;
+        }
+        bool h = false;
+        #pragma unroll
+        for (int q = 0; q < kDynUnroll; ++q) h = h | (u[q] >= 0 ? hit(u[q]) : false);
+        if (ballot(h)) {
+            any = true;
+            k0 += kDynUnroll * kWave;
+            break;
+        }
+    }
+    if (lane_id() == 0) *read += min(k0, c);
+    return any;
+}
+
+__global__ void k_dyn_clear(uint32_t* P, uint32_t* C, uint32_t* S, int64_t nw, int64_t* rcnt) {
+    GRID_STRIDE(w, nw) {
+        P[w] = 0;
+        C[w] = 0;
+        S[w] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < kRcWords) rcnt[threadIdx.x] = 0;
+}
+
 // after the deletes: every row that lost an entry is compacted once (the first
 // delete to claim it does it), so rows hold no deleted entries afterwards
 __global__ void k_dyn_compact(DynArgs a, const int32_t* edges, const int8_t* ops, int64_t k) {
-    GRID_STRIDE(i, k) {
-        if (ops[i]) continue;
+    if (k <= wave_count()) {
+        const int64_t i = wave_index();
+        if (i >= k || ops[i]) return;
         const int32_t u = edges[2 * i], v = edges[2 * i + 1];
-        if (u < 0 || v < 0 || u >= a.n || v >= a.n || u == v) continue;
+        if (u < 0 || v < 0 || u >= a.n || v >= a.n || u == v) return;
         const int32_t hi = a.key[u] > a.key[v] ? u : v, lo = hi == u ? v : u;
-        const uint32_t bl = 1u << (lo & 31), bh = 1u << (hi & 31);
-        if (!(atomicOr(&a.claim_h[lo >> 5], bl) & bl)) a.hcnt[lo] = compact_row(a.hcol + a.drp[lo], a.hcnt[lo]);
-        if (!(atomicOr(&a.claim_l[hi >> 5], bh) & bh)) a.lcnt[hi] = compact_row(a.lcol + a.drp[hi], a.lcnt[hi]);
+        int own = 0;
+        if (lane_id() == 0) {
+            const uint32_t bl = 1u << (lo & 31), bh = 1u << (hi & 31);
+            own = (!(atomicOr(&a.claim_h[lo >> 5], bl) & bl) ? 1 : 0) | (!(atomicOr(&a.claim_l[hi >> 5], bh) & bh) ? 2 : 0);
+        }
+        own = __shfl(own, 0, kWave);
+        if (own & 1) {
+            const int32_t c = wave_compact(a.hcol + a.drp[lo], a.hcnt[lo]);
+            if (lane_id() == 0) a.hcnt[lo] = c;
+        }
+        if (own & 2) {
+            const int32_t c = wave_compact(a.lcol + a.drp[hi], a.lcnt[hi]);
+            if (lane_id() == 0) a.lcnt[hi] = c;
+        }
+        return;
+    }
+    DYN_ITEMS(i, k) {
+        bool own_h = false, own_l = false;
+        int32_t hi = 0, lo = 0;
+        if (i < k && !ops[i]) {
+            const int32_t u = edges[2 * i], v = edges[2 * i + 1];
+            if (u >= 0 && v >= 0 && u < a.n && v < a.n && u != v) {
+                hi = a.key[u] > a.key[v] ? u : v;
+                lo = hi == u ? v : u;
+                const uint32_t bl = 1u << (lo & 31), bh = 1u << (hi & 31);
+                own_h = !(atomicOr(&a.claim_h[lo >> 5], bl) & bl);
+                own_l = !(atomicOr(&a.claim_l[hi >> 5], bh) & bh);
+            }
+        }
+        const int32_t ch = own_h ? a.hcnt[lo] : 0, cl = own_l ? a.lcnt[hi] : 0;
+        if (own_h && ch <= kDynLight) a.hcnt[lo] = compact_row(a.hcol + a.drp[lo], ch);
+        if (own_l && cl <= kDynLight) a.lcnt[hi] = compact_row(a.lcol + a.drp[hi], cl);
+        for (uint64_t hv = ballot(own_h && ch > kDynLight); hv; hv &= hv - 1) {
+            const int l = __builtin_ctzll(hv);
+            const int32_t x = __shfl(lo, l, kWave);
+            const int32_t c = wave_compact(a.hcol + a.drp[x], __shfl(ch, l, kWave));
+            if (lane_id() == 0) a.hcnt[x] = c;
+        }
+        for (uint64_t hv = ballot(own_l && cl > kDynLight); hv; hv &= hv - 1) {
+            const int l = __builtin_ctzll(hv);
+            const int32_t x = __shfl(hi, l, kWave);
+            const int32_t c = wave_compact(a.lcol + a.drp[x], __shfl(cl, l, kWave));
+            if (lane_id() == 0) a.lcnt[x] = c;
+        }
     }
 }
 
@@ -108,20 +254,55 @@ __global__ void k_dyn_unclaim(uint32_t* claim, int64_t nw) { GRID_STRIDE(w, nw) 
 
 // deletes: -1 over the entry in H(lo) and in L(hi)
 __global__ void k_dyn_delete(DynArgs a, const int32_t* edges, const int8_t* ops, int64_t k) {
-    GRID_STRIDE(i, k) {
-        if (ops[i]) continue;
+    if (k <= wave_count()) {
+        const int64_t i = wave_index();
+        if (i >= k || ops[i]) return;
         const int32_t u = edges[2 * i], v = edges[2 * i + 1];
         if (u < 0 || v < 0 || u >= a.n || v >= a.n || u == v) {
-            atomicOr((unsigned long long*)&a.rcnt[kRcErr], (unsigned long long)kErrEdge);
-            continue;
+            if (lane_id() == 0) atomicOr((unsigned long long*)&a.rcnt[kRcErr], (unsigned long long)kErrEdge);
+            return;
         }
         const int32_t hi = a.key[u] > a.key[v] ? u : v, lo = hi == u ? v : u;
-        bool fh = false, fl = false;
-        const int32_t ch = a.hcnt[lo], cl = a.lcnt[hi];
-        for (int32_t j = 0; j < ch && !fh; ++j) fh = atomicCAS(&a.hcol[a.drp[lo] + j], hi, -1) == hi;
-        for (int32_t j = 0; j < cl && !fl; ++j) fl = atomicCAS(&a.lcol[a.drp[hi] + j], lo, -1) == lo;
-        if (!fh || !fl) atomicOr((unsigned long long*)&a.rcnt[kRcErr], (unsigned long long)kErrMissing);
-        make_pending(a, lo, a.list[1], &a.rcnt[kRcList1]);
+        const bool fh = wave_clear(a.hcol + a.drp[lo], a.hcnt[lo], hi);
+        const bool fl = wave_clear(a.lcol + a.drp[hi], a.lcnt[hi], lo);
+        if (lane_id() == 0) {
+            if (!fh || !fl) atomicOr((unsigned long long*)&a.rcnt[kRcErr], (unsigned long long)kErrMissing);
+            make_pending(a, lo, a.list[1], &a.rcnt[kRcList1]);
+        }
+        return;
+    }
+    DYN_ITEMS(i, k) {
+        bool act = i < k && !ops[i];
+        int32_t hi = 0, lo = 0;
+        if (act) {
+            const int32_t u = edges[2 * i], v = edges[2 * i + 1];
+            if (u < 0 || v < 0 || u >= a.n || v >= a.n || u == v) {
+                atomicOr((unsigned long long*)&a.rcnt[kRcErr], (unsigned long long)kErrEdge);
+                act = false;
+            } else {
+                hi = a.key[u] > a.key[v] ? u : v;
+                lo = hi == u ? v : u;
+            }
+        }
+        const int32_t ch = act ? a.hcnt[lo] : 0, cl = act ? a.lcnt[hi] : 0;
+        bool fh = act && ch <= kDynLight && lane_clear(a.hcol + a.drp[lo], ch, hi);
+        bool fl = act && cl <= kDynLight && lane_clear(a.lcol + a.drp[hi], cl, lo);
+        for (uint64_t hv = ballot(act && ch > kDynLight); hv; hv &= hv - 1) {
+            const int l = __builtin_ctzll(hv);
+            const int32_t x = __shfl(lo, l, kWave);
+            const bool f = wave_clear(a.hcol + a.drp[x], __shfl(ch, l, kWave), __shfl(hi, l, kWave));
+            if (lane_id() == l) fh = f;
+        }
+        for (uint64_t hv = ballot(act && cl > kDynLight); hv; hv &= hv - 1) {
+            const int l = __builtin_ctzll(hv);
+            const int32_t x = __shfl(hi, l, kWave);
+            const bool f = wave_clear(a.lcol + a.drp[x], __shfl(cl, l, kWave), __shfl(lo, l, kWave));
+            if (lane_id() == l) fl = f;
+        }
+        if (act) {
+            if (!fh || !fl) atomicOr((unsigned long long*)&a.rcnt[kRcErr], (unsigned long long)kErrMissing);
+            make_pending(a, lo, a.list[1], &a.rcnt[kRcList1]);
+        }
     }
 }
 
@@ -176,14 +357,33 @@ __global__ void __launch_bounds__(kBlock) k_rep_cand(DynArgs a, int r) {
     }
     const int32_t* L = a.list[r & 1];
     const int64_t nl = a.rcnt[r & 1];
-    GRID_STRIDE(i, nl) {
+    int64_t read = 0;
+    auto blocks = [&](int32_t u) { return bitv(a.P, u) || bitv(a.S, u); };
+    if (nl <= wave_count()) {
+        const int64_t i = wave_index();
+        if (i >= nl) return;
         const int32_t v = L[i];
-        const int64_t e0 = a.drp[v];
-        const int32_t c = a.hcnt[v];
-        bool cand = true;
-        for (int32_t j = 0; j < c && cand; ++j) {
-            const int32_t u = a.hcol[e0 + j];
-            if (u >= 0 && (bitv(a.P, u) || bitv(a.S, u))) cand = false;
+        const bool hit = wave_any(a.hcol + a.drp[v], a.hcnt[v], blocks, &read);
+        if (!hit && lane_id() == 0) atomicOr(&a.C[v >> 5], 1u << (v & 31));
+        return;
+    }
+    DYN_ITEMS(i, nl) {
+        const bool act = i < nl;
+        const int32_t v = act ? L[i] : 0;
+        const int32_t c = act ? a.hcnt[v] : 0;
+        bool cand = act;
+        if (act && c <= kDynLight) {
+            const int32_t* row = a.hcol + a.drp[v];
+            for (int32_t j = 0; j < c && cand; ++j) {
+                const int32_t u = row[j];
+                if (u >= 0 && blocks(u)) cand = false;
+            }
+        }
+        for (uint64_t hv = ballot(act && c > kDynLight); hv; hv &= hv - 1) {
+            const int l = __builtin_ctzll(hv);
+            const int32_t x = __shfl(v, l, kWave);
+            const bool hit = wave_any(a.hcol + a.drp[x], __shfl(c, l, kWave), blocks, &read);
+            if (lane_id() == l) cand = !hit;
         }
         if (cand) atomicOr(&a.C[v >> 5], 1u << (v & 31));
     }
@@ -194,23 +394,49 @@ __global__ void __launch_bounds__(kBlock) k_rep_decide(DynArgs a, int r) {
     const int32_t* L = a.list[r & 1];
     const int64_t nl = a.rcnt[r & 1];
     int64_t work = 0;
-    GRID_STRIDE(i, nl) {
-        const int32_t v = L[i];
-        if (bitv(a.C, v)) {
-            a.dec[atomicAdd((unsigned long long*)&a.rcnt[kRcDecided], 1ull)] = v;
-            continue;
+    auto excludes = [&](int32_t u) { return bitv(a.C, u) || (!bitv(a.P, u) && bitv(a.S, u)); };
+    if (nl <= wave_count()) {
+        const int64_t i = wave_index();
+        if (i < nl) {
+            const int32_t v = L[i];
+            if (bitv(a.C, v)) {
+                if (lane_id() == 0) a.dec[atomicAdd((unsigned long long*)&a.rcnt[kRcDecided], 1ull)] = v;
+            } else {
+                const bool out = wave_any(a.hcol + a.drp[v], a.hcnt[v], excludes, &work);
+                if (lane_id() == 0) {
+                    if (out) a.dec[atomicAdd((unsigned long long*)&a.rcnt[kRcDecided], 1ull)] = ~v;
+                    else a.list[(r + 1) & 1][atomicAdd((unsigned long long*)&a.rcnt[(r + 1) & 1], 1ull)] = v;
+                }
+            }
         }
-        const int64_t e0 = a.drp[v];
-        const int32_t c = a.hcnt[v];
+        if (work) atomicAdd((unsigned long long*)&a.rcnt[kRcWork], (unsigned long long)work);
+        return;
+    }
+    DYN_ITEMS(i, nl) {
+        const bool act = i < nl;
+        const int32_t v = act ? L[i] : 0;
+        const bool in = act && bitv(a.C, v);
+        const bool scan = act && !in;
+        const int32_t c = scan ? a.hcnt[v] : 0;
         bool out = false;
-        int32_t j = 0;
-        for (; j < c && !out; ++j) {
-            const int32_t u = a.hcol[e0 + j];
-            if (u >= 0 && (bitv(a.C, u) || (!bitv(a.P, u) && bitv(a.S, u)))) out = true;
+        if (scan && c <= kDynLight) {
+            const int32_t* row = a.hcol + a.drp[v];
+            int32_t j = 0;
+            for (; j < c && !out; ++j) {
+                const int32_t u = row[j];
+                if (u >= 0 && excludes(u)) out = true;
+            }
+            work += j;
         }
-        work += j;
-        if (out) a.dec[atomicAdd((unsigned long long*)&a.rcnt[kRcDecided], 1ull)] = ~v;
-        else a.list[(r + 1) & 1][atomicAdd((unsigned long long*)&a.rcnt[(r + 1) & 1], 1ull)] = v;
+        for (uint64_t hv = ballot(scan && c > kDynLight); hv; hv &= hv - 1) {
+            const int l = __builtin_ctzll(hv);
+            const int32_t x = __shfl(v, l, kWave);
+            const bool hit = wave_any(a.hcol + a.drp[x], __shfl(c, l, kWave), excludes, &work);
+            if (lane_id() == l) out = hit;
+        }
+        if (in) a.dec[atomicAdd((unsigned long long*)&a.rcnt[kRcDecided], 1ull)] = v;
+        else if (out) a.dec[atomicAdd((unsigned long long*)&a.rcnt[kRcDecided], 1ull)] = ~v;
+        else if (act) a.list[(r + 1) & 1][atomicAdd((unsigned long long*)&a.rcnt[(r + 1) & 1], 1ull)] = v;
     }
     if (work) atomicAdd((unsigned long long*)&a.rcnt[kRcWork], (unsigned long long)work);
 }
@@ -233,18 +459,53 @@ __global__ void __launch_bounds__(kBlock) k_rep_apply(DynArgs a) {
 // round r, wake: the lower neighbours of every flipped vertex are pending again
 __global__ void __launch_bounds__(kBlock) k_rep_wake(DynArgs a, int r) {
     const int64_t nf = a.rcnt[kRcFlipped];
-    GRID_STRIDE(i, nf) {
+    int32_t* next = a.list[(r + 1) & 1];
+    int64_t* cnt = &a.rcnt[(r + 1) & 1];
+    if (nf <= wave_count()) {
+        const int64_t i = wave_index();
+        if (i >= nf) return;
         const int32_t v = a.flip[i];
-        const int64_t e0 = a.drp[v];
         const int32_t c = a.lcnt[v];
-        for (int32_t j = 0; j < c; ++j) {
-            const int32_t w = a.lcol[e0 + j];
-            if (w >= 0) make_pending(a, w, a.list[(r + 1) & 1], &a.rcnt[(r + 1) & 1]);
+        const int32_t* row = a.lcol + a.drp[v];
+        for (int32_t j = lane_id(); j < c; j += kWave) {
+            const int32_t w = row[j];
+            if (w >= 0) make_pending(a, w, next, cnt);
+        }
+        return;
+    }
+    DYN_ITEMS(i, nf) {
+        const bool act = i < nf;
+        const int32_t v = act ? a.flip[i] : 0;
+        const int32_t c = act ? a.lcnt[v] : 0;
+        if (act && c <= kDynLight) {
+            const int32_t* row = a.lcol + a.drp[v];
+            for (int32_t j = 0; j < c; ++j) {
+                const int32_t w = row[j];
+                if (w >= 0) make_pending(a, w, next, cnt);
+            }
+        }
+        for (uint64_t hv = ballot(act && c > kDynLight); hv; hv &= hv - 1) {
+            const int l = __builtin_ctzll(hv);
+            const int32_t x = __shfl(v, l, kWave), cx = __shfl(c, l, kWave);
+            const int32_t* row = a.lcol + a.drp[x];
+            for (int32_t k0 = 0; k0 < cx; k0 += kDynUnroll * kWave) {
+                int32_t w[kDynUnroll];
+                #pragma unroll
+                for (int q = 0; q < kDynUnroll; ++q) {
+                    const int32_t j = k0 + q * kWave + lane_id();
+                    w[q] = j < cx ? row[j] : -1;
+                }
+                #pragma unroll
+                for (int q = 0; q < kDynUnroll; ++q)
+                    if (w[q] >= 0) make_pending(a, w[q], next, cnt);
+            }
         }
     }
 }
 
-__global__ void k_dyn_store(const uint32_t* S, int64_t n, uint8_t* in_set, int64_t* n_in) {
+// the result bytes and the set size (a workgroup sum, one atomic per workgroup)
+__global__ void __launch_bounds__(kBlock) k_dyn_store(const uint32_t* S, int64_t n, uint8_t* in_set, int64_t* n_in) {
+    __shared__ int64_t part[kBlock / kWave];
     int64_t cnt = 0;
     GRID_STRIDE(v, n) {
         const uint32_t x = bitv(S, v);
@@ -252,7 +513,13 @@ __global__ void k_dyn_store(const uint32_t* S, int64_t n, uint8_t* in_set, int64
         cnt += x;
     }
     for (int off = kWave / 2; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, kWave);
-    if (lane_id() == 0 && cnt) atomicAdd((unsigned long long*)n_in, (unsigned long long)cnt);
+    if (lane_id() == 0) part[threadIdx.x / kWave] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t sum = 0;
+        for (int w = 0; w < kBlock / kWave; ++w) sum += part[w];
+        if (sum) atomicAdd((unsigned long long*)n_in, (unsigned long long)sum);
+    }
 }
 
 DynArgs dyn_args(mis_graph* g) {
@@ -312,8 +579,13 @@ int mis_update_edges(mis_graph* g, const int32_t* edges, const int8_t* ops, int6
     if (n == 0) return MIS_OK;
     DynArgs a = dyn_args(g);
     DLAUNCH(k_dyn_clear, std::max<int64_t>(nw, kRcWords), a.P, a.C, a.S, nw, a.rcnt);
-    DLAUNCH(k_dyn_delete, count, a, edges, ops, count);
-    DLAUNCH(k_dyn_compact, count, a, edges, ops, count);
+    // a wave per edit (the two kernels take that form when the grid has a wave for each)
+    const unsigned egrid = (unsigned)std::min<int64_t>(ceil_div(count, (int64_t)(kBlock / kWave)), 65536);
+    if (count > 0) {
+        hipLaunchKernelGGL(k_dyn_delete, dim3(egrid), dim3(kBlock), 0, s, a, edges, ops, count);
+        hipLaunchKernelGGL(k_dyn_compact, dim3(egrid), dim3(kBlock), 0, s, a, edges, ops, count);
+        TC_HIP(hipGetLastError());
+    }
     DLAUNCH(k_dyn_unclaim, nw, a.C, nw);
     DLAUNCH(k_dyn_insert, count, a, edges, ops, count);
     DLAUNCH(k_dyn_load, nw, in_set, n, a.S);
@@ -342,7 +614,9 @@ int mis_update_edges(mis_graph* g, const int32_t* edges, const int8_t* ops, int6
         if (r > 2 * n + 16) { set_error("repair did not settle"); return MIS_EINTERNAL; }
     }
     TC_HIP(hipMemsetAsync(a.rcnt + kRcIn, 0, 8, s));
-    DLAUNCH(k_dyn_store, n, a.S, n, in_set, a.rcnt + kRcIn);
+    hipLaunchKernelGGL(k_dyn_store, dim3((unsigned)std::min<int64_t>(ceil_div(n, kBlock), 1024)), dim3(kBlock), 0, s,
+                       a.S, n, in_set, a.rcnt + kRcIn);
+    TC_HIP(hipGetLastError());
     if (st) {
         int64_t nin = 0;
         TC_HIP(hipMemcpyAsync(&nin, a.rcnt + kRcIn, 8, hipMemcpyDeviceToHost, s));

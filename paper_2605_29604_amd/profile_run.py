@@ -477,7 +477,7 @@ Command (run from /tmp; REPO = the repository root, OUT = a directory for the ou
 ```
 rocprofv3 --kernel-trace --stats --output-format csv -d $OUT/stats -o run -- \\
     python3 $REPO/bench.py --steps 3 --warmup 1 --no-cpu --no-batch --no-serve --no-tune \\
-        --no-configs > $OUT/bench.json
+        --no-configs --no-dynamic > $OUT/bench.json
 python3 paper_2605_29604_amd/profile_run.py --summarize-stats $OUT/stats {name} $OUT/bench.json
 ```
 
