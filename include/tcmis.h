@@ -470,7 +470,11 @@ size_t mis_noalloc_max_bytes(void);
  *            previous update), out: the result on the edited graph
  *   stats  : optional HOST: rounds of the repair, n_in, units[0] = entries read
  * Deletes apply before inserts.  The handle's rows change in place, and a later
- * mis_solve solves the edited graph from scratch.  Synchronises `stream`.
+ * mis_solve solves the edited graph from scratch.  When the edits leave more than
+ * n/256 vertices to re-decide, or one of them with more than 4,096 higher-priority
+ * neighbours (a hub's row would be scanned in every repair round), the set is
+ * recomputed by a full solve of the edited handle instead (the same result; stats
+ * then describe that solve).  Synchronises `stream`.
  * Errors: MIS_EINVAL (not a dynamic handle; an edit out of range, a self-loop or a
  * missing edge), MIS_ENOMEM (a row ran out of slots: the handle no longer holds
  * that edge -- rebuild with a larger dyn_slack), MIS_EHIP.

@@ -38,7 +38,15 @@ namespace {
 
 // rcnt layout
 enum : int { kRcList0 = 0, kRcList1 = 1, kRcDecided = 2, kRcFlipped = 3, kRcErr = 4, kRcWork = 5, kRcIn = 6,
-             kRcWords = 8 };
+             kRcMaxRow = 7, kRcWords = 8 };
+
+// The repair re-decides the pending vertices round by round, one wave per long row;
+// a pending vertex with a very long H row (a hub of a power-law graph) makes every
+// round wait for its scan, and a large pending set costs as much as a solve.  Past
+// either bound the set is recomputed by a full solve of the edited handle instead
+// (the same result: the recursion has one solution).
+constexpr int64_t kRepairRowMax = 4096;   // longest H row among the edits' lower ends
+constexpr int64_t kRepairShare = 256;     // pending vertices above n / kRepairShare
 enum : int64_t { kErrFull = 1, kErrMissing = 2, kErrEdge = 4 };
 
 __device__ inline uint32_t bitv(const uint32_t* m, int64_t v) { return (m[v >> 5] >> (v & 31)) & 1u; }
@@ -69,6 +77,12 @@ __device__ inline void make_pending(const DynArgs& a, int32_t v, int32_t* list, 
         const unsigned long long i = atomicAdd((unsigned long long*)cnt, 1ull);
         list[i] = v;
     }
+}
+
+// an edit's lower end: pending, and its H row length into the edits' maximum
+__device__ inline void lower_end(const DynArgs& a, int32_t lo) {
+    make_pending(a, lo, a.list[1], &a.rcnt[kRcList1]);
+    atomicMax((unsigned long long*)&a.rcnt[kRcMaxRow], (unsigned long long)max(a.hcnt[lo], 0));
 }
 
 // Rows longer than kDynLight entries (a hub's row holds up to the graph's largest
@@ -267,7 +281,7 @@ __global__ void k_dyn_delete(DynArgs a, const int32_t* edges, const int8_t* ops,
         const bool fl = wave_clear(a.lcol + a.drp[hi], a.lcnt[hi], lo);
         if (lane_id() == 0) {
             if (!fh || !fl) atomicOr((unsigned long long*)&a.rcnt[kRcErr], (unsigned long long)kErrMissing);
-            make_pending(a, lo, a.list[1], &a.rcnt[kRcList1]);
+            lower_end(a, lo);
         }
         return;
     }
@@ -301,7 +315,7 @@ __global__ void k_dyn_delete(DynArgs a, const int32_t* edges, const int8_t* ops,
         }
         if (act) {
             if (!fh || !fl) atomicOr((unsigned long long*)&a.rcnt[kRcErr], (unsigned long long)kErrMissing);
-            make_pending(a, lo, a.list[1], &a.rcnt[kRcList1]);
+            lower_end(a, lo);
         }
     }
 }
@@ -331,7 +345,7 @@ __global__ void k_dyn_insert(DynArgs a, const int32_t* edges, const int8_t* ops,
             atomicSub(&a.lcnt[hi], 1);
             atomicOr((unsigned long long*)&a.rcnt[kRcErr], (unsigned long long)kErrFull);
         }
-        make_pending(a, lo, a.list[1], &a.rcnt[kRcList1]);
+        lower_end(a, lo);
     }
 }
 
@@ -591,6 +605,24 @@ int mis_update_edges(mis_graph* g, const int32_t* edges, const int8_t* ops, int6
     DLAUNCH(k_dyn_load, nw, in_set, n, a.S);
     const dim3 grid((unsigned)std::max(1, g->grid_blocks)), blk(kBlock);
     int64_t h[kRcWords] = {};
+    TC_HIP(hipMemcpyAsync(h, a.rcnt, sizeof(h), hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+    if (h[kRcErr] & kErrEdge) { set_error("an edit names a vertex out of range or a self-loop"); return MIS_EINVAL; }
+    if (h[kRcErr] & kErrMissing) { set_error("a deleted edge was not in the graph"); return MIS_EINVAL; }
+    if (h[kRcErr] & kErrFull) {
+        set_error("a row has no slot left for an inserted edge: rebuild with a larger dyn_slack");
+        return MIS_ENOMEM;
+    }
+    if (h[kRcMaxRow] > kRepairRowMax || h[kRcList1] * kRepairShare > n) {
+        mis_stats full = {};
+        TC_CHECK(mis_solve(g, in_set, 0, nullptr, 0, &full, stream));
+        if (st) {
+            st->rounds = full.rounds;
+            st->n_in = full.n_in;
+            st->units[0] = full.units[0] + full.units[2];
+        }
+        return MIS_OK;
+    }
     int r = 0;
     const int poll = std::max(1, g->poll_rounds);
     for (;;) {

@@ -55,10 +55,23 @@ def random_edits(rng, n, edges, k_del, k_ins, hub=None):
     return dels, sorted(ins)
 
 
-@pytest.mark.parametrize("name", ["rmat12", "grid12", "er3000"])
-def test_edit_batches_repair_to_the_oracle(name):
+# (graph, edits of each kind in batch b: per * (b + 1), repair expected).  The library
+# repairs locally unless the edits leave more than n/256 vertices pending or a pending
+# vertex with more than 4,096 higher-priority neighbours; then it solves the edited
+# handle in full.  The small graphs take the full solve, the larger ones with few edits
+# the repair (which reads far fewer entries than a solve's first round).
+CASES = [("rmat12", 40, False), ("grid12", 40, False), ("er3000", 40, False),
+         ("grid32", 10, True), ("er40000", 10, True)]
+
+
+@pytest.mark.parametrize("name,per,repair", CASES)
+def test_edit_batches_repair_to_the_oracle(name, per, repair):
     t = T()
-    g = gen.er(3000, 12000, 4) if name == "er3000" else gen.workload(name, seed=3)
+    if name.startswith("er"):
+        n_er = int(name[2:])
+        g = gen.er(n_er, 4 * n_er, 4)
+    else:
+        g = gen.workload(name, seed=3)
     keys0 = oracle.keys(g.row_ptr, 5)
     rp0 = torch.from_numpy(g.row_ptr).cuda()
     ci0 = torch.from_numpy(g.col_idx).cuda()
@@ -72,7 +85,7 @@ def test_edit_batches_repair_to_the_oracle(name):
     rng = np.random.default_rng(11)
     hub = int(np.argmax(np.diff(g.row_ptr)))
     for b in range(4):
-        dels, ins = random_edits(rng, g.n, edges, 40 * (b + 1), 40 * (b + 1), hub=hub)
+        dels, ins = random_edits(rng, g.n, edges, per * (b + 1), per * (b + 1), hub=hub)
         edges = (edges - set(dels)) | set(ins)
         pairs = np.array(dels + ins, dtype=np.int32).reshape(-1, 2)
         flip = rng.random(len(pairs)) < 0.5              # either endpoint order
@@ -91,6 +104,8 @@ def test_edit_batches_repair_to_the_oracle(name):
               f"{info['rounds']}, entries read {info['entries_read']}", flush=True)
         assert np.array_equal(got, want), f"batch {b}: {int((got != want).sum())} vertices differ"
         assert info["n_in"] == int(want.sum())
+        if repair:   # the local repair ran, not a full solve
+            assert info["entries_read"] < g.n // 4, info
     # a full solve of the edited handle: same set and round trace as the oracle
     out2, st2 = t.mis_solve(h)
     torch.cuda.synchronize()
