@@ -112,20 +112,22 @@ __device__ inline bool lane_clear(int32_t* row, int32_t c, int32_t x) {
     return false;
 }
 
-// The wave forms take kDynUnroll steps of 64 entries at a time, all their loads in
-// flight together (a hub's row takes hundreds of such steps).
+// The wave forms take several steps of 64 entries at a time, all their loads in flight
+// together (a hub's row takes hundreds of such steps): kDynUnroll where each entry also
+// costs bitmap gathers, kClearUnroll where it is only compared or moved.
 constexpr int kDynUnroll = 8;
+constexpr int kClearUnroll = 16;
 
 __device__ inline bool wave_clear(int32_t* row, int32_t c, int32_t x) {
-    for (int32_t k0 = 0; k0 < c; k0 += kDynUnroll * kWave) {
-        int32_t u[kDynUnroll];
+    for (int32_t k0 = 0; k0 < c; k0 += kClearUnroll * kWave) {
+        int32_t u[kClearUnroll];
         #pragma unroll
-        for (int q = 0; q < kDynUnroll; ++q) {
+        for (int q = 0; q < kClearUnroll; ++q) {
             const int32_t j = k0 + q * kWave + lane_id();
             u[q] = j < c ? row[j] : -1;
         }
         #pragma unroll
-        for (int q = 0; q < kDynUnroll; ++q) {
+        for (int q = 0; q < kClearUnroll; ++q) {
             const uint64_t m = ballot(u[q] == x);
             if (m) {
                 if (lane_id() == __builtin_ctzll(m)) row[k0 + q * kWave + lane_id()] = -1;
@@ -149,7 +151,7 @@ __device__ inline int32_t compact_row(int32_t* row, int32_t c) {
 }
 
 __device__ inline int32_t wave_compact(int32_t* row, int32_t c) {
-    constexpr int kU = kDynUnroll / 2;
+    constexpr int kU = kClearUnroll / 2;
     int32_t w = 0;
     for (int32_t k0 = 0; k0 < c; k0 += kU * kWave) {
         int32_t x[kU];
